@@ -1,0 +1,162 @@
+"""SIMP compliance minimisation pieces (oracle, float64, CPU).
+
+Paper: Sec. "Three-Dimensional SIMP Topology Optimization": problem Eq. (tomin)
+(minimise f^T u subject to K u = f and a volume fraction), the SIMP interpolation
+Eq. (simp), a cone density filter of radius rmin, analytic sensitivities and the
+optimality-criteria (OC) update with bisection on the volume multiplier.
+
+Readings where the paper is silent (all textbook density-filter SIMP):
+  * the density entering K is the filtered field xphys = H x / Hs (no projection);
+  * cone weights H_ej = max(0, rmin - |c_e - c_j|) over element centroids, the
+    neighbourhood truncated at the domain boundary, Hs_e = sum_j H_ej;
+  * sensitivities are chained through the filter: dc <- H (dc / Hs), dv <- H (1 / Hs);
+  * OC: lambda bracketed in [0, 1e9], bisection until (l2 - l1) / (l1 + l2) <= 1e-3,
+    x_new = clip(x * sqrt(-dc / (dv * lambda)), max(0, x - m), min(1, x + m)), and the
+    volume test filters x_new and compares its sum with volfrac * n_elem
+    ("greater" moves the lower bracket up);
+  * initial design x = volfrac everywhere, initial displacement 0.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import fem, solvers
+
+
+# ------------------------------------------------------------------------ filter
+def filter_matrix(nx: int, ny: int, nz: int, rmin: float):
+    """Explicit sparse H (n_elem x n_elem) and Hs = H 1 from centroid distances."""
+    R = int(np.ceil(rmin)) - 1
+    ez, ey, ex = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
+    rows, cols, vals = [], [], []
+    for dk in range(-R, R + 1):
+        for dj in range(-R, R + 1):
+            for di in range(-R, R + 1):
+                w = rmin - np.sqrt(di * di + dj * dj + dk * dk)
+                if w <= 0.0:
+                    continue
+                jx, jy, jz = ex + di, ey + dj, ez + dk
+                ok = (jx >= 0) & (jx < nx) & (jy >= 0) & (jy < ny) & (jz >= 0) & (jz < nz)
+                rows.append((ex + nx * (ey + ny * ez))[ok])
+                cols.append((jx + nx * (jy + ny * jz))[ok])
+                vals.append(np.full(ok.sum(), w))
+    n = nx * ny * nz
+    H = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n)).tocsr()
+    Hs = np.asarray(H.sum(axis=1)).ravel()
+    return H, Hs
+
+
+def filter_forward(H, Hs, x):
+    """xphys = H x / Hs."""
+    return (H @ x) / Hs
+
+
+def filter_adjoint(H, Hs, g):
+    """Chain rule through the density filter: H^T (g / Hs) (H is symmetric)."""
+    return H.T @ (g / Hs)
+
+
+# ------------------------------------------------------------ compliance, sensitivity
+def compliance(f, u):
+    """c = f^T u (Eq. tomin objective)."""
+    return float(f @ u)
+
+
+def element_energy(nx, ny, nz, u, KE):
+    """ce_e = u_e^T K_E u_e for every element."""
+    ue = u[fem.edof_table(nx, ny, nz)]
+    return np.einsum("ei,ij,ej->e", ue, KE, ue)
+
+
+def sensitivity(nx, ny, nz, xphys, u, KE, E0, Emin, penal):
+    """dc_e = d(f^T u)/d xphys_e = -p xphys_e^(p-1) (E0 - Emin) ce_e  (adjoint-free)."""
+    ce = element_energy(nx, ny, nz, u, KE)
+    return -penal * np.power(xphys, penal - 1.0) * (E0 - Emin) * ce
+
+
+# ---------------------------------------------------------------------------- OC
+def oc_update(x, dc, dv, H, Hs, volfrac, move=0.2, l1=0.0, l2=1e9, rel_tol=1e-3):
+    """Optimality-criteria update with bisection on the volume multiplier.
+
+    Returns (x_new, xphys_new, change, number_of_bisection_steps)."""
+    n = x.size
+    target = volfrac * n
+    steps = 0
+    while (l2 - l1) / (l1 + l2) > rel_tol:
+        lmid = 0.5 * (l2 + l1)
+        xnew = np.sqrt(-dc / (dv * lmid)) * x
+        xnew = np.minimum(np.minimum(xnew, x + move), 1.0)
+        xnew = np.maximum(np.maximum(xnew, x - move), 0.0)
+        xphys = filter_forward(H, Hs, xnew)
+        if xphys.sum() > target:
+            l1 = lmid
+        else:
+            l2 = lmid
+        steps += 1
+    change = float(np.max(np.abs(xnew - x)))
+    return xnew, xphys, change, steps
+
+
+# --------------------------------------------------------------------------- SIMP
+class Problem:
+    """Everything the oracle needs for one mesh: K_E, edof, filter, BCs, loads."""
+
+    def __init__(self, nx, ny, nz, fixed_dofs, f, E0=1.0, Emin=1e-9, nu=0.3, penal=3.0,
+                 rmin=1.5, volfrac=0.3, **_):
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.E0, self.Emin, self.nu, self.penal, self.rmin = E0, Emin, nu, penal, rmin
+        self.volfrac = volfrac
+        self.n_elem = nx * ny * nz
+        self.n_dof = 3 * (nx + 1) * (ny + 1) * (nz + 1)
+        self.KE = fem.element_stiffness(nu)
+        self.fixed = fem.fixed_mask(self.n_dof, fixed_dofs)
+        self.f = np.asarray(f, dtype=np.float64).copy()
+        self.H, self.Hs = filter_matrix(nx, ny, nz, rmin)
+        self.dv = filter_adjoint(self.H, self.Hs, np.ones(self.n_elem))
+
+    def modulus(self, xphys):
+        return fem.simp_modulus(xphys, self.E0, self.Emin, self.penal)
+
+    def stiffness(self, xphys):
+        K = fem.assemble_K(self.nx, self.ny, self.nz, self.modulus(xphys), self.KE)
+        return fem.constrain(K, self.fixed)
+
+    def diag(self, xphys):
+        return fem.diag_K(self.nx, self.ny, self.nz, self.modulus(xphys), self.KE,
+                          self.fixed)
+
+    def solve(self, xphys, u0=None, tol=1e-8, maxit=20000, direct=False):
+        Kc = self.stiffness(xphys)
+        if direct:
+            return solvers.solve_direct(Kc, self.f), 0
+        u, it, _ = solvers.pcg_jacobi(lambda v: Kc @ v, self.diag(xphys), self.f, u0,
+                                      tol, maxit)
+        return u, it
+
+    def sensitivity(self, xphys, u):
+        return sensitivity(self.nx, self.ny, self.nz, xphys, u, self.KE, self.E0,
+                           self.Emin, self.penal)
+
+
+def simp_run(prob: Problem, iters: int, tol=1e-8, move=0.2, direct=False, maxit=20000):
+    """Plain SIMP loop: x = volfrac; each iteration solves K(xphys) u = f (warm start),
+    takes c and dc, filters dc, runs OC and refilters.  Returns per-iteration history
+    and the final (x, xphys, u)."""
+    x = np.full(prob.n_elem, prob.volfrac)
+    xphys = filter_forward(prob.H, prob.Hs, x)
+    u = np.zeros(prob.n_dof)
+    hist = []
+    for _ in range(iters):
+        u, its = prob.solve(xphys, u, tol=tol, maxit=maxit, direct=direct)
+        c = compliance(prob.f, u)
+        dc = prob.sensitivity(xphys, u)
+        dc_f = filter_adjoint(prob.H, prob.Hs, dc)
+        xnew, xphys_new, change, steps = oc_update(x, dc_f, prob.dv, prob.H, prob.Hs,
+                                                   prob.volfrac, move)
+        hist.append(dict(c=c, cg_iters=its, change=change, bisect=steps,
+                         vol=float(xphys_new.mean())))
+        x, xphys = xnew, xphys_new
+    return hist, x, xphys, u
