@@ -1,0 +1,198 @@
+"""Benchmark of the fused matrix-free operator and the PCG solve on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--prec fp32|fp64] [--no-pcg] [--no-cpu-baseline]
+
+Timed region: K applications of y = K_c(x) v on the 340x170x85 cantilever (4.9M
+elements, 15.0M DOFs) with seeded x ~ U(0.01, 1), v ~ N(0, 1), rotating over enough
+independent (x, v, y) buffer sets (>= 512 MB) that the 256 MB Infinity Cache cannot hold
+them, bracketed by torch.cuda.synchronize().  `value` = DOFs processed per second
+(GDOF/s).  Alongside, in the same JSON line:
+  * roofline: algorithmic bytes per launch / measured launch time vs 8 TB/s,
+  * kv_other_precision: the same measurement for the other operator precision,
+  * pcg: wall time to ||r|| <= 1e-6 ||f|| for plain FP64 Jacobi-PCG and for FP64
+    refinement around an FP32 inner Jacobi-PCG, with the compliance difference,
+  * cpu_baseline: the CPU oracle's element-by-element K v on a bounded sample.
+Only one GPU is supported: --gpus N > 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kv_bytes(prec: str, n_node: int, n_elem: int) -> int:
+    """Algorithmic HBM bytes of one K v launch: v read once and y written once (3 values
+    per node), the density read once per element, the 1-byte BC mask once per node."""
+    w = 8 if prec == "fp64" else 4
+    return 2 * 3 * w * n_node + w * n_elem + n_node
+
+
+def time_kv(t, nx, ny, nz, prec, steps, warmup, seed=42):
+    import numpy as np
+    import torch
+
+    import synth_inputs as si
+
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    rho, v = si.random_density_and_vector(nx, ny, nz, seed)
+    set_bytes = kv_bytes(prec, t.n_node, t.n_elem)
+    nset = max(2, -(-512 * 2 ** 20 // set_bytes))
+    xs = [torch.tensor(rho, dtype=dt, device="cuda:0") for _ in range(nset)]
+    vs = [torch.tensor(v, dtype=dt, device="cuda:0") for _ in range(nset)]
+    ys = [torch.empty_like(vs[0]) for _ in range(nset)]
+    del rho, v
+    for i in range(warmup):
+        t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[2 * i].record(stream)
+        t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec)
+        ev[2 * i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)]
+    avg_ms = float(np.mean(launch_ms))
+    ok = bool(torch.isfinite(ys[(steps - 1) % nset]).all())
+    del xs, vs, ys
+    torch.cuda.empty_cache()
+    return dict(wall_s=wall, avg_launch_ms=avg_ms, median_launch_ms=float(np.median(launch_ms)),
+                bytes=set_bytes, buffer_sets=nset, finite=ok)
+
+
+def time_pcg(t, nx, ny, nz, tol, volfrac=0.3):
+    import numpy as np
+    import torch
+
+    import synth_inputs as si
+
+    f = torch.tensor(si.cantilever_load(nx, ny, nz), device="cuda:0")
+    x = torch.full((t.n_elem,), volfrac, dtype=torch.float64, device="cuda:0")
+    out = {}
+    for name, kw in [("plain_fp64", dict(mode="plain_fp64")),
+                     ("ir_fp32", dict(mode="ir", inner_prec="fp32", inner_tol=1e-2,
+                                      max_outer=30))]:
+        u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = t.pcg_solve(x, f, u, tol=tol, maxit=50000, check_every=64, **kw)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        c = float(torch.dot(f, u))
+        out[name] = dict(seconds=sec, iterations=st["iterations"],
+                         outer_iterations=st["outer_iterations"], status=st["status"],
+                         true_rel_residual=st["true_rel_residual"], compliance=c)
+    p, m = out["plain_fp64"], out["ir_fp32"]
+    out["speedup_ir_over_plain"] = p["seconds"] / m["seconds"]
+    out["compliance_rel_diff"] = abs(p["compliance"] - m["compliance"]) / abs(p["compliance"])
+    return out
+
+
+def cpu_baseline(budget_s=20.0):
+    """The oracle's element-by-element K v (gather, dense 24x24 product, scatter-add)
+    on the 120x60x30 mesh, repeated until ~budget_s of CPU time."""
+    import numpy as np
+
+    import synth_inputs as si
+    from oracle import fem
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    nx, ny, nz = 120, 60, 30
+    rho, v = si.random_density_and_vector(nx, ny, nz, 42)
+    KE = fem.element_stiffness(0.3)
+    E = fem.simp_modulus(rho, 1.0, 1e-9, 3.0)
+    fixed = fem.fixed_mask(v.size, si.cantilever_fixed_dofs(nx, ny, nz))
+    calls, t0 = 0, time.perf_counter()
+    while True:
+        fem.apply_K_elementwise(nx, ny, nz, E, KE, v, fixed)
+        calls += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or calls >= 50:
+            break
+    return {"value": calls * v.size / el / 1e9, "unit": "GDOF/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"oracle element-by-element K v on the 120x60x30 cantilever "
+                      f"({v.size} DOFs), {calls} calls in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="cantilever_340x170x85")
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--pcg-tol", type=float, default=1e-6)
+    ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth_inputs as si
+    from paper_2604_18020_amd import Tosimp
+
+    cfg = si.CONFIGS[a.workload]
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+    t = Tosimp(0).set_mesh(nx, ny, nz)
+    fixed = (si.cantilever_fixed_dofs if cfg["kind"] == "cantilever" else si.torsion_fixed_dofs)(nx, ny, nz)
+    t.set_bcs(fixed)
+
+    main_kv = time_kv(t, nx, ny, nz, a.prec, a.steps, a.warmup)
+    other = "fp64" if a.prec == "fp32" else "fp32"
+    other_kv = time_kv(t, nx, ny, nz, other, max(20, a.steps // 4), 5)
+
+    ms = main_kv["wall_s"] * 1e3 / a.steps
+    value = t.n_dof / (ms * 1e-3) / 1e9
+    achieved = main_kv["bytes"] / (main_kv["avg_launch_ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "bytes_per_launch": main_kv["bytes"],
+                "avg_launch_us": main_kv["avg_launch_ms"] * 1e3}
+    line = {
+        "metric": "K·v GDOF/s + PCG time-to-1e-6 residual: plain FP64 vs mixed/learned form",
+        "value": value, "unit": "GDOF/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if a.prec == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": a.workload, "n_elem": t.n_elem, "n_dof": t.n_dof,
+                   "operator_precision": a.prec, "buffer_sets": main_kv["buffer_sets"],
+                   "inputs": "rho~U(0.01,1), v~N(0,1), seed 42; cantilever BCs"},
+        "roofline": roofline,
+        "kv_other_precision": {
+            "precision": other,
+            "gdof_s": t.n_dof / (other_kv["avg_launch_ms"] * 1e-3) / 1e9,
+            "achieved_gbs": other_kv["bytes"] / (other_kv["avg_launch_ms"] * 1e-3) / 1e9,
+            "frac": other_kv["bytes"] / (other_kv["avg_launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "avg_launch_us": other_kv["avg_launch_ms"] * 1e3},
+    }
+    if not a.no_pcg:
+        line["pcg"] = dict(workload=f"{a.workload}, cold start, uniform density 0.3, "
+                                    f"tol {a.pcg_tol:g}",
+                           **time_pcg(t, nx, ny, nz, a.pcg_tol))
+    t.close()
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

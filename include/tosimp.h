@@ -1,0 +1,209 @@
+/*
+ * tosimp.h -- C ABI of the MI355X (gfx950) matrix-free 3D SIMP library.
+ *
+ * Problem (paper Sec. "Three-Dimensional SIMP Topology Optimization", Eq. tomin):
+ * minimise the compliance f^T u subject to K(x) u = f and a volume fraction, on a
+ * structured grid of nx*ny*nz cubic trilinear (Q1) hexahedra of edge h.
+ *
+ * Conventions shared by every entry point
+ *   Numbering   node (i,j,k) has id n = i + (nx+1)*(j + (ny+1)*k); DOF 3*n + c
+ *               (c = 0,1,2 for x,y,z, interleaved); element (ex,ey,ez) has id
+ *               ex + nx*(ey + ny*ez); local node a = ax + 2*ay + 4*az.
+ *   Operator    K_c = P K P + (I - P), P the diagonal free-DOF mask: fixed rows and
+ *               columns are identity, so CG on K_c solves the free block exactly.
+ *   Memory      every array argument named *_dev is caller-owned device memory on
+ *               the context's device (contiguous, no strides); *_host is host memory.
+ *               The library never frees caller memory.  It owns only a workspace it
+ *               allocates in tosimp_set_mesh and frees on re-mesh or destroy.
+ *   Streams     work is enqueued on the context's stream (tosimp_set_stream).  Entry
+ *               points that return host scalars synchronise that stream; the others
+ *               are asynchronous.
+ *   Errors      every entry point returns an int status: 0 = OK, > 0 = informational
+ *               with a valid result, < 0 = error with outputs unspecified; the text of
+ *               the last error is tosimp_last_error(ctx).  Nothing aborts and no C++
+ *               exception crosses the ABI.  A context is not thread-safe.
+ */
+#ifndef TOSIMP_H
+#define TOSIMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------ */
+#define TOSIMP_OK 0
+#define TOSIMP_NOT_CONVERGED 1   /* iteration cap hit; the iterate is valid          */
+#define TOSIMP_FALLBACK_USED 2   /* a preconditioner fallback was taken              */
+#define TOSIMP_EINVAL (-1)       /* bad argument (null pointer, size, enum, layout)  */
+#define TOSIMP_ESTATE (-2)       /* call order violated (e.g. no mesh set)           */
+#define TOSIMP_EHIP (-3)         /* HIP runtime error                                 */
+#define TOSIMP_EBREAKDOWN (-4)   /* CG breakdown: p^T K p <= 0 or non-finite         */
+#define TOSIMP_EPRECISION (-5)   /* precision refused by the conditioning rule       */
+#define TOSIMP_ENOMEM (-6)       /* workspace allocation failed                       */
+
+/* ---- element types and operator precisions ------------------------------------ */
+#define TOSIMP_F64 0
+#define TOSIMP_F32 1
+
+#define TOSIMP_PREC_FP64 0       /* FP64 storage and arithmetic                       */
+#define TOSIMP_PREC_FP32 1       /* FP32 storage and arithmetic                       */
+#define TOSIMP_PREC_BF16_MFMA 2  /* FP32 storage, BF16 MFMA contraction, FP32 acc.    */
+#define TOSIMP_PREC_FP16_MFMA 3  /* FP32 storage, FP16 MFMA contraction, FP32 acc.    */
+
+/* ---- filter modes -------------------------------------------------------------- */
+#define TOSIMP_FILTER_FORWARD 0  /* out = H in / Hs                                   */
+#define TOSIMP_FILTER_ADJOINT 1  /* out = H (in / Hs)                                 */
+
+/* ---- solver modes -------------------------------------------------------------- */
+#define TOSIMP_SOLVE_PLAIN_FP64 0 /* Jacobi-PCG, FP64 vectors and reductions           */
+#define TOSIMP_SOLVE_IR 1         /* FP64 refinement around a low-precision inner CG  */
+
+#define TOSIMP_PRECOND_JACOBI 0
+#define TOSIMP_PRECOND_NN 1       /* learned U-Net correction in flexible CG          */
+
+typedef struct tosimp_ctx tosimp_ctx;
+
+typedef struct tosimp_solve_opts {
+  double tol;        /* stop when ||r|| <= tol * ||b|| (see tosimp_pcg_solve)         */
+  int maxit;         /* cap on CG iterations (plain) or on inner iterations in total  */
+  int mode;          /* TOSIMP_SOLVE_*                                                */
+  int inner_prec;    /* TOSIMP_PREC_* of the inner solve in IR mode                   */
+  double inner_tol;  /* relative tolerance of each inner solve in IR mode             */
+  int max_outer;     /* cap on refinement steps in IR mode                            */
+  int precond;       /* TOSIMP_PRECOND_*                                              */
+  int check_every;   /* host convergence polls every this many iterations (>= 1)      */
+  int enforce_rule;  /* 1: refuse inner precisions failing u*kappa < 1 (needs kappa)  */
+  double kappa;      /* condition estimate used by enforce_rule (0: unknown)          */
+} tosimp_solve_opts;
+
+typedef struct tosimp_solve_stats {
+  int iterations;          /* total CG iterations (inner iterations in IR mode)      */
+  int outer_iterations;    /* refinement steps (0 in plain mode)                     */
+  int fallbacks;           /* NN -> Jacobi fallbacks taken                           */
+  int status;              /* same value the call returned                           */
+  double rel_residual;     /* final ||r|| / ||b|| the solver judged convergence on   */
+  double true_rel_residual;/* ||b - K u|| / ||b|| recomputed in FP64 at exit         */
+} tosimp_solve_stats;
+
+typedef struct tosimp_step_opts {
+  double volfrac;    /* target volume fraction                                       */
+  double move;       /* OC move limit                                                 */
+  tosimp_solve_opts solve;
+} tosimp_step_opts;
+
+typedef struct tosimp_step_stats {
+  double compliance; /* f^T u after the solve                                         */
+  double change;     /* max |x_new - x|                                               */
+  double volume;     /* mean of the new filtered density                              */
+  int bisection_steps;
+  tosimp_solve_stats solve;
+} tosimp_step_stats;
+
+/* ---- lifecycle ------------------------------------------------------------------
+ * tosimp_create: make a context on HIP device `device` using `stream` (a hipStream_t,
+ * NULL for the default stream).  *out receives the handle.  tosimp_destroy frees the
+ * workspace (synchronising the stream first); NULL is accepted.                      */
+int tosimp_create(int device, void* stream, tosimp_ctx** out);
+int tosimp_destroy(tosimp_ctx* ctx);
+int tosimp_set_stream(tosimp_ctx* ctx, void* stream);
+const char* tosimp_last_error(const tosimp_ctx* ctx);
+/* Library version string and a NUL-separated list of compiled GPU targets. */
+const char* tosimp_version(void);
+
+/* ---- problem set-up ---------------------------------------------------------------
+ * tosimp_set_mesh (paper Sec. "Three-Dimensional SIMP Topology Optimization",
+ * Eq. simp): nx, ny, nz >= 1 elements of edge h > 0; SIMP modulus
+ * E_e = Emin + x_e^penal (E0 - Emin); Poisson ratio nu in (-1, 0.5); density-filter
+ * radius rmin > 0 (in element edges).  Builds the 24x24 element stiffness by 2x2x2
+ * Gauss quadrature and its exact factorisation in the tensor Hadamard basis, the filter
+ * weights, and allocates the workspace (EINVAL on bad sizes, ENOMEM on failure).
+ * Clears any previous boundary conditions and loads.                                 */
+int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0,
+                    double Emin, double nu, double penal, double rmin);
+/* Dirichlet set: `n` DOF ids (host, any order, duplicates allowed) held at zero.
+ * EINVAL if an id is out of range.                                                   */
+int tosimp_set_bcs(tosimp_ctx* ctx, const int64_t* fixed_dofs_host, int64_t n);
+/* Load vector f (device, n_dof FP64); copied into the workspace.  EINVAL if f is
+ * non-zero on a fixed DOF.                                                            */
+int tosimp_set_loads(tosimp_ctx* ctx, const double* f_dev);
+/* Mesh counts: n_elem, n_node, n_dof (any pointer may be NULL).                      */
+int tosimp_counts(const tosimp_ctx* ctx, int64_t* n_elem, int64_t* n_node, int64_t* n_dof);
+
+/* ---- the operator ----------------------------------------------------------------
+ * tosimp_apply_K (paper Eq. matfree and Alg. "Fused Gather-GEMM-Scatter"):
+ * y = K_c(xphys) v, one fused pass (gather the 24 element DOFs, multiply by
+ * E_e K_E, accumulate), deterministic (no atomics; bit-identical across calls).
+ * xphys: n_elem element densities of type xdtype; v, y: n_dof values.  prec selects
+ * the arithmetic: PREC_FP64 needs v, y FP64; PREC_FP32 and the MFMA precisions need
+ * v, y FP32.  y is overwritten (not accumulated); y must not alias v.                */
+int tosimp_apply_K(tosimp_ctx* ctx, const void* xphys_dev, int xdtype, const void* v_dev,
+                   void* y_dev, int prec);
+/* Jacobi diagonal (paper Sec. "Preconditioned Conjugate Gradient"): d = diag(K_c),
+ * n_dof values of type dtype (1 on fixed DOFs).                                      */
+int tosimp_diag_K(tosimp_ctx* ctx, const void* xphys_dev, int xdtype, void* d_dev,
+                  int dtype);
+
+/* ---- the solve -------------------------------------------------------------------
+ * tosimp_pcg_solve (paper Sec. "Preconditioned Conjugate Gradient and Warm-Start
+ * Strategy"; Sec. "BF16 Arithmetic in the Conjugate Gradient Solver" for IR mode):
+ * solve K_c(xphys) u = b.  xphys: n_elem FP64; b: n_dof FP64 (must be zero on fixed
+ * DOFs); u_inout: n_dof FP64 initial guess (warm start), overwritten by the solution
+ * (its fixed DOFs are zeroed first).
+ * PLAIN_FP64: Jacobi-PCG in FP64, stop on the recursive ||r|| <= tol ||b||.
+ * IR: outer loop in FP64 (true residual r = b - K u, u += s e) around an inner
+ * Jacobi-PCG (or NN flexible CG) in FP32 vectors on the unit-norm residual with FP32
+ * or MFMA operator; every dot product, norm, alpha and beta is accumulated in FP64.
+ * Returns OK, NOT_CONVERGED (cap hit, u valid), FALLBACK_USED, EBREAKDOWN or
+ * EPRECISION (enforce_rule and u_inner * kappa >= 1).  stats may be NULL.           */
+int tosimp_pcg_solve(tosimp_ctx* ctx, const double* xphys_dev, const double* b_dev,
+                     double* u_inout_dev, const tosimp_solve_opts* opts,
+                     tosimp_solve_stats* stats);
+
+/* ---- SIMP pieces -----------------------------------------------------------------
+ * tosimp_sensitivity (paper Sec. "Three-Dimensional SIMP Topology Optimization"):
+ * dc_e = -penal xphys_e^(penal-1) (E0 - Emin) u_e^T K_E u_e (n_elem FP64) and the
+ * compliance f^T u (FP64 host scalar; synchronises; c_host may be NULL).             */
+int tosimp_sensitivity(tosimp_ctx* ctx, const double* xphys_dev, const double* u_dev,
+                       double* dc_dev, double* c_host);
+/* Cone density filter, weights max(0, rmin - centroid distance), neighbourhood cut
+ * at the domain boundary.  FORWARD: out = H in / Hs; ADJOINT: out = H (in / Hs).
+ * in, out: n_elem FP64, must not alias.                                               */
+int tosimp_filter(tosimp_ctx* ctx, const double* in_dev, double* out_dev, int mode);
+/* Optimality-criteria update with bisection on the volume multiplier (bracket
+ * [0, 1e9], stop when (l2-l1)/(l1+l2) <= 1e-3):
+ * x_new = clip(x sqrt(-dc / (dv lambda)), max(0, x - move), min(1, x + move)) with
+ * dv = H(1/Hs); the volume test is sum(filter(x_new)) > volfrac n_elem, evaluated
+ * exactly as the weighted sum dv^T x_new.  dc must be the filtered sensitivity.
+ * Writes x_new and xphys_new = filter(x_new) (n_elem FP64), returns max|x_new - x|
+ * in *change_host and the step count in *steps_host (either may be NULL).           */
+int tosimp_oc_update(tosimp_ctx* ctx, const double* x_dev, const double* dc_dev,
+                     double volfrac, double move, double* x_new_dev,
+                     double* xphys_new_dev, double* change_host, int* steps_host);
+/* One SIMP iteration: solve K(xphys) u = f (warm start from u_inout), sensitivity,
+ * adjoint filter, OC update; x_inout and xphys_inout (n_elem FP64) are replaced by the
+ * new design, u_inout (n_dof FP64) by the solution.  Synchronises.                  */
+int tosimp_simp_step(tosimp_ctx* ctx, double* x_inout_dev, double* xphys_inout_dev,
+                     double* u_inout_dev, const tosimp_step_opts* opts,
+                     tosimp_step_stats* stats);
+
+/* ---- conditioning ----------------------------------------------------------------
+ * tosimp_lanczos (paper Sec. "Condition Number Estimation" estimates the extremes of
+ * K; here by symmetric Lanczos in FP64, no reorthogonalisation): k steps on K_c(xphys)
+ * (jacobi_scaled = 0) or on D^-1/2 K_c D^-1/2 (jacobi_scaled = 1) from the start
+ * vector v0 (n_dof FP64 device, zeroed on fixed DOFs so the Krylov space stays in the
+ * free block).  Writes alpha[0..m) and beta[0..m-1) to host arrays of length k and
+ * m to *steps_host (m < k only on an invariant subspace).  Synchronises.
+ * tosimp_tridiag_extremes: smallest and largest eigenvalue of the symmetric
+ * tridiagonal (alpha, beta) of order m by Sturm bisection (host only).              */
+int tosimp_lanczos(tosimp_ctx* ctx, const double* xphys_dev, const double* v0_dev, int k,
+                   int jacobi_scaled, double* alpha_host, double* beta_host,
+                   int* steps_host);
+int tosimp_tridiag_extremes(const double* alpha, const double* beta, int m, double* lmin,
+                            double* lmax);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TOSIMP_H */

@@ -163,3 +163,42 @@ def rigid_body_modes(nx: int, ny: int, nz: int) -> np.ndarray:
         omega[w] = 1.0
         R[:, 3 + w] = np.cross(omega[None, :], X).ravel()
     return R
+
+
+def apply_K_rows(nx, ny, nz, xphys, v, fixed_dofs, dofs, KE, E0=1.0, Emin=1e-9, penal=3.0):
+    """(K_c v)[d] for selected DOFs only, summing the contributions of the (at most
+    eight) elements around each DOF's node; for checking full-size runs one row at a
+    time.  xphys, v may be huge arrays: only the touched entries are read."""
+    fixed = np.zeros(0, dtype=np.int64) if fixed_dofs is None else np.asarray(fixed_dofs)
+    fixed_set = set(int(x) for x in fixed)
+    out = np.zeros(len(dofs))
+    for t, d in enumerate(dofs):
+        d = int(d)
+        if d in fixed_set:
+            out[t] = v[d]
+            continue
+        n, c = divmod(d, 3)
+        i = n % (nx + 1)
+        j = (n // (nx + 1)) % (ny + 1)
+        k = n // ((nx + 1) * (ny + 1))
+        s = 0.0
+        for ez in (k - 1, k):
+            for ey in (j - 1, j):
+                for ex in (i - 1, i):
+                    if not (0 <= ex < nx and 0 <= ey < ny and 0 <= ez < nz):
+                        continue
+                    e = ex + nx * (ey + ny * ez)
+                    a = (i - ex) + 2 * (j - ey) + 4 * (k - ez)
+                    Ee = Emin + xphys[e] ** penal * (E0 - Emin)
+                    ed = np.empty(24, dtype=np.int64)
+                    for b in range(8):
+                        nb = (ex + (b & 1)) + (nx + 1) * ((ey + ((b >> 1) & 1))
+                                                          + (ny + 1) * (ez + ((b >> 2) & 1)))
+                        ed[3 * b:3 * b + 3] = 3 * nb + np.arange(3)
+                    ve = v[ed].astype(np.float64)
+                    for q in range(24):
+                        if int(ed[q]) in fixed_set:
+                            ve[q] = 0.0
+                    s += Ee * (KE[3 * a + c] @ ve)
+        out[t] = s
+    return out

@@ -78,14 +78,18 @@ def sensitivity(nx, ny, nz, xphys, u, KE, E0, Emin, penal):
 
 
 # ---------------------------------------------------------------------------- OC
-def oc_update(x, dc, dv, H, Hs, volfrac, move=0.2, l1=0.0, l2=1e9, rel_tol=1e-3):
+def oc_update(x, dc, dv, H, Hs, volfrac, move=0.2, l1=0.0, l2=1e9, rel_tol=1e-3,
+              max_steps=256):
     """Optimality-criteria update with bisection on the volume multiplier.
 
-    Returns (x_new, xphys_new, change, number_of_bisection_steps)."""
+    Returns (x_new, xphys_new, change, number_of_bisection_steps).  Raises if the
+    bracket has not closed after max_steps (e.g. all sensitivities zero)."""
     n = x.size
     target = volfrac * n
     steps = 0
     while (l2 - l1) / (l1 + l2) > rel_tol:
+        if steps >= max_steps:
+            raise RuntimeError("OC bisection did not terminate")
         lmid = 0.5 * (l2 + l1)
         xnew = np.sqrt(-dc / (dv * lmid)) * x
         xnew = np.minimum(np.minimum(xnew, x + move), 1.0)

@@ -1,0 +1,281 @@
+"""ctypes binding of libtosimp.so (argument marshalling only).
+
+Every numerical step runs in the library's HIP kernels; torch tensors are used only as
+device memory and torch's current stream as the stream.  If the shared object is not
+built, importing this module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtosimp.so")
+
+OK, NOT_CONVERGED, FALLBACK_USED = 0, 1, 2
+F64, F32 = 0, 1
+PREC = {"fp64": 0, "fp32": 1, "bf16_mfma": 2, "fp16_mfma": 3}
+FILTER = {"forward": 0, "adjoint": 1}
+SOLVE = {"plain_fp64": 0, "ir": 1}
+PRECOND = {"jacobi": 0, "nn": 1}
+_DT = {torch.float64: F64, torch.float32: F32}
+
+
+class TosimpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tosimp error {code}: {msg}")
+        self.code = code
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("mode", C.c_int),
+                ("inner_prec", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int),
+                ("precond", C.c_int), ("check_every", C.c_int), ("enforce_rule", C.c_int),
+                ("kappa", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("outer_iterations", C.c_int),
+                ("fallbacks", C.c_int), ("status", C.c_int),
+                ("rel_residual", C.c_double), ("true_rel_residual", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class StepOpts(C.Structure):
+    _fields_ = [("volfrac", C.c_double), ("move", C.c_double), ("solve", SolveOpts)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("compliance", C.c_double), ("change", C.c_double), ("volume", C.c_double),
+                ("bisection_steps", C.c_int), ("solve", SolveStats)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "solve"}
+        d["solve"] = self.solve.as_dict()
+        return d
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2604_18020_amd.build` (hipcc, gfx950)")
+    lib = C.CDLL(LIB_PATH)
+    P, I, D, L = C.c_void_p, C.c_int, C.c_double, C.c_int64
+    sig = {
+        "tosimp_create": (I, [I, P, C.POINTER(P)]),
+        "tosimp_destroy": (I, [P]),
+        "tosimp_set_stream": (I, [P, P]),
+        "tosimp_last_error": (C.c_char_p, [P]),
+        "tosimp_version": (C.c_char_p, []),
+        "tosimp_set_mesh": (I, [P, I, I, I, D, D, D, D, D, D]),
+        "tosimp_set_bcs": (I, [P, P, L]),
+        "tosimp_set_loads": (I, [P, P]),
+        "tosimp_counts": (I, [P, P, P, P]),
+        "tosimp_apply_K": (I, [P, P, I, P, P, I]),
+        "tosimp_diag_K": (I, [P, P, I, P, I]),
+        "tosimp_pcg_solve": (I, [P, P, P, P, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
+        "tosimp_sensitivity": (I, [P, P, P, P, C.POINTER(D)]),
+        "tosimp_filter": (I, [P, P, P, I]),
+        "tosimp_oc_update": (I, [P, P, P, D, D, P, P, C.POINTER(D), C.POINTER(I)]),
+        "tosimp_simp_step": (I, [P, P, P, P, C.POINTER(StepOpts), C.POINTER(StepStats)]),
+        "tosimp_lanczos": (I, [P, P, P, I, I, P, P, C.POINTER(I)]),
+        "tosimp_tridiag_extremes": (I, [P, P, I, C.POINTER(D), C.POINTER(D)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype, fn.argtypes = res, args
+    return lib
+
+
+LIB = _load()
+
+
+def _ptr(t: torch.Tensor, dtype=None, numel=None, device=None, name="tensor"):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, context on cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Tosimp:
+    """One library context bound to a device; follows torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            s = torch.cuda.current_stream(self.device).cuda_stream
+        rc = LIB.tosimp_create(self.device, C.c_void_p(s), C.byref(h))
+        if rc != 0:
+            raise TosimpError(rc, "tosimp_create failed")
+        self._h = h
+        self.n_elem = self.n_node = self.n_dof = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            LIB.tosimp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ plumbing
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        LIB.tosimp_set_stream(self._h, C.c_void_p(s))
+
+    def _check(self, rc):
+        if rc < 0:
+            raise TosimpError(rc, LIB.tosimp_last_error(self._h).decode())
+        return rc
+
+    def _dev(self, t, dtype=None, numel=None, name="tensor"):
+        return _ptr(t, dtype, numel, self.device, name)
+
+    # ------------------------------------------------------------------ set-up
+    def set_mesh(self, nx, ny, nz, h=1.0, E0=1.0, Emin=1e-9, nu=0.3, penal=3.0, rmin=1.5):
+        self._sync_stream()
+        self._check(LIB.tosimp_set_mesh(self._h, nx, ny, nz, h, E0, Emin, nu, penal, rmin))
+        ne, nn, nd = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(LIB.tosimp_counts(self._h, C.byref(ne), C.byref(nn), C.byref(nd)))
+        self.n_elem, self.n_node, self.n_dof = ne.value, nn.value, nd.value
+        self.dims = (nx, ny, nz)
+        return self
+
+    def set_bcs(self, fixed_dofs):
+        a = np.ascontiguousarray(np.asarray(fixed_dofs, dtype=np.int64))
+        self._check(LIB.tosimp_set_bcs(self._h, a.ctypes.data_as(C.c_void_p), a.size))
+
+    def set_loads(self, f: torch.Tensor):
+        self._sync_stream()
+        self._check(LIB.tosimp_set_loads(self._h, self._dev(f, torch.float64, self.n_dof, "f")))
+
+    # ------------------------------------------------------------------ operator
+    def apply_K(self, x, v, y=None, prec="fp64"):
+        p = PREC[prec]
+        vt = torch.float64 if p == 0 else torch.float32
+        if y is None:
+            y = torch.empty_like(v)
+        self._sync_stream()
+        self._check(LIB.tosimp_apply_K(
+            self._h, self._dev(x, None, self.n_elem, "x"), _DT[x.dtype],
+            self._dev(v, vt, self.n_dof, "v"), self._dev(y, vt, self.n_dof, "y"), p))
+        return y
+
+    def diag_K(self, x, dtype=torch.float64):
+        d = torch.empty(self.n_dof, dtype=dtype, device=x.device)
+        self._sync_stream()
+        self._check(LIB.tosimp_diag_K(self._h, self._dev(x, None, self.n_elem, "x"),
+                                      _DT[x.dtype], self._dev(d, dtype, self.n_dof, "d"),
+                                      _DT[dtype]))
+        return d
+
+    # ------------------------------------------------------------------ solve
+    @staticmethod
+    def solve_opts(tol=1e-8, maxit=20000, mode="plain_fp64", inner_prec="fp32",
+                   inner_tol=1e-3, max_outer=30, precond="jacobi", check_every=16,
+                   enforce_rule=False, kappa=0.0):
+        return SolveOpts(tol, maxit, SOLVE[mode], PREC[inner_prec], inner_tol, max_outer,
+                         PRECOND[precond], check_every, int(enforce_rule), kappa)
+
+    def pcg_solve(self, x, b, u, **kw):
+        o = self.solve_opts(**kw)
+        s = SolveStats()
+        self._sync_stream()
+        rc = self._check(LIB.tosimp_pcg_solve(
+            self._h, self._dev(x, torch.float64, self.n_elem, "x"),
+            self._dev(b, torch.float64, self.n_dof, "b"),
+            self._dev(u, torch.float64, self.n_dof, "u"), C.byref(o), C.byref(s)))
+        d = s.as_dict()
+        d["rc"] = rc
+        return d
+
+    # ------------------------------------------------------------------ SIMP
+    def sensitivity(self, x, u, dc=None):
+        if dc is None:
+            dc = torch.empty(self.n_elem, dtype=torch.float64, device=x.device)
+        c = C.c_double()
+        self._sync_stream()
+        self._check(LIB.tosimp_sensitivity(
+            self._h, self._dev(x, torch.float64, self.n_elem, "x"),
+            self._dev(u, torch.float64, self.n_dof, "u"),
+            self._dev(dc, torch.float64, self.n_elem, "dc"), C.byref(c)))
+        return dc, c.value
+
+    def filter(self, inp, mode="forward", out=None):
+        if out is None:
+            out = torch.empty_like(inp)
+        self._sync_stream()
+        self._check(LIB.tosimp_filter(self._h, self._dev(inp, torch.float64, self.n_elem, "in"),
+                                      self._dev(out, torch.float64, self.n_elem, "out"),
+                                      FILTER[mode]))
+        return out
+
+    def oc_update(self, x, dc, volfrac, move=0.2):
+        xn = torch.empty_like(x)
+        xpn = torch.empty_like(x)
+        ch, st = C.c_double(), C.c_int()
+        self._sync_stream()
+        self._check(LIB.tosimp_oc_update(
+            self._h, self._dev(x, torch.float64, self.n_elem, "x"),
+            self._dev(dc, torch.float64, self.n_elem, "dc"), volfrac, move,
+            self._dev(xn, torch.float64, self.n_elem, "x_new"),
+            self._dev(xpn, torch.float64, self.n_elem, "xphys_new"), C.byref(ch), C.byref(st)))
+        return xn, xpn, ch.value, st.value
+
+    def simp_step(self, x, xphys, u, volfrac=0.3, move=0.2, **solve_kw):
+        o = StepOpts(volfrac, move, self.solve_opts(**solve_kw))
+        s = StepStats()
+        self._sync_stream()
+        rc = self._check(LIB.tosimp_simp_step(
+            self._h, self._dev(x, torch.float64, self.n_elem, "x"),
+            self._dev(xphys, torch.float64, self.n_elem, "xphys"),
+            self._dev(u, torch.float64, self.n_dof, "u"), C.byref(o), C.byref(s)))
+        d = s.as_dict()
+        d["rc"] = rc
+        return d
+
+    # ------------------------------------------------------------------ Lanczos
+    def lanczos(self, x, v0, k, jacobi_scaled=False):
+        a = np.zeros(k)
+        b = np.zeros(max(k, 1))
+        m = C.c_int()
+        self._sync_stream()
+        self._check(LIB.tosimp_lanczos(
+            self._h, self._dev(x, torch.float64, self.n_elem, "x"),
+            self._dev(v0, torch.float64, self.n_dof, "v0"), k, int(jacobi_scaled),
+            a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), C.byref(m)))
+        return a[:m.value].copy(), b[:max(m.value - 1, 0)].copy()
+
+
+def tridiag_extremes(alpha, beta):
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    lo, hi = C.c_double(), C.c_double()
+    rc = LIB.tosimp_tridiag_extremes(a.ctypes.data_as(C.c_void_p),
+                                     b.ctypes.data_as(C.c_void_p) if b.size else None,
+                                     a.size, C.byref(lo), C.byref(hi))
+    if rc != 0:
+        raise TosimpError(rc, "tridiag_extremes")
+    return lo.value, hi.value
+
+
+def version() -> str:
+    return LIB.tosimp_version().decode()

@@ -1,0 +1,72 @@
+"""Compile the gfx950 HIP sources of the library into an in-tree shared object.
+
+    python -m paper_2604_18020_amd.build        # or build() from Python
+
+Every translation unit in csrc/ is compiled with hipcc for gfx950 only, then linked
+into paper_2604_18020_amd/libtosimp.so next to this file.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import glob
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD_DIR = os.path.join(ROOT, "_build")
+LIB = os.path.join(HERE, "libtosimp.so")
+
+ARCH = "gfx950"
+# Packed FP32 instructions are disabled for every device pass.
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+          "-Wno-unused-but-set-variable", "-I", INCLUDE, "-I", CSRC]
+
+
+def _hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def _compile(src: str, obj: str) -> tuple[str, int, str]:
+    cmd = [_hipcc(), *COMMON, "-c", src, "-o", obj]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    return src, p.returncode, p.stdout + p.stderr
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    objs = [os.path.join(BUILD_DIR, os.path.basename(s) + ".o") for s in srcs]
+    jobs = jobs or min(8, os.cpu_count() or 1, len(srcs))
+    errors = []
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for src, rc, out in ex.map(lambda a: _compile(*a), zip(srcs, objs)):
+            if verbose or rc:
+                filt = "\n".join(l for l in out.splitlines()
+                                 if "packed-fp32-ops" not in l and "is not a recognized feature" not in l)
+                if filt.strip():
+                    print(f"--- {os.path.basename(src)}\n{filt}", file=sys.stderr)
+            if rc:
+                errors.append(src)
+    if errors:
+        raise RuntimeError("hipcc failed for: " + ", ".join(map(os.path.basename, errors)))
+    tmp = LIB + ".tmp"
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode:
+        raise RuntimeError("link failed:\n" + p.stdout + p.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

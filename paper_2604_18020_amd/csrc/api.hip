@@ -1,0 +1,813 @@
+// C ABI entry points: context, set-up, operator, solvers, SIMP pieces, Lanczos.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+using namespace tosimp;
+
+namespace tosimp {
+hipError_t kv_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
+                     const void* v, void* y, double* partials, SolverState* st,
+                     double* out, int fin, bool guarded);
+hipError_t kv_mfma_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
+                          const float* v, float* y, SolverState* st, bool guarded);
+hipError_t launch_alpha_from_dot32(const tosimp_ctx* c, const float* p, const float* q,
+                                   double* partials, SolverState* st);
+hipError_t launch_sqrt_scalar(const tosimp_ctx* c, const SolverState* st, double* out);
+}  // namespace tosimp
+
+extern "C" void tosimp_nn_release(tosimp_ctx* ctx);
+extern "C" int tosimp_nn_fcg_solve(tosimp_ctx* ctx, const float* x32, const float* b32,
+                                   float* e32, double tol, int maxit, int check_every,
+                                   int prec, int* iters, int* fallbacks, int* done);
+
+int tosimp_fail(tosimp_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+#define REQUIRE(cond, code, msg)                          \
+  do {                                                    \
+    if (!(cond)) return tosimp_fail(ctx, code, msg);      \
+  } while (0)
+
+namespace {
+
+// ------------------------------------------------------------- element stiffness
+// K_E of a cube of edge h, unit Young's modulus, Poisson ratio nu: sum over the
+// 2x2x2 Gauss points of B^T D B |J| w (exact for trilinear shape functions).
+void element_stiffness(double nu, double h, double* KE) {
+  const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const double mu = 1.0 / (2.0 * (1.0 + nu));
+  double D[6][6] = {};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) D[i][j] = lam;
+  for (int i = 0; i < 3; ++i) D[i][i] += 2.0 * mu;
+  for (int i = 3; i < 6; ++i) D[i][i] = mu;
+  const double g[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  std::memset(KE, 0, sizeof(double) * 576);
+  for (int qz = 0; qz < 2; ++qz)
+    for (int qy = 0; qy < 2; ++qy)
+      for (int qx = 0; qx < 2; ++qx) {
+        const double xi[3] = {g[qx], g[qy], g[qz]};
+        double dN[8][3];
+        for (int a = 0; a < 8; ++a) {
+          double f[3], df[3];
+          for (int d = 0; d < 3; ++d) {
+            const int bit = (a >> d) & 1;
+            f[d] = bit ? xi[d] : 1.0 - xi[d];
+            df[d] = bit ? 1.0 : -1.0;
+          }
+          // physical gradient on a cube of edge h: d/dX = (1/h) d/dxi
+          dN[a][0] = df[0] * f[1] * f[2] / h;
+          dN[a][1] = f[0] * df[1] * f[2] / h;
+          dN[a][2] = f[0] * f[1] * df[2] / h;
+        }
+        double B[6][24] = {};
+        for (int a = 0; a < 8; ++a) {
+          B[0][3 * a] = dN[a][0];
+          B[1][3 * a + 1] = dN[a][1];
+          B[2][3 * a + 2] = dN[a][2];
+          B[3][3 * a] = dN[a][1];
+          B[3][3 * a + 1] = dN[a][0];
+          B[4][3 * a + 1] = dN[a][2];
+          B[4][3 * a + 2] = dN[a][1];
+          B[5][3 * a] = dN[a][2];
+          B[5][3 * a + 2] = dN[a][0];
+        }
+        const double wJ = 0.125 * h * h * h;
+        double DB[6][24];
+        for (int i = 0; i < 6; ++i)
+          for (int j = 0; j < 24; ++j) {
+            double s = 0;
+            for (int k = 0; k < 6; ++k) s += D[i][k] * B[k][j];
+            DB[i][j] = s;
+          }
+        for (int i = 0; i < 24; ++i)
+          for (int j = 0; j < 24; ++j) {
+            double s = 0;
+            for (int k = 0; k < 6; ++k) s += B[k][i] * DB[k][j];
+            KE[i * 24 + j] += s * wJ;
+          }
+      }
+}
+
+// S = H K_E H^T in the tensor Hadamard basis; returns false if S does not have the
+// cube's 45-entry pattern (then the factored kernels cannot be used).
+bool hadamard_consts(const double* KE, HadConsts* hc, double* max_dev) {
+  double H[24][24] = {};
+  for (int m = 0; m < 8; ++m)
+    for (int a = 0; a < 8; ++a) {
+      double s = 1.0;
+      for (int d = 0; d < 3; ++d)
+        if ((m >> d) & 1) s *= ((a >> d) & 1) ? 1.0 : -1.0;
+      for (int c = 0; c < 3; ++c) H[3 * m + c][3 * a + c] = s;
+    }
+  static double S[24][24];
+  double T[24][24];
+  for (int i = 0; i < 24; ++i)
+    for (int j = 0; j < 24; ++j) {
+      double s = 0;
+      for (int k = 0; k < 24; ++k) s += H[i][k] * KE[k * 24 + j];
+      T[i][j] = s;
+    }
+  double smax = 0;
+  for (int i = 0; i < 24; ++i)
+    for (int j = 0; j < 24; ++j) {
+      double s = 0;
+      for (int k = 0; k < 24; ++k) s += T[i][k] * H[j][k];
+      S[i][j] = s;
+      smax = std::max(smax, std::fabs(s));
+    }
+  auto at = [&](int m, int c, int m2, int c2) { return S[3 * m + c][3 * m2 + c2]; };
+  const double Ad = at(1, 0, 1, 0), Ao = at(1, 0, 2, 1), Cs = at(1, 1, 1, 1);
+  const double Bd = at(3, 0, 3, 0), Bo = at(3, 0, 6, 2), Cd = at(3, 2, 3, 2);
+  const double Co = at(3, 2, 5, 1), Hg = at(7, 0, 7, 0);
+  double M[24][24] = {};
+  auto put = [&](int m, int c, int m2, int c2, double v) { M[3 * m + c][3 * m2 + c2] = v; };
+  const int nb[3][2] = {{1, 0}, {2, 1}, {4, 2}};
+  for (auto& p : nb)
+    for (auto& q : nb) put(p[0], p[1], q[0], q[1], (p[0] == q[0]) ? Ad : Ao);
+  const int sh[3][4] = {{1, 1, 2, 0}, {1, 2, 4, 0}, {2, 2, 4, 1}};
+  for (auto& s : sh) {
+    put(s[0], s[1], s[0], s[1], Cs);
+    put(s[0], s[1], s[2], s[3], Cs);
+    put(s[2], s[3], s[0], s[1], Cs);
+    put(s[2], s[3], s[2], s[3], Cs);
+  }
+  const int bp[3][4] = {{3, 0, 6, 2}, {3, 1, 5, 2}, {5, 0, 6, 1}};
+  for (auto& s : bp) {
+    put(s[0], s[1], s[0], s[1], Bd);
+    put(s[0], s[1], s[2], s[3], Bo);
+    put(s[2], s[3], s[0], s[1], Bo);
+    put(s[2], s[3], s[2], s[3], Bd);
+  }
+  const int tw[3][2] = {{3, 2}, {5, 1}, {6, 0}};
+  for (auto& p : tw)
+    for (auto& q : tw) put(p[0], p[1], q[0], q[1], (p[0] == q[0]) ? Cd : Co);
+  for (int c = 0; c < 3; ++c) put(7, c, 7, c, Hg);
+  double dev = 0;
+  for (int i = 0; i < 24; ++i)
+    for (int j = 0; j < 24; ++j) dev = std::max(dev, std::fabs(S[i][j] - M[i][j]));
+  *max_dev = dev / smax;
+  const double s = 1.0 / 64.0;
+  hc->ad = (Ad - Ao) * s;
+  hc->ao = Ao * s;
+  hc->cs = Cs * s;
+  hc->bd = Bd * s;
+  hc->bo = Bo * s;
+  hc->cd = (Cd - Co) * s;
+  hc->co = Co * s;
+  hc->hg = Hg * s;
+  return *max_dev <= 1e-12;
+}
+
+void free_ws(tosimp_ctx* c) {
+  Workspace& w = c->ws;
+  void* dev[] = {w.mask, w.f,   w.Hs,  w.dv,  w.fw,  w.dinv, w.dinv32,  w.r,
+                 w.p,    w.q,   w.w,   w.r32, w.p32, w.q32,  w.e32,     w.z32,
+                 w.x32,  w.etmp, w.partials, w.lanczos, w.st, w.oc};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  if (w.st_host) (void)hipHostFree(w.st_host);
+  if (w.oc_host) (void)hipHostFree(w.oc_host);
+  w = Workspace{};
+}
+
+template <typename P>
+hipError_t dmalloc(P** p, size_t bytes) {
+  return hipMalloc((void**)p, bytes < 256 ? 256 : bytes);
+}
+
+int check_ready(tosimp_ctx* ctx, bool need_bcs = true) {
+  if (!ctx) return TOSIMP_EINVAL;
+  if (!ctx->has_mesh) return tosimp_fail(ctx, TOSIMP_ESTATE, "no mesh: call tosimp_set_mesh first");
+  (void)need_bcs;
+  return TOSIMP_OK;
+}
+
+int set_device(tosimp_ctx* ctx) {
+  TOSIMP_HIP(ctx, hipSetDevice(ctx->device));
+  return TOSIMP_OK;
+}
+
+}  // namespace
+
+// ===================================================================== lifecycle
+extern "C" {
+
+const char* tosimp_version(void) { return "tosimp 0.1 (gfx950)"; }
+
+int tosimp_create(int device, void* stream, tosimp_ctx** out) {
+  if (!out) return TOSIMP_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TOSIMP_EINVAL;
+  tosimp_ctx* c = new (std::nothrow) tosimp_ctx();
+  if (!c) return TOSIMP_ENOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return TOSIMP_EHIP;
+  }
+  *out = c;
+  return TOSIMP_OK;
+}
+
+int tosimp_destroy(tosimp_ctx* ctx) {
+  if (!ctx) return TOSIMP_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  free_ws(ctx);
+  tosimp_nn_release(ctx);
+  delete ctx;
+  return TOSIMP_OK;
+}
+
+int tosimp_set_stream(tosimp_ctx* ctx, void* stream) {
+  if (!ctx) return TOSIMP_EINVAL;
+  ctx->stream = (hipStream_t)stream;
+  return TOSIMP_OK;
+}
+
+const char* tosimp_last_error(const tosimp_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : "null context";
+}
+
+int tosimp_counts(const tosimp_ctx* ctx, int64_t* n_elem, int64_t* n_node, int64_t* n_dof) {
+  if (!ctx || !ctx->has_mesh) return ctx ? TOSIMP_ESTATE : TOSIMP_EINVAL;
+  if (n_elem) *n_elem = ctx->n_elem;
+  if (n_node) *n_node = ctx->n_node;
+  if (n_dof) *n_dof = ctx->n_dof;
+  return TOSIMP_OK;
+}
+
+// ===================================================================== set-up
+int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0,
+                    double Emin, double nu, double penal, double rmin) {
+  if (!ctx) return TOSIMP_EINVAL;
+  REQUIRE(nx >= 1 && ny >= 1 && nz >= 1, TOSIMP_EINVAL, "mesh sizes must be >= 1");
+  REQUIRE(h > 0 && std::isfinite(h), TOSIMP_EINVAL, "h must be positive");
+  REQUIRE(E0 > 0 && Emin >= 0 && Emin < E0, TOSIMP_EINVAL, "need 0 <= Emin < E0");
+  REQUIRE(nu > -1.0 && nu < 0.5, TOSIMP_EINVAL, "nu must be in (-1, 0.5)");
+  REQUIRE(penal >= 1.0 && penal <= 16.0, TOSIMP_EINVAL, "penal must be in [1, 16]");
+  REQUIRE(rmin > 0 && rmin <= kMaxFilterR + 1, TOSIMP_EINVAL, "rmin must be in (0, 4]");
+  const int64_t n_elem = (int64_t)nx * ny * nz;
+  const int64_t n_node = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  REQUIRE(3 * n_node < (int64_t)1 << 31, TOSIMP_EINVAL, "mesh too large (n_dof >= 2^31)");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  free_ws(ctx);
+  ctx->has_mesh = ctx->has_bcs = ctx->has_loads = false;
+  ctx->nx = nx; ctx->ny = ny; ctx->nz = nz;
+  ctx->n_elem = n_elem; ctx->n_node = n_node; ctx->n_dof = 3 * n_node;
+  ctx->h = h; ctx->E0 = E0; ctx->Emin = Emin; ctx->nu = nu; ctx->penal = penal;
+  ctx->rmin = rmin;
+  element_stiffness(nu, h, ctx->KE);
+  double dev = 0;
+  if (!hadamard_consts(ctx->KE, &ctx->hc, &dev))
+    return tosimp_fail(ctx, TOSIMP_EINVAL, "element stiffness lacks the cube pattern");
+  ctx->kd = ctx->KE[0];
+  for (int i = 1; i < 24; ++i)
+    REQUIRE(std::fabs(ctx->KE[i * 25] - ctx->kd) <= 1e-14 * ctx->kd, TOSIMP_EINVAL,
+            "unequal diagonal of K_E");
+  // Filter weights on the offset cube.
+  ctx->fR = (int)std::ceil(rmin) - 1;
+  const int W = 2 * ctx->fR + 1;
+  for (int dk = 0; dk < W; ++dk)
+    for (int dj = 0; dj < W; ++dj)
+      for (int di = 0; di < W; ++di) {
+        const double d = std::sqrt((double)((di - ctx->fR) * (di - ctx->fR) +
+                                            (dj - ctx->fR) * (dj - ctx->fR) +
+                                            (dk - ctx->fR) * (dk - ctx->fR)));
+        ctx->fw_host[di + W * (dj + W * dk)] = std::max(0.0, rmin - d);
+      }
+  REQUIRE(kv_num_blocks(ctx) <= kMaxPartials, TOSIMP_EINVAL, "mesh too large for the tiling");
+
+  Workspace& w = ctx->ws;
+  const size_t nd = (size_t)ctx->n_dof, nn = (size_t)n_node, ne = (size_t)n_elem;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+  A(dmalloc(&w.mask, nn));
+  A(dmalloc(&w.f, nd * 8));
+  A(dmalloc(&w.Hs, ne * 8));
+  A(dmalloc(&w.dv, ne * 8));
+  A(dmalloc(&w.fw, sizeof(double) * kMaxFilterTaps));
+  A(dmalloc(&w.dinv, nn * 8));
+  A(dmalloc(&w.dinv32, nn * 4));
+  A(dmalloc(&w.r, nd * 8));
+  A(dmalloc(&w.p, nd * 8));
+  A(dmalloc(&w.q, nd * 8));
+  A(dmalloc(&w.w, nd * 8));
+  A(dmalloc(&w.r32, nd * 4));
+  A(dmalloc(&w.p32, nd * 4));
+  A(dmalloc(&w.q32, nd * 4));
+  A(dmalloc(&w.e32, nd * 4));
+  A(dmalloc(&w.z32, nd * 4));
+  A(dmalloc(&w.x32, ne * 4));
+  A(dmalloc(&w.etmp, ne * 8 * 4));
+  A(dmalloc(&w.partials, sizeof(double) * kMaxPartials * 4));
+  A(dmalloc(&w.st, sizeof(SolverState) * 3));
+  A(dmalloc(&w.oc, sizeof(OcState)));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&w.st_host, sizeof(SolverState) * 3);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&w.oc_host, sizeof(OcState));
+  if (e != hipSuccess) {
+    free_ws(ctx);
+    return tosimp_fail(ctx, TOSIMP_ENOMEM, std::string("workspace: ") + hipGetErrorString(e));
+  }
+  TOSIMP_HIP(ctx, hipMemsetAsync(w.mask, 0, nn, ctx->stream));
+  TOSIMP_HIP(ctx, hipMemsetAsync(w.f, 0, nd * 8, ctx->stream));
+  TOSIMP_HIP(ctx, hipMemsetAsync(w.st, 0, sizeof(SolverState) * 3, ctx->stream));
+  TOSIMP_HIP(ctx, hipMemsetAsync(w.oc, 0, sizeof(OcState), ctx->stream));
+  TOSIMP_HIP(ctx, hipMemcpyAsync(w.fw, ctx->fw_host, sizeof(double) * kMaxFilterTaps,
+                                 hipMemcpyHostToDevice, ctx->stream));
+  TOSIMP_HIP(ctx, launch_filter_rowsum(ctx, w.Hs));
+  // dv = H (1 / Hs): adjoint filter of a vector of ones.
+  double* ones = w.etmp;
+  {
+    std::vector<double> h1(ne, 1.0);
+    TOSIMP_HIP(ctx, hipMemcpyAsync(ones, h1.data(), ne * 8, hipMemcpyHostToDevice, ctx->stream));
+    TOSIMP_HIP(ctx, launch_filter(ctx, ones, w.dv, TOSIMP_FILTER_ADJOINT, w.Hs));
+    TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  ctx->has_mesh = true;
+  return TOSIMP_OK;
+}
+
+int tosimp_set_bcs(tosimp_ctx* ctx, const int64_t* fixed, int64_t n) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(n >= 0 && (n == 0 || fixed), TOSIMP_EINVAL, "bad fixed-DOF list");
+  std::vector<uint8_t> m((size_t)ctx->n_node, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t d = fixed[i];
+    REQUIRE(d >= 0 && d < ctx->n_dof, TOSIMP_EINVAL, "fixed DOF id out of range");
+    m[(size_t)(d / 3)] |= (uint8_t)(1u << (d % 3));
+  }
+  if ((rc = set_device(ctx))) return rc;
+  TOSIMP_HIP(ctx, hipMemcpyAsync(ctx->ws.mask, m.data(), m.size(), hipMemcpyHostToDevice,
+                                 ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->has_bcs = true;
+  return TOSIMP_OK;
+}
+
+int tosimp_set_loads(tosimp_ctx* ctx, const double* f_dev) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(f_dev, TOSIMP_EINVAL, "null load vector");
+  if ((rc = set_device(ctx))) return rc;
+  const size_t nd = (size_t)ctx->n_dof;
+  std::vector<double> f(nd);
+  std::vector<uint8_t> m((size_t)ctx->n_node);
+  TOSIMP_HIP(ctx, hipMemcpyAsync(f.data(), f_dev, nd * 8, hipMemcpyDeviceToHost, ctx->stream));
+  TOSIMP_HIP(ctx, hipMemcpyAsync(m.data(), ctx->ws.mask, m.size(), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (size_t i = 0; i < nd; ++i) {
+    REQUIRE(std::isfinite(f[i]), TOSIMP_EINVAL, "non-finite load");
+    if ((m[i / 3] >> (i % 3)) & 1)
+      REQUIRE(f[i] == 0.0, TOSIMP_EINVAL, "load on a fixed DOF");
+  }
+  TOSIMP_HIP(ctx, hipMemcpyAsync(ctx->ws.f, f_dev, nd * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->has_loads = true;
+  return TOSIMP_OK;
+}
+
+// ===================================================================== operator
+int tosimp_apply_K(tosimp_ctx* ctx, const void* x, int xdtype, const void* v, void* y,
+                   int prec) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(x && v && y, TOSIMP_EINVAL, "null pointer");
+  REQUIRE(v != y, TOSIMP_EINVAL, "y must not alias v");
+  REQUIRE(xdtype == TOSIMP_F64 || xdtype == TOSIMP_F32, TOSIMP_EINVAL, "bad xdtype");
+  REQUIRE(prec >= TOSIMP_PREC_FP64 && prec <= TOSIMP_PREC_FP16_MFMA, TOSIMP_EINVAL,
+          "bad precision");
+  if ((rc = set_device(ctx))) return rc;
+  if (prec == TOSIMP_PREC_BF16_MFMA || prec == TOSIMP_PREC_FP16_MFMA) {
+    TOSIMP_HIP(ctx, kv_mfma_launch(ctx, prec, xdtype, x, (const float*)v, (float*)y,
+                                   ctx->ws.st, false));
+  } else {
+    TOSIMP_HIP(ctx, kv_launch(ctx, prec, xdtype, x, v, y, nullptr, ctx->ws.st, nullptr, 0,
+                              false));
+  }
+  return TOSIMP_OK;
+}
+
+int tosimp_diag_K(tosimp_ctx* ctx, const void* x, int xdtype, void* d, int dtype) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(x && d, TOSIMP_EINVAL, "null pointer");
+  REQUIRE((xdtype == TOSIMP_F64 || xdtype == TOSIMP_F32) &&
+              (dtype == TOSIMP_F64 || dtype == TOSIMP_F32),
+          TOSIMP_EINVAL, "bad dtype");
+  if ((rc = set_device(ctx))) return rc;
+  TOSIMP_HIP(ctx, launch_diag_full(ctx, xdtype, x, dtype, d));
+  return TOSIMP_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================== solvers
+namespace {
+
+struct PcgResult {
+  int iters = 0;
+  int done = 0;
+  double rr = 0, bb = 0;
+};
+
+// Jacobi-PCG on K_c(x) with vectors of type T; b, u, dinv of type T.  When zero_guess
+// the initial iterate is 0 (u is cleared) and no initial operator application is made.
+template <typename T>
+int run_pcg(tosimp_ctx* ctx, int prec, const void* x, int xdtype, const T* b, T* u,
+            const T* dinv, int slot, double tol, int maxit, int check_every, bool zero_guess,
+            PcgResult* res) {
+  Workspace& w = ctx->ws;
+  T *r, *p, *q;
+  if constexpr (sizeof(T) == 8) {
+    r = (T*)w.r; p = (T*)w.p; q = (T*)w.q;
+  } else {
+    r = (T*)w.r32; p = (T*)w.p32; q = (T*)w.q32;
+  }
+  SolverState* st = w.st + slot;
+  SolverState* sh = w.st_host + slot;
+  // Stage the initial state through the pinned mirror (no pageable async copy).
+  *sh = SolverState{};
+  sh->aux = tol * tol;
+  sh->maxit = maxit < 1 ? 1 : maxit;
+  TOSIMP_HIP(ctx, hipMemcpyAsync(st, sh, sizeof(SolverState), hipMemcpyHostToDevice,
+                                 ctx->stream));
+  double* part = w.partials;
+  double* kvpart = w.partials + 2 * kMaxPartials;
+  if (zero_guess) {
+    TOSIMP_HIP(ctx, launch_fill_zero(ctx, u, ctx->n_dof * (int64_t)sizeof(T)));
+    TOSIMP_HIP(ctx, launch_pcg_init<T>(ctx, b, nullptr, r, p, dinv, st, part, 0));
+  } else {
+    TOSIMP_HIP(ctx, kv_launch(ctx, prec, xdtype, x, u, q, nullptr, st, nullptr, 0, false));
+    TOSIMP_HIP(ctx, launch_pcg_init<T>(ctx, b, q, r, p, dinv, st, part, 1));
+  }
+  const bool mfma = prec == TOSIMP_PREC_BF16_MFMA || prec == TOSIMP_PREC_FP16_MFMA;
+  if (check_every < 1) check_every = 1;
+  for (;;) {
+    TOSIMP_HIP(ctx, hipMemcpyAsync(sh, st, sizeof(SolverState), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+    TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (sh->done) break;
+    for (int i = 0; i < check_every; ++i) {
+      if (mfma) {
+        // MFMA operator computes q only; the step length comes from a separate dot.
+        TOSIMP_HIP(ctx, kv_mfma_launch(ctx, prec, xdtype, x, (const float*)p, (float*)q, st,
+                                       true));
+        TOSIMP_HIP(ctx, launch_alpha_from_dot32(ctx, (const float*)p, (const float*)q, kvpart, st));
+      } else {
+        TOSIMP_HIP(ctx, kv_launch(ctx, prec, xdtype, x, p, q, kvpart, st, nullptr, 1, true));
+      }
+      TOSIMP_HIP(ctx, launch_pcg_update<T>(ctx, u, r, p, q, dinv, st, part));
+      TOSIMP_HIP(ctx, launch_pcg_direction<T>(ctx, r, p, dinv, st));
+    }
+  }
+  res->iters = sh->iter;
+  res->done = sh->done;
+  res->rr = sh->rr;
+  res->bb = sh->bb;
+  return TOSIMP_OK;
+}
+
+double unit_roundoff(int prec) {
+  switch (prec) {
+    case TOSIMP_PREC_FP64: return std::ldexp(1.0, -53);
+    case TOSIMP_PREC_FP32: return std::ldexp(1.0, -24);
+    case TOSIMP_PREC_FP16_MFMA: return std::ldexp(1.0, -11);
+    case TOSIMP_PREC_BF16_MFMA: return std::ldexp(1.0, -8);
+  }
+  return 1.0;
+}
+
+// ||b - K_c u|| in FP64 into *rr (uses w.q as scratch and w.r as the residual).
+int true_residual(tosimp_ctx* ctx, const double* x, const double* b, const double* u,
+                  double* rr) {
+  Workspace& w = ctx->ws;
+  SolverState* st = w.st + 2;
+  TOSIMP_HIP(ctx, kv_launch(ctx, TOSIMP_PREC_FP64, TOSIMP_F64, x, u, w.q, nullptr, st, nullptr,
+                            0, false));
+  TOSIMP_HIP(ctx, launch_residual64(ctx, b, w.q, w.r, w.partials, st));
+  TOSIMP_HIP(ctx, hipMemcpyAsync(w.st_host + 2, st, sizeof(SolverState), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *rr = w.st_host[2].rr;
+  return TOSIMP_OK;
+}
+
+int norm2_host(tosimp_ctx* ctx, const double* a, int64_t n, double* out) {
+  Workspace& w = ctx->ws;
+  SolverState* st = w.st + 2;
+  TOSIMP_HIP(ctx, launch_dot64(ctx, a, a, n, w.partials, st, 0));
+  TOSIMP_HIP(ctx, hipMemcpyAsync(w.st_host + 2, st, sizeof(SolverState), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *out = w.st_host[2].aux;
+  return TOSIMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tosimp_pcg_solve(tosimp_ctx* ctx, const double* x, const double* b, double* u,
+                     const tosimp_solve_opts* o, tosimp_solve_stats* stats) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(x && b && u && o, TOSIMP_EINVAL, "null pointer");
+  REQUIRE(o->tol > 0 && o->maxit >= 0, TOSIMP_EINVAL, "bad tol/maxit");
+  REQUIRE(o->mode == TOSIMP_SOLVE_PLAIN_FP64 || o->mode == TOSIMP_SOLVE_IR, TOSIMP_EINVAL,
+          "bad solve mode");
+  REQUIRE(b != u, TOSIMP_EINVAL, "u must not alias b");
+  if ((rc = set_device(ctx))) return rc;
+  tosimp_solve_stats s{};
+  Workspace& w = ctx->ws;
+  TOSIMP_HIP(ctx, launch_mask_vec(ctx, u));
+  if (o->mode == TOSIMP_SOLVE_PLAIN_FP64) {
+    REQUIRE(o->precond == TOSIMP_PRECOND_JACOBI, TOSIMP_EINVAL,
+            "plain FP64 mode uses the Jacobi preconditioner");
+    TOSIMP_HIP(ctx, launch_diag_inv(ctx, x, w.dinv, nullptr));
+    PcgResult pr;
+    rc = run_pcg<double>(ctx, TOSIMP_PREC_FP64, x, TOSIMP_F64, b, u, w.dinv, 0, o->tol,
+                         o->maxit, o->check_every, false, &pr);
+    if (rc) return rc;
+    s.iterations = pr.iters;
+    s.rel_residual = pr.bb > 0 ? std::sqrt(pr.rr / pr.bb) : 0.0;
+    s.status = pr.done == 3 ? TOSIMP_EBREAKDOWN
+                            : (pr.done == 2 ? TOSIMP_NOT_CONVERGED : TOSIMP_OK);
+    double rr = 0;
+    if ((rc = true_residual(ctx, x, b, u, &rr))) return rc;
+    s.true_rel_residual = pr.bb > 0 ? std::sqrt(rr / pr.bb) : 0.0;
+  } else {
+    const int ip = o->inner_prec;
+    REQUIRE(ip == TOSIMP_PREC_FP32 || ip == TOSIMP_PREC_BF16_MFMA || ip == TOSIMP_PREC_FP16_MFMA,
+            TOSIMP_EINVAL, "IR inner precision must be FP32 or an MFMA precision");
+    REQUIRE(o->inner_tol > 0 && o->inner_tol < 1 && o->max_outer >= 1, TOSIMP_EINVAL,
+            "bad inner_tol/max_outer");
+    if (o->enforce_rule) {
+      REQUIRE(o->kappa > 0, TOSIMP_EINVAL, "enforce_rule needs kappa > 0");
+      if (unit_roundoff(ip) * o->kappa >= 1.0)
+        return tosimp_fail(ctx, TOSIMP_EPRECISION,
+                           "inner precision refused: unit roundoff * kappa >= 1");
+    }
+    TOSIMP_HIP(ctx, launch_diag_inv(ctx, x, w.dinv, w.dinv32));
+    TOSIMP_HIP(ctx, launch_copy_cast_x(ctx, x, w.x32));
+    double bb = 0;
+    if ((rc = norm2_host(ctx, b, ctx->n_dof, &bb))) return rc;
+    const double bn = std::sqrt(bb);
+    int total = 0, outer = 0, fallbacks = 0, slow = 0;
+    double prev = -1, rel = 0;
+    int status = TOSIMP_OK;
+    for (;;) {
+      double rr = 0;
+      if ((rc = true_residual(ctx, x, b, u, &rr))) return rc;  // residual left in w.r
+      rel = bn > 0 ? std::sqrt(rr) / bn : 0.0;
+      if (!std::isfinite(rel)) { status = TOSIMP_EBREAKDOWN; break; }
+      if (rel <= o->tol || bn == 0) break;
+      if (outer >= o->max_outer || total >= o->maxit) { status = TOSIMP_NOT_CONVERGED; break; }
+      if (prev > 0 && rel > 0.5 * prev) {
+        if (++slow >= 2) { status = TOSIMP_NOT_CONVERGED; break; }  // stagnation
+      } else {
+        slow = 0;
+      }
+      prev = rel;
+      const double sc = std::sqrt(rr);
+      TOSIMP_HIP(ctx, launch_scale_to32(ctx, w.r, 1.0 / sc, w.e32));  // rhs in e32
+      int it = 0, done = 0;
+      if (o->precond == TOSIMP_PRECOND_NN) {
+        int fb = 0;
+        rc = tosimp_nn_fcg_solve(ctx, w.x32, w.e32, w.z32, o->inner_tol, o->maxit - total,
+                                 o->check_every, ip, &it, &fb, &done);
+        if (rc < 0) return rc;
+        fallbacks += fb;
+      } else {
+        PcgResult pr;
+        rc = run_pcg<float>(ctx, ip, w.x32, TOSIMP_F32, w.e32, w.z32, w.dinv32, 1,
+                            o->inner_tol, o->maxit - total, o->check_every, true, &pr);
+        if (rc) return rc;
+        it = pr.iters;
+        done = pr.done;
+      }
+      total += it;
+      ++outer;
+      TOSIMP_HIP(ctx, launch_axpy_from32(ctx, u, sc, w.z32));
+      if (done == 3 && it == 0) { status = TOSIMP_EBREAKDOWN; break; }
+    }
+    s.iterations = total;
+    s.outer_iterations = outer;
+    s.fallbacks = fallbacks;
+    s.rel_residual = rel;
+    s.true_rel_residual = rel;
+    s.status = status;
+    if (status == TOSIMP_OK && fallbacks > 0) s.status = TOSIMP_FALLBACK_USED;
+  }
+  if (stats) *stats = s;
+  if (s.status < 0) return tosimp_fail(ctx, s.status, "solve failed (breakdown)");
+  return s.status;
+}
+
+// ===================================================================== SIMP pieces
+int tosimp_sensitivity(tosimp_ctx* ctx, const double* x, const double* u, double* dc,
+                       double* c_host) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(x && u && dc, TOSIMP_EINVAL, "null pointer");
+  if ((rc = set_device(ctx))) return rc;
+  TOSIMP_HIP(ctx, launch_sensitivity(ctx, x, u, dc));
+  if (c_host) {
+    Workspace& w = ctx->ws;
+    SolverState* st = w.st + 2;
+    TOSIMP_HIP(ctx, launch_dot64(ctx, w.f, u, ctx->n_dof, w.partials, st, 0));
+    TOSIMP_HIP(ctx, hipMemcpyAsync(w.st_host + 2, st, sizeof(SolverState),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+    TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *c_host = w.st_host[2].aux;
+  }
+  return TOSIMP_OK;
+}
+
+int tosimp_filter(tosimp_ctx* ctx, const double* in, double* out, int mode) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(in && out && in != out, TOSIMP_EINVAL, "null or aliased pointer");
+  REQUIRE(mode == TOSIMP_FILTER_FORWARD || mode == TOSIMP_FILTER_ADJOINT, TOSIMP_EINVAL,
+          "bad filter mode");
+  if ((rc = set_device(ctx))) return rc;
+  TOSIMP_HIP(ctx, launch_filter(ctx, in, out, mode, ctx->ws.Hs));
+  return TOSIMP_OK;
+}
+
+int tosimp_oc_update(tosimp_ctx* ctx, const double* x, const double* dc, double volfrac,
+                     double move, double* x_new, double* xphys_new, double* change_host,
+                     int* steps_host) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(x && dc && x_new && xphys_new, TOSIMP_EINVAL, "null pointer");
+  REQUIRE(x_new != x && xphys_new != x_new, TOSIMP_EINVAL, "aliased outputs");
+  REQUIRE(volfrac > 0 && volfrac <= 1 && move > 0, TOSIMP_EINVAL, "bad volfrac/move");
+  if ((rc = set_device(ctx))) return rc;
+  Workspace& w = ctx->ws;
+  *w.oc_host = OcState{};
+  w.oc_host->l1 = 0.0;
+  w.oc_host->l2 = 1e9;
+  w.oc_host->target = volfrac * (double)ctx->n_elem;
+  TOSIMP_HIP(ctx, hipMemcpyAsync(w.oc, w.oc_host, sizeof(OcState), hipMemcpyHostToDevice,
+                                 ctx->stream));
+  for (int batch = 0; batch < 16; ++batch) {
+    for (int i = 0; i < 16; ++i)
+      TOSIMP_HIP(ctx, launch_oc_step(ctx, x, dc, w.dv, move, w.oc, w.partials));
+    TOSIMP_HIP(ctx, hipMemcpyAsync(w.oc_host, w.oc, sizeof(OcState), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+    TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (w.oc_host->done) break;
+  }
+  REQUIRE(w.oc_host->done, TOSIMP_EINVAL, "OC bisection did not terminate");
+  TOSIMP_HIP(ctx, launch_oc_final(ctx, x, dc, w.dv, move, w.oc, x_new, w.partials));
+  TOSIMP_HIP(ctx, launch_filter(ctx, x_new, xphys_new, TOSIMP_FILTER_FORWARD, w.Hs));
+  TOSIMP_HIP(ctx, hipMemcpyAsync(w.oc_host, w.oc, sizeof(OcState), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (change_host) *change_host = w.oc_host->change;
+  if (steps_host) *steps_host = w.oc_host->steps;
+  return TOSIMP_OK;
+}
+
+int tosimp_simp_step(tosimp_ctx* ctx, double* x, double* xphys, double* u,
+                     const tosimp_step_opts* o, tosimp_step_stats* stats) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(x && xphys && u && o, TOSIMP_EINVAL, "null pointer");
+  REQUIRE(ctx->has_loads, TOSIMP_ESTATE, "no loads: call tosimp_set_loads first");
+  Workspace& w = ctx->ws;
+  const size_t ne = (size_t)ctx->n_elem;
+  double* dc = w.etmp;
+  double* dcf = w.etmp + ne;
+  double* xn = w.etmp + 2 * ne;
+  double* xpn = w.etmp + 3 * ne;
+  tosimp_step_stats s{};
+  rc = tosimp_pcg_solve(ctx, xphys, w.f, u, &o->solve, &s.solve);
+  if (rc < 0) return rc;
+  int rc2 = tosimp_sensitivity(ctx, xphys, u, dc, &s.compliance);
+  if (rc2) return rc2;
+  if ((rc2 = tosimp_filter(ctx, dc, dcf, TOSIMP_FILTER_ADJOINT))) return rc2;
+  if ((rc2 = tosimp_oc_update(ctx, x, dcf, o->volfrac, o->move, xn, xpn, &s.change,
+                              &s.bisection_steps)))
+    return rc2;
+  s.volume = w.oc_host->vol / (double)ne;
+  TOSIMP_HIP(ctx, hipMemcpyAsync(x, xn, ne * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  TOSIMP_HIP(ctx, hipMemcpyAsync(xphys, xpn, ne * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (stats) *stats = s;
+  return rc;
+}
+
+// ===================================================================== Lanczos
+int tosimp_lanczos(tosimp_ctx* ctx, const double* x, const double* v0, int k, int jacobi,
+                   double* alpha_host, double* beta_host, int* steps_host) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(x && v0 && alpha_host && beta_host && k >= 1, TOSIMP_EINVAL, "bad arguments");
+  if ((rc = set_device(ctx))) return rc;
+  Workspace& w = ctx->ws;
+  if (w.lanczos_cap < k + 1) {
+    if (w.lanczos) TOSIMP_HIP(ctx, hipFree(w.lanczos));
+    w.lanczos = nullptr;
+    TOSIMP_HIP(ctx, hipMalloc((void**)&w.lanczos, sizeof(double) * 2 * (size_t)(k + 1)));
+    w.lanczos_cap = k + 1;
+  }
+  double* dal = w.lanczos;               // alpha[0..k)
+  double* dbe = w.lanczos + w.lanczos_cap;  // beta[-1..k): dbe[0] = ||v0||
+  SolverState* st = w.st + 2;
+  double* s_node = nullptr;
+  if (jacobi) {
+    TOSIMP_HIP(ctx, launch_diag_inv(ctx, x, w.dinv, nullptr));
+    s_node = (double*)w.etmp;  // sqrt(dinv) per node needs n_node <= 4 n_elem doubles
+    REQUIRE(ctx->n_node <= 4 * ctx->n_elem, TOSIMP_EINVAL, "mesh too thin for Lanczos scratch");
+    TOSIMP_HIP(ctx, launch_sqrt_node(ctx, w.dinv, s_node));
+  }
+  double *q = w.p, *qprev = w.q, *wv = w.w, *tmp = w.r;
+  // q0 = v0 / ||v0||
+  TOSIMP_HIP(ctx, launch_dot64(ctx, v0, v0, ctx->n_dof, w.partials, st, 1));
+  TOSIMP_HIP(ctx, launch_sqrt_scalar(ctx, st, dbe));
+  TOSIMP_HIP(ctx, launch_lanczos_normalize(ctx, v0, dbe, q));
+  for (int j = 0; j < k; ++j) {
+    const double* in = q;
+    if (jacobi) {
+      TOSIMP_HIP(ctx, launch_node_scale(ctx, s_node, q, tmp));
+      in = tmp;
+    }
+    TOSIMP_HIP(ctx, kv_launch(ctx, TOSIMP_PREC_FP64, TOSIMP_F64, x, in, wv, w.partials, st,
+                              dal + j, 2, false));
+    TOSIMP_HIP(ctx, launch_lanczos_update(ctx, wv, q, j > 0 ? qprev : nullptr, dal + j,
+                                          j > 0 ? dbe + j : nullptr, s_node,
+                                          w.partials + kMaxPartials, dbe + j + 1));
+    TOSIMP_HIP(ctx, launch_lanczos_normalize(ctx, wv, dbe + j + 1, qprev));
+    std::swap(q, qprev);
+  }
+  std::vector<double> ha(k), hb(k + 1);
+  TOSIMP_HIP(ctx, hipMemcpyAsync(ha.data(), dal, sizeof(double) * k, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+  TOSIMP_HIP(ctx, hipMemcpyAsync(hb.data(), dbe, sizeof(double) * (k + 1),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  int m = k;
+  for (int j = 0; j < k - 1; ++j)
+    if (!(hb[j + 1] > 0.0)) {
+      m = j + 1;
+      break;
+    }
+  for (int j = 0; j < m; ++j) alpha_host[j] = ha[j];
+  for (int j = 0; j + 1 < m; ++j) beta_host[j] = hb[j + 1];
+  if (steps_host) *steps_host = m;
+  return TOSIMP_OK;
+}
+
+// Number of eigenvalues of the tridiagonal (a, b) smaller than s (Sturm count).
+static int sturm_count(const double* a, const double* b, int m, double s) {
+  int cnt = 0;
+  double d = 1.0;
+  for (int i = 0; i < m; ++i) {
+    const double b2 = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+    d = (a[i] - s) - (i > 0 ? b2 / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0) ++cnt;
+  }
+  return cnt;
+}
+
+int tosimp_tridiag_extremes(const double* a, const double* b, int m, double* lmin,
+                            double* lmax) {
+  if (!a || m < 1 || (m > 1 && !b) || !lmin || !lmax) return TOSIMP_EINVAL;
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto kth = [&](int kk) {  // kk-th smallest eigenvalue (0-based)
+    double l = lo, h = hi;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (l + h);
+      if (mid <= l || mid >= h) break;
+      if (sturm_count(a, b, m, mid) > kk) h = mid;
+      else l = mid;
+    }
+    return 0.5 * (l + h);
+  };
+  *lmin = kth(0);
+  *lmax = kth(m - 1);
+  return TOSIMP_OK;
+}
+
+}  // extern "C"

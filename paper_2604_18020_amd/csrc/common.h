@@ -1,0 +1,178 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "tosimp.h"
+
+namespace tosimp {
+
+// ---------------------------------------------------------------------------------
+// Element stiffness in the tensor Hadamard basis.
+//
+// Per axis the basis is {v0 + v1, v1 - v0}; the 8 modes of an element are the tensor
+// products, mode m = mx + 2 my + 4 mz (bit set = difference along that axis).  With H
+// the resulting 24x24 transform (acting on each displacement component), H^T H = 8 I
+// per component pair, so K_E = H^T S H / 64 with S = H K_E H^T.  On a cube S has 45
+// non-zeros in eight distinct values, grouped by the strain states they represent:
+//   normal block   {(1,x),(2,y),(4,z)}: diagonal ad + ao, off-diagonal ao
+//   shear pairs    {(1,y),(2,x)}, {(1,z),(4,x)}, {(2,z),(4,y)}: all four entries cs
+//   bending pairs  {(3,x),(6,z)}, {(3,y),(5,z)}, {(5,x),(6,y)}: diagonal bd, off bo
+//   twist block    {(3,z),(5,y),(6,x)}: diagonal cd + co, off-diagonal co
+//   hourglass      (7,c): diagonal hg
+// Constants stored here already include the 1/64 normalisation and the edge length.
+// ---------------------------------------------------------------------------------
+struct HadConsts {
+  double ad, ao, cs, bd, bo, cd, co, hg;
+};
+
+// Filter stencil (cone weights on the integer offset cube [-R, R]^3).
+constexpr int kMaxFilterR = 3;
+constexpr int kMaxFilterTaps = (2 * kMaxFilterR + 1) * (2 * kMaxFilterR + 1) * (2 * kMaxFilterR + 1);
+
+// Device-side scalar state of an iterative solve; one instance per solver level.
+struct SolverState {
+  double rz;      // <r, z> of the current iterate
+  double alpha;   // step length
+  double beta;    // direction update coefficient
+  double rr;      // ||r||^2
+  double bb;      // ||b||^2
+  double tol2;    // tol^2 * ||b||^2
+  double pq;      // <p, K p>
+  double aux;     // scratch scalar (e.g. FCG numerator)
+  int iter;       // completed iterations
+  int maxit;      // iteration cap
+  int done;       // 0 running, 1 converged, 2 cap, 3 breakdown
+  int pad;
+  unsigned cnt[4];  // last-block counters (reset by the last block)
+};
+
+// Device-side state of the OC bisection.
+struct OcState {
+  double l1, l2, lmid, target, vol, change;
+  int steps, done;
+  unsigned cnt[4];
+};
+
+constexpr int kRedBlocks = 1024;   // fixed grid of the vector kernels (deterministic)
+constexpr int kRedThreads = 256;
+constexpr int kMaxPartials = 65536;
+
+// Workspace owned by a context (device pointers unless noted).
+struct Workspace {
+  uint8_t* mask = nullptr;     // n_node: bit c set = DOF 3n+c fixed
+  double* f = nullptr;         // n_dof load vector
+  double* Hs = nullptr;        // n_elem filter row sums
+  double* dv = nullptr;        // n_elem H(1/Hs)
+  double* fw = nullptr;        // filter weights, (2R+1)^3
+  double* dinv = nullptr;      // n_node inverse Jacobi diagonal (FP64)
+  float* dinv32 = nullptr;     // n_node inverse Jacobi diagonal (FP32)
+  double* r = nullptr;         // FP64 vectors, n_dof each
+  double* p = nullptr;
+  double* q = nullptr;
+  double* w = nullptr;
+  float* r32 = nullptr;        // FP32 vectors, n_dof each
+  float* p32 = nullptr;
+  float* q32 = nullptr;
+  float* e32 = nullptr;
+  float* z32 = nullptr;
+  float* x32 = nullptr;        // n_elem FP32 density copy
+  double* etmp = nullptr;      // n_elem scratch (x 4)
+  double* partials = nullptr;  // kMaxPartials x 4
+  double* lanczos = nullptr;   // 2 x (kmax) alpha/beta on device
+  int lanczos_cap = 0;
+  SolverState* st = nullptr;   // 2 solver states (outer / inner)
+  OcState* oc = nullptr;
+  SolverState* st_host = nullptr;  // pinned host mirror
+  OcState* oc_host = nullptr;
+};
+
+}  // namespace tosimp
+
+struct tosimp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool has_mesh = false, has_bcs = false, has_loads = false;
+  int nx = 0, ny = 0, nz = 0;
+  int64_t n_elem = 0, n_node = 0, n_dof = 0;
+  double h = 1, E0 = 1, Emin = 1e-9, nu = 0.3, penal = 3, rmin = 1.5;
+  double KE[576];              // host FP64 element stiffness (edge h)
+  double kd = 0;               // common diagonal entry of K_E
+  tosimp::HadConsts hc{};
+  int fR = 0;                  // filter half-width
+  double fw_host[tosimp::kMaxFilterTaps];
+  tosimp::Workspace ws;
+  void* nn = nullptr;          // learned preconditioner state (nn.hip)
+};
+
+// ------------------------------------------------------------------ error plumbing
+int tosimp_fail(tosimp_ctx* ctx, int code, const std::string& msg);
+#define TOSIMP_HIP(ctx, call)                                                          \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return tosimp_fail(ctx, TOSIMP_EHIP,                                             \
+                         std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+// ----------------------------------------------------------- kernel launch wrappers
+namespace tosimp {
+
+// Operator kernels (kv.hip).
+hipError_t launch_apply_K(const tosimp_ctx* c, int prec, int xdtype, const void* x,
+                          const void* v, void* y, double* dot_partials, int* nblocks);
+int kv_num_blocks(const tosimp_ctx* c);
+hipError_t launch_diag_inv(const tosimp_ctx* c, const double* xphys, double* dinv64,
+                           float* dinv32);
+hipError_t launch_diag_full(const tosimp_ctx* c, int xdtype, const void* x, int dtype,
+                            void* d);
+
+// Solver kernels (vec.hip).
+hipError_t launch_finalize_dot(const tosimp_ctx* c, const double* partials, int n,
+                               SolverState* st, int what);
+template <typename T>
+hipError_t launch_pcg_init(const tosimp_ctx* c, const T* b, const T* Ku, T* r, T* p,
+                           const void* dinv, SolverState* st, double* partials, int use_Ku);
+template <typename T>
+hipError_t launch_pcg_update(const tosimp_ctx* c, T* u, T* r, const T* p, const T* q,
+                             const void* dinv, SolverState* st, double* partials);
+template <typename T>
+hipError_t launch_pcg_direction(const tosimp_ctx* c, const T* r, T* p, const void* dinv,
+                                SolverState* st);
+hipError_t launch_mask_vec(const tosimp_ctx* c, double* v);
+hipError_t launch_residual64(const tosimp_ctx* c, const double* b, const double* Ku,
+                             double* r, double* partials, SolverState* st);
+hipError_t launch_scale_to32(const tosimp_ctx* c, const double* r, double inv_s, float* r32);
+hipError_t launch_axpy_from32(const tosimp_ctx* c, double* u, double s, const float* e);
+hipError_t launch_copy_cast_x(const tosimp_ctx* c, const double* x, float* x32);
+hipError_t launch_fill_zero(const tosimp_ctx* c, void* p, int64_t bytes);
+hipError_t launch_dot64(const tosimp_ctx* c, const double* a, const double* b, int64_t n,
+                        double* partials, SolverState* st, int what);
+hipError_t launch_lanczos_update(const tosimp_ctx* c, double* w, const double* q,
+                                 const double* qprev, const double* alpha_j,
+                                 const double* beta_jm1, const double* scale_node,
+                                 double* partials, double* beta_j);
+hipError_t launch_lanczos_normalize(const tosimp_ctx* c, const double* w, const double* beta_j,
+                                    double* qnext);
+hipError_t launch_node_scale(const tosimp_ctx* c, const double* s_node, const double* v,
+                             double* out);
+hipError_t launch_sqrt_node(const tosimp_ctx* c, const double* dinv, double* out);
+
+// SIMP kernels (topopt.hip).
+hipError_t launch_sensitivity(const tosimp_ctx* c, const double* xphys, const double* u,
+                              double* dc);
+hipError_t launch_filter(const tosimp_ctx* c, const double* in, double* out, int mode,
+                         const double* Hs);
+hipError_t launch_filter_rowsum(const tosimp_ctx* c, double* Hs);
+hipError_t launch_oc_init(const tosimp_ctx* c, OcState* oc, double target);
+hipError_t launch_oc_step(const tosimp_ctx* c, const double* x, const double* dc,
+                          const double* dv, double move, OcState* oc, double* partials);
+hipError_t launch_oc_final(const tosimp_ctx* c, const double* x, const double* dc,
+                           const double* dv, double move, OcState* oc, double* xnew,
+                           double* partials);
+
+}  // namespace tosimp

@@ -1,0 +1,460 @@
+// Fused matrix-free operator y = K_c(x) v on the structured Q1 mesh (FP64 / FP32).
+//
+// Paper: Eq. (matfree) and Alg. "Fused Gather-GEMM-Scatter": one pass that gathers
+// the 24 DOFs of each element, multiplies by E_e K_E and accumulates into y.  The
+// paper uses one thread per element, K_E in shared memory and atomic scatter.
+//
+// gfx950 design (deterministic, no atomics, one launch):
+//  * A block owns a 15 x 15 column of nodes and a chunk of node planes.  Its 256
+//    threads are the 16 x 16 element columns that touch those nodes (one halo element
+//    on the low side of each axis is recomputed by the neighbouring block).
+//  * The block streams up the z axis.  Each step stages one node plane of v (17 x 17
+//    nodes x 3 components, masked) in LDS with coalesced row loads that are prefetched
+//    one plane ahead.  Each thread applies the element stiffness of its element column
+//    at the current layer and keeps every partial result in registers in the 2D
+//    (x, y) Hadamard basis: the forward transform of a plane is reused as the bottom
+//    face of the next layer, and the top-face contributions of a layer are added to
+//    the bottom-face contributions of the next before a single inverse transform.
+//  * K_E is applied in factored form K_E = H^T S H / 64 (45 non-zeros in S, eight
+//    distinct values, see common.h): about 150 VALU ops per element instead of 1,152.
+//  * Each node sums the four element-column contributions around it from LDS in a
+//    fixed order and is written once, coalesced.  Fixed DOFs output y = v.
+//  * Block ids are remapped so that each XCD gets a contiguous range of tiles.
+//  * Optionally the block's share of <v, y> (FP64) is reduced and the last block
+//    finalises it (CG step length, Lanczos alpha).
+#include "common.h"
+#include "dev.h"
+
+namespace tosimp {
+
+constexpr int KBX = 16, KBY = 16;  // element columns per block (x, y)
+
+template <typename T>
+struct KvC {
+  T ad, ao, cs, bd, bo, cd, co, hg;
+};
+
+enum KvFin { FIN_NONE = 0, FIN_ALPHA = 1, FIN_SCALAR = 2 };
+
+template <typename T, typename XT>
+struct KvArgs {
+  const T* v;
+  T* y;
+  const XT* x;
+  const uint8_t* mask;
+  double* partials;   // one slot per tile when a dot is requested
+  SolverState* st;    // FIN_ALPHA target
+  double* out;        // FIN_SCALAR target
+  int fin;
+  int nx, ny, nz;
+  int tiles_x, tiles_y, chunks_z, kz, ntiles, per_xcd;
+  T E0mEmin, Emin;
+  T penal;
+  KvC<T> k;
+};
+
+template <typename T, typename XT, bool P3>
+__device__ __forceinline__ T simp_E(XT xv, T Emin, T E0mEmin, T penal) {
+  T x = static_cast<T>(xv);
+  T xp;
+  if constexpr (P3) {
+    xp = x * x * x;
+  } else {
+    xp = x > T(0) ? pow(x, penal) : T(0);
+  }
+  return Emin + xp * E0mEmin;
+}
+
+template <typename T, typename XT, bool P3, bool DOT>
+__device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
+  constexpr int NXL = KBX + 1, NYL = KBY + 1, ROW = 3 * NXL, NPV = ROW * NYL;
+  constexpr int NLD = (NPV + 255) / 256;
+  __shared__ T sv[NPV];
+  __shared__ T sc[KBY * KBX * 12];
+  __shared__ uint8_t sm[NXL * NYL];
+  __shared__ double sred[4];
+
+  const int bid = blockIdx.x;
+  const int t = (bid & 7) * A.per_xcd + (bid >> 3);
+  if (t >= A.ntiles) return;  // whole block: padding of the XCD remap
+  const int tx = t % A.tiles_x;
+  const int rest = t / A.tiles_x;
+  const int ty = rest % A.tiles_y;
+  const int cz = rest / A.tiles_y;
+
+  const int tid = threadIdx.x, lx = tid % KBX, ly = tid / KBX;
+  const int ex0 = tx * (KBX - 1) - 1, ey0 = ty * (KBY - 1) - 1;
+  const int k0 = cz * A.kz;
+  const int k1 = min(k0 + A.kz, A.nz + 1);
+  const int NX1 = A.nx + 1;
+  const int64_t plane = (int64_t)NX1 * (A.ny + 1);
+
+  // Plane-load slots: flat LDS index f = jl*ROW + il*3 + c matches a contiguous row
+  // segment of the interleaved vector, so consecutive threads read consecutive words.
+  int goff[NLD];
+  int gcomp[NLD];
+  bool gok[NLD];
+#pragma unroll
+  for (int s = 0; s < NLD; ++s) {
+    const int f = tid + 256 * s;
+    const int jl = f / ROW, w = f - jl * ROW, il = w / 3, c = w - il * 3;
+    const int i = ex0 + il, j = ey0 + jl;
+    gok[s] = f < NPV && i >= 0 && i <= A.nx && j >= 0 && j <= A.ny;
+    goff[s] = gok[s] ? i + NX1 * j : 0;
+    gcomp[s] = c;
+  }
+  T pv[NLD];
+  uint8_t pm[NLD];
+  auto prefetch = [&](int k) {
+    const bool kok = k >= 0 && k <= A.nz;
+#pragma unroll
+    for (int s = 0; s < NLD; ++s) {
+      pv[s] = T(0);
+      pm[s] = 0;
+      if (gok[s] && kok) {
+        const int64_t n = goff[s] + plane * k;
+        const uint8_t m = A.mask[n];
+        const T val = A.v[3 * n + gcomp[s]];
+        pv[s] = ((m >> gcomp[s]) & 1) ? T(0) : val;
+        pm[s] = m;
+      }
+    }
+  };
+
+  // Element column of this thread.
+  const int ex = ex0 + lx, ey = ey0 + ly;
+  const bool exy_ok = ex >= 0 && ex < A.nx && ey >= 0 && ey < A.ny;
+  const int64_t ebase = exy_ok ? (int64_t)ex + (int64_t)A.nx * ey : 0;
+  const int64_t elayer = (int64_t)A.nx * A.ny;
+  auto layer_ok = [&](int ez) { return exy_ok && ez >= 0 && ez < A.nz; };
+  auto load_x = [&](int ez) -> XT { return layer_ok(ez) ? A.x[ebase + elayer * ez] : XT(0); };
+  // Node owned by this thread in the output phase: local (lx+1, ly+1).
+  const int ni = ex0 + lx + 1, nj = ey0 + ly + 1;
+  const bool owner = lx < KBX - 1 && ly < KBY - 1 && ni <= A.nx && nj <= A.ny;
+  const int64_t nbase = (int64_t)ni + (int64_t)NX1 * nj;
+
+  T tb[12], acc[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    tb[i] = T(0);
+    acc[i] = T(0);
+  }
+  T vown[3] = {T(0), T(0), T(0)};
+  uint8_t mown = 0;
+  double dotacc = 0.0;
+
+  prefetch(k0 - 1);
+  XT xnext = load_x(k0 - 1);
+  bool xnext_ok = layer_ok(k0 - 1);
+  bool need_sync = false;
+
+  for (int p = k0 - 1; p <= k1; ++p) {
+    if (need_sync) __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NLD; ++s) {
+      const int f = tid + 256 * s;
+      if (f < NPV) {
+        sv[f] = pv[s];
+        if (gcomp[s] == 0) sm[f / 3] = pm[s];
+      }
+    }
+    __syncthreads();
+    const XT xcur = xnext;
+    const bool xcur_ok = xnext_ok;
+    if (p < k1) prefetch(p + 1);
+    if (p >= k0 && p < k1) {
+      xnext = load_x(p);
+      xnext_ok = layer_ok(p);
+    }
+
+    // Forward 2D transform of the top face (plane p) of this element column.
+    T tt[12];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T v00 = sv[ly * ROW + lx * 3 + c];
+      const T v10 = sv[ly * ROW + (lx + 1) * 3 + c];
+      const T v01 = sv[(ly + 1) * ROW + lx * 3 + c];
+      const T v11 = sv[(ly + 1) * ROW + (lx + 1) * 3 + c];
+      const T a0 = v00 + v10, a1 = v10 - v00, b0 = v01 + v11, b1 = v11 - v01;
+      tt[0 * 3 + c] = a0 + b0;
+      tt[1 * 3 + c] = a1 + b1;
+      tt[2 * 3 + c] = b0 - a0;
+      tt[3 * 3 + c] = b1 - a1;
+    }
+    T vnew[3];
+    uint8_t mnew = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vnew[c] = sv[(ly + 1) * ROW + (lx + 1) * 3 + c];
+    mnew = sm[(ly + 1) * NXL + lx + 1];
+
+    need_sync = true;
+    if (p >= k0) {
+      // ---- element layer ez = p - 1: bottom face tb, top face tt -------------
+      const T E = xcur_ok ? simp_E<T, XT, P3>(xcur, A.Emin, A.E0mEmin, A.penal) : T(0);
+      // 3D Hadamard coefficients: mode m = m2 + 4 mz.
+#define HB(m2, c) (tb[(m2) * 3 + (c)] + tt[(m2) * 3 + (c)])
+#define HT(m2, c) (tt[(m2) * 3 + (c)] - tb[(m2) * 3 + (c)])
+      const T h1x = HB(1, 0), h1y = HB(1, 1), h1z = HB(1, 2);
+      const T h2x = HB(2, 0), h2y = HB(2, 1), h2z = HB(2, 2);
+      const T h3x = HB(3, 0), h3y = HB(3, 1), h3z = HB(3, 2);
+      const T h4x = HT(0, 0), h4y = HT(0, 1), h4z = HT(0, 2);
+      const T h5x = HT(1, 0), h5y = HT(1, 1), h5z = HT(1, 2);
+      const T h6x = HT(2, 0), h6y = HT(2, 1), h6z = HT(2, 2);
+      const T h7x = HT(3, 0), h7y = HT(3, 1), h7z = HT(3, 2);
+#undef HB
+#undef HT
+      const T kad = E * A.k.ad, kao = E * A.k.ao, kcs = E * A.k.cs, kbd = E * A.k.bd;
+      const T kbo = E * A.k.bo, kcd = E * A.k.cd, kco = E * A.k.co, khg = E * A.k.hg;
+      // normal-strain block
+      const T sA = kao * (h1x + h2y + h4z);
+      const T g1x = kad * h1x + sA, g2y = kad * h2y + sA, g4z = kad * h4z + sA;
+      // shear pairs
+      const T s1 = kcs * (h1y + h2x), s2 = kcs * (h1z + h4x), s3 = kcs * (h2z + h4y);
+      const T g1y = s1, g2x = s1, g1z = s2, g4x = s2, g2z = s3, g4y = s3;
+      // bending pairs
+      const T g3x = kbd * h3x + kbo * h6z, g6z = kbo * h3x + kbd * h6z;
+      const T g3y = kbd * h3y + kbo * h5z, g5z = kbo * h3y + kbd * h5z;
+      const T g5x = kbd * h5x + kbo * h6y, g6y = kbo * h5x + kbd * h6y;
+      // twist block
+      const T sC = kco * (h3z + h5y + h6x);
+      const T g3z = kcd * h3z + sC, g5y = kcd * h5y + sC, g6x = kcd * h6x + sC;
+      // hourglass
+      const T g7x = khg * h7x, g7y = khg * h7y, g7z = khg * h7z;
+
+      // Inverse z stage: bottom face gets g[m2] - g[m2+4], top face g[m2] + g[m2+4].
+      T R[12];
+      R[0] = acc[0] - g4x;  R[1] = acc[1] - g4y;  R[2] = acc[2] - g4z;
+      R[3] = acc[3] + (g1x - g5x);  R[4] = acc[4] + (g1y - g5y);  R[5] = acc[5] + (g1z - g5z);
+      R[6] = acc[6] + (g2x - g6x);  R[7] = acc[7] + (g2y - g6y);  R[8] = acc[8] + (g2z - g6z);
+      R[9] = acc[9] + (g3x - g7x);  R[10] = acc[10] + (g3y - g7y); R[11] = acc[11] + (g3z - g7z);
+      acc[0] = g4x;  acc[1] = g4y;  acc[2] = g4z;
+      acc[3] = g1x + g5x;  acc[4] = g1y + g5y;  acc[5] = g1z + g5z;
+      acc[6] = g2x + g6x;  acc[7] = g2y + g6y;  acc[8] = g2z + g6z;
+      acc[9] = g3x + g7x;  acc[10] = g3y + g7y; acc[11] = g3z + g7z;
+
+      if (p - 1 >= k0) {
+        // ---- node plane p-1 is complete in R: inverse 2D transform to corners --
+        T* out = sc + (ly * KBX + lx) * 12;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T u0 = R[0 * 3 + c] - R[2 * 3 + c], u1 = R[1 * 3 + c] - R[3 * 3 + c];
+          const T w0 = R[0 * 3 + c] + R[2 * 3 + c], w1 = R[1 * 3 + c] + R[3 * 3 + c];
+          out[0 * 3 + c] = u0 - u1;  // corner (0,0)
+          out[1 * 3 + c] = u0 + u1;  // corner (1,0)
+          out[2 * 3 + c] = w0 - w1;  // corner (0,1)
+          out[3 * 3 + c] = w0 + w1;  // corner (1,1)
+        }
+        __syncthreads();
+        need_sync = false;
+        if (owner) {
+          const T* e00 = sc + (ly * KBX + lx) * 12;           // corner (1,1)
+          const T* e10 = sc + (ly * KBX + lx + 1) * 12;       // corner (0,1)
+          const T* e01 = sc + ((ly + 1) * KBX + lx) * 12;     // corner (1,0)
+          const T* e11 = sc + ((ly + 1) * KBX + lx + 1) * 12; // corner (0,0)
+          const int64_t n = nbase + plane * (p - 1);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            T yv = (e00[9 + c] + e10[6 + c]) + (e01[3 + c] + e11[0 + c]);
+            if ((mown >> c) & 1) yv = A.v[3 * n + c];
+            A.y[3 * n + c] = yv;
+            if constexpr (DOT) dotacc += (double)vown[c] * (double)yv;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 12; ++i) tb[i] = tt[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vown[c] = vnew[c];
+    mown = mnew;
+  }
+
+  if constexpr (DOT) {
+    const double bsum = block_sum<256>(dotacc, sred);
+    if (threadIdx.x == 0) A.partials[t] = bsum;
+    if (last_block_arrive(&A.st->cnt[0], (unsigned)A.ntiles)) {
+      const double tot = sum_partials<256>(A.partials, A.ntiles, 1, sred);
+      if (threadIdx.x == 0) {
+        if (A.fin == FIN_ALPHA) {
+          SolverState* st = A.st;
+          st->pq = tot;
+          if (!(tot > 0.0) || !finite_val(tot)) {
+            st->done = 3;  // breakdown
+            st->alpha = 0.0;
+          } else {
+            st->alpha = st->rz / tot;
+          }
+        } else if (A.fin == FIN_SCALAR) {
+          *A.out = tot;
+        }
+        A.st->cnt[0] = 0u;
+      }
+    }
+  }
+}
+
+template <typename T, typename XT, bool P3, bool DOT>
+__global__ __launch_bounds__(256) void kv_stream(KvArgs<T, XT> A) {
+  kv_body<T, XT, P3, DOT>(A);
+}
+
+// Solver variant: skips the whole operator once the solve has finished, so batches of
+// iterations can be enqueued without a host round trip per iteration.
+template <typename T, typename XT, bool P3, bool DOT>
+__global__ __launch_bounds__(256) void kv_stream_guarded(KvArgs<T, XT> A) {
+  if (A.st->done) return;
+  kv_body<T, XT, P3, DOT>(A);
+}
+
+// ------------------------------------------------------------------ host side
+struct KvGeom {
+  int tiles_x, tiles_y, chunks_z, kz, ntiles, per_xcd, grid;
+};
+
+static KvGeom kv_geom(const tosimp_ctx* c) {
+  KvGeom g;
+  g.tiles_x = (c->nx + 1 + KBX - 2) / (KBX - 1);
+  g.tiles_y = (c->ny + 1 + KBY - 2) / (KBY - 1);
+  const int cols = g.tiles_x * g.tiles_y;
+  // Aim for >= ~2048 blocks (8 per CU) while keeping chunks >= 4 planes deep.
+  int chunks = (2048 + cols - 1) / cols;
+  int kz = (c->nz + 1 + chunks - 1) / chunks;
+  if (kz < 4) kz = 4;
+  g.kz = kz;
+  g.chunks_z = (c->nz + 1 + kz - 1) / kz;
+  g.ntiles = cols * g.chunks_z;
+  g.per_xcd = (g.ntiles + 7) / 8;
+  g.grid = g.per_xcd * 8;
+  return g;
+}
+
+int kv_num_blocks(const tosimp_ctx* c) { return kv_geom(c).ntiles; }
+
+template <typename T>
+static KvC<T> kv_consts(const tosimp_ctx* c) {
+  KvC<T> k;
+  k.ad = (T)c->hc.ad; k.ao = (T)c->hc.ao; k.cs = (T)c->hc.cs; k.bd = (T)c->hc.bd;
+  k.bo = (T)c->hc.bo; k.cd = (T)c->hc.cd; k.co = (T)c->hc.co; k.hg = (T)c->hc.hg;
+  return k;
+}
+
+template <typename T, typename XT>
+static hipError_t kv_launch_t(const tosimp_ctx* c, const XT* x, const T* v, T* y,
+                              double* partials, SolverState* st, double* out, int fin,
+                              bool guarded) {
+  const KvGeom g = kv_geom(c);
+  KvArgs<T, XT> A;
+  A.v = v; A.y = y; A.x = x; A.mask = c->ws.mask;
+  A.partials = partials; A.st = st; A.out = out; A.fin = fin;
+  A.nx = c->nx; A.ny = c->ny; A.nz = c->nz;
+  A.tiles_x = g.tiles_x; A.tiles_y = g.tiles_y; A.chunks_z = g.chunks_z; A.kz = g.kz;
+  A.ntiles = g.ntiles; A.per_xcd = g.per_xcd;
+  A.E0mEmin = (T)(c->E0 - c->Emin); A.Emin = (T)c->Emin; A.penal = (T)c->penal;
+  A.k = kv_consts<T>(c);
+  const bool p3 = c->penal == 3.0;
+  const bool dot = fin != FIN_NONE;
+  dim3 grid(g.grid), block(256);
+  if (guarded) {
+    if (p3 && dot) kv_stream_guarded<T, XT, true, true><<<grid, block, 0, c->stream>>>(A);
+    else if (p3) kv_stream_guarded<T, XT, true, false><<<grid, block, 0, c->stream>>>(A);
+    else if (dot) kv_stream_guarded<T, XT, false, true><<<grid, block, 0, c->stream>>>(A);
+    else kv_stream_guarded<T, XT, false, false><<<grid, block, 0, c->stream>>>(A);
+  } else {
+    if (p3 && dot) kv_stream<T, XT, true, true><<<grid, block, 0, c->stream>>>(A);
+    else if (p3) kv_stream<T, XT, true, false><<<grid, block, 0, c->stream>>>(A);
+    else if (dot) kv_stream<T, XT, false, true><<<grid, block, 0, c->stream>>>(A);
+    else kv_stream<T, XT, false, false><<<grid, block, 0, c->stream>>>(A);
+  }
+  return hipGetLastError();
+}
+
+hipError_t kv_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
+                     const void* v, void* y, double* partials, SolverState* st,
+                     double* out, int fin, bool guarded) {
+  if (prec == TOSIMP_PREC_FP64) {
+    if (xdtype == TOSIMP_F64)
+      return kv_launch_t<double, double>(c, (const double*)x, (const double*)v, (double*)y,
+                                         partials, st, out, fin, guarded);
+    return kv_launch_t<double, float>(c, (const float*)x, (const double*)v, (double*)y,
+                                      partials, st, out, fin, guarded);
+  }
+  if (xdtype == TOSIMP_F64)
+    return kv_launch_t<float, double>(c, (const double*)x, (const float*)v, (float*)y,
+                                      partials, st, out, fin, guarded);
+  return kv_launch_t<float, float>(c, (const float*)x, (const float*)v, (float*)y, partials,
+                                   st, out, fin, guarded);
+}
+
+// ------------------------------------------------------------ Jacobi diagonal
+// Every diagonal entry of K_E is the same value kd, so diag(K)_(n,c) = kd * sum of E
+// over the (at most eight) elements around node n, identical for the three components.
+template <typename XT, bool P3>
+__global__ __launch_bounds__(256) void diag_node_kernel(const XT* __restrict__ x, int nx,
+                                                        int ny, int nz, double kd,
+                                                        double Emin, double E0mEmin,
+                                                        double penal, double* dinv64,
+                                                        float* dinv32, double* dfull,
+                                                        float* dfull32,
+                                                        const uint8_t* mask) {
+  const int64_t NX1 = nx + 1, NY1 = ny + 1;
+  const int64_t n_node = NX1 * NY1 * (nz + 1);
+  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < n_node;
+       n += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % NX1);
+    const int64_t r = n / NX1;
+    const int j = (int)(r % NY1);
+    const int k = (int)(r / NY1);
+    double s = 0.0;
+    for (int dz = -1; dz <= 0; ++dz)
+      for (int dy = -1; dy <= 0; ++dy)
+        for (int dx = -1; dx <= 0; ++dx) {
+          const int ex = i + dx, ey = j + dy, ez = k + dz;
+          if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
+          const double xv = (double)x[ex + (int64_t)nx * (ey + (int64_t)ny * ez)];
+          const double xp = P3 ? xv * xv * xv : (xv > 0.0 ? pow(xv, penal) : 0.0);
+          s += Emin + xp * E0mEmin;
+        }
+    const double d = kd * s;
+    if (dinv64) dinv64[n] = 1.0 / d;
+    if (dinv32) dinv32[n] = (float)(1.0 / d);
+    if (dfull || dfull32) {
+      const uint8_t m = mask[n];
+      for (int c = 0; c < 3; ++c) {
+        const double dc = ((m >> c) & 1) ? 1.0 : d;
+        if (dfull) dfull[3 * n + c] = dc;
+        if (dfull32) dfull32[3 * n + c] = (float)dc;
+      }
+    }
+  }
+}
+
+template <typename XT>
+static hipError_t diag_launch(const tosimp_ctx* c, const XT* x, double* dinv64,
+                              float* dinv32, double* dfull, float* dfull32) {
+  const bool p3 = c->penal == 3.0;
+  dim3 grid(2048), block(256);
+  if (p3)
+    diag_node_kernel<XT, true><<<grid, block, 0, c->stream>>>(
+        x, c->nx, c->ny, c->nz, c->kd, c->Emin, c->E0 - c->Emin, c->penal, dinv64, dinv32,
+        dfull, dfull32, c->ws.mask);
+  else
+    diag_node_kernel<XT, false><<<grid, block, 0, c->stream>>>(
+        x, c->nx, c->ny, c->nz, c->kd, c->Emin, c->E0 - c->Emin, c->penal, dinv64, dinv32,
+        dfull, dfull32, c->ws.mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_inv(const tosimp_ctx* c, const double* xphys, double* dinv64,
+                           float* dinv32) {
+  return diag_launch<double>(c, xphys, dinv64, dinv32, nullptr, nullptr);
+}
+
+hipError_t launch_diag_full(const tosimp_ctx* c, int xdtype, const void* x, int dtype,
+                            void* d) {
+  double* d64 = dtype == TOSIMP_F64 ? (double*)d : nullptr;
+  float* d32 = dtype == TOSIMP_F32 ? (float*)d : nullptr;
+  if (xdtype == TOSIMP_F64) return diag_launch<double>(c, (const double*)x, nullptr, nullptr, d64, d32);
+  return diag_launch<float>(c, (const float*)x, nullptr, nullptr, d64, d32);
+}
+
+}  // namespace tosimp

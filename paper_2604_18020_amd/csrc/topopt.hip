@@ -1,0 +1,205 @@
+// SIMP kernels: element sensitivities, cone density filter, OC bisection (FP64).
+//
+// Paper: Sec. "Three-Dimensional SIMP Topology Optimization" (analytic sensitivities,
+// cone filter of radius rmin, optimality-criteria update with bisection on the volume
+// multiplier).  The update rule, the filter chain rule and the bisection constants are
+// the standard density-filter SIMP ones (bracket [0, 1e9], relative width 1e-3).
+#include "common.h"
+#include "dev.h"
+
+namespace tosimp {
+
+// ------------------------------------------------------------ sensitivities
+// ce_e = u_e^T K_E u_e evaluated in the Hadamard basis as hat^T S hat (hat = H u_e);
+// dc_e = -p x^(p-1) (E0 - Emin) ce_e.
+__global__ __launch_bounds__(256) void sensitivity_kernel(
+    const double* __restrict__ x, const double* __restrict__ u, double* __restrict__ dc,
+    int nx, int ny, int nz, HadConsts k, double penal, double E0mEmin) {
+  const int64_t n_elem = (int64_t)nx * ny * nz;
+  const int64_t NX1 = nx + 1, plane = NX1 * (ny + 1);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_elem;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int ex = (int)(e % nx);
+    const int64_t r = e / nx;
+    const int ey = (int)(r % ny);
+    const int ez = (int)(r / ny);
+    const int64_t n0 = ex + NX1 * ey + plane * ez;
+    double h[8][3];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int64_t n = n0 + (a & 1) + NX1 * ((a >> 1) & 1) + plane * ((a >> 2) & 1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) h[a][c] = u[3 * n + c];
+    }
+    // Butterflies along x, y, z: afterwards h[m][c] is mode m (bit set = difference).
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (!(a & bit))
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double s = h[a][c] + h[a | bit][c], d = h[a | bit][c] - h[a][c];
+            h[a][c] = s;
+            h[a | bit][c] = d;
+          }
+    const double sA = k.ao * (h[1][0] + h[2][1] + h[4][2]);
+    const double sC = k.co * (h[3][2] + h[5][1] + h[6][0]);
+    const double s1 = k.cs * (h[1][1] + h[2][0]);
+    const double s2 = k.cs * (h[1][2] + h[4][0]);
+    const double s3 = k.cs * (h[2][2] + h[4][1]);
+    double ce = 0.0;
+    ce += h[1][0] * (k.ad * h[1][0] + sA) + h[2][1] * (k.ad * h[2][1] + sA) +
+          h[4][2] * (k.ad * h[4][2] + sA);
+    ce += s1 * (h[1][1] + h[2][0]) + s2 * (h[1][2] + h[4][0]) + s3 * (h[2][2] + h[4][1]);
+    ce += h[3][0] * (k.bd * h[3][0] + k.bo * h[6][2]) + h[6][2] * (k.bo * h[3][0] + k.bd * h[6][2]);
+    ce += h[3][1] * (k.bd * h[3][1] + k.bo * h[5][2]) + h[5][2] * (k.bo * h[3][1] + k.bd * h[5][2]);
+    ce += h[5][0] * (k.bd * h[5][0] + k.bo * h[6][1]) + h[6][1] * (k.bo * h[5][0] + k.bd * h[6][1]);
+    ce += h[3][2] * (k.cd * h[3][2] + sC) + h[5][1] * (k.cd * h[5][1] + sC) +
+          h[6][0] * (k.cd * h[6][0] + sC);
+    ce += k.hg * (h[7][0] * h[7][0] + h[7][1] * h[7][1] + h[7][2] * h[7][2]);
+    const double xv = x[e];
+    const double dxp = penal == 3.0 ? 3.0 * xv * xv
+                                    : (xv > 0.0 ? penal * pow(xv, penal - 1.0) : 0.0);
+    dc[e] = -dxp * E0mEmin * ce;
+  }
+}
+
+hipError_t launch_sensitivity(const tosimp_ctx* c, const double* xphys, const double* u,
+                              double* dc) {
+  sensitivity_kernel<<<2048, 256, 0, c->stream>>>(xphys, u, dc, c->nx, c->ny, c->nz, c->hc,
+                                                  c->penal, c->E0 - c->Emin);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ filter
+// Cone filter over the offset cube [-R, R]^3 with weights w (zero outside the cone).
+// mode 0: out = sum w in_j / Hs_e; mode 1: out = sum w in_j / Hs_j; mode 2: Hs = sum w.
+__global__ __launch_bounds__(256) void filter_kernel(const double* __restrict__ in,
+                                                     double* __restrict__ out,
+                                                     const double* __restrict__ Hs,
+                                                     const double* __restrict__ w, int R,
+                                                     int nx, int ny, int nz, int mode) {
+  const int64_t n_elem = (int64_t)nx * ny * nz;
+  const int W = 2 * R + 1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_elem;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int ex = (int)(e % nx);
+    const int64_t r = e / nx;
+    const int ey = (int)(r % ny);
+    const int ez = (int)(r / ny);
+    double s = 0.0;
+    for (int dk = -R; dk <= R; ++dk) {
+      const int jz = ez + dk;
+      if (jz < 0 || jz >= nz) continue;
+      for (int dj = -R; dj <= R; ++dj) {
+        const int jy = ey + dj;
+        if (jy < 0 || jy >= ny) continue;
+        for (int di = -R; di <= R; ++di) {
+          const int jx = ex + di;
+          if (jx < 0 || jx >= nx) continue;
+          const double wt = w[(di + R) + W * ((dj + R) + W * (dk + R))];
+          if (wt <= 0.0) continue;
+          const int64_t j = jx + (int64_t)nx * (jy + (int64_t)ny * jz);
+          if (mode == 2) s += wt;
+          else if (mode == 1) s += wt * (in[j] / Hs[j]);
+          else s += wt * in[j];
+        }
+      }
+    }
+    out[e] = mode == 0 ? s / Hs[e] : s;
+  }
+}
+
+hipError_t launch_filter(const tosimp_ctx* c, const double* in, double* out, int mode,
+                         const double* Hs) {
+  filter_kernel<<<2048, 256, 0, c->stream>>>(in, out, Hs, c->ws.fw, c->fR, c->nx, c->ny,
+                                             c->nz, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_rowsum(const tosimp_ctx* c, double* Hs) {
+  filter_kernel<<<2048, 256, 0, c->stream>>>(nullptr, Hs, nullptr, c->ws.fw, c->fR, c->nx,
+                                             c->ny, c->nz, 2);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------- OC
+__device__ __forceinline__ double oc_x(double xv, double dcv, double dvv, double lmid,
+                                       double move) {
+  double xn = sqrt(-dcv / (dvv * lmid)) * xv;
+  xn = fmin(fmin(xn, xv + move), 1.0);
+  xn = fmax(fmax(xn, xv - move), 0.0);
+  return xn;
+}
+
+// One bisection step: volume dv^T x_new(lmid) against the target moves l1 or l2.
+__global__ __launch_bounds__(kRedThreads) void oc_step_kernel(
+    const double* __restrict__ x, const double* __restrict__ dc, const double* __restrict__ dv,
+    double move, int64_t n, OcState* oc, double* partials) {
+  __shared__ double sred[kRedThreads / 64];
+  if (oc->done) return;
+  const double lmid = 0.5 * (oc->l2 + oc->l1);
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads)
+    s += dv[i] * oc_x(x[i], dc[i], dv[i], lmid, move);
+  const double bs = block_sum<kRedThreads>(s, sred);
+  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+  if (last_block_arrive(&oc->cnt[0], gridDim.x)) {
+    const double vol = sum_partials<kRedThreads>(partials, gridDim.x, 1, sred);
+    if (threadIdx.x == 0) {
+      oc->vol = vol;
+      oc->lmid = lmid;
+      if (vol > oc->target) oc->l1 = lmid;
+      else oc->l2 = lmid;
+      oc->steps += 1;
+      if (!((oc->l2 - oc->l1) / (oc->l1 + oc->l2) > 1e-3)) oc->done = 1;
+      oc->cnt[0] = 0u;
+    }
+  }
+}
+
+// x_new at the last evaluated multiplier and change = max |x_new - x|.
+__global__ __launch_bounds__(kRedThreads) void oc_final_kernel(
+    const double* __restrict__ x, const double* __restrict__ dc, const double* __restrict__ dv,
+    double move, int64_t n, OcState* oc, double* __restrict__ xnew, double* partials) {
+  __shared__ double sred[kRedThreads / 64];
+  const double lmid = oc->lmid;
+  double mx = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const double xv = x[i];
+    const double xn = oc_x(xv, dc[i], dv[i], lmid, move);
+    xnew[i] = xn;
+    mx = fmax(mx, fabs(xn - xv));
+  }
+  const double bm = block_max<kRedThreads>(mx, sred);
+  if (threadIdx.x == 0) partials[blockIdx.x] = bm;
+  if (last_block_arrive(&oc->cnt[1], gridDim.x)) {
+    const double tot = max_partials<kRedThreads>(partials, gridDim.x, 1, sred);
+    if (threadIdx.x == 0) {
+      oc->change = tot;
+      oc->cnt[1] = 0u;
+    }
+  }
+}
+
+hipError_t launch_oc_step(const tosimp_ctx* c, const double* x, const double* dc,
+                          const double* dv, double move, OcState* oc, double* partials) {
+  oc_step_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(x, dc, dv, move, c->n_elem, oc,
+                                                            partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_oc_final(const tosimp_ctx* c, const double* x, const double* dc,
+                           const double* dv, double move, OcState* oc, double* xnew,
+                           double* partials) {
+  oc_final_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(x, dc, dv, move, c->n_elem, oc,
+                                                             xnew, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_oc_init(const tosimp_ctx*, OcState*, double) { return hipSuccess; }
+
+}  // namespace tosimp

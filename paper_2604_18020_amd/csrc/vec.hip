@@ -1,0 +1,405 @@
+// Vector kernels of the CG solvers, refinement loop and Lanczos (FP64 / FP32 storage,
+// FP64 reductions).
+//
+// Paper: Sec. "Preconditioned Conjugate Gradient and Warm-Start Strategy" (Jacobi-PCG,
+// stop on the unpreconditioned ||r_k|| / ||f||) and Sec. "BF16 Arithmetic in the
+// Conjugate Gradient Solver" (refinement r = f - K u, e ~ K^-1 r, u += e).
+//
+// Every kernel uses a fixed grid (kRedBlocks x kRedThreads) and a grid-stride loop, so
+// each block's share of a reduction is fixed; block partials are summed by the last
+// block in index order.  Reductions are therefore bit-reproducible.  All dot products,
+// norms, alpha and beta are FP64 whatever the vector type.  Solver control lives in a
+// device SolverState: once `done` is set every later kernel of the batch returns at
+// once, so the host enqueues batches of iterations and polls only between batches.
+#include "common.h"
+#include "dev.h"
+
+namespace tosimp {
+
+// r = b - K u (masked), z = r * dinv, p = z; accumulates ||r||^2, <r,z>, ||b||^2.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void pcg_init_kernel(
+    const T* __restrict__ b, const T* __restrict__ Ku, T* __restrict__ r,
+    T* __restrict__ p, const T* __restrict__ dinv, const uint8_t* __restrict__ mask,
+    int64_t n_dof, SolverState* st, double* partials, int use_Ku) {
+  __shared__ double sred[kRedThreads / 64];
+  double rr = 0.0, rz = 0.0, bb = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n_dof;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const int64_t n = i / 3;
+    const int c = (int)(i - 3 * n);
+    const bool fixed = (mask[n] >> c) & 1;
+    const T bv = fixed ? T(0) : b[i];
+    const T rv = use_Ku ? (fixed ? T(0) : bv - Ku[i]) : bv;
+    const T zv = rv * dinv[n];
+    r[i] = rv;
+    p[i] = zv;
+    rr += (double)rv * (double)rv;
+    rz += (double)rv * (double)zv;
+    bb += (double)bv * (double)bv;
+  }
+  const double s0 = block_sum<kRedThreads>(rr, sred);
+  const double s1 = block_sum<kRedThreads>(rz, sred);
+  const double s2 = block_sum<kRedThreads>(bb, sred);
+  if (threadIdx.x == 0) {
+    partials[3 * blockIdx.x + 0] = s0;
+    partials[3 * blockIdx.x + 1] = s1;
+    partials[3 * blockIdx.x + 2] = s2;
+  }
+  if (last_block_arrive(&st->cnt[1], gridDim.x)) {
+    const double RR = sum_partials<kRedThreads>(partials + 0, gridDim.x, 3, sred);
+    const double RZ = sum_partials<kRedThreads>(partials + 1, gridDim.x, 3, sred);
+    const double BB = sum_partials<kRedThreads>(partials + 2, gridDim.x, 3, sred);
+    if (threadIdx.x == 0) {
+      st->rr = RR;
+      st->rz = RZ;
+      st->bb = BB;
+      st->tol2 = st->aux * BB;  // aux holds tol^2 on entry
+      st->iter = 0;
+      st->done = (BB == 0.0 || RR <= st->tol2) ? 1 : 0;
+      if (!finite_val(RR) || !finite_val(RZ)) st->done = 3;
+      st->cnt[1] = 0u;
+    }
+  }
+}
+
+// u += alpha p, r -= alpha q; accumulates ||r||^2 and <r, r dinv>; the last block
+// counts the iteration, tests convergence and forms beta.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void pcg_update_kernel(
+    T* __restrict__ u, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
+    const T* __restrict__ dinv, int64_t n_dof, SolverState* st, double* partials) {
+  __shared__ double sred[kRedThreads / 64];
+  if (st->done) return;
+  const T alpha = (T)st->alpha;
+  double rr = 0.0, rz = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n_dof;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const int64_t n = i / 3;
+    const T pv = p[i];
+    u[i] += alpha * pv;
+    const T rv = r[i] - alpha * q[i];
+    r[i] = rv;
+    rr += (double)rv * (double)rv;
+    rz += (double)rv * (double)(rv * dinv[n]);
+  }
+  const double s0 = block_sum<kRedThreads>(rr, sred);
+  const double s1 = block_sum<kRedThreads>(rz, sred);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x + 0] = s0;
+    partials[2 * blockIdx.x + 1] = s1;
+  }
+  if (last_block_arrive(&st->cnt[1], gridDim.x)) {
+    const double RR = sum_partials<kRedThreads>(partials + 0, gridDim.x, 2, sred);
+    const double RZ = sum_partials<kRedThreads>(partials + 1, gridDim.x, 2, sred);
+    if (threadIdx.x == 0) {
+      st->iter += 1;
+      st->rr = RR;
+      const double beta = RZ / st->rz;
+      st->beta = beta;
+      st->rz = RZ;
+      if (!finite_val(RR) || !finite_val(beta)) st->done = 3;
+      else if (RR <= st->tol2) st->done = 1;
+      else if (st->iter >= st->maxit) st->done = 2;
+      st->cnt[1] = 0u;
+    }
+  }
+}
+
+// p = r dinv + beta p.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void pcg_direction_kernel(
+    const T* __restrict__ r, T* __restrict__ p, const T* __restrict__ dinv, int64_t n_dof,
+    const SolverState* st) {
+  if (st->done) return;
+  const T beta = (T)st->beta;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n_dof;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const int64_t n = i / 3;
+    p[i] = r[i] * dinv[n] + beta * p[i];
+  }
+}
+
+template <typename T>
+hipError_t launch_pcg_init(const tosimp_ctx* c, const T* b, const T* Ku, T* r, T* p,
+                           const void* dinv, SolverState* st, double* partials, int use_Ku) {
+  pcg_init_kernel<T><<<kRedBlocks, kRedThreads, 0, c->stream>>>(
+      b, Ku, r, p, (const T*)dinv, c->ws.mask, c->n_dof, st, partials, use_Ku);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pcg_update(const tosimp_ctx* c, T* u, T* r, const T* p, const T* q,
+                             const void* dinv, SolverState* st, double* partials) {
+  pcg_update_kernel<T><<<kRedBlocks, kRedThreads, 0, c->stream>>>(
+      u, r, p, q, (const T*)dinv, c->n_dof, st, partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pcg_direction(const tosimp_ctx* c, const T* r, T* p, const void* dinv,
+                                SolverState* st) {
+  pcg_direction_kernel<T><<<kRedBlocks, kRedThreads, 0, c->stream>>>(r, p, (const T*)dinv,
+                                                                     c->n_dof, st);
+  return hipGetLastError();
+}
+
+template hipError_t launch_pcg_init<double>(const tosimp_ctx*, const double*, const double*,
+                                            double*, double*, const void*, SolverState*,
+                                            double*, int);
+template hipError_t launch_pcg_init<float>(const tosimp_ctx*, const float*, const float*,
+                                           float*, float*, const void*, SolverState*,
+                                           double*, int);
+template hipError_t launch_pcg_update<double>(const tosimp_ctx*, double*, double*,
+                                              const double*, const double*, const void*,
+                                              SolverState*, double*);
+template hipError_t launch_pcg_update<float>(const tosimp_ctx*, float*, float*, const float*,
+                                             const float*, const void*, SolverState*,
+                                             double*);
+template hipError_t launch_pcg_direction<double>(const tosimp_ctx*, const double*, double*,
+                                                 const void*, SolverState*);
+template hipError_t launch_pcg_direction<float>(const tosimp_ctx*, const float*, float*,
+                                                const void*, SolverState*);
+
+// ------------------------------------------------------------------ misc vectors
+__global__ void mask_vec_kernel(double* v, const uint8_t* mask, int64_t n_dof) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_dof;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = i / 3;
+    if ((mask[n] >> (int)(i - 3 * n)) & 1) v[i] = 0.0;
+  }
+}
+
+hipError_t launch_mask_vec(const tosimp_ctx* c, double* v) {
+  mask_vec_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(v, c->ws.mask, c->n_dof);
+  return hipGetLastError();
+}
+
+// r = b - Ku (masked) and ||r||^2 into st->rr (FP64 true residual of refinement).
+__global__ __launch_bounds__(kRedThreads) void residual64_kernel(
+    const double* __restrict__ b, const double* __restrict__ Ku, double* __restrict__ r,
+    const uint8_t* __restrict__ mask, int64_t n_dof, double* partials, SolverState* st) {
+  __shared__ double sred[kRedThreads / 64];
+  double rr = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n_dof;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const int64_t n = i / 3;
+    const bool fixed = (mask[n] >> (int)(i - 3 * n)) & 1;
+    const double rv = fixed ? 0.0 : b[i] - Ku[i];
+    r[i] = rv;
+    rr += rv * rv;
+  }
+  const double s0 = block_sum<kRedThreads>(rr, sred);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s0;
+  if (last_block_arrive(&st->cnt[2], gridDim.x)) {
+    const double RR = sum_partials<kRedThreads>(partials, gridDim.x, 1, sred);
+    if (threadIdx.x == 0) {
+      st->rr = RR;
+      st->cnt[2] = 0u;
+    }
+  }
+}
+
+hipError_t launch_residual64(const tosimp_ctx* c, const double* b, const double* Ku,
+                             double* r, double* partials, SolverState* st) {
+  residual64_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(b, Ku, r, c->ws.mask,
+                                                               c->n_dof, partials, st);
+  return hipGetLastError();
+}
+
+__global__ void scale_to32_kernel(const double* r, double inv_s, float* r32, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    r32[i] = (float)(r[i] * inv_s);
+}
+
+hipError_t launch_scale_to32(const tosimp_ctx* c, const double* r, double inv_s, float* r32) {
+  scale_to32_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(r, inv_s, r32, c->n_dof);
+  return hipGetLastError();
+}
+
+__global__ void axpy_from32_kernel(double* u, double s, const float* e, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    u[i] += s * (double)e[i];
+}
+
+hipError_t launch_axpy_from32(const tosimp_ctx* c, double* u, double s, const float* e) {
+  axpy_from32_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(u, s, e, c->n_dof);
+  return hipGetLastError();
+}
+
+__global__ void cast_kernel(const double* x, float* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+hipError_t launch_copy_cast_x(const tosimp_ctx* c, const double* x, float* x32) {
+  cast_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(x, x32, c->n_elem);
+  return hipGetLastError();
+}
+
+__global__ void zero_kernel(uint32_t* p, int64_t nwords) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t launch_fill_zero(const tosimp_ctx* c, void* p, int64_t bytes) {
+  zero_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>((uint32_t*)p, bytes / 4);
+  return hipGetLastError();
+}
+
+// <a, b> over n values into st->aux (what = 0) or st->rr (what = 1).
+__global__ __launch_bounds__(kRedThreads) void dot64_kernel(const double* __restrict__ a,
+                                                            const double* __restrict__ b,
+                                                            int64_t n, double* partials,
+                                                            SolverState* st, int what) {
+  __shared__ double sred[kRedThreads / 64];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads)
+    s += a[i] * b[i];
+  const double bs = block_sum<kRedThreads>(s, sred);
+  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+  if (last_block_arrive(&st->cnt[2], gridDim.x)) {
+    const double tot = sum_partials<kRedThreads>(partials, gridDim.x, 1, sred);
+    if (threadIdx.x == 0) {
+      if (what == 0) st->aux = tot;
+      else st->rr = tot;
+      st->cnt[2] = 0u;
+    }
+  }
+}
+
+hipError_t launch_dot64(const tosimp_ctx* c, const double* a, const double* b, int64_t n,
+                        double* partials, SolverState* st, int what) {
+  dot64_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(a, b, n, partials, st, what);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Lanczos
+// w = (s o w) - alpha_j q - beta_{j-1} q_prev, ||w|| -> beta_j (s: optional per-node
+// scaling for the Jacobi-scaled operator; q_prev and beta_{j-1} may be null at j = 0).
+__global__ __launch_bounds__(kRedThreads) void lanczos_update_kernel(
+    double* __restrict__ w, const double* __restrict__ q, const double* __restrict__ qprev,
+    const double* alpha_j, const double* beta_jm1, const double* __restrict__ s_node,
+    int64_t n_dof, double* partials, double* beta_j, unsigned* cnt) {
+  __shared__ double sred[kRedThreads / 64];
+  const double a = *alpha_j;
+  const double bprev = beta_jm1 ? *beta_jm1 : 0.0;
+  double ss = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n_dof;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    double wv = w[i];
+    if (s_node) wv *= s_node[i / 3];
+    wv -= a * q[i];
+    if (qprev) wv -= bprev * qprev[i];
+    w[i] = wv;
+    ss += wv * wv;
+  }
+  const double bs = block_sum<kRedThreads>(ss, sred);
+  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+  if (last_block_arrive(cnt, gridDim.x)) {
+    const double tot = sum_partials<kRedThreads>(partials, gridDim.x, 1, sred);
+    if (threadIdx.x == 0) {
+      *beta_j = sqrt(tot);
+      *cnt = 0u;
+    }
+  }
+}
+
+hipError_t launch_lanczos_update(const tosimp_ctx* c, double* w, const double* q,
+                                 const double* qprev, const double* alpha_j,
+                                 const double* beta_jm1, const double* scale_node,
+                                 double* partials, double* beta_j) {
+  lanczos_update_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(
+      w, q, qprev, alpha_j, beta_jm1, scale_node, c->n_dof, partials, beta_j,
+      &c->ws.st[0].cnt[3]);
+  return hipGetLastError();
+}
+
+__global__ void lanczos_normalize_kernel(const double* w, const double* beta_j, double* qn,
+                                         int64_t n) {
+  const double b = *beta_j;
+  const double inv = b > 0.0 ? 1.0 / b : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    qn[i] = w[i] * inv;
+}
+
+hipError_t launch_lanczos_normalize(const tosimp_ctx* c, const double* w, const double* beta_j,
+                                    double* qnext) {
+  lanczos_normalize_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(w, beta_j, qnext,
+                                                                      c->n_dof);
+  return hipGetLastError();
+}
+
+__global__ void node_scale_kernel(const double* s, const double* v, double* out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = v[i] * s[i / 3];
+}
+
+hipError_t launch_node_scale(const tosimp_ctx* c, const double* s_node, const double* v,
+                             double* out) {
+  node_scale_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(s_node, v, out, c->n_dof);
+  return hipGetLastError();
+}
+
+__global__ void sqrt_node_kernel(const double* d, double* out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = sqrt(d[i]);
+}
+
+hipError_t launch_sqrt_node(const tosimp_ctx* c, const double* dinv, double* out) {
+  sqrt_node_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(dinv, out, c->n_node);
+  return hipGetLastError();
+}
+
+// alpha = <r,z> / <p, q> for operators that do not fuse the dot (MFMA variant).
+__global__ __launch_bounds__(kRedThreads) void alpha_dot32_kernel(const float* __restrict__ p,
+                                                                  const float* __restrict__ q,
+                                                                  int64_t n, double* partials,
+                                                                  SolverState* st) {
+  __shared__ double sred[kRedThreads / 64];
+  if (st->done) return;
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads)
+    s += (double)p[i] * (double)q[i];
+  const double bs = block_sum<kRedThreads>(s, sred);
+  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+  if (last_block_arrive(&st->cnt[0], gridDim.x)) {
+    const double tot = sum_partials<kRedThreads>(partials, gridDim.x, 1, sred);
+    if (threadIdx.x == 0) {
+      st->pq = tot;
+      if (!(tot > 0.0) || !finite_val(tot)) {
+        st->done = 3;
+        st->alpha = 0.0;
+      } else {
+        st->alpha = st->rz / tot;
+      }
+      st->cnt[0] = 0u;
+    }
+  }
+}
+
+hipError_t launch_alpha_from_dot32(const tosimp_ctx* c, const float* p, const float* q,
+                                   double* partials, SolverState* st) {
+  alpha_dot32_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(p, q, c->n_dof, partials, st);
+  return hipGetLastError();
+}
+
+__global__ void sqrt_scalar_kernel(const SolverState* st, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = sqrt(st->rr);
+}
+
+hipError_t launch_sqrt_scalar(const tosimp_ctx* c, const SolverState* st, double* out) {
+  sqrt_scalar_kernel<<<1, 64, 0, c->stream>>>(st, out);
+  return hipGetLastError();
+}
+
+}  // namespace tosimp

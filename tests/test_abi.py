@@ -1,0 +1,54 @@
+"""CPU checks of the C ABI: the shared library loads and exports every declared entry
+point; host-only entry points (tridiagonal extremes) and argument validation work
+without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"^\s*(?:int|const char\*|void)\s+(tosimp_\w+)\s*\(", txt, re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for must in ["tosimp_create", "tosimp_set_mesh", "tosimp_set_bcs", "tosimp_set_loads",
+                 "tosimp_apply_K", "tosimp_pcg_solve", "tosimp_sensitivity", "tosimp_filter",
+                 "tosimp_oc_update", "tosimp_simp_step", "tosimp_lanczos"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2604_18020_amd import LIB_PATH
+    lib = ctypes.CDLL(LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_tridiag_extremes_host():
+    from paper_2604_18020_amd import tridiag_extremes
+    rng = np.random.default_rng(0)
+    a, b = rng.standard_normal(50), rng.uniform(0.1, 1.0, 49)
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    ev = np.linalg.eigvalsh(T)
+    lo, hi = tridiag_extremes(a, b)
+    assert abs(lo - ev[0]) < 1e-12 and abs(hi - ev[-1]) < 1e-12
+    lo1, hi1 = tridiag_extremes(np.array([2.5]), np.array([]))
+    assert lo1 == pytest.approx(2.5) and hi1 == pytest.approx(2.5)
+
+
+def test_null_context_is_rejected():
+    from paper_2604_18020_amd.binding import LIB
+    assert LIB.tosimp_set_mesh(None, 1, 1, 1, 1.0, 1.0, 1e-9, 0.3, 3.0, 1.5) < 0
+    assert LIB.tosimp_apply_K(None, None, 0, None, None, 0) < 0
+    assert LIB.tosimp_destroy(None) == 0

@@ -1,0 +1,144 @@
+"""GPU parity of the fused operator y = K_c(x) v and the Jacobi diagonal against the CPU
+oracle (assembled CSR), element by element.
+
+Tolerances: FP64 <= 1e-12 relative (2-norm and max-norm), FP32 <= 1e-5 relative
+(2-norm); the FP32 max-norm bound 2e-5 follows from ~150 rounded operations of unit
+roundoff 6e-8 on values of the size of max|y|."""
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+from oracle import fem
+from tests.helpers import dev, gpu_problem, maxrel, rel
+
+pytestmark = pytest.mark.gpu
+KE = fem.element_stiffness(0.3)
+
+
+def _oracle_y(nx, ny, nz, rho, v, fixed, penal=3.0, nu=0.3, h=1.0):
+    KEl = fem.element_stiffness(nu) * h
+    E = fem.simp_modulus(rho, 1.0, 1e-9, penal)
+    K = fem.assemble_K(nx, ny, nz, E, KEl)
+    return fem.constrain(K, fem.fixed_mask(v.size, fixed)) @ v
+
+
+SIZES = [(16, 8, 8), (37, 19, 23), (31, 16, 9), (1, 1, 1), (2, 1, 3), (15, 14, 40),
+         (29, 29, 3), (45, 2, 17), (3, 47, 2)]
+
+
+@pytest.mark.parametrize("dims", SIZES)
+def test_apply_K_fp64_matches_oracle(dims):
+    nx, ny, nz = dims
+    t, fixed, _ = gpu_problem(nx, ny, nz)
+    rho, v = si.random_density_and_vector(nx, ny, nz, seed=42)
+    y = t.apply_K(dev(rho), dev(v)).cpu().numpy()
+    y_ref = _oracle_y(nx, ny, nz, rho, v, fixed)
+    assert rel(y, y_ref) <= 1e-12
+    assert maxrel(y, y_ref) <= 1e-12
+    assert np.array_equal(y[fixed], v[fixed])
+
+
+@pytest.mark.parametrize("dims", [(16, 8, 8), (37, 19, 23), (15, 14, 40)])
+def test_apply_K_fp32_matches_oracle(dims):
+    nx, ny, nz = dims
+    t, fixed, _ = gpu_problem(nx, ny, nz)
+    rho, v = si.random_density_and_vector(nx, ny, nz, seed=7)
+    y_ref = _oracle_y(nx, ny, nz, rho, v, fixed)
+    for xdt in (torch.float32, torch.float64):
+        y = t.apply_K(dev(rho, xdt), dev(v, torch.float32), prec="fp32").double().cpu().numpy()
+        assert rel(y, y_ref) <= 1e-5
+        assert maxrel(y, y_ref) <= 2e-5
+
+
+def test_apply_K_torsion_bcs_and_general_penal_nu_h():
+    nx, ny, nz = 12, 12, 20
+    t, fixed, _ = gpu_problem(nx, ny, nz, kind="torsion", penal=2.5, nu=0.25, h=0.5)
+    rho, v = si.random_density_and_vector(nx, ny, nz, seed=3)
+    y = t.apply_K(dev(rho), dev(v)).cpu().numpy()
+    y_ref = _oracle_y(nx, ny, nz, rho, v, fixed, penal=2.5, nu=0.25, h=0.5)
+    assert maxrel(y, y_ref) <= 1e-12
+
+
+def test_apply_K_rigid_modes_in_null_space():
+    nx, ny, nz = 20, 17, 9
+    t, _, _ = gpu_problem(nx, ny, nz, kind="free")
+    rho = np.random.default_rng(1).uniform(0.01, 1, nx * ny * nz)
+    R = fem.rigid_body_modes(nx, ny, nz)
+    x = dev(rho)
+    scale = np.linalg.norm(t.apply_K(x, dev(np.random.default_rng(2).standard_normal(R.shape[0]))).cpu().numpy())
+    for k in range(6):
+        y = t.apply_K(x, dev(R[:, k])).cpu().numpy()
+        assert np.linalg.norm(y) <= 1e-13 * scale * np.linalg.norm(R[:, k])
+
+
+def test_apply_K_bitwise_reproducible():
+    nx, ny, nz = 40, 21, 33
+    t, _, _ = gpu_problem(nx, ny, nz)
+    rho, v = si.random_density_and_vector(nx, ny, nz, seed=5)
+    x, vd = dev(rho), dev(v)
+    y0 = t.apply_K(x, vd)
+    for _ in range(5):
+        assert torch.equal(t.apply_K(x, vd), y0)
+    x32, v32 = x.float(), vd.float()
+    z0 = t.apply_K(x32, v32, prec="fp32")
+    for _ in range(3):
+        assert torch.equal(t.apply_K(x32, v32, prec="fp32"), z0)
+
+
+@pytest.mark.parametrize("dims", [(16, 8, 8), (23, 9, 31)])
+def test_diag_matches_oracle(dims):
+    nx, ny, nz = dims
+    t, fixed, _ = gpu_problem(nx, ny, nz)
+    rho = np.random.default_rng(9).uniform(0.01, 1, nx * ny * nz)
+    d = t.diag_K(dev(rho)).cpu().numpy()
+    E = fem.simp_modulus(rho, 1.0, 1e-9, 3.0)
+    d_ref = fem.diag_K(nx, ny, nz, E, KE, fem.fixed_mask(d.size, fixed))
+    assert maxrel(d, d_ref) <= 1e-14
+    d32 = t.diag_K(dev(rho), dtype=torch.float32).double().cpu().numpy()
+    assert maxrel(d32, d_ref) <= 1e-6
+
+
+def test_bad_arguments_raise():
+    from paper_2604_18020_amd import TosimpError
+    t, _, _ = gpu_problem(4, 3, 2)
+    x = torch.zeros(24, dtype=torch.float64, device="cuda:0")
+    v = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(TosimpError):
+        t.apply_K(x, v, y=v)
+    with pytest.raises(ValueError):
+        t.apply_K(x, v[:-1])
+    with pytest.raises(TypeError):
+        t.apply_K(x, v.float(), prec="fp64")
+
+
+def _samples(nx, ny, nz, rng, n=1500):
+    """Sample DOFs uniformly plus on tile and chunk seams of the operator's blocking."""
+    NX1, NY1 = nx + 1, ny + 1
+    pick = list(rng.integers(0, 3 * NX1 * NY1 * (nz + 1), n))
+    for _ in range(300):
+        i = int(rng.choice([0, 14, 15, 29, 30, nx - 1, nx]))
+        j = int(rng.choice([0, 14, 15, 29, 30, ny - 1, ny]))
+        k = int(rng.choice([0, 1, 10, 11, 21, 22, nz - 1, nz]))
+        pick.append(3 * (i + NX1 * (j + NY1 * k)) + int(rng.integers(0, 3)))
+    return np.array(pick, dtype=np.int64)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_K_full_size_4p9M_sampled(prec):
+    """340x170x85 (4.9M elements, 15M DOFs), the benchmark's launch configuration,
+    checked on ~1,800 sampled outputs computed one by one by the oracle."""
+    nx, ny, nz = 340, 170, 85
+    t, fixed, _ = gpu_problem(nx, ny, nz)
+    rho, v = si.random_density_and_vector(nx, ny, nz, seed=42)
+    if prec == "fp64":
+        y = t.apply_K(dev(rho), dev(v)).cpu().numpy()
+        tol = 1e-12
+    else:
+        y = t.apply_K(dev(rho, torch.float32), dev(v, torch.float32), prec="fp32").double().cpu().numpy()
+        tol = 2e-5
+    dofs = _samples(nx, ny, nz, np.random.default_rng(0))
+    y_ref = fem.apply_K_rows(nx, ny, nz, rho, v, fixed, dofs, KE)
+    scale = np.max(np.abs(y_ref))
+    assert np.max(np.abs(y[dofs] - y_ref)) <= tol * scale
+    assert np.all(np.isfinite(y))
