@@ -140,6 +140,8 @@ def main():
     ap.add_argument("--pcg-tol", type=float, default=1e-6)
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device copy (for scaling profiler byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -157,6 +159,12 @@ def main():
     fixed = (si.cantilever_fixed_dofs if cfg["kind"] == "cantilever" else si.torsion_fixed_dofs)(nx, ny, nz)
     t.set_bcs(fixed)
 
+    if a.copy_calibration:
+        src = torch.empty(2 ** 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     main_kv = time_kv(t, nx, ny, nz, a.prec, a.steps, a.warmup)
     other = "fp64" if a.prec == "fp32" else "fp32"
     other_kv = time_kv(t, nx, ny, nz, other, max(20, a.steps // 4), 5)

@@ -65,13 +65,60 @@ __device__ __forceinline__ T simp_E(XT xv, T Emin, T E0mEmin, T penal) {
   return Emin + xp * E0mEmin;
 }
 
-template <typename T, typename XT, bool P3, bool DOT>
+// ---------------------------------------------------------------- buffer access
+// Raw buffer loads/stores: the per-lane offset is loop-invariant, the moving plane
+// base lives in the (uniform) resource, and the hardware range check returns 0 for
+// offsets past num_records and drops such stores; halo lanes and non-owner lanes use
+// an offset beyond any buffer.
+constexpr int kOOB = 0x7FFFFFF0;
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, long long bytes) {
+  const int n = bytes <= 0 ? 0 : (bytes >= 0x7FFFFFFF ? 0x7FFFFFFF : (int)bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, kRsrcWord3);
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, int off, int soff);
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, int off, int soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, int off, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+}
+__device__ __forceinline__ uint8_t buf_ld_u8(__amdgpu_buffer_rsrc_t r, int off, int soff) {
+  return __builtin_amdgcn_raw_buffer_load_b8(r, off, soff, 0);
+}
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, int off, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, soff, 0);
+}
+__device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, int off, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, soff, 0);
+}
+
+// a if sel == 0 else b, as a bitwise blend (no branch around the computation of a).
+__device__ __forceinline__ float bit_select(float a, float b, unsigned sel) {
+  const unsigned m = 0u - sel;
+  return __uint_as_float((__float_as_uint(a) & ~m) | (__float_as_uint(b) & m));
+}
+__device__ __forceinline__ double bit_select(double a, double b, unsigned sel) {
+  const unsigned long long m = 0ull - (unsigned long long)sel;
+  return __builtin_bit_cast(double, (__builtin_bit_cast(unsigned long long, a) & ~m) |
+                                        (__builtin_bit_cast(unsigned long long, b) & m));
+}
+
+template <typename T, typename XT, bool P3, bool DOT, int D, int KZMAX>
 __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   constexpr int NXL = KBX + 1, NYL = KBY + 1, ROW = 3 * NXL, NPV = ROW * NYL;
   constexpr int NLD = (NPV + 255) / 256;
-  __shared__ T sv[NPV];
-  __shared__ T sc[KBY * KBX * 12];
-  __shared__ uint8_t sm[NXL * NYL];
+  constexpr int NE = KBX * KBY;
+  __shared__ T sv[NLD * 256];    // node plane (17 x 17 nodes x 3), masked; padded
+  __shared__ T sr[NLD * 256];    // the same plane unmasked (fixed rows output y = v)
+  __shared__ T sc[12 * NE];      // corner contributions, [corner*3 + c][element column]
   __shared__ double sred[4];
 
   const int bid = blockIdx.x;
@@ -85,90 +132,100 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   const int tid = threadIdx.x, lx = tid % KBX, ly = tid / KBX;
   const int ex0 = tx * (KBX - 1) - 1, ey0 = ty * (KBY - 1) - 1;
   const int k0 = cz * A.kz;
-  const int k1 = min(k0 + A.kz, A.nz + 1);
+  const int k1 = min(k0 + A.kz, A.nz + 1);  // owned node planes [k0, k1)
   const int NX1 = A.nx + 1;
-  const int64_t plane = (int64_t)NX1 * (A.ny + 1);
+  const int plane = NX1 * (A.ny + 1);  // nodes per plane
+  const int n_node = plane * (A.nz + 1);
+  const int elayer = A.nx * A.ny;
+  // One resource per array for the whole launch; planes move in the scalar offset.
+  const auto rv = make_rsrc(A.v, 3LL * n_node * (long long)sizeof(T));
+  const auto ry = make_rsrc(A.y, 3LL * n_node * (long long)sizeof(T));
+  const auto rm = make_rsrc(A.mask, n_node);
+  const auto rx = make_rsrc(A.x, (long long)elayer * A.nz * (long long)sizeof(XT));
+  const int vplane_bytes = 3 * plane * (int)sizeof(T);
 
   // Plane-load slots: flat LDS index f = jl*ROW + il*3 + c matches a contiguous row
   // segment of the interleaved vector, so consecutive threads read consecutive words.
-  int goff[NLD];
-  int gcomp[NLD];
-  bool gok[NLD];
+  int voff[NLD], moff[NLD], gcomp[NLD];
 #pragma unroll
   for (int s = 0; s < NLD; ++s) {
     const int f = tid + 256 * s;
     const int jl = f / ROW, w = f - jl * ROW, il = w / 3, c = w - il * 3;
     const int i = ex0 + il, j = ey0 + jl;
-    gok[s] = f < NPV && i >= 0 && i <= A.nx && j >= 0 && j <= A.ny;
-    goff[s] = gok[s] ? i + NX1 * j : 0;
+    const bool ok = f < NPV && i >= 0 && i <= A.nx && j >= 0 && j <= A.ny;
+    const int node = i + NX1 * j;
+    voff[s] = ok ? (3 * node + c) * (int)sizeof(T) : kOOB;
+    moff[s] = ok ? node : kOOB;
     gcomp[s] = c;
   }
-  T pv[NLD];
-  uint8_t pm[NLD];
-  auto prefetch = [&](int k) {
-    const bool kok = k >= 0 && k <= A.nz;
-#pragma unroll
-    for (int s = 0; s < NLD; ++s) {
-      pv[s] = T(0);
-      pm[s] = 0;
-      if (gok[s] && kok) {
-        const int64_t n = goff[s] + plane * k;
-        const uint8_t m = A.mask[n];
-        const T val = A.v[3 * n + gcomp[s]];
-        pv[s] = ((m >> gcomp[s]) & 1) ? T(0) : val;
-        pm[s] = m;
-      }
-    }
-  };
-
   // Element column of this thread.
   const int ex = ex0 + lx, ey = ey0 + ly;
   const bool exy_ok = ex >= 0 && ex < A.nx && ey >= 0 && ey < A.ny;
-  const int64_t ebase = exy_ok ? (int64_t)ex + (int64_t)A.nx * ey : 0;
-  const int64_t elayer = (int64_t)A.nx * A.ny;
-  auto layer_ok = [&](int ez) { return exy_ok && ez >= 0 && ez < A.nz; };
-  auto load_x = [&](int ez) -> XT { return layer_ok(ez) ? A.x[ebase + elayer * ez] : XT(0); };
+  const int xoff = exy_ok ? (ex + A.nx * ey) * (int)sizeof(XT) : kOOB;
   // Node owned by this thread in the output phase: local (lx+1, ly+1).
   const int ni = ex0 + lx + 1, nj = ey0 + ly + 1;
   const bool owner = lx < KBX - 1 && ly < KBY - 1 && ni <= A.nx && nj <= A.ny;
-  const int64_t nbase = (int64_t)ni + (int64_t)NX1 * nj;
+  const int yoff = owner ? 3 * (ni + NX1 * nj) * (int)sizeof(T) : kOOB;
+  const int moffown = owner ? ni + NX1 * nj : kOOB;
 
-  T tb[12], acc[12];
+  // Register ring of D planes in flight: the plane's values and BC bytes, the owned
+  // node's BC byte, and the density of the element layer below the plane.  The main
+  // loop is branch-free so that every wait is for a load issued D steps earlier
+  // (vmcnt waits are in order: any late load would drain the whole ring).  Planes
+  // outside the mesh load a clamped plane with every DOF flagged fixed (zero).
+  T pv[D][NLD];
+  uint8_t pm[D][NLD];
+  uint8_t po[D];
+  XT px[D];
+  auto issue = [&](T* v, uint8_t* m, uint8_t& mo, XT& xv, int k) {
+    const int kc = min(max(k, 0), A.nz);
+#pragma unroll
+    for (int s = 0; s < NLD; ++s) {
+      m[s] = buf_ld_u8(rm, moff[s], plane * kc);
+      v[s] = buf_ld<T>(rv, voff[s], vplane_bytes * kc);
+    }
+    mo = buf_ld_u8(rm, moffown, plane * kc);
+    const int ez = min(max(k - 1, 0), A.nz - 1);
+    xv = buf_ld<XT>(rx, xoff, elayer * ez * (int)sizeof(XT));
+  };
+
+  T TA[12], TB[12];   // 2D-basis faces (ping-pong: bottom / top)
+  T VA[3], VB[3];     // own node values (unmasked) of the matching planes
+  uint8_t MA = 0, MB = 0;
+  T acc[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) {
-    tb[i] = T(0);
+    TA[i] = T(0);
+    TB[i] = T(0);
     acc[i] = T(0);
   }
-  T vown[3] = {T(0), T(0), T(0)};
-  uint8_t mown = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) VA[c] = VB[c] = T(0);
   double dotacc = 0.0;
 
-  prefetch(k0 - 1);
-  XT xnext = load_x(k0 - 1);
-  bool xnext_ok = layer_ok(k0 - 1);
-  bool need_sync = false;
-
-  for (int p = k0 - 1; p <= k1; ++p) {
-    if (need_sync) __syncthreads();
+  // One z step at node plane p: stage the plane, transform the top face, and (when
+  // ELEM) apply element layer p-1 and (when OUT) emit node plane p-1.
+  auto step = [&](int p, T* v, uint8_t* m, uint8_t& mo, XT& xv, const T* tb, T* tt,
+                  const T* vown, T* vnew, uint8_t mown, uint8_t& mnew, bool elem, bool out,
+                  int refill) {
+    // Keep each step's instructions inside its own region: the scheduler must not hoist
+    // a later step's use of a ring slot above this step (that would wait on a fresh load).
+    __builtin_amdgcn_sched_barrier(0);
+    // A plane outside the mesh (p = -1 or nz + 1) was loaded clamped: zero it here.
+    const int force = (p >= 0 && p <= A.nz) ? 0 : 7;
 #pragma unroll
     for (int s = 0; s < NLD; ++s) {
       const int f = tid + 256 * s;
-      if (f < NPV) {
-        sv[f] = pv[s];
-        if (gcomp[s] == 0) sm[f / 3] = pm[s];
-      }
+      sv[f] = (((m[s] | force) >> gcomp[s]) & 1) ? T(0) : v[s];
+      sr[f] = v[s];
     }
+    const XT xcur = xv;
+    mnew = mo;
     __syncthreads();
-    const XT xcur = xnext;
-    const bool xcur_ok = xnext_ok;
-    if (p < k1) prefetch(p + 1);
-    if (p >= k0 && p < k1) {
-      xnext = load_x(p);
-      xnext_ok = layer_ok(p);
-    }
+    issue(v, m, mo, xv, refill);
+    __builtin_amdgcn_sched_barrier(0);
 
     // Forward 2D transform of the top face (plane p) of this element column.
-    T tt[12];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const T v00 = sv[ly * ROW + lx * 3 + c];
@@ -181,17 +238,13 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
       tt[2 * 3 + c] = b0 - a0;
       tt[3 * 3 + c] = b1 - a1;
     }
-    T vnew[3];
-    uint8_t mnew = 0;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) vnew[c] = sv[(ly + 1) * ROW + (lx + 1) * 3 + c];
-    mnew = sm[(ly + 1) * NXL + lx + 1];
+    for (int c = 0; c < 3; ++c) vnew[c] = sr[(ly + 1) * ROW + (lx + 1) * 3 + c];
 
-    need_sync = true;
-    if (p >= k0) {
+    if (elem) {
       // ---- element layer ez = p - 1: bottom face tb, top face tt -------------
-      const T E = xcur_ok ? simp_E<T, XT, P3>(xcur, A.Emin, A.E0mEmin, A.penal) : T(0);
-      // 3D Hadamard coefficients: mode m = m2 + 4 mz.
+      const bool eok = exy_ok && p - 1 >= 0 && p - 1 < A.nz;
+      const T E = eok ? simp_E<T, XT, P3>(xcur, A.Emin, A.E0mEmin, A.penal) : T(0);
 #define HB(m2, c) (tb[(m2) * 3 + (c)] + tt[(m2) * 3 + (c)])
 #define HT(m2, c) (tt[(m2) * 3 + (c)] - tb[(m2) * 3 + (c)])
       const T h1x = HB(1, 0), h1y = HB(1, 1), h1z = HB(1, 2);
@@ -205,20 +258,15 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
 #undef HT
       const T kad = E * A.k.ad, kao = E * A.k.ao, kcs = E * A.k.cs, kbd = E * A.k.bd;
       const T kbo = E * A.k.bo, kcd = E * A.k.cd, kco = E * A.k.co, khg = E * A.k.hg;
-      // normal-strain block
       const T sA = kao * (h1x + h2y + h4z);
       const T g1x = kad * h1x + sA, g2y = kad * h2y + sA, g4z = kad * h4z + sA;
-      // shear pairs
       const T s1 = kcs * (h1y + h2x), s2 = kcs * (h1z + h4x), s3 = kcs * (h2z + h4y);
       const T g1y = s1, g2x = s1, g1z = s2, g4x = s2, g2z = s3, g4y = s3;
-      // bending pairs
       const T g3x = kbd * h3x + kbo * h6z, g6z = kbo * h3x + kbd * h6z;
       const T g3y = kbd * h3y + kbo * h5z, g5z = kbo * h3y + kbd * h5z;
       const T g5x = kbd * h5x + kbo * h6y, g6y = kbo * h5x + kbd * h6y;
-      // twist block
       const T sC = kco * (h3z + h5y + h6x);
       const T g3z = kcd * h3z + sC, g5y = kcd * h5y + sC, g6x = kcd * h6x + sC;
-      // hourglass
       const T g7x = khg * h7x, g7y = khg * h7y, g7z = khg * h7z;
 
       // Inverse z stage: bottom face gets g[m2] - g[m2+4], top face g[m2] + g[m2+4].
@@ -232,41 +280,52 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
       acc[6] = g2x + g6x;  acc[7] = g2y + g6y;  acc[8] = g2z + g6z;
       acc[9] = g3x + g7x;  acc[10] = g3y + g7y; acc[11] = g3z + g7z;
 
-      if (p - 1 >= k0) {
+      if (out) {
         // ---- node plane p-1 is complete in R: inverse 2D transform to corners --
-        T* out = sc + (ly * KBX + lx) * 12;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const T u0 = R[0 * 3 + c] - R[2 * 3 + c], u1 = R[1 * 3 + c] - R[3 * 3 + c];
           const T w0 = R[0 * 3 + c] + R[2 * 3 + c], w1 = R[1 * 3 + c] + R[3 * 3 + c];
-          out[0 * 3 + c] = u0 - u1;  // corner (0,0)
-          out[1 * 3 + c] = u0 + u1;  // corner (1,0)
-          out[2 * 3 + c] = w0 - w1;  // corner (0,1)
-          out[3 * 3 + c] = w0 + w1;  // corner (1,1)
-        }
-        __syncthreads();
-        need_sync = false;
-        if (owner) {
-          const T* e00 = sc + (ly * KBX + lx) * 12;           // corner (1,1)
-          const T* e10 = sc + (ly * KBX + lx + 1) * 12;       // corner (0,1)
-          const T* e01 = sc + ((ly + 1) * KBX + lx) * 12;     // corner (1,0)
-          const T* e11 = sc + ((ly + 1) * KBX + lx + 1) * 12; // corner (0,0)
-          const int64_t n = nbase + plane * (p - 1);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            T yv = (e00[9 + c] + e10[6 + c]) + (e01[3 + c] + e11[0 + c]);
-            if ((mown >> c) & 1) yv = A.v[3 * n + c];
-            A.y[3 * n + c] = yv;
-            if constexpr (DOT) dotacc += (double)vown[c] * (double)yv;
-          }
+          sc[(0 * 3 + c) * NE + tid] = u0 - u1;  // corner (0,0)
+          sc[(1 * 3 + c) * NE + tid] = u0 + u1;  // corner (1,0)
+          sc[(2 * 3 + c) * NE + tid] = w0 - w1;  // corner (0,1)
+          sc[(3 * 3 + c) * NE + tid] = w0 + w1;  // corner (1,1)
         }
       }
     }
+    // Barrier: the corners are complete, and every read of the plane buffers is done
+    // before the next step overwrites them.
+    __syncthreads();
+    if (elem && out) {
+      const int soff = vplane_bytes * (p - 1);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) tb[i] = tt[i];
+      for (int c = 0; c < 3; ++c) {
+        T yv = (sc[(9 + c) * NE + tid] + sc[(6 + c) * NE + tid + 1]) +
+               (sc[(3 + c) * NE + tid + KBX] + sc[(0 + c) * NE + tid + KBX + 1]);
+        yv = bit_select(yv, vown[c], (mown >> c) & 1);  // fixed rows are identity: y = v
+        buf_st(yv, ry, yoff + c * (int)sizeof(T), soff);
+        if constexpr (DOT) dotacc += owner ? (double)vown[c] * (double)yv : 0.0;
+      }
+    }
+  };
+
+  // Prologue: fill the ring with planes k0-1 .. k0+D-2.
 #pragma unroll
-    for (int c = 0; c < 3; ++c) vown[c] = vnew[c];
-    mown = mnew;
+  for (int s = 0; s < D; ++s) issue(pv[s], pm[s], po[s], px[s], k0 - 1 + s);
+  // Fully unrolled z sweep (no loop back-edge, so no register copies of in-flight
+  // loads): step i handles plane k0-1+i; plane k0-1 only seeds the bottom face, plane
+  // k0 applies layer k0-1 (plane k0-1 is not owned), later steps emit the plane below.
+#pragma unroll
+  for (int i = 0; i < KZMAX + 2; ++i) {
+    const int p = k0 - 1 + i;
+    if (p > k1) break;
+    const int refill = min(p + D, k1);
+    if (i % 2 == 0)
+      step(p, pv[i % D], pm[i % D], po[i % D], px[i % D], TA, TB, VA, VB, MA, MB, i >= 1,
+           i >= 2, refill);
+    else
+      step(p, pv[i % D], pm[i % D], po[i % D], px[i % D], TB, TA, VB, VA, MB, MA, i >= 1,
+           i >= 2, refill);
   }
 
   if constexpr (DOT) {
@@ -293,9 +352,15 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   }
 }
 
+// Planes in flight per block, and the deepest z chunk a block sweeps (fully unrolled).
+template <typename T>
+constexpr int kv_depth() { return sizeof(T) == 8 ? 2 : 4; }
+template <typename T>
+constexpr int kv_kzmax() { return sizeof(T) == 8 ? 24 : 16; }
+
 template <typename T, typename XT, bool P3, bool DOT>
 __global__ __launch_bounds__(256) void kv_stream(KvArgs<T, XT> A) {
-  kv_body<T, XT, P3, DOT>(A);
+  kv_body<T, XT, P3, DOT, kv_depth<T>(), kv_kzmax<T>()>(A);
 }
 
 // Solver variant: skips the whole operator once the solve has finished, so batches of
@@ -303,7 +368,7 @@ __global__ __launch_bounds__(256) void kv_stream(KvArgs<T, XT> A) {
 template <typename T, typename XT, bool P3, bool DOT>
 __global__ __launch_bounds__(256) void kv_stream_guarded(KvArgs<T, XT> A) {
   if (A.st->done) return;
-  kv_body<T, XT, P3, DOT>(A);
+  kv_body<T, XT, P3, DOT, kv_depth<T>(), kv_kzmax<T>()>(A);
 }
 
 // ------------------------------------------------------------------ host side
@@ -311,24 +376,56 @@ struct KvGeom {
   int tiles_x, tiles_y, chunks_z, kz, ntiles, per_xcd, grid;
 };
 
-static KvGeom kv_geom(const tosimp_ctx* c) {
+// Tiling of the node grid: 15 x 15 node columns per block and `kz` node planes per
+// chunk.  A chunk of kz planes costs kz + 2 plane loads, so deep chunks waste less;
+// but the whole grid runs in ceil(ntiles / resident) rounds of equal blocks, so the
+// chunk count is chosen to minimise rounds * (kz + 2) for the number of blocks the
+// GPU keeps resident (occupancy x CUs).
+static KvGeom kv_geom_for(const tosimp_ctx* c, int resident, int kzmax) {
   KvGeom g;
   g.tiles_x = (c->nx + 1 + KBX - 2) / (KBX - 1);
   g.tiles_y = (c->ny + 1 + KBY - 2) / (KBY - 1);
   const int cols = g.tiles_x * g.tiles_y;
-  // Aim for >= ~2048 blocks (8 per CU) while keeping chunks >= 4 planes deep.
-  int chunks = (2048 + cols - 1) / cols;
-  int kz = (c->nz + 1 + chunks - 1) / chunks;
-  if (kz < 4) kz = 4;
-  g.kz = kz;
-  g.chunks_z = (c->nz + 1 + kz - 1) / kz;
+  const int planes = c->nz + 1;
+  if (resident < 1) resident = 1;
+  double best = 1e300;
+  int best_kz = kzmax < planes ? kzmax : planes;
+  for (int chunks = 1; chunks <= planes; ++chunks) {
+    const int kz = (planes + chunks - 1) / chunks;
+    if (kz > kzmax) continue;
+    const int nch = (planes + kz - 1) / kz;
+    const long long n = (long long)cols * nch;
+    const long long rounds = (n + resident - 1) / resident;
+    // Fewer blocks than resident slots leave CUs idle: count the idle fraction.
+    const double fill = n >= resident ? 1.0 : (double)n / resident;
+    const double cost = (double)rounds * (kz + 2) / fill;
+    if (cost < best - 1e-9) {
+      best = cost;
+      best_kz = kz;
+    }
+  }
+  g.kz = best_kz;
+  g.chunks_z = (planes + g.kz - 1) / g.kz;
   g.ntiles = cols * g.chunks_z;
   g.per_xcd = (g.ntiles + 7) / 8;
   g.grid = g.per_xcd * 8;
   return g;
 }
 
-int kv_num_blocks(const tosimp_ctx* c) { return kv_geom(c).ntiles; }
+static int num_cus(const tosimp_ctx* c) {
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+      n < 1)
+    n = 256;
+  return n;
+}
+
+// Upper bound on the blocks any operator launch uses (for sizing partial sums).
+int kv_num_blocks(const tosimp_ctx* c) {
+  const int tx = (c->nx + 1 + KBX - 2) / (KBX - 1);
+  const int ty = (c->ny + 1 + KBY - 2) / (KBY - 1);
+  return tx * ty * (c->nz + 1);
+}
 
 template <typename T>
 static KvC<T> kv_consts(const tosimp_ctx* c) {
@@ -338,34 +435,44 @@ static KvC<T> kv_consts(const tosimp_ctx* c) {
   return k;
 }
 
+template <typename K>
+static int resident_blocks(const tosimp_ctx* c, K kernel) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu * num_cus(c);
+}
+
+template <typename T, typename XT, bool P3, bool DOT>
+static hipError_t kv_launch_v(const tosimp_ctx* c, KvArgs<T, XT> A, bool guarded) {
+  auto kern = guarded ? kv_stream_guarded<T, XT, P3, DOT> : kv_stream<T, XT, P3, DOT>;
+  static int resident[2] = {0, 0};
+  int& res = resident[guarded ? 1 : 0];
+  if (res == 0) res = resident_blocks(c, kern);
+  const KvGeom g = kv_geom_for(c, res, kv_kzmax<T>());
+  A.tiles_x = g.tiles_x; A.tiles_y = g.tiles_y; A.chunks_z = g.chunks_z; A.kz = g.kz;
+  A.ntiles = g.ntiles; A.per_xcd = g.per_xcd;
+  kern<<<dim3(g.grid), dim3(256), 0, c->stream>>>(A);
+  return hipGetLastError();
+}
+
 template <typename T, typename XT>
 static hipError_t kv_launch_t(const tosimp_ctx* c, const XT* x, const T* v, T* y,
                               double* partials, SolverState* st, double* out, int fin,
                               bool guarded) {
-  const KvGeom g = kv_geom(c);
   KvArgs<T, XT> A;
   A.v = v; A.y = y; A.x = x; A.mask = c->ws.mask;
   A.partials = partials; A.st = st; A.out = out; A.fin = fin;
   A.nx = c->nx; A.ny = c->ny; A.nz = c->nz;
-  A.tiles_x = g.tiles_x; A.tiles_y = g.tiles_y; A.chunks_z = g.chunks_z; A.kz = g.kz;
-  A.ntiles = g.ntiles; A.per_xcd = g.per_xcd;
   A.E0mEmin = (T)(c->E0 - c->Emin); A.Emin = (T)c->Emin; A.penal = (T)c->penal;
   A.k = kv_consts<T>(c);
   const bool p3 = c->penal == 3.0;
   const bool dot = fin != FIN_NONE;
-  dim3 grid(g.grid), block(256);
-  if (guarded) {
-    if (p3 && dot) kv_stream_guarded<T, XT, true, true><<<grid, block, 0, c->stream>>>(A);
-    else if (p3) kv_stream_guarded<T, XT, true, false><<<grid, block, 0, c->stream>>>(A);
-    else if (dot) kv_stream_guarded<T, XT, false, true><<<grid, block, 0, c->stream>>>(A);
-    else kv_stream_guarded<T, XT, false, false><<<grid, block, 0, c->stream>>>(A);
-  } else {
-    if (p3 && dot) kv_stream<T, XT, true, true><<<grid, block, 0, c->stream>>>(A);
-    else if (p3) kv_stream<T, XT, true, false><<<grid, block, 0, c->stream>>>(A);
-    else if (dot) kv_stream<T, XT, false, true><<<grid, block, 0, c->stream>>>(A);
-    else kv_stream<T, XT, false, false><<<grid, block, 0, c->stream>>>(A);
-  }
-  return hipGetLastError();
+  if (p3 && dot) return kv_launch_v<T, XT, true, true>(c, A, guarded);
+  if (p3) return kv_launch_v<T, XT, true, false>(c, A, guarded);
+  if (dot) return kv_launch_v<T, XT, false, true>(c, A, guarded);
+  return kv_launch_v<T, XT, false, false>(c, A, guarded);
 }
 
 hipError_t kv_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
