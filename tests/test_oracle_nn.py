@@ -1,0 +1,130 @@
+"""Pins of the oracle's network pieces: convolutions against a library convolution (torch,
+CPU, float64, tests only), gradients against autograd and finite differences, adjoint
+identities, Adam against its textbook formulas, and flexible CG against plain PCG."""
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+from oracle import fem, nn, solvers
+
+torch.set_default_dtype(torch.float64)
+
+
+@pytest.mark.parametrize("stride,shape", [(1, (3, 5, 4, 6)), (2, (2, 7, 5, 4)), (2, (4, 6, 6, 6))])
+def test_conv3d_matches_library(stride, shape):
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(shape)
+    w = rng.standard_normal((5, shape[0], 3, 3, 3))
+    ref = torch.nn.functional.conv3d(torch.tensor(x)[None], torch.tensor(w), stride=stride,
+                                     padding=1)[0].numpy()
+    y = nn.conv3d(x, w, stride)
+    assert y.shape == ref.shape
+    assert np.max(np.abs(y - ref)) < 1e-12
+
+
+def test_conv1x1_matches_library():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((6, 3, 4, 5))
+    w = rng.standard_normal((3, 6, 1, 1, 1))
+    ref = torch.nn.functional.conv3d(torch.tensor(x)[None], torch.tensor(w))[0].numpy()
+    assert np.max(np.abs(nn.conv3d(x, w) - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("stride,shape,k", [(1, (3, 5, 4, 6), 3), (2, (2, 7, 5, 4), 3),
+                                            (1, (4, 3, 3, 3), 1)])
+def test_conv3d_gradients_match_autograd(stride, shape, k):
+    rng = np.random.default_rng(2)
+    x = torch.tensor(rng.standard_normal(shape), requires_grad=True)
+    w = torch.tensor(rng.standard_normal((3, shape[0], k, k, k)), requires_grad=True)
+    y = torch.nn.functional.conv3d(x[None], w, stride=stride, padding=k // 2)[0]
+    g = torch.tensor(rng.standard_normal(y.shape))
+    (y * g).sum().backward()
+    dx = nn.conv3d_bwd_data(g.numpy(), w.detach().numpy(), shape, stride)
+    dw = nn.conv3d_bwd_weight(x.detach().numpy(), g.numpy(), k, stride)
+    assert np.max(np.abs(dx - x.grad.numpy())) < 1e-12
+    assert np.max(np.abs(dw - w.grad.numpy())) < 1e-12
+
+
+def test_upsample_and_adjoint():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((2, 3, 4, 2))
+    up = nn.upsample(x, (5, 7, 4))
+    assert up.shape == (2, 5, 7, 4)
+    assert up[1, 4, 6, 3] == x[1, 2, 3, 1]
+    g = rng.standard_normal(up.shape)
+    assert abs(np.sum(up * g) - np.sum(x * nn.upsample_adjoint(g, x.shape[1:]))) < 1e-12
+
+
+def test_unet_gradient_finite_difference():
+    base = 2
+    rng = np.random.default_rng(4)
+    params = nn.unet_init(base, 4, 3, seed=1)
+    x = rng.standard_normal((4, 5, 4, 6))
+    target = rng.standard_normal((3, 5, 4, 6))
+    mask = (rng.uniform(size=(3, 5, 4, 6)) > 0.1).astype(float)
+    out, cache = nn.unet_forward(params, x, base)
+    assert out.shape == (3, 5, 4, 6)
+    loss, dout = nn.rel_mse_loss(out, target, mask)
+    grads = nn.unet_backward(params, cache, dout, base)
+    h = 1e-6
+    for name in ["e0a", "d1", "m2b", "u1a", "u0a", "head"]:
+        for _ in range(3):
+            idx = tuple(rng.integers(0, s) for s in params[name].shape)
+            p_ = {k: v.copy() for k, v in params.items()}
+            p_[name][idx] += h
+            lp = nn.rel_mse_loss(nn.unet_forward(p_, x, base)[0], target, mask)[0]
+            p_[name][idx] -= 2 * h
+            lm = nn.rel_mse_loss(nn.unet_forward(p_, x, base)[0], target, mask)[0]
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - grads[name][idx]) <= 1e-6 * max(1e-3, abs(fd)), (name, idx)
+
+
+def test_adam_step_textbook():
+    p = {"a": np.array([1.0, -2.0])}
+    g = {"a": np.array([0.5, 0.25])}
+    st = {}
+    nn.adam_step(p, g, st, lr=0.1)
+    # first step: m = 0.1 g, v = 0.001 g^2, bias-corrected mhat = g, vhat = g^2
+    assert np.allclose(p["a"], [1.0 - 0.1 * 0.5 / (0.5 + 1e-8), -2.0 - 0.1 * 0.25 / (0.25 + 1e-8)],
+                       rtol=0, atol=1e-15)
+
+
+def test_fcg_equals_pcg_with_fixed_preconditioner():
+    nx, ny, nz = 6, 3, 3
+    rho = np.random.default_rng(5).uniform(0.2, 1, nx * ny * nz)
+    E = fem.simp_modulus(rho, 1.0, 1e-9, 3.0)
+    K = fem.assemble_K(nx, ny, nz, E, fem.element_stiffness(0.3))
+    fixed = fem.fixed_mask(K.shape[0], si.cantilever_fixed_dofs(nx, ny, nz))
+    Kc = fem.constrain(K, fixed)
+    f = si.cantilever_load(nx, ny, nz)
+    d = Kc.diagonal()
+    _, it_p, h_p = solvers.pcg_jacobi(lambda v: Kc @ v, d, f, None, 1e-10)
+    _, it_f, h_f = nn.fcg(lambda v: Kc @ v, lambda r: r / d, f, None, 1e-10)
+    # identical in exact arithmetic: the first iterates agree to rounding, the counts
+    # agree up to rounding drift late in the run
+    assert abs(it_p - it_f) <= 2
+    hp, hf = np.array(h_p[:30]), np.array(h_f[:30])
+    assert np.max(np.abs(hf / hp - 1.0)) < 1e-8
+
+
+def test_node_density():
+    x = np.random.default_rng(6).uniform(0, 1, 24)
+    rn = nn.node_density(x, 4, 3, 2)
+    assert rn.shape == (3, 4, 5)
+    assert rn[0, 0, 0] == x[0]
+    e = x.reshape(2, 3, 4)
+    assert abs(rn[1, 1, 1] - e[0:2, 0:2, 0:2].mean()) < 1e-15
+    assert np.allclose(nn.node_density(np.full(24, 0.3), 4, 3, 2), 0.3)
+
+
+def test_nn_preconditioner_masks_and_scales():
+    nx, ny, nz = 4, 3, 2
+    params = nn.unet_init(2, 4, 3, seed=2)
+    rho = nn.node_density(np.full(nx * ny * nz, 0.5), nx, ny, nz)
+    fixed = fem.fixed_mask(3 * 60, si.cantilever_fixed_dofs(nx, ny, nz))
+    r = np.random.default_rng(7).standard_normal(180)
+    z1 = nn.nn_precondition(params, r, rho, fixed, base=2)
+    z2 = nn.nn_precondition(params, 3.0 * r, rho, fixed, base=2)
+    assert np.all(z1[fixed] == 0)
+    assert np.allclose(z2, 3.0 * z1, rtol=1e-12, atol=0)  # homogeneous in ||r||
