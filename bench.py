@@ -144,8 +144,8 @@ def main():
                     help="also run one 1 GiB device copy (for scaling profiler byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the sharded design, one process per GPU, is documented with it).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -14,7 +14,8 @@
  *   Memory      every array argument named *_dev is caller-owned device memory on
  *               the context's device (contiguous, no strides); *_host is host memory.
  *               The library never frees caller memory.  It owns only a workspace it
- *               allocates in tosimp_set_mesh and frees on re-mesh or destroy.
+ *               allocates in tosimp_set_mesh (and tosimp_nn_create) and frees on
+ *               re-mesh or destroy.
  *   Streams     work is enqueued on the context's stream (tosimp_set_stream).  Entry
  *               points that return host scalars synchronise that stream; the others
  *               are asynchronous.
@@ -76,6 +77,10 @@ typedef struct tosimp_solve_opts {
   int check_every;   /* host convergence polls every this many iterations (>= 1)      */
   int enforce_rule;  /* 1: refuse inner precisions failing u*kappa < 1 (needs kappa)  */
   double kappa;      /* condition estimate used by enforce_rule (0: unknown)          */
+  float* harvest_r;  /* PLAIN_FP64 only, optional (NULL = off): device FP32 array of    */
+  float* harvest_u;  /*   harvest_cap x n_dof each, receiving r_k and u_k every          */
+  int harvest_cap;   /*   harvest_every iterations (k = 0, he, 2 he, ...) until full;    */
+  int harvest_every; /*   tosimp_nn_make_targets turns u_k into e_k = u* - u_k           */
 } tosimp_solve_opts;
 
 typedef struct tosimp_solve_stats {
@@ -85,6 +90,7 @@ typedef struct tosimp_solve_stats {
   int status;              /* same value the call returned                           */
   double rel_residual;     /* final ||r|| / ||b|| the solver judged convergence on   */
   double true_rel_residual;/* ||b - K u|| / ||b|| recomputed in FP64 at exit         */
+  int harvested;           /* (r_k, u_k) pairs written to the harvest arrays         */
 } tosimp_solve_stats;
 
 typedef struct tosimp_step_opts {
@@ -150,7 +156,7 @@ int tosimp_diag_K(tosimp_ctx* ctx, const void* xphys_dev, int xdtype, void* d_de
  * Strategy"; Sec. "BF16 Arithmetic in the Conjugate Gradient Solver" for IR mode):
  * solve K_c(xphys) u = b.  xphys: n_elem FP64; b: n_dof FP64 (must be zero on fixed
  * DOFs); u_inout: n_dof FP64 initial guess (warm start), overwritten by the solution
- * (its fixed DOFs are zeroed first).
+ * (its fixed DOFs are zeroed first).  b and u_inout must be 16-byte aligned.
  * PLAIN_FP64: Jacobi-PCG in FP64, stop on the recursive ||r|| <= tol ||b||.
  * IR: outer loop in FP64 (true residual r = b - K u, u += s e) around an inner
  * Jacobi-PCG (or NN flexible CG) in FP32 vectors on the unit-norm residual with FP32
@@ -202,6 +208,51 @@ int tosimp_lanczos(tosimp_ctx* ctx, const double* xphys_dev, const double* v0_de
                    int* steps_host);
 int tosimp_tridiag_extremes(const double* alpha, const double* beta, int m, double* lmin,
                             double* lmax);
+
+/* ---- learned preconditioner -------------------------------------------------------
+ * A 3-level 3D-convolutional U-Net N on the node grid, used as a variable
+ * preconditioner z = ||r|| N(r / ||r||, rho_node) in flexible CG (IR mode with
+ * precond = TOSIMP_PRECOND_NN).  Not in the paper (its Sec. "Path to Geometric
+ * Multigrid Integration" names stronger preconditioners as the way past Jacobi-PCG).
+ * Layers (c_in -> c_out, kernel, stride; b = base): e0a 4->b, e0b b->b, d1 b->2b s2,
+ * e1 2b->2b, d2 2b->4b s2, m2a 4b->4b, m2b 4b->4b, u1a [up(m2b), e1] 6b->2b,
+ * u1b 2b->2b, u0a [up(u1b), e0b] 3b->b, u0b b->b (all 3x3x3, zero padding 1, leaky
+ * ReLU 0.01), head b->3 (1x1x1, linear); nearest up-sampling; no biases.
+ * Weights: FP32 master copy in [layer][c_out][c_in][kz][ky][kx] order (layers as
+ * listed), compute copies in BF16 (bf16 = 1) or FP32.  Training: Adam (0.9, 0.999,
+ * 1e-8) on the relative masked loss sum_free (N - e/||r||)^2 / sum_free (e/||r||)^2.
+ *
+ * tosimp_nn_create: build the network for the current mesh (base 16 or 32); weights
+ *   are zero until set.  Replaces an existing network.  Allocates its workspace.
+ * tosimp_nn_num_params: number of FP32 master weights.
+ * tosimp_nn_set_weights / get_weights: copy the master weights from / to host memory
+ *   (n must equal the count); set_weights also resets the Adam moments.  Synchronise.
+ * tosimp_nn_set_density: nodal density (mean of the adjacent elements) from an FP32
+ *   element density on the device; used by apply and train_step.
+ * tosimp_nn_apply: z = ||r|| N(r/||r||, rho_node), zero on fixed DOFs (FP32 device
+ *   vectors, n_dof; r and z must not alias).
+ * tosimp_nn_forward: test hook, raw network output [n_node][3] FP32 for a channels-last
+ *   input [n_node][4] FP32 (both device).
+ * tosimp_nn_loss_grad: test hook, the loss against target [n_node][3] (device FP32;
+ *   DOFs fixed by the BC mask excluded) into *loss_host and its gradient (master
+ *   layout, host FP32, may be NULL).  Synchronises.
+ * tosimp_nn_train_step: one Adam step on the mean loss of nb pairs (r, e), device FP32
+ *   [nb][n_dof] each.  Synchronises; *loss_host = mean loss before the step.
+ * tosimp_nn_make_targets: harvest_u[k] <- u_star - harvest_u[k] for k < count
+ *   (u_star FP64 device, harvest_u FP32 device [count][n_dof]).                       */
+int tosimp_nn_create(tosimp_ctx* ctx, int base, int bf16);
+int tosimp_nn_num_params(const tosimp_ctx* ctx, int64_t* n);
+int tosimp_nn_set_weights(tosimp_ctx* ctx, const float* w_host, int64_t n);
+int tosimp_nn_get_weights(tosimp_ctx* ctx, float* w_host, int64_t n);
+int tosimp_nn_set_density(tosimp_ctx* ctx, const float* x32_dev);
+int tosimp_nn_apply(tosimp_ctx* ctx, const float* r_dev, float* z_dev);
+int tosimp_nn_forward(tosimp_ctx* ctx, const float* x4_dev, float* out3_dev);
+int tosimp_nn_loss_grad(tosimp_ctx* ctx, const float* x4_dev, const float* target3_dev,
+                        double* loss_host, float* grad_host);
+int tosimp_nn_train_step(tosimp_ctx* ctx, const float* r_batch_dev, const float* e_batch_dev,
+                         int nb, double lr, double* loss_host);
+int tosimp_nn_make_targets(tosimp_ctx* ctx, const double* u_star_dev, float* harvest_u_dev,
+                           int count);
 
 #ifdef __cplusplus
 }

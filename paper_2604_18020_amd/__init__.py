@@ -3,7 +3,7 @@
 The compute path is the HIP library libtosimp.so (C ABI in include/tosimp.h); this
 package is its thin binding.  Import it with the library built in-tree:
 
-    python -m paper_2604_18020_amd.build
+    python paper_2604_18020_amd/build.py
 """
 from .binding import (F32, F64, PREC, Tosimp, TosimpError, tridiag_extremes,  # noqa: F401
                       version, LIB_PATH)

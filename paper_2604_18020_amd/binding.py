@@ -34,13 +34,15 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("mode", C.c_int),
                 ("inner_prec", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int),
                 ("precond", C.c_int), ("check_every", C.c_int), ("enforce_rule", C.c_int),
-                ("kappa", C.c_double)]
+                ("kappa", C.c_double), ("harvest_r", C.c_void_p), ("harvest_u", C.c_void_p),
+                ("harvest_cap", C.c_int), ("harvest_every", C.c_int)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("outer_iterations", C.c_int),
                 ("fallbacks", C.c_int), ("status", C.c_int),
-                ("rel_residual", C.c_double), ("true_rel_residual", C.c_double)]
+                ("rel_residual", C.c_double), ("true_rel_residual", C.c_double),
+                ("harvested", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -63,7 +65,7 @@ class StepStats(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_2604_18020_amd.build` (hipcc, gfx950)")
+                          "`python paper_2604_18020_amd/build.py` (hipcc, gfx950)")
     lib = C.CDLL(LIB_PATH)
     P, I, D, L = C.c_void_p, C.c_int, C.c_double, C.c_int64
     sig = {
@@ -85,6 +87,16 @@ def _load():
         "tosimp_simp_step": (I, [P, P, P, P, C.POINTER(StepOpts), C.POINTER(StepStats)]),
         "tosimp_lanczos": (I, [P, P, P, I, I, P, P, C.POINTER(I)]),
         "tosimp_tridiag_extremes": (I, [P, P, I, C.POINTER(D), C.POINTER(D)]),
+        "tosimp_nn_create": (I, [P, I, I]),
+        "tosimp_nn_num_params": (I, [P, C.POINTER(L)]),
+        "tosimp_nn_set_weights": (I, [P, P, L]),
+        "tosimp_nn_get_weights": (I, [P, P, L]),
+        "tosimp_nn_set_density": (I, [P, P]),
+        "tosimp_nn_apply": (I, [P, P, P]),
+        "tosimp_nn_forward": (I, [P, P, P]),
+        "tosimp_nn_loss_grad": (I, [P, P, P, C.POINTER(D), P]),
+        "tosimp_nn_train_step": (I, [P, P, P, I, D, C.POINTER(D)]),
+        "tosimp_nn_make_targets": (I, [P, P, P, I]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -190,13 +202,21 @@ class Tosimp:
     # ------------------------------------------------------------------ solve
     @staticmethod
     def solve_opts(tol=1e-8, maxit=20000, mode="plain_fp64", inner_prec="fp32",
-                   inner_tol=1e-3, max_outer=30, precond="jacobi", check_every=16,
+                   inner_tol=1e-5, max_outer=30, precond="jacobi", check_every=16,
                    enforce_rule=False, kappa=0.0):
         return SolveOpts(tol, maxit, SOLVE[mode], PREC[inner_prec], inner_tol, max_outer,
-                         PRECOND[precond], check_every, int(enforce_rule), kappa)
+                         PRECOND[precond], check_every, int(enforce_rule), kappa, None, None,
+                         0, 0)
 
-    def pcg_solve(self, x, b, u, **kw):
+    def pcg_solve(self, x, b, u, harvest=None, harvest_every=1, **kw):
+        """harvest: optional (r, u) pair of FP32 device tensors [cap, n_dof] (plain FP64)."""
         o = self.solve_opts(**kw)
+        if harvest is not None:
+            hr, hu = harvest
+            cap = hr.shape[0]
+            o.harvest_r = self._dev(hr, torch.float32, cap * self.n_dof, "harvest_r").value
+            o.harvest_u = self._dev(hu, torch.float32, cap * self.n_dof, "harvest_u").value
+            o.harvest_cap, o.harvest_every = cap, int(harvest_every)
         s = SolveStats()
         self._sync_stream()
         rc = self._check(LIB.tosimp_pcg_solve(
@@ -263,6 +283,76 @@ class Tosimp:
             self._dev(v0, torch.float64, self.n_dof, "v0"), k, int(jacobi_scaled),
             a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), C.byref(m)))
         return a[:m.value].copy(), b[:max(m.value - 1, 0)].copy()
+
+
+    # ------------------------------------------------------------------ learned preconditioner
+    def nn_create(self, base=16, bf16=True):
+        self._sync_stream()
+        self._check(LIB.tosimp_nn_create(self._h, int(base), int(bool(bf16))))
+        n = C.c_int64()
+        self._check(LIB.tosimp_nn_num_params(self._h, C.byref(n)))
+        self.nn_params = n.value
+        return self
+
+    def nn_set_weights(self, w):
+        a = np.ascontiguousarray(np.asarray(w, dtype=np.float32).reshape(-1))
+        self._sync_stream()
+        self._check(LIB.tosimp_nn_set_weights(self._h, a.ctypes.data_as(C.c_void_p), a.size))
+
+    def nn_get_weights(self):
+        a = np.zeros(self.nn_params, dtype=np.float32)
+        self._sync_stream()
+        self._check(LIB.tosimp_nn_get_weights(self._h, a.ctypes.data_as(C.c_void_p), a.size))
+        return a
+
+    def nn_set_density(self, x32):
+        self._sync_stream()
+        self._check(LIB.tosimp_nn_set_density(self._h, self._dev(x32, torch.float32, self.n_elem,
+                                                                 "x32")))
+
+    def nn_apply(self, r, z=None):
+        if z is None:
+            z = torch.empty_like(r)
+        self._sync_stream()
+        self._check(LIB.tosimp_nn_apply(self._h, self._dev(r, torch.float32, self.n_dof, "r"),
+                                        self._dev(z, torch.float32, self.n_dof, "z")))
+        return z
+
+    def nn_forward(self, x4):
+        out = torch.empty(self.n_node, 3, dtype=torch.float32, device=x4.device)
+        self._sync_stream()
+        self._check(LIB.tosimp_nn_forward(self._h, self._dev(x4, torch.float32, 4 * self.n_node,
+                                                             "x4"),
+                                          self._dev(out, torch.float32, 3 * self.n_node, "out")))
+        return out
+
+    def nn_loss_grad(self, x4, target3, want_grad=True):
+        loss = C.c_double()
+        g = np.zeros(self.nn_params, dtype=np.float32) if want_grad else None
+        self._sync_stream()
+        self._check(LIB.tosimp_nn_loss_grad(
+            self._h, self._dev(x4, torch.float32, 4 * self.n_node, "x4"),
+            self._dev(target3, torch.float32, 3 * self.n_node, "target"), C.byref(loss),
+            g.ctypes.data_as(C.c_void_p) if want_grad else None))
+        return loss.value, g
+
+    def nn_train_step(self, r_batch, e_batch, lr=1e-3):
+        nb = r_batch.shape[0]
+        loss = C.c_double()
+        self._sync_stream()
+        self._check(LIB.tosimp_nn_train_step(
+            self._h, self._dev(r_batch, torch.float32, nb * self.n_dof, "r_batch"),
+            self._dev(e_batch, torch.float32, nb * self.n_dof, "e_batch"), nb, lr,
+            C.byref(loss)))
+        return loss.value
+
+    def nn_make_targets(self, u_star, harvest_u, count):
+        if harvest_u.numel() < int(count) * self.n_dof:
+            raise ValueError("harvest_u holds fewer than count x n_dof values")
+        self._sync_stream()
+        self._check(LIB.tosimp_nn_make_targets(
+            self._h, self._dev(u_star, torch.float64, self.n_dof, "u_star"),
+            self._dev(harvest_u, torch.float32, None, "harvest_u"), int(count)))
 
 
 def tridiag_extremes(alpha, beta):

@@ -1,6 +1,9 @@
 """Compile the gfx950 HIP sources of the library into an in-tree shared object.
 
-    python -m paper_2604_18020_amd.build        # or build() from Python
+    python paper_2604_18020_amd/build.py        # or build() from Python
+
+This file imports nothing from the package (whose import loads the library), so it
+runs with the library absent or stale.
 
 Every translation unit in csrc/ is compiled with hipcc for gfx950 only, then linked
 into paper_2604_18020_amd/libtosimp.so next to this file.
@@ -22,7 +25,8 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtosimp.so")
 
 ARCH = "gfx950"
-# Packed FP32 instructions are disabled for every device pass.
+# Packed FP32 instructions are disabled for every device pass: some of their forms have
+# produced silently wrong results on this hardware.
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
@@ -60,7 +64,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     if errors:
         raise RuntimeError("hipcc failed for: " + ", ".join(map(os.path.basename, errors)))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,-z,defs", *objs, "-o", tmp]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode:
         raise RuntimeError("link failed:\n" + p.stdout + p.stderr)

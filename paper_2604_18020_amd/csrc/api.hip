@@ -9,22 +9,6 @@
 
 using namespace tosimp;
 
-namespace tosimp {
-hipError_t kv_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
-                     const void* v, void* y, double* partials, SolverState* st,
-                     double* out, int fin, bool guarded);
-hipError_t kv_mfma_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
-                          const float* v, float* y, SolverState* st, bool guarded);
-hipError_t launch_alpha_from_dot32(const tosimp_ctx* c, const float* p, const float* q,
-                                   double* partials, SolverState* st);
-hipError_t launch_sqrt_scalar(const tosimp_ctx* c, const SolverState* st, double* out);
-}  // namespace tosimp
-
-extern "C" void tosimp_nn_release(tosimp_ctx* ctx);
-extern "C" int tosimp_nn_fcg_solve(tosimp_ctx* ctx, const float* x32, const float* b32,
-                                   float* e32, double tol, int maxit, int check_every,
-                                   int prec, int* iters, int* fallbacks, int* done);
-
 int tosimp_fail(tosimp_ctx* ctx, int code, const std::string& msg) {
   if (ctx) ctx->err = msg;
   return code;
@@ -167,10 +151,11 @@ bool hadamard_consts(const double* KE, HadConsts* hc, double* max_dev) {
 }
 
 void free_ws(tosimp_ctx* c) {
+  nn_release(c);  // the network's tensors are sized for the mesh
   Workspace& w = c->ws;
   void* dev[] = {w.mask, w.f,   w.Hs,  w.dv,  w.fw,  w.dinv, w.dinv32,  w.r,
                  w.p,    w.q,   w.w,   w.r32, w.p32, w.q32,  w.e32,     w.z32,
-                 w.x32,  w.etmp, w.partials, w.lanczos, w.st, w.oc};
+                 w.x32,  w.etmp, w.partials, w.lanczos, w.st, w.oc, w.ke_mfma};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (w.st_host) (void)hipHostFree(w.st_host);
@@ -224,7 +209,7 @@ int tosimp_destroy(tosimp_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   free_ws(ctx);
-  tosimp_nn_release(ctx);
+  nn_release(ctx);
   delete ctx;
   return TOSIMP_OK;
 }
@@ -315,6 +300,7 @@ int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0
   A(dmalloc(&w.partials, sizeof(double) * kMaxPartials * 4));
   A(dmalloc(&w.st, sizeof(SolverState) * 3));
   A(dmalloc(&w.oc, sizeof(OcState)));
+  A(dmalloc(&w.ke_mfma, sizeof(uint16_t) * 2 * 2 * 64 * 8));
   if (e == hipSuccess) e = hipHostMalloc((void**)&w.st_host, sizeof(SolverState) * 3);
   if (e == hipSuccess) e = hipHostMalloc((void**)&w.oc_host, sizeof(OcState));
   if (e != hipSuccess) {
@@ -327,6 +313,32 @@ int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0
   TOSIMP_HIP(ctx, hipMemsetAsync(w.oc, 0, sizeof(OcState), ctx->stream));
   TOSIMP_HIP(ctx, hipMemcpyAsync(w.fw, ctx->fw_host, sizeof(double) * kMaxFilterTaps,
                                  hipMemcpyHostToDevice, ctx->stream));
+  {
+    // K_E (24x24, zero-padded to 32x32) in the A-operand lane layout of
+    // v_mfma_f32_16x16x32_{bf16,f16}: lane l holds row 16 t + l % 16, columns
+    // 8 (l / 16) .. + 7 of row tile t; rounding to nearest even.
+    std::vector<uint16_t> tab(2 * 2 * 64 * 8);
+    for (int pr = 0; pr < 2; ++pr)
+      for (int t = 0; t < 2; ++t)
+        for (int l = 0; l < 64; ++l)
+          for (int j = 0; j < 8; ++j) {
+            const int m = 16 * t + l % 16, k = 8 * (l / 16) + j;
+            const float v = (m < 24 && k < 24) ? (float)ctx->KE[m * 24 + k] : 0.0f;
+            uint16_t bits;
+            if (pr == 0) {
+              uint32_t u;
+              std::memcpy(&u, &v, 4);
+              bits = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+            } else {
+              const _Float16 hv = (_Float16)v;
+              std::memcpy(&bits, &hv, 2);
+            }
+            tab[((pr * 2 + t) * 64 + l) * 8 + j] = bits;
+          }
+    TOSIMP_HIP(ctx, hipMemcpyAsync(w.ke_mfma, tab.data(), tab.size() * 2, hipMemcpyHostToDevice,
+                                   ctx->stream));
+    TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
   TOSIMP_HIP(ctx, launch_filter_rowsum(ctx, w.Hs));
   // dv = H (1 / Hs): adjoint filter of a vector of ones.
   double* ones = w.etmp;
@@ -421,7 +433,15 @@ namespace {
 struct PcgResult {
   int iters = 0;
   int done = 0;
+  int harvested = 0;
   double rr = 0, bb = 0;
+};
+
+// Optional copies of (r_k, u_k) taken at the host polls of an FP64 solve.
+struct Harvest {
+  float* r = nullptr;
+  float* u = nullptr;
+  int cap = 0;
 };
 
 // Jacobi-PCG on K_c(x) with vectors of type T; b, u, dinv of type T.  When zero_guess
@@ -429,7 +449,7 @@ struct PcgResult {
 template <typename T>
 int run_pcg(tosimp_ctx* ctx, int prec, const void* x, int xdtype, const T* b, T* u,
             const T* dinv, int slot, double tol, int maxit, int check_every, bool zero_guess,
-            PcgResult* res) {
+            PcgResult* res, const Harvest* hv = nullptr) {
   Workspace& w = ctx->ws;
   T *r, *p, *q;
   if constexpr (sizeof(T) == 8) {
@@ -461,6 +481,14 @@ int run_pcg(tosimp_ctx* ctx, int prec, const void* x, int xdtype, const T* b, T*
                                    ctx->stream));
     TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (sh->done) break;
+    if constexpr (sizeof(T) == 8) {
+      if (hv && res->harvested < hv->cap) {
+        const size_t off = (size_t)res->harvested * ctx->n_dof;
+        TOSIMP_HIP(ctx, launch_cast32(ctx, (const double*)r, hv->r + off, ctx->n_dof));
+        TOSIMP_HIP(ctx, launch_cast32(ctx, (const double*)u, hv->u + off, ctx->n_dof));
+        res->harvested += 1;
+      }
+    }
     for (int i = 0; i < check_every; ++i) {
       if (mfma) {
         // MFMA operator computes q only; the step length comes from a separate dot.
@@ -530,6 +558,8 @@ int tosimp_pcg_solve(tosimp_ctx* ctx, const double* x, const double* b, double* 
   REQUIRE(o->mode == TOSIMP_SOLVE_PLAIN_FP64 || o->mode == TOSIMP_SOLVE_IR, TOSIMP_EINVAL,
           "bad solve mode");
   REQUIRE(b != u, TOSIMP_EINVAL, "u must not alias b");
+  REQUIRE(((uintptr_t)u & 15) == 0 && ((uintptr_t)b & 15) == 0, TOSIMP_EINVAL,
+          "u and b must be 16-byte aligned");
   if ((rc = set_device(ctx))) return rc;
   tosimp_solve_stats s{};
   Workspace& w = ctx->ws;
@@ -539,9 +569,20 @@ int tosimp_pcg_solve(tosimp_ctx* ctx, const double* x, const double* b, double* 
             "plain FP64 mode uses the Jacobi preconditioner");
     TOSIMP_HIP(ctx, launch_diag_inv(ctx, x, w.dinv, nullptr));
     PcgResult pr;
+    Harvest hv;
+    int every = o->check_every;
+    if (o->harvest_r || o->harvest_u) {
+      REQUIRE(o->harvest_r && o->harvest_u && o->harvest_cap >= 1 && o->harvest_every >= 1,
+              TOSIMP_EINVAL, "harvest needs both arrays, harvest_cap >= 1, harvest_every >= 1");
+      hv.r = o->harvest_r;
+      hv.u = o->harvest_u;
+      hv.cap = o->harvest_cap;
+      every = o->harvest_every;
+    }
     rc = run_pcg<double>(ctx, TOSIMP_PREC_FP64, x, TOSIMP_F64, b, u, w.dinv, 0, o->tol,
-                         o->maxit, o->check_every, false, &pr);
+                         o->maxit, every, false, &pr, hv.cap ? &hv : nullptr);
     if (rc) return rc;
+    s.harvested = pr.harvested;
     s.iterations = pr.iters;
     s.rel_residual = pr.bb > 0 ? std::sqrt(pr.rr / pr.bb) : 0.0;
     s.status = pr.done == 3 ? TOSIMP_EBREAKDOWN
@@ -587,8 +628,8 @@ int tosimp_pcg_solve(tosimp_ctx* ctx, const double* x, const double* b, double* 
       int it = 0, done = 0;
       if (o->precond == TOSIMP_PRECOND_NN) {
         int fb = 0;
-        rc = tosimp_nn_fcg_solve(ctx, w.x32, w.e32, w.z32, o->inner_tol, o->maxit - total,
-                                 o->check_every, ip, &it, &fb, &done);
+        rc = nn_fcg_solve(ctx, ip, w.x32, w.e32, w.z32, o->inner_tol, o->maxit - total,
+                          o->check_every, &it, &fb, &done);
         if (rc < 0) return rc;
         fallbacks += fb;
       } else {

@@ -46,7 +46,7 @@ struct SolverState {
   int iter;       // completed iterations
   int maxit;      // iteration cap
   int done;       // 0 running, 1 converged, 2 cap, 3 breakdown
-  int pad;
+  int nfallback;  // flexible CG: preconditioner fallbacks taken
   unsigned cnt[4];  // last-block counters (reset by the last block)
 };
 
@@ -82,6 +82,7 @@ struct Workspace {
   float* x32 = nullptr;        // n_elem FP32 density copy
   double* etmp = nullptr;      // n_elem scratch (x 4)
   double* partials = nullptr;  // kMaxPartials x 4
+  uint16_t* ke_mfma = nullptr; // K_E in the MFMA A-operand layout: [bf16|f16][2][64][8]
   double* lanczos = nullptr;   // 2 x (kmax) alpha/beta on device
   int lanczos_cap = 0;
   SolverState* st = nullptr;   // 2 solver states (outer / inner)
@@ -122,7 +123,14 @@ int tosimp_fail(tosimp_ctx* ctx, int code, const std::string& msg);
 // ----------------------------------------------------------- kernel launch wrappers
 namespace tosimp {
 
-// Operator kernels (kv.hip).
+// Operator kernels (kv.hip, kv_mfma.hip).  kv_launch: y = K_c(x) v with an optional
+// fused <v, y> finished into st (FIN_ALPHA) or *out (FIN_SCALAR); guarded launches
+// return at once when st->done is set.
+hipError_t kv_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
+                     const void* v, void* y, double* partials, SolverState* st,
+                     double* out, int fin, bool guarded);
+hipError_t kv_mfma_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
+                          const float* v, float* y, SolverState* st, bool guarded);
 hipError_t launch_apply_K(const tosimp_ctx* c, int prec, int xdtype, const void* x,
                           const void* v, void* y, double* dot_partials, int* nblocks);
 int kv_num_blocks(const tosimp_ctx* c);
@@ -149,6 +157,7 @@ hipError_t launch_residual64(const tosimp_ctx* c, const double* b, const double*
 hipError_t launch_scale_to32(const tosimp_ctx* c, const double* r, double inv_s, float* r32);
 hipError_t launch_axpy_from32(const tosimp_ctx* c, double* u, double s, const float* e);
 hipError_t launch_copy_cast_x(const tosimp_ctx* c, const double* x, float* x32);
+hipError_t launch_cast32(const tosimp_ctx* c, const double* x, float* y, int64_t n);
 hipError_t launch_fill_zero(const tosimp_ctx* c, void* p, int64_t bytes);
 hipError_t launch_dot64(const tosimp_ctx* c, const double* a, const double* b, int64_t n,
                         double* partials, SolverState* st, int what);
@@ -161,6 +170,16 @@ hipError_t launch_lanczos_normalize(const tosimp_ctx* c, const double* w, const 
 hipError_t launch_node_scale(const tosimp_ctx* c, const double* s_node, const double* v,
                              double* out);
 hipError_t launch_sqrt_node(const tosimp_ctx* c, const double* dinv, double* out);
+hipError_t launch_alpha_from_dot32(const tosimp_ctx* c, const float* p, const float* q,
+                                   double* partials, SolverState* st);
+hipError_t launch_sqrt_scalar(const tosimp_ctx* c, const SolverState* st, double* out);
+
+// Learned preconditioner (nn.hip).  nn_fcg_solve: flexible CG on K_c(x32) e = b32 with
+// the network as preconditioner (Jacobi fallback), FP32 vectors, zero initial guess.
+void nn_release(tosimp_ctx* ctx);
+int nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const float* b32, float* e32,
+                 double tol, int maxit, int check_every, int* iters, int* fallbacks,
+                 int* done);
 
 // SIMP kernels (topopt.hip).
 hipError_t launch_sensitivity(const tosimp_ctx* c, const double* xphys, const double* u,

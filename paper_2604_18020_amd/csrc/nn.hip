@@ -1,9 +1,1151 @@
-// Learned preconditioner (U-Net) state; filled in by the network kernels.
+// Learned preconditioner: 3D-convolutional U-Net on the node grid, trained on the GPU.
+//
+// Not in the paper (its Sec. "Path to Geometric Multigrid Integration" names stronger
+// preconditioning as the way past Jacobi-PCG); the network follows the project brief:
+// 3 levels with base, 2 base and 4 base channels, inputs (r_x, r_y, r_z, nodal density),
+// output a 3-component correction, LeakyReLU, no biases, nearest up-sampling and
+// concatenated skips.  The layer list is the same as the oracle's.
+//
+// Tensors are channels-last: [voxel][channel], voxel = x + X (y + Y z) on a level's grid.
+// Convolutions are implicit GEMMs on the matrix cores:
+//   forward      Y[o][co]  = sum_{t, ci} W[co][t][ci] X[nbr(o, t)][ci]
+//   data grad    dX[i][ci] = sum_{t, co} W[co][t][ci] dZ[o(i, t)][co]   (W stored as WT)
+//   weight grad  dW[co][t][ci] = sum_o dZ[o][co] X[nbr(o, t)][ci]
+// with K = taps x channels in chunks of 32 (one v_mfma_f32_16x16x32_bf16, or eight
+// v_mfma_f32_16x16x4f32 for FP32 storage).  A wave owns 16 output voxels x all output
+// channels.  dZ = dY * leaky'(a) is formed on load from the layer's stored activation a
+// (leaky ReLU preserves the sign, so a determines the slope).  Weight gradients are
+// reduced per voxel chunk and the chunks summed in a fixed order (deterministic).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "common.h"
+#include "dev.h"
 
-extern "C" void tosimp_nn_release(tosimp_ctx* ctx) { (void)ctx; }
+namespace tosimp {
 
-extern "C" int tosimp_nn_fcg_solve(tosimp_ctx* ctx, const float*, const float*, float*, double,
-                                   int, int, int, int*, int*, int*) {
-  return tosimp_fail(ctx, TOSIMP_ESTATE, "no learned preconditioner has been created");
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr float kLeak = 0.01f;
+
+// ---------------------------------------------------------------- element types
+struct bf16_t {
+  unsigned short bits;
+};
+
+__device__ __forceinline__ float to_f(float v) { return v; }
+__device__ __forceinline__ float to_f(bf16_t v) { return __uint_as_float((unsigned)v.bits << 16); }
+template <typename ST>
+__device__ __forceinline__ ST from_f(float f);
+template <>
+__device__ __forceinline__ float from_f<float>(float f) { return f; }
+template <>
+__device__ __forceinline__ bf16_t from_f<bf16_t>(float f) {
+  const unsigned u = __float_as_uint(f);
+  bf16_t r;
+  r.bits = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  return r;
 }
+
+// Eight consecutive values of a row (16 bytes for bf16, 32 for fp32).
+template <typename ST>
+struct Pack8;
+template <>
+struct Pack8<bf16_t> {
+  u16x8 v;
+  __device__ __forceinline__ void load(const bf16_t* p) { v = *reinterpret_cast<const u16x8*>(p); }
+  __device__ __forceinline__ void zero() { v = (u16x8){0, 0, 0, 0, 0, 0, 0, 0}; }
+  __device__ __forceinline__ float get(int j) const { return __uint_as_float((unsigned)v[j] << 16); }
+  __device__ __forceinline__ void set(int j, float f) { v[j] = from_f<bf16_t>(f).bits; }
+};
+template <>
+struct Pack8<float> {
+  float v[8];
+  __device__ __forceinline__ void load(const float* p) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    const float4 b = *reinterpret_cast<const float4*>(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  }
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = 0.0f;
+  }
+  __device__ __forceinline__ float get(int j) const { return v[j]; }
+  __device__ __forceinline__ void set(int j, float f) { v[j] = f; }
+};
+
+// acc += A (16 x 32) * B (32 x 16): lane (m or n = l % 16, q = l / 16) supplies eight
+// consecutive k of the chunk, k = 8 q + j (the same assignment in A and B).
+__device__ __forceinline__ void mma32(f32x4& acc, const Pack8<bf16_t>& a, const Pack8<bf16_t>& b) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a.v),
+                                                __builtin_bit_cast(bf16x8, b.v), acc, 0, 0, 0);
+}
+__device__ __forceinline__ void mma32(f32x4& acc, const Pack8<float>& a, const Pack8<float>& b) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[j], b.v[j], acc, 0, 0, 0);
+}
+
+struct Grid3 {
+  int X, Y, Z;
+  __host__ __device__ int n() const { return X * Y * Z; }
+};
+
+// ------------------------------------------------------------- convolution kernels
+struct ConvArgs {
+  const void* in;      // FWD: X [Vin][cin]; BWD: dY [Vout][cout] (gradient wrt the output)
+  const void* act;     // BWD: the layer's stored output a [Vout][cout] (null: no activation)
+  const void* w;       // FWD: W [cout][taps][cin]; BWD: WT [cin][taps][cout]
+  void* out;           // FWD: Y [Vout][cout]; BWD: dX [Vin][cin]
+  Grid3 gin, gout;     // input / output grids of the forward convolution
+  int cin, cout;       // channels (multiples of 8 / 16) of the forward convolution
+  int ksize, stride;
+  int apply_act;       // FWD: leaky ReLU on the output
+};
+
+// One wave: 16 "row" voxels of the result x a group of up to 64 result channels
+// (blockIdx.y selects the group).  FWD rows are output voxels, K = taps x cin, result
+// channels cout; BWD rows are input voxels, K = taps x cout, result channels cin.
+template <typename ST, bool BWD>
+__global__ __launch_bounds__(256) void conv_igemm_kernel(ConvArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const Grid3 rg = BWD ? a.gin : a.gout;   // grid of the rows
+  const Grid3 og = BWD ? a.gout : a.gin;   // grid the operand A is read from
+  const int nrow = rg.n();
+  const int v0 = wave * 16;
+  if (v0 >= nrow) return;
+  const int kch = BWD ? a.cout : a.cin;    // channels along K
+  const int nres = BWD ? a.cin : a.cout;   // result channels
+  const int taps = a.ksize * a.ksize * a.ksize;
+  const int K = taps * kch;
+  const int m = lane & 15, q = lane >> 4;
+  const int v = v0 + m;
+  const bool vok = v < nrow;
+  const int vx = v % rg.X, vy = (v / rg.X) % rg.Y, vz = v / (rg.X * rg.Y);
+  const int pad = a.ksize / 2;
+  const ST* in = (const ST*)a.in;
+  const ST* act = (const ST*)a.act;
+  const ST* w = (const ST*)a.w;
+  const int cg = blockIdx.y * 64;  // first result channel of this group
+  const int nblk = min(4, (nres - cg) / 16);
+  f32x4 acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int k = k0 + 8 * q;
+    Pack8<ST> A;
+    A.zero();
+    if (vok && k < K) {
+      const int t = k / kch, c = k - t * kch;
+      const int tx = t % a.ksize, ty = (t / a.ksize) % a.ksize, tz = t / (a.ksize * a.ksize);
+      int sx, sy, sz;
+      bool ok;
+      if (!BWD) {
+        sx = vx * a.stride + tx - pad;
+        sy = vy * a.stride + ty - pad;
+        sz = vz * a.stride + tz - pad;
+        ok = sx >= 0 && sx < og.X && sy >= 0 && sy < og.Y && sz >= 0 && sz < og.Z;
+      } else {
+        const int ux = vx + pad - tx, uy = vy + pad - ty, uz = vz + pad - tz;
+        ok = ux >= 0 && uy >= 0 && uz >= 0 && ux % a.stride == 0 && uy % a.stride == 0 &&
+             uz % a.stride == 0;
+        sx = ux / a.stride;
+        sy = uy / a.stride;
+        sz = uz / a.stride;
+        ok = ok && sx < og.X && sy < og.Y && sz < og.Z;
+      }
+      if (ok) {
+        const long long s = (long long)sx + (long long)og.X * (sy + (long long)og.Y * sz);
+        A.load(in + s * kch + c);
+        if (BWD && act) {
+          Pack8<ST> av;
+          av.load(act + s * kch + c);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) A.set(j, A.get(j) * (av.get(j) > 0.0f ? 1.0f : kLeak));
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b < nblk) {
+        Pack8<ST> B;
+        B.zero();
+        if (k < K) B.load(w + (long long)(cg + b * 16 + m) * K + k);
+        mma32(acc[b], A, B);
+      }
+    }
+  }
+  ST* out = (ST*)a.out;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    if (b < nblk) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = v0 + 4 * q + j;
+        if (row < nrow) {
+          float val = acc[b][j];
+          if (!BWD && a.apply_act) val = val > 0.0f ? val : kLeak * val;
+          out[(long long)row * nres + cg + b * 16 + m] = from_f<ST>(val);
+        }
+      }
+    }
+  }
+}
+
+// Weight gradient, one block per (chunk of cvox output voxels, tap): the block's four
+// waves split the (cout/16) x (cin/16) tiles; K = the chunk's voxels, 8 per lane group.
+// Partial sums go to part[chunk][cout][taps][cin]; conv_wgrad_reduce sums the chunks in
+// index order.  cvox is a multiple of 32.
+template <typename ST>
+__global__ __launch_bounds__(256) void conv_wgrad_kernel(ConvArgs a, float* part, int cvox) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int chunk = blockIdx.x, t = blockIdx.y;
+  const int taps = a.ksize * a.ksize * a.ksize;
+  const int pad = a.ksize / 2;
+  const int tx = t % a.ksize, ty = (t / a.ksize) % a.ksize, tz = t / (a.ksize * a.ksize);
+  const ST* X = (const ST*)a.in;   // layer input [Vin][cin]
+  const ST* dY = (const ST*)a.out; // gradient wrt the layer output [Vout][cout]
+  const ST* act = (const ST*)a.act;
+  const int nco = a.cout / 16, nci = (a.cin + 15) / 16;
+  const int m = lane & 15, q = lane >> 4;
+  const int Vout = a.gout.n();
+  for (int tile = wv; tile < nco * nci; tile += 4) {
+    const int cb = tile / nci, ib = tile % nci;
+    const int co = cb * 16 + m, ci = ib * 16 + m;
+    f32x4 acc = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < cvox; k0 += 32) {
+      Pack8<ST> A, B;  // A: dZ^T (co x voxels), B: X_t (voxels x ci)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int o = chunk * cvox + k0 + 8 * q + j;
+        float dz = 0.0f, xv = 0.0f;
+        if (o < Vout) {
+          dz = to_f(dY[(long long)o * a.cout + co]);
+          if (act) dz *= to_f(act[(long long)o * a.cout + co]) > 0.0f ? 1.0f : kLeak;
+          const int ox = o % a.gout.X, oy = (o / a.gout.X) % a.gout.Y, oz = o / (a.gout.X * a.gout.Y);
+          const int sx = ox * a.stride + tx - pad, sy = oy * a.stride + ty - pad,
+                    sz = oz * a.stride + tz - pad;
+          if (ci < a.cin && sx >= 0 && sx < a.gin.X && sy >= 0 && sy < a.gin.Y && sz >= 0 &&
+              sz < a.gin.Z)
+            xv = to_f(X[((long long)sx + (long long)a.gin.X * (sy + (long long)a.gin.Y * sz)) *
+                            a.cin + ci]);
+        }
+        A.set(j, dz);
+        B.set(j, xv);
+      }
+      mma32(acc, A, B);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int orow = cb * 16 + 4 * q + j;  // co
+      const int ocol = ib * 16 + m;          // ci
+      if (ocol < a.cin)
+        part[(((long long)chunk * a.cout + orow) * taps + t) * a.cin + ocol] = acc[j];
+    }
+  }
+}
+
+__global__ void conv_wgrad_reduce(const float* part, int nchunk, int n, float* grad, int accumulate) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int c = 0; c < nchunk; ++c) s += part[(long long)c * n + i];
+    grad[i] = accumulate ? grad[i] + s : s;
+  }
+}
+
+// ----------------------------------------------------------- elementwise kernels
+// Network input: [v][0..2] = r / ||r|| (DOF vector is node-major, so already
+// channels-last), [v][3] = nodal density, [v][4..7] = 0.
+template <typename ST>
+__global__ void build_input_kernel(const float* r, const double* rnorm2, const float* rho_node,
+                                   ST* inp, int n_node) {
+  const float inv = (float)(1.0 / sqrt(fmax(*rnorm2, 1e-300)));
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n_node; v += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) inp[8 * v + c] = from_f<ST>(r[3 * v + c] * inv);
+    inp[8 * v + 3] = from_f<ST>(rho_node[v]);
+#pragma unroll
+    for (int c = 4; c < 8; ++c) inp[8 * v + c] = from_f<ST>(0.0f);
+  }
+}
+
+// Same from an FP32 channels-last [v][4] tensor (test hook / training input).
+template <typename ST>
+__global__ void pad_input_kernel(const float* x4, ST* inp, int n) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) inp[8 * v + c] = from_f<ST>(x4[4 * v + c]);
+#pragma unroll
+    for (int c = 4; c < 8; ++c) inp[8 * v + c] = from_f<ST>(0.0f);
+  }
+}
+
+// Nodal density: mean of the (up to 8) elements around each node.
+__global__ void node_density_kernel(const float* x, int nx, int ny, int nz, float* rho) {
+  const int n_node = (nx + 1) * (ny + 1) * (nz + 1);
+  for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < n_node; n += gridDim.x * blockDim.x) {
+    const int i = n % (nx + 1), j = (n / (nx + 1)) % (ny + 1), k = n / ((nx + 1) * (ny + 1));
+    float s = 0.0f;
+    int c = 0;
+    for (int dz = -1; dz <= 0; ++dz)
+      for (int dy = -1; dy <= 0; ++dy)
+        for (int dx = -1; dx <= 0; ++dx) {
+          const int ex = i + dx, ey = j + dy, ez = k + dz;
+          if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
+          s += x[ex + nx * (ey + ny * ez)];
+          ++c;
+        }
+    rho[n] = s / (float)c;
+  }
+}
+
+// [up(coarse) | skip] concatenation: dst[v][0..c1) = coarse[parent(v)], dst[v][c1..) = skip[v].
+template <typename ST>
+__global__ void upcat_kernel(const ST* coarse, Grid3 gc, int c1, const ST* skip, int c2, ST* dst,
+                             Grid3 gf) {
+  const int n = gf.n(), ct = c1 + c2;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (long long)n * ct;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int v = (int)(i / ct), c = (int)(i % ct);
+    if (c < c1) {
+      const int x = v % gf.X, y = (v / gf.X) % gf.Y, z = v / (gf.X * gf.Y);
+      const int pv = (x / 2) + gc.X * ((y / 2) + gc.Y * (z / 2));
+      dst[i] = coarse[(long long)pv * c1 + c];
+    } else {
+      dst[i] = skip[(long long)v * c2 + (c - c1)];
+    }
+  }
+}
+
+// Adjoint of the up-sampling half of upcat: coarse[pv][c] = sum over children of g[v][c].
+template <typename ST>
+__global__ void upcat_adjoint_kernel(const ST* g, Grid3 gf, int ct, ST* coarse, Grid3 gc, int c1) {
+  const int n = gc.n();
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (long long)n * c1;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int pv = (int)(i / c1), c = (int)(i % c1);
+    const int px = pv % gc.X, py = (pv / gc.X) % gc.Y, pz = pv / (gc.X * gc.Y);
+    float s = 0.0f;
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const int x = 2 * px + dx, y = 2 * py + dy, z = 2 * pz + dz;
+          if (x < gf.X && y < gf.Y && z < gf.Z)
+            s += to_f(g[((long long)x + (long long)gf.X * (y + (long long)gf.Y * z)) * ct + c]);
+        }
+    coarse[i] = from_f<ST>(s);
+  }
+}
+
+// dst[v][c] = a[v][c] + b[v][boff + c] (gradient of a tensor used by a conv and a skip).
+template <typename ST>
+__global__ void add_skip_kernel(ST* dst, const ST* a, const ST* b, int n, int c, int bct, int boff) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (long long)n * c;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long v = i / c;
+    const int ch = (int)(i % c);
+    dst[i] = from_f<ST>(to_f(a[i]) + to_f(b[v * bct + boff + ch]));
+  }
+}
+
+// Relative masked MSE of the 3 output channels against target e (FP32 DOF layout):
+// loss = sum(m (out - e)^2) / sum(m e^2); writes dLoss/dout into g [v][16] (padded).
+template <typename ST>
+__global__ __launch_bounds__(256) void loss_kernel(const ST* out, const float* e, const uint8_t* mask,
+                                                   int n_node, double* partials, double* den_num,
+                                                   unsigned* cnt) {
+  __shared__ double sred[4];
+  double num = 0.0, den = 0.0;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n_node; v += gridDim.x * blockDim.x) {
+    const uint8_t mk = mask[v];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if ((mk >> c) & 1) continue;
+      const double t = e[3 * v + c], d = (double)to_f(out[16 * v + c]) - t;
+      num += d * d;
+      den += t * t;
+    }
+  }
+  const double s0 = block_sum<256>(num, sred);
+  const double s1 = block_sum<256>(den, sred);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = s0;
+    partials[2 * blockIdx.x + 1] = s1;
+  }
+  if (last_block_arrive(cnt, gridDim.x)) {
+    const double N = sum_partials<256>(partials, gridDim.x, 2, sred);
+    const double Dn = sum_partials<256>(partials + 1, gridDim.x, 2, sred);
+    if (threadIdx.x == 0) {
+      den_num[0] = Dn;
+      den_num[1] = N;
+      *cnt = 0u;
+    }
+  }
+}
+
+template <typename ST>
+__global__ void loss_grad_kernel(const ST* out, const float* e, const uint8_t* mask, int n_node,
+                                 const double* den_num, ST* g) {
+  const float s = (float)(2.0 / fmax(den_num[0], 1e-300));
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n_node; v += gridDim.x * blockDim.x) {
+    const uint8_t mk = mask[v];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      float gv = 0.0f;
+      if (c < 3 && !((mk >> c) & 1)) gv = s * (to_f(out[16 * v + c]) - e[3 * v + c]);
+      g[16 * v + c] = from_f<ST>(gv);
+    }
+  }
+}
+
+// Network output to a DOF vector: z[3v + c] = scale * out[v][c], zero on fixed DOFs.
+template <typename ST>
+__global__ void output_kernel(const ST* out, const uint8_t* mask, const double* rnorm2, float* z,
+                              int n_node) {
+  const float s = (float)sqrt(*rnorm2);
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n_node; v += gridDim.x * blockDim.x) {
+    const uint8_t mk = mask[v];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[3 * v + c] = ((mk >> c) & 1) ? 0.0f : s * to_f(out[16 * v + c]);
+  }
+}
+
+// Adam on the FP32 master weights, then the compute copies: W [co][t][ci_pad] and the
+// transposed WT [ci_pad][t][co] used by the data gradient (padding channels stay 0).
+struct AdamArgs {
+  float lr, b1, b2, eps, c1, c2;  // c1 = 1 - b1^t, c2 = 1 - b2^t
+};
+
+__global__ void adam_kernel(float* w, float* m, float* v, const float* g, int n, AdamArgs a) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
+    const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+  }
+}
+
+// master layout [co][ci][taps] (as the oracle's W[o, i, a, b, c] flattened; taps ordered
+// z, y, x) -> W [co_pad][taps][ci_pad] and WT [ci_pad][taps][co_pad].
+template <typename ST>
+__global__ void pack_weights_kernel(const float* master, int co, int ci, int taps, int cop, int cip,
+                                    ST* W, ST* WT) {
+  const int n = cop * taps * cip;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int c_i = i % cip, t = (i / cip) % taps, c_o = i / (cip * taps);
+    const float val = (c_o < co && c_i < ci) ? master[((long long)c_o * ci + c_i) * taps + t] : 0.0f;
+    W[i] = from_f<ST>(val);
+    WT[((long long)c_i * taps + t) * cop + c_o] = from_f<ST>(val);
+  }
+}
+
+// gradient [co][taps][ci_pad] -> master layout [co][ci][taps]
+__global__ void unpack_grad_kernel(const float* g, int co, int ci, int taps, int cip, float* out) {
+  const int n = co * ci * taps;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int t = i % taps, c_i = (i / taps) % ci, c_o = i / (taps * ci);
+    out[i] = g[((long long)c_o * taps + t) * cip + c_i];
+  }
+}
+
+// Small helpers of the training and test entry points.
+__global__ void accum_kernel(float* acc, const float* g, int n, int add) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    acc[i] = add ? acc[i] + g[i] : g[i];
+}
+
+__global__ void scale_kernel(float* g, int n, float s) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) g[i] *= s;
+}
+__global__ void take3_bf16(const bf16_t* o, float* out, int n) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    for (int c = 0; c < 3; ++c) out[3 * v + c] = to_f(o[16 * v + c]);
+}
+__global__ void take3_f32(const float* o, float* out, int n) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    for (int c = 0; c < 3; ++c) out[3 * v + c] = o[16 * v + c];
+}
+
+
+// ------------------------------------------------------------------- flexible CG
+// FCG(1): z_k = M(r_k), beta_k = -<z_k, q_{k-1}> / <p_{k-1}, q_{k-1}>, p_k = z_k + beta_k
+// p_{k-1}, alpha_k = <r_k, z_k> / <p_k, q_k>.  A network output that is not a descent
+// direction (<r, z> <= 0 or non-finite) is replaced by the Jacobi step z = D^-1 r.
+// State: st->rz = <r, z>, st->pq = <p, q> (from the operator's fused dot), st->aux = 1
+// while the current z must be replaced, st->nfallback counts the replacements.
+__global__ __launch_bounds__(256) void fcg_check_kernel(const float* __restrict__ r,
+                                                        const float* __restrict__ z,
+                                                        const float* __restrict__ q, int n,
+                                                        SolverState* st, double* partials) {
+  __shared__ double sred[4];
+  if (st->done) return;
+  const bool first = st->iter == 0;
+  double rz = 0.0, zq = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const double zi = z[i];
+    rz += (double)r[i] * zi;
+    if (!first) zq += zi * (double)q[i];
+  }
+  const double s0 = block_sum<256>(rz, sred);
+  const double s1 = block_sum<256>(zq, sred);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = s0;
+    partials[2 * blockIdx.x + 1] = s1;
+  }
+  if (last_block_arrive(&st->cnt[2], gridDim.x)) {
+    const double RZ = sum_partials<256>(partials, gridDim.x, 2, sred);
+    const double ZQ = sum_partials<256>(partials + 1, gridDim.x, 2, sred);
+    if (threadIdx.x == 0) {
+      const double beta = first ? 0.0 : -ZQ / st->pq;
+      if (finite_val(RZ) && finite_val(beta) && RZ > 0.0) {
+        st->aux = 0.0;
+        st->rz = RZ;
+        st->beta = beta;
+      } else {
+        st->aux = 1.0;
+      }
+      st->cnt[2] = 0u;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void fcg_fallback_kernel(const float* __restrict__ r,
+                                                           float* __restrict__ z,
+                                                           const float* __restrict__ q,
+                                                           const float* __restrict__ dinv, int n,
+                                                           SolverState* st, double* partials) {
+  __shared__ double sred[4];
+  if (st->done || st->aux == 0.0) return;
+  const bool first = st->iter == 0;
+  double rz = 0.0, zq = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const float zi = r[i] * dinv[(unsigned)i / 3u];
+    z[i] = zi;
+    rz += (double)r[i] * (double)zi;
+    if (!first) zq += (double)zi * (double)q[i];
+  }
+  const double s0 = block_sum<256>(rz, sred);
+  const double s1 = block_sum<256>(zq, sred);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = s0;
+    partials[2 * blockIdx.x + 1] = s1;
+  }
+  if (last_block_arrive(&st->cnt[2], gridDim.x)) {
+    const double RZ = sum_partials<256>(partials, gridDim.x, 2, sred);
+    const double ZQ = sum_partials<256>(partials + 1, gridDim.x, 2, sred);
+    if (threadIdx.x == 0) {
+      const double beta = first ? 0.0 : -ZQ / st->pq;
+      st->rz = RZ;
+      st->beta = beta;
+      st->aux = 0.0;
+      st->nfallback += 1;
+      if (!finite_val(RZ) || !finite_val(beta) || !(RZ > 0.0)) st->done = 3;
+      st->cnt[2] = 0u;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void fcg_direction_kernel(const float* __restrict__ z,
+                                                            float* __restrict__ p, int n,
+                                                            const SolverState* st) {
+  if (st->done) return;
+  const bool first = st->iter == 0;
+  const float beta = (float)st->beta;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    p[i] = first ? z[i] : z[i] + beta * p[i];
+}
+
+}  // namespace tosimp
+
+// =========================================================================== host side
+using namespace tosimp;
+
+namespace {
+
+struct Layer {
+  const char* name;
+  int ci, co, k, s;      // logical channels, kernel size, stride
+  int cip, cop;          // padded channels (ci to 8, co to 16)
+  int level_in, level_out;
+  size_t moff, goff;     // offsets into the master / gradient arrays (floats)
+  size_t woff;           // offset into the packed compute weights (elements)
+};
+
+struct NNState {
+  int base = 16;
+  int bf16 = 1;          // storage type of weights and activations
+  size_t es = 2;         // element size
+  std::vector<Layer> L;
+  size_t nparam = 0, npacked = 0;
+  Grid3 g[3];
+  float* master = nullptr;     // FP32 weights [co][ci][taps] per layer
+  float* m = nullptr;
+  float* v = nullptr;
+  float* grad = nullptr;       // gradient in master layout
+  float* gpack = nullptr;      // gradient per layer in [co][taps][ci_pad]
+  void* W = nullptr;           // packed compute weights
+  void* WT = nullptr;
+  void* act[13] = {};          // per layer output (a), plus input at index 12
+  void* cat1 = nullptr;        // [up(m2b) | s1] at level 1
+  void* cat0 = nullptr;        // [up(u1b) | s0] at level 0
+  void* gbuf[6] = {};          // gradient scratch (largest level-0 sizes)
+  float* gsum = nullptr;       // summed gradient of a training batch (master layout)
+  float* wpart = nullptr;      // weight-gradient partials
+  size_t wpart_cap = 0;
+  float* rho_node = nullptr;
+  double* scal = nullptr;      // device scalars: [0] ||r||^2, [1..2] den/num, ...
+  double* part = nullptr;
+  unsigned* cnt = nullptr;
+  int adam_t = 0;
+};
+
+NNState* nn_of(tosimp_ctx* c) { return (NNState*)c->nn; }
+
+int ceil16(int c) { return (c + 15) / 16 * 16; }
+int ceil8(int c) { return (c + 7) / 8 * 8; }
+
+// Voxels per weight-gradient chunk: a multiple of 256 keeping the chunk count <= 512.
+int wgrad_chunk(int nvox) {
+  const int per = (nvox + 511) / 512;
+  return std::max(256, (per + 255) / 256 * 256);
+}
+
+template <typename ST>
+hipError_t conv_fwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* in, void* out, int act) {
+  ConvArgs a{};
+  a.in = in;
+  a.w = (const char*)S->W + l.woff * S->es;
+  a.out = out;
+  a.gin = S->g[l.level_in];
+  a.gout = S->g[l.level_out];
+  a.cin = l.cip;
+  a.cout = l.cop;
+  a.ksize = l.k;
+  a.stride = l.s;
+  a.apply_act = act;
+  const int waves = (a.gout.n() + 15) / 16;
+  conv_igemm_kernel<ST, false><<<dim3((waves + 3) / 4, (a.cout + 63) / 64), 256, 0, c->stream>>>(a);
+  return hipGetLastError();
+}
+
+// dX (wrt this layer's input) from dY (wrt its activated output) and a (its output).
+template <typename ST>
+hipError_t conv_bwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* dY, const void* a_out,
+                    const void* x_in, void* dX, bool need_dx) {
+  ConvArgs a{};
+  a.gin = S->g[l.level_in];
+  a.gout = S->g[l.level_out];
+  a.cin = l.cip;
+  a.cout = l.cop;
+  a.ksize = l.k;
+  a.stride = l.s;
+  const int taps = l.k * l.k * l.k;
+  // weight gradient
+  {
+    ConvArgs b = a;
+    b.in = x_in;
+    b.out = const_cast<void*>(dY);
+    b.act = a_out;
+    const int cvox = wgrad_chunk(a.gout.n());
+    const int nchunk = (a.gout.n() + cvox - 1) / cvox;
+    const size_t need = (size_t)nchunk * l.cop * taps * l.cip;
+    if (need > S->wpart_cap) return hipErrorInvalidValue;
+    conv_wgrad_kernel<ST><<<dim3(nchunk, taps), 256, 0, c->stream>>>(b, S->wpart, cvox);
+    const int n = l.cop * taps * l.cip;
+    conv_wgrad_reduce<<<(n + 255) / 256, 256, 0, c->stream>>>(S->wpart, nchunk, n,
+                                                              S->gpack + l.goff, 0);
+  }
+  if (need_dx) {
+    a.in = dY;
+    a.act = a_out;
+    a.w = (const char*)S->WT + l.woff * S->es;
+    a.out = dX;
+    const int waves = (a.gin.n() + 15) / 16;
+    conv_igemm_kernel<ST, true><<<dim3((waves + 3) / 4, (a.cin + 63) / 64), 256, 0, c->stream>>>(a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+void tosimp::nn_release(tosimp_ctx* ctx) {
+  NNState* S = ctx ? nn_of(ctx) : nullptr;
+  if (!S) return;
+  void* ptrs[] = {S->master, S->m,        S->v,    S->grad, S->gpack, S->W,   S->WT, S->cat1,
+                  S->cat0,   S->wpart,    S->rho_node, S->scal, S->part, S->cnt, S->gsum};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (void* p : S->act)
+    if (p) (void)hipFree(p);
+  for (void* p : S->gbuf)
+    if (p) (void)hipFree(p);
+  delete S;
+  ctx->nn = nullptr;
+}
+
+
+namespace {
+
+hipError_t nn_alloc(void** p, size_t bytes) { return hipMalloc(p, bytes < 256 ? 256 : bytes); }
+
+// Forward pass from the padded input tensor in act[12]; layer outputs in act[0..11].
+template <typename ST>
+hipError_t nn_forward(tosimp_ctx* c, NNState* S) {
+  hipError_t e = hipSuccess;
+  auto F = [&](int li, const void* in, int act) {
+    if (e == hipSuccess) e = conv_fwd<ST>(c, S, S->L[li], in, S->act[li], act);
+  };
+  const int b = S->base;
+  F(0, S->act[12], 1);                 // e0a
+  F(1, S->act[0], 1);                  // e0b -> s0
+  F(2, S->act[1], 1);                  // d1
+  F(3, S->act[2], 1);                  // e1 -> s1
+  F(4, S->act[3], 1);                  // d2
+  F(5, S->act[4], 1);                  // m2a
+  F(6, S->act[5], 1);                  // m2b
+  if (e != hipSuccess) return e;
+  upcat_kernel<ST><<<2048, 256, 0, c->stream>>>((const ST*)S->act[6], S->g[2], 4 * b,
+                                               (const ST*)S->act[3], 2 * b, (ST*)S->cat1, S->g[1]);
+  F(7, S->cat1, 1);                    // u1a
+  F(8, S->act[7], 1);                  // u1b
+  if (e != hipSuccess) return e;
+  upcat_kernel<ST><<<2048, 256, 0, c->stream>>>((const ST*)S->act[8], S->g[1], 2 * b,
+                                               (const ST*)S->act[1], b, (ST*)S->cat0, S->g[0]);
+  F(9, S->cat0, 1);                    // u0a
+  F(10, S->act[9], 1);                 // u0b
+  F(11, S->act[10], 0);                // head (no activation)
+  return e == hipSuccess ? hipGetLastError() : e;
+}
+
+// Backward pass from dLoss/d(head output) in gbuf[0] ([v0][16]); per-layer weight
+// gradients land in gpack.  Buffer use (G = gbuf):
+//   head: G0 -> G1; u0b: G1 -> G2; u0a: G2 -> G3 (= [up | s0] grad, kept);
+//   up-adjoint G3 -> G4 (level 1); u1b: G4 -> G1; u1a: G1 -> G5 (= [up | s1], kept);
+//   up-adjoint G5 -> G4 (level 2); m2b: G4 -> G1; m2a: G1 -> G2; d2: G2 -> G1;
+//   G4 = G1 + skip(G5); e1: G4 -> G2; d1: G2 -> G1; G4 = G1 + skip(G3); e0b: G4 -> G2;
+//   e0a: weight gradient only.
+template <typename ST>
+hipError_t nn_backward(tosimp_ctx* c, NNState* S) {
+  void** G = S->gbuf;
+  const int b = S->base;
+  hipError_t e = hipSuccess;
+  auto B = [&](int li, const void* dY, const void* aout, const void* xin, void* dX, bool ndx) {
+    if (e == hipSuccess) e = conv_bwd<ST>(c, S, S->L[li], dY, aout, xin, dX, ndx);
+  };
+  B(11, G[0], nullptr, S->act[10], G[1], true);   // head (linear)
+  B(10, G[1], S->act[10], S->act[9], G[2], true); // u0b
+  B(9, G[2], S->act[9], S->cat0, G[3], true);     // u0a -> [2b up | b skip]
+  if (e != hipSuccess) return e;
+  upcat_adjoint_kernel<ST><<<2048, 256, 0, c->stream>>>((const ST*)G[3], S->g[0], 3 * b,
+                                                       (ST*)G[4], S->g[1], 2 * b);
+  B(8, G[4], S->act[8], S->act[7], G[1], true);   // u1b
+  B(7, G[1], S->act[7], S->cat1, G[5], true);     // u1a -> [4b up | 2b skip]
+  if (e != hipSuccess) return e;
+  upcat_adjoint_kernel<ST><<<2048, 256, 0, c->stream>>>((const ST*)G[5], S->g[1], 6 * b,
+                                                       (ST*)G[4], S->g[2], 4 * b);
+  B(6, G[4], S->act[6], S->act[5], G[1], true);   // m2b
+  B(5, G[1], S->act[5], S->act[4], G[2], true);   // m2a
+  B(4, G[2], S->act[4], S->act[3], G[1], true);   // d2 -> grad wrt s1 (conv path)
+  if (e != hipSuccess) return e;
+  add_skip_kernel<ST><<<2048, 256, 0, c->stream>>>((ST*)G[4], (const ST*)G[1], (const ST*)G[5],
+                                                  S->g[1].n(), 2 * b, 6 * b, 4 * b);
+  B(3, G[4], S->act[3], S->act[2], G[2], true);   // e1
+  B(2, G[2], S->act[2], S->act[1], G[1], true);   // d1 -> grad wrt s0 (conv path)
+  if (e != hipSuccess) return e;
+  add_skip_kernel<ST><<<2048, 256, 0, c->stream>>>((ST*)G[4], (const ST*)G[1], (const ST*)G[3],
+                                                  S->g[0].n(), b, 3 * b, 2 * b);
+  B(1, G[4], S->act[1], S->act[0], G[2], true);   // e0b
+  B(0, G[2], S->act[0], S->act[12], nullptr, false);  // e0a
+  if (e != hipSuccess) return e;
+  for (const Layer& l : S->L) {
+    const int taps = l.k * l.k * l.k;
+    const int n = l.co * l.ci * taps;
+    unpack_grad_kernel<<<(n + 255) / 256, 256, 0, c->stream>>>(S->gpack + l.goff, l.co, l.ci, taps,
+                                                               l.cip, S->grad + l.moff);
+  }
+  return hipGetLastError();
+}
+
+template <typename ST>
+hipError_t nn_pack(tosimp_ctx* c, NNState* S) {
+  for (const Layer& l : S->L) {
+    const int taps = l.k * l.k * l.k;
+    const int n = l.cop * taps * l.cip;
+    pack_weights_kernel<ST><<<(n + 255) / 256, 256, 0, c->stream>>>(
+        S->master + l.moff, l.co, l.ci, taps, l.cop, l.cip, (ST*)S->W + l.woff,
+        (ST*)S->WT + l.woff);
+  }
+  return hipGetLastError();
+}
+
+// ||r||^2 of an FP32 vector into *out (FP64, deterministic).
+__global__ __launch_bounds__(256) void norm2f_kernel(const float* r, int n, double* partials,
+                                                     double* out, unsigned* cnt) {
+  __shared__ double sred[4];
+  double s = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    s += (double)r[i] * (double)r[i];
+  const double bs = block_sum<256>(s, sred);
+  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+  if (last_block_arrive(cnt, gridDim.x)) {
+    const double tot = sum_partials<256>(partials, gridDim.x, 1, sred);
+    if (threadIdx.x == 0) {
+      *out = tot;
+      *cnt = 0u;
+    }
+  }
+}
+
+__global__ void scale_target_kernel(const float* e, const double* rnorm2, float* out, int n) {
+  const float inv = (float)(1.0 / sqrt(fmax(*rnorm2, 1e-300)));
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    out[i] = e[i] * inv;
+}
+
+__global__ void sub_targets_kernel(const double* ustar, float* hu, int n_dof, int count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (long long)n_dof * count;
+       i += (long long)gridDim.x * blockDim.x)
+    hu[i] = (float)(ustar[i % n_dof] - (double)hu[i]);
+}
+
+template <typename ST>
+int nn_apply_t(tosimp_ctx* ctx, NNState* S, const float* r, float* z) {
+  const int nn = (int)ctx->n_node;
+  norm2f_kernel<<<1024, 256, 0, ctx->stream>>>(r, (int)ctx->n_dof, S->part, S->scal, S->cnt);
+  build_input_kernel<ST><<<2048, 256, 0, ctx->stream>>>(r, S->scal, S->rho_node, (ST*)S->act[12], nn);
+  TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S));
+  output_kernel<ST><<<2048, 256, 0, ctx->stream>>>((const ST*)S->act[11], ctx->ws.mask, S->scal, z, nn);
+  TOSIMP_HIP(ctx, hipGetLastError());
+  return TOSIMP_OK;
+}
+
+// One sample: forward on (r, rho), loss against e / ||r||, backward; grad += sample grad.
+template <typename ST>
+int nn_sample_grad(tosimp_ctx* ctx, NNState* S, const float* r, const float* e, float* tgt,
+                   float* gacc, bool first, double* loss) {
+  const int nn = (int)ctx->n_node;
+  norm2f_kernel<<<1024, 256, 0, ctx->stream>>>(r, (int)ctx->n_dof, S->part, S->scal, S->cnt);
+  build_input_kernel<ST><<<2048, 256, 0, ctx->stream>>>(r, S->scal, S->rho_node, (ST*)S->act[12], nn);
+  scale_target_kernel<<<2048, 256, 0, ctx->stream>>>(e, S->scal, tgt, (int)ctx->n_dof);
+  TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S));
+  loss_kernel<ST><<<1024, 256, 0, ctx->stream>>>((const ST*)S->act[11], tgt, ctx->ws.mask, nn,
+                                                 S->part, S->scal + 1, S->cnt + 1);
+  loss_grad_kernel<ST><<<2048, 256, 0, ctx->stream>>>((const ST*)S->act[11], tgt, ctx->ws.mask, nn,
+                                                      S->scal + 1, (ST*)S->gbuf[0]);
+  TOSIMP_HIP(ctx, nn_backward<ST>(ctx, S));
+  accum_kernel<<<(int)((S->nparam + 255) / 256), 256, 0, ctx->stream>>>(gacc, S->grad, (int)S->nparam,
+                                                                       first ? 0 : 1);
+  double dn[2];
+  TOSIMP_HIP(ctx, hipMemcpyAsync(dn, S->scal + 1, sizeof(dn), hipMemcpyDeviceToHost, ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *loss = dn[0] > 0 ? dn[1] / dn[0] : 0.0;
+  return TOSIMP_OK;
+}
+
+}  // namespace
+
+
+// Flexible CG with the network as preconditioner (see the FCG kernels above).  Vectors:
+// r, p, q in the FP32 workspace, z in the FP64 scratch w (as floats); the iterate is e32.
+int tosimp::nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const float* b32,
+                         float* e32, double tol, int maxit, int check_every, int* iters,
+                         int* fallbacks, int* done) {
+  NNState* S = nn_of(ctx);
+  if (!S) return tosimp_fail(ctx, TOSIMP_ESTATE, "NN preconditioner requested but no network");
+  Workspace& w = ctx->ws;
+  float *r = w.r32, *p = w.p32, *q = w.q32, *z = (float*)w.w;
+  const int n = (int)ctx->n_dof;
+  SolverState* st = w.st + 1;
+  SolverState* sh = w.st_host + 1;
+  *sh = SolverState{};
+  sh->aux = tol * tol;
+  sh->maxit = maxit < 1 ? 1 : maxit;
+  TOSIMP_HIP(ctx, hipMemcpyAsync(st, sh, sizeof(SolverState), hipMemcpyHostToDevice, ctx->stream));
+  node_density_kernel<<<2048, 256, 0, ctx->stream>>>(x32, ctx->nx, ctx->ny, ctx->nz, S->rho_node);
+  TOSIMP_HIP(ctx, launch_fill_zero(ctx, e32, (int64_t)n * 4));
+  double* part = w.partials;
+  double* kvpart = w.partials + 2 * kMaxPartials;
+  TOSIMP_HIP(ctx, launch_pcg_init<float>(ctx, b32, nullptr, r, p, w.dinv32, st, part, 0));
+  const bool mfma = prec == TOSIMP_PREC_BF16_MFMA || prec == TOSIMP_PREC_FP16_MFMA;
+  const int vb = std::min(2048, (n + 255) / 256);
+  if (check_every < 1) check_every = 1;
+  for (;;) {
+    TOSIMP_HIP(ctx, hipMemcpyAsync(sh, st, sizeof(SolverState), hipMemcpyDeviceToHost, ctx->stream));
+    TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (sh->done) break;
+    for (int i = 0; i < check_every; ++i) {
+      int rc = S->bf16 ? nn_apply_t<bf16_t>(ctx, S, r, z) : nn_apply_t<float>(ctx, S, r, z);
+      if (rc) return rc;
+      fcg_check_kernel<<<vb, 256, 0, ctx->stream>>>(r, z, q, n, st, part);
+      fcg_fallback_kernel<<<vb, 256, 0, ctx->stream>>>(r, z, q, w.dinv32, n, st, part);
+      fcg_direction_kernel<<<vb, 256, 0, ctx->stream>>>(z, p, n, st);
+      TOSIMP_HIP(ctx, hipGetLastError());
+      if (mfma) {
+        TOSIMP_HIP(ctx, kv_mfma_launch(ctx, prec, TOSIMP_F32, x32, p, q, st, true));
+        TOSIMP_HIP(ctx, launch_alpha_from_dot32(ctx, p, q, kvpart, st));
+      } else {
+        TOSIMP_HIP(ctx, kv_launch(ctx, TOSIMP_PREC_FP32, TOSIMP_F32, x32, p, q, kvpart, st,
+                                  nullptr, 1, true));
+      }
+      TOSIMP_HIP(ctx, launch_pcg_update<float>(ctx, e32, r, p, q, w.dinv32, st, part));
+    }
+  }
+  *iters = sh->iter;
+  *fallbacks = sh->nfallback;
+  *done = sh->done;
+  return TOSIMP_OK;
+}
+
+#define NN_REQUIRE(cond, code, msg)                       \
+  do {                                                    \
+    if (!(cond)) return tosimp_fail(ctx, code, msg);      \
+  } while (0)
+
+extern "C" {
+
+int tosimp_nn_create(tosimp_ctx* ctx, int base, int bf16) {
+  if (!ctx) return TOSIMP_EINVAL;
+  NN_REQUIRE(ctx->has_mesh, TOSIMP_ESTATE, "no mesh");
+  NN_REQUIRE(base == 16 || base == 32, TOSIMP_EINVAL, "base channels must be 16 or 32");
+  nn_release(ctx);
+  NNState* S = new NNState();
+  ctx->nn = S;
+  S->base = base;
+  S->bf16 = bf16 ? 1 : 0;
+  S->es = bf16 ? 2 : 4;
+  const int b = base;
+  S->g[0] = {ctx->nx + 1, ctx->ny + 1, ctx->nz + 1};
+  for (int lv = 1; lv < 3; ++lv)
+    S->g[lv] = {(S->g[lv - 1].X - 1) / 2 + 1, (S->g[lv - 1].Y - 1) / 2 + 1, (S->g[lv - 1].Z - 1) / 2 + 1};
+  struct D { const char* n; int ci, co, k, s, li, lo; };
+  const D defs[12] = {{"e0a", 4, b, 3, 1, 0, 0},         {"e0b", b, b, 3, 1, 0, 0},
+                      {"d1", b, 2 * b, 3, 2, 0, 1},      {"e1", 2 * b, 2 * b, 3, 1, 1, 1},
+                      {"d2", 2 * b, 4 * b, 3, 2, 1, 2},  {"m2a", 4 * b, 4 * b, 3, 1, 2, 2},
+                      {"m2b", 4 * b, 4 * b, 3, 1, 2, 2}, {"u1a", 6 * b, 2 * b, 3, 1, 1, 1},
+                      {"u1b", 2 * b, 2 * b, 3, 1, 1, 1}, {"u0a", 3 * b, b, 3, 1, 0, 0},
+                      {"u0b", b, b, 3, 1, 0, 0},         {"head", b, 3, 1, 1, 0, 0}};
+  size_t mo = 0, wo = 0;
+  size_t wpart = 0;
+  for (const D& d : defs) {
+    Layer l;
+    l.name = d.n;
+    l.ci = d.ci;
+    l.co = d.co;
+    l.k = d.k;
+    l.s = d.s;
+    l.cip = ceil8(d.ci);   // the 4 input channels are padded to 8, the rest are 16k
+    l.cop = ceil16(d.co);  // the 3 head outputs are padded to 16
+    l.level_in = d.li;
+    l.level_out = d.lo;
+    const int taps = d.k * d.k * d.k;
+    l.moff = mo;
+    l.goff = wo;
+    l.woff = wo;
+    mo += (size_t)d.co * d.ci * taps;
+    wo += (size_t)l.cop * taps * l.cip;
+    const int nvox = S->g[d.lo].n();
+    const size_t nchunk = (nvox + wgrad_chunk(nvox) - 1) / wgrad_chunk(nvox);
+    wpart = std::max(wpart, nchunk * l.cop * taps * l.cip);
+    S->L.push_back(l);
+  }
+  S->nparam = mo;
+  S->npacked = wo;
+  S->wpart_cap = wpart;
+  const size_t n0 = S->g[0].n(), n1 = S->g[1].n();
+  hipError_t e = hipSuccess;
+  auto A = [&](void** p, size_t bytes) { if (e == hipSuccess) e = nn_alloc(p, bytes); };
+  A((void**)&S->master, mo * 4);
+  A((void**)&S->m, mo * 4);
+  A((void**)&S->v, mo * 4);
+  A((void**)&S->grad, mo * 4);
+  A((void**)&S->gsum, mo * 4);
+  A((void**)&S->gpack, wo * 4);
+  A(&S->W, wo * S->es);
+  A(&S->WT, wo * S->es);
+  for (int i = 0; i < 12; ++i) {
+    const Layer& l = S->L[i];
+    A(&S->act[i], (size_t)S->g[l.level_out].n() * l.cop * S->es);
+  }
+  A(&S->act[12], n0 * 8 * S->es);
+  A(&S->cat1, n1 * 6 * b * S->es);
+  A(&S->cat0, n0 * 3 * b * S->es);
+  const size_t gsz = std::max(n0 * 3 * b, n1 * 6 * b) * S->es;
+  for (int i = 0; i < 6; ++i) A(&S->gbuf[i], gsz);
+  A((void**)&S->wpart, wpart * 4);
+  A((void**)&S->rho_node, n0 * 4);
+  A((void**)&S->scal, 64 * 8);
+  A((void**)&S->part, 4096 * 8);
+  A((void**)&S->cnt, 64);
+  if (e != hipSuccess) {
+    nn_release(ctx);
+    return tosimp_fail(ctx, TOSIMP_ENOMEM, "network workspace");
+  }
+  TOSIMP_HIP(ctx, hipMemsetAsync(S->m, 0, mo * 4, ctx->stream));
+  TOSIMP_HIP(ctx, hipMemsetAsync(S->v, 0, mo * 4, ctx->stream));
+  TOSIMP_HIP(ctx, hipMemsetAsync(S->master, 0, mo * 4, ctx->stream));
+  TOSIMP_HIP(ctx, hipMemsetAsync(S->cnt, 0, 64, ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TOSIMP_OK;
+}
+
+int tosimp_nn_num_params(const tosimp_ctx* ctx, int64_t* n) {
+  if (!ctx || !ctx->nn || !n) return TOSIMP_EINVAL;
+  *n = (int64_t)((const NNState*)ctx->nn)->nparam;
+  return TOSIMP_OK;
+}
+
+int tosimp_nn_set_weights(tosimp_ctx* ctx, const float* w_host, int64_t n) {
+  if (!ctx) return TOSIMP_EINVAL;
+  NNState* S = nn_of(ctx);
+  NN_REQUIRE(S, TOSIMP_ESTATE, "no network");
+  NN_REQUIRE(w_host && n == (int64_t)S->nparam, TOSIMP_EINVAL, "weight count mismatch");
+  TOSIMP_HIP(ctx, hipMemcpyAsync(S->master, w_host, n * 4, hipMemcpyHostToDevice, ctx->stream));
+  TOSIMP_HIP(ctx, hipMemsetAsync(S->m, 0, n * 4, ctx->stream));
+  TOSIMP_HIP(ctx, hipMemsetAsync(S->v, 0, n * 4, ctx->stream));
+  S->adam_t = 0;
+  if (S->bf16) TOSIMP_HIP(ctx, nn_pack<bf16_t>(ctx, S));
+  else TOSIMP_HIP(ctx, nn_pack<float>(ctx, S));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TOSIMP_OK;
+}
+
+int tosimp_nn_get_weights(tosimp_ctx* ctx, float* w_host, int64_t n) {
+  if (!ctx) return TOSIMP_EINVAL;
+  NNState* S = nn_of(ctx);
+  NN_REQUIRE(S, TOSIMP_ESTATE, "no network");
+  NN_REQUIRE(w_host && n == (int64_t)S->nparam, TOSIMP_EINVAL, "weight count mismatch");
+  TOSIMP_HIP(ctx, hipMemcpyAsync(w_host, S->master, n * 4, hipMemcpyDeviceToHost, ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TOSIMP_OK;
+}
+
+// Nodal density from the element density (FP32); cached for the following applies.
+int tosimp_nn_set_density(tosimp_ctx* ctx, const float* x32) {
+  if (!ctx) return TOSIMP_EINVAL;
+  NNState* S = nn_of(ctx);
+  NN_REQUIRE(S && x32, TOSIMP_ESTATE, "no network or density");
+  node_density_kernel<<<2048, 256, 0, ctx->stream>>>(x32, ctx->nx, ctx->ny, ctx->nz, S->rho_node);
+  TOSIMP_HIP(ctx, hipGetLastError());
+  return TOSIMP_OK;
+}
+
+int tosimp_nn_apply(tosimp_ctx* ctx, const float* r, float* z) {
+  if (!ctx) return TOSIMP_EINVAL;
+  NNState* S = nn_of(ctx);
+  NN_REQUIRE(S && r && z && r != (const float*)z, TOSIMP_EINVAL, "bad arguments");
+  return S->bf16 ? nn_apply_t<bf16_t>(ctx, S, r, z) : nn_apply_t<float>(ctx, S, r, z);
+}
+
+// Test hook: raw network on an FP32 channels-last [v0][4] input; out [v0][3] FP32.
+int tosimp_nn_forward(tosimp_ctx* ctx, const float* x4, float* out3) {
+  if (!ctx) return TOSIMP_EINVAL;
+  NNState* S = nn_of(ctx);
+  NN_REQUIRE(S && x4 && out3, TOSIMP_EINVAL, "bad arguments");
+  const int n0 = S->g[0].n();
+  if (S->bf16) {
+    pad_input_kernel<bf16_t><<<2048, 256, 0, ctx->stream>>>(x4, (bf16_t*)S->act[12], n0);
+    TOSIMP_HIP(ctx, nn_forward<bf16_t>(ctx, S));
+    take3_bf16<<<2048, 256, 0, ctx->stream>>>((const bf16_t*)S->act[11], out3, n0);
+  } else {
+    pad_input_kernel<float><<<2048, 256, 0, ctx->stream>>>(x4, (float*)S->act[12], n0);
+    TOSIMP_HIP(ctx, nn_forward<float>(ctx, S));
+    take3_f32<<<2048, 256, 0, ctx->stream>>>((const float*)S->act[11], out3, n0);
+  }
+  TOSIMP_HIP(ctx, hipGetLastError());
+  return TOSIMP_OK;
+}
+
+// Test hook: loss and gradients (master layout, host) for one raw input [v0][4] and
+// target [v0][3] (FP32, device); the mask is the context's BC mask.
+int tosimp_nn_loss_grad(tosimp_ctx* ctx, const float* x4, const float* target3, double* loss_host,
+                        float* grad_host) {
+  if (!ctx) return TOSIMP_EINVAL;
+  NNState* S = nn_of(ctx);
+  NN_REQUIRE(S && x4 && target3, TOSIMP_EINVAL, "bad arguments");
+  const int n0 = S->g[0].n();
+  if (S->bf16) {
+    pad_input_kernel<bf16_t><<<2048, 256, 0, ctx->stream>>>(x4, (bf16_t*)S->act[12], n0);
+    TOSIMP_HIP(ctx, nn_forward<bf16_t>(ctx, S));
+    loss_kernel<bf16_t><<<1024, 256, 0, ctx->stream>>>((const bf16_t*)S->act[11], target3, ctx->ws.mask,
+                                                       n0, S->part, S->scal + 1, S->cnt + 1);
+    loss_grad_kernel<bf16_t><<<2048, 256, 0, ctx->stream>>>((const bf16_t*)S->act[11], target3,
+                                                            ctx->ws.mask, n0, S->scal + 1,
+                                                            (bf16_t*)S->gbuf[0]);
+    TOSIMP_HIP(ctx, nn_backward<bf16_t>(ctx, S));
+  } else {
+    pad_input_kernel<float><<<2048, 256, 0, ctx->stream>>>(x4, (float*)S->act[12], n0);
+    TOSIMP_HIP(ctx, nn_forward<float>(ctx, S));
+    loss_kernel<float><<<1024, 256, 0, ctx->stream>>>((const float*)S->act[11], target3, ctx->ws.mask,
+                                                      n0, S->part, S->scal + 1, S->cnt + 1);
+    loss_grad_kernel<float><<<2048, 256, 0, ctx->stream>>>((const float*)S->act[11], target3,
+                                                           ctx->ws.mask, n0, S->scal + 1,
+                                                           (float*)S->gbuf[0]);
+    TOSIMP_HIP(ctx, nn_backward<float>(ctx, S));
+  }
+  double dn[2];
+  TOSIMP_HIP(ctx, hipMemcpyAsync(dn, S->scal + 1, sizeof(dn), hipMemcpyDeviceToHost, ctx->stream));
+  if (grad_host)
+    TOSIMP_HIP(ctx, hipMemcpyAsync(grad_host, S->grad, S->nparam * 4, hipMemcpyDeviceToHost, ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (loss_host) *loss_host = dn[0] > 0 ? dn[1] / dn[0] : 0.0;
+  return TOSIMP_OK;
+}
+
+// One Adam step on the summed gradient of nb (residual, error) pairs (device FP32, DOF
+// layout, nb x n_dof each), with the nodal density set by tosimp_nn_set_density.
+int tosimp_nn_train_step(tosimp_ctx* ctx, const float* r_batch, const float* e_batch, int nb,
+                         double lr, double* loss_host) {
+  if (!ctx) return TOSIMP_EINVAL;
+  NNState* S = nn_of(ctx);
+  NN_REQUIRE(S && r_batch && e_batch && nb >= 1 && lr > 0, TOSIMP_EINVAL, "bad arguments");
+  float* tgt = (float*)ctx->ws.w;  // scaled target (n_dof floats fit in the FP64 scratch)
+  float* gsum = S->gsum;
+  double tot = 0.0;
+  for (int s = 0; s < nb; ++s) {
+    double l = 0.0;
+    const float* r = r_batch + (size_t)s * ctx->n_dof;
+    const float* e = e_batch + (size_t)s * ctx->n_dof;
+    int rc = S->bf16 ? nn_sample_grad<bf16_t>(ctx, S, r, e, tgt, gsum, s == 0, &l)
+                     : nn_sample_grad<float>(ctx, S, r, e, tgt, gsum, s == 0, &l);
+    if (rc) return rc;
+    tot += l;
+  }
+  S->adam_t += 1;
+  AdamArgs a;
+  a.lr = (float)lr;
+  a.b1 = 0.9f;
+  a.b2 = 0.999f;
+  a.eps = 1e-8f;
+  a.c1 = (float)(1.0 - std::pow(0.9, S->adam_t));
+  a.c2 = (float)(1.0 - std::pow(0.999, S->adam_t));
+  // Adam step on the batch-mean gradient (the mean loss of the batch).
+  scale_kernel<<<(int)((S->nparam + 255) / 256), 256, 0, ctx->stream>>>(gsum, (int)S->nparam,
+                                                                       1.0f / (float)nb);
+  adam_kernel<<<(int)((S->nparam + 255) / 256), 256, 0, ctx->stream>>>(S->master, S->m, S->v, gsum,
+                                                                      (int)S->nparam, a);
+  if (S->bf16) TOSIMP_HIP(ctx, nn_pack<bf16_t>(ctx, S));
+  else TOSIMP_HIP(ctx, nn_pack<float>(ctx, S));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (loss_host) *loss_host = tot / nb;
+  return TOSIMP_OK;
+}
+
+// Harvested targets: hu[k] <- u_star - hu[k] for k < count (u_star FP64, hu FP32).
+int tosimp_nn_make_targets(tosimp_ctx* ctx, const double* u_star, float* harvest_u, int count) {
+  if (!ctx || !ctx->has_mesh) return TOSIMP_EINVAL;
+  NN_REQUIRE(u_star && harvest_u && count >= 0, TOSIMP_EINVAL, "bad arguments");
+  if (count == 0) return TOSIMP_OK;
+  sub_targets_kernel<<<4096, 256, 0, ctx->stream>>>(u_star, harvest_u, (int)ctx->n_dof, count);
+  TOSIMP_HIP(ctx, hipGetLastError());
+  return TOSIMP_OK;
+}
+
+}  // extern "C"
+

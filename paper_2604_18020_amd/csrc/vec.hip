@@ -16,6 +16,13 @@
 
 namespace tosimp {
 
+// Streaming solver kernels use a fixed grid per mesh (about four 16-byte vectors per
+// thread, capped so the partial sums fit), hence a fixed reduction order.
+static int vec_blocks(const tosimp_ctx* c) {
+  const int64_t want = (c->n_dof + 8 * kRedThreads - 1) / (8 * kRedThreads);
+  return (int)(want < 1 ? 1 : (want > kMaxPartials / 2 ? kMaxPartials / 2 : want));
+}
+
 // r = b - K u (masked), z = r * dinv, p = z; accumulates ||r||^2, <r,z>, ||b||^2.
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void pcg_init_kernel(
@@ -63,25 +70,72 @@ __global__ __launch_bounds__(kRedThreads) void pcg_init_kernel(
   }
 }
 
+// Vector width of the streaming kernels: 16 bytes per lane per array.
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+  typedef double2 type;
+  static constexpr int W = 2;
+};
+template <>
+struct Vec<float> {
+  typedef float4 type;
+  static constexpr int W = 4;
+};
+
+template <typename T>
+__device__ __forceinline__ T vget(const typename Vec<T>::type& v, int k) {
+  return reinterpret_cast<const T*>(&v)[k];
+}
+template <typename T>
+__device__ __forceinline__ void vset(typename Vec<T>::type& v, int k, T x) {
+  reinterpret_cast<T*>(&v)[k] = x;
+}
+
 // u += alpha p, r -= alpha q; accumulates ||r||^2 and <r, r dinv>; the last block
-// counts the iteration, tests convergence and forms beta.
+// counts the iteration, tests convergence and forms beta.  Flat over DOFs, 16 bytes per
+// lane per array (the node of DOF i is i / 3; n_dof < 2^31, so 32-bit arithmetic).
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void pcg_update_kernel(
     T* __restrict__ u, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
-    const T* __restrict__ dinv, int64_t n_dof, SolverState* st, double* partials) {
+    const T* __restrict__ dinv, int n_dof, SolverState* st, double* partials) {
+  typedef typename Vec<T>::type VT;
+  constexpr int W = Vec<T>::W;
   __shared__ double sred[kRedThreads / 64];
   if (st->done) return;
   const T alpha = (T)st->alpha;
   double rr = 0.0, rz = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n_dof;
-       i += (int64_t)gridDim.x * kRedThreads) {
-    const int64_t n = i / 3;
-    const T pv = p[i];
-    u[i] += alpha * pv;
-    const T rv = r[i] - alpha * q[i];
-    r[i] = rv;
-    rr += (double)rv * (double)rv;
-    rz += (double)rv * (double)(rv * dinv[n]);
+  const int nvec = n_dof / W;
+  for (int v = blockIdx.x * kRedThreads + threadIdx.x; v < nvec; v += gridDim.x * kRedThreads) {
+    VT uv = reinterpret_cast<const VT*>(u)[v];
+    const VT pv = reinterpret_cast<const VT*>(p)[v];
+    VT rv = reinterpret_cast<const VT*>(r)[v];
+    const VT qv = reinterpret_cast<const VT*>(q)[v];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const unsigned i = (unsigned)(v * W + k);
+      const T d = dinv[i / 3u];
+      const T uu = vget<T>(uv, k) + alpha * vget<T>(pv, k);
+      const T rn = vget<T>(rv, k) - alpha * vget<T>(qv, k);
+      vset<T>(uv, k, uu);
+      vset<T>(rv, k, rn);
+      rr += (double)rn * (double)rn;
+      rz += (double)rn * (double)(rn * d);
+    }
+    reinterpret_cast<VT*>(u)[v] = uv;
+    reinterpret_cast<VT*>(r)[v] = rv;
+  }
+  // tail (n_dof not a multiple of W), handled by block 0
+  if (blockIdx.x == 0) {
+    for (int i = nvec * W + threadIdx.x; i < n_dof; i += kRedThreads) {
+      const T d = dinv[(unsigned)i / 3u];
+      u[i] += alpha * p[i];
+      const T rn = r[i] - alpha * q[i];
+      r[i] = rn;
+      rr += (double)rn * (double)rn;
+      rz += (double)rn * (double)(rn * d);
+    }
   }
   const double s0 = block_sum<kRedThreads>(rr, sred);
   const double s1 = block_sum<kRedThreads>(rz, sred);
@@ -106,18 +160,29 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update_kernel(
   }
 }
 
-// p = r dinv + beta p.
+// p = r dinv + beta p, flat over DOFs, 16 bytes per lane.
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void pcg_direction_kernel(
-    const T* __restrict__ r, T* __restrict__ p, const T* __restrict__ dinv, int64_t n_dof,
+    const T* __restrict__ r, T* __restrict__ p, const T* __restrict__ dinv, int n_dof,
     const SolverState* st) {
+  typedef typename Vec<T>::type VT;
+  constexpr int W = Vec<T>::W;
   if (st->done) return;
   const T beta = (T)st->beta;
-  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n_dof;
-       i += (int64_t)gridDim.x * kRedThreads) {
-    const int64_t n = i / 3;
-    p[i] = r[i] * dinv[n] + beta * p[i];
+  const int nvec = n_dof / W;
+  for (int v = blockIdx.x * kRedThreads + threadIdx.x; v < nvec; v += gridDim.x * kRedThreads) {
+    const VT rv = reinterpret_cast<const VT*>(r)[v];
+    VT pv = reinterpret_cast<const VT*>(p)[v];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const unsigned i = (unsigned)(v * W + k);
+      vset<T>(pv, k, vget<T>(rv, k) * dinv[i / 3u] + beta * vget<T>(pv, k));
+    }
+    reinterpret_cast<VT*>(p)[v] = pv;
   }
+  if (blockIdx.x == 0)
+    for (int i = nvec * W + threadIdx.x; i < n_dof; i += kRedThreads)
+      p[i] = r[i] * dinv[(unsigned)i / 3u] + beta * p[i];
 }
 
 template <typename T>
@@ -131,16 +196,16 @@ hipError_t launch_pcg_init(const tosimp_ctx* c, const T* b, const T* Ku, T* r, T
 template <typename T>
 hipError_t launch_pcg_update(const tosimp_ctx* c, T* u, T* r, const T* p, const T* q,
                              const void* dinv, SolverState* st, double* partials) {
-  pcg_update_kernel<T><<<kRedBlocks, kRedThreads, 0, c->stream>>>(
-      u, r, p, q, (const T*)dinv, c->n_dof, st, partials);
+  pcg_update_kernel<T><<<vec_blocks(c), kRedThreads, 0, c->stream>>>(
+      u, r, p, q, (const T*)dinv, (int)c->n_dof, st, partials);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_pcg_direction(const tosimp_ctx* c, const T* r, T* p, const void* dinv,
                                 SolverState* st) {
-  pcg_direction_kernel<T><<<kRedBlocks, kRedThreads, 0, c->stream>>>(r, p, (const T*)dinv,
-                                                                     c->n_dof, st);
+  pcg_direction_kernel<T><<<vec_blocks(c), kRedThreads, 0, c->stream>>>(r, p, (const T*)dinv,
+                                                                       (int)c->n_dof, st);
   return hipGetLastError();
 }
 
@@ -233,6 +298,11 @@ __global__ void cast_kernel(const double* x, float* y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (float)x[i];
+}
+
+hipError_t launch_cast32(const tosimp_ctx* c, const double* x, float* y, int64_t n) {
+  cast_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(x, y, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_copy_cast_x(const tosimp_ctx* c, const double* x, float* x32) {

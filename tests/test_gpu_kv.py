@@ -3,7 +3,7 @@ oracle (assembled CSR), element by element.
 
 Tolerances: FP64 <= 1e-12 relative (2-norm and max-norm), FP32 <= 1e-5 relative
 (2-norm); the FP32 max-norm bound 2e-5 follows from ~150 rounded operations of unit
-roundoff 6e-8 on values of the size of max|y| (see DESIGN.md)."""
+roundoff 6e-8 on values of the size of max|y|."""
 import numpy as np
 import pytest
 import torch
@@ -142,3 +142,30 @@ def test_apply_K_full_size_4p9M_sampled(prec):
     scale = np.max(np.abs(y_ref))
     assert np.max(np.abs(y[dofs] - y_ref)) <= tol * scale
     assert np.all(np.isfinite(y))
+
+
+@pytest.mark.parametrize("prec,u", [("bf16_mfma", 2.0 ** -9), ("fp16_mfma", 2.0 ** -11)])
+@pytest.mark.parametrize("dims", [(16, 8, 8), (37, 19, 23), (2, 1, 3), (15, 14, 40)])
+def test_apply_K_mfma_within_rounding_bound(prec, u, dims):
+    """Low-precision contraction: K_E and the element DOFs are rounded to the MFMA input
+    type (unit roundoff u), products and sums are FP32.  Per free DOF the error is then
+    at most (2u + u^2 + ~50 * 2^-24) (|K| |v|)_i, with |K| |v| = sum_e E_e |K_E| |v_e|
+    computed by the oracle; 2.5u is asserted, plus 1e-6 max(|K||v|) for FP16 values
+    below its normal range (the per-element power-of-two scaling keeps the rest exact)."""
+    nx, ny, nz = dims
+    t, fixed, _ = gpu_problem(nx, ny, nz)
+    rho, v = si.random_density_and_vector(nx, ny, nz, seed=11)
+    v32 = v.astype(np.float32).astype(np.float64)
+    rho32 = rho.astype(np.float32).astype(np.float64)
+    E = fem.simp_modulus(rho32, 1.0, 1e-9, 3.0)
+    y_ref = fem.apply_K_elementwise(nx, ny, nz, E, KE, v32, fixed)
+    bound = fem.apply_K_elementwise(nx, ny, nz, E, np.abs(KE), np.abs(v32), fixed)
+    free = ~fem.fixed_mask(v.size, fixed)
+    for xdt in (torch.float32, torch.float64):
+        y = t.apply_K(dev(rho32, xdt), dev(v32, torch.float32), prec=prec).double().cpu().numpy()
+        err = np.abs(y - y_ref)
+        lim = 2.5 * u * bound + 1e-6 * bound[free].max()
+        assert np.all(err[free] <= lim[free]), float(np.max(err[free] / lim[free]))
+        assert np.array_equal(y[~free], v32[~free])
+        # the bound is not vacuous: the error is of the size the rounding predicts
+        assert rel(y, y_ref) <= 4 * u

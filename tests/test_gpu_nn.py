@@ -1,0 +1,268 @@
+"""GPU parity of the learned preconditioner against the oracle: U-Net forward and weight
+gradients (FP32 and BF16 storage), the preconditioner application, an Adam step, the
+harvesting of (r_k, u_k) pairs from FP64 PCG, and flexible CG with the Jacobi fallback.
+
+Tolerances: FP32 storage runs the convolutions on v_mfma_f32_16x16x4f32 with FP32
+accumulation over at most 27 x 96 products per output, so relative errors stay near
+1e-6; 1e-4 is asserted.  BF16 storage rounds weights and every activation to 8
+mantissa bits (relative 2^-9 per rounding, 12 layers deep): 5e-2 is asserted on the
+output and on each layer's gradient as a whole (relative L2)."""
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+from oracle import fem, nn, solvers
+from tests.helpers import dev, gpu_problem, rel
+
+pytestmark = pytest.mark.gpu
+
+BASE = 16
+
+
+def _flat(params, base=BASE):
+    return np.concatenate([params[name].reshape(-1) for name, *_ in nn.unet_layers(base)])
+
+
+def _unflat(vec, base=BASE):
+    out, o = {}, 0
+    for name, ci, co, k, _ in nn.unet_layers(base):
+        n = co * ci * k ** 3
+        out[name] = vec[o:o + n].reshape(co, ci, k, k, k)
+        o += n
+    return out
+
+
+def _to_oracle(a, grid, c):
+    X, Y, Z = grid
+    return np.asarray(a, dtype=np.float64).reshape(Z, Y, X, c).transpose(3, 0, 1, 2)
+
+
+def _from_oracle(a):
+    return np.ascontiguousarray(a.transpose(1, 2, 3, 0)).reshape(-1)
+
+
+def _net(nx, ny, nz, bf16, seed=1, kind="cantilever"):
+    t, fixed, f = gpu_problem(nx, ny, nz, kind)
+    t.nn_create(BASE, bf16=bf16)
+    params = nn.unet_init(BASE, 4, 3, seed=seed)
+    w = _flat(params)
+    assert t.nn_params == w.size
+    t.nn_set_weights(w.astype(np.float32))
+    # the oracle runs the FP32-rounded weights the library holds
+    params32 = _unflat(w.astype(np.float32).astype(np.float64))
+    return t, fixed, f, params32
+
+
+def _inputs(nx, ny, nz, seed=3):
+    rng = np.random.default_rng(seed)
+    grid = (nx + 1, ny + 1, nz + 1)
+    x4 = rng.standard_normal((grid[2], grid[1], grid[0], 4)).astype(np.float32)
+    x4[..., 3] = rng.uniform(0.0, 1.0, x4.shape[:3])
+    return grid, x4
+
+
+@pytest.mark.parametrize("dims", [(8, 6, 5), (19, 12, 9)])
+def test_forward_fp32_matches_oracle(dims):
+    nx, ny, nz = dims
+    t, _, _, params = _net(nx, ny, nz, bf16=False)
+    grid, x4 = _inputs(nx, ny, nz)
+    out = t.nn_forward(dev(x4.reshape(-1))).cpu().numpy()
+    ref, _ = nn.unet_forward(params, _to_oracle(x4, grid, 4), BASE)
+    err = rel(_to_oracle(out, grid, 3), ref)
+    t.close()
+    assert err <= 1e-4, err
+
+
+def test_forward_bf16_close_to_oracle():
+    nx, ny, nz = 8, 6, 5
+    t, _, _, params = _net(nx, ny, nz, bf16=True)
+    grid, x4 = _inputs(nx, ny, nz)
+    out = t.nn_forward(dev(x4.reshape(-1))).cpu().numpy()
+    ref, _ = nn.unet_forward(params, _to_oracle(x4, grid, 4), BASE)
+    err = rel(_to_oracle(out, grid, 3), ref)
+    t.close()
+    assert err <= 5e-2, err
+
+
+@pytest.mark.parametrize("bf16,tol,gtol", [(False, 1e-4, 1e-4), (True, 5e-2, 0.15)])
+def test_loss_and_gradients_match_oracle(bf16, tol, gtol):
+    """The weight gradient is a signed sum over every voxel, so its relative error is the
+    storage rounding times the cancellation ratio sum|terms| / |sum|; in BF16 the first
+    layers also see the rounding of every gradient tensor of the backward chain.  BF16
+    asserts 15% (relative L2) and a direction within 8 degrees (cosine >= 0.99)."""
+    nx, ny, nz = 8, 6, 5
+    t, fixed, _, params = _net(nx, ny, nz, bf16=bf16)
+    grid, x4 = _inputs(nx, ny, nz)
+    target = np.random.default_rng(9).standard_normal(3 * t.n_node).astype(np.float32)
+    loss, g = t.nn_loss_grad(dev(x4.reshape(-1)), dev(target))
+    xo = _to_oracle(x4, grid, 4)
+    out, cache = nn.unet_forward(params, xo, BASE)
+    free = np.ones(3 * t.n_node)
+    free[fixed] = 0.0
+    lo, dout = nn.rel_mse_loss(out, _to_oracle(target, grid, 3), _to_oracle(free, grid, 3))
+    grads = nn.unet_backward(params, cache, dout, BASE)
+    t.close()
+    assert abs(loss - lo) <= tol * lo
+    gg = _unflat(g.astype(np.float64))
+    errs = {name: rel(gg[name], grads[name]) for name, *_ in nn.unet_layers(BASE)}
+    cos = {name: float(np.sum(gg[name] * grads[name]) /
+                       (np.linalg.norm(gg[name]) * np.linalg.norm(grads[name])))
+           for name in errs}
+    assert max(errs.values()) <= gtol, errs
+    assert min(cos.values()) >= (0.99 if bf16 else 1 - 1e-8), cos
+
+
+def test_apply_matches_oracle_preconditioner():
+    nx, ny, nz = 8, 6, 5
+    t, fixed, _, params = _net(nx, ny, nz, bf16=False)
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0.05, 1.0, t.n_elem).astype(np.float32)
+    r = rng.standard_normal(t.n_dof).astype(np.float32)
+    r[fixed] = 0.0
+    t.nn_set_density(dev(x))
+    z = t.nn_apply(dev(r)).cpu().numpy()
+    rho = nn.node_density(x.astype(np.float64), nx, ny, nz)
+    fm = fem.fixed_mask(t.n_dof, fixed)
+    zo = nn.nn_precondition(params, r.astype(np.float64), rho, fm, base=BASE)
+    t.close()
+    assert np.all(z[fixed] == 0.0)
+    assert rel(z, zo) <= 1e-4
+
+
+def test_train_step_is_adam_on_mean_gradient():
+    nx, ny, nz = 8, 6, 5
+    t, fixed, _, params = _net(nx, ny, nz, bf16=False)
+    rng = np.random.default_rng(5)
+    x = np.full(t.n_elem, 0.5, dtype=np.float32)
+    t.nn_set_density(dev(x))
+    nb = 2
+    R = rng.standard_normal((nb, t.n_dof)).astype(np.float32)
+    E = rng.standard_normal((nb, t.n_dof)).astype(np.float32)
+    R[:, fixed] = 0.0
+    lr = 1e-3
+    loss = t.nn_train_step(dev(R), dev(E), lr=lr)
+    w1 = t.nn_get_weights().astype(np.float64)
+    # oracle: mean loss and mean gradient over the batch, then one Adam step
+    rho = nn.node_density(x.astype(np.float64), nx, ny, nz)
+    grid = (nx + 1, ny + 1, nz + 1)
+    free = np.ones(t.n_dof)
+    free[fixed] = 0.0
+    gsum = {k: np.zeros_like(v) for k, v in params.items()}
+    lsum = 0.0
+    for s in range(nb):
+        rn = np.linalg.norm(R[s].astype(np.float64))
+        inp = np.concatenate([_to_oracle(R[s] / rn, grid, 3), rho[None]], axis=0)
+        out, cache = nn.unet_forward(params, inp, BASE)
+        lo, dout = nn.rel_mse_loss(out, _to_oracle(E[s] / rn, grid, 3), _to_oracle(free, grid, 3))
+        lsum += lo
+        for k, v in nn.unet_backward(params, cache, dout, BASE).items():
+            gsum[k] += v
+    gmean = {k: v / nb for k, v in gsum.items()}
+    p_new = {k: v.copy() for k, v in params.items()}
+    nn.adam_step(p_new, gmean, {}, lr=lr)
+    w_ref = _flat(p_new)
+    w0 = _flat(params)
+    t.close()
+    assert abs(loss - lsum / nb) <= 1e-4 * lsum / nb
+    # the first Adam step moves each weight by lr * g / (|g| + eps): compare the moves
+    d_gpu, d_ref = w1 - w0, w_ref - w0
+    g_flat = np.abs(_flat(gmean))
+    big = g_flat > 1e-3 * np.max(g_flat)  # weights whose gradient sign FP32 settles
+    assert np.max(np.abs(d_gpu[big] - d_ref[big])) <= 1e-3 * lr
+    assert np.max(np.abs(d_gpu)) <= lr * (1 + 1e-5)
+
+
+def test_weights_roundtrip_and_errors():
+    from paper_2604_18020_amd import TosimpError
+    t, _, _ = gpu_problem(6, 4, 4)
+    with pytest.raises(TosimpError):
+        t.nn_create(base=12)
+    t.nn_create(16, bf16=True)
+    w = np.random.default_rng(0).standard_normal(t.nn_params).astype(np.float32)
+    t.nn_set_weights(w)
+    assert np.array_equal(t.nn_get_weights(), w)
+    with pytest.raises(TosimpError):
+        t.nn_set_weights(w[:-1])
+    t.close()
+
+
+def test_harvest_pairs_from_fp64_pcg():
+    nx, ny, nz = 12, 6, 6
+    t, fixed, f = gpu_problem(nx, ny, nz)
+    rng = np.random.default_rng(6)
+    xd = dev(rng.uniform(0.1, 1.0, t.n_elem))
+    b = dev(f)
+    u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+    cap, every = 6, 5
+    hr = torch.zeros(cap, t.n_dof, dtype=torch.float32, device="cuda:0")
+    hu = torch.zeros(cap, t.n_dof, dtype=torch.float32, device="cuda:0")
+    st = t.pcg_solve(xd, b, u, tol=1e-10, harvest=(hr, hu), harvest_every=every)
+    assert st["harvested"] == min(cap, (st["iterations"] - 1) // every + 1)
+    # pair k is (r, u) after k * every iterations of the same Jacobi-PCG run in the oracle
+    xo = xd.cpu().numpy()
+    K = fem.constrain(fem.assemble_K(nx, ny, nz, fem.simp_modulus(xo, 1.0, 1e-9, 3.0),
+                                     fem.element_stiffness(0.3)), fem.fixed_mask(t.n_dof, fixed))
+    d = K.diagonal()
+    for k in range(st["harvested"]):
+        uk, _, _ = solvers.pcg_jacobi(lambda v: K @ v, d, f, None, 1e-30, maxit=k * every)
+        rk = f - K @ uk
+        assert rel(hu[k].cpu().numpy(), uk) <= 1e-6 or k == 0
+        assert rel(hr[k].cpu().numpy(), rk) <= 1e-5
+    assert np.all(hu[0].cpu().numpy() == 0.0)  # zero initial guess
+    n = st["harvested"]
+    t.nn_make_targets(u, hu, n)
+    e0 = hu[0].cpu().numpy()
+    assert rel(e0, u.cpu().numpy()) <= 1e-7
+    t.close()
+
+
+def _fcg_problem(nx=12, ny=6, nz=6, seed=7):
+    t, fixed, f = gpu_problem(nx, ny, nz)
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.1, 1.0, t.n_elem)
+    return t, fixed, f, x
+
+
+def test_fcg_zero_network_falls_back_to_jacobi():
+    t, fixed, f, x = _fcg_problem()
+    t.nn_create(16, bf16=True)
+    t.nn_set_weights(np.zeros(t.nn_params, dtype=np.float32))
+    kw = dict(tol=1e-8, mode="ir", inner_prec="fp32", inner_tol=1e-5, check_every=1)
+    u1 = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+    s_nn = t.pcg_solve(dev(x), dev(f), u1, precond="nn", **kw)
+    u2 = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+    s_j = t.pcg_solve(dev(x), dev(f), u2, precond="jacobi", **kw)
+    t.close()
+    # z = N(r) = 0 is never a descent direction: every step takes the Jacobi fallback,
+    # and FCG with a fixed SPD preconditioner is PCG
+    assert s_nn["fallbacks"] == s_nn["iterations"]
+    assert s_nn["rc"] == 2  # TOSIMP_FALLBACK_USED
+    assert abs(s_nn["iterations"] - s_j["iterations"]) <= 2 * s_j["outer_iterations"]
+    assert s_nn["true_rel_residual"] <= 1e-8
+
+
+def test_fcg_random_network_converges_to_direct_solution():
+    t, fixed, f, x = _fcg_problem()
+    t.nn_create(16, bf16=True)
+    t.nn_set_weights(_flat(nn.unet_init(BASE, 4, 3, seed=2)).astype(np.float32))
+    u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+    s = t.pcg_solve(dev(x), dev(f), u, precond="nn", tol=1e-9, mode="ir", inner_prec="fp32",
+                    inner_tol=1e-5, check_every=1, maxit=5000)
+    nx, ny, nz = t.dims
+    t.close()
+    assert s["rc"] in (0, 2)
+    assert s["true_rel_residual"] <= 1e-9
+    E = fem.simp_modulus(x, 1.0, 1e-9, 3.0)
+    u_ref = solvers.solve_direct(fem.constrain(fem.assemble_K(nx, ny, nz, E, fem.element_stiffness(0.3)),
+                                               fem.fixed_mask(3 * (nx + 1) * (ny + 1) * (nz + 1), fixed)), f)
+    assert rel(u.cpu().numpy(), u_ref) <= 1e-6
+
+
+def test_nn_precond_without_network_is_rejected():
+    from paper_2604_18020_amd import TosimpError
+    t, fixed, f, x = _fcg_problem()
+    u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(TosimpError):
+        t.pcg_solve(dev(x), dev(f), u, precond="nn", mode="ir", tol=1e-8)
+    t.close()
