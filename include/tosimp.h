@@ -71,7 +71,8 @@ typedef struct tosimp_solve_opts {
   int maxit;         /* cap on CG iterations (plain) or on inner iterations in total  */
   int mode;          /* TOSIMP_SOLVE_*                                                */
   int inner_prec;    /* TOSIMP_PREC_* of the inner solve in IR mode                   */
-  double inner_tol;  /* relative tolerance of each inner solve in IR mode             */
+  double inner_tol;  /* IR: relative tolerance of each inner solve, loosened to       */
+                     /*   min(0.5, 0.3 tol ||b|| / ||r||) when that reaches tol       */
   int max_outer;     /* cap on refinement steps in IR mode                            */
   int precond;       /* TOSIMP_PRECOND_*                                              */
   int check_every;   /* host convergence polls every this many iterations (>= 1)      */
@@ -210,9 +211,9 @@ int tosimp_tridiag_extremes(const double* alpha, const double* beta, int m, doub
                             double* lmax);
 
 /* ---- learned preconditioner -------------------------------------------------------
- * A 3-level 3D-convolutional U-Net N on the node grid, used as a variable
- * preconditioner z = ||r|| N(r / ||r||, rho_node) in flexible CG (IR mode with
- * precond = TOSIMP_PRECOND_NN).  Not in the paper (its Sec. "Path to Geometric
+ * A 3-level 3D-convolutional U-Net N on the node grid supplies the correction of a
+ * variable two-stage preconditioner (tosimp_nn_precondition) in flexible CG (IR mode
+ * with precond = TOSIMP_PRECOND_NN).  Not in the paper (its Sec. "Path to Geometric
  * Multigrid Integration" names stronger preconditioners as the way past Jacobi-PCG).
  * Layers (c_in -> c_out, kernel, stride; b = base): e0a 4->b, e0b b->b, d1 b->2b s2,
  * e1 2b->2b, d2 2b->4b s2, m2a 4b->4b, m2b 4b->4b, u1a [up(m2b), e1] 6b->2b,
@@ -220,17 +221,23 @@ int tosimp_tridiag_extremes(const double* alpha, const double* beta, int m, doub
  * ReLU 0.01), head b->3 (1x1x1, linear); nearest up-sampling; no biases.
  * Weights: FP32 master copy in [layer][c_out][c_in][kz][ky][kx] order (layers as
  * listed), compute copies in BF16 (bf16 = 1) or FP32.  Training: Adam (0.9, 0.999,
- * 1e-8) on the relative masked loss sum_free (N - e/||r||)^2 / sum_free (e/||r||)^2.
+ * 1e-8) on the relative masked loss sum_free (N - t)^2 / sum_free t^2 with the target
+ * direction t = e / ||e||: flexible CG does not depend on the scale of z.
  *
  * tosimp_nn_create: build the network for the current mesh (base 16 or 32); weights
  *   are zero until set.  Replaces an existing network.  Allocates its workspace.
  * tosimp_nn_num_params: number of FP32 master weights.
  * tosimp_nn_set_weights / get_weights: copy the master weights from / to host memory
  *   (n must equal the count); set_weights also resets the Adam moments.  Synchronise.
- * tosimp_nn_set_density: nodal density (mean of the adjacent elements) from an FP32
- *   element density on the device; used by apply and train_step.
+ * tosimp_nn_set_density: nodal density (mean of the adjacent elements) from an element
+ *   density on the device (xdtype TOSIMP_F64 or TOSIMP_F32); used by apply and
+ *   train_step until the next call.
  * tosimp_nn_apply: z = ||r|| N(r/||r||, rho_node), zero on fixed DOFs (FP32 device
  *   vectors, n_dof; r and z must not alias).
+ * tosimp_nn_precondition: the preconditioner flexible CG applies, at element density
+ *   x32 (FP32 device): n = ||r|| N(r/||r||, rho_node), s = <r,n>/<n,K n> (0 unless
+ *   both are positive), z = s n + D^-1 (r - s K n), D the Jacobi diagonal of K_c(x32).
+ *   Sets the nodal density.  r, z: FP32 device n_dof, distinct.  Synchronises.
  * tosimp_nn_forward: test hook, raw network output [n_node][3] FP32 for a channels-last
  *   input [n_node][4] FP32 (both device).
  * tosimp_nn_loss_grad: test hook, the loss against target [n_node][3] (device FP32;
@@ -244,8 +251,10 @@ int tosimp_nn_create(tosimp_ctx* ctx, int base, int bf16);
 int tosimp_nn_num_params(const tosimp_ctx* ctx, int64_t* n);
 int tosimp_nn_set_weights(tosimp_ctx* ctx, const float* w_host, int64_t n);
 int tosimp_nn_get_weights(tosimp_ctx* ctx, float* w_host, int64_t n);
-int tosimp_nn_set_density(tosimp_ctx* ctx, const float* x32_dev);
+int tosimp_nn_set_density(tosimp_ctx* ctx, const void* x_dev, int xdtype);
 int tosimp_nn_apply(tosimp_ctx* ctx, const float* r_dev, float* z_dev);
+int tosimp_nn_precondition(tosimp_ctx* ctx, const float* x32_dev, const float* r_dev,
+                           float* z_dev);
 int tosimp_nn_forward(tosimp_ctx* ctx, const float* x4_dev, float* out3_dev);
 int tosimp_nn_loss_grad(tosimp_ctx* ctx, const float* x4_dev, const float* target3_dev,
                         double* loss_host, float* grad_host);

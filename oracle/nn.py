@@ -274,3 +274,20 @@ def nn_precondition(params, r: np.ndarray, rho_node: np.ndarray, fixed_mask: np.
     z = out.transpose(1, 2, 3, 0).reshape(-1) * rn
     z[fixed_mask] = 0.0
     return z
+
+
+def two_stage(r: np.ndarray, n: np.ndarray, apply_K, d: np.ndarray) -> np.ndarray:
+    """Correction n followed by a Jacobi step on the remaining residual:
+    s = <r, n> / <n, K n> (the scale minimising the energy norm of the error after the
+    correction; 0 unless both are positive), z = s n + D^-1 (r - s K n)."""
+    Kn = apply_K(n)
+    rn, nkn = float(r @ n), float(n @ Kn)
+    s = rn / nkn if (rn > 0 and nkn > 0) else 0.0
+    return s * n + (r - s * Kn) / d
+
+
+def nn_two_stage_precondition(params, r, rho_node, fixed_mask, apply_K, d, base=16):
+    """The learned preconditioner of the flexible CG: two_stage with n the network output."""
+    n = nn_precondition(params, r, rho_node, fixed_mask, base)
+    return two_stage(r, n, apply_K, d)
+

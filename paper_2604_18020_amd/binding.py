@@ -91,8 +91,9 @@ def _load():
         "tosimp_nn_num_params": (I, [P, C.POINTER(L)]),
         "tosimp_nn_set_weights": (I, [P, P, L]),
         "tosimp_nn_get_weights": (I, [P, P, L]),
-        "tosimp_nn_set_density": (I, [P, P]),
+        "tosimp_nn_set_density": (I, [P, P, I]),
         "tosimp_nn_apply": (I, [P, P, P]),
+        "tosimp_nn_precondition": (I, [P, P, P, P]),
         "tosimp_nn_forward": (I, [P, P, P]),
         "tosimp_nn_loss_grad": (I, [P, P, P, C.POINTER(D), P]),
         "tosimp_nn_train_step": (I, [P, P, P, I, D, C.POINTER(D)]),
@@ -208,8 +209,7 @@ class Tosimp:
                          PRECOND[precond], check_every, int(enforce_rule), kappa, None, None,
                          0, 0)
 
-    def pcg_solve(self, x, b, u, harvest=None, harvest_every=1, **kw):
-        """harvest: optional (r, u) pair of FP32 device tensors [cap, n_dof] (plain FP64)."""
+    def _opts_with_harvest(self, harvest, harvest_every, **kw):
         o = self.solve_opts(**kw)
         if harvest is not None:
             hr, hu = harvest
@@ -217,6 +217,11 @@ class Tosimp:
             o.harvest_r = self._dev(hr, torch.float32, cap * self.n_dof, "harvest_r").value
             o.harvest_u = self._dev(hu, torch.float32, cap * self.n_dof, "harvest_u").value
             o.harvest_cap, o.harvest_every = cap, int(harvest_every)
+        return o
+
+    def pcg_solve(self, x, b, u, harvest=None, harvest_every=1, **kw):
+        """harvest: optional (r, u) pair of FP32 device tensors [cap, n_dof] (plain FP64)."""
+        o = self._opts_with_harvest(harvest, harvest_every, **kw)
         s = SolveStats()
         self._sync_stream()
         rc = self._check(LIB.tosimp_pcg_solve(
@@ -260,8 +265,9 @@ class Tosimp:
             self._dev(xpn, torch.float64, self.n_elem, "xphys_new"), C.byref(ch), C.byref(st)))
         return xn, xpn, ch.value, st.value
 
-    def simp_step(self, x, xphys, u, volfrac=0.3, move=0.2, **solve_kw):
-        o = StepOpts(volfrac, move, self.solve_opts(**solve_kw))
+    def simp_step(self, x, xphys, u, volfrac=0.3, move=0.2, harvest=None, harvest_every=1,
+                  **solve_kw):
+        o = StepOpts(volfrac, move, self._opts_with_harvest(harvest, harvest_every, **solve_kw))
         s = StepStats()
         self._sync_stream()
         rc = self._check(LIB.tosimp_simp_step(
@@ -289,6 +295,7 @@ class Tosimp:
     def nn_create(self, base=16, bf16=True):
         self._sync_stream()
         self._check(LIB.tosimp_nn_create(self._h, int(base), int(bool(bf16))))
+        self.nn_base = int(base)
         n = C.c_int64()
         self._check(LIB.tosimp_nn_num_params(self._h, C.byref(n)))
         self.nn_params = n.value
@@ -305,10 +312,10 @@ class Tosimp:
         self._check(LIB.tosimp_nn_get_weights(self._h, a.ctypes.data_as(C.c_void_p), a.size))
         return a
 
-    def nn_set_density(self, x32):
+    def nn_set_density(self, x):
         self._sync_stream()
-        self._check(LIB.tosimp_nn_set_density(self._h, self._dev(x32, torch.float32, self.n_elem,
-                                                                 "x32")))
+        self._check(LIB.tosimp_nn_set_density(self._h, self._dev(x, None, self.n_elem, "x"),
+                                              _DT[x.dtype]))
 
     def nn_apply(self, r, z=None):
         if z is None:
@@ -316,6 +323,16 @@ class Tosimp:
         self._sync_stream()
         self._check(LIB.tosimp_nn_apply(self._h, self._dev(r, torch.float32, self.n_dof, "r"),
                                         self._dev(z, torch.float32, self.n_dof, "z")))
+        return z
+
+    def nn_precondition(self, x32, r, z=None):
+        if z is None:
+            z = torch.empty_like(r)
+        self._sync_stream()
+        self._check(LIB.tosimp_nn_precondition(
+            self._h, self._dev(x32, torch.float32, self.n_elem, "x32"),
+            self._dev(r, torch.float32, self.n_dof, "r"),
+            self._dev(z, torch.float32, self.n_dof, "z")))
         return z
 
     def nn_forward(self, x4):

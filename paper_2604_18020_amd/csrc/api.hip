@@ -625,17 +625,21 @@ int tosimp_pcg_solve(tosimp_ctx* ctx, const double* x, const double* b, double* 
       prev = rel;
       const double sc = std::sqrt(rr);
       TOSIMP_HIP(ctx, launch_scale_to32(ctx, w.r, 1.0 / sc, w.e32));  // rhs in e32
+      // Inner target: inner_tol, but no tighter than the reduction still needed to
+      // reach tol (with a safety factor for the inner solve's own rounding).
+      const double need = 0.3 * o->tol * bn / sc;
+      const double itol = std::min(0.5, std::max(o->inner_tol, need));
       int it = 0, done = 0;
       if (o->precond == TOSIMP_PRECOND_NN) {
         int fb = 0;
-        rc = nn_fcg_solve(ctx, ip, w.x32, w.e32, w.z32, o->inner_tol, o->maxit - total,
+        rc = nn_fcg_solve(ctx, ip, w.x32, w.e32, w.z32, itol, o->maxit - total,
                           o->check_every, &it, &fb, &done);
         if (rc < 0) return rc;
         fallbacks += fb;
       } else {
         PcgResult pr;
         rc = run_pcg<float>(ctx, ip, w.x32, TOSIMP_F32, w.e32, w.z32, w.dinv32, 1,
-                            o->inner_tol, o->maxit - total, o->check_every, true, &pr);
+                            itol, o->maxit - total, o->check_every, true, &pr);
         if (rc) return rc;
         it = pr.iters;
         done = pr.done;

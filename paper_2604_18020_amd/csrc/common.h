@@ -42,19 +42,19 @@ struct SolverState {
   double bb;      // ||b||^2
   double tol2;    // tol^2 * ||b||^2
   double pq;      // <p, K p>
-  double aux;     // scratch scalar (e.g. FCG numerator)
+  double aux;     // scratch scalar (tol^2 on entry; FCG: fallback flag)
+  double s_rn;    // two-stage preconditioner: <r, n> and <n, K n>
+  double s_nkn;
   int iter;       // completed iterations
   int maxit;      // iteration cap
   int done;       // 0 running, 1 converged, 2 cap, 3 breakdown
   int nfallback;  // flexible CG: preconditioner fallbacks taken
-  unsigned cnt[4];  // last-block counters (reset by the last block)
 };
 
 // Device-side state of the OC bisection.
 struct OcState {
   double l1, l2, lmid, target, vol, change;
   int steps, done;
-  unsigned cnt[4];
 };
 
 constexpr int kRedBlocks = 1024;   // fixed grid of the vector kernels (deterministic)
@@ -136,6 +136,7 @@ hipError_t launch_apply_K(const tosimp_ctx* c, int prec, int xdtype, const void*
 int kv_num_blocks(const tosimp_ctx* c);
 hipError_t launch_diag_inv(const tosimp_ctx* c, const double* xphys, double* dinv64,
                            float* dinv32);
+hipError_t launch_diag_inv32(const tosimp_ctx* c, const float* x32, float* dinv32);
 hipError_t launch_diag_full(const tosimp_ctx* c, int xdtype, const void* x, int dtype,
                             void* d);
 

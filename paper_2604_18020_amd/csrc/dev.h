@@ -1,4 +1,4 @@
-// Device helpers: deterministic reductions and the last-block pattern.
+// Device helpers: deterministic block reductions and two-kernel grid reductions.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -49,24 +49,6 @@ __device__ __forceinline__ double block_max(double v, double* sbuf) {
   return r;
 }
 
-// Called by every thread of a block after thread 0 stored the block's partial.
-// Returns true in exactly one block: the last of `expected` arriving blocks.  The
-// release fence before the counter increment and the acquire fence after it make
-// every other block's partial visible to the last block (agent scope, across XCDs).
-__device__ __forceinline__ bool last_block_arrive(unsigned* cnt, unsigned expected) {
-  __shared__ int s_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned t = atomicAdd(cnt, 1u);
-    s_last = (t == expected - 1u);
-  }
-  __syncthreads();
-  const bool last = s_last != 0;
-  if (last) __threadfence();
-  return last;
-}
-
 // Sum n partials (stride `stride` doubles apart) in a fixed order; valid in thread 0.
 template <int NT>
 __device__ __forceinline__ double sum_partials(const double* part, int n, int stride,
@@ -82,6 +64,51 @@ __device__ __forceinline__ double max_partials(const double* part, int n, int st
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += NT) s = fmax(s, part[(size_t)i * stride]);
   return block_max<NT>(s, sbuf);
+}
+
+// Grid reductions take two launches: the reduction kernel stores NV block sums per block
+// (store_block_sums) and a one-block finalize kernel adds them in block order and hands
+// the totals to a functor (thread 0), which updates the solver state.  The kernel
+// boundary orders the two.  A single-kernel "last block finishes" scheme needs a
+// device-scope release fence in every block, which on a multi-XCD GPU writes back that
+// XCD's L2 cache: thousands of such fences cost far more than the second launch.
+template <int NV, int NT = 256>
+__device__ __forceinline__ void store_block_sums(const double (&v)[NV], double* partials,
+                                                 double* sbuf) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double s = block_sum<NT>(v[k], sbuf);
+    if (threadIdx.x == 0) partials[(size_t)NV * blockIdx.x + k] = s;
+  }
+}
+
+template <int NV, typename F>
+__global__ __launch_bounds__(256) void finalize_sum_kernel(const double* partials, int nb, F f) {
+  __shared__ double sbuf[4];
+  double tot[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) tot[k] = sum_partials<256>(partials + k, nb, NV, sbuf);
+  if (threadIdx.x == 0) f(tot);
+}
+
+template <typename F>
+__global__ __launch_bounds__(256) void finalize_max_kernel(const double* partials, int nb, F f) {
+  __shared__ double sbuf[4];
+  double tot[1];
+  tot[0] = max_partials<256>(partials, nb, 1, sbuf);
+  if (threadIdx.x == 0) f(tot);
+}
+
+template <int NV, typename F>
+inline hipError_t launch_finalize_sum(hipStream_t s, const double* partials, int nb, F f) {
+  finalize_sum_kernel<NV, F><<<1, 256, 0, s>>>(partials, nb, f);
+  return hipGetLastError();
+}
+
+template <typename F>
+inline hipError_t launch_finalize_max(hipStream_t s, const double* partials, int nb, F f) {
+  finalize_max_kernel<F><<<1, 256, 0, s>>>(partials, nb, f);
+  return hipGetLastError();
 }
 
 template <typename T>

@@ -20,8 +20,8 @@
 //  * Each node sums the four element-column contributions around it from LDS in a
 //    fixed order and is written once, coalesced.  Fixed DOFs output y = v.
 //  * Block ids are remapped so that each XCD gets a contiguous range of tiles.
-//  * Optionally the block's share of <v, y> (FP64) is reduced and the last block
-//    finalises it (CG step length, Lanczos alpha).
+//  * Optionally the block's share of <v, y> (FP64) is stored per tile and a one-block
+//    kernel finalises it (CG step length, Lanczos alpha).
 #include "common.h"
 #include "dev.h"
 
@@ -93,11 +93,18 @@ __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, int o
 __device__ __forceinline__ uint8_t buf_ld_u8(__amdgpu_buffer_rsrc_t r, int off, int soff) {
   return __builtin_amdgcn_raw_buffer_load_b8(r, off, soff, 0);
 }
-__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, int off, int soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, soff, 0);
+// Stores take the whole offset in the VGPR and a zero soffset.  The compiler merges the
+// three component stores of a node into one 16-byte (FP64) store; after a store wider
+// than 8 bytes the data VGPRs must not be overwritten by the next VALU instruction, and
+// the compiler inserts that wait state only when soffset is not an SGPR.  With the plane
+// offset in an SGPR soffset the wait was omitted and the store occasionally wrote the
+// value of the following instruction.  Out-of-range lanes keep an offset past
+// num_records (the sum stays below 2^32 and the range check is unsigned).
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
 }
-__device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, int off, int soff) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, soff, 0);
+__device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
 }
 
 // a if sel == 0 else b, as a bitwise blend (no branch around the computation of a).
@@ -303,7 +310,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
         T yv = (sc[(9 + c) * NE + tid] + sc[(6 + c) * NE + tid + 1]) +
                (sc[(3 + c) * NE + tid + KBX] + sc[(0 + c) * NE + tid + KBX + 1]);
         yv = bit_select(yv, vown[c], (mown >> c) & 1);  // fixed rows are identity: y = v
-        buf_st(yv, ry, yoff + c * (int)sizeof(T), soff);
+        buf_st(yv, ry, (unsigned)yoff + (unsigned)(c * (int)sizeof(T)) + (unsigned)soff);
         if constexpr (DOT) dotacc += owner ? (double)vown[c] * (double)yv : 0.0;
       }
     }
@@ -330,27 +337,32 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
 
   if constexpr (DOT) {
     const double bsum = block_sum<256>(dotacc, sred);
-    if (threadIdx.x == 0) A.partials[t] = bsum;
-    if (last_block_arrive(&A.st->cnt[0], (unsigned)A.ntiles)) {
-      const double tot = sum_partials<256>(A.partials, A.ntiles, 1, sred);
-      if (threadIdx.x == 0) {
-        if (A.fin == FIN_ALPHA) {
-          SolverState* st = A.st;
-          st->pq = tot;
-          if (!(tot > 0.0) || !finite_val(tot)) {
-            st->done = 3;  // breakdown
-            st->alpha = 0.0;
-          } else {
-            st->alpha = st->rz / tot;
-          }
-        } else if (A.fin == FIN_SCALAR) {
-          *A.out = tot;
-        }
-        A.st->cnt[0] = 0u;
-      }
-    }
+    if (threadIdx.x == 0) A.partials[t] = bsum;  // one slot per tile
   }
 }
+
+// Finishes the fused <v, K v>: CG step length (FIN_ALPHA) or a plain scalar.
+struct KvDotFin {
+  SolverState* st;
+  double* out;
+  int fin;
+  int guarded;
+  __device__ void operator()(const double* t) const {
+    if (guarded && st->done) return;
+    const double tot = t[0];
+    if (fin == FIN_ALPHA) {
+      st->pq = tot;
+      if (!(tot > 0.0) || !finite_val(tot)) {
+        st->done = 3;  // breakdown
+        st->alpha = 0.0;
+      } else {
+        st->alpha = st->rz / tot;
+      }
+    } else {
+      *out = tot;
+    }
+  }
+};
 
 // Planes in flight per block, and the deepest z chunk a block sweeps (fully unrolled).
 template <typename T>
@@ -453,8 +465,13 @@ static hipError_t kv_launch_v(const tosimp_ctx* c, KvArgs<T, XT> A, bool guarded
   const KvGeom g = kv_geom_for(c, res, kv_kzmax<T>());
   A.tiles_x = g.tiles_x; A.tiles_y = g.tiles_y; A.chunks_z = g.chunks_z; A.kz = g.kz;
   A.ntiles = g.ntiles; A.per_xcd = g.per_xcd;
+  if (DOT && g.ntiles > 2 * kMaxPartials) return hipErrorInvalidValue;  // partial slots
   kern<<<dim3(g.grid), dim3(256), 0, c->stream>>>(A);
-  return hipGetLastError();
+  if (!DOT) return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize_sum<1>(c->stream, A.partials, g.ntiles,
+                                KvDotFin{A.st, A.out, A.fin, guarded ? 1 : 0});
 }
 
 template <typename T, typename XT>
@@ -554,6 +571,10 @@ static hipError_t diag_launch(const tosimp_ctx* c, const XT* x, double* dinv64,
 hipError_t launch_diag_inv(const tosimp_ctx* c, const double* xphys, double* dinv64,
                            float* dinv32) {
   return diag_launch<double>(c, xphys, dinv64, dinv32, nullptr, nullptr);
+}
+
+hipError_t launch_diag_inv32(const tosimp_ctx* c, const float* x32, float* dinv32) {
+  return diag_launch<float>(c, x32, nullptr, dinv32, nullptr, nullptr);
 }
 
 hipError_t launch_diag_full(const tosimp_ctx* c, int xdtype, const void* x, int dtype,

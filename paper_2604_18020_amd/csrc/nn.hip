@@ -286,7 +286,8 @@ __global__ void pad_input_kernel(const float* x4, ST* inp, int n) {
 }
 
 // Nodal density: mean of the (up to 8) elements around each node.
-__global__ void node_density_kernel(const float* x, int nx, int ny, int nz, float* rho) {
+template <typename XT>
+__global__ void node_density_kernel(const XT* x, int nx, int ny, int nz, float* rho) {
   const int n_node = (nx + 1) * (ny + 1) * (nz + 1);
   for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < n_node; n += gridDim.x * blockDim.x) {
     const int i = n % (nx + 1), j = (n / (nx + 1)) % (ny + 1), k = n / ((nx + 1) * (ny + 1));
@@ -297,7 +298,7 @@ __global__ void node_density_kernel(const float* x, int nx, int ny, int nz, floa
         for (int dx = -1; dx <= 0; ++dx) {
           const int ex = i + dx, ey = j + dy, ez = k + dz;
           if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
-          s += x[ex + nx * (ey + ny * ez)];
+          s += (float)x[ex + nx * (ey + ny * ez)];
           ++c;
         }
     rho[n] = s / (float)c;
@@ -357,8 +358,7 @@ __global__ void add_skip_kernel(ST* dst, const ST* a, const ST* b, int n, int c,
 // loss = sum(m (out - e)^2) / sum(m e^2); writes dLoss/dout into g [v][16] (padded).
 template <typename ST>
 __global__ __launch_bounds__(256) void loss_kernel(const ST* out, const float* e, const uint8_t* mask,
-                                                   int n_node, double* partials, double* den_num,
-                                                   unsigned* cnt) {
+                                                   int n_node, double* partials) {
   __shared__ double sred[4];
   double num = 0.0, den = 0.0;
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n_node; v += gridDim.x * blockDim.x) {
@@ -371,21 +371,24 @@ __global__ __launch_bounds__(256) void loss_kernel(const ST* out, const float* e
       den += t * t;
     }
   }
-  const double s0 = block_sum<256>(num, sred);
-  const double s1 = block_sum<256>(den, sred);
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = s0;
-    partials[2 * blockIdx.x + 1] = s1;
+  const double v[2] = {num, den};
+  store_block_sums<2>(v, partials, sred);
+}
+
+struct LossFin {
+  double* den_num;
+  __device__ void operator()(const double* t) const {
+    den_num[0] = t[1];
+    den_num[1] = t[0];
   }
-  if (last_block_arrive(cnt, gridDim.x)) {
-    const double N = sum_partials<256>(partials, gridDim.x, 2, sred);
-    const double Dn = sum_partials<256>(partials + 1, gridDim.x, 2, sred);
-    if (threadIdx.x == 0) {
-      den_num[0] = Dn;
-      den_num[1] = N;
-      *cnt = 0u;
-    }
-  }
+};
+
+// den_num[0] = sum m e^2, den_num[1] = sum m (out - e)^2.
+template <typename ST>
+hipError_t launch_loss(hipStream_t s, const ST* out, const float* e, const uint8_t* mask, int n,
+                       double* partials, double* den_num) {
+  loss_kernel<ST><<<1024, 256, 0, s>>>(out, e, mask, n, partials);
+  return launch_finalize_sum<2>(s, partials, 1024, LossFin{den_num});
 }
 
 template <typename ST>
@@ -419,13 +422,14 @@ __global__ void output_kernel(const ST* out, const uint8_t* mask, const double* 
 // transposed WT [ci_pad][t][co] used by the data gradient (padding channels stay 0).
 struct AdamArgs {
   float lr, b1, b2, eps, c1, c2;  // c1 = 1 - b1^t, c2 = 1 - b2^t
+  float omb1, omb2;                // 1 - b1, 1 - b2 (rounded from FP64)
 };
 
 __global__ void adam_kernel(float* w, float* m, float* v, const float* g, int n, AdamArgs a) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const float gi = g[i];
-    const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
-    const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
+    const float mi = a.b1 * m[i] + a.omb1 * gi;
+    const float vi = a.b2 * v[i] + a.omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     w[i] -= a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
@@ -493,28 +497,25 @@ __global__ __launch_bounds__(256) void fcg_check_kernel(const float* __restrict_
     rz += (double)r[i] * zi;
     if (!first) zq += zi * (double)q[i];
   }
-  const double s0 = block_sum<256>(rz, sred);
-  const double s1 = block_sum<256>(zq, sred);
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = s0;
-    partials[2 * blockIdx.x + 1] = s1;
-  }
-  if (last_block_arrive(&st->cnt[2], gridDim.x)) {
-    const double RZ = sum_partials<256>(partials, gridDim.x, 2, sred);
-    const double ZQ = sum_partials<256>(partials + 1, gridDim.x, 2, sred);
-    if (threadIdx.x == 0) {
-      const double beta = first ? 0.0 : -ZQ / st->pq;
-      if (finite_val(RZ) && finite_val(beta) && RZ > 0.0) {
-        st->aux = 0.0;
-        st->rz = RZ;
-        st->beta = beta;
-      } else {
-        st->aux = 1.0;
-      }
-      st->cnt[2] = 0u;
+  const double v[2] = {rz, zq};
+  store_block_sums<2>(v, partials, sred);
+}
+
+struct FcgCheckFin {
+  SolverState* st;
+  __device__ void operator()(const double* t) const {
+    if (st->done) return;
+    const double RZ = t[0], ZQ = t[1];
+    const double beta = st->iter == 0 ? 0.0 : -ZQ / st->pq;
+    if (finite_val(RZ) && finite_val(beta) && RZ > 0.0) {
+      st->aux = 0.0;
+      st->rz = RZ;
+      st->beta = beta;
+    } else {
+      st->aux = 1.0;  // replace z by the Jacobi step
     }
   }
-}
+};
 
 __global__ __launch_bounds__(256) void fcg_fallback_kernel(const float* __restrict__ r,
                                                            float* __restrict__ z,
@@ -531,24 +532,58 @@ __global__ __launch_bounds__(256) void fcg_fallback_kernel(const float* __restri
     rz += (double)r[i] * (double)zi;
     if (!first) zq += (double)zi * (double)q[i];
   }
-  const double s0 = block_sum<256>(rz, sred);
-  const double s1 = block_sum<256>(zq, sred);
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = s0;
-    partials[2 * blockIdx.x + 1] = s1;
+  const double v[2] = {rz, zq};
+  store_block_sums<2>(v, partials, sred);
+}
+
+struct FcgFallbackFin {
+  SolverState* st;
+  __device__ void operator()(const double* t) const {
+    if (st->done || st->aux == 0.0) return;
+    const double RZ = t[0], ZQ = t[1];
+    const double beta = st->iter == 0 ? 0.0 : -ZQ / st->pq;
+    st->rz = RZ;
+    st->beta = beta;
+    st->aux = 0.0;
+    st->nfallback += 1;
+    if (!finite_val(RZ) || !finite_val(beta) || !(RZ > 0.0)) st->done = 3;
   }
-  if (last_block_arrive(&st->cnt[2], gridDim.x)) {
-    const double RZ = sum_partials<256>(partials, gridDim.x, 2, sred);
-    const double ZQ = sum_partials<256>(partials + 1, gridDim.x, 2, sred);
-    if (threadIdx.x == 0) {
-      const double beta = first ? 0.0 : -ZQ / st->pq;
-      st->rz = RZ;
-      st->beta = beta;
-      st->aux = 0.0;
-      st->nfallback += 1;
-      if (!finite_val(RZ) || !finite_val(beta) || !(RZ > 0.0)) st->done = 3;
-      st->cnt[2] = 0u;
-    }
+};
+
+// Two-stage preconditioner: n = network correction, then a Jacobi step on what remains,
+//   s = <r, n> / <n, K n> (energy-optimal scale of n; 0 unless both are positive),
+//   z = s n + D^-1 (r - s K n).
+// With n = K^-1 r this returns K^-1 r; with n = 0 it is the Jacobi step.
+__global__ __launch_bounds__(256) void dot_rn_kernel(const float* __restrict__ r,
+                                                     const float* __restrict__ nv, int n,
+                                                     const SolverState* st, double* partials) {
+  __shared__ double sred[4];
+  if (st->done) return;
+  double s = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    s += (double)r[i] * (double)nv[i];
+  const double v[1] = {s};
+  store_block_sums<1>(v, partials, sred);
+}
+
+struct SetRn {
+  SolverState* st;
+  __device__ void operator()(const double* t) const {
+    if (!st->done) st->s_rn = t[0];
+  }
+};
+
+__global__ __launch_bounds__(256) void two_stage_kernel(const float* __restrict__ r,
+                                                        const float* __restrict__ Kn,
+                                                        const float* __restrict__ dinv,
+                                                        float* __restrict__ z, int n,
+                                                        const SolverState* st) {
+  if (st->done) return;
+  const double rn = st->s_rn, nkn = st->s_nkn;
+  const float sc = (rn > 0.0 && nkn > 0.0 && finite_val(rn / nkn)) ? (float)(rn / nkn) : 0.0f;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const float nv = z[i];  // z holds n on entry
+    z[i] = sc * nv + dinv[(unsigned)i / 3u] * (r[i] - sc * Kn[i]);
   }
 }
 
@@ -600,9 +635,8 @@ struct NNState {
   float* wpart = nullptr;      // weight-gradient partials
   size_t wpart_cap = 0;
   float* rho_node = nullptr;
-  double* scal = nullptr;      // device scalars: [0] ||r||^2, [1..2] den/num, ...
+  double* scal = nullptr;      // device scalars: [0] ||r||^2, [1..2] den/num, [3] ||e||^2
   double* part = nullptr;
-  unsigned* cnt = nullptr;
   int adam_t = 0;
 };
 
@@ -679,7 +713,7 @@ void tosimp::nn_release(tosimp_ctx* ctx) {
   NNState* S = ctx ? nn_of(ctx) : nullptr;
   if (!S) return;
   void* ptrs[] = {S->master, S->m,        S->v,    S->grad, S->gpack, S->W,   S->WT, S->cat1,
-                  S->cat0,   S->wpart,    S->rho_node, S->scal, S->part, S->cnt, S->gsum};
+                  S->cat0,   S->wpart,    S->rho_node, S->scal, S->part, S->gsum};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : S->act)
@@ -786,25 +820,28 @@ hipError_t nn_pack(tosimp_ctx* c, NNState* S) {
 }
 
 // ||r||^2 of an FP32 vector into *out (FP64, deterministic).
-__global__ __launch_bounds__(256) void norm2f_kernel(const float* r, int n, double* partials,
-                                                     double* out, unsigned* cnt) {
+__global__ __launch_bounds__(256) void norm2f_kernel(const float* r, int n, double* partials) {
   __shared__ double sred[4];
   double s = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     s += (double)r[i] * (double)r[i];
-  const double bs = block_sum<256>(s, sred);
-  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-  if (last_block_arrive(cnt, gridDim.x)) {
-    const double tot = sum_partials<256>(partials, gridDim.x, 1, sred);
-    if (threadIdx.x == 0) {
-      *out = tot;
-      *cnt = 0u;
-    }
-  }
+  const double v[1] = {s};
+  store_block_sums<1>(v, partials, sred);
 }
 
-__global__ void scale_target_kernel(const float* e, const double* rnorm2, float* out, int n) {
-  const float inv = (float)(1.0 / sqrt(fmax(*rnorm2, 1e-300)));
+struct SetScalar {
+  double* out;
+  __device__ void operator()(const double* t) const { *out = t[0]; }
+};
+
+// ||r||^2 into *out (two launches, deterministic).
+hipError_t launch_norm2f(hipStream_t s, const float* r, int n, double* partials, double* out) {
+  norm2f_kernel<<<1024, 256, 0, s>>>(r, n, partials);
+  return launch_finalize_sum<1>(s, partials, 1024, SetScalar{out});
+}
+
+__global__ void scale_target_kernel(const float* e, const double* enorm2, float* out, int n) {
+  const float inv = (float)(1.0 / sqrt(fmax(*enorm2, 1e-300)));
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     out[i] = e[i] * inv;
 }
@@ -818,7 +855,7 @@ __global__ void sub_targets_kernel(const double* ustar, float* hu, int n_dof, in
 template <typename ST>
 int nn_apply_t(tosimp_ctx* ctx, NNState* S, const float* r, float* z) {
   const int nn = (int)ctx->n_node;
-  norm2f_kernel<<<1024, 256, 0, ctx->stream>>>(r, (int)ctx->n_dof, S->part, S->scal, S->cnt);
+  TOSIMP_HIP(ctx, launch_norm2f(ctx->stream, r, (int)ctx->n_dof, S->part, S->scal));
   build_input_kernel<ST><<<2048, 256, 0, ctx->stream>>>(r, S->scal, S->rho_node, (ST*)S->act[12], nn);
   TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S));
   output_kernel<ST><<<2048, 256, 0, ctx->stream>>>((const ST*)S->act[11], ctx->ws.mask, S->scal, z, nn);
@@ -826,17 +863,21 @@ int nn_apply_t(tosimp_ctx* ctx, NNState* S, const float* r, float* z) {
   return TOSIMP_OK;
 }
 
-// One sample: forward on (r, rho), loss against e / ||r||, backward; grad += sample grad.
+// One sample: forward on (r / ||r||, rho), loss against e / ||e||, backward; the sample's
+// gradient is stored or added to gacc.
 template <typename ST>
 int nn_sample_grad(tosimp_ctx* ctx, NNState* S, const float* r, const float* e, float* tgt,
                    float* gacc, bool first, double* loss) {
   const int nn = (int)ctx->n_node;
-  norm2f_kernel<<<1024, 256, 0, ctx->stream>>>(r, (int)ctx->n_dof, S->part, S->scal, S->cnt);
+  TOSIMP_HIP(ctx, launch_norm2f(ctx->stream, r, (int)ctx->n_dof, S->part, S->scal));
   build_input_kernel<ST><<<2048, 256, 0, ctx->stream>>>(r, S->scal, S->rho_node, (ST*)S->act[12], nn);
-  scale_target_kernel<<<2048, 256, 0, ctx->stream>>>(e, S->scal, tgt, (int)ctx->n_dof);
+  // Target direction e / ||e||: flexible CG is invariant to the scale of z, and the
+  // unit-norm target matches the scale of the unit-norm input.
+  TOSIMP_HIP(ctx, launch_norm2f(ctx->stream, e, (int)ctx->n_dof, S->part, S->scal + 3));
+  scale_target_kernel<<<2048, 256, 0, ctx->stream>>>(e, S->scal + 3, tgt, (int)ctx->n_dof);
   TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S));
-  loss_kernel<ST><<<1024, 256, 0, ctx->stream>>>((const ST*)S->act[11], tgt, ctx->ws.mask, nn,
-                                                 S->part, S->scal + 1, S->cnt + 1);
+  TOSIMP_HIP(ctx, launch_loss<ST>(ctx->stream, (const ST*)S->act[11], tgt, ctx->ws.mask, nn,
+                                   S->part, S->scal + 1));
   loss_grad_kernel<ST><<<2048, 256, 0, ctx->stream>>>((const ST*)S->act[11], tgt, ctx->ws.mask, nn,
                                                       S->scal + 1, (ST*)S->gbuf[0]);
   TOSIMP_HIP(ctx, nn_backward<ST>(ctx, S));
@@ -852,8 +893,26 @@ int nn_sample_grad(tosimp_ctx* ctx, NNState* S, const float* r, const float* e, 
 }  // namespace
 
 
-// Flexible CG with the network as preconditioner (see the FCG kernels above).  Vectors:
-// r, p, q in the FP32 workspace, z in the FP64 scratch w (as floats); the iterate is e32.
+// The learned preconditioner z = M(r) on FP32 vectors: the network correction n
+// (written to z), K n into Kn, the two scalars into st, then the Jacobi stage in place.
+template <typename ST>
+int nn_precond_t(tosimp_ctx* ctx, NNState* S, const float* x32, const float* r, float* z,
+                 float* Kn, SolverState* st, double* part, double* kvpart) {
+  const int n = (int)ctx->n_dof;
+  const int vb = std::min(2048, (n + 255) / 256);
+  int rc = nn_apply_t<ST>(ctx, S, r, z);
+  if (rc) return rc;
+  TOSIMP_HIP(ctx, kv_launch(ctx, TOSIMP_PREC_FP32, TOSIMP_F32, x32, z, Kn, kvpart, st,
+                            &st->s_nkn, 2, true));
+  dot_rn_kernel<<<vb, 256, 0, ctx->stream>>>(r, z, n, st, part);
+  TOSIMP_HIP(ctx, launch_finalize_sum<1>(ctx->stream, part, vb, SetRn{st}));
+  two_stage_kernel<<<vb, 256, 0, ctx->stream>>>(r, Kn, ctx->ws.dinv32, z, n, st);
+  TOSIMP_HIP(ctx, hipGetLastError());
+  return TOSIMP_OK;
+}
+
+// Flexible CG with the learned preconditioner (see the FCG kernels above).  Vectors: r, p,
+// q in the FP32 workspace, z and K n in the FP64 scratch w (as floats); the iterate is e32.
 int tosimp::nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const float* b32,
                          float* e32, double tol, int maxit, int check_every, int* iters,
                          int* fallbacks, int* done) {
@@ -862,13 +921,15 @@ int tosimp::nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const floa
   Workspace& w = ctx->ws;
   float *r = w.r32, *p = w.p32, *q = w.q32, *z = (float*)w.w;
   const int n = (int)ctx->n_dof;
+  float* Kn = z + n;
   SolverState* st = w.st + 1;
   SolverState* sh = w.st_host + 1;
   *sh = SolverState{};
   sh->aux = tol * tol;
   sh->maxit = maxit < 1 ? 1 : maxit;
   TOSIMP_HIP(ctx, hipMemcpyAsync(st, sh, sizeof(SolverState), hipMemcpyHostToDevice, ctx->stream));
-  node_density_kernel<<<2048, 256, 0, ctx->stream>>>(x32, ctx->nx, ctx->ny, ctx->nz, S->rho_node);
+  node_density_kernel<float><<<2048, 256, 0, ctx->stream>>>(x32, ctx->nx, ctx->ny, ctx->nz,
+                                                           S->rho_node);
   TOSIMP_HIP(ctx, launch_fill_zero(ctx, e32, (int64_t)n * 4));
   double* part = w.partials;
   double* kvpart = w.partials + 2 * kMaxPartials;
@@ -881,10 +942,13 @@ int tosimp::nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const floa
     TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (sh->done) break;
     for (int i = 0; i < check_every; ++i) {
-      int rc = S->bf16 ? nn_apply_t<bf16_t>(ctx, S, r, z) : nn_apply_t<float>(ctx, S, r, z);
+      int rc = S->bf16 ? nn_precond_t<bf16_t>(ctx, S, x32, r, z, Kn, st, part, kvpart)
+                       : nn_precond_t<float>(ctx, S, x32, r, z, Kn, st, part, kvpart);
       if (rc) return rc;
       fcg_check_kernel<<<vb, 256, 0, ctx->stream>>>(r, z, q, n, st, part);
+      TOSIMP_HIP(ctx, launch_finalize_sum<2>(ctx->stream, part, vb, FcgCheckFin{st}));
       fcg_fallback_kernel<<<vb, 256, 0, ctx->stream>>>(r, z, q, w.dinv32, n, st, part);
+      TOSIMP_HIP(ctx, launch_finalize_sum<2>(ctx->stream, part, vb, FcgFallbackFin{st}));
       fcg_direction_kernel<<<vb, 256, 0, ctx->stream>>>(z, p, n, st);
       TOSIMP_HIP(ctx, hipGetLastError());
       if (mfma) {
@@ -982,7 +1046,6 @@ int tosimp_nn_create(tosimp_ctx* ctx, int base, int bf16) {
   A((void**)&S->rho_node, n0 * 4);
   A((void**)&S->scal, 64 * 8);
   A((void**)&S->part, 4096 * 8);
-  A((void**)&S->cnt, 64);
   if (e != hipSuccess) {
     nn_release(ctx);
     return tosimp_fail(ctx, TOSIMP_ENOMEM, "network workspace");
@@ -990,7 +1053,6 @@ int tosimp_nn_create(tosimp_ctx* ctx, int base, int bf16) {
   TOSIMP_HIP(ctx, hipMemsetAsync(S->m, 0, mo * 4, ctx->stream));
   TOSIMP_HIP(ctx, hipMemsetAsync(S->v, 0, mo * 4, ctx->stream));
   TOSIMP_HIP(ctx, hipMemsetAsync(S->master, 0, mo * 4, ctx->stream));
-  TOSIMP_HIP(ctx, hipMemsetAsync(S->cnt, 0, 64, ctx->stream));
   TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return TOSIMP_OK;
 }
@@ -1026,12 +1088,19 @@ int tosimp_nn_get_weights(tosimp_ctx* ctx, float* w_host, int64_t n) {
   return TOSIMP_OK;
 }
 
-// Nodal density from the element density (FP32); cached for the following applies.
-int tosimp_nn_set_density(tosimp_ctx* ctx, const float* x32) {
+// Nodal density from the element density (FP64 or FP32); kept for the following calls.
+int tosimp_nn_set_density(tosimp_ctx* ctx, const void* x, int xdtype) {
   if (!ctx) return TOSIMP_EINVAL;
   NNState* S = nn_of(ctx);
-  NN_REQUIRE(S && x32, TOSIMP_ESTATE, "no network or density");
-  node_density_kernel<<<2048, 256, 0, ctx->stream>>>(x32, ctx->nx, ctx->ny, ctx->nz, S->rho_node);
+  NN_REQUIRE(S, TOSIMP_ESTATE, "no network");
+  NN_REQUIRE(x && (xdtype == TOSIMP_F64 || xdtype == TOSIMP_F32), TOSIMP_EINVAL,
+             "bad density pointer or dtype");
+  if (xdtype == TOSIMP_F64)
+    node_density_kernel<double><<<2048, 256, 0, ctx->stream>>>((const double*)x, ctx->nx, ctx->ny,
+                                                                ctx->nz, S->rho_node);
+  else
+    node_density_kernel<float><<<2048, 256, 0, ctx->stream>>>((const float*)x, ctx->nx, ctx->ny,
+                                                               ctx->nz, S->rho_node);
   TOSIMP_HIP(ctx, hipGetLastError());
   return TOSIMP_OK;
 }
@@ -1041,6 +1110,30 @@ int tosimp_nn_apply(tosimp_ctx* ctx, const float* r, float* z) {
   NNState* S = nn_of(ctx);
   NN_REQUIRE(S && r && z && r != (const float*)z, TOSIMP_EINVAL, "bad arguments");
   return S->bf16 ? nn_apply_t<bf16_t>(ctx, S, r, z) : nn_apply_t<float>(ctx, S, r, z);
+}
+
+// The full preconditioner of the flexible CG (network, then the Jacobi stage) at the
+// element density x32 (FP32; also sets the nodal density and the FP32 Jacobi diagonal).
+// r, z: FP32 n_dof, distinct.  Uses the FP64 scratch vector w and solver slot 2.
+int tosimp_nn_precondition(tosimp_ctx* ctx, const float* x32, const float* r, float* z) {
+  if (!ctx) return TOSIMP_EINVAL;
+  NNState* S = nn_of(ctx);
+  NN_REQUIRE(S && x32 && r && z && r != (const float*)z, TOSIMP_EINVAL, "bad arguments");
+  Workspace& w = ctx->ws;
+  SolverState* st = w.st + 2;
+  w.st_host[2] = SolverState{};
+  TOSIMP_HIP(ctx, hipMemcpyAsync(st, w.st_host + 2, sizeof(SolverState), hipMemcpyHostToDevice,
+                                 ctx->stream));
+  TOSIMP_HIP(ctx, launch_diag_inv32(ctx, x32, w.dinv32));
+  node_density_kernel<float><<<2048, 256, 0, ctx->stream>>>(x32, ctx->nx, ctx->ny, ctx->nz,
+                                                           S->rho_node);
+  float* Kn = (float*)w.w;
+  double* kvpart = w.partials + 2 * kMaxPartials;
+  int rc = S->bf16 ? nn_precond_t<bf16_t>(ctx, S, x32, r, z, Kn, st, w.partials, kvpart)
+                   : nn_precond_t<float>(ctx, S, x32, r, z, Kn, st, w.partials, kvpart);
+  if (rc) return rc;
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TOSIMP_OK;
 }
 
 // Test hook: raw network on an FP32 channels-last [v0][4] input; out [v0][3] FP32.
@@ -1073,8 +1166,8 @@ int tosimp_nn_loss_grad(tosimp_ctx* ctx, const float* x4, const float* target3, 
   if (S->bf16) {
     pad_input_kernel<bf16_t><<<2048, 256, 0, ctx->stream>>>(x4, (bf16_t*)S->act[12], n0);
     TOSIMP_HIP(ctx, nn_forward<bf16_t>(ctx, S));
-    loss_kernel<bf16_t><<<1024, 256, 0, ctx->stream>>>((const bf16_t*)S->act[11], target3, ctx->ws.mask,
-                                                       n0, S->part, S->scal + 1, S->cnt + 1);
+    TOSIMP_HIP(ctx, launch_loss<bf16_t>(ctx->stream, (const bf16_t*)S->act[11], target3,
+                                        ctx->ws.mask, n0, S->part, S->scal + 1));
     loss_grad_kernel<bf16_t><<<2048, 256, 0, ctx->stream>>>((const bf16_t*)S->act[11], target3,
                                                             ctx->ws.mask, n0, S->scal + 1,
                                                             (bf16_t*)S->gbuf[0]);
@@ -1082,8 +1175,8 @@ int tosimp_nn_loss_grad(tosimp_ctx* ctx, const float* x4, const float* target3, 
   } else {
     pad_input_kernel<float><<<2048, 256, 0, ctx->stream>>>(x4, (float*)S->act[12], n0);
     TOSIMP_HIP(ctx, nn_forward<float>(ctx, S));
-    loss_kernel<float><<<1024, 256, 0, ctx->stream>>>((const float*)S->act[11], target3, ctx->ws.mask,
-                                                      n0, S->part, S->scal + 1, S->cnt + 1);
+    TOSIMP_HIP(ctx, launch_loss<float>(ctx->stream, (const float*)S->act[11], target3,
+                                       ctx->ws.mask, n0, S->part, S->scal + 1));
     loss_grad_kernel<float><<<2048, 256, 0, ctx->stream>>>((const float*)S->act[11], target3,
                                                            ctx->ws.mask, n0, S->scal + 1,
                                                            (float*)S->gbuf[0]);
@@ -1125,6 +1218,8 @@ int tosimp_nn_train_step(tosimp_ctx* ctx, const float* r_batch, const float* e_b
   a.eps = 1e-8f;
   a.c1 = (float)(1.0 - std::pow(0.9, S->adam_t));
   a.c2 = (float)(1.0 - std::pow(0.999, S->adam_t));
+  a.omb1 = (float)(1.0 - 0.9);
+  a.omb2 = (float)(1.0 - 0.999);
   // Adam step on the batch-mean gradient (the mean loss of the batch).
   scale_kernel<<<(int)((S->nparam + 255) / 256), 256, 0, ctx->stream>>>(gsum, (int)S->nparam,
                                                                        1.0f / (float)nb);

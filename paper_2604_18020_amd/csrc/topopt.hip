@@ -144,21 +144,25 @@ __global__ __launch_bounds__(kRedThreads) void oc_step_kernel(
   for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kRedThreads)
     s += dv[i] * oc_x(x[i], dc[i], dv[i], lmid, move);
-  const double bs = block_sum<kRedThreads>(s, sred);
-  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-  if (last_block_arrive(&oc->cnt[0], gridDim.x)) {
-    const double vol = sum_partials<kRedThreads>(partials, gridDim.x, 1, sred);
-    if (threadIdx.x == 0) {
-      oc->vol = vol;
-      oc->lmid = lmid;
-      if (vol > oc->target) oc->l1 = lmid;
-      else oc->l2 = lmid;
-      oc->steps += 1;
-      if (!((oc->l2 - oc->l1) / (oc->l1 + oc->l2) > 1e-3)) oc->done = 1;
-      oc->cnt[0] = 0u;
-    }
-  }
+  const double v[1] = {s};
+  store_block_sums<1>(v, partials, sred);
 }
+
+// The volume at lmid moves l1 or l2; stop once the bracket is 1e-3 relative.
+struct OcStepFin {
+  OcState* oc;
+  __device__ void operator()(const double* t) const {
+    if (oc->done) return;
+    const double lmid = 0.5 * (oc->l2 + oc->l1);
+    const double vol = t[0];
+    oc->vol = vol;
+    oc->lmid = lmid;
+    if (vol > oc->target) oc->l1 = lmid;
+    else oc->l2 = lmid;
+    oc->steps += 1;
+    if (!((oc->l2 - oc->l1) / (oc->l1 + oc->l2) > 1e-3)) oc->done = 1;
+  }
+};
 
 // x_new at the last evaluated multiplier and change = max |x_new - x|.
 __global__ __launch_bounds__(kRedThreads) void oc_final_kernel(
@@ -176,20 +180,18 @@ __global__ __launch_bounds__(kRedThreads) void oc_final_kernel(
   }
   const double bm = block_max<kRedThreads>(mx, sred);
   if (threadIdx.x == 0) partials[blockIdx.x] = bm;
-  if (last_block_arrive(&oc->cnt[1], gridDim.x)) {
-    const double tot = max_partials<kRedThreads>(partials, gridDim.x, 1, sred);
-    if (threadIdx.x == 0) {
-      oc->change = tot;
-      oc->cnt[1] = 0u;
-    }
-  }
 }
+
+struct OcChangeFin {
+  OcState* oc;
+  __device__ void operator()(const double* t) const { oc->change = t[0]; }
+};
 
 hipError_t launch_oc_step(const tosimp_ctx* c, const double* x, const double* dc,
                           const double* dv, double move, OcState* oc, double* partials) {
   oc_step_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(x, dc, dv, move, c->n_elem, oc,
                                                             partials);
-  return hipGetLastError();
+  return launch_finalize_sum<1>(c->stream, partials, kRedBlocks, OcStepFin{oc});
 }
 
 hipError_t launch_oc_final(const tosimp_ctx* c, const double* x, const double* dc,
@@ -197,7 +199,7 @@ hipError_t launch_oc_final(const tosimp_ctx* c, const double* x, const double* d
                            double* partials) {
   oc_final_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(x, dc, dv, move, c->n_elem, oc,
                                                              xnew, partials);
-  return hipGetLastError();
+  return launch_finalize_max(c->stream, partials, kRedBlocks, OcChangeFin{oc});
 }
 
 hipError_t launch_oc_init(const tosimp_ctx*, OcState*, double) { return hipSuccess; }

@@ -5,22 +5,22 @@
 // stop on the unpreconditioned ||r_k|| / ||f||) and Sec. "BF16 Arithmetic in the
 // Conjugate Gradient Solver" (refinement r = f - K u, e ~ K^-1 r, u += e).
 //
-// Every kernel uses a fixed grid (kRedBlocks x kRedThreads) and a grid-stride loop, so
-// each block's share of a reduction is fixed; block partials are summed by the last
-// block in index order.  Reductions are therefore bit-reproducible.  All dot products,
-// norms, alpha and beta are FP64 whatever the vector type.  Solver control lives in a
-// device SolverState: once `done` is set every later kernel of the batch returns at
-// once, so the host enqueues batches of iterations and polls only between batches.
+// Every kernel uses a fixed grid and a grid-stride loop, so each block's share of a
+// reduction is fixed; block partials are summed in block order by a one-block finalize
+// kernel.  Reductions are therefore bit-reproducible.  All dot products, norms, alpha
+// and beta are FP64 whatever the vector type.  Solver control lives in a device
+// SolverState: once `done` is set every later kernel of the batch returns at once, so
+// the host enqueues batches of iterations and polls only between batches.
 #include "common.h"
 #include "dev.h"
 
 namespace tosimp {
 
-// Streaming solver kernels use a fixed grid per mesh (about four 16-byte vectors per
-// thread, capped so the partial sums fit), hence a fixed reduction order.
+// Streaming solver kernels use a fixed grid per mesh (eight blocks per CU at most, a
+// few 16-byte vectors per thread), hence a fixed reduction order.
 static int vec_blocks(const tosimp_ctx* c) {
   const int64_t want = (c->n_dof + 8 * kRedThreads - 1) / (8 * kRedThreads);
-  return (int)(want < 1 ? 1 : (want > kMaxPartials / 2 ? kMaxPartials / 2 : want));
+  return (int)(want < 1 ? 1 : (want > 2048 ? 2048 : want));
 }
 
 // r = b - K u (masked), z = r * dinv, p = z; accumulates ||r||^2, <r,z>, ||b||^2.
@@ -45,30 +45,23 @@ __global__ __launch_bounds__(kRedThreads) void pcg_init_kernel(
     rz += (double)rv * (double)zv;
     bb += (double)bv * (double)bv;
   }
-  const double s0 = block_sum<kRedThreads>(rr, sred);
-  const double s1 = block_sum<kRedThreads>(rz, sred);
-  const double s2 = block_sum<kRedThreads>(bb, sred);
-  if (threadIdx.x == 0) {
-    partials[3 * blockIdx.x + 0] = s0;
-    partials[3 * blockIdx.x + 1] = s1;
-    partials[3 * blockIdx.x + 2] = s2;
-  }
-  if (last_block_arrive(&st->cnt[1], gridDim.x)) {
-    const double RR = sum_partials<kRedThreads>(partials + 0, gridDim.x, 3, sred);
-    const double RZ = sum_partials<kRedThreads>(partials + 1, gridDim.x, 3, sred);
-    const double BB = sum_partials<kRedThreads>(partials + 2, gridDim.x, 3, sred);
-    if (threadIdx.x == 0) {
-      st->rr = RR;
-      st->rz = RZ;
-      st->bb = BB;
-      st->tol2 = st->aux * BB;  // aux holds tol^2 on entry
-      st->iter = 0;
-      st->done = (BB == 0.0 || RR <= st->tol2) ? 1 : 0;
-      if (!finite_val(RR) || !finite_val(RZ)) st->done = 3;
-      st->cnt[1] = 0u;
-    }
-  }
+  const double v[3] = {rr, rz, bb};
+  store_block_sums<3>(v, partials, sred);
 }
+
+struct PcgInitFin {
+  SolverState* st;
+  __device__ void operator()(const double* t) const {
+    const double RR = t[0], RZ = t[1], BB = t[2];
+    st->rr = RR;
+    st->rz = RZ;
+    st->bb = BB;
+    st->tol2 = st->aux * BB;  // aux holds tol^2 on entry
+    st->iter = 0;
+    st->done = (BB == 0.0 || RR <= st->tol2) ? 1 : 0;
+    if (!finite_val(RR) || !finite_val(RZ)) st->done = 3;
+  }
+};
 
 // Vector width of the streaming kernels: 16 bytes per lane per array.
 template <typename T>
@@ -93,8 +86,8 @@ __device__ __forceinline__ void vset(typename Vec<T>::type& v, int k, T x) {
   reinterpret_cast<T*>(&v)[k] = x;
 }
 
-// u += alpha p, r -= alpha q; accumulates ||r||^2 and <r, r dinv>; the last block
-// counts the iteration, tests convergence and forms beta.  Flat over DOFs, 16 bytes per
+// u += alpha p, r -= alpha q; block sums of ||r||^2 and <r, r dinv> (PcgUpdateFin then
+// counts the iteration, tests convergence and forms beta).  Flat over DOFs, 16 bytes per
 // lane per array (the node of DOF i is i / 3; n_dof < 2^31, so 32-bit arithmetic).
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void pcg_update_kernel(
@@ -137,28 +130,26 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update_kernel(
       rz += (double)rn * (double)(rn * d);
     }
   }
-  const double s0 = block_sum<kRedThreads>(rr, sred);
-  const double s1 = block_sum<kRedThreads>(rz, sred);
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x + 0] = s0;
-    partials[2 * blockIdx.x + 1] = s1;
-  }
-  if (last_block_arrive(&st->cnt[1], gridDim.x)) {
-    const double RR = sum_partials<kRedThreads>(partials + 0, gridDim.x, 2, sred);
-    const double RZ = sum_partials<kRedThreads>(partials + 1, gridDim.x, 2, sred);
-    if (threadIdx.x == 0) {
-      st->iter += 1;
-      st->rr = RR;
-      const double beta = RZ / st->rz;
-      st->beta = beta;
-      st->rz = RZ;
-      if (!finite_val(RR) || !finite_val(beta)) st->done = 3;
-      else if (RR <= st->tol2) st->done = 1;
-      else if (st->iter >= st->maxit) st->done = 2;
-      st->cnt[1] = 0u;
-    }
-  }
+  const double v[2] = {rr, rz};
+  store_block_sums<2>(v, partials, sred);
 }
+
+// Counts the iteration, tests convergence and forms beta.
+struct PcgUpdateFin {
+  SolverState* st;
+  __device__ void operator()(const double* t) const {
+    if (st->done) return;
+    const double RR = t[0], RZ = t[1];
+    st->iter += 1;
+    st->rr = RR;
+    const double beta = RZ / st->rz;
+    st->beta = beta;
+    st->rz = RZ;
+    if (!finite_val(RR) || !finite_val(beta)) st->done = 3;
+    else if (RR <= st->tol2) st->done = 1;
+    else if (st->iter >= st->maxit) st->done = 2;
+  }
+};
 
 // p = r dinv + beta p, flat over DOFs, 16 bytes per lane.
 template <typename T>
@@ -190,15 +181,16 @@ hipError_t launch_pcg_init(const tosimp_ctx* c, const T* b, const T* Ku, T* r, T
                            const void* dinv, SolverState* st, double* partials, int use_Ku) {
   pcg_init_kernel<T><<<kRedBlocks, kRedThreads, 0, c->stream>>>(
       b, Ku, r, p, (const T*)dinv, c->ws.mask, c->n_dof, st, partials, use_Ku);
-  return hipGetLastError();
+  return launch_finalize_sum<3>(c->stream, partials, kRedBlocks, PcgInitFin{st});
 }
 
 template <typename T>
 hipError_t launch_pcg_update(const tosimp_ctx* c, T* u, T* r, const T* p, const T* q,
                              const void* dinv, SolverState* st, double* partials) {
-  pcg_update_kernel<T><<<vec_blocks(c), kRedThreads, 0, c->stream>>>(
-      u, r, p, q, (const T*)dinv, (int)c->n_dof, st, partials);
-  return hipGetLastError();
+  const int nb = vec_blocks(c);
+  pcg_update_kernel<T><<<nb, kRedThreads, 0, c->stream>>>(u, r, p, q, (const T*)dinv,
+                                                          (int)c->n_dof, st, partials);
+  return launch_finalize_sum<2>(c->stream, partials, nb, PcgUpdateFin{st});
 }
 
 template <typename T>
@@ -254,22 +246,20 @@ __global__ __launch_bounds__(kRedThreads) void residual64_kernel(
     r[i] = rv;
     rr += rv * rv;
   }
-  const double s0 = block_sum<kRedThreads>(rr, sred);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s0;
-  if (last_block_arrive(&st->cnt[2], gridDim.x)) {
-    const double RR = sum_partials<kRedThreads>(partials, gridDim.x, 1, sred);
-    if (threadIdx.x == 0) {
-      st->rr = RR;
-      st->cnt[2] = 0u;
-    }
-  }
+  const double v[1] = {rr};
+  store_block_sums<1>(v, partials, sred);
 }
+
+struct SetRr {
+  SolverState* st;
+  __device__ void operator()(const double* t) const { st->rr = t[0]; }
+};
 
 hipError_t launch_residual64(const tosimp_ctx* c, const double* b, const double* Ku,
                              double* r, double* partials, SolverState* st) {
   residual64_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(b, Ku, r, c->ws.mask,
                                                                c->n_dof, partials, st);
-  return hipGetLastError();
+  return launch_finalize_sum<1>(c->stream, partials, kRedBlocks, SetRr{st});
 }
 
 __global__ void scale_to32_kernel(const double* r, double inv_s, float* r32, int64_t n) {
@@ -331,22 +321,25 @@ __global__ __launch_bounds__(kRedThreads) void dot64_kernel(const double* __rest
   for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kRedThreads)
     s += a[i] * b[i];
-  const double bs = block_sum<kRedThreads>(s, sred);
-  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-  if (last_block_arrive(&st->cnt[2], gridDim.x)) {
-    const double tot = sum_partials<kRedThreads>(partials, gridDim.x, 1, sred);
-    if (threadIdx.x == 0) {
-      if (what == 0) st->aux = tot;
-      else st->rr = tot;
-      st->cnt[2] = 0u;
-    }
-  }
+  const double v[1] = {s};
+  store_block_sums<1>(v, partials, sred);
+  (void)st;
+  (void)what;
 }
+
+struct SetDot {
+  SolverState* st;
+  int what;
+  __device__ void operator()(const double* t) const {
+    if (what == 0) st->aux = t[0];
+    else st->rr = t[0];
+  }
+};
 
 hipError_t launch_dot64(const tosimp_ctx* c, const double* a, const double* b, int64_t n,
                         double* partials, SolverState* st, int what) {
   dot64_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(a, b, n, partials, st, what);
-  return hipGetLastError();
+  return launch_finalize_sum<1>(c->stream, partials, kRedBlocks, SetDot{st, what});
 }
 
 // ------------------------------------------------------------------ Lanczos
@@ -355,7 +348,7 @@ hipError_t launch_dot64(const tosimp_ctx* c, const double* a, const double* b, i
 __global__ __launch_bounds__(kRedThreads) void lanczos_update_kernel(
     double* __restrict__ w, const double* __restrict__ q, const double* __restrict__ qprev,
     const double* alpha_j, const double* beta_jm1, const double* __restrict__ s_node,
-    int64_t n_dof, double* partials, double* beta_j, unsigned* cnt) {
+    int64_t n_dof, double* partials) {
   __shared__ double sred[kRedThreads / 64];
   const double a = *alpha_j;
   const double bprev = beta_jm1 ? *beta_jm1 : 0.0;
@@ -369,25 +362,22 @@ __global__ __launch_bounds__(kRedThreads) void lanczos_update_kernel(
     w[i] = wv;
     ss += wv * wv;
   }
-  const double bs = block_sum<kRedThreads>(ss, sred);
-  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-  if (last_block_arrive(cnt, gridDim.x)) {
-    const double tot = sum_partials<kRedThreads>(partials, gridDim.x, 1, sred);
-    if (threadIdx.x == 0) {
-      *beta_j = sqrt(tot);
-      *cnt = 0u;
-    }
-  }
+  const double v[1] = {ss};
+  store_block_sums<1>(v, partials, sred);
 }
+
+struct SetSqrt {
+  double* out;
+  __device__ void operator()(const double* t) const { *out = sqrt(t[0]); }
+};
 
 hipError_t launch_lanczos_update(const tosimp_ctx* c, double* w, const double* q,
                                  const double* qprev, const double* alpha_j,
                                  const double* beta_jm1, const double* scale_node,
                                  double* partials, double* beta_j) {
   lanczos_update_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(
-      w, q, qprev, alpha_j, beta_jm1, scale_node, c->n_dof, partials, beta_j,
-      &c->ws.st[0].cnt[3]);
-  return hipGetLastError();
+      w, q, qprev, alpha_j, beta_jm1, scale_node, c->n_dof, partials);
+  return launch_finalize_sum<1>(c->stream, partials, kRedBlocks, SetSqrt{beta_j});
 }
 
 __global__ void lanczos_normalize_kernel(const double* w, const double* beta_j, double* qn,
@@ -440,27 +430,30 @@ __global__ __launch_bounds__(kRedThreads) void alpha_dot32_kernel(const float* _
   for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kRedThreads)
     s += (double)p[i] * (double)q[i];
-  const double bs = block_sum<kRedThreads>(s, sred);
-  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-  if (last_block_arrive(&st->cnt[0], gridDim.x)) {
-    const double tot = sum_partials<kRedThreads>(partials, gridDim.x, 1, sred);
-    if (threadIdx.x == 0) {
-      st->pq = tot;
-      if (!(tot > 0.0) || !finite_val(tot)) {
-        st->done = 3;
-        st->alpha = 0.0;
-      } else {
-        st->alpha = st->rz / tot;
-      }
-      st->cnt[0] = 0u;
+  const double v[1] = {s};
+  store_block_sums<1>(v, partials, sred);
+}
+
+// alpha = <r, z> / <p, K p> (breakdown when <p, K p> is not positive and finite).
+struct AlphaFin {
+  SolverState* st;
+  __device__ void operator()(const double* t) const {
+    if (st->done) return;
+    const double tot = t[0];
+    st->pq = tot;
+    if (!(tot > 0.0) || !finite_val(tot)) {
+      st->done = 3;
+      st->alpha = 0.0;
+    } else {
+      st->alpha = st->rz / tot;
     }
   }
-}
+};
 
 hipError_t launch_alpha_from_dot32(const tosimp_ctx* c, const float* p, const float* q,
                                    double* partials, SolverState* st) {
   alpha_dot32_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(p, q, c->n_dof, partials, st);
-  return hipGetLastError();
+  return launch_finalize_sum<1>(c->stream, partials, kRedBlocks, AlphaFin{st});
 }
 
 __global__ void sqrt_scalar_kernel(const SolverState* st, double* out) {

@@ -144,6 +144,26 @@ def test_apply_K_full_size_4p9M_sampled(prec):
     assert np.all(np.isfinite(y))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_K_full_size_repeatable(prec):
+    """Every output of every call is identical at 4.9M elements (deterministic owner
+    writes, no atomics).  Regression test for a store whose data registers were
+    overwritten before the store read them: a few outputs per call, at random places,
+    took the value of the next instruction."""
+    nx, ny, nz = 340, 170, 85
+    t, fixed, _ = gpu_problem(nx, ny, nz)
+    rho, v = si.random_density_and_vector(nx, ny, nz, seed=42)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    x, vd = dev(rho, dt), dev(v, dt)
+    y0 = t.apply_K(x, vd, prec=prec)
+    y = torch.empty_like(y0)
+    bad = []
+    for _ in range(12):
+        t.apply_K(x, vd, y, prec=prec)
+        bad.append(int((y != y0).sum()))
+    assert not any(bad), bad
+
+
 @pytest.mark.parametrize("prec,u", [("bf16_mfma", 2.0 ** -9), ("fp16_mfma", 2.0 ** -11)])
 @pytest.mark.parametrize("dims", [(16, 8, 8), (37, 19, 23), (2, 1, 3), (15, 14, 40)])
 def test_apply_K_mfma_within_rounding_bound(prec, u, dims):

@@ -154,7 +154,8 @@ def test_train_step_is_adam_on_mean_gradient():
         rn = np.linalg.norm(R[s].astype(np.float64))
         inp = np.concatenate([_to_oracle(R[s] / rn, grid, 3), rho[None]], axis=0)
         out, cache = nn.unet_forward(params, inp, BASE)
-        lo, dout = nn.rel_mse_loss(out, _to_oracle(E[s] / rn, grid, 3), _to_oracle(free, grid, 3))
+        en = np.linalg.norm(E[s].astype(np.float64))
+        lo, dout = nn.rel_mse_loss(out, _to_oracle(E[s] / en, grid, 3), _to_oracle(free, grid, 3))
         lsum += lo
         for k, v in nn.unet_backward(params, cache, dout, BASE).items():
             gsum[k] += v
@@ -170,7 +171,8 @@ def test_train_step_is_adam_on_mean_gradient():
     g_flat = np.abs(_flat(gmean))
     big = g_flat > 1e-3 * np.max(g_flat)  # weights whose gradient sign FP32 settles
     assert np.max(np.abs(d_gpu[big] - d_ref[big])) <= 1e-3 * lr
-    assert np.max(np.abs(d_gpu)) <= lr * (1 + 1e-5)
+    # no weight moves by more than lr (plus the FP32 rounding of the stored weight)
+    assert np.all(np.abs(d_gpu) <= lr * (1 + 1e-6) + 2.0 ** -23 * np.abs(w0))
 
 
 def test_weights_roundtrip_and_errors():
@@ -224,7 +226,7 @@ def _fcg_problem(nx=12, ny=6, nz=6, seed=7):
     return t, fixed, f, x
 
 
-def test_fcg_zero_network_falls_back_to_jacobi():
+def test_fcg_zero_network_is_jacobi_pcg():
     t, fixed, f, x = _fcg_problem()
     t.nn_create(16, bf16=True)
     t.nn_set_weights(np.zeros(t.nn_params, dtype=np.float32))
@@ -234,12 +236,31 @@ def test_fcg_zero_network_falls_back_to_jacobi():
     u2 = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
     s_j = t.pcg_solve(dev(x), dev(f), u2, precond="jacobi", **kw)
     t.close()
-    # z = N(r) = 0 is never a descent direction: every step takes the Jacobi fallback,
-    # and FCG with a fixed SPD preconditioner is PCG
-    assert s_nn["fallbacks"] == s_nn["iterations"]
-    assert s_nn["rc"] == 2  # TOSIMP_FALLBACK_USED
-    assert abs(s_nn["iterations"] - s_j["iterations"]) <= 2 * s_j["outer_iterations"]
+    # n = N(r) = 0 gives s = 0 and z = D^-1 r: flexible CG with the Jacobi preconditioner,
+    # which is PCG in exact arithmetic.  FCG's beta = -<z, q_prev> / <p_prev, q_prev> and
+    # PCG's <r, z> ratio round differently in FP32, so the counts drift apart a little.
+    assert s_nn["fallbacks"] == 0 and s_nn["rc"] == 0
+    assert abs(s_nn["iterations"] - s_j["iterations"]) <= 0.15 * s_j["iterations"]
     assert s_nn["true_rel_residual"] <= 1e-8
+
+
+@pytest.mark.parametrize("bf16,tol", [(False, 1e-4), (True, 5e-2)])
+def test_two_stage_preconditioner_matches_oracle(bf16, tol):
+    nx, ny, nz = 8, 6, 5
+    t, fixed, _, params = _net(nx, ny, nz, bf16=bf16)
+    rng = np.random.default_rng(12)
+    x = rng.uniform(0.05, 1.0, t.n_elem).astype(np.float32)
+    r = rng.standard_normal(t.n_dof).astype(np.float32)
+    r[fixed] = 0.0
+    z = t.nn_precondition(dev(x), dev(r)).cpu().numpy()
+    x64 = x.astype(np.float64)
+    fm = fem.fixed_mask(t.n_dof, fixed)
+    Kc = fem.constrain(fem.assemble_K(nx, ny, nz, fem.simp_modulus(x64, 1.0, 1e-9, 3.0),
+                                      fem.element_stiffness(0.3)), fm)
+    zo = nn.nn_two_stage_precondition(params, r.astype(np.float64), nn.node_density(x64, nx, ny, nz),
+                                      fm, lambda v: Kc @ v, Kc.diagonal(), base=BASE)
+    t.close()
+    assert rel(z, zo) <= tol
 
 
 def test_fcg_random_network_converges_to_direct_solution():

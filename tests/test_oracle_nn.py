@@ -128,3 +128,45 @@ def test_nn_preconditioner_masks_and_scales():
     z2 = nn.nn_precondition(params, 3.0 * r, rho, fixed, base=2)
     assert np.all(z1[fixed] == 0)
     assert np.allclose(z2, 3.0 * z1, rtol=1e-12, atol=0)  # homogeneous in ||r||
+
+
+def _small_system(seed=8):
+    nx, ny, nz = 5, 3, 3
+    rho = np.random.default_rng(seed).uniform(0.2, 1, nx * ny * nz)
+    K = fem.assemble_K(nx, ny, nz, fem.simp_modulus(rho, 1.0, 1e-9, 3.0), fem.element_stiffness(0.3))
+    fixed = fem.fixed_mask(K.shape[0], si.cantilever_fixed_dofs(nx, ny, nz))
+    Kc = fem.constrain(K, fixed)
+    r = np.random.default_rng(seed + 1).standard_normal(K.shape[0])
+    r[fixed] = 0.0
+    return Kc, fixed, r
+
+
+def test_two_stage_exact_correction_returns_solution():
+    Kc, fixed, r = _small_system()
+    e = np.linalg.solve(Kc.toarray(), r)
+    z = nn.two_stage(r, e, lambda v: Kc @ v, Kc.diagonal())
+    assert np.max(np.abs(z - e)) <= 1e-10 * np.max(np.abs(e))
+
+
+def test_two_stage_zero_correction_is_jacobi():
+    Kc, fixed, r = _small_system()
+    d = Kc.diagonal()
+    z = nn.two_stage(r, np.zeros_like(r), lambda v: Kc @ v, d)
+    assert np.array_equal(z, r / d)
+
+
+def test_two_stage_scale_invariant_and_energy_optimal():
+    Kc, fixed, r = _small_system()
+    rng = np.random.default_rng(3)
+    n = np.linalg.solve(Kc.toarray(), r) + 0.3 * rng.standard_normal(r.size)
+    n[fixed] = 0.0
+    A = lambda v: Kc @ v
+    z1 = nn.two_stage(r, n, A, Kc.diagonal())
+    z2 = nn.two_stage(r, 7.5 * n, A, Kc.diagonal())
+    assert np.allclose(z1, z2, rtol=1e-12, atol=1e-14)
+    # s minimises the energy norm of e - s n
+    e = np.linalg.solve(Kc.toarray(), r)
+    s = (r @ n) / (n @ (Kc @ n))
+    en = lambda c: (e - c * n) @ (Kc @ (e - c * n))
+    assert en(s) <= min(en(0.99 * s), en(1.01 * s))
+
