@@ -27,7 +27,7 @@
 
 namespace tosimp {
 
-constexpr int KBX = 16, KBY = 16;  // element columns per block (x, y)
+constexpr int KBX = 32, KBY = 8;  // element columns per block (x, y)
 
 template <typename T>
 struct KvC {
@@ -123,9 +123,10 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   constexpr int NXL = KBX + 1, NYL = KBY + 1, ROW = 3 * NXL, NPV = ROW * NYL;
   constexpr int NLD = (NPV + 255) / 256;
   constexpr int NE = KBX * KBY;
-  __shared__ T sv[NLD * 256];    // node plane (17 x 17 nodes x 3), masked; padded
+  __shared__ T sv[NLD * 256];    // node plane ((KBX+1) x (KBY+1) nodes x 3), masked; padded
   __shared__ T sr[NLD * 256];    // the same plane unmasked (fixed rows output y = v)
   __shared__ T sc[12 * NE];      // corner contributions, [corner*3 + c][element column]
+  __shared__ T so[2][NLD * 256]; // finished output planes (owned nodes), same layout as sv
   __shared__ double sred[4];
 
   const int bid = blockIdx.x;
@@ -154,6 +155,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   // Plane-load slots: flat LDS index f = jl*ROW + il*3 + c matches a contiguous row
   // segment of the interleaved vector, so consecutive threads read consecutive words.
   int voff[NLD], moff[NLD], gcomp[NLD];
+  unsigned ooff[NLD];
 #pragma unroll
   for (int s = 0; s < NLD; ++s) {
     const int f = tid + 256 * s;
@@ -164,6 +166,9 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     voff[s] = ok ? (3 * node + c) * (int)sizeof(T) : kOOB;
     moff[s] = ok ? node : kOOB;
     gcomp[s] = c;
+    // owned output slot: local node (il, jl) with 1 <= il <= KBX-1, 1 <= jl <= KBY-1
+    const bool own = ok && il >= 1 && il <= KBX - 1 && jl >= 1 && jl <= KBY - 1;
+    ooff[s] = own ? (unsigned)voff[s] : (unsigned)kOOB;
   }
   // Element column of this thread.
   const int ex = ex0 + lx, ey = ey0 + ly;
@@ -172,7 +177,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   // Node owned by this thread in the output phase: local (lx+1, ly+1).
   const int ni = ex0 + lx + 1, nj = ey0 + ly + 1;
   const bool owner = lx < KBX - 1 && ly < KBY - 1 && ni <= A.nx && nj <= A.ny;
-  const int yoff = owner ? 3 * (ni + NX1 * nj) * (int)sizeof(T) : kOOB;
+  const int sown = (ly + 1) * ROW + (lx + 1) * 3;  // this thread's owned node in so
   const int moffown = owner ? ni + NX1 * nj : kOOB;
 
   // Register ring of D planes in flight: the plane's values and BC bytes, the owned
@@ -212,9 +217,18 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
 
   // One z step at node plane p: stage the plane, transform the top face, and (when
   // ELEM) apply element layer p-1 and (when OUT) emit node plane p-1.
+  // Coalesced write of a finished output plane q from so[q & 1]: every thread stores its
+  // flat slots that hold an owned node (row segments of the interleaved vector).
+  auto store_plane = [&](int q) {
+    const T* src = so[q & 1];
+    const unsigned qoff = (unsigned)(vplane_bytes * q);
+#pragma unroll
+    for (int s = 0; s < NLD; ++s) buf_st(src[tid + 256 * s], ry, ooff[s] + qoff);
+  };
+
   auto step = [&](int p, T* v, uint8_t* m, uint8_t& mo, XT& xv, const T* tb, T* tt,
                   const T* vown, T* vnew, uint8_t mown, uint8_t& mnew, bool elem, bool out,
-                  int refill) {
+                  bool flush, int refill) {
     // Keep each step's instructions inside its own region: the scheduler must not hoist
     // a later step's use of a ring slot above this step (that would wait on a fresh load).
     __builtin_amdgcn_sched_barrier(0);
@@ -230,6 +244,8 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     mnew = mo;
     __syncthreads();
     issue(v, m, mo, xv, refill);
+    // The output plane finished in the previous step (p - 2) leaves in coalesced rows.
+    if (flush) store_plane(p - 2);
     __builtin_amdgcn_sched_barrier(0);
 
     // Forward 2D transform of the top face (plane p) of this element column.
@@ -304,13 +320,15 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     // before the next step overwrites them.
     __syncthreads();
     if (elem && out) {
-      const int soff = vplane_bytes * (p - 1);
+      // Node plane p-1: sum the four element columns around the owned node into so; the
+      // next step stores it (after its first barrier).
+      T* dst = so[(p - 1) & 1];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         T yv = (sc[(9 + c) * NE + tid] + sc[(6 + c) * NE + tid + 1]) +
                (sc[(3 + c) * NE + tid + KBX] + sc[(0 + c) * NE + tid + KBX + 1]);
         yv = bit_select(yv, vown[c], (mown >> c) & 1);  // fixed rows are identity: y = v
-        buf_st(yv, ry, (unsigned)yoff + (unsigned)(c * (int)sizeof(T)) + (unsigned)soff);
+        if (owner) dst[sown + c] = yv;
         if constexpr (DOT) dotacc += owner ? (double)vown[c] * (double)yv : 0.0;
       }
     }
@@ -329,11 +347,14 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     const int refill = min(p + D, k1);
     if (i % 2 == 0)
       step(p, pv[i % D], pm[i % D], po[i % D], px[i % D], TA, TB, VA, VB, MA, MB, i >= 1,
-           i >= 2, refill);
+           i >= 2, i >= 3, refill);
     else
       step(p, pv[i % D], pm[i % D], po[i % D], px[i % D], TB, TA, VB, VA, MB, MA, i >= 1,
-           i >= 2, refill);
+           i >= 2, i >= 3, refill);
   }
+  // The last output plane (k1 - 1, finished in the final step).
+  __syncthreads();
+  store_plane(k1 - 1);
 
   if constexpr (DOT) {
     const double bsum = block_sum<256>(dotacc, sred);
