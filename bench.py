@@ -165,6 +165,113 @@ def time_nn(workload="cantilever_200x100x50", simp_iters=10, per_solve=200, ever
     return out
 
 
+def _problem(workload):
+    import torch
+
+    import synth_inputs as si
+    from paper_2604_18020_amd import Tosimp
+
+    cfg = si.CONFIGS[workload]
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+    t = Tosimp(0).set_mesh(nx, ny, nz)
+    if cfg["kind"] == "cantilever":
+        fixed, f = si.cantilever_fixed_dofs(nx, ny, nz), si.cantilever_load(nx, ny, nz)
+    else:
+        fixed, f = si.torsion_fixed_dofs(nx, ny, nz), si.torsion_load(nx, ny, nz)
+    t.set_bcs(fixed)
+    fd = torch.tensor(f, device="cuda:0")
+    t.set_loads(fd)
+    return t, cfg, fd, fixed
+
+
+def precision_study(workload="cantilever_340x170x85", lanczos_steps=400, tol=1e-6):
+    """Condition estimate (Lanczos, FP64) at uniform density, the precision rule
+    u_l kappa < 1 for each inner precision, and refinement solves with FP32, BF16-MFMA and
+    FP16-MFMA inner operators (rule not enforced, to show the outcome), each compared with
+    an FP64 solve to 1e-10 in compliance, displacement and sensitivity."""
+    import numpy as np
+    import torch
+
+    from paper_2604_18020_amd import tridiag_extremes
+
+    t, cfg, f, fixed = _problem(workload)
+    x = torch.full((t.n_elem,), cfg["volfrac"], dtype=torch.float64, device="cuda:0")
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(t.n_dof)
+    v[fixed] = 0.0  # the Krylov space stays in the free block
+    v0 = torch.tensor(v, device="cuda:0")
+    out = {"workload": workload, "density": cfg["volfrac"]}
+    for scaled in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a, b = t.lanczos(x, v0, lanczos_steps, jacobi_scaled=scaled)
+        lo, hi = tridiag_extremes(a, b)
+        out["lanczos_jacobi" if scaled else "lanczos"] = {
+            "steps": int(len(a)), "lambda_min": lo, "lambda_max": hi, "kappa": hi / lo,
+            "seconds": time.perf_counter() - t0}
+    kappa = out["lanczos_jacobi"]["kappa"]
+    u = {"fp32": 2.0 ** -24, "bf16_mfma": 2.0 ** -8, "fp16_mfma": 2.0 ** -11}
+    out["rule"] = {k: {"unit_roundoff": v, "u_kappa": v * kappa, "allowed": v * kappa < 1}
+                   for k, v in u.items()}
+    u_ref, ref = _solve_timed(t, x, f, 1e-10, mode="plain_fp64", check_every=64)
+    dc_ref, c_ref = t.sensitivity(x, u_ref)
+    dcn = float(torch.max(torch.abs(dc_ref)))
+    un = float(torch.linalg.vector_norm(u_ref))
+    runs = [("plain_fp64", dict(mode="plain_fp64", check_every=64))]
+    runs += [(f"ir_{p}", dict(mode="ir", inner_prec=p, inner_tol=1e-4, max_outer=12,
+                              check_every=64)) for p in ("fp32", "bf16_mfma", "fp16_mfma")]
+    for name, kw in runs:
+        try:
+            uu, r = _solve_timed(t, x, f, tol, **kw)
+        except Exception as e:  # a refused or broken-down solve is a result too
+            out[name] = {"error": str(e)}
+            continue
+        dc, c = t.sensitivity(x, uu)
+        r["compliance_rel_err"] = abs(c - c_ref) / abs(c_ref)
+        r["displacement_rel_err"] = float(torch.linalg.vector_norm(uu - u_ref)) / un
+        r["sensitivity_max_rel_err"] = float(torch.max(torch.abs(dc - dc_ref))) / dcn
+        out[name] = r
+    out["reference"] = {"tol": 1e-10, "iterations": ref["iterations"], "compliance": c_ref}
+    t.close()
+    return out
+
+
+def simp_study(workload, iters=None, tol=None):
+    """SIMP iterations from uniform density with warm-started solves: plain FP64
+    Jacobi-PCG against FP64 refinement around FP32 Jacobi-PCG (same tolerance)."""
+    import torch
+
+    t, cfg, f, _ = _problem(workload)
+    iters = iters or cfg["simp_iters"]
+    tol = tol or cfg["pcg_tol"]
+    out = {"workload": workload, "iterations": iters, "tol": tol}
+    finals = {}
+    for name, kw in [("plain_fp64", dict(mode="plain_fp64")),
+                     ("ir_fp32", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4))]:
+        x = torch.full((t.n_elem,), cfg["volfrac"], dtype=torch.float64, device="cuda:0")
+        xp = x.clone()
+        u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+        comp, its = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            st = t.simp_step(x, xp, u, volfrac=cfg["volfrac"], move=0.2, tol=tol, maxit=50000,
+                             check_every=64, **kw)
+            comp.append(st["compliance"])
+            its.append(st["solve"]["iterations"])
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.perf_counter() - t0, "compliance": comp,
+                     "cg_iterations": its, "total_cg_iterations": int(sum(its))}
+        finals[name] = xp.clone()
+    out["speedup_ir_over_plain"] = out["plain_fp64"]["seconds"] / out["ir_fp32"]["seconds"]
+    c0, c1 = out["plain_fp64"]["compliance"], out["ir_fp32"]["compliance"]
+    out["max_compliance_rel_diff"] = max(abs(a - b) / abs(a) for a, b in zip(c0, c1))
+    out["final_density_max_diff"] = float(torch.max(torch.abs(finals["plain_fp64"] -
+                                                              finals["ir_fp32"])))
+    t.close()
+    return out
+
+
 def cpu_baseline(budget_s=20.0):
     """The oracle's element-by-element K v (gather, dense 24x24 product, scatter-add)
     on the 120x60x30 mesh, repeated until ~budget_s of CPU time."""
@@ -206,6 +313,9 @@ def main():
     ap.add_argument("--pcg-tol", type=float, default=1e-6)
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-nn", action="store_true", help="skip the learned-preconditioner leg")
+    ap.add_argument("--suite", action="store_true",
+                    help="instead of the benchmark line: precision study (340x170x85) and "
+                         "SIMP runs (120x60x30, torsion 55x55x165), one JSON line each")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for scaling profiler byte counters)")
@@ -219,6 +329,12 @@ def main():
 
     import synth_inputs as si
     from paper_2604_18020_amd import Tosimp
+
+    if a.suite:
+        print(json.dumps({"precision_study": precision_study()}), flush=True)
+        print(json.dumps({"simp_study": simp_study("cantilever_120x60x30")}), flush=True)
+        print(json.dumps({"simp_study": simp_study("torsion_55x55x165")}), flush=True)
+        return
 
     cfg = si.CONFIGS[a.workload]
     nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]

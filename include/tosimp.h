@@ -221,8 +221,9 @@ int tosimp_tridiag_extremes(const double* alpha, const double* beta, int m, doub
  * ReLU 0.01), head b->3 (1x1x1, linear); nearest up-sampling; no biases.
  * Weights: FP32 master copy in [layer][c_out][c_in][kz][ky][kx] order (layers as
  * listed), compute copies in BF16 (bf16 = 1) or FP32.  Training: Adam (0.9, 0.999,
- * 1e-8) on the relative masked loss sum_free (N - t)^2 / sum_free t^2 with the target
- * direction t = e / ||e||: flexible CG does not depend on the scale of z.
+ * 1e-8) on the relative masked loss sum_free (N - t)^2 / sum_free t^2 with the unit-RMS
+ * target t = e sqrt(n_dof) / ||e|| (flexible CG does not depend on the scale of z); the
+ * residual input enters at unit RMS, r sqrt(n_dof) / ||r||.
  *
  * tosimp_nn_create: build the network for the current mesh (base 16 or 32); weights
  *   are zero until set.  Replaces an existing network.  Allocates its workspace.
@@ -232,10 +233,10 @@ int tosimp_tridiag_extremes(const double* alpha, const double* beta, int m, doub
  * tosimp_nn_set_density: nodal density (mean of the adjacent elements) from an element
  *   density on the device (xdtype TOSIMP_F64 or TOSIMP_F32); used by apply and
  *   train_step until the next call.
- * tosimp_nn_apply: z = ||r|| N(r/||r||, rho_node), zero on fixed DOFs (FP32 device
- *   vectors, n_dof; r and z must not alias).
+ * tosimp_nn_apply: z = (||r|| / sqrt(n_dof)) N(r sqrt(n_dof) / ||r||, rho_node), zero on
+ *   fixed DOFs (FP32 device vectors, n_dof; r and z must not alias).
  * tosimp_nn_precondition: the preconditioner flexible CG applies, at element density
- *   x32 (FP32 device): n = ||r|| N(r/||r||, rho_node), s = <r,n>/<n,K n> (0 unless
+ *   x32 (FP32 device): n = tosimp_nn_apply(r), s = <r,n>/<n,K n> (0 unless
  *   both are positive), z = s n + D^-1 (r - s K n), D the Jacobi diagonal of K_c(x32).
  *   Sets the nodal density.  r, z: FP32 device n_dof, distinct.  Synchronises.
  * tosimp_nn_forward: test hook, raw network output [n_node][3] FP32 for a channels-last

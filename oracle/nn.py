@@ -263,15 +263,18 @@ def node_density(xphys: np.ndarray, nx: int, ny: int, nz: int) -> np.ndarray:
 
 def nn_precondition(params, r: np.ndarray, rho_node: np.ndarray, fixed_mask: np.ndarray,
                     base=16) -> np.ndarray:
-    """z = ||r|| N([r / ||r||, rho_node]) on the node grid, zero on fixed DOFs."""
+    """z = (||r|| / sqrt(n)) N([r sqrt(n) / ||r||, rho_node]) on the node grid (n = r.size:
+    the residual channels enter at unit RMS, the scale of the density channel), zero on
+    fixed DOFs.  Homogeneous of degree one in r."""
     D, H, W_ = rho_node.shape
     rn = np.linalg.norm(r)
     if rn == 0:
         return np.zeros_like(r)
-    rr = (r / rn).reshape(D, H, W_, 3).transpose(3, 0, 1, 2)
+    g = np.sqrt(r.size) / rn
+    rr = (r * g).reshape(D, H, W_, 3).transpose(3, 0, 1, 2)
     inp = np.concatenate([rr, rho_node[None]], axis=0)
     out, _ = unet_forward(params, inp, base)
-    z = out.transpose(1, 2, 3, 0).reshape(-1) * rn
+    z = out.transpose(1, 2, 3, 0).reshape(-1) / g
     z[fixed_mask] = 0.0
     return z
 

@@ -471,7 +471,8 @@ int run_pcg(tosimp_ctx* ctx, int prec, const void* x, int xdtype, const T* b, T*
     TOSIMP_HIP(ctx, launch_fill_zero(ctx, u, ctx->n_dof * (int64_t)sizeof(T)));
     TOSIMP_HIP(ctx, launch_pcg_init<T>(ctx, b, nullptr, r, p, dinv, st, part, 0));
   } else {
-    TOSIMP_HIP(ctx, kv_launch(ctx, prec, xdtype, x, u, q, nullptr, st, nullptr, 0, false));
+    // u was masked on entry to the solve; every CG vector stays zero on fixed DOFs
+    TOSIMP_HIP(ctx, kv_launch(ctx, prec, xdtype, x, u, q, nullptr, st, nullptr, 0, false, true));
     TOSIMP_HIP(ctx, launch_pcg_init<T>(ctx, b, q, r, p, dinv, st, part, 1));
   }
   const bool mfma = prec == TOSIMP_PREC_BF16_MFMA || prec == TOSIMP_PREC_FP16_MFMA;
@@ -496,7 +497,7 @@ int run_pcg(tosimp_ctx* ctx, int prec, const void* x, int xdtype, const T* b, T*
                                        true));
         TOSIMP_HIP(ctx, launch_alpha_from_dot32(ctx, (const float*)p, (const float*)q, kvpart, st));
       } else {
-        TOSIMP_HIP(ctx, kv_launch(ctx, prec, xdtype, x, p, q, kvpart, st, nullptr, 1, true));
+        TOSIMP_HIP(ctx, kv_launch(ctx, prec, xdtype, x, p, q, kvpart, st, nullptr, 1, true, true));
       }
       TOSIMP_HIP(ctx, launch_pcg_update<T>(ctx, u, r, p, q, dinv, st, part));
       TOSIMP_HIP(ctx, launch_pcg_direction<T>(ctx, r, p, dinv, st));
@@ -525,7 +526,7 @@ int true_residual(tosimp_ctx* ctx, const double* x, const double* b, const doubl
   Workspace& w = ctx->ws;
   SolverState* st = w.st + 2;
   TOSIMP_HIP(ctx, kv_launch(ctx, TOSIMP_PREC_FP64, TOSIMP_F64, x, u, w.q, nullptr, st, nullptr,
-                            0, false));
+                            0, false, true));
   TOSIMP_HIP(ctx, launch_residual64(ctx, b, w.q, w.r, w.partials, st));
   TOSIMP_HIP(ctx, hipMemcpyAsync(w.st_host + 2, st, sizeof(SolverState), hipMemcpyDeviceToHost,
                                  ctx->stream));

@@ -125,10 +125,11 @@ namespace tosimp {
 
 // Operator kernels (kv.hip, kv_mfma.hip).  kv_launch: y = K_c(x) v with an optional
 // fused <v, y> finished into st (FIN_ALPHA) or *out (FIN_SCALAR); guarded launches
-// return at once when st->done is set.
+// return at once when st->done is set; premasked: the caller guarantees v = 0 on fixed
+// DOFs (then the plane BC bytes are not read).
 hipError_t kv_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
                      const void* v, void* y, double* partials, SolverState* st,
-                     double* out, int fin, bool guarded);
+                     double* out, int fin, bool guarded, bool premasked = false);
 hipError_t kv_mfma_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
                           const float* v, float* y, SolverState* st, bool guarded);
 hipError_t launch_apply_K(const tosimp_ctx* c, int prec, int xdtype, const void* x,

@@ -118,7 +118,10 @@ __device__ __forceinline__ double bit_select(double a, double b, unsigned sel) {
                                         (__builtin_bit_cast(unsigned long long, b) & m));
 }
 
-template <typename T, typename XT, bool P3, bool DOT, int D, int KZMAX>
+// PM: v is known to be zero on fixed DOFs (every vector the CG iterations apply K_c to
+// is), so the plane's BC bytes are not loaded and v needs no masking; only the owned
+// node's BC byte is read (fixed rows output y = v = 0).
+template <typename T, typename XT, bool P3, bool DOT, bool PM, int D, int KZMAX>
 __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   constexpr int NXL = KBX + 1, NYL = KBY + 1, ROW = 3 * NXL, NPV = ROW * NYL;
   constexpr int NLD = (NPV + 255) / 256;
@@ -193,7 +196,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     const int kc = min(max(k, 0), A.nz);
 #pragma unroll
     for (int s = 0; s < NLD; ++s) {
-      m[s] = buf_ld_u8(rm, moff[s], plane * kc);
+      if constexpr (!PM) m[s] = buf_ld_u8(rm, moff[s], plane * kc);
       v[s] = buf_ld<T>(rv, voff[s], vplane_bytes * kc);
     }
     mo = buf_ld_u8(rm, moffown, plane * kc);
@@ -237,8 +240,12 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
 #pragma unroll
     for (int s = 0; s < NLD; ++s) {
       const int f = tid + 256 * s;
-      sv[f] = (((m[s] | force) >> gcomp[s]) & 1) ? T(0) : v[s];
-      sr[f] = v[s];
+      if constexpr (PM) {
+        sv[f] = force ? T(0) : v[s];
+      } else {
+        sv[f] = (((m[s] | force) >> gcomp[s]) & 1) ? T(0) : v[s];
+        sr[f] = v[s];
+      }
     }
     const XT xcur = xv;
     mnew = mo;
@@ -262,7 +269,8 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
       tt[3 * 3 + c] = b1 - a1;
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) vnew[c] = sr[(ly + 1) * ROW + (lx + 1) * 3 + c];
+    for (int c = 0; c < 3; ++c) vnew[c] = PM ? sv[(ly + 1) * ROW + (lx + 1) * 3 + c]
+                                              : sr[(ly + 1) * ROW + (lx + 1) * 3 + c];
 
     if (elem) {
       // ---- element layer ez = p - 1: bottom face tb, top face tt -------------
@@ -391,17 +399,17 @@ constexpr int kv_depth() { return sizeof(T) == 8 ? 2 : 4; }
 template <typename T>
 constexpr int kv_kzmax() { return sizeof(T) == 8 ? 24 : 16; }
 
-template <typename T, typename XT, bool P3, bool DOT>
+template <typename T, typename XT, bool P3, bool DOT, bool PM>
 __global__ __launch_bounds__(256) void kv_stream(KvArgs<T, XT> A) {
-  kv_body<T, XT, P3, DOT, kv_depth<T>(), kv_kzmax<T>()>(A);
+  kv_body<T, XT, P3, DOT, PM, kv_depth<T>(), kv_kzmax<T>()>(A);
 }
 
 // Solver variant: skips the whole operator once the solve has finished, so batches of
 // iterations can be enqueued without a host round trip per iteration.
-template <typename T, typename XT, bool P3, bool DOT>
+template <typename T, typename XT, bool P3, bool DOT, bool PM>
 __global__ __launch_bounds__(256) void kv_stream_guarded(KvArgs<T, XT> A) {
   if (A.st->done) return;
-  kv_body<T, XT, P3, DOT, kv_depth<T>(), kv_kzmax<T>()>(A);
+  kv_body<T, XT, P3, DOT, PM, kv_depth<T>(), kv_kzmax<T>()>(A);
 }
 
 // ------------------------------------------------------------------ host side
@@ -477,9 +485,9 @@ static int resident_blocks(const tosimp_ctx* c, K kernel) {
   return per_cu * num_cus(c);
 }
 
-template <typename T, typename XT, bool P3, bool DOT>
+template <typename T, typename XT, bool P3, bool DOT, bool PM>
 static hipError_t kv_launch_v(const tosimp_ctx* c, KvArgs<T, XT> A, bool guarded) {
-  auto kern = guarded ? kv_stream_guarded<T, XT, P3, DOT> : kv_stream<T, XT, P3, DOT>;
+  auto kern = guarded ? kv_stream_guarded<T, XT, P3, DOT, PM> : kv_stream<T, XT, P3, DOT, PM>;
   static int resident[2] = {0, 0};
   int& res = resident[guarded ? 1 : 0];
   if (res == 0) res = resident_blocks(c, kern);
@@ -495,7 +503,7 @@ static hipError_t kv_launch_v(const tosimp_ctx* c, KvArgs<T, XT> A, bool guarded
                                 KvDotFin{A.st, A.out, A.fin, guarded ? 1 : 0});
 }
 
-template <typename T, typename XT>
+template <typename T, typename XT, bool PM>
 static hipError_t kv_launch_t(const tosimp_ctx* c, const XT* x, const T* v, T* y,
                               double* partials, SolverState* st, double* out, int fin,
                               bool guarded) {
@@ -507,27 +515,34 @@ static hipError_t kv_launch_t(const tosimp_ctx* c, const XT* x, const T* v, T* y
   A.k = kv_consts<T>(c);
   const bool p3 = c->penal == 3.0;
   const bool dot = fin != FIN_NONE;
-  if (p3 && dot) return kv_launch_v<T, XT, true, true>(c, A, guarded);
-  if (p3) return kv_launch_v<T, XT, true, false>(c, A, guarded);
-  if (dot) return kv_launch_v<T, XT, false, true>(c, A, guarded);
-  return kv_launch_v<T, XT, false, false>(c, A, guarded);
+  if (p3 && dot) return kv_launch_v<T, XT, true, true, PM>(c, A, guarded);
+  if (p3) return kv_launch_v<T, XT, true, false, PM>(c, A, guarded);
+  if (dot) return kv_launch_v<T, XT, false, true, PM>(c, A, guarded);
+  return kv_launch_v<T, XT, false, false, PM>(c, A, guarded);
 }
 
 hipError_t kv_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
                      const void* v, void* y, double* partials, SolverState* st,
-                     double* out, int fin, bool guarded) {
+                     double* out, int fin, bool guarded, bool premasked) {
   if (prec == TOSIMP_PREC_FP64) {
-    if (xdtype == TOSIMP_F64)
-      return kv_launch_t<double, double>(c, (const double*)x, (const double*)v, (double*)y,
-                                         partials, st, out, fin, guarded);
-    return kv_launch_t<double, float>(c, (const float*)x, (const double*)v, (double*)y,
-                                      partials, st, out, fin, guarded);
+    if (xdtype == TOSIMP_F64) {
+      if (premasked)
+        return kv_launch_t<double, double, true>(c, (const double*)x, (const double*)v,
+                                                 (double*)y, partials, st, out, fin, guarded);
+      return kv_launch_t<double, double, false>(c, (const double*)x, (const double*)v,
+                                                (double*)y, partials, st, out, fin, guarded);
+    }
+    return kv_launch_t<double, float, false>(c, (const float*)x, (const double*)v, (double*)y,
+                                             partials, st, out, fin, guarded);
   }
   if (xdtype == TOSIMP_F64)
-    return kv_launch_t<float, double>(c, (const double*)x, (const float*)v, (float*)y,
-                                      partials, st, out, fin, guarded);
-  return kv_launch_t<float, float>(c, (const float*)x, (const float*)v, (float*)y, partials,
-                                   st, out, fin, guarded);
+    return kv_launch_t<float, double, false>(c, (const double*)x, (const float*)v, (float*)y,
+                                             partials, st, out, fin, guarded);
+  if (premasked)
+    return kv_launch_t<float, float, true>(c, (const float*)x, (const float*)v, (float*)y,
+                                           partials, st, out, fin, guarded);
+  return kv_launch_t<float, float, false>(c, (const float*)x, (const float*)v, (float*)y,
+                                          partials, st, out, fin, guarded);
 }
 
 // ------------------------------------------------------------ Jacobi diagonal

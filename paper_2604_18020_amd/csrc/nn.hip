@@ -264,7 +264,8 @@ __global__ void conv_wgrad_reduce(const float* part, int nchunk, int n, float* g
 template <typename ST>
 __global__ void build_input_kernel(const float* r, const double* rnorm2, const float* rho_node,
                                    ST* inp, int n_node) {
-  const float inv = (float)(1.0 / sqrt(fmax(*rnorm2, 1e-300)));
+  // residual at unit RMS per DOF: r sqrt(n_dof) / ||r||
+  const float inv = (float)(sqrt(3.0 * n_node) / sqrt(fmax(*rnorm2, 1e-300)));
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n_node; v += gridDim.x * blockDim.x) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) inp[8 * v + c] = from_f<ST>(r[3 * v + c] * inv);
@@ -410,7 +411,7 @@ __global__ void loss_grad_kernel(const ST* out, const float* e, const uint8_t* m
 template <typename ST>
 __global__ void output_kernel(const ST* out, const uint8_t* mask, const double* rnorm2, float* z,
                               int n_node) {
-  const float s = (float)sqrt(*rnorm2);
+  const float s = (float)(sqrt(*rnorm2) / sqrt(3.0 * n_node));  // ||r|| / sqrt(n_dof)
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n_node; v += gridDim.x * blockDim.x) {
     const uint8_t mk = mask[v];
 #pragma unroll
@@ -841,7 +842,7 @@ hipError_t launch_norm2f(hipStream_t s, const float* r, int n, double* partials,
 }
 
 __global__ void scale_target_kernel(const float* e, const double* enorm2, float* out, int n) {
-  const float inv = (float)(1.0 / sqrt(fmax(*enorm2, 1e-300)));
+  const float inv = (float)(sqrt((double)n) / sqrt(fmax(*enorm2, 1e-300)));  // unit RMS
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     out[i] = e[i] * inv;
 }
@@ -863,7 +864,8 @@ int nn_apply_t(tosimp_ctx* ctx, NNState* S, const float* r, float* z) {
   return TOSIMP_OK;
 }
 
-// One sample: forward on (r / ||r||, rho), loss against e / ||e||, backward; the sample's
+// One sample: forward on (r, rho) with r at unit RMS, loss against e at unit RMS,
+// backward; the sample's
 // gradient is stored or added to gacc.
 template <typename ST>
 int nn_sample_grad(tosimp_ctx* ctx, NNState* S, const float* r, const float* e, float* tgt,
@@ -871,8 +873,8 @@ int nn_sample_grad(tosimp_ctx* ctx, NNState* S, const float* r, const float* e, 
   const int nn = (int)ctx->n_node;
   TOSIMP_HIP(ctx, launch_norm2f(ctx->stream, r, (int)ctx->n_dof, S->part, S->scal));
   build_input_kernel<ST><<<2048, 256, 0, ctx->stream>>>(r, S->scal, S->rho_node, (ST*)S->act[12], nn);
-  // Target direction e / ||e||: flexible CG is invariant to the scale of z, and the
-  // unit-norm target matches the scale of the unit-norm input.
+  // Target e sqrt(n_dof) / ||e|| (unit RMS, the scale of the inputs): flexible CG does
+  // not depend on the scale of z.
   TOSIMP_HIP(ctx, launch_norm2f(ctx->stream, e, (int)ctx->n_dof, S->part, S->scal + 3));
   scale_target_kernel<<<2048, 256, 0, ctx->stream>>>(e, S->scal + 3, tgt, (int)ctx->n_dof);
   TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S));
@@ -903,7 +905,7 @@ int nn_precond_t(tosimp_ctx* ctx, NNState* S, const float* x32, const float* r, 
   int rc = nn_apply_t<ST>(ctx, S, r, z);
   if (rc) return rc;
   TOSIMP_HIP(ctx, kv_launch(ctx, TOSIMP_PREC_FP32, TOSIMP_F32, x32, z, Kn, kvpart, st,
-                            &st->s_nkn, 2, true));
+                            &st->s_nkn, 2, true, true));
   dot_rn_kernel<<<vb, 256, 0, ctx->stream>>>(r, z, n, st, part);
   TOSIMP_HIP(ctx, launch_finalize_sum<1>(ctx->stream, part, vb, SetRn{st}));
   two_stage_kernel<<<vb, 256, 0, ctx->stream>>>(r, Kn, ctx->ws.dinv32, z, n, st);
@@ -956,7 +958,7 @@ int tosimp::nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const floa
         TOSIMP_HIP(ctx, launch_alpha_from_dot32(ctx, p, q, kvpart, st));
       } else {
         TOSIMP_HIP(ctx, kv_launch(ctx, TOSIMP_PREC_FP32, TOSIMP_F32, x32, p, q, kvpart, st,
-                                  nullptr, 1, true));
+                                  nullptr, 1, true, true));
       }
       TOSIMP_HIP(ctx, launch_pcg_update<float>(ctx, e32, r, p, q, w.dinv32, st, part));
     }

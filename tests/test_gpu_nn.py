@@ -151,11 +151,11 @@ def test_train_step_is_adam_on_mean_gradient():
     gsum = {k: np.zeros_like(v) for k, v in params.items()}
     lsum = 0.0
     for s in range(nb):
-        rn = np.linalg.norm(R[s].astype(np.float64))
-        inp = np.concatenate([_to_oracle(R[s] / rn, grid, 3), rho[None]], axis=0)
+        g = np.sqrt(t.n_dof) / np.linalg.norm(R[s].astype(np.float64))
+        inp = np.concatenate([_to_oracle(R[s] * g, grid, 3), rho[None]], axis=0)
         out, cache = nn.unet_forward(params, inp, BASE)
-        en = np.linalg.norm(E[s].astype(np.float64))
-        lo, dout = nn.rel_mse_loss(out, _to_oracle(E[s] / en, grid, 3), _to_oracle(free, grid, 3))
+        ge = np.sqrt(t.n_dof) / np.linalg.norm(E[s].astype(np.float64))
+        lo, dout = nn.rel_mse_loss(out, _to_oracle(E[s] * ge, grid, 3), _to_oracle(free, grid, 3))
         lsum += lo
         for k, v in nn.unet_backward(params, cache, dout, BASE).items():
             gsum[k] += v
@@ -168,9 +168,14 @@ def test_train_step_is_adam_on_mean_gradient():
     assert abs(loss - lsum / nb) <= 1e-4 * lsum / nb
     # the first Adam step moves each weight by lr * g / (|g| + eps): compare the moves
     d_gpu, d_ref = w1 - w0, w_ref - w0
+    # The move is lr * sign(g) up to eps: it is exact only where FP32 settles the sign of
+    # the gradient, a signed sum over all voxels.  Gradients above 1% of the largest must
+    # all agree, and the weights that disagree carry under 1% of the gradient's l1 mass.
     g_flat = np.abs(_flat(gmean))
-    big = g_flat > 1e-3 * np.max(g_flat)  # weights whose gradient sign FP32 settles
-    assert np.max(np.abs(d_gpu[big] - d_ref[big])) <= 1e-3 * lr
+    big = g_flat > 1e-2 * np.max(g_flat)
+    match = np.abs(d_gpu - d_ref) <= 1e-3 * lr
+    assert np.all(match[big])
+    assert np.sum(g_flat[~match]) <= 1e-2 * np.sum(g_flat)
     # no weight moves by more than lr (plus the FP32 rounding of the stored weight)
     assert np.all(np.abs(d_gpu) <= lr * (1 + 1e-6) + 2.0 ** -23 * np.abs(w0))
 
