@@ -52,6 +52,10 @@ extern "C" {
 #define TOSIMP_PREC_FP32 1       /* FP32 storage and arithmetic                       */
 #define TOSIMP_PREC_BF16_MFMA 2  /* FP32 storage, BF16 MFMA contraction, FP32 acc.    */
 #define TOSIMP_PREC_FP16_MFMA 3  /* FP32 storage, FP16 MFMA contraction, FP32 acc.    */
+/* Flag OR-ed into the precision of tosimp_apply_K: the caller guarantees v = 0 on every
+ * fixed DOF (as for every CG vector); the per-node BC bytes of v's planes are then not
+ * read.  The result is bit-identical to the call without the flag for such v.        */
+#define TOSIMP_V_ZERO_ON_FIXED 0x100
 
 /* ---- filter modes -------------------------------------------------------------- */
 #define TOSIMP_FILTER_FORWARD 0  /* out = H in / Hs                                   */
@@ -144,7 +148,8 @@ int tosimp_counts(const tosimp_ctx* ctx, int64_t* n_elem, int64_t* n_node, int64
  * E_e K_E, accumulate), deterministic (no atomics; bit-identical across calls).
  * xphys: n_elem element densities of type xdtype; v, y: n_dof values.  prec selects
  * the arithmetic: PREC_FP64 needs v, y FP64; PREC_FP32 and the MFMA precisions need
- * v, y FP32.  y is overwritten (not accumulated); y must not alias v.                */
+ * v, y FP32; it may carry TOSIMP_V_ZERO_ON_FIXED (FP64/FP32 with xdtype of the same
+ * width; ignored otherwise).  y is overwritten (not accumulated); y must not alias v. */
 int tosimp_apply_K(tosimp_ctx* ctx, const void* xphys_dev, int xdtype, const void* v_dev,
                    void* y_dev, int prec);
 /* Jacobi diagonal (paper Sec. "Preconditioned Conjugate Gradient"): d = diag(K_c),

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libtosimp.so")
 
 OK, NOT_CONVERGED, FALLBACK_USED = 0, 1, 2
 F64, F32 = 0, 1
+V_ZERO_ON_FIXED = 0x100
 PREC = {"fp64": 0, "fp32": 1, "bf16_mfma": 2, "fp16_mfma": 3}
 FILTER = {"forward": 0, "adjoint": 1}
 SOLVE = {"plain_fp64": 0, "ir": 1}
@@ -181,7 +182,8 @@ class Tosimp:
         self._check(LIB.tosimp_set_loads(self._h, self._dev(f, torch.float64, self.n_dof, "f")))
 
     # ------------------------------------------------------------------ operator
-    def apply_K(self, x, v, y=None, prec="fp64"):
+    def apply_K(self, x, v, y=None, prec="fp64", v_zero_on_fixed=False):
+        """v_zero_on_fixed: the caller guarantees v = 0 on fixed DOFs (skips the BC bytes)."""
         p = PREC[prec]
         vt = torch.float64 if p == 0 else torch.float32
         if y is None:
@@ -189,7 +191,7 @@ class Tosimp:
         self._sync_stream()
         self._check(LIB.tosimp_apply_K(
             self._h, self._dev(x, None, self.n_elem, "x"), _DT[x.dtype],
-            self._dev(v, vt, self.n_dof, "v"), self._dev(y, vt, self.n_dof, "y"), p))
+            self._dev(v, vt, self.n_dof, "v"), self._dev(y, vt, self.n_dof, "y"), p | (V_ZERO_ON_FIXED if v_zero_on_fixed else 0)))
         return y
 
     def diag_K(self, x, dtype=torch.float64):

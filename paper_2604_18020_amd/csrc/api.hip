@@ -400,6 +400,8 @@ int tosimp_apply_K(tosimp_ctx* ctx, const void* x, int xdtype, const void* v, vo
   REQUIRE(x && v && y, TOSIMP_EINVAL, "null pointer");
   REQUIRE(v != y, TOSIMP_EINVAL, "y must not alias v");
   REQUIRE(xdtype == TOSIMP_F64 || xdtype == TOSIMP_F32, TOSIMP_EINVAL, "bad xdtype");
+  const bool vzero = (prec & TOSIMP_V_ZERO_ON_FIXED) != 0;
+  prec &= ~TOSIMP_V_ZERO_ON_FIXED;
   REQUIRE(prec >= TOSIMP_PREC_FP64 && prec <= TOSIMP_PREC_FP16_MFMA, TOSIMP_EINVAL,
           "bad precision");
   if ((rc = set_device(ctx))) return rc;
@@ -408,7 +410,7 @@ int tosimp_apply_K(tosimp_ctx* ctx, const void* x, int xdtype, const void* v, vo
                                    ctx->ws.st, false));
   } else {
     TOSIMP_HIP(ctx, kv_launch(ctx, prec, xdtype, x, v, y, nullptr, ctx->ws.st, nullptr, 0,
-                              false));
+                              false, vzero));
   }
   return TOSIMP_OK;
 }

@@ -28,6 +28,7 @@
 namespace tosimp {
 
 constexpr int KBX = 32, KBY = 8;  // element columns per block (x, y)
+static_assert(64 % KBX == 0 && KBX * KBY == 256, "a row of element columns lies in one wave");
 
 template <typename T>
 struct KvC {
@@ -128,7 +129,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   constexpr int NE = KBX * KBY;
   __shared__ T sv[NLD * 256];    // node plane ((KBX+1) x (KBY+1) nodes x 3), masked; padded
   __shared__ T sr[NLD * 256];    // the same plane unmasked (fixed rows output y = v)
-  __shared__ T sc[12 * NE];      // corner contributions, [corner*3 + c][element column]
+  __shared__ T sb[3 * NE];       // lower-row corner pairs, [c][element column]
   __shared__ T so[2][NLD * 256]; // finished output planes (owned nodes), same layout as sv
   __shared__ double sred[4];
 
@@ -229,6 +230,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     for (int s = 0; s < NLD; ++s) buf_st(src[tid + 256 * s], ry, ooff[s] + qoff);
   };
 
+  T ya[3];  // upper-row corner pair of the owned node, kept across the barrier
   auto step = [&](int p, T* v, uint8_t* m, uint8_t& mo, XT& xv, const T* tb, T* tt,
                   const T* vown, T* vnew, uint8_t mown, uint8_t& mnew, bool elem, bool out,
                   bool flush, int refill) {
@@ -313,14 +315,19 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
 
       if (out) {
         // ---- node plane p-1 is complete in R: inverse 2D transform to corners --
+        // The owned node (lx+1, ly+1) sums corner (1,1) of this column, (0,1) of column
+        // lx+1, (1,0) of column (lx, ly+1) and (0,0) of (lx+1, ly+1).  The x neighbour
+        // is the next lane (rows are 32 lanes, lane 31 owns no node), so the pairs
+        // along x come from a lane shuffle; only the pair of the row below goes
+        // through LDS.
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const T u0 = R[0 * 3 + c] - R[2 * 3 + c], u1 = R[1 * 3 + c] - R[3 * 3 + c];
           const T w0 = R[0 * 3 + c] + R[2 * 3 + c], w1 = R[1 * 3 + c] + R[3 * 3 + c];
-          sc[(0 * 3 + c) * NE + tid] = u0 - u1;  // corner (0,0)
-          sc[(1 * 3 + c) * NE + tid] = u0 + u1;  // corner (1,0)
-          sc[(2 * 3 + c) * NE + tid] = w0 - w1;  // corner (0,1)
-          sc[(3 * 3 + c) * NE + tid] = w0 + w1;  // corner (1,1)
+          const T c00 = u0 - u1, c10 = u0 + u1, c01 = w0 - w1, c11 = w0 + w1;
+          const T n01 = __shfl_down(c01, 1, 64), n00 = __shfl_down(c00, 1, 64);
+          ya[c] = c11 + n01;
+          sb[c * NE + tid] = c10 + n00;
         }
       }
     }
@@ -333,8 +340,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
       T* dst = so[(p - 1) & 1];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        T yv = (sc[(9 + c) * NE + tid] + sc[(6 + c) * NE + tid + 1]) +
-               (sc[(3 + c) * NE + tid + KBX] + sc[(0 + c) * NE + tid + KBX + 1]);
+        T yv = ya[c] + sb[c * NE + tid + KBX];
         yv = bit_select(yv, vown[c], (mown >> c) & 1);  // fixed rows are identity: y = v
         if (owner) dst[sown + c] = yv;
         if constexpr (DOT) dotacc += owner ? (double)vown[c] * (double)yv : 0.0;
@@ -394,8 +400,10 @@ struct KvDotFin {
 };
 
 // Planes in flight per block, and the deepest z chunk a block sweeps (fully unrolled).
+// A deeper register ring measured slower on MI355X: its registers cost occupancy, and
+// more resident blocks hide the load latency better than deeper prefetch per block.
 template <typename T>
-constexpr int kv_depth() { return sizeof(T) == 8 ? 2 : 4; }
+constexpr int kv_depth() { return sizeof(T) == 8 ? 1 : 2; }
 template <typename T>
 constexpr int kv_kzmax() { return sizeof(T) == 8 ? 24 : 16; }
 

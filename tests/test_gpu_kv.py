@@ -189,3 +189,20 @@ def test_apply_K_mfma_within_rounding_bound(prec, u, dims):
         assert np.array_equal(y[~free], v32[~free])
         # the bound is not vacuous: the error is of the size the rounding predicts
         assert rel(y, y_ref) <= 4 * u
+
+
+@pytest.mark.parametrize("dims", [(16, 8, 8), (37, 19, 23), (2, 1, 3), (70, 9, 13)])
+def test_apply_K_zero_on_fixed_flag_is_bit_identical(dims):
+    """The path the CG iterations use (v known to be zero on fixed DOFs, BC bytes of the
+    planes not read) gives bit-identical results to the general path."""
+    nx, ny, nz = dims
+    t, fixed, _ = gpu_problem(nx, ny, nz)
+    rho, v = si.random_density_and_vector(nx, ny, nz, seed=13)
+    v[fixed] = 0.0
+    for dt, prec in [(torch.float64, "fp64"), (torch.float32, "fp32")]:
+        x, vd = dev(rho, dt), dev(v, dt)
+        y0 = t.apply_K(x, vd, prec=prec)
+        y1 = t.apply_K(x, vd, prec=prec, v_zero_on_fixed=True)
+        assert torch.equal(y0, y1), prec
+        assert torch.all(y1[torch.as_tensor(fixed, device="cuda:0")] == 0)
+
