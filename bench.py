@@ -32,6 +32,31 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of one K v launch at 340x170x85 from two rocprofv3 --pmc passes
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 1 GiB device copy in the same run),
+# valid only for the kernel sources they were taken with (sha256 of kv.hip, dev.h,
+# common.h); reported as null once those change.
+KV_TRAFFIC = {
+    "fp32": (2.0 * 47912.9 + 59025.2) * 1024,
+    "fp64": (2.0 * 94589.6 + 118005.5) * 1024,
+}
+KV_TRAFFIC_SOURCES = {
+    "kv.hip": "f1c2f710ebdcae96cffcff2c0bf2e863c5e347d334aee6c21f618efdb7108d68",
+    "dev.h": "8b034b72e2a61608c66958d1e7d70253194fbb2bdf91fc179096b8fecc73a390",
+    "common.h": "fb2e54c7aabc71b5962cc2a301edb95c019615f678e797a3976272ceee5ab4b4",
+}
+
+
+def kv_traffic(prec: str):
+    """Measured HBM bytes per launch if the kernel sources match the measurement."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2604_18020_amd", "csrc")
+    for fn, h in KV_TRAFFIC_SOURCES.items():
+        with open(os.path.join(csrc, fn), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != h:
+                return None
+    return KV_TRAFFIC[prec]
+
 
 def kv_bytes(prec: str, n_node: int, n_elem: int) -> int:
     """Algorithmic HBM bytes of one K v launch: v read once and y written once (3 values
@@ -71,10 +96,19 @@ def time_kv(t, nx, ny, nz, prec, steps, warmup, fixed, seed=42):
     wall = time.perf_counter() - t0
     launch_ms = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)]
     avg_ms = float(np.mean(launch_ms))
+    # the same launches back to back without per-launch events (includes launch gaps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec, v_zero_on_fixed=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1) / steps
     ok = bool(torch.isfinite(ys[(steps - 1) % nset]).all())
     del xs, vs, ys
     torch.cuda.empty_cache()
     return dict(wall_s=wall, avg_launch_ms=avg_ms, median_launch_ms=float(np.median(launch_ms)),
+                batch_ms=batch_ms,
                 bytes=set_bytes, buffer_sets=nset, finite=ok)
 
 
@@ -83,7 +117,8 @@ def _solve_timed(t, x, f, tol, **kw):
     u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = t.pcg_solve(x, f, u, tol=tol, maxit=60000, **kw)
+    kw.setdefault("maxit", 60000)
+    st = t.pcg_solve(x, f, u, tol=tol, **kw)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     c = float(torch.dot(f, u))
@@ -161,7 +196,7 @@ def time_nn(workload="cantilever_200x100x50", simp_iters=10, per_solve=200, ever
                      ("ir_fp32_jacobi", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,
                                              check_every=64)),
                      ("ir_fp32_nn_fcg", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,
-                                             precond="nn", check_every=8))]:
+                                             precond="nn", check_every=8, maxit=6000))]:
         _, r = _solve_timed(t, xp, f, tol, **kw)
         out[name] = r
     t.close()
@@ -359,9 +394,11 @@ def main():
     value = t.n_dof / (ms * 1e-3) / 1e9
     achieved = main_kv["bytes"] / (main_kv["avg_launch_ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": kv_traffic(a.prec),
                 "bytes_per_launch": main_kv["bytes"],
-                "avg_launch_us": main_kv["avg_launch_ms"] * 1e3}
+                "avg_launch_us": main_kv["avg_launch_ms"] * 1e3,
+                "median_launch_us": main_kv["median_launch_ms"] * 1e3,
+                "back_to_back_us": main_kv["batch_ms"] * 1e3}
     line = {
         "metric": "K·v GDOF/s + PCG time-to-1e-6 residual: plain FP64 vs mixed/learned form",
         "value": value, "unit": "GDOF/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -377,7 +414,10 @@ def main():
             "gdof_s": t.n_dof / (other_kv["avg_launch_ms"] * 1e-3) / 1e9,
             "achieved_gbs": other_kv["bytes"] / (other_kv["avg_launch_ms"] * 1e-3) / 1e9,
             "frac": other_kv["bytes"] / (other_kv["avg_launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "avg_launch_us": other_kv["avg_launch_ms"] * 1e3},
+            "avg_launch_us": other_kv["avg_launch_ms"] * 1e3,
+            "median_launch_us": other_kv["median_launch_ms"] * 1e3,
+            "back_to_back_us": other_kv["batch_ms"] * 1e3,
+            "traffic": kv_traffic(other)},
     }
     if not a.no_pcg:
         line["pcg"] = dict(workload=f"{a.workload}, cold start, uniform density 0.3, "
