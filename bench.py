@@ -180,6 +180,7 @@ def time_nn(workload="cantilever_200x100x50", simp_iters=10, per_solve=200, ever
     t_harvest = time.perf_counter() - t0
     t.nn_create(16, bf16=True)
     t.nn_set_weights(learned.he_normal_weights(t, 0))
+    t.nn_set_loss("energy")
     t0 = time.perf_counter()
     losses = learned.train(t, ps, train_steps, batch=batch, lr=lr)
     torch.cuda.synchronize()
@@ -190,7 +191,8 @@ def time_nn(workload="cantilever_200x100x50", simp_iters=10, per_solve=200, ever
                        f"iteration {simp_iters + 1}, cold start, tol {tol:g}",
            "pairs": int(sum(s["solve"]["harvested"] for s in stats)),
            "harvest_s": t_harvest, "train_steps": train_steps, "batch": batch,
-           "train_s": t_train, "loss_first50": float(np.mean(losses[:50])),
+           "train_s": t_train, "loss": "energy norm of the best multiple of the correction",
+           "loss_first50": float(np.mean(losses[:50])),
            "loss_last50": float(np.mean(losses[-50:]))}
     for name, kw in [("plain_fp64_jacobi", dict(mode="plain_fp64", check_every=64)),
                      ("ir_fp32_jacobi", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,

@@ -236,8 +236,8 @@ int tosimp_tridiag_extremes(const double* alpha, const double* beta, int m, doub
  * tosimp_nn_set_weights / get_weights: copy the master weights from / to host memory
  *   (n must equal the count); set_weights also resets the Adam moments.  Synchronise.
  * tosimp_nn_set_density: nodal density (mean of the adjacent elements) from an element
- *   density on the device (xdtype TOSIMP_F64 or TOSIMP_F32); used by apply and
- *   train_step until the next call.
+ *   density on the device (xdtype TOSIMP_F64 or TOSIMP_F32), and an FP32 copy of the
+ *   density for the energy loss; used by apply and train_step until the next call.
  * tosimp_nn_apply: z = (||r|| / sqrt(n_dof)) N(r sqrt(n_dof) / ||r||, rho_node), zero on
  *   fixed DOFs (FP32 device vectors, n_dof; r and z must not alias).
  * tosimp_nn_precondition: the preconditioner flexible CG applies, at element density
@@ -251,6 +251,12 @@ int tosimp_tridiag_extremes(const double* alpha, const double* beta, int m, doub
  *   layout, host FP32, may be NULL).  Synchronises.
  * tosimp_nn_train_step: one Adam step on the mean loss of nb pairs (r, e), device FP32
  *   [nb][n_dof] each.  Synchronises; *loss_host = mean loss before the step.
+ * tosimp_nn_set_loss: training loss, 0 = the relative MSE above (default), 1 = energy
+ *   norm: for the correction n (network output on free DOFs) and a pair (r, e),
+ *   L = 1 - <n,r>^2 / (<n,K n> <e,r>), the relative K-norm error of the best multiple of
+ *   n, K at the density of tosimp_nn_set_density.
+ * tosimp_nn_sample_grad: test hook, loss and gradient (master layout, host FP32, may be
+ *   NULL) of one pair (r, e) (device FP32, n_dof each).  Synchronises.
  * tosimp_nn_make_targets: harvest_u[k] <- u_star - harvest_u[k] for k < count
  *   (u_star FP64 device, harvest_u FP32 device [count][n_dof]).                       */
 int tosimp_nn_create(tosimp_ctx* ctx, int base, int bf16);
@@ -268,6 +274,9 @@ int tosimp_nn_train_step(tosimp_ctx* ctx, const float* r_batch_dev, const float*
                          int nb, double lr, double* loss_host);
 int tosimp_nn_make_targets(tosimp_ctx* ctx, const double* u_star_dev, float* harvest_u_dev,
                            int count);
+int tosimp_nn_set_loss(tosimp_ctx* ctx, int kind);
+int tosimp_nn_sample_grad(tosimp_ctx* ctx, const float* r_dev, const float* e_dev,
+                          double* loss_host, float* grad_host);
 
 #ifdef __cplusplus
 }

@@ -203,6 +203,21 @@ def rel_mse_loss(out, target, mask):
     return float(np.sum(d * d) / den), 2.0 * d * mask / den
 
 
+def energy_loss(n, r, e, apply_K, free):
+    """Relative energy-norm error of the best multiple of the correction n:
+    with a = <n, r>, q = <n, K n>, c = <e, r> (e = K^-1 r, so c = ||e||_K^2),
+    L = min_s ||s n - e||_K^2 / ||e||_K^2 = 1 - a^2 / (q c),
+    and dL/dn = -(2 a / (q c)) (r - (a / q) K n), on free DOFs (n is masked first)."""
+    n = n * free
+    Kn = apply_K(n)
+    a, q, c = float(n @ r), float(n @ Kn), float(e @ r)
+    if not (q > 0 and c > 0):
+        return 1.0, np.zeros_like(n)
+    L = 1.0 - a * a / (q * c)
+    g = -(2.0 * a / (q * c)) * (r - (a / q) * Kn) * free
+    return L, g
+
+
 def adam_step(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8):
     """One Adam update (bias-corrected moments) of every parameter, in place."""
     state["t"] = state.get("t", 0) + 1

@@ -99,6 +99,8 @@ def _load():
         "tosimp_nn_loss_grad": (I, [P, P, P, C.POINTER(D), P]),
         "tosimp_nn_train_step": (I, [P, P, P, I, D, C.POINTER(D)]),
         "tosimp_nn_make_targets": (I, [P, P, P, I]),
+        "tosimp_nn_set_loss": (I, [P, I]),
+        "tosimp_nn_sample_grad": (I, [P, P, P, C.POINTER(D), P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -364,6 +366,19 @@ class Tosimp:
             self._dev(e_batch, torch.float32, nb * self.n_dof, "e_batch"), nb, lr,
             C.byref(loss)))
         return loss.value
+
+    def nn_set_loss(self, kind="mse"):
+        self._check(LIB.tosimp_nn_set_loss(self._h, {"mse": 0, "energy": 1}[kind]))
+
+    def nn_sample_grad(self, r, e, want_grad=True):
+        loss = C.c_double()
+        g = np.zeros(self.nn_params, dtype=np.float32) if want_grad else None
+        self._sync_stream()
+        self._check(LIB.tosimp_nn_sample_grad(
+            self._h, self._dev(r, torch.float32, self.n_dof, "r"),
+            self._dev(e, torch.float32, self.n_dof, "e"), C.byref(loss),
+            g.ctypes.data_as(C.c_void_p) if want_grad else None))
+        return loss.value, g
 
     def nn_make_targets(self, u_star, harvest_u, count):
         if harvest_u.numel() < int(count) * self.n_dof:

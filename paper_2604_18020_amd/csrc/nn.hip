@@ -479,6 +479,64 @@ __global__ void take3_f32(const float* o, float* out, int n) {
 }
 
 
+// ------------------------------------------------------------ energy-norm loss
+// Training loss of the correction n (head output on free DOFs, DOF layout) for a pair
+// (r, e = K^-1 r): L = 1 - a^2 / (q c), a = <n, r>, q = <n, K n>, c = <e, r>, the relative
+// energy-norm error of the best multiple of n; dL/dn = -(2a / (q c)) (r - (a/q) K n).
+template <typename ST>
+__global__ void head_to_dof_kernel(const ST* out, const uint8_t* mask, float* nd, int n_node) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n_node; v += gridDim.x * blockDim.x) {
+    const uint8_t mk = mask[v];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) nd[3 * v + c] = ((mk >> c) & 1) ? 0.0f : to_f(out[16 * v + c]);
+  }
+}
+
+__global__ __launch_bounds__(256) void energy_dots_kernel(const float* __restrict__ nd,
+                                                          const float* __restrict__ r,
+                                                          const float* __restrict__ e, int n,
+                                                          double* partials) {
+  __shared__ double sred[4];
+  double a = 0.0, c = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    a += (double)nd[i] * (double)r[i];
+    c += (double)e[i] * (double)r[i];
+  }
+  const double v[2] = {a, c};
+  store_block_sums<2>(v, partials, sred);
+}
+
+// scal[4] = q (from the operator's fused dot); sets scal[5] = a, scal[6] = c and the
+// reported loss as scal[2] / scal[1].
+struct EnergyFin {
+  double* scal;
+  __device__ void operator()(const double* t) const {
+    const double a = t[0], c = t[1], q = scal[4];
+    scal[5] = a;
+    scal[6] = c;
+    scal[1] = 1.0;
+    scal[2] = (q > 0.0 && c > 0.0) ? 1.0 - a * a / (q * c) : 1.0;
+  }
+};
+
+template <typename ST>
+__global__ void energy_grad_kernel(const float* r, const float* Knd, const uint8_t* mask,
+                                   const double* scal, ST* g, int n_node) {
+  const double q = scal[4], a = scal[5], c = scal[6];
+  const bool ok = q > 0.0 && c > 0.0;
+  const float k1 = ok ? (float)(-2.0 * a / (q * c)) : 0.0f;
+  const float sa = ok ? (float)(a / q) : 0.0f;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n_node; v += gridDim.x * blockDim.x) {
+    const uint8_t mk = mask[v];
+#pragma unroll
+    for (int ch = 0; ch < 16; ++ch) {
+      float gv = 0.0f;
+      if (ch < 3 && !((mk >> ch) & 1)) gv = k1 * (r[3 * v + ch] - sa * Knd[3 * v + ch]);
+      g[16 * v + ch] = from_f<ST>(gv);
+    }
+  }
+}
+
 // ------------------------------------------------------------------- flexible CG
 // FCG(1): z_k = M(r_k), beta_k = -<z_k, q_{k-1}> / <p_{k-1}, q_{k-1}>, p_k = z_k + beta_k
 // p_{k-1}, alpha_k = <r_k, z_k> / <p_k, q_k>.  A network output that is not a descent
@@ -633,6 +691,8 @@ struct NNState {
   void* cat0 = nullptr;        // [up(u1b) | s0] at level 0
   void* gbuf[6] = {};          // gradient scratch (largest level-0 sizes)
   float* gsum = nullptr;       // summed gradient of a training batch (master layout)
+  float* x32 = nullptr;        // element density of the training pairs (FP32, for K n)
+  int loss_kind = 0;           // 0: relative MSE to the unit-RMS error; 1: energy norm
   float* wpart = nullptr;      // weight-gradient partials
   size_t wpart_cap = 0;
   float* rho_node = nullptr;
@@ -714,7 +774,7 @@ void tosimp::nn_release(tosimp_ctx* ctx) {
   NNState* S = ctx ? nn_of(ctx) : nullptr;
   if (!S) return;
   void* ptrs[] = {S->master, S->m,        S->v,    S->grad, S->gpack, S->W,   S->WT, S->cat1,
-                  S->cat0,   S->wpart,    S->rho_node, S->scal, S->part, S->gsum};
+                  S->cat0,   S->wpart,    S->rho_node, S->scal, S->part, S->gsum, S->x32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : S->act)
@@ -873,15 +933,31 @@ int nn_sample_grad(tosimp_ctx* ctx, NNState* S, const float* r, const float* e, 
   const int nn = (int)ctx->n_node;
   TOSIMP_HIP(ctx, launch_norm2f(ctx->stream, r, (int)ctx->n_dof, S->part, S->scal));
   build_input_kernel<ST><<<2048, 256, 0, ctx->stream>>>(r, S->scal, S->rho_node, (ST*)S->act[12], nn);
-  // Target e sqrt(n_dof) / ||e|| (unit RMS, the scale of the inputs): flexible CG does
-  // not depend on the scale of z.
-  TOSIMP_HIP(ctx, launch_norm2f(ctx->stream, e, (int)ctx->n_dof, S->part, S->scal + 3));
-  scale_target_kernel<<<2048, 256, 0, ctx->stream>>>(e, S->scal + 3, tgt, (int)ctx->n_dof);
   TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S));
-  TOSIMP_HIP(ctx, launch_loss<ST>(ctx->stream, (const ST*)S->act[11], tgt, ctx->ws.mask, nn,
-                                   S->part, S->scal + 1));
-  loss_grad_kernel<ST><<<2048, 256, 0, ctx->stream>>>((const ST*)S->act[11], tgt, ctx->ws.mask, nn,
-                                                      S->scal + 1, (ST*)S->gbuf[0]);
+  if (S->loss_kind == 1) {
+    // energy norm: n on free DOFs, K n (FP32 operator at the pair's density), the dots
+    float* nd = (float*)ctx->ws.w;
+    float* Knd = ctx->ws.q32;
+    const int n = (int)ctx->n_dof;
+    const int vb = std::min(2048, (n + 255) / 256);
+    head_to_dof_kernel<ST><<<2048, 256, 0, ctx->stream>>>((const ST*)S->act[11], ctx->ws.mask, nd, nn);
+    TOSIMP_HIP(ctx, kv_launch(ctx, TOSIMP_PREC_FP32, TOSIMP_F32, S->x32, nd, Knd,
+                              ctx->ws.partials + 2 * kMaxPartials, ctx->ws.st + 2, S->scal + 4,
+                              2, false, true));
+    energy_dots_kernel<<<vb, 256, 0, ctx->stream>>>(nd, r, e, n, S->part);
+    TOSIMP_HIP(ctx, launch_finalize_sum<2>(ctx->stream, S->part, vb, EnergyFin{S->scal}));
+    energy_grad_kernel<ST><<<2048, 256, 0, ctx->stream>>>(r, Knd, ctx->ws.mask, S->scal,
+                                                          (ST*)S->gbuf[0], nn);
+  } else {
+    // Target e sqrt(n_dof) / ||e|| (unit RMS, the scale of the inputs): flexible CG does
+    // not depend on the scale of z.
+    TOSIMP_HIP(ctx, launch_norm2f(ctx->stream, e, (int)ctx->n_dof, S->part, S->scal + 3));
+    scale_target_kernel<<<2048, 256, 0, ctx->stream>>>(e, S->scal + 3, tgt, (int)ctx->n_dof);
+    TOSIMP_HIP(ctx, launch_loss<ST>(ctx->stream, (const ST*)S->act[11], tgt, ctx->ws.mask, nn,
+                                     S->part, S->scal + 1));
+    loss_grad_kernel<ST><<<2048, 256, 0, ctx->stream>>>((const ST*)S->act[11], tgt, ctx->ws.mask,
+                                                        nn, S->scal + 1, (ST*)S->gbuf[0]);
+  }
   TOSIMP_HIP(ctx, nn_backward<ST>(ctx, S));
   accum_kernel<<<(int)((S->nparam + 255) / 256), 256, 0, ctx->stream>>>(gacc, S->grad, (int)S->nparam,
                                                                        first ? 0 : 1);
@@ -1032,6 +1108,7 @@ int tosimp_nn_create(tosimp_ctx* ctx, int base, int bf16) {
   A((void**)&S->v, mo * 4);
   A((void**)&S->grad, mo * 4);
   A((void**)&S->gsum, mo * 4);
+  A((void**)&S->x32, (size_t)ctx->n_elem * 4);
   A((void**)&S->gpack, wo * 4);
   A(&S->W, wo * S->es);
   A(&S->WT, wo * S->es);
@@ -1097,13 +1174,48 @@ int tosimp_nn_set_density(tosimp_ctx* ctx, const void* x, int xdtype) {
   NN_REQUIRE(S, TOSIMP_ESTATE, "no network");
   NN_REQUIRE(x && (xdtype == TOSIMP_F64 || xdtype == TOSIMP_F32), TOSIMP_EINVAL,
              "bad density pointer or dtype");
-  if (xdtype == TOSIMP_F64)
+  if (xdtype == TOSIMP_F64) {
     node_density_kernel<double><<<2048, 256, 0, ctx->stream>>>((const double*)x, ctx->nx, ctx->ny,
                                                                 ctx->nz, S->rho_node);
-  else
+    TOSIMP_HIP(ctx, launch_copy_cast_x(ctx, (const double*)x, S->x32));
+  } else {
     node_density_kernel<float><<<2048, 256, 0, ctx->stream>>>((const float*)x, ctx->nx, ctx->ny,
                                                                ctx->nz, S->rho_node);
+    TOSIMP_HIP(ctx, hipMemcpyAsync(S->x32, x, (size_t)ctx->n_elem * 4, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+  }
   TOSIMP_HIP(ctx, hipGetLastError());
+  return TOSIMP_OK;
+}
+
+// Loss used by tosimp_nn_train_step and tosimp_nn_sample_grad (0: relative MSE to the
+// unit-RMS error, 1: energy norm of the best multiple of the correction).
+int tosimp_nn_set_loss(tosimp_ctx* ctx, int kind) {
+  if (!ctx) return TOSIMP_EINVAL;
+  NNState* S = nn_of(ctx);
+  NN_REQUIRE(S, TOSIMP_ESTATE, "no network");
+  NN_REQUIRE(kind == 0 || kind == 1, TOSIMP_EINVAL, "loss kind must be 0 or 1");
+  S->loss_kind = kind;
+  return TOSIMP_OK;
+}
+
+// Test hook: loss and gradient (master layout, host) of one pair (r, e) at the density
+// set by tosimp_nn_set_density.
+int tosimp_nn_sample_grad(tosimp_ctx* ctx, const float* r, const float* e, double* loss_host,
+                          float* grad_host) {
+  if (!ctx) return TOSIMP_EINVAL;
+  NNState* S = nn_of(ctx);
+  NN_REQUIRE(S && r && e, TOSIMP_EINVAL, "bad arguments");
+  float* tgt = (float*)ctx->ws.w + ctx->n_dof;  // second half: the energy loss uses the first
+  double l = 0.0;
+  int rc = S->bf16 ? nn_sample_grad<bf16_t>(ctx, S, r, e, tgt, S->gsum, true, &l)
+                   : nn_sample_grad<float>(ctx, S, r, e, tgt, S->gsum, true, &l);
+  if (rc) return rc;
+  if (grad_host)
+    TOSIMP_HIP(ctx, hipMemcpyAsync(grad_host, S->gsum, S->nparam * 4, hipMemcpyDeviceToHost,
+                                   ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (loss_host) *loss_host = l;
   return TOSIMP_OK;
 }
 
@@ -1200,7 +1312,7 @@ int tosimp_nn_train_step(tosimp_ctx* ctx, const float* r_batch, const float* e_b
   if (!ctx) return TOSIMP_EINVAL;
   NNState* S = nn_of(ctx);
   NN_REQUIRE(S && r_batch && e_batch && nb >= 1 && lr > 0, TOSIMP_EINVAL, "bad arguments");
-  float* tgt = (float*)ctx->ws.w;  // scaled target (n_dof floats fit in the FP64 scratch)
+  float* tgt = (float*)ctx->ws.w + ctx->n_dof;  // scaled target (second half of the FP64 scratch)
   float* gsum = S->gsum;
   double tot = 0.0;
   for (int s = 0; s < nb; ++s) {

@@ -292,3 +292,37 @@ def test_nn_precond_without_network_is_rejected():
     with pytest.raises(TosimpError):
         t.pcg_solve(dev(x), dev(f), u, precond="nn", mode="ir", tol=1e-8)
     t.close()
+
+
+@pytest.mark.parametrize("bf16,tol", [(False, 1e-4), (True, 0.15)])
+def test_energy_loss_gradient_matches_oracle(bf16, tol):
+    nx, ny, nz = 8, 6, 5
+    t, fixed, _, params = _net(nx, ny, nz, bf16=bf16)
+    t.nn_set_loss("energy")
+    rng = np.random.default_rng(21)
+    x = rng.uniform(0.1, 1.0, t.n_elem).astype(np.float32)
+    x64 = x.astype(np.float64)
+    fm = fem.fixed_mask(t.n_dof, fixed)
+    Kc = fem.constrain(fem.assemble_K(nx, ny, nz, fem.simp_modulus(x64, 1.0, 1e-9, 3.0),
+                                      fem.element_stiffness(0.3)), fm)
+    r = rng.standard_normal(t.n_dof)
+    r[fm] = 0.0
+    r = r.astype(np.float32).astype(np.float64)
+    e = np.linalg.solve(Kc.toarray(), r).astype(np.float32).astype(np.float64)
+    t.nn_set_density(dev(x))
+    loss, g = t.nn_sample_grad(dev(r, torch.float32), dev(e, torch.float32))
+    # oracle: unit-RMS input, correction on free DOFs, energy loss, back through the net
+    grid = (nx + 1, ny + 1, nz + 1)
+    gsc = np.sqrt(t.n_dof) / np.linalg.norm(r)
+    inp = np.concatenate([_to_oracle(r * gsc, grid, 3), nn.node_density(x64, nx, ny, nz)[None]], axis=0)
+    out, cache = nn.unet_forward(params, inp, BASE)
+    n = out.transpose(1, 2, 3, 0).reshape(-1)
+    free = (~fm).astype(float)
+    lo, gd = nn.energy_loss(n, r, e, lambda v: Kc @ v, free)
+    grads = nn.unet_backward(params, cache, _to_oracle(gd, grid, 3), BASE)
+    t.close()
+    assert abs(loss - lo) <= tol * max(lo, 1e-3)
+    gg = _unflat(g.astype(np.float64))
+    errs = {name: rel(gg[name], grads[name]) for name, *_ in nn.unet_layers(BASE)}
+    assert max(errs.values()) <= tol, errs
+

@@ -170,3 +170,28 @@ def test_two_stage_scale_invariant_and_energy_optimal():
     en = lambda c: (e - c * n) @ (Kc @ (e - c * n))
     assert en(s) <= min(en(0.99 * s), en(1.01 * s))
 
+
+def test_energy_loss_definition_gradient_and_exact_case():
+    Kc, fixed, r = _small_system(11)
+    free = (~fixed).astype(float)
+    A = lambda v: Kc @ v
+    e = np.linalg.solve(Kc.toarray(), r)
+    rng = np.random.default_rng(12)
+    n = e + 0.5 * rng.standard_normal(r.size)
+    L, g = nn.energy_loss(n, r, e, A, free)
+    # the definition: best multiple of the masked correction, energy norm, relative
+    nm = n * free
+    s = (nm @ r) / (nm @ (Kc @ nm))
+    d = s * nm - e
+    assert abs(L - (d @ (Kc @ d)) / (e @ (Kc @ e))) <= 1e-12
+    # exact direction: zero loss (any positive multiple)
+    assert abs(nn.energy_loss(3.0 * e, r, e, A, free)[0]) <= 1e-12
+    # gradient against central differences
+    h = 1e-6
+    for i in rng.choice(np.flatnonzero(free), 6, replace=False):
+        dp = np.zeros_like(n)
+        dp[i] = h
+        fd = (nn.energy_loss(n + dp, r, e, A, free)[0] - nn.energy_loss(n - dp, r, e, A, free)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd))
+    assert np.all(g[fixed] == 0)
+
