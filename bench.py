@@ -10,6 +10,8 @@ them, bracketed by torch.cuda.synchronize().  `value` = DOFs processed per secon
 (GDOF/s).  Alongside, in the same JSON line:
   * roofline: algorithmic bytes per launch / measured launch time vs 8 TB/s,
   * kv_other_precision: the same measurement for the other operator precision,
+  * kv_mfma: the BF16 / FP16 matrix-core contraction variant (FP32 storage),
+  * kv_torsion_55x55x165: FP32 / FP64 on the torsion mesh,
   * pcg: wall time to ||r|| <= 1e-6 ||f|| for plain FP64 Jacobi-PCG and for FP64
     refinement around an FP32 inner Jacobi-PCG, with the compliance error of each
     against an FP64 solve to 1e-10,
@@ -421,11 +423,30 @@ def main():
             "back_to_back_us": other_kv["batch_ms"] * 1e3,
             "traffic": kv_traffic(other)},
     }
+    def summary(r, prec):
+        us = r["avg_launch_ms"] * 1e3
+        return {"gdof_s": t.n_dof / (us * 1e-6) / 1e9, "achieved_gbs": r["bytes"] / (us * 1e-6) / 1e9,
+                "frac": r["bytes"] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "avg_launch_us": us}
+    # low-precision contraction on the matrix cores (FP32 storage, FP32 accumulate)
+    line["kv_mfma"] = {p: summary(time_kv(t, nx, ny, nz, p, 50, 5, fixed), p)
+                       for p in ("bf16_mfma", "fp16_mfma")}
     if not a.no_pcg:
         line["pcg"] = dict(workload=f"{a.workload}, cold start, uniform density 0.3, "
                                     f"tol {a.pcg_tol:g}",
                            **time_pcg(t, nx, ny, nz, a.pcg_tol))
     t.close()
+    # the torsion mesh (55x55x165, 499,125 elements)
+    tor = Tosimp(0).set_mesh(55, 55, 165)
+    tfix = si.torsion_fixed_dofs(55, 55, 165)
+    tor.set_bcs(tfix)
+    line["kv_torsion_55x55x165"] = {}
+    for p in ("fp32", "fp64"):
+        r = time_kv(tor, 55, 55, 165, p, 100, 10, tfix)
+        us = r["avg_launch_ms"] * 1e3
+        line["kv_torsion_55x55x165"][p] = {
+            "gdof_s": tor.n_dof / (us * 1e-6) / 1e9, "avg_launch_us": us,
+            "frac": r["bytes"] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    tor.close()
     if not a.no_nn:
         line["learned_pcg"] = time_nn()
     if not a.no_cpu_baseline:

@@ -86,6 +86,7 @@ typedef struct tosimp_solve_opts {
   float* harvest_u;  /*   harvest_cap x n_dof each, receiving r_k and u_k every          */
   int harvest_cap;   /*   harvest_every iterations (k = 0, he, 2 he, ...) until full;    */
   int harvest_every; /*   tosimp_nn_make_targets turns u_k into e_k = u* - u_k           */
+  int fcg_window;    /* PRECOND_NN: flexible CG keeps this many directions (1..16; 0 = 1) */
 } tosimp_solve_opts;
 
 typedef struct tosimp_solve_stats {

@@ -236,28 +236,32 @@ def adam_step(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 # ------------------------------------------------------------------ flexible CG
-def fcg(apply_A, precond, b, x0=None, tol=1e-8, maxit=10000):
-    """Flexible CG with truncation 1: z_k = M_k(r_k),
-    beta_k = -<z_k, q_{k-1}> / <p_{k-1}, q_{k-1}>, p_k = z_k + beta_k p_{k-1}, q = A p,
+def fcg(apply_A, precond, b, x0=None, tol=1e-8, maxit=10000, window=1):
+    """Flexible CG truncated to the `window` latest directions (FCG(m)): z_k = M_k(r_k),
+    p_k = z_k - sum_j (<z_k, q_j> / <p_j, q_j>) p_j over the window, q_k = A p_k,
     alpha_k = <r_k, z_k> / <p_k, q_k>.  With a fixed SPD preconditioner this reproduces
-    PCG in exact arithmetic.  Stops on ||r|| <= tol ||b||.  Returns (x, iters, history)."""
+    PCG in exact arithmetic for every window.  Stops on ||r|| <= tol ||b||.
+    Returns (x, iters, history)."""
     x = np.zeros_like(b) if x0 is None else x0.copy()
     bn = np.linalg.norm(b)
     r = b - apply_A(x)
     hist = [np.linalg.norm(r) / bn]
-    p = q = None
+    P, Q = [], []
     it = 0
     while hist[-1] > tol and it < maxit:
         z = precond(r)
-        if p is None:
-            p = z.copy()
-        else:
-            beta = -(z @ q) / (p @ q)
-            p = z + beta * p
+        p = z.copy()
+        for pj, qj in zip(P, Q):
+            p -= (z @ qj) / (pj @ qj) * pj
         q = apply_A(p)
         alpha = (r @ z) / (p @ q)
         x = x + alpha * p
         r = r - alpha * q
+        P.append(p)
+        Q.append(q)
+        if len(P) > window:
+            P.pop(0)
+            Q.pop(0)
         it += 1
         hist.append(np.linalg.norm(r) / bn)
     return x, it, hist

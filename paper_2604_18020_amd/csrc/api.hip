@@ -636,7 +636,7 @@ int tosimp_pcg_solve(tosimp_ctx* ctx, const double* x, const double* b, double* 
       if (o->precond == TOSIMP_PRECOND_NN) {
         int fb = 0;
         rc = nn_fcg_solve(ctx, ip, w.x32, w.e32, w.z32, itol, o->maxit - total,
-                          o->check_every, &it, &fb, &done);
+                          o->check_every, o->fcg_window, &it, &fb, &done);
         if (rc < 0) return rc;
         fallbacks += fb;
       } else {

@@ -180,8 +180,8 @@ hipError_t launch_sqrt_scalar(const tosimp_ctx* c, const SolverState* st, double
 // the network as preconditioner (Jacobi fallback), FP32 vectors, zero initial guess.
 void nn_release(tosimp_ctx* ctx);
 int nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const float* b32, float* e32,
-                 double tol, int maxit, int check_every, int* iters, int* fallbacks,
-                 int* done);
+                 double tol, int maxit, int check_every, int window, int* iters,
+                 int* fallbacks, int* done);
 
 // SIMP kernels (topopt.hip).
 hipError_t launch_sensitivity(const tosimp_ctx* c, const double* xphys, const double* u,

@@ -538,76 +538,102 @@ __global__ void energy_grad_kernel(const float* r, const float* Knd, const uint8
 }
 
 // ------------------------------------------------------------------- flexible CG
-// FCG(1): z_k = M(r_k), beta_k = -<z_k, q_{k-1}> / <p_{k-1}, q_{k-1}>, p_k = z_k + beta_k
-// p_{k-1}, alpha_k = <r_k, z_k> / <p_k, q_k>.  A network output that is not a descent
-// direction (<r, z> <= 0 or non-finite) is replaced by the Jacobi step z = D^-1 r.
-// State: st->rz = <r, z>, st->pq = <p, q> (from the operator's fused dot), st->aux = 1
-// while the current z must be replaced, st->nfallback counts the replacements.
-__global__ __launch_bounds__(256) void fcg_check_kernel(const float* __restrict__ r,
-                                                        const float* __restrict__ z,
-                                                        const float* __restrict__ q, int n,
-                                                        SolverState* st, double* partials) {
+// FCG(m) (flexible CG truncated to the m latest directions): z_k = M(r_k),
+//   p_k = z_k + sum_j beta_j p_j,  beta_j = -<z_k, q_j> / <p_j, q_j>  (j: the window),
+//   q_k = K p_k,  alpha_k = <r_k, z_k> / <p_k, q_k>.
+// m = 1 is FCG(1); with a fixed SPD preconditioner every m gives PCG in exact arithmetic.
+// A z that is not a descent direction (<r, z> <= 0 or non-finite) is replaced by the
+// Jacobi step z = D^-1 r.  Directions and their images live in a ring of m slots; the
+// host passes the window size and the slot of each enqueued iteration (kernels of a
+// finished solve return at once, so the host's count equals the device's).
+constexpr int kFcgMax = 16;
+
+struct FcgWin {
+  const float* P[kFcgMax];
+  const float* Q[kFcgMax];
+  int nw;  // directions in the window (slots 0 .. nw-1)
+};
+
+// <r, z> and <z, q_j> for the window; pass 1 runs only when a fallback is pending.
+__global__ __launch_bounds__(256) void fcgm_dots_kernel(const float* __restrict__ r,
+                                                        const float* __restrict__ z, FcgWin w,
+                                                        int n, const SolverState* st, int pass,
+                                                        double* partials) {
   __shared__ double sred[4];
-  if (st->done) return;
-  const bool first = st->iter == 0;
-  double rz = 0.0, zq = 0.0;
+  if (st->done || (pass == 1 && st->aux == 0.0)) return;
+  double acc[1 + kFcgMax];
+#pragma unroll
+  for (int j = 0; j <= kFcgMax; ++j) acc[j] = 0.0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const double zi = z[i];
-    rz += (double)r[i] * zi;
-    if (!first) zq += zi * (double)q[i];
+    acc[0] += (double)r[i] * zi;
+#pragma unroll
+    for (int j = 0; j < kFcgMax; ++j)
+      if (j < w.nw) acc[1 + j] += zi * (double)w.Q[j][i];
   }
-  const double v[2] = {rz, zq};
-  store_block_sums<2>(v, partials, sred);
+  store_block_sums<1 + kFcgMax>(acc, partials, sred);
 }
 
-struct FcgCheckFin {
+struct FcgmFin {
   SolverState* st;
+  double* pq;    // <p_j, q_j> per slot
+  double* coef;  // beta_j per slot (output)
+  int nw;
+  int pass;      // 0: check the network's z; 1: after the Jacobi replacement
   __device__ void operator()(const double* t) const {
-    if (st->done) return;
-    const double RZ = t[0], ZQ = t[1];
-    const double beta = st->iter == 0 ? 0.0 : -ZQ / st->pq;
-    if (finite_val(RZ) && finite_val(beta) && RZ > 0.0) {
-      st->aux = 0.0;
-      st->rz = RZ;
-      st->beta = beta;
+    if (st->done || (pass == 1 && st->aux == 0.0)) return;
+    const double RZ = t[0];
+    bool ok = finite_val(RZ) && RZ > 0.0;
+    for (int j = 0; j < kFcgMax; ++j) {
+      const double b = j < nw ? -t[1 + j] / pq[j] : 0.0;
+      coef[j] = b;
+      ok = ok && finite_val(b);
+    }
+    if (pass == 0) {
+      if (ok) {
+        st->aux = 0.0;
+        st->rz = RZ;
+      } else {
+        st->aux = 1.0;  // replace z by the Jacobi step
+      }
     } else {
-      st->aux = 1.0;  // replace z by the Jacobi step
+      st->rz = RZ;
+      st->aux = 0.0;
+      st->nfallback += 1;
+      if (!ok) st->done = 3;
     }
   }
 };
 
-__global__ __launch_bounds__(256) void fcg_fallback_kernel(const float* __restrict__ r,
+__global__ __launch_bounds__(256) void fcg_jacobi_z_kernel(const float* __restrict__ r,
                                                            float* __restrict__ z,
-                                                           const float* __restrict__ q,
                                                            const float* __restrict__ dinv, int n,
-                                                           SolverState* st, double* partials) {
-  __shared__ double sred[4];
+                                                           const SolverState* st) {
   if (st->done || st->aux == 0.0) return;
-  const bool first = st->iter == 0;
-  double rz = 0.0, zq = 0.0;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const float zi = r[i] * dinv[(unsigned)i / 3u];
-    z[i] = zi;
-    rz += (double)r[i] * (double)zi;
-    if (!first) zq += (double)zi * (double)q[i];
-  }
-  const double v[2] = {rz, zq};
-  store_block_sums<2>(v, partials, sred);
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    z[i] = r[i] * dinv[(unsigned)i / 3u];
 }
 
-struct FcgFallbackFin {
-  SolverState* st;
-  __device__ void operator()(const double* t) const {
-    if (st->done || st->aux == 0.0) return;
-    const double RZ = t[0], ZQ = t[1];
-    const double beta = st->iter == 0 ? 0.0 : -ZQ / st->pq;
-    st->rz = RZ;
-    st->beta = beta;
-    st->aux = 0.0;
-    st->nfallback += 1;
-    if (!finite_val(RZ) || !finite_val(beta) || !(RZ > 0.0)) st->done = 3;
+// p_slot = z + sum_j beta_j p_j (the slot's old direction is read before it is replaced).
+__global__ __launch_bounds__(256) void fcgm_direction_kernel(const float* __restrict__ z, FcgWin w,
+                                                             const double* coef, float* pout,
+                                                             int n, const SolverState* st) {
+  if (st->done) return;
+  float b[kFcgMax];
+#pragma unroll
+  for (int j = 0; j < kFcgMax; ++j) b[j] = j < w.nw ? (float)coef[j] : 0.0f;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    float v = z[i];
+#pragma unroll
+    for (int j = 0; j < kFcgMax; ++j)
+      if (j < w.nw) v += b[j] * w.P[j][i];
+    pout[i] = v;
   }
-};
+}
+
+__global__ void fcg_store_pq_kernel(const SolverState* st, double* pq, int slot) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && !st->done) pq[slot] = st->pq;
+}
 
 // Two-stage preconditioner: n = network correction, then a Jacobi step on what remains,
 //   s = <r, n> / <n, K n> (energy-optimal scale of n; 0 unless both are positive),
@@ -646,16 +672,6 @@ __global__ __launch_bounds__(256) void two_stage_kernel(const float* __restrict_
   }
 }
 
-__global__ __launch_bounds__(256) void fcg_direction_kernel(const float* __restrict__ z,
-                                                            float* __restrict__ p, int n,
-                                                            const SolverState* st) {
-  if (st->done) return;
-  const bool first = st->iter == 0;
-  const float beta = (float)st->beta;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
-    p[i] = first ? z[i] : z[i] + beta * p[i];
-}
-
 }  // namespace tosimp
 
 // =========================================================================== host side
@@ -692,6 +708,11 @@ struct NNState {
   void* gbuf[6] = {};          // gradient scratch (largest level-0 sizes)
   float* gsum = nullptr;       // summed gradient of a training batch (master layout)
   float* x32 = nullptr;        // element density of the training pairs (FP32, for K n)
+  float* fcgP = nullptr;       // flexible CG: direction ring [fcg_cap][n_dof] and images
+  float* fcgQ = nullptr;
+  int fcg_cap = 0;
+  double* fpq = nullptr;       // <p_j, q_j> per ring slot
+  double* fco = nullptr;       // direction coefficients per ring slot
   int loss_kind = 0;           // 0: relative MSE to the unit-RMS error; 1: energy norm
   float* wpart = nullptr;      // weight-gradient partials
   size_t wpart_cap = 0;
@@ -774,7 +795,8 @@ void tosimp::nn_release(tosimp_ctx* ctx) {
   NNState* S = ctx ? nn_of(ctx) : nullptr;
   if (!S) return;
   void* ptrs[] = {S->master, S->m,        S->v,    S->grad, S->gpack, S->W,   S->WT, S->cat1,
-                  S->cat0,   S->wpart,    S->rho_node, S->scal, S->part, S->gsum, S->x32};
+                  S->cat0,   S->wpart,    S->rho_node, S->scal, S->part, S->gsum, S->x32,
+                  S->fcgP, S->fcgQ, S->fpq, S->fco};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : S->act)
@@ -989,16 +1011,30 @@ int nn_precond_t(tosimp_ctx* ctx, NNState* S, const float* x32, const float* r, 
   return TOSIMP_OK;
 }
 
-// Flexible CG with the learned preconditioner (see the FCG kernels above).  Vectors: r, p,
-// q in the FP32 workspace, z and K n in the FP64 scratch w (as floats); the iterate is e32.
+// Flexible CG, FCG(m), with the learned preconditioner (see the FCG kernels above).
+// Vectors: r in the FP32 workspace, z and K n in the FP64 scratch w (as floats), the m
+// directions and their images in the network state; the iterate is e32.
 int tosimp::nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const float* b32,
-                         float* e32, double tol, int maxit, int check_every, int* iters,
-                         int* fallbacks, int* done) {
+                         float* e32, double tol, int maxit, int check_every, int window,
+                         int* iters, int* fallbacks, int* done) {
   NNState* S = nn_of(ctx);
   if (!S) return tosimp_fail(ctx, TOSIMP_ESTATE, "NN preconditioner requested but no network");
+  if (window < 1) window = 1;
+  if (window > kFcgMax)
+    return tosimp_fail(ctx, TOSIMP_EINVAL, "flexible CG window must be at most 16");
   Workspace& w = ctx->ws;
-  float *r = w.r32, *p = w.p32, *q = w.q32, *z = (float*)w.w;
   const int n = (int)ctx->n_dof;
+  if (S->fcg_cap < window) {  // direction ring, grown on demand
+    if (S->fcgP) (void)hipFree(S->fcgP);
+    if (S->fcgQ) (void)hipFree(S->fcgQ);
+    S->fcgP = S->fcgQ = nullptr;
+    S->fcg_cap = 0;
+    if (nn_alloc((void**)&S->fcgP, (size_t)window * n * 4) != hipSuccess ||
+        nn_alloc((void**)&S->fcgQ, (size_t)window * n * 4) != hipSuccess)
+      return tosimp_fail(ctx, TOSIMP_ENOMEM, "flexible CG directions");
+    S->fcg_cap = window;
+  }
+  float *r = w.r32, *z = (float*)w.w;
   float* Kn = z + n;
   SolverState* st = w.st + 1;
   SolverState* sh = w.st_host + 1;
@@ -1011,32 +1047,47 @@ int tosimp::nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const floa
   TOSIMP_HIP(ctx, launch_fill_zero(ctx, e32, (int64_t)n * 4));
   double* part = w.partials;
   double* kvpart = w.partials + 2 * kMaxPartials;
-  TOSIMP_HIP(ctx, launch_pcg_init<float>(ctx, b32, nullptr, r, p, w.dinv32, st, part, 0));
+  // r = b (masked), ||r||, ||b||, tolerance; the direction written here is not used
+  TOSIMP_HIP(ctx, launch_pcg_init<float>(ctx, b32, nullptr, r, S->fcgP, w.dinv32, st, part, 0));
   const bool mfma = prec == TOSIMP_PREC_BF16_MFMA || prec == TOSIMP_PREC_FP16_MFMA;
   const int vb = std::min(2048, (n + 255) / 256);
   if (check_every < 1) check_every = 1;
+  FcgWin win{};
+  for (int j = 0; j < window; ++j) {
+    win.P[j] = S->fcgP + (size_t)j * n;
+    win.Q[j] = S->fcgQ + (size_t)j * n;
+  }
+  long long k = 0;  // iterations enqueued
   for (;;) {
     TOSIMP_HIP(ctx, hipMemcpyAsync(sh, st, sizeof(SolverState), hipMemcpyDeviceToHost, ctx->stream));
     TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (sh->done) break;
-    for (int i = 0; i < check_every; ++i) {
+    for (int i = 0; i < check_every; ++i, ++k) {
+      const int slot = (int)(k % window);
+      win.nw = (int)std::min<long long>(k, window);
+      float* P = S->fcgP + (size_t)slot * n;
+      float* Q = S->fcgQ + (size_t)slot * n;
       int rc = S->bf16 ? nn_precond_t<bf16_t>(ctx, S, x32, r, z, Kn, st, part, kvpart)
                        : nn_precond_t<float>(ctx, S, x32, r, z, Kn, st, part, kvpart);
       if (rc) return rc;
-      fcg_check_kernel<<<vb, 256, 0, ctx->stream>>>(r, z, q, n, st, part);
-      TOSIMP_HIP(ctx, launch_finalize_sum<2>(ctx->stream, part, vb, FcgCheckFin{st}));
-      fcg_fallback_kernel<<<vb, 256, 0, ctx->stream>>>(r, z, q, w.dinv32, n, st, part);
-      TOSIMP_HIP(ctx, launch_finalize_sum<2>(ctx->stream, part, vb, FcgFallbackFin{st}));
-      fcg_direction_kernel<<<vb, 256, 0, ctx->stream>>>(z, p, n, st);
+      fcgm_dots_kernel<<<vb, 256, 0, ctx->stream>>>(r, z, win, n, st, 0, part);
+      TOSIMP_HIP(ctx, launch_finalize_sum<1 + kFcgMax>(ctx->stream, part, vb,
+                                                      FcgmFin{st, S->fpq, S->fco, win.nw, 0}));
+      fcg_jacobi_z_kernel<<<vb, 256, 0, ctx->stream>>>(r, z, w.dinv32, n, st);
+      fcgm_dots_kernel<<<vb, 256, 0, ctx->stream>>>(r, z, win, n, st, 1, part);
+      TOSIMP_HIP(ctx, launch_finalize_sum<1 + kFcgMax>(ctx->stream, part, vb,
+                                                      FcgmFin{st, S->fpq, S->fco, win.nw, 1}));
+      fcgm_direction_kernel<<<vb, 256, 0, ctx->stream>>>(z, win, S->fco, P, n, st);
       TOSIMP_HIP(ctx, hipGetLastError());
       if (mfma) {
-        TOSIMP_HIP(ctx, kv_mfma_launch(ctx, prec, TOSIMP_F32, x32, p, q, st, true));
-        TOSIMP_HIP(ctx, launch_alpha_from_dot32(ctx, p, q, kvpart, st));
+        TOSIMP_HIP(ctx, kv_mfma_launch(ctx, prec, TOSIMP_F32, x32, P, Q, st, true));
+        TOSIMP_HIP(ctx, launch_alpha_from_dot32(ctx, P, Q, kvpart, st));
       } else {
-        TOSIMP_HIP(ctx, kv_launch(ctx, TOSIMP_PREC_FP32, TOSIMP_F32, x32, p, q, kvpart, st,
+        TOSIMP_HIP(ctx, kv_launch(ctx, TOSIMP_PREC_FP32, TOSIMP_F32, x32, P, Q, kvpart, st,
                                   nullptr, 1, true, true));
       }
-      TOSIMP_HIP(ctx, launch_pcg_update<float>(ctx, e32, r, p, q, w.dinv32, st, part));
+      fcg_store_pq_kernel<<<1, 64, 0, ctx->stream>>>(st, S->fpq, slot);
+      TOSIMP_HIP(ctx, launch_pcg_update<float>(ctx, e32, r, P, Q, w.dinv32, st, part));
     }
   }
   *iters = sh->iter;
@@ -1109,6 +1160,8 @@ int tosimp_nn_create(tosimp_ctx* ctx, int base, int bf16) {
   A((void**)&S->grad, mo * 4);
   A((void**)&S->gsum, mo * 4);
   A((void**)&S->x32, (size_t)ctx->n_elem * 4);
+  A((void**)&S->fpq, kFcgMax * 8);
+  A((void**)&S->fco, kFcgMax * 8);
   A((void**)&S->gpack, wo * 4);
   A(&S->W, wo * S->es);
   A(&S->WT, wo * S->es);

@@ -231,13 +231,14 @@ def _fcg_problem(nx=12, ny=6, nz=6, seed=7):
     return t, fixed, f, x
 
 
-def test_fcg_zero_network_is_jacobi_pcg():
+@pytest.mark.parametrize("window", [1, 8])
+def test_fcg_zero_network_is_jacobi_pcg(window):
     t, fixed, f, x = _fcg_problem()
     t.nn_create(16, bf16=True)
     t.nn_set_weights(np.zeros(t.nn_params, dtype=np.float32))
     kw = dict(tol=1e-8, mode="ir", inner_prec="fp32", inner_tol=1e-5, check_every=1)
     u1 = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
-    s_nn = t.pcg_solve(dev(x), dev(f), u1, precond="nn", **kw)
+    s_nn = t.pcg_solve(dev(x), dev(f), u1, precond="nn", fcg_window=window, **kw)
     u2 = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
     s_j = t.pcg_solve(dev(x), dev(f), u2, precond="jacobi", **kw)
     t.close()
@@ -268,13 +269,14 @@ def test_two_stage_preconditioner_matches_oracle(bf16, tol):
     assert rel(z, zo) <= tol
 
 
-def test_fcg_random_network_converges_to_direct_solution():
+@pytest.mark.parametrize("window", [1, 16])
+def test_fcg_random_network_converges_to_direct_solution(window):
     t, fixed, f, x = _fcg_problem()
     t.nn_create(16, bf16=True)
     t.nn_set_weights(_flat(nn.unet_init(BASE, 4, 3, seed=2)).astype(np.float32))
     u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
     s = t.pcg_solve(dev(x), dev(f), u, precond="nn", tol=1e-9, mode="ir", inner_prec="fp32",
-                    inner_tol=1e-5, check_every=1, maxit=5000)
+                    inner_tol=1e-5, check_every=1, maxit=5000, fcg_window=window)
     nx, ny, nz = t.dims
     t.close()
     assert s["rc"] in (0, 2)
@@ -283,6 +285,16 @@ def test_fcg_random_network_converges_to_direct_solution():
     u_ref = solvers.solve_direct(fem.constrain(fem.assemble_K(nx, ny, nz, E, fem.element_stiffness(0.3)),
                                                fem.fixed_mask(3 * (nx + 1) * (ny + 1) * (nz + 1), fixed)), f)
     assert rel(u.cpu().numpy(), u_ref) <= 1e-6
+
+
+def test_fcg_window_out_of_range_is_rejected():
+    from paper_2604_18020_amd import TosimpError
+    t, fixed, f, x = _fcg_problem()
+    t.nn_create(16, bf16=True)
+    u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(TosimpError):
+        t.pcg_solve(dev(x), dev(f), u, precond="nn", mode="ir", tol=1e-8, fcg_window=17)
+    t.close()
 
 
 def test_nn_precond_without_network_is_rejected():

@@ -195,3 +195,23 @@ def test_energy_loss_definition_gradient_and_exact_case():
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd))
     assert np.all(g[fixed] == 0)
 
+
+def test_fcg_window_equals_pcg_with_fixed_preconditioner_and_helps_variable_one():
+    nx, ny, nz = 6, 3, 3
+    rho = np.random.default_rng(15).uniform(0.2, 1, nx * ny * nz)
+    K = fem.assemble_K(nx, ny, nz, fem.simp_modulus(rho, 1.0, 1e-9, 3.0), fem.element_stiffness(0.3))
+    fixed = fem.fixed_mask(K.shape[0], si.cantilever_fixed_dofs(nx, ny, nz))
+    Kc = fem.constrain(K, fixed)
+    f = si.cantilever_load(nx, ny, nz)
+    d = Kc.diagonal()
+    _, it_p, h_p = solvers.pcg_jacobi(lambda v: Kc @ v, d, f, None, 1e-10)
+    for m in (1, 3, 8):
+        _, it_f, h_f = nn.fcg(lambda v: Kc @ v, lambda r: r / d, f, None, 1e-10, window=m)
+        assert abs(it_p - it_f) <= 2
+        assert np.max(np.abs(np.array(h_f[:30]) / np.array(h_p[:30]) - 1.0)) < 1e-8
+    # a preconditioner that changes every step: a longer window converges no slower
+    rng = np.random.default_rng(16)
+    noisy = lambda r: (r / d) * rng.uniform(0.5, 1.5, r.size)
+    its = [nn.fcg(lambda v: Kc @ v, noisy, f, None, 1e-8, window=m)[1] for m in (1, 8)]
+    assert its[1] <= its[0]
+
