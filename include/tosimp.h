@@ -87,6 +87,8 @@ typedef struct tosimp_solve_opts {
   int harvest_cap;   /*   harvest_every iterations (k = 0, he, 2 he, ...) until full;    */
   int harvest_every; /*   tosimp_nn_make_targets turns u_k into e_k = u* - u_k           */
   int fcg_window;    /* PRECOND_NN: flexible CG keeps this many directions (1..16; 0 = 1) */
+  int eager;         /* 1: launch every kernel directly; 0: Jacobi-PCG replays batches of */
+                     /*    check_every iterations as a HIP graph (same kernels, same order) */
 } tosimp_solve_opts;
 
 typedef struct tosimp_solve_stats {
@@ -169,7 +171,9 @@ int tosimp_diag_K(tosimp_ctx* ctx, const void* xphys_dev, int xdtype, void* d_de
  * Jacobi-PCG (or NN flexible CG) in FP32 vectors on the unit-norm residual with FP32
  * or MFMA operator; every dot product, norm, alpha and beta is accumulated in FP64.
  * Returns OK, NOT_CONVERGED (cap hit, u valid), FALLBACK_USED, EBREAKDOWN or
- * EPRECISION (enforce_rule and u_inner * kappa >= 1).  stats may be NULL.           */
+ * EPRECISION (enforce_rule and u_inner * kappa >= 1).  stats may be NULL.
+ * The solve runs on a stream of the context, ordered after the work already enqueued on
+ * the caller's stream and before any work enqueued there after the call.            */
 int tosimp_pcg_solve(tosimp_ctx* ctx, const double* xphys_dev, const double* b_dev,
                      double* u_inout_dev, const tosimp_solve_opts* opts,
                      tosimp_solve_stats* stats);

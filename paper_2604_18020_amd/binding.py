@@ -36,7 +36,8 @@ class SolveOpts(C.Structure):
                 ("inner_prec", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int),
                 ("precond", C.c_int), ("check_every", C.c_int), ("enforce_rule", C.c_int),
                 ("kappa", C.c_double), ("harvest_r", C.c_void_p), ("harvest_u", C.c_void_p),
-                ("harvest_cap", C.c_int), ("harvest_every", C.c_int), ("fcg_window", C.c_int)]
+                ("harvest_cap", C.c_int), ("harvest_every", C.c_int), ("fcg_window", C.c_int),
+                ("eager", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -208,10 +209,10 @@ class Tosimp:
     @staticmethod
     def solve_opts(tol=1e-8, maxit=20000, mode="plain_fp64", inner_prec="fp32",
                    inner_tol=1e-5, max_outer=30, precond="jacobi", check_every=16,
-                   enforce_rule=False, kappa=0.0, fcg_window=1):
+                   enforce_rule=False, kappa=0.0, fcg_window=1, eager=False):
         return SolveOpts(tol, maxit, SOLVE[mode], PREC[inner_prec], inner_tol, max_outer,
                          PRECOND[precond], check_every, int(enforce_rule), kappa, None, None,
-                         0, 0, int(fcg_window))
+                         0, 0, int(fcg_window), int(bool(eager)))
 
     def _opts_with_harvest(self, harvest, harvest_every, **kw):
         o = self.solve_opts(**kw)

@@ -208,6 +208,12 @@ int tosimp_destroy(tosimp_ctx* ctx) {
   if (!ctx) return TOSIMP_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->own_stream) {
+    (void)hipStreamSynchronize(ctx->own_stream);
+    (void)hipStreamDestroy(ctx->own_stream);
+    (void)hipEventDestroy(ctx->ev_in);
+    (void)hipEventDestroy(ctx->ev_out);
+  }
   free_ws(ctx);
   nn_release(ctx);
   delete ctx;
@@ -451,7 +457,7 @@ struct Harvest {
 template <typename T>
 int run_pcg(tosimp_ctx* ctx, int prec, const void* x, int xdtype, const T* b, T* u,
             const T* dinv, int slot, double tol, int maxit, int check_every, bool zero_guess,
-            PcgResult* res, const Harvest* hv = nullptr) {
+            PcgResult* res, const Harvest* hv = nullptr, bool graphs = false) {
   Workspace& w = ctx->ws;
   T *r, *p, *q;
   if constexpr (sizeof(T) == 8) {
@@ -479,6 +485,34 @@ int run_pcg(tosimp_ctx* ctx, int prec, const void* x, int xdtype, const T* b, T*
   }
   const bool mfma = prec == TOSIMP_PREC_BF16_MFMA || prec == TOSIMP_PREC_FP16_MFMA;
   if (check_every < 1) check_every = 1;
+  // One batch of check_every iterations (every kernel returns at once after convergence).
+  auto batch = [&]() -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < check_every && e == hipSuccess; ++i) {
+      if (mfma) {
+        // MFMA operator computes q only; the step length comes from a separate dot.
+        e = kv_mfma_launch(ctx, prec, xdtype, x, (const float*)p, (float*)q, st, true);
+        if (e == hipSuccess)
+          e = launch_alpha_from_dot32(ctx, (const float*)p, (const float*)q, kvpart, st);
+      } else {
+        e = kv_launch(ctx, prec, xdtype, x, p, q, kvpart, st, nullptr, 1, true, true);
+      }
+      if (e == hipSuccess) e = launch_pcg_update<T>(ctx, u, r, p, q, dinv, st, part);
+      if (e == hipSuccess) e = launch_pcg_direction<T>(ctx, r, p, dinv, st);
+    }
+    return e;
+  };
+  // After one eager batch, the batch is captured once into a HIP graph and replayed: on
+  // small meshes the iteration is bound by kernel launches.  The graph holds only this
+  // library's kernels (no memset or copy nodes).
+  hipGraphExec_t exec = nullptr;
+  int batches = 0;
+  struct ExecGuard {
+    hipGraphExec_t* e;
+    ~ExecGuard() {
+      if (*e) (void)hipGraphExecDestroy(*e);
+    }
+  } guard{&exec};
   for (;;) {
     TOSIMP_HIP(ctx, hipMemcpyAsync(sh, st, sizeof(SolverState), hipMemcpyDeviceToHost,
                                    ctx->stream));
@@ -492,18 +526,23 @@ int run_pcg(tosimp_ctx* ctx, int prec, const void* x, int xdtype, const T* b, T*
         res->harvested += 1;
       }
     }
-    for (int i = 0; i < check_every; ++i) {
-      if (mfma) {
-        // MFMA operator computes q only; the step length comes from a separate dot.
-        TOSIMP_HIP(ctx, kv_mfma_launch(ctx, prec, xdtype, x, (const float*)p, (float*)q, st,
-                                       true));
-        TOSIMP_HIP(ctx, launch_alpha_from_dot32(ctx, (const float*)p, (const float*)q, kvpart, st));
-      } else {
-        TOSIMP_HIP(ctx, kv_launch(ctx, prec, xdtype, x, p, q, kvpart, st, nullptr, 1, true, true));
-      }
-      TOSIMP_HIP(ctx, launch_pcg_update<T>(ctx, u, r, p, q, dinv, st, part));
-      TOSIMP_HIP(ctx, launch_pcg_direction<T>(ctx, r, p, dinv, st));
+    if (graphs && batches == 1 && !exec) {
+      hipGraph_t g = nullptr;
+      TOSIMP_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+      const hipError_t ce = batch();
+      const hipError_t ee = hipStreamEndCapture(ctx->stream, &g);
+      TOSIMP_HIP(ctx, ce);
+      TOSIMP_HIP(ctx, ee);
+      const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      TOSIMP_HIP(ctx, ie);
     }
+    if (exec) {
+      TOSIMP_HIP(ctx, hipGraphLaunch(exec, ctx->stream));
+    } else {
+      TOSIMP_HIP(ctx, batch());
+    }
+    ++batches;
   }
   res->iters = sh->iter;
   res->done = sh->done;
@@ -552,10 +591,12 @@ int norm2_host(tosimp_ctx* ctx, const double* a, int64_t n, double* out) {
 
 extern "C" {
 
-int tosimp_pcg_solve(tosimp_ctx* ctx, const double* x, const double* b, double* u,
-                     const tosimp_solve_opts* o, tosimp_solve_stats* stats) {
-  int rc = check_ready(ctx);
-  if (rc) return rc;
+}  // extern "C"
+
+namespace {
+int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
+                   const tosimp_solve_opts* o, tosimp_solve_stats* stats) {
+  int rc = 0;
   REQUIRE(x && b && u && o, TOSIMP_EINVAL, "null pointer");
   REQUIRE(o->tol > 0 && o->maxit >= 0, TOSIMP_EINVAL, "bad tol/maxit");
   REQUIRE(o->mode == TOSIMP_SOLVE_PLAIN_FP64 || o->mode == TOSIMP_SOLVE_IR, TOSIMP_EINVAL,
@@ -583,7 +624,7 @@ int tosimp_pcg_solve(tosimp_ctx* ctx, const double* x, const double* b, double* 
       every = o->harvest_every;
     }
     rc = run_pcg<double>(ctx, TOSIMP_PREC_FP64, x, TOSIMP_F64, b, u, w.dinv, 0, o->tol,
-                         o->maxit, every, false, &pr, hv.cap ? &hv : nullptr);
+                         o->maxit, every, false, &pr, hv.cap ? &hv : nullptr, !o->eager);
     if (rc) return rc;
     s.harvested = pr.harvested;
     s.iterations = pr.iters;
@@ -642,7 +683,8 @@ int tosimp_pcg_solve(tosimp_ctx* ctx, const double* x, const double* b, double* 
       } else {
         PcgResult pr;
         rc = run_pcg<float>(ctx, ip, w.x32, TOSIMP_F32, w.e32, w.z32, w.dinv32, 1,
-                            itol, o->maxit - total, o->check_every, true, &pr);
+                            itol, o->maxit - total, o->check_every, true, &pr, nullptr,
+                            !o->eager);
         if (rc) return rc;
         it = pr.iters;
         done = pr.done;
@@ -663,6 +705,35 @@ int tosimp_pcg_solve(tosimp_ctx* ctx, const double* x, const double* b, double* 
   if (stats) *stats = s;
   if (s.status < 0) return tosimp_fail(ctx, s.status, "solve failed (breakdown)");
   return s.status;
+}
+}  // namespace
+
+extern "C" {
+
+// The solve runs on the context's own stream (non-blocking, default priority), ordered
+// after the caller's stream by an event and before any later work on it by another, so
+// that its iteration batches can be captured as HIP graphs whatever stream the caller
+// uses (the legacy default stream cannot be captured).
+int tosimp_pcg_solve(tosimp_ctx* ctx, const double* x, const double* b, double* u,
+                     const tosimp_solve_opts* o, tosimp_solve_stats* stats) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(o, TOSIMP_EINVAL, "null pointer");
+  if ((rc = set_device(ctx))) return rc;
+  if (!ctx->own_stream) {
+    TOSIMP_HIP(ctx, hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
+    TOSIMP_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+    TOSIMP_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+  }
+  hipStream_t user = ctx->stream;
+  TOSIMP_HIP(ctx, hipEventRecord(ctx->ev_in, user));
+  TOSIMP_HIP(ctx, hipStreamWaitEvent(ctx->own_stream, ctx->ev_in, 0));
+  ctx->stream = ctx->own_stream;
+  rc = pcg_solve_impl(ctx, x, b, u, o, stats);
+  ctx->stream = user;
+  TOSIMP_HIP(ctx, hipEventRecord(ctx->ev_out, ctx->own_stream));
+  TOSIMP_HIP(ctx, hipStreamWaitEvent(user, ctx->ev_out, 0));
+  return rc;
 }
 
 // ===================================================================== SIMP pieces

@@ -95,7 +95,9 @@ struct Workspace {
 
 struct tosimp_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;     // the caller's stream
+  hipStream_t own_stream = nullptr; // the solver's stream (created on first use)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::string err;
   bool has_mesh = false, has_bcs = false, has_loads = false;
   int nx = 0, ny = 0, nz = 0;

@@ -134,3 +134,43 @@ def test_lanczos_extremes_match_dense(jacobi):
     ao, bo = solvers.lanczos_tridiagonal(lambda x: A @ x, v0[~fixed], 20)
     assert np.max(np.abs(a[:20] - ao)) <= 1e-11 * hi
     assert np.max(np.abs(b[:19] - bo)) <= 1e-11 * hi
+
+
+@pytest.mark.parametrize("mode", ["plain_fp64", "ir"])
+def test_graph_replay_matches_eager_bitwise(mode):
+    """Batches of check_every iterations replayed as a HIP graph (tens of replays, with
+    the host's polls and copies between them) give the same iterates as direct launches."""
+    nx, ny, nz = 24, 12, 12
+    t, fixed, f = gpu_problem(nx, ny, nz)
+    rho = np.random.default_rng(31).uniform(0.1, 1.0, nx * ny * nz)
+    kw = dict(tol=1e-9, check_every=8, mode=mode)
+    if mode == "ir":
+        kw.update(inner_prec="fp32", inner_tol=1e-4)
+    out = []
+    for eager in (True, False, False):
+        u = torch.zeros(f.size, dtype=torch.float64, device="cuda:0")
+        st = t.pcg_solve(dev(rho), dev(f), u, eager=eager, **kw)
+        out.append((u.cpu().numpy(), st["iterations"]))
+    t.close()
+    assert out[0][1] > 80  # many replays
+    for u, it in out[1:]:
+        assert it == out[0][1]
+        assert np.array_equal(u, out[0][0])
+
+
+def test_solve_on_a_side_stream():
+    nx, ny, nz = 16, 8, 8
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        t, fixed, f = gpu_problem(nx, ny, nz)
+        rho = dev(np.full(nx * ny * nz, 0.4))
+        b = dev(f)
+        u = torch.zeros(f.size, dtype=torch.float64, device="cuda:0")
+        st = t.pcg_solve(rho, b, u, tol=1e-10)
+        c = torch.dot(b, u)  # on the side stream, after the solve
+    side.synchronize()
+    Kc, _ = _oracle_system(nx, ny, nz, np.full(nx * ny * nz, 0.4))
+    u_ref = solvers.solve_direct(Kc, f)
+    t.close()
+    assert st["rc"] == 0
+    assert abs(float(c) - f @ u_ref) <= 1e-8 * abs(f @ u_ref)
