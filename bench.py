@@ -226,7 +226,7 @@ def _problem(workload):
     return t, cfg, fd, fixed
 
 
-def precision_study(workload="cantilever_340x170x85", lanczos_steps=400, tol=1e-6):
+def precision_study(workload="cantilever_340x170x85", lanczos_steps=1500, tol=1e-6):
     """Condition estimate (Lanczos, FP64) at uniform density, the precision rule
     u_l kappa < 1 for each inner precision, and refinement solves with FP32, BF16-MFMA and
     FP16-MFMA inner operators (rule not enforced, to show the outcome), each compared with

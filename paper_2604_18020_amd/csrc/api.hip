@@ -250,7 +250,10 @@ int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0
   REQUIRE(rmin > 0 && rmin <= kMaxFilterR + 1, TOSIMP_EINVAL, "rmin must be in (0, 4]");
   const int64_t n_elem = (int64_t)nx * ny * nz;
   const int64_t n_node = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
-  REQUIRE(3 * n_node < (int64_t)1 << 31, TOSIMP_EINVAL, "mesh too large (n_dof >= 2^31)");
+  // The fused operator addresses an FP64 DOF vector through a buffer resource with
+  // 32-bit byte offsets: 24 bytes per node must stay below 2^31 (89.4M nodes).
+  REQUIRE(24 * n_node < (int64_t)1 << 31, TOSIMP_EINVAL,
+          "mesh too large (more than 89,478,485 nodes)");
   int rc = set_device(ctx);
   if (rc) return rc;
   TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -279,7 +282,6 @@ int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0
                                             (dk - ctx->fR) * (dk - ctx->fR)));
         ctx->fw_host[di + W * (dj + W * dk)] = std::max(0.0, rmin - d);
       }
-  REQUIRE(kv_num_blocks(ctx) <= kMaxPartials, TOSIMP_EINVAL, "mesh too large for the tiling");
 
   Workspace& w = ctx->ws;
   const size_t nd = (size_t)ctx->n_dof, nn = (size_t)n_node, ne = (size_t)n_elem;
@@ -303,7 +305,9 @@ int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0
   A(dmalloc(&w.z32, nd * 4));
   A(dmalloc(&w.x32, ne * 4));
   A(dmalloc(&w.etmp, ne * 8 * 4));
-  A(dmalloc(&w.partials, sizeof(double) * kMaxPartials * 4));
+  // partial sums: 2 kMaxPartials for the vector kernels, then one slot per operator tile
+  w.kv_part_cap = std::max<int64_t>(2 * kMaxPartials, kv_num_blocks(ctx));
+  A(dmalloc(&w.partials, sizeof(double) * (2 * kMaxPartials + w.kv_part_cap)));
   A(dmalloc(&w.st, sizeof(SolverState) * 3));
   A(dmalloc(&w.oc, sizeof(OcState)));
   A(dmalloc(&w.ke_mfma, sizeof(uint16_t) * 2 * 2 * 64 * 8));

@@ -81,7 +81,8 @@ struct Workspace {
   float* z32 = nullptr;
   float* x32 = nullptr;        // n_elem FP32 density copy
   double* etmp = nullptr;      // n_elem scratch (x 4)
-  double* partials = nullptr;  // kMaxPartials x 4
+  double* partials = nullptr;  // 2 kMaxPartials + kv_part_cap
+  int64_t kv_part_cap = 0;     // operator tiles a fused dot may use
   uint16_t* ke_mfma = nullptr; // K_E in the MFMA A-operand layout: [bf16|f16][2][64][8]
   double* lanczos = nullptr;   // 2 x (kmax) alpha/beta on device
   int lanczos_cap = 0;

@@ -502,7 +502,7 @@ static hipError_t kv_launch_v(const tosimp_ctx* c, KvArgs<T, XT> A, bool guarded
   const KvGeom g = kv_geom_for(c, res, kv_kzmax<T>());
   A.tiles_x = g.tiles_x; A.tiles_y = g.tiles_y; A.chunks_z = g.chunks_z; A.kz = g.kz;
   A.ntiles = g.ntiles; A.per_xcd = g.per_xcd;
-  if (DOT && g.ntiles > 2 * kMaxPartials) return hipErrorInvalidValue;  // partial slots
+  if (DOT && g.ntiles > c->ws.kv_part_cap) return hipErrorInvalidValue;  // partial slots
   kern<<<dim3(g.grid), dim3(256), 0, c->stream>>>(A);
   if (!DOT) return hipGetLastError();
   const hipError_t e = hipGetLastError();

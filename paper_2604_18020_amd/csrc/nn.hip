@@ -106,9 +106,15 @@ struct ConvArgs {
   int apply_act;       // FWD: leaky ReLU on the output
 };
 
-// One wave: 16 "row" voxels of the result x a group of up to 64 result channels
+// One wave: RT x 16 "row" voxels of the result x a group of up to 64 result channels
 // (blockIdx.y selects the group).  FWD rows are output voxels, K = taps x cin, result
-// channels cout; BWD rows are input voxels, K = taps x cout, result channels cin.
+// channels cout; BWD rows are input voxels, K = taps x cout, result channels cin.  Each
+// K chunk of 32 loads the RT gathered A tiles and the weight tiles once and issues
+// RT x (channels / 16) matrix-core products.  RT = 4 (each weight tile serving four voxel
+// tiles) measured slower than RT = 1 on MI355X: the gathered activation loads need the
+// latency hiding of more waves more than the weight reuse.
+constexpr int kConvRT = 1;
+
 template <typename ST, bool BWD>
 __global__ __launch_bounds__(256) void conv_igemm_kernel(ConvArgs a) {
   const int lane = threadIdx.x & 63;
@@ -116,81 +122,97 @@ __global__ __launch_bounds__(256) void conv_igemm_kernel(ConvArgs a) {
   const Grid3 rg = BWD ? a.gin : a.gout;   // grid of the rows
   const Grid3 og = BWD ? a.gout : a.gin;   // grid the operand A is read from
   const int nrow = rg.n();
-  const int v0 = wave * 16;
+  const int v0 = wave * 16 * kConvRT;
   if (v0 >= nrow) return;
   const int kch = BWD ? a.cout : a.cin;    // channels along K
   const int nres = BWD ? a.cin : a.cout;   // result channels
   const int taps = a.ksize * a.ksize * a.ksize;
   const int K = taps * kch;
   const int m = lane & 15, q = lane >> 4;
-  const int v = v0 + m;
-  const bool vok = v < nrow;
-  const int vx = v % rg.X, vy = (v / rg.X) % rg.Y, vz = v / (rg.X * rg.Y);
   const int pad = a.ksize / 2;
   const ST* in = (const ST*)a.in;
   const ST* act = (const ST*)a.act;
   const ST* w = (const ST*)a.w;
   const int cg = blockIdx.y * 64;  // first result channel of this group
   const int nblk = min(4, (nres - cg) / 16);
-  f32x4 acc[4];
+  int vx[kConvRT], vy[kConvRT], vz[kConvRT];
+  bool vok[kConvRT];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) acc[b] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+  for (int r = 0; r < kConvRT; ++r) {
+    const int v = v0 + 16 * r + m;
+    vok[r] = v < nrow;
+    vx[r] = v % rg.X;
+    vy[r] = (v / rg.X) % rg.Y;
+    vz[r] = v / (rg.X * rg.Y);
+  }
+  f32x4 acc[kConvRT][4];
+#pragma unroll
+  for (int r = 0; r < kConvRT; ++r)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[r][b] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
 
   for (int k0 = 0; k0 < K; k0 += 32) {
     const int k = k0 + 8 * q;
-    Pack8<ST> A;
-    A.zero();
-    if (vok && k < K) {
-      const int t = k / kch, c = k - t * kch;
-      const int tx = t % a.ksize, ty = (t / a.ksize) % a.ksize, tz = t / (a.ksize * a.ksize);
-      int sx, sy, sz;
-      bool ok;
-      if (!BWD) {
-        sx = vx * a.stride + tx - pad;
-        sy = vy * a.stride + ty - pad;
-        sz = vz * a.stride + tz - pad;
-        ok = sx >= 0 && sx < og.X && sy >= 0 && sy < og.Y && sz >= 0 && sz < og.Z;
-      } else {
-        const int ux = vx + pad - tx, uy = vy + pad - ty, uz = vz + pad - tz;
-        ok = ux >= 0 && uy >= 0 && uz >= 0 && ux % a.stride == 0 && uy % a.stride == 0 &&
-             uz % a.stride == 0;
-        sx = ux / a.stride;
-        sy = uy / a.stride;
-        sz = uz / a.stride;
-        ok = ok && sx < og.X && sy < og.Y && sz < og.Z;
-      }
-      if (ok) {
-        const long long s = (long long)sx + (long long)og.X * (sy + (long long)og.Y * sz);
-        A.load(in + s * kch + c);
-        if (BWD && act) {
-          Pack8<ST> av;
-          av.load(act + s * kch + c);
-#pragma unroll
-          for (int j = 0; j < 8; ++j) A.set(j, A.get(j) * (av.get(j) > 0.0f ? 1.0f : kLeak));
-        }
-      }
-    }
+    const bool kok = k < K;
+    const int t = kok ? k / kch : 0, c = kok ? k - t * kch : 0;
+    const int tx = t % a.ksize, ty = (t / a.ksize) % a.ksize, tz = t / (a.ksize * a.ksize);
+    Pack8<ST> B[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      if (b < nblk) {
-        Pack8<ST> B;
-        B.zero();
-        if (k < K) B.load(w + (long long)(cg + b * 16 + m) * K + k);
-        mma32(acc[b], A, B);
+      B[b].zero();
+      if (b < nblk && kok) B[b].load(w + (long long)(cg + b * 16 + m) * K + k);
+    }
+#pragma unroll
+    for (int r = 0; r < kConvRT; ++r) {
+      Pack8<ST> A;
+      A.zero();
+      if (vok[r] && kok) {
+        int sx, sy, sz;
+        bool ok;
+        if (!BWD) {
+          sx = vx[r] * a.stride + tx - pad;
+          sy = vy[r] * a.stride + ty - pad;
+          sz = vz[r] * a.stride + tz - pad;
+          ok = sx >= 0 && sx < og.X && sy >= 0 && sy < og.Y && sz >= 0 && sz < og.Z;
+        } else {
+          const int ux = vx[r] + pad - tx, uy = vy[r] + pad - ty, uz = vz[r] + pad - tz;
+          ok = ux >= 0 && uy >= 0 && uz >= 0 && ux % a.stride == 0 && uy % a.stride == 0 &&
+               uz % a.stride == 0;
+          sx = ux / a.stride;
+          sy = uy / a.stride;
+          sz = uz / a.stride;
+          ok = ok && sx < og.X && sy < og.Y && sz < og.Z;
+        }
+        if (ok) {
+          const long long s = (long long)sx + (long long)og.X * (sy + (long long)og.Y * sz);
+          A.load(in + s * kch + c);
+          if (BWD && act) {
+            Pack8<ST> av;
+            av.load(act + s * kch + c);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) A.set(j, A.get(j) * (av.get(j) > 0.0f ? 1.0f : kLeak));
+          }
+        }
       }
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (b < nblk) mma32(acc[r][b], A, B[b]);
     }
   }
   ST* out = (ST*)a.out;
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    if (b < nblk) {
+  for (int r = 0; r < kConvRT; ++r) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = v0 + 4 * q + j;
-        if (row < nrow) {
-          float val = acc[b][j];
-          if (!BWD && a.apply_act) val = val > 0.0f ? val : kLeak * val;
-          out[(long long)row * nres + cg + b * 16 + m] = from_f<ST>(val);
+    for (int b = 0; b < 4; ++b) {
+      if (b < nblk) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = v0 + 16 * r + 4 * q + j;
+          if (row < nrow) {
+            float val = acc[r][b][j];
+            if (!BWD && a.apply_act) val = val > 0.0f ? val : kLeak * val;
+            out[(long long)row * nres + cg + b * 16 + m] = from_f<ST>(val);
+          }
         }
       }
     }
@@ -746,7 +768,7 @@ hipError_t conv_fwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* in, v
   a.ksize = l.k;
   a.stride = l.s;
   a.apply_act = act;
-  const int waves = (a.gout.n() + 15) / 16;
+  const int waves = (a.gout.n() + 16 * kConvRT - 1) / (16 * kConvRT);
   conv_igemm_kernel<ST, false><<<dim3((waves + 3) / 4, (a.cout + 63) / 64), 256, 0, c->stream>>>(a);
   return hipGetLastError();
 }
@@ -783,7 +805,7 @@ hipError_t conv_bwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* dY, c
     a.act = a_out;
     a.w = (const char*)S->WT + l.woff * S->es;
     a.out = dX;
-    const int waves = (a.gin.n() + 15) / 16;
+    const int waves = (a.gin.n() + 16 * kConvRT - 1) / (16 * kConvRT);
     conv_igemm_kernel<ST, true><<<dim3((waves + 3) / 4, (a.cin + 63) / 64), 256, 0, c->stream>>>(a);
   }
   return hipGetLastError();
