@@ -39,13 +39,13 @@ HBM_PEAK_GBS = 8000.0
 # valid only for the kernel sources they were taken with (sha256 of kv.hip, dev.h,
 # common.h); reported as null once those change.
 KV_TRAFFIC = {
-    "fp32": (2.0 * 47912.9 + 59025.2) * 1024,
-    "fp64": (2.0 * 94589.6 + 118005.5) * 1024,
+    "fp32": (2.0 * 47912.8 + 59015.7) * 1024,
+    "fp64": (2.0 * 94556.8 + 118030.0) * 1024,
 }
 KV_TRAFFIC_SOURCES = {
-    "kv.hip": "f1c2f710ebdcae96cffcff2c0bf2e863c5e347d334aee6c21f618efdb7108d68",
+    "kv.hip": "4b78517b58847eb8d8542e97e148ce93e8b007cfb80992c38fcd8bf9f8c36640",
     "dev.h": "8b034b72e2a61608c66958d1e7d70253194fbb2bdf91fc179096b8fecc73a390",
-    "common.h": "fb2e54c7aabc71b5962cc2a301edb95c019615f678e797a3976272ceee5ab4b4",
+    "common.h": "0fb34b47b783d116919f0bf6c6476b6389862f628453b920def55fa4c30fe055",
 }
 
 
@@ -182,7 +182,7 @@ def time_nn(workload="cantilever_200x100x50", simp_iters=10, per_solve=200, ever
     t_harvest = time.perf_counter() - t0
     t.nn_create(16, bf16=True)
     t.nn_set_weights(learned.he_normal_weights(t, 0))
-    t.nn_set_loss("energy")
+    t.nn_set_loss("mse")
     t0 = time.perf_counter()
     losses = learned.train(t, ps, train_steps, batch=batch, lr=lr)
     torch.cuda.synchronize()
@@ -193,14 +193,14 @@ def time_nn(workload="cantilever_200x100x50", simp_iters=10, per_solve=200, ever
                        f"iteration {simp_iters + 1}, cold start, tol {tol:g}",
            "pairs": int(sum(s["solve"]["harvested"] for s in stats)),
            "harvest_s": t_harvest, "train_steps": train_steps, "batch": batch,
-           "train_s": t_train, "loss": "energy norm of the best multiple of the correction",
+           "train_s": t_train, "loss": "relative MSE to the unit-RMS error",
            "loss_first50": float(np.mean(losses[:50])),
            "loss_last50": float(np.mean(losses[-50:]))}
     for name, kw in [("plain_fp64_jacobi", dict(mode="plain_fp64", check_every=64)),
                      ("ir_fp32_jacobi", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,
                                              check_every=64)),
                      ("ir_fp32_nn_fcg", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,
-                                             precond="nn", check_every=8, maxit=6000))]:
+                                             precond="nn", check_every=8, maxit=20000))]:
         _, r = _solve_timed(t, xp, f, tol, **kw)
         out[name] = r
     t.close()

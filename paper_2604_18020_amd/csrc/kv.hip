@@ -5,20 +5,24 @@
 // paper uses one thread per element, K_E in shared memory and atomic scatter.
 //
 // gfx950 design (deterministic, no atomics, one launch):
-//  * A block owns a 15 x 15 column of nodes and a chunk of node planes.  Its 256
-//    threads are the 16 x 16 element columns that touch those nodes (one halo element
-//    on the low side of each axis is recomputed by the neighbouring block).
-//  * The block streams up the z axis.  Each step stages one node plane of v (17 x 17
-//    nodes x 3 components, masked) in LDS with coalesced row loads that are prefetched
-//    one plane ahead.  Each thread applies the element stiffness of its element column
-//    at the current layer and keeps every partial result in registers in the 2D
-//    (x, y) Hadamard basis: the forward transform of a plane is reused as the bottom
-//    face of the next layer, and the top-face contributions of a layer are added to
-//    the bottom-face contributions of the next before a single inverse transform.
+//  * A block owns a 31 x 7 column of nodes and a chunk of node planes.  Its 256
+//    threads are the 32 x 8 element columns that touch those nodes (one halo element
+//    on the low side of each axis is recomputed by the neighbouring block); a row of 32
+//    element columns lies in one wavefront.
+//  * The block streams up the z axis.  Each step stages one node plane of v (33 x 9
+//    nodes x 3 components) in LDS with coalesced row loads issued one plane ahead.
+//    Each thread applies the element stiffness of its element column at the current
+//    layer and keeps every partial result in registers in the 2D (x, y) Hadamard basis:
+//    the forward transform of a plane is reused as the bottom face of the next layer,
+//    and the top-face contributions of a layer are added to the bottom-face
+//    contributions of the next before a single inverse transform.
 //  * K_E is applied in factored form K_E = H^T S H / 64 (45 non-zeros in S, eight
 //    distinct values, see common.h): about 150 VALU ops per element instead of 1,152.
-//  * Each node sums the four element-column contributions around it from LDS in a
-//    fixed order and is written once, coalesced.  Fixed DOFs output y = v.
+//  * Each owned node sums the four element-column contributions around it in a fixed
+//    order (the x pair by a lane shuffle, the y pair through LDS); finished planes are
+//    staged in LDS and written as coalesced row segments.  Fixed DOFs output y = v.
+//  * Operands known to be zero on fixed DOFs (all CG vectors) skip the BC bytes of the
+//    loaded planes; only the owned node's BC byte is read.
 //  * Block ids are remapped so that each XCD gets a contiguous range of tiles.
 //  * Optionally the block's share of <v, y> (FP64) is stored per tile and a one-block
 //    kernel finalises it (CG step length, Lanczos alpha).

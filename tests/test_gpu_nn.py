@@ -338,3 +338,15 @@ def test_energy_loss_gradient_matches_oracle(bf16, tol):
     errs = {name: rel(gg[name], grads[name]) for name, *_ in nn.unet_layers(BASE)}
     assert max(errs.values()) <= tol, errs
 
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 3)])
+def test_forward_on_degenerate_grids_matches_oracle(dims):
+    """Level grids of one or two nodes per axis (stride-2 convolutions down to 1 x 1 x 1)."""
+    nx, ny, nz = dims
+    t, _, _, params = _net(nx, ny, nz, bf16=False)
+    grid, x4 = _inputs(nx, ny, nz, seed=8)
+    out = t.nn_forward(dev(x4.reshape(-1))).cpu().numpy()
+    ref, _ = nn.unet_forward(params, _to_oracle(x4, grid, 4), BASE)
+    t.close()
+    assert rel(_to_oracle(out, grid, 3), ref) <= 1e-4
