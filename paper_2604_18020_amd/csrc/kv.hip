@@ -128,6 +128,10 @@ __device__ __forceinline__ double bit_select(double a, double b, unsigned sel) {
 // node's BC byte is read (fixed rows output y = v = 0).
 template <typename T, typename XT, bool P3, bool DOT, bool PM, int D, int KZMAX>
 __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
+  // Multiply-adds are fused only within one expression, never across statements, so
+  // every z step rounds identically whatever was folded away around it (a chunk's first
+  // layer starts from zero accumulators): results do not depend on the chunk depth.
+#pragma clang fp contract(on)
   constexpr int NXL = KBX + 1, NYL = KBY + 1, ROW = 3 * NXL, NPV = ROW * NYL;
   constexpr int NLD = (NPV + 255) / 256;
   constexpr int NE = KBX * KBY;
