@@ -67,7 +67,10 @@ def kv_bytes(prec: str, n_node: int, n_elem: int) -> int:
     return 2 * 3 * w * n_node + w * n_elem + n_node
 
 
-def time_kv(t, nx, ny, nz, prec, steps, warmup, fixed, seed=42):
+def time_kv(t, nx, ny, nz, prec, steps, warmup, fixed, seed=42, resident=False):
+    """Per-launch HIP-event timing of the operator as the CG iterations apply it.  Buffer
+    sets are rotated so that >= 512 MB are touched (the 256 MB Infinity Cache cannot hold
+    them); resident=True uses one set ("MALL-resident" figures)."""
     import numpy as np
     import torch
 
@@ -79,7 +82,7 @@ def time_kv(t, nx, ny, nz, prec, steps, warmup, fixed, seed=42):
     # block; fixed rows are identity), with the library told so
     v[fixed] = 0.0
     set_bytes = kv_bytes(prec, t.n_node, t.n_elem)
-    nset = max(2, -(-512 * 2 ** 20 // set_bytes))
+    nset = 1 if resident else max(2, -(-512 * 2 ** 20 // set_bytes))
     xs = [torch.tensor(rho, dtype=dt, device="cuda:0") for _ in range(nset)]
     vs = [torch.tensor(v, dtype=dt, device="cuda:0") for _ in range(nset)]
     ys = [torch.empty_like(vs[0]) for _ in range(nset)]
@@ -140,6 +143,13 @@ def time_pcg(t, nx, ny, nz, tol, volfrac=0.3):
 
     f = torch.tensor(si.cantilever_load(nx, ny, nz), device="cuda:0")
     t.set_loads(f)
+    return pcg_compare(t, f, tol, volfrac)
+
+
+def pcg_compare(t, f, tol, volfrac=0.3):
+    """The solves of time_pcg for a context whose BCs and loads are set (f on device)."""
+    import torch
+
     x = torch.full((t.n_elem,), volfrac, dtype=torch.float64, device="cuda:0")
     _, ref = _solve_timed(t, x, f, 1e-10, mode="plain_fp64", check_every=64)
     out = {"reference_compliance_tol1e-10": ref["compliance"]}
@@ -314,6 +324,47 @@ def simp_study(workload, iters=None, tol=None):
     return out
 
 
+def kv_reps(n_elem):
+    """Launches per K v timing: 5e7 / n_elem, at least 100 and at most 2,000."""
+    return max(100, min(2000, int(5e7 // n_elem)))
+
+
+def kv_study(workloads=("cantilever_120x60x30", "cantilever_340x170x85")):
+    """K v in every precision, HBM-bound (rotated buffer sets) and MALL-resident (one
+    set), on the K v microbenchmark inputs."""
+    out = {}
+    for w in workloads:
+        t, cfg, _, fixed = _problem(w)
+        nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+        reps = kv_reps(t.n_elem)
+        res = {"launches": reps}
+        for p in ("fp64", "fp32", "bf16_mfma", "fp16_mfma"):
+            res[p] = {}
+            for label, resident in (("hbm", False), ("mall_resident", True)):
+                r = time_kv(t, nx, ny, nz, p, reps, 10, fixed, resident=resident)
+                us = r["avg_launch_ms"] * 1e3
+                res[p][label] = {"avg_launch_us": us, "median_launch_us": r["median_launch_ms"] * 1e3,
+                                 "gdof_s": t.n_dof / (us * 1e-6) / 1e9,
+                                 "algorithmic_gbs": r["bytes"] / (us * 1e-6) / 1e9,
+                                 "frac_of_8tbs": r["bytes"] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                 "buffer_sets": r["buffer_sets"], "finite": r["finite"]}
+        out[w] = res
+        t.close()
+    return out
+
+
+def pcg_cold_study(workloads=("cantilever_120x60x30", "torsion_55x55x165",
+                              "cantilever_200x100x50"), tol=1e-6):
+    """Cold-start PCG at uniform density on the other benchmark meshes (the main line
+    covers 340x170x85): plain FP64 against FP32 refinement, compliance against 1e-10."""
+    out = {}
+    for w in workloads:
+        t, cfg, f, _ = _problem(w)
+        out[w] = pcg_compare(t, f, tol, cfg["volfrac"])
+        t.close()
+    return out
+
+
 def cpu_baseline(budget_s=20.0):
     """The oracle's element-by-element K v (gather, dense 24x24 product, scatter-add)
     on the 120x60x30 mesh, repeated until ~budget_s of CPU time."""
@@ -373,6 +424,8 @@ def main():
     from paper_2604_18020_amd import Tosimp
 
     if a.suite:
+        print(json.dumps({"kv_study": kv_study()}), flush=True)
+        print(json.dumps({"pcg_cold_study": pcg_cold_study()}), flush=True)
         print(json.dumps({"precision_study": precision_study()}), flush=True)
         print(json.dumps({"simp_study": simp_study("cantilever_120x60x30")}), flush=True)
         print(json.dumps({"simp_study": simp_study("torsion_55x55x165")}), flush=True)
