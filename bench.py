@@ -39,13 +39,13 @@ HBM_PEAK_GBS = 8000.0
 # valid only for the kernel sources they were taken with (sha256 of kv.hip, dev.h,
 # common.h); reported as null once those change.
 KV_TRAFFIC = {
-    "fp32": (2.0 * 49157.8 + 59079.7) * 1024,
-    "fp64": (2.0 * 94615.6 + 117993.4) * 1024,
+    "fp32": (2.0 * 49142.2 + 59152.5) * 1024,
+    "fp64": (2.0 * 94573.8 + 118002.0) * 1024,
 }
 KV_TRAFFIC_SOURCES = {
     "kv.hip": "8982e55833ad3a7f1d53cfd980a316220a546b3c816cf4d9484c87f4bf83d548",
     "dev.h": "8b034b72e2a61608c66958d1e7d70253194fbb2bdf91fc179096b8fecc73a390",
-    "common.h": "0fb34b47b783d116919f0bf6c6476b6389862f628453b920def55fa4c30fe055",
+    "common.h": "9dc818e6f7573b73d7463e4772be341a0c339abd126bd10f350fb271356785cf",
 }
 
 

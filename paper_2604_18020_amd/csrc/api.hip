@@ -501,8 +501,9 @@ int run_pcg(tosimp_ctx* ctx, int prec, const void* x, int xdtype, const T* b, T*
       } else {
         e = kv_launch(ctx, prec, xdtype, x, p, q, kvpart, st, nullptr, 1, true, true);
       }
-      if (e == hipSuccess) e = launch_pcg_update<T>(ctx, u, r, p, q, dinv, st, part);
-      if (e == hipSuccess) e = launch_pcg_direction<T>(ctx, r, p, dinv, st);
+      // r and the step length first; u moves with the direction update (one read of p)
+      if (e == hipSuccess) e = launch_pcg_update<T>(ctx, nullptr, r, nullptr, q, dinv, st, part);
+      if (e == hipSuccess) e = launch_pcg_direction<T>(ctx, r, p, u, dinv, st);
     }
     return e;
   };
@@ -548,6 +549,8 @@ int run_pcg(tosimp_ctx* ctx, int prec, const void* x, int xdtype, const T* b, T*
     }
     ++batches;
   }
+  // the step of the iteration that ended the solve, if its direction update did not run
+  TOSIMP_HIP(ctx, launch_pcg_finish<T>(ctx, u, p, st));
   res->iters = sh->iter;
   res->done = sh->done;
   res->rr = sh->rr;

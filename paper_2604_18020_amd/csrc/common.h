@@ -49,6 +49,7 @@ struct SolverState {
   int maxit;      // iteration cap
   int done;       // 0 running, 1 converged, 2 cap, 3 breakdown
   int nfallback;  // flexible CG: preconditioner fallbacks taken
+  int upend;      // Jacobi-PCG: the last iteration's u += alpha p is still to be applied
 };
 
 // Device-side state of the OC bisection.
@@ -150,12 +151,15 @@ hipError_t launch_finalize_dot(const tosimp_ctx* c, const double* partials, int 
 template <typename T>
 hipError_t launch_pcg_init(const tosimp_ctx* c, const T* b, const T* Ku, T* r, T* p,
                            const void* dinv, SolverState* st, double* partials, int use_Ku);
+// u == nullptr: u is left to launch_pcg_direction (and launch_pcg_finish).
 template <typename T>
 hipError_t launch_pcg_update(const tosimp_ctx* c, T* u, T* r, const T* p, const T* q,
                              const void* dinv, SolverState* st, double* partials);
 template <typename T>
-hipError_t launch_pcg_direction(const tosimp_ctx* c, const T* r, T* p, const void* dinv,
+hipError_t launch_pcg_direction(const tosimp_ctx* c, const T* r, T* p, T* u, const void* dinv,
                                 SolverState* st);
+template <typename T>
+hipError_t launch_pcg_finish(const tosimp_ctx* c, T* u, const T* p, SolverState* st);
 hipError_t launch_mask_vec(const tosimp_ctx* c, double* v);
 hipError_t launch_residual64(const tosimp_ctx* c, const double* b, const double* Ku,
                              double* r, double* partials, SolverState* st);

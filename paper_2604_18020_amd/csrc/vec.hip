@@ -86,10 +86,11 @@ __device__ __forceinline__ void vset(typename Vec<T>::type& v, int k, T x) {
   reinterpret_cast<T*>(&v)[k] = x;
 }
 
-// u += alpha p, r -= alpha q; block sums of ||r||^2 and <r, r dinv> (PcgUpdateFin then
-// counts the iteration, tests convergence and forms beta).  Flat over DOFs, 16 bytes per
-// lane per array (the node of DOF i is i / 3; n_dof < 2^31, so 32-bit arithmetic).
-template <typename T>
+// r -= alpha q and (WU) u += alpha p; block sums of ||r||^2 and <r, r dinv>
+// (PcgUpdateFin then counts the iteration, tests convergence and forms beta).  Flat over
+// DOFs, 16 bytes per lane per array (the node of DOF i is i / 3; n_dof < 2^31, so 32-bit
+// arithmetic).  Jacobi-PCG leaves u to the direction kernel, which reads p anyway.
+template <typename T, bool WU>
 __global__ __launch_bounds__(kRedThreads) void pcg_update_kernel(
     T* __restrict__ u, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
     const T* __restrict__ dinv, int n_dof, SolverState* st, double* partials) {
@@ -101,29 +102,31 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update_kernel(
   double rr = 0.0, rz = 0.0;
   const int nvec = n_dof / W;
   for (int v = blockIdx.x * kRedThreads + threadIdx.x; v < nvec; v += gridDim.x * kRedThreads) {
-    VT uv = reinterpret_cast<const VT*>(u)[v];
-    const VT pv = reinterpret_cast<const VT*>(p)[v];
     VT rv = reinterpret_cast<const VT*>(r)[v];
     const VT qv = reinterpret_cast<const VT*>(q)[v];
+    if constexpr (WU) {
+      VT uv = reinterpret_cast<const VT*>(u)[v];
+      const VT pv = reinterpret_cast<const VT*>(p)[v];
+#pragma unroll
+      for (int k = 0; k < W; ++k) vset<T>(uv, k, vget<T>(uv, k) + alpha * vget<T>(pv, k));
+      reinterpret_cast<VT*>(u)[v] = uv;
+    }
 #pragma unroll
     for (int k = 0; k < W; ++k) {
       const unsigned i = (unsigned)(v * W + k);
       const T d = dinv[i / 3u];
-      const T uu = vget<T>(uv, k) + alpha * vget<T>(pv, k);
       const T rn = vget<T>(rv, k) - alpha * vget<T>(qv, k);
-      vset<T>(uv, k, uu);
       vset<T>(rv, k, rn);
       rr += (double)rn * (double)rn;
       rz += (double)rn * (double)(rn * d);
     }
-    reinterpret_cast<VT*>(u)[v] = uv;
     reinterpret_cast<VT*>(r)[v] = rv;
   }
   // tail (n_dof not a multiple of W), handled by block 0
   if (blockIdx.x == 0) {
     for (int i = nvec * W + threadIdx.x; i < n_dof; i += kRedThreads) {
       const T d = dinv[(unsigned)i / 3u];
-      u[i] += alpha * p[i];
+      if constexpr (WU) u[i] += alpha * p[i];
       const T rn = r[i] - alpha * q[i];
       r[i] = rn;
       rr += (double)rn * (double)rn;
@@ -134,9 +137,12 @@ __global__ __launch_bounds__(kRedThreads) void pcg_update_kernel(
   store_block_sums<2>(v, partials, sred);
 }
 
-// Counts the iteration, tests convergence and forms beta.
+// Counts the iteration, tests convergence and forms beta.  When the iteration ends the
+// solve and u is left to the direction kernel (which then does not run), the step
+// u += alpha p is marked pending for pcg_finish_kernel.
 struct PcgUpdateFin {
   SolverState* st;
+  int u_deferred;
   __device__ void operator()(const double* t) const {
     if (st->done) return;
     const double RR = t[0], RZ = t[1];
@@ -148,22 +154,31 @@ struct PcgUpdateFin {
     if (!finite_val(RR) || !finite_val(beta)) st->done = 3;
     else if (RR <= st->tol2) st->done = 1;
     else if (st->iter >= st->maxit) st->done = 2;
+    if (st->done && u_deferred) st->upend = 1;
   }
 };
 
-// p = r dinv + beta p, flat over DOFs, 16 bytes per lane.
+// u += alpha p (when u is given) and p = r dinv + beta p, flat over DOFs, 16 bytes per
+// lane: the old p is read once for both.
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void pcg_direction_kernel(
-    const T* __restrict__ r, T* __restrict__ p, const T* __restrict__ dinv, int n_dof,
-    const SolverState* st) {
+    const T* __restrict__ r, T* __restrict__ p, T* __restrict__ u, const T* __restrict__ dinv,
+    int n_dof, const SolverState* st) {
   typedef typename Vec<T>::type VT;
   constexpr int W = Vec<T>::W;
   if (st->done) return;
+  const T alpha = (T)st->alpha;
   const T beta = (T)st->beta;
   const int nvec = n_dof / W;
   for (int v = blockIdx.x * kRedThreads + threadIdx.x; v < nvec; v += gridDim.x * kRedThreads) {
     const VT rv = reinterpret_cast<const VT*>(r)[v];
     VT pv = reinterpret_cast<const VT*>(p)[v];
+    if (u) {
+      VT uv = reinterpret_cast<const VT*>(u)[v];
+#pragma unroll
+      for (int k = 0; k < W; ++k) vset<T>(uv, k, vget<T>(uv, k) + alpha * vget<T>(pv, k));
+      reinterpret_cast<VT*>(u)[v] = uv;
+    }
 #pragma unroll
     for (int k = 0; k < W; ++k) {
       const unsigned i = (unsigned)(v * W + k);
@@ -172,8 +187,31 @@ __global__ __launch_bounds__(kRedThreads) void pcg_direction_kernel(
     reinterpret_cast<VT*>(p)[v] = pv;
   }
   if (blockIdx.x == 0)
-    for (int i = nvec * W + threadIdx.x; i < n_dof; i += kRedThreads)
+    for (int i = nvec * W + threadIdx.x; i < n_dof; i += kRedThreads) {
+      if (u) u[i] += alpha * p[i];
       p[i] = r[i] * dinv[(unsigned)i / 3u] + beta * p[i];
+    }
+}
+
+// The step u += alpha p of the iteration that ended the solve (see PcgUpdateFin).
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void pcg_finish_kernel(T* __restrict__ u,
+                                                                 const T* __restrict__ p,
+                                                                 int n_dof, const SolverState* st) {
+  typedef typename Vec<T>::type VT;
+  constexpr int W = Vec<T>::W;
+  if (!st->upend) return;
+  const T alpha = (T)st->alpha;
+  const int nvec = n_dof / W;
+  for (int v = blockIdx.x * kRedThreads + threadIdx.x; v < nvec; v += gridDim.x * kRedThreads) {
+    VT uv = reinterpret_cast<const VT*>(u)[v];
+    const VT pv = reinterpret_cast<const VT*>(p)[v];
+#pragma unroll
+    for (int k = 0; k < W; ++k) vset<T>(uv, k, vget<T>(uv, k) + alpha * vget<T>(pv, k));
+    reinterpret_cast<VT*>(u)[v] = uv;
+  }
+  if (blockIdx.x == 0)
+    for (int i = nvec * W + threadIdx.x; i < n_dof; i += kRedThreads) u[i] += alpha * p[i];
 }
 
 template <typename T>
@@ -188,16 +226,26 @@ template <typename T>
 hipError_t launch_pcg_update(const tosimp_ctx* c, T* u, T* r, const T* p, const T* q,
                              const void* dinv, SolverState* st, double* partials) {
   const int nb = vec_blocks(c);
-  pcg_update_kernel<T><<<nb, kRedThreads, 0, c->stream>>>(u, r, p, q, (const T*)dinv,
-                                                          (int)c->n_dof, st, partials);
-  return launch_finalize_sum<2>(c->stream, partials, nb, PcgUpdateFin{st});
+  if (u)
+    pcg_update_kernel<T, true><<<nb, kRedThreads, 0, c->stream>>>(
+        u, r, p, q, (const T*)dinv, (int)c->n_dof, st, partials);
+  else
+    pcg_update_kernel<T, false><<<nb, kRedThreads, 0, c->stream>>>(
+        nullptr, r, nullptr, q, (const T*)dinv, (int)c->n_dof, st, partials);
+  return launch_finalize_sum<2>(c->stream, partials, nb, PcgUpdateFin{st, u ? 0 : 1});
 }
 
 template <typename T>
-hipError_t launch_pcg_direction(const tosimp_ctx* c, const T* r, T* p, const void* dinv,
+hipError_t launch_pcg_direction(const tosimp_ctx* c, const T* r, T* p, T* u, const void* dinv,
                                 SolverState* st) {
-  pcg_direction_kernel<T><<<vec_blocks(c), kRedThreads, 0, c->stream>>>(r, p, (const T*)dinv,
-                                                                       (int)c->n_dof, st);
+  pcg_direction_kernel<T><<<vec_blocks(c), kRedThreads, 0, c->stream>>>(
+      r, p, u, (const T*)dinv, (int)c->n_dof, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pcg_finish(const tosimp_ctx* c, T* u, const T* p, SolverState* st) {
+  pcg_finish_kernel<T><<<vec_blocks(c), kRedThreads, 0, c->stream>>>(u, p, (int)c->n_dof, st);
   return hipGetLastError();
 }
 
@@ -214,9 +262,13 @@ template hipError_t launch_pcg_update<float>(const tosimp_ctx*, float*, float*, 
                                              const float*, const void*, SolverState*,
                                              double*);
 template hipError_t launch_pcg_direction<double>(const tosimp_ctx*, const double*, double*,
-                                                 const void*, SolverState*);
-template hipError_t launch_pcg_direction<float>(const tosimp_ctx*, const float*, float*,
+                                                 double*, const void*, SolverState*);
+template hipError_t launch_pcg_direction<float>(const tosimp_ctx*, const float*, float*, float*,
                                                 const void*, SolverState*);
+template hipError_t launch_pcg_finish<double>(const tosimp_ctx*, double*, const double*,
+                                              SolverState*);
+template hipError_t launch_pcg_finish<float>(const tosimp_ctx*, float*, const float*,
+                                             SolverState*);
 
 // ------------------------------------------------------------------ misc vectors
 __global__ void mask_vec_kernel(double* v, const uint8_t* mask, int64_t n_dof) {
