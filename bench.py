@@ -39,11 +39,11 @@ HBM_PEAK_GBS = 8000.0
 # valid only for the kernel sources they were taken with (sha256 of kv.hip, dev.h,
 # common.h); reported as null once those change.
 KV_TRAFFIC = {
-    "fp32": (2.0 * 49142.2 + 59152.5) * 1024,
-    "fp64": (2.0 * 94573.8 + 118002.0) * 1024,
+    "fp32": (2.0 * 49115.2 + 59283.2) * 1024,
+    "fp64": (2.0 * 94548.1 + 118109.0) * 1024,
 }
 KV_TRAFFIC_SOURCES = {
-    "kv.hip": "8982e55833ad3a7f1d53cfd980a316220a546b3c816cf4d9484c87f4bf83d548",
+    "kv.hip": "1f304fefd1d26b37ccd0c22f57760132c89092ce8e54c45a8a71ee11257a2c13",
     "dev.h": "8b034b72e2a61608c66958d1e7d70253194fbb2bdf91fc179096b8fecc73a390",
     "common.h": "9dc818e6f7573b73d7463e4772be341a0c339abd126bd10f350fb271356785cf",
 }

@@ -19,8 +19,10 @@
 //  * K_E is applied in factored form K_E = H^T S H / 64 (45 non-zeros in S, eight
 //    distinct values, see common.h): about 150 VALU ops per element instead of 1,152.
 //  * Each owned node sums the four element-column contributions around it in a fixed
-//    order (the x pair by a lane shuffle, the y pair through LDS); finished planes are
-//    staged in LDS and written as coalesced row segments.  Fixed DOFs output y = v.
+//    order (the x pair by a DPP shift of the wave by one lane, the y pair through LDS);
+//    finished planes are staged in LDS and written as coalesced row segments, the
+//    plane's base in the scalar buffer resource.  Fixed DOFs output y = v (a branch
+//    that only waves holding a clamped node take).
 //  * Operands known to be zero on fixed DOFs (all CG vectors) skip the BC bytes of the
 //    loaded planes; only the owned node's BC byte is read.
 //  * Block ids are remapped so that each XCD gets a contiguous range of tiles.
@@ -83,6 +85,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, lo
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, kRsrcWord3);
 }
 
+// For byte counts already known to be below 2^31 (the launcher's size limit).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc32(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kRsrcWord3);
+}
+
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 template <typename T>
@@ -123,6 +130,19 @@ __device__ __forceinline__ double bit_select(double a, double b, unsigned sel) {
                                         (__builtin_bit_cast(unsigned long long, b) & m));
 }
 
+// The value of lane l + 1 in lane l (a DPP shift of the whole wave by one lane; lane 63
+// reads 0).  The compiler folds the move into the instruction that consumes it.
+__device__ __forceinline__ float lane_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_next(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x130, 0xF, 0xF, false);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x130, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // PM: v is known to be zero on fixed DOFs (every vector the CG iterations apply K_c to
 // is), so the plane's BC bytes are not loaded and v needs no masking; only the owned
 // node's BC byte is read (fixed rows output y = v = 0).
@@ -159,7 +179,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   const int elayer = A.nx * A.ny;
   // One resource per array for the whole launch; planes move in the scalar offset.
   const auto rv = make_rsrc(A.v, 3LL * n_node * (long long)sizeof(T));
-  const auto ry = make_rsrc(A.y, 3LL * n_node * (long long)sizeof(T));
+  const int ybytes = 3 * n_node * (int)sizeof(T);  // < 2^31 (launcher's node limit)
   const auto rm = make_rsrc(A.mask, n_node);
   const auto rx = make_rsrc(A.x, (long long)elayer * A.nz * (long long)sizeof(XT));
   const int vplane_bytes = 3 * plane * (int)sizeof(T);
@@ -231,11 +251,14 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   // ELEM) apply element layer p-1 and (when OUT) emit node plane p-1.
   // Coalesced write of a finished output plane q from so[q & 1]: every thread stores its
   // flat slots that hold an owned node (row segments of the interleaved vector).
+  // The plane's base moves into the (scalar) resource, so the per-lane offsets stay
+  // loop-invariant and soffset stays zero.
   auto store_plane = [&](int q) {
     const T* src = so[q & 1];
-    const unsigned qoff = (unsigned)(vplane_bytes * q);
+    const int qb = vplane_bytes * q;
+    const auto ryq = make_rsrc32(reinterpret_cast<const char*>(A.y) + qb, ybytes - qb);
 #pragma unroll
-    for (int s = 0; s < NLD; ++s) buf_st(src[tid + 256 * s], ry, ooff[s] + qoff);
+    for (int s = 0; s < NLD; ++s) buf_st(src[tid + 256 * s], ryq, ooff[s]);
   };
 
   T ya[3];  // upper-row corner pair of the owned node, kept across the barrier
@@ -326,14 +349,14 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
         // The owned node (lx+1, ly+1) sums corner (1,1) of this column, (0,1) of column
         // lx+1, (1,0) of column (lx, ly+1) and (0,0) of (lx+1, ly+1).  The x neighbour
         // is the next lane (rows are 32 lanes, lane 31 owns no node), so the pairs
-        // along x come from a lane shuffle; only the pair of the row below goes
+        // along x come from the next lane (lane_next); only the pair of the row below goes
         // through LDS.
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const T u0 = R[0 * 3 + c] - R[2 * 3 + c], u1 = R[1 * 3 + c] - R[3 * 3 + c];
           const T w0 = R[0 * 3 + c] + R[2 * 3 + c], w1 = R[1 * 3 + c] + R[3 * 3 + c];
           const T c00 = u0 - u1, c10 = u0 + u1, c01 = w0 - w1, c11 = w0 + w1;
-          const T n01 = __shfl_down(c01, 1, 64), n00 = __shfl_down(c00, 1, 64);
+          const T n01 = lane_next(c01), n00 = lane_next(c00);
           ya[c] = c11 + n01;
           sb[c * NE + tid] = c10 + n00;
         }
@@ -346,12 +369,19 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
       // Node plane p-1: sum the four element columns around the owned node into so; the
       // next step stores it (after its first barrier).
       T* dst = so[(p - 1) & 1];
+      T yv[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) yv[c] = ya[c] + sb[c * NE + tid + KBX];
+      // Fixed rows are identity (y = v).  Only nodes on the clamped boundary have fixed
+      // DOFs, so almost every wave skips this branch.
+      if (mown) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) yv[c] = bit_select(yv[c], vown[c], (mown >> c) & 1);
+      }
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        T yv = ya[c] + sb[c * NE + tid + KBX];
-        yv = bit_select(yv, vown[c], (mown >> c) & 1);  // fixed rows are identity: y = v
-        if (owner) dst[sown + c] = yv;
-        if constexpr (DOT) dotacc += owner ? (double)vown[c] * (double)yv : 0.0;
+        if (owner) dst[sown + c] = yv[c];
+        if constexpr (DOT) dotacc += owner ? (double)vown[c] * (double)yv[c] : 0.0;
       }
     }
   };
