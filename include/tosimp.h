@@ -132,8 +132,9 @@ const char* tosimp_version(void);
  * E_e = Emin + x_e^penal (E0 - Emin); Poisson ratio nu in (-1, 0.5); density-filter
  * radius rmin > 0 (in element edges).  Builds the 24x24 element stiffness by 2x2x2
  * Gauss quadrature and its exact factorisation in the tensor Hadamard basis, the filter
- * weights, and allocates the workspace (EINVAL on bad sizes, ENOMEM on failure).
- * Clears any previous boundary conditions and loads.                                 */
+ * weights, and allocates the workspace (EINVAL on bad sizes, among them meshes of more
+ * than 89,478,484 nodes, the limit of the operator's 32-bit byte offsets into an FP64
+ * DOF vector; ENOMEM on failure).  Clears any previous boundary conditions and loads. */
 int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0,
                     double Emin, double nu, double penal, double rmin);
 /* Dirichlet set: `n` DOF ids (host, any order, duplicates allowed) held at zero.

@@ -251,9 +251,10 @@ int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0
   const int64_t n_elem = (int64_t)nx * ny * nz;
   const int64_t n_node = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   // The fused operator addresses an FP64 DOF vector through a buffer resource with
-  // 32-bit byte offsets: 24 bytes per node must stay below 2^31 (89.4M nodes).
-  REQUIRE(24 * n_node < (int64_t)1 << 31, TOSIMP_EINVAL,
-          "mesh too large (more than 89,478,485 nodes)");
+  // 32-bit byte offsets and gives lanes outside the mesh the offset 0x7FFFFFF0, which
+  // must lie past the end of every array: 24 bytes per node <= 0x7FFFFFF0.
+  REQUIRE(24 * n_node <= (int64_t)0x7FFFFFF0, TOSIMP_EINVAL,
+          "mesh too large (more than 89,478,484 nodes)");
   int rc = set_device(ctx);
   if (rc) return rc;
   TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));

@@ -113,14 +113,15 @@ def test_bad_arguments_raise():
 
 
 def _samples(nx, ny, nz, rng, n=1500):
-    """Sample DOFs uniformly plus on tile and chunk seams of the operator's blocking."""
+    """Sample DOFs uniformly plus on tile seams (blocks own 31 x 7 node columns) and z
+    chunk seams (chunks of 9-13 planes at the benchmark size) and the last planes."""
     NX1, NY1 = nx + 1, ny + 1
     pick = list(rng.integers(0, 3 * NX1 * NY1 * (nz + 1), n))
     for _ in range(300):
-        i = int(rng.choice([0, 14, 15, 29, 30, nx - 1, nx]))
-        j = int(rng.choice([0, 14, 15, 29, 30, ny - 1, ny]))
-        k = int(rng.choice([0, 1, 10, 11, 21, 22, nz - 1, nz]))
-        pick.append(3 * (i + NX1 * (j + NY1 * k)) + int(rng.integers(0, 3)))
+        i = int(rng.choice([0, 1, 30, 31, 61, 62, nx - 1, nx]))
+        j = int(rng.choice([0, 1, 6, 7, 13, 14, ny - 1, ny]))
+        k = int(rng.choice([0, 1, 9, 10, 11, 12, 13, 21, 22, nz - 1, nz]))
+        pick.append(3 * (min(i, nx) + NX1 * (min(j, ny) + NY1 * min(k, nz))) + int(rng.integers(0, 3)))
     return np.array(pick, dtype=np.int64)
 
 
@@ -243,3 +244,42 @@ def test_apply_K_smooth_displacement_within_rounding_bound(record_property):
     # the cancellation is real: |K| |u| exceeds |K u| by orders of magnitude
     assert np.linalg.norm(bound[free]) > 1e3 * np.linalg.norm(y_ref[free])
     t.close()
+
+
+def test_set_mesh_rejects_meshes_beyond_the_offset_limit():
+    """126 x 112 x 6234 elements have 127 * 113 * 6235 = 89,478,485 nodes: an FP64 DOF
+    vector would span 2,147,483,640 bytes, past the operator's out-of-range offset
+    0x7FFFFFF0, so the mesh is refused before anything is allocated."""
+    from paper_2604_18020_amd import Tosimp, TosimpError
+    t = Tosimp(0)
+    with pytest.raises(TosimpError):
+        t.set_mesh(126, 112, 6234)
+    t.set_mesh(2, 2, 2)  # the context stays usable
+    t.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_K_near_the_size_limit_sampled(prec):
+    """126 x 112 x 6233 elements (89,464,134 nodes, 99.98% of the limit): plane offsets
+    reach 2^31 - 3.4e5 bytes in FP64.  Sampled outputs, the top planes included, against
+    the oracle's rows."""
+    nx, ny, nz = 126, 112, 6233
+    t, fixed, _ = gpu_problem(nx, ny, nz)
+    rho, v = si.random_density_and_vector(nx, ny, nz, seed=17)
+    if prec == "fp64":
+        y = t.apply_K(dev(rho), dev(v)).cpu().numpy()
+        tol = 1e-12
+    else:
+        y = t.apply_K(dev(rho, torch.float32), dev(v, torch.float32), prec="fp32").double().cpu().numpy()
+        tol = 2e-5
+    t.close()
+    rng = np.random.default_rng(3)
+    NX1, NY1 = nx + 1, ny + 1
+    top = [3 * (int(i) + NX1 * (int(j) + NY1 * k)) + int(c)
+           for k in (nz - 1, nz) for i, j, c in zip(rng.integers(0, NX1, 200),
+                                                     rng.integers(0, NY1, 200),
+                                                     rng.integers(0, 3, 200))]
+    dofs = np.concatenate([_samples(nx, ny, nz, rng, n=600), np.array(top, dtype=np.int64)])
+    y_ref = fem.apply_K_rows(nx, ny, nz, rho, v, fixed, dofs, KE)
+    assert np.max(np.abs(y[dofs] - y_ref)) <= tol * np.max(np.abs(y_ref))
+    assert np.all(np.isfinite(y[dofs]))
