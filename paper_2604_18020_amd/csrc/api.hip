@@ -91,7 +91,7 @@ bool hadamard_consts(const double* KE, HadConsts* hc, double* max_dev) {
         if ((m >> d) & 1) s *= ((a >> d) & 1) ? 1.0 : -1.0;
       for (int c = 0; c < 3; ++c) H[3 * m + c][3 * a + c] = s;
     }
-  static double S[24][24];
+  double S[24][24];
   double T[24][24];
   for (int i = 0; i < 24; ++i)
     for (int j = 0; j < 24; ++j) {

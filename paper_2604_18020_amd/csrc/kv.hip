@@ -28,6 +28,8 @@
 //  * Block ids are remapped so that each XCD gets a contiguous range of tiles.
 //  * Optionally the block's share of <v, y> (FP64) is stored per tile and a one-block
 //    kernel finalises it (CG step length, Lanczos alpha).
+#include <atomic>
+
 #include "common.h"
 #include "dev.h"
 
@@ -534,9 +536,17 @@ static int resident_blocks(const tosimp_ctx* c, K kernel) {
 template <typename T, typename XT, bool P3, bool DOT, bool PM>
 static hipError_t kv_launch_v(const tosimp_ctx* c, KvArgs<T, XT> A, bool guarded) {
   auto kern = guarded ? kv_stream_guarded<T, XT, P3, DOT, PM> : kv_stream<T, XT, P3, DOT, PM>;
-  static int resident[2] = {0, 0};
-  int& res = resident[guarded ? 1 : 0];
-  if (res == 0) res = resident_blocks(c, kern);
+  // Resident blocks per device and kernel instance, computed once (concurrent first calls
+  // compute the same value; devices beyond the table are queried every time).
+  constexpr int kDevs = 64;
+  static std::atomic<int> resident[kDevs][2];
+  int res = 0;
+  const bool cached = c->device >= 0 && c->device < kDevs;
+  if (cached) res = resident[c->device][guarded ? 1 : 0].load(std::memory_order_relaxed);
+  if (res == 0) {
+    res = resident_blocks(c, kern);
+    if (cached) resident[c->device][guarded ? 1 : 0].store(res, std::memory_order_relaxed);
+  }
   const KvGeom g = kv_geom_for(c, res, kv_kzmax<T>());
   A.tiles_x = g.tiles_x; A.tiles_y = g.tiles_y; A.chunks_z = g.chunks_z; A.kz = g.kz;
   A.ntiles = g.ntiles; A.per_xcd = g.per_xcd;
