@@ -10,7 +10,8 @@
 //    on the low side of each axis is recomputed by the neighbouring block); a row of 32
 //    element columns lies in one wavefront.
 //  * The block streams up the z axis.  Each step stages one node plane of v (33 x 9
-//    nodes x 3 components) in LDS with coalesced row loads issued one plane ahead.
+//    nodes x 3 components) in LDS with coalesced row loads issued ahead (two planes
+//    in FP32, one in FP64).
 //    Each thread applies the element stiffness of its element column at the current
 //    layer and keeps every partial result in registers in the 2D (x, y) Hadamard basis:
 //    the forward transform of a plane is reused as the bottom face of the next layer,
@@ -465,11 +466,11 @@ struct KvGeom {
   int tiles_x, tiles_y, chunks_z, kz, ntiles, per_xcd, grid;
 };
 
-// Tiling of the node grid: 15 x 15 node columns per block and `kz` node planes per
-// chunk.  A chunk of kz planes costs kz + 2 plane loads, so deep chunks waste less;
-// but the whole grid runs in ceil(ntiles / resident) rounds of equal blocks, so the
-// chunk count is chosen to minimise rounds * (kz + 2) for the number of blocks the
-// GPU keeps resident (occupancy x CUs).
+// Tiling of the node grid: (KBX-1) x (KBY-1) = 31 x 7 node columns per block and `kz`
+// node planes per chunk.  A chunk of kz planes costs kz + 2 plane loads, so deep chunks
+// waste less; but the whole grid runs in ceil(ntiles / resident) rounds of equal blocks,
+// so the chunk count is chosen to minimise rounds * (kz + 2) for the number of blocks
+// the GPU keeps resident (occupancy x CUs).
 static KvGeom kv_geom_for(const tosimp_ctx* c, int resident, int kzmax) {
   KvGeom g;
   g.tiles_x = (c->nx + 1 + KBX - 2) / (KBX - 1);

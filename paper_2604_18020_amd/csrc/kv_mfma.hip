@@ -7,8 +7,9 @@
 // product in FP32.  On gfx950 one 16x16x32 MFMA covers the whole padded K = 24 -> 32
 // reduction, so a 16-element group needs two MFMAs (output rows 0-15 and 16-31).
 //
-// Structure: the same owner-computes z sweep as the FP32/FP64 kernel (15 x 15 owned
-// nodes per block, one node plane staged per step), with the element stage replaced by
+// Structure: the owner-computes z sweep of the FP32/FP64 kernel on 16 x 16 element-column
+// tiles (15 x 15 owned nodes per block, one node plane staged per step), with the
+// element stage replaced by
 //   1. each wave gathers, for 4 groups of 16 element columns, the 24 masked DOFs of each
 //      element from the two LDS node planes in the MFMA B-operand lane layout
 //      (lane l: element l % 16 of the group, DOFs 8 (l / 16) .. + 7), converts them,
