@@ -283,3 +283,49 @@ def test_apply_K_near_the_size_limit_sampled(prec):
     y_ref = fem.apply_K_rows(nx, ny, nz, rho, v, fixed, dofs, KE)
     assert np.max(np.abs(y[dofs] - y_ref)) <= tol * np.max(np.abs(y_ref))
     assert np.all(np.isfinite(y[dofs]))
+
+
+def test_apply_K_every_dof_fixed_is_identity():
+    """With every DOF fixed K_c = I: y = v exactly in every precision, and a solve of a
+    zero load converges at once to u = 0."""
+    from paper_2604_18020_amd import Tosimp
+    nx, ny, nz = 9, 5, 4
+    t = Tosimp(0).set_mesh(nx, ny, nz)
+    n_dof = 3 * (nx + 1) * (ny + 1) * (nz + 1)
+    t.set_bcs(np.arange(n_dof))
+    rho, v = si.random_density_and_vector(nx, ny, nz, seed=8)
+    assert np.array_equal(t.apply_K(dev(rho), dev(v)).cpu().numpy(), v)
+    v32 = v.astype(np.float32)
+    for prec in ("fp32", "bf16_mfma", "fp16_mfma"):
+        y = t.apply_K(dev(rho, torch.float32), dev(v32), prec=prec).cpu().numpy()
+        assert np.array_equal(y, v32), prec
+    t.set_loads(torch.zeros(n_dof, dtype=torch.float64, device="cuda:0"))
+    u = torch.ones(n_dof, dtype=torch.float64, device="cuda:0")
+    st = t.pcg_solve(dev(rho), torch.zeros(n_dof, dtype=torch.float64, device="cuda:0"), u,
+                     tol=1e-8)
+    t.close()
+    assert st["iterations"] == 0 and st["rc"] == 0
+    assert torch.count_nonzero(u).item() == 0
+
+
+@pytest.mark.parametrize("penal", [3.0, 2.5])
+@pytest.mark.parametrize("level", [0.0, 1.0])
+def test_apply_K_density_extremes(level, penal):
+    """x = 0 everywhere (E = Emin: K scaled by 1e-9; the general-penalty path takes
+    x^p = 0 without evaluating pow at 0) and x = 1 (E = E0), FP64 and FP32."""
+    nx, ny, nz = 17, 9, 11
+    t, fixed, _ = gpu_problem(nx, ny, nz, penal=penal)
+    rho = np.full(nx * ny * nz, level)
+    _, v = si.random_density_and_vector(nx, ny, nz, seed=9)
+    y_ref = _oracle_y(nx, ny, nz, rho, v, fixed, penal=penal)
+    free = ~fem.fixed_mask(v.size, fixed)
+    y = t.apply_K(dev(rho), dev(v)).cpu().numpy()
+    # free rows against their own scale (1e-9 of the fixed rows' when x = 0)
+    assert maxrel(y[free], y_ref[free]) <= 1e-12
+    assert np.array_equal(y[~free], v[~free])
+    v32 = v.astype(np.float32)
+    y32 = t.apply_K(dev(rho, torch.float32), dev(v32), prec="fp32").double().cpu().numpy()
+    y32_ref = _oracle_y(nx, ny, nz, rho, v32.astype(np.float64), fixed, penal=penal)
+    assert rel(y32[free], y32_ref[free]) <= 1e-5
+    assert np.array_equal(y32[~free], v32[~free].astype(np.float64))
+    t.close()
