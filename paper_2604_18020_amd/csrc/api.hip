@@ -858,9 +858,9 @@ int tosimp_lanczos(tosimp_ctx* ctx, const double* x, const double* v0, int k, in
   SolverState* st = w.st + 2;
   double* s_node = nullptr;
   if (jacobi) {
+    // sqrt(dinv) per node, in place (every solve recomputes w.dinv at its start)
     TOSIMP_HIP(ctx, launch_diag_inv(ctx, x, w.dinv, nullptr));
-    s_node = (double*)w.etmp;  // sqrt(dinv) per node needs n_node <= 4 n_elem doubles
-    REQUIRE(ctx->n_node <= 4 * ctx->n_elem, TOSIMP_EINVAL, "mesh too thin for Lanczos scratch");
+    s_node = w.dinv;
     TOSIMP_HIP(ctx, launch_sqrt_node(ctx, w.dinv, s_node));
   }
   double *q = w.p, *qprev = w.q, *wv = w.w, *tmp = w.r;

@@ -174,3 +174,27 @@ def test_solve_on_a_side_stream():
     t.close()
     assert st["rc"] == 0
     assert abs(float(c) - f @ u_ref) <= 1e-8 * abs(f @ u_ref)
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_lanczos_past_the_free_dimension(jacobi):
+    """More steps than free DOFs (2 x 1 x 1: 24 free DOFs, 60 steps): the Krylov space is
+    exhausted, so beta reaches zero or rounding level; the returned tridiagonal is finite
+    and its extremes are the free block's eigenvalue extremes."""
+    from paper_2604_18020_amd import tridiag_extremes
+    nx, ny, nz = 2, 1, 1
+    rho = np.array([0.3, 0.9])
+    Kc, f = _oracle_system(nx, ny, nz, rho)
+    fixed = fem.fixed_mask(f.size, si.cantilever_fixed_dofs(nx, ny, nz))
+    assert int((~fixed).sum()) == 24
+    lo, hi = solvers.kappa_dense(solvers.free_block(Kc, fixed), jacobi_scaled=jacobi)
+    t, _, _ = gpu_problem(nx, ny, nz)
+    v0 = np.random.default_rng(5).standard_normal(f.size)
+    v0[fixed] = 0.0
+    a, b = t.lanczos(dev(rho), dev(v0), 60, jacobi_scaled=jacobi)
+    t.close()
+    assert 1 <= len(a) <= 60 and len(b) == len(a) - 1
+    assert np.all(np.isfinite(a)) and np.all(np.isfinite(b))
+    lmin, lmax = tridiag_extremes(a, b)
+    assert abs(lmax - hi) <= 1e-8 * hi
+    assert abs(lmin - lo) <= 1e-8 * hi
