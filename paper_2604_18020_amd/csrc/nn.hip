@@ -219,12 +219,32 @@ __global__ __launch_bounds__(256) void conv_igemm_kernel(ConvArgs a) {
   }
 }
 
-// Weight gradient, one block per (chunk of cvox output voxels, tap): the block's four
-// waves split the (cout/16) x (cin/16) tiles; K = the chunk's voxels, 8 per lane group.
-// Partial sums go to part[chunk][cout][taps][cin]; conv_wgrad_reduce sums the chunks in
-// index order.  cvox is a multiple of 32.
+// Weight gradient, one block per (chunk of cvox output voxels, tap, group of up to 32
+// (cout/16 x cin/16) tiles).  Per step of kc voxels (a multiple of 32 dividing cvox,
+// as many as fit 32 KB of LDS) the block stages dZ = dY leaky'(a)
+// and the tap's input rows X[nbr(o, t)] in LDS, both transposed to [channel][voxel], with
+// coalesced 16-byte row loads; each lane's eight consecutive voxels of a channel are then
+// one 16-byte LDS read, and each wave issues one matrix-core product per tile it owns
+// (K = the chunk's voxels in order, 8 per lane group).  Partial sums go to
+// part[chunk][cout][taps][cin]; conv_wgrad_reduce sums the chunks in index order.
+// cvox is a multiple of 256, cout of 16, cin of 8.
+constexpr int kWgPad = 8;           // LDS row pitch kc + 8 elements (rows stay 16-byte aligned)
+constexpr int kWgTiles = 8;         // tiles per wave and block group
+constexpr int kWgLds = 32768;       // LDS budget of the staged step
+
+__device__ __forceinline__ void put_elem(bf16_t* p, const Pack8<bf16_t>& a, int j) {
+  p->bits = a.v[j];
+}
+__device__ __forceinline__ void put_elem(float* p, const Pack8<float>& a, int j) { *p = a.v[j]; }
+
 template <typename ST>
-__global__ __launch_bounds__(256) void conv_wgrad_kernel(ConvArgs a, float* part, int cvox) {
+__global__ __launch_bounds__(256) void conv_wgrad_kernel(ConvArgs a, float* part, int cvox,
+                                                         int kc) {
+  extern __shared__ __align__(16) unsigned char wg_smem[];
+  const int cout = a.cout, cin = a.cin;
+  const int pitch = kc + kWgPad;
+  ST* sdz = reinterpret_cast<ST*>(wg_smem);    // [cout][pitch]
+  ST* sxt = sdz + (size_t)cout * pitch;         // [cin][pitch]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int chunk = blockIdx.x, t = blockIdx.y;
   const int taps = a.ksize * a.ksize * a.ksize;
@@ -233,41 +253,78 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(ConvArgs a, float* part
   const ST* X = (const ST*)a.in;   // layer input [Vin][cin]
   const ST* dY = (const ST*)a.out; // gradient wrt the layer output [Vout][cout]
   const ST* act = (const ST*)a.act;
-  const int nco = a.cout / 16, nci = (a.cin + 15) / 16;
+  const int nci = (cin + 15) / 16;
+  const int tile_end = min((cout / 16) * nci, (int)(blockIdx.z + 1) * 4 * kWgTiles);
+  const int tile0 = blockIdx.z * 4 * kWgTiles + wv;  // this wave: tile0, tile0 + 4, ...
   const int m = lane & 15, q = lane >> 4;
   const int Vout = a.gout.n();
-  for (int tile = wv; tile < nco * nci; tile += 4) {
-    const int cb = tile / nci, ib = tile % nci;
-    const int co = cb * 16 + m, ci = ib * 16 + m;
-    f32x4 acc = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < cvox; k0 += 32) {
-      Pack8<ST> A, B;  // A: dZ^T (co x voxels), B: X_t (voxels x ci)
+  const int c8o = cout / 8, c8i = cin / 8;
+  f32x4 acc[kWgTiles];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int o = chunk * cvox + k0 + 8 * q + j;
-        float dz = 0.0f, xv = 0.0f;
-        if (o < Vout) {
-          dz = to_f(dY[(long long)o * a.cout + co]);
-          if (act) dz *= to_f(act[(long long)o * a.cout + co]) > 0.0f ? 1.0f : kLeak;
-          const int ox = o % a.gout.X, oy = (o / a.gout.X) % a.gout.Y, oz = o / (a.gout.X * a.gout.Y);
-          const int sx = ox * a.stride + tx - pad, sy = oy * a.stride + ty - pad,
-                    sz = oz * a.stride + tz - pad;
-          if (ci < a.cin && sx >= 0 && sx < a.gin.X && sy >= 0 && sy < a.gin.Y && sz >= 0 &&
-              sz < a.gin.Z)
-            xv = to_f(X[((long long)sx + (long long)a.gin.X * (sy + (long long)a.gin.Y * sz)) *
-                            a.cin + ci]);
+  for (int j = 0; j < kWgTiles; ++j) acc[j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < cvox; k0 += kc) {
+    __syncthreads();  // the previous stage's reads are done
+    for (int idx = threadIdx.x; idx < kc * c8o; idx += 256) {
+      const int v = idx / c8o, c8 = idx - v * c8o;
+      const int o = chunk * cvox + k0 + v;
+      Pack8<ST> d;
+      d.zero();
+      if (o < Vout) {
+        d.load(dY + (long long)o * cout + 8 * c8);
+        if (act) {
+          Pack8<ST> av;
+          av.load(act + (long long)o * cout + 8 * c8);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) d.set(j, d.get(j) * (av.get(j) > 0.0f ? 1.0f : kLeak));
         }
-        A.set(j, dz);
-        B.set(j, xv);
       }
-      mma32(acc, A, B);
-    }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int orow = cb * 16 + 4 * q + j;  // co
-      const int ocol = ib * 16 + m;          // ci
-      if (ocol < a.cin)
-        part[(((long long)chunk * a.cout + orow) * taps + t) * a.cin + ocol] = acc[j];
+      for (int j = 0; j < 8; ++j) put_elem(sdz + (8 * c8 + j) * pitch + v, d, j);
+    }
+    for (int idx = threadIdx.x; idx < kc * c8i; idx += 256) {
+      const int v = idx / c8i, c8 = idx - v * c8i;
+      const int o = chunk * cvox + k0 + v;
+      Pack8<ST> xv;
+      xv.zero();
+      if (o < Vout) {
+        const int ox = o % a.gout.X, oy = (o / a.gout.X) % a.gout.Y, oz = o / (a.gout.X * a.gout.Y);
+        const int sx = ox * a.stride + tx - pad, sy = oy * a.stride + ty - pad,
+                  sz = oz * a.stride + tz - pad;
+        if (sx >= 0 && sx < a.gin.X && sy >= 0 && sy < a.gin.Y && sz >= 0 && sz < a.gin.Z)
+          xv.load(X + ((long long)sx + (long long)a.gin.X * (sy + (long long)a.gin.Y * sz)) * cin +
+                  8 * c8);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) put_elem(sxt + (8 * c8 + j) * pitch + v, xv, j);
+    }
+    __syncthreads();
+    for (int ks = 0; ks < kc; ks += 32) {
+#pragma unroll
+      for (int j = 0; j < kWgTiles; ++j) {
+        const int tile = tile0 + 4 * j;
+        if (tile < tile_end) {
+          const int cb = tile / nci, ib = tile % nci;
+          const int ci = ib * 16 + m;
+          Pack8<ST> A, B;
+          A.load(sdz + (cb * 16 + m) * pitch + ks + 8 * q);
+          if (ci < cin) B.load(sxt + ci * pitch + ks + 8 * q); else B.zero();
+          mma32(acc[j], A, B);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kWgTiles; ++j) {
+    const int tile = tile0 + 4 * j;
+    if (tile < tile_end) {
+      const int cb = tile / nci, ib = tile % nci;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int orow = cb * 16 + 4 * q + jj;  // co
+        const int ocol = ib * 16 + m;           // ci
+        if (ocol < cin)
+          part[(((long long)chunk * cout + orow) * taps + t) * cin + ocol] = acc[j][jj];
+      }
     }
   }
 }
@@ -795,7 +852,13 @@ hipError_t conv_bwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* dY, c
     const int nchunk = (a.gout.n() + cvox - 1) / cvox;
     const size_t need = (size_t)nchunk * l.cop * taps * l.cip;
     if (need > S->wpart_cap) return hipErrorInvalidValue;
-    conv_wgrad_kernel<ST><<<dim3(nchunk, taps), 256, 0, c->stream>>>(b, S->wpart, cvox);
+    const int ntile = (l.cop / 16) * ((l.cip + 15) / 16);
+    const int ngroup = (ntile + 4 * kWgTiles - 1) / (4 * kWgTiles);
+    int kc = 256;  // voxels per staged step: the largest power of two fitting the budget
+    while (kc > 32 && (size_t)(l.cop + l.cip) * (kc + kWgPad) * S->es > (size_t)kWgLds) kc /= 2;
+    const size_t smem = (size_t)(l.cop + l.cip) * (kc + kWgPad) * S->es;
+    conv_wgrad_kernel<ST><<<dim3(nchunk, taps, ngroup), 256, smem, c->stream>>>(b, S->wpart,
+                                                                                cvox, kc);
     const int n = l.cop * taps * l.cip;
     conv_wgrad_reduce<<<(n + 255) / 256, 256, 0, c->stream>>>(S->wpart, nchunk, n,
                                                               S->gpack + l.goff, 0);
