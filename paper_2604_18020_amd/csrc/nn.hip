@@ -111,12 +111,20 @@ struct ConvArgs {
 // channels cout; BWD rows are input voxels, K = taps x cout, result channels cin.  Each
 // K chunk of 32 loads the RT gathered A tiles and the weight tiles once and issues
 // RT x (channels / 16) matrix-core products.  RT = 4 (each weight tile serving four voxel
-// tiles) measured slower than RT = 1 on MI355X: the gathered activation loads need the
-// latency hiding of more waves more than the weight reuse.
+// tiles) measured slower than RT = 1 on MI355X, RT = 2 the same, and so did issuing the
+// loads of two to four K chunks before their products (12-70% slower): the gathered
+// activation loads need the latency hiding of more waves more than weight reuse or
+// in-wave overlap, which cost registers and with them waves.
 constexpr int kConvRT = 1;
 
+// BF16: the accumulators are held in ordinary VGPRs (no AGPR split), which lets eight
+// (forward) or seven (data gradient) waves share a SIMD instead of six or five; the
+// loads are latency-bound, so the extra waves shorten a forward pass by ~6%.  FP32
+// needs more registers than that bound allows and keeps the compiler's choice.
 template <typename ST, bool BWD>
-__global__ __launch_bounds__(256) void conv_igemm_kernel(ConvArgs a) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(ST) == 2 ? (BWD ? 7 : 8) : 1)))
+void conv_igemm_kernel(ConvArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const Grid3 rg = BWD ? a.gin : a.gout;   // grid of the rows
