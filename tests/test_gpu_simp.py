@@ -46,19 +46,37 @@ def test_filter_matches_oracle(dims, rmin):
     assert maxrel(ad, topopt.filter_adjoint(H, Hs, a)) <= 1e-13
 
 
-def test_oc_matches_oracle():
+@pytest.mark.parametrize("volfrac,move,seed", [(0.3, 0.2, 3), (0.05, 0.05, 4), (0.7, 0.5, 5),
+                                               (1.0 - 1e-9, 1.0, 6)])
+def test_oc_matches_oracle(volfrac, move, seed):
     nx, ny, nz = 16, 8, 8
     prob = _prob(nx, ny, nz)
-    rng = np.random.default_rng(3)
+    rng = np.random.default_rng(seed)
     x = rng.uniform(0.05, 0.7, prob.n_elem)
     dc = -rng.uniform(0.001, 3.0, prob.n_elem)
-    xn_o, xp_o, ch_o, steps_o = topopt.oc_update(x, dc, prob.dv, prob.H, prob.Hs, 0.3, 0.2)
+    xn_o, xp_o, ch_o, steps_o = topopt.oc_update(x, dc, prob.dv, prob.H, prob.Hs, volfrac, move)
     t, _, _ = gpu_problem(nx, ny, nz)
-    xn, xp, ch, steps = t.oc_update(dev(x), dev(dc), 0.3, 0.2)
+    xn, xp, ch, steps = t.oc_update(dev(x), dev(dc), volfrac, move)
     assert steps == steps_o
     assert np.max(np.abs(xn.cpu().numpy() - xn_o)) <= 1e-14
     assert np.max(np.abs(xp.cpu().numpy() - xp_o)) <= 1e-14
     assert ch == pytest.approx(ch_o, abs=1e-15)
+
+
+def test_oc_without_a_volume_crossing_is_an_error_on_both_sides():
+    """All sensitivities zero (every multiplier gives x - move) or a volume fraction of 1
+    (no density exceeds it): the bisection bracket never closes; the oracle raises after
+    its step cap and the library reports the same instead of looping."""
+    from paper_2604_18020_amd import TosimpError
+    nx, ny, nz = 8, 4, 4
+    prob = _prob(nx, ny, nz)
+    x = np.full(prob.n_elem, 0.3)
+    t, _, _ = gpu_problem(nx, ny, nz)
+    for dc, volfrac in [(np.zeros(prob.n_elem), 0.3), (-np.ones(prob.n_elem), 1.0)]:
+        with pytest.raises(RuntimeError):
+            topopt.oc_update(x, dc, prob.dv, prob.H, prob.Hs, volfrac, 0.2)
+        with pytest.raises(TosimpError, match="did not terminate"):
+            t.oc_update(dev(x), dev(dc), volfrac, 0.2)
 
 
 @pytest.mark.parametrize("mode", ["plain_fp64", "ir"])
