@@ -82,12 +82,36 @@ __device__ __forceinline__ void store_block_sums(const double (&v)[NV], double* 
   }
 }
 
+// Each thread adds the partials i = t, t + 256, t + 512, ... of every sum in increasing i
+// (the order fixes the result bit for bit); the loads of U consecutive strides are
+// issued before their additions, so a thread waits for about n / (256 U) load latencies
+// instead of n / 256.
 template <int NV, typename F>
 __global__ __launch_bounds__(256) void finalize_sum_kernel(const double* partials, int nb, F f) {
+  constexpr int NT = 256;
+  constexpr int U = NV <= 2 ? 8 : (NV <= 4 ? 4 : 2);
   __shared__ double sbuf[4];
+  double s[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) s[k] = 0.0;
+  int i = threadIdx.x;
+  for (; i + (U - 1) * NT < nb; i += U * NT) {
+    double v[U][NV];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[j][k] = partials[(size_t)NV * (i + j * NT) + k];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) s[k] += v[j][k];
+  }
+  for (; i < nb; i += NT)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] += partials[(size_t)NV * i + k];
   double tot[NV];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) tot[k] = sum_partials<256>(partials + k, nb, NV, sbuf);
+  for (int k = 0; k < NV; ++k) tot[k] = block_sum<NT>(s[k], sbuf);
   if (threadIdx.x == 0) f(tot);
 }
 
