@@ -39,12 +39,12 @@ HBM_PEAK_GBS = 8000.0
 # valid only for the kernel sources they were taken with (sha256 of kv.hip, dev.h,
 # common.h); reported as null once those change.
 KV_TRAFFIC = {
-    "fp32": (2.0 * 49110.5 + 59293.6) * 1024,
-    "fp64": (2.0 * 94590.6 + 118148.0) * 1024,
+    "fp32": (2.0 * 49104.8 + 59314.6) * 1024,
+    "fp64": (2.0 * 94586.7 + 118163.7) * 1024,
 }
 KV_TRAFFIC_SOURCES = {
     "kv.hip": "b997b4519ff1929ca674a395eed60a690f3b07fdc361d552c77a7f7902184c22",
-    "dev.h": "8b034b72e2a61608c66958d1e7d70253194fbb2bdf91fc179096b8fecc73a390",
+    "dev.h": "914e569c6016d8856a85207550abda3abeb3299f20de5017738d7e883af47280",
     "common.h": "9dc818e6f7573b73d7463e4772be341a0c339abd126bd10f350fb271356785cf",
 }
 
