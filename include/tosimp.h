@@ -153,7 +153,8 @@ int tosimp_counts(const tosimp_ctx* ctx, int64_t* n_elem, int64_t* n_node, int64
  * xphys: n_elem element densities of type xdtype; v, y: n_dof values.  prec selects
  * the arithmetic: PREC_FP64 needs v, y FP64; PREC_FP32 and the MFMA precisions need
  * v, y FP32; it may carry TOSIMP_V_ZERO_ON_FIXED (FP64/FP32 with xdtype of the same
- * width; ignored otherwise).  y is overwritten (not accumulated); y must not alias v. */
+ * width; ignored otherwise).  y is overwritten (not accumulated); y must not overlap v
+ * or xphys (EINVAL).                                                                  */
 int tosimp_apply_K(tosimp_ctx* ctx, const void* xphys_dev, int xdtype, const void* v_dev,
                    void* y_dev, int prec);
 /* Jacobi diagonal (paper Sec. "Preconditioned Conjugate Gradient"): d = diag(K_c),
@@ -182,12 +183,13 @@ int tosimp_pcg_solve(tosimp_ctx* ctx, const double* xphys_dev, const double* b_d
 /* ---- SIMP pieces -----------------------------------------------------------------
  * tosimp_sensitivity (paper Sec. "Three-Dimensional SIMP Topology Optimization"):
  * dc_e = -penal xphys_e^(penal-1) (E0 - Emin) u_e^T K_E u_e (n_elem FP64) and the
- * compliance f^T u (FP64 host scalar; synchronises; c_host may be NULL).             */
+ * compliance f^T u (FP64 host scalar; synchronises; c_host may be NULL).  dc must not
+ * overlap u, which is read around every element (EINVAL).                            */
 int tosimp_sensitivity(tosimp_ctx* ctx, const double* xphys_dev, const double* u_dev,
                        double* dc_dev, double* c_host);
 /* Cone density filter, weights max(0, rmin - centroid distance), neighbourhood cut
  * at the domain boundary.  FORWARD: out = H in / Hs; ADJOINT: out = H (in / Hs).
- * in, out: n_elem FP64, must not alias.                                               */
+ * in, out: n_elem FP64, must not overlap (EINVAL).                                    */
 int tosimp_filter(tosimp_ctx* ctx, const double* in_dev, double* out_dev, int mode);
 /* Optimality-criteria update with bisection on the volume multiplier (bracket
  * [0, 1e9], stop when (l2-l1)/(l1+l2) <= 1e-3):
@@ -195,7 +197,9 @@ int tosimp_filter(tosimp_ctx* ctx, const double* in_dev, double* out_dev, int mo
  * dv = H(1/Hs); the volume test is sum(filter(x_new)) > volfrac n_elem, evaluated
  * exactly as the weighted sum dv^T x_new.  dc must be the filtered sensitivity.
  * Writes x_new and xphys_new = filter(x_new) (n_elem FP64), returns max|x_new - x|
- * in *change_host and the step count in *steps_host (either may be NULL).           */
+ * in *change_host and the step count in *steps_host (either may be NULL).  x_new must
+ * not overlap x, dc or xphys_new (EINVAL).  A bracket that has not closed after 256
+ * steps (no multiplier puts the volume above the target) is an EINVAL error.          */
 int tosimp_oc_update(tosimp_ctx* ctx, const double* x_dev, const double* dc_dev,
                      double volfrac, double move, double* x_new_dev,
                      double* xphys_new_dev, double* change_host, int* steps_host);

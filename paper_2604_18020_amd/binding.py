@@ -258,9 +258,9 @@ class Tosimp:
                                       FILTER[mode]))
         return out
 
-    def oc_update(self, x, dc, volfrac, move=0.2):
-        xn = torch.empty_like(x)
-        xpn = torch.empty_like(x)
+    def oc_update(self, x, dc, volfrac, move=0.2, x_new=None, xphys_new=None):
+        xn = torch.empty_like(x) if x_new is None else x_new
+        xpn = torch.empty_like(x) if xphys_new is None else xphys_new
         ch, st = C.c_double(), C.c_int()
         self._sync_stream()
         self._check(LIB.tosimp_oc_update(

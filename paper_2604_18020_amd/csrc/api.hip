@@ -21,6 +21,12 @@ int tosimp_fail(tosimp_ctx* ctx, int code, const std::string& msg) {
 
 namespace {
 
+// True when the byte ranges [a, a + an) and [b, b + bn) overlap.
+bool overlaps(const void* a, int64_t an, const void* b, int64_t bn) {
+  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + (uintptr_t)bn && pb < pa + (uintptr_t)an;
+}
+
 // ------------------------------------------------------------- element stiffness
 // K_E of a cube of edge h, unit Young's modulus, Poisson ratio nu: sum over the
 // 2x2x2 Gauss points of B^T D B |J| w (exact for trilinear shape functions).
@@ -409,12 +415,17 @@ int tosimp_apply_K(tosimp_ctx* ctx, const void* x, int xdtype, const void* v, vo
   int rc = check_ready(ctx);
   if (rc) return rc;
   REQUIRE(x && v && y, TOSIMP_EINVAL, "null pointer");
-  REQUIRE(v != y, TOSIMP_EINVAL, "y must not alias v");
   REQUIRE(xdtype == TOSIMP_F64 || xdtype == TOSIMP_F32, TOSIMP_EINVAL, "bad xdtype");
   const bool vzero = (prec & TOSIMP_V_ZERO_ON_FIXED) != 0;
   prec &= ~TOSIMP_V_ZERO_ON_FIXED;
   REQUIRE(prec >= TOSIMP_PREC_FP64 && prec <= TOSIMP_PREC_FP16_MFMA, TOSIMP_EINVAL,
           "bad precision");
+  {
+    const int64_t vb = ctx->n_dof * (prec == TOSIMP_PREC_FP64 ? 8 : 4);
+    const int64_t xb = ctx->n_elem * (xdtype == TOSIMP_F64 ? 8 : 4);
+    REQUIRE(!overlaps(v, vb, y, vb) && !overlaps(x, xb, y, vb), TOSIMP_EINVAL,
+            "y must not overlap v or xphys");
+  }
   if ((rc = set_device(ctx))) return rc;
   if (prec == TOSIMP_PREC_BF16_MFMA || prec == TOSIMP_PREC_FP16_MFMA) {
     TOSIMP_HIP(ctx, kv_mfma_launch(ctx, prec, xdtype, x, (const float*)v, (float*)y,
@@ -750,6 +761,8 @@ int tosimp_sensitivity(tosimp_ctx* ctx, const double* x, const double* u, double
   int rc = check_ready(ctx);
   if (rc) return rc;
   REQUIRE(x && u && dc, TOSIMP_EINVAL, "null pointer");
+  REQUIRE(!overlaps(dc, 8 * ctx->n_elem, u, 8 * ctx->n_dof), TOSIMP_EINVAL,
+          "dc must not overlap u");
   if ((rc = set_device(ctx))) return rc;
   TOSIMP_HIP(ctx, launch_sensitivity(ctx, x, u, dc));
   if (c_host) {
@@ -767,7 +780,9 @@ int tosimp_sensitivity(tosimp_ctx* ctx, const double* x, const double* u, double
 int tosimp_filter(tosimp_ctx* ctx, const double* in, double* out, int mode) {
   int rc = check_ready(ctx);
   if (rc) return rc;
-  REQUIRE(in && out && in != out, TOSIMP_EINVAL, "null or aliased pointer");
+  REQUIRE(in && out, TOSIMP_EINVAL, "null pointer");
+  REQUIRE(!overlaps(in, 8 * ctx->n_elem, out, 8 * ctx->n_elem), TOSIMP_EINVAL,
+          "in and out must not overlap");
   REQUIRE(mode == TOSIMP_FILTER_FORWARD || mode == TOSIMP_FILTER_ADJOINT, TOSIMP_EINVAL,
           "bad filter mode");
   if ((rc = set_device(ctx))) return rc;
@@ -781,7 +796,12 @@ int tosimp_oc_update(tosimp_ctx* ctx, const double* x, const double* dc, double 
   int rc = check_ready(ctx);
   if (rc) return rc;
   REQUIRE(x && dc && x_new && xphys_new, TOSIMP_EINVAL, "null pointer");
-  REQUIRE(x_new != x && xphys_new != x_new, TOSIMP_EINVAL, "aliased outputs");
+  {
+    const int64_t nb = 8 * ctx->n_elem;
+    REQUIRE(!overlaps(x_new, nb, x, nb) && !overlaps(x_new, nb, dc, nb) &&
+                !overlaps(xphys_new, nb, x_new, nb),
+            TOSIMP_EINVAL, "x_new must not overlap x, dc or xphys_new");
+  }
   REQUIRE(volfrac > 0 && volfrac <= 1 && move > 0, TOSIMP_EINVAL, "bad volfrac/move");
   if ((rc = set_device(ctx))) return rc;
   Workspace& w = ctx->ws;

@@ -110,6 +110,19 @@ def test_bad_arguments_raise():
         t.apply_K(x, v[:-1])
     with pytest.raises(TypeError):
         t.apply_K(x, v.float(), prec="fp64")
+    # partial overlaps are refused; adjacent ranges are fine
+    n = t.n_dof
+    buf = torch.zeros(2 * n + 32, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(TosimpError, match="overlap"):
+        t.apply_K(x, buf[:n], y=buf[8:8 + n])
+    with pytest.raises(TosimpError, match="overlap"):
+        t.apply_K(buf[n - 4:n - 4 + t.n_elem], buf[:n], y=buf[n:2 * n])
+    with pytest.raises(TosimpError, match="overlap"):
+        t.sensitivity(x, buf[:n], dc=buf[n - 4:n - 4 + t.n_elem])
+    y = t.apply_K(x + 0.5, buf[:n], y=buf[n:2 * n])
+    dc, _ = t.sensitivity(x + 0.5, buf[:n], dc=buf[n:n + t.n_elem])
+    torch.cuda.synchronize()
+    assert torch.equal(y, torch.zeros_like(y)) and torch.equal(dc, torch.zeros_like(dc))
 
 
 def _samples(nx, ny, nz, rng, n=1500):

@@ -63,6 +63,23 @@ def test_oc_matches_oracle(volfrac, move, seed):
     assert ch == pytest.approx(ch_o, abs=1e-15)
 
 
+def test_overlapping_filter_and_oc_buffers_are_refused():
+    from paper_2604_18020_amd import TosimpError
+    t, _, _ = gpu_problem(8, 4, 4)
+    n = t.n_elem
+    buf = torch.full((3 * n,), 0.3, dtype=torch.float64, device="cuda:0")
+    dc = -torch.ones(n, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(TosimpError, match="overlap"):
+        t.filter(buf[:n], out=buf[5:5 + n])
+    with pytest.raises(TosimpError, match="overlap"):
+        t.oc_update(buf[:n], dc, 0.3, 0.2, x_new=buf[n - 1:2 * n - 1], xphys_new=buf[2 * n:])
+    with pytest.raises(TosimpError, match="overlap"):
+        t.oc_update(buf[:n], dc, 0.3, 0.2, x_new=buf[n:2 * n], xphys_new=buf[2 * n - 3:3 * n - 3])
+    out = t.filter(buf[:n], out=buf[n:2 * n])  # adjacent ranges are accepted
+    torch.cuda.synchronize()
+    assert torch.allclose(out, torch.full_like(out, 0.3), rtol=0, atol=1e-15)
+
+
 def test_oc_without_a_volume_crossing_is_an_error_on_both_sides():
     """All sensitivities zero (every multiplier gives x - move) or a volume fraction of 1
     (no density exceeds it): the bisection bracket never closes; the oracle raises after
