@@ -58,6 +58,7 @@ template <>
 struct Pack8<bf16_t> {
   u16x8 v;
   __device__ __forceinline__ void load(const bf16_t* p) { v = *reinterpret_cast<const u16x8*>(p); }
+  __device__ __forceinline__ void store(bf16_t* p) const { *reinterpret_cast<u16x8*>(p) = v; }
   __device__ __forceinline__ void zero() { v = (u16x8){0, 0, 0, 0, 0, 0, 0, 0}; }
   __device__ __forceinline__ float get(int j) const { return __uint_as_float((unsigned)v[j] << 16); }
   __device__ __forceinline__ void set(int j, float f) { v[j] = from_f<bf16_t>(f).bits; }
@@ -69,6 +70,10 @@ struct Pack8<float> {
     const float4 a = *reinterpret_cast<const float4*>(p);
     const float4 b = *reinterpret_cast<const float4*>(p + 4);
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  }
+  __device__ __forceinline__ void store(float* p) const {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<float4*>(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
   }
   __device__ __forceinline__ void zero() {
 #pragma unroll
@@ -337,10 +342,23 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(ConvArgs a, float* part
   }
 }
 
-__global__ void conv_wgrad_reduce(const float* part, int nchunk, int n, float* grad, int accumulate) {
+// Sums the chunks in index order; the loads of 16 chunks are issued before their
+// additions (one thread per weight, so a layer has only a few thousand threads and each
+// would otherwise wait for nchunk load latencies in a row).
+__global__ __launch_bounds__(256) void conv_wgrad_reduce(const float* part, int nchunk, int n,
+                                                         float* grad, int accumulate) {
+  constexpr int U = 16;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     float s = 0.0f;
-    for (int c = 0; c < nchunk; ++c) s += part[(long long)c * n + i];
+    int c = 0;
+    for (; c + U <= nchunk; c += U) {
+      float v[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) v[j] = part[(long long)(c + j) * n + i];
+#pragma unroll
+      for (int j = 0; j < U; ++j) s += v[j];
+    }
+    for (; c < nchunk; ++c) s += part[(long long)c * n + i];
     grad[i] = accumulate ? grad[i] + s : s;
   }
 }
@@ -394,20 +412,26 @@ __global__ void node_density_kernel(const XT* x, int nx, int ny, int nz, float* 
 }
 
 // [up(coarse) | skip] concatenation: dst[v][0..c1) = coarse[parent(v)], dst[v][c1..) = skip[v].
+// One thread copies eight channels (16 B in BF16) of one voxel; c1 and c2 are multiples of
+// 8 and n (c1 + c2) / 8 < 2^31 (at most 12 chunks per voxel at the largest mesh), so the
+// index arithmetic is 32-bit.
 template <typename ST>
-__global__ void upcat_kernel(const ST* coarse, Grid3 gc, int c1, const ST* skip, int c2, ST* dst,
-                             Grid3 gf) {
-  const int n = gf.n(), ct = c1 + c2;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (long long)n * ct;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int v = (int)(i / ct), c = (int)(i % ct);
-    if (c < c1) {
-      const int x = v % gf.X, y = (v / gf.X) % gf.Y, z = v / (gf.X * gf.Y);
-      const int pv = (x / 2) + gc.X * ((y / 2) + gc.Y * (z / 2));
-      dst[i] = coarse[(long long)pv * c1 + c];
+__global__ __launch_bounds__(256) void upcat_kernel(const ST* coarse, Grid3 gc, int c1,
+                                                    const ST* skip, int c2, ST* dst, Grid3 gf) {
+  const unsigned ct8 = (unsigned)(c1 + c2) / 8, c18 = (unsigned)c1 / 8;
+  const unsigned units = (unsigned)gf.n() * ct8;
+  for (unsigned u = blockIdx.x * blockDim.x + threadIdx.x; u < units; u += gridDim.x * blockDim.x) {
+    const unsigned v = u / ct8, c8 = u - v * ct8;
+    Pack8<ST> p;
+    if (c8 < c18) {
+      const unsigned x = v % (unsigned)gf.X, y = (v / (unsigned)gf.X) % (unsigned)gf.Y,
+                     z = v / ((unsigned)gf.X * (unsigned)gf.Y);
+      const unsigned pv = (x / 2) + (unsigned)gc.X * ((y / 2) + (unsigned)gc.Y * (z / 2));
+      p.load(coarse + (size_t)pv * c1 + 8 * c8);
     } else {
-      dst[i] = skip[(long long)v * c2 + (c - c1)];
+      p.load(skip + (size_t)v * c2 + 8 * (c8 - c18));
     }
+    p.store(dst + (size_t)u * 8);
   }
 }
 
