@@ -167,7 +167,8 @@ int tosimp_diag_K(tosimp_ctx* ctx, const void* xphys_dev, int xdtype, void* d_de
  * Strategy"; Sec. "BF16 Arithmetic in the Conjugate Gradient Solver" for IR mode):
  * solve K_c(xphys) u = b.  xphys: n_elem FP64; b: n_dof FP64 (must be zero on fixed
  * DOFs); u_inout: n_dof FP64 initial guess (warm start), overwritten by the solution
- * (its fixed DOFs are zeroed first).  b and u_inout must be 16-byte aligned.
+ * (its fixed DOFs are zeroed first).  b and u_inout must be 16-byte aligned, and
+ * u_inout must not overlap b or xphys (EINVAL).
  * PLAIN_FP64: Jacobi-PCG in FP64, stop on the recursive ||r|| <= tol ||b||.
  * IR: outer loop in FP64 (true residual r = b - K u, u += s e) around an inner
  * Jacobi-PCG (or NN flexible CG) in FP32 vectors on the unit-norm residual with FP32

@@ -608,10 +608,6 @@ int norm2_host(tosimp_ctx* ctx, const double* a, int64_t n, double* out) {
 
 }  // namespace
 
-extern "C" {
-
-}  // extern "C"
-
 namespace {
 int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
                    const tosimp_solve_opts* o, tosimp_solve_stats* stats) {
@@ -620,7 +616,9 @@ int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
   REQUIRE(o->tol > 0 && o->maxit >= 0, TOSIMP_EINVAL, "bad tol/maxit");
   REQUIRE(o->mode == TOSIMP_SOLVE_PLAIN_FP64 || o->mode == TOSIMP_SOLVE_IR, TOSIMP_EINVAL,
           "bad solve mode");
-  REQUIRE(b != u, TOSIMP_EINVAL, "u must not alias b");
+  REQUIRE(!overlaps(u, 8 * ctx->n_dof, b, 8 * ctx->n_dof) &&
+              !overlaps(u, 8 * ctx->n_dof, x, 8 * ctx->n_elem),
+          TOSIMP_EINVAL, "u must not overlap b or xphys");
   REQUIRE(((uintptr_t)u & 15) == 0 && ((uintptr_t)b & 15) == 0, TOSIMP_EINVAL,
           "u and b must be 16-byte aligned");
   if ((rc = set_device(ctx))) return rc;

@@ -68,6 +68,22 @@ def test_pcg_zero_rhs():
     assert st["rc"] == 0 and st["iterations"] == 0
 
 
+def test_pcg_refuses_u_overlapping_b_or_density():
+    from paper_2604_18020_amd import TosimpError
+    t, _, f = gpu_problem(6, 3, 3)
+    n = f.size
+    buf = torch.zeros(2 * n + 64, dtype=torch.float64, device="cuda:0")
+    buf[:n] = dev(f)
+    x = dev(np.full(54, 0.5))
+    with pytest.raises(TosimpError, match="overlap"):
+        t.pcg_solve(x, buf[:n], buf[n - 2:2 * n - 2], tol=1e-8)
+    with pytest.raises(TosimpError, match="overlap"):
+        t.pcg_solve(buf[2 * n + 2:2 * n + 56], buf[:n], buf[n + 6:2 * n + 6], tol=1e-8)
+    # adjacent: accepted and solved
+    st = t.pcg_solve(x, buf[:n], buf[n:2 * n], tol=1e-8)
+    assert st["rc"] == 0 and st["true_rel_residual"] <= 1e-8
+
+
 def test_paper_iteration_count_216k():
     """Cold-start Jacobi-PCG iterations on the paper's 120x60x30 case (golden)."""
     case = json.load(open(os.path.join(GOLDEN, "paper_pcg_iterations.json")))["cases"][1]
