@@ -59,6 +59,25 @@ def filter_adjoint(H, Hs, g):
     return H.T @ (g / Hs)
 
 
+# ------------------------------------------------------------------- projection
+def heaviside_project(xbar, beta, eta=0.5):
+    """Smoothed Heaviside projection of the filtered density (Sec. "Three-Dimensional
+    SIMP Topology Optimization", the projection equation of the three-field scheme):
+    (tanh(beta eta) + tanh(beta (xbar - eta))) / (tanh(beta eta) + tanh(beta (1 - eta)))."""
+    xbar = np.asarray(xbar, dtype=np.float64)
+    den = np.tanh(beta * eta) + np.tanh(beta * (1.0 - eta))
+    return (np.tanh(beta * eta) + np.tanh(beta * (xbar - eta))) / den
+
+
+def heaviside_derivative(xbar, beta, eta=0.5):
+    """d(projection)/d(xbar) of heaviside_project: beta (1 - tanh^2(beta (xbar - eta)))
+    over the same denominator (the chain-rule factor of the sensitivities)."""
+    xbar = np.asarray(xbar, dtype=np.float64)
+    den = np.tanh(beta * eta) + np.tanh(beta * (1.0 - eta))
+    t = np.tanh(beta * (xbar - eta))
+    return beta * (1.0 - t * t) / den
+
+
 # ------------------------------------------------------------ compliance, sensitivity
 def compliance(f, u):
     """c = f^T u (Eq. tomin objective)."""

@@ -124,3 +124,48 @@ def test_simp_pcg_equals_direct_path():
     for a, b in zip(h1, h2):
         assert abs(a["c"] - b["c"]) <= 1e-9 * a["c"]
     assert np.max(np.abs(x1 - x2)) < 1e-8
+
+
+# ---- smoothed Heaviside projection (pins independent of the formula's own form) ----
+@pytest.mark.parametrize("beta,eta", [(1.0, 0.5), (8.0, 0.5), (32.0, 0.3), (4.0, 0.7)])
+def test_projection_fixes_the_ends_and_increases(beta, eta):
+    x = np.linspace(0.0, 1.0, 1001)
+    h = topopt.heaviside_project(x, beta, eta)
+    assert abs(h[0]) <= 1e-15 and abs(h[-1] - 1.0) <= 1e-15
+    assert np.all(np.diff(h) >= 0)  # tanh saturates to 1.0 in double far from eta
+    assert np.all(np.diff(h[np.abs(x[:-1] - eta) < 0.1]) > 0)
+
+
+def test_projection_limits_identity_and_step():
+    x = np.linspace(0.0, 1.0, 201)
+    for eta in (0.5, 0.3):
+        # beta -> 0: tanh is linear, the projection is the identity (error O(beta^2))
+        assert np.max(np.abs(topopt.heaviside_project(x, 1e-4, eta) - x)) <= 1e-8
+        # beta -> infinity: a unit step at eta
+        big = topopt.heaviside_project(np.array([eta - 0.05, eta + 0.05]), 400.0, eta)
+        assert big[0] <= 1e-6 and big[1] >= 1.0 - 1e-6
+
+
+@pytest.mark.parametrize("beta", [1.0, 16.0])
+def test_projection_at_half_is_odd_about_the_threshold(beta):
+    t = np.linspace(0.0, 0.5, 101)
+    a = topopt.heaviside_project(0.5 + t, beta, 0.5)
+    b = topopt.heaviside_project(0.5 - t, beta, 0.5)
+    assert np.max(np.abs(a + b - 1.0)) <= 1e-15
+    # eta = 1/2: the same map written as 1/2 + tanh(beta (x - 1/2)) / (2 tanh(beta / 2))
+    alt = 0.5 + np.tanh(beta * t) / (2.0 * np.tanh(beta / 2.0))
+    assert np.max(np.abs(a - alt)) <= 1e-15
+
+
+@pytest.mark.parametrize("beta,eta", [(2.0, 0.5), (16.0, 0.5), (8.0, 0.35)])
+def test_projection_derivative_against_differences_and_its_integral(beta, eta):
+    from scipy.integrate import quad
+    x = np.linspace(0.01, 0.99, 99)
+    h = 1e-6
+    fd = (topopt.heaviside_project(x + h, beta, eta) -
+          topopt.heaviside_project(x - h, beta, eta)) / (2 * h)
+    d = topopt.heaviside_derivative(x, beta, eta)
+    assert np.max(np.abs(fd - d)) <= 1e-7 * np.max(d)
+    total, _ = quad(lambda s: float(topopt.heaviside_derivative(s, beta, eta)), 0.0, 1.0,
+                    epsabs=1e-13, epsrel=1e-13, limit=200)
+    assert abs(total - 1.0) <= 1e-10
