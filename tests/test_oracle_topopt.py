@@ -133,7 +133,7 @@ def test_projection_fixes_the_ends_and_increases(beta, eta):
     h = topopt.heaviside_project(x, beta, eta)
     assert abs(h[0]) <= 1e-15 and abs(h[-1] - 1.0) <= 1e-15
     assert np.all(np.diff(h) >= 0)  # tanh saturates to 1.0 in double far from eta
-    assert np.all(np.diff(h[np.abs(x[:-1] - eta) < 0.1]) > 0)
+    assert np.all(np.diff(h)[np.abs(x[:-1] - eta) < 0.1] > 0)
 
 
 def test_projection_limits_identity_and_step():
