@@ -39,13 +39,13 @@ HBM_PEAK_GBS = 8000.0
 # valid only for the kernel sources they were taken with (sha256 of kv.hip, dev.h,
 # common.h); reported as null once those change.
 KV_TRAFFIC = {
-    "fp32": (2.0 * 49104.8 + 59314.6) * 1024,
-    "fp64": (2.0 * 94586.7 + 118163.7) * 1024,
+    "fp32": (2.0 * 49121.5 + 59237.0) * 1024,
+    "fp64": (2.0 * 94562.9 + 118117.0) * 1024,
 }
 KV_TRAFFIC_SOURCES = {
     "kv.hip": "b997b4519ff1929ca674a395eed60a690f3b07fdc361d552c77a7f7902184c22",
     "dev.h": "914e569c6016d8856a85207550abda3abeb3299f20de5017738d7e883af47280",
-    "common.h": "9dc818e6f7573b73d7463e4772be341a0c339abd126bd10f350fb271356785cf",
+    "common.h": "8e6881f18d94e4f7dfdc2b633ca224dff98cba74af3245bd4494e9b4733b8bc9",
 }
 
 
@@ -353,6 +353,38 @@ def kv_study(workloads=("cantilever_120x60x30", "cantilever_340x170x85")):
     return out
 
 
+def projection_study(workload="cantilever_340x170x85", reps=200, sets=4):
+    """The Heaviside projection kernel (and its chain-rule form) on one density field per
+    element of the mesh: algorithmic bytes 16 (read xbar, write out) and 24 (also g) per
+    element; buffer sets rotated so the 256 MB Infinity Cache cannot hold them."""
+    import numpy as np
+    import torch
+
+    t, cfg, _, _ = _problem(workload)
+    n = t.n_elem
+    rng = np.random.default_rng(3)
+    xs = [torch.tensor(rng.uniform(0.0, 1.0, n), device="cuda:0") for _ in range(sets)]
+    gs = [torch.tensor(rng.standard_normal(n), device="cuda:0") for _ in range(sets)]
+    outs = [torch.empty(n, dtype=torch.float64, device="cuda:0") for _ in range(sets)]
+    res = {"workload": workload, "n_elem": n, "launches": reps}
+    for label, chain, per in (("projection", False, 16), ("chain_rule", True, 24)):
+        for k in range(8):
+            t.project(xs[k % sets], 8.0, 0.5, g=gs[k % sets] if chain else None, out=outs[k % sets])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(reps):
+            t.project(xs[k % sets], 8.0, 0.5, g=gs[k % sets] if chain else None, out=outs[k % sets])
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        gbs = per * n / (us * 1e-6) / 1e9
+        res[label] = {"avg_launch_us": us, "bytes_per_launch": per * n, "algorithmic_gbs": gbs,
+                      "frac_of_8tbs": gbs / HBM_PEAK_GBS}
+    t.close()
+    return res
+
+
 def pcg_cold_study(workloads=("cantilever_120x60x30", "torsion_55x55x165",
                               "cantilever_200x100x50"), tol=1e-6):
     """Cold-start PCG at uniform density on the other benchmark meshes (the main line
@@ -425,6 +457,7 @@ def main():
 
     if a.suite:
         print(json.dumps({"kv_study": kv_study()}), flush=True)
+        print(json.dumps({"projection_study": projection_study()}), flush=True)
         print(json.dumps({"pcg_cold_study": pcg_cold_study()}), flush=True)
         print(json.dumps({"precision_study": precision_study()}), flush=True)
         print(json.dumps({"simp_study": simp_study("cantilever_120x60x30")}), flush=True)

@@ -192,6 +192,16 @@ int tosimp_sensitivity(tosimp_ctx* ctx, const double* xphys_dev, const double* u
  * at the domain boundary.  FORWARD: out = H in / Hs; ADJOINT: out = H (in / Hs).
  * in, out: n_elem FP64, must not overlap (EINVAL).                                    */
 int tosimp_filter(tosimp_ctx* ctx, const double* in_dev, double* out_dev, int mode);
+/* Smoothed Heaviside projection of the three-field scheme (paper Sec.
+ * "Three-Dimensional SIMP Topology Optimization", projection equation), elementwise on
+ * n_elem FP64 values, den = tanh(beta eta) + tanh(beta (1 - eta)):
+ *   g_dev NULL:  out = (tanh(beta eta) + tanh(beta (in - eta))) / den   (the projection)
+ *   g_dev set:   out = g beta (1 - tanh^2(beta (in - eta))) / den        (chain rule:
+ *                g times the derivative of the projection at in)
+ * beta > 0 and finite, 0 <= eta <= 1 (EINVAL otherwise).  out may be in or g itself but
+ * must not partly overlap either (EINVAL).  Asynchronous.                             */
+int tosimp_project(tosimp_ctx* ctx, const double* in_dev, const double* g_dev,
+                   double* out_dev, double beta, double eta);
 /* Optimality-criteria update with bisection on the volume multiplier (bracket
  * [0, 1e9], stop when (l2-l1)/(l1+l2) <= 1e-3):
  * x_new = clip(x sqrt(-dc / (dv lambda)), max(0, x - move), min(1, x + move)) with

@@ -85,6 +85,7 @@ def _load():
         "tosimp_pcg_solve": (I, [P, P, P, P, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
         "tosimp_sensitivity": (I, [P, P, P, P, C.POINTER(D)]),
         "tosimp_filter": (I, [P, P, P, I]),
+        "tosimp_project": (I, [P, P, P, P, D, D]),
         "tosimp_oc_update": (I, [P, P, P, D, D, P, P, C.POINTER(D), C.POINTER(I)]),
         "tosimp_simp_step": (I, [P, P, P, P, C.POINTER(StepOpts), C.POINTER(StepStats)]),
         "tosimp_lanczos": (I, [P, P, P, I, I, P, P, C.POINTER(I)]),
@@ -256,6 +257,17 @@ class Tosimp:
         self._check(LIB.tosimp_filter(self._h, self._dev(inp, torch.float64, self.n_elem, "in"),
                                       self._dev(out, torch.float64, self.n_elem, "out"),
                                       FILTER[mode]))
+        return out
+
+    def project(self, xbar, beta, eta=0.5, g=None, out=None):
+        """Heaviside projection of xbar, or (with g) g times its derivative at xbar."""
+        if out is None:
+            out = torch.empty_like(xbar)
+        self._sync_stream()
+        self._check(LIB.tosimp_project(
+            self._h, self._dev(xbar, torch.float64, self.n_elem, "xbar"),
+            None if g is None else self._dev(g, torch.float64, self.n_elem, "g"),
+            self._dev(out, torch.float64, self.n_elem, "out"), float(beta), float(eta)))
         return out
 
     def oc_update(self, x, dc, volfrac, move=0.2, x_new=None, xphys_new=None):

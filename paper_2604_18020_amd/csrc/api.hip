@@ -788,6 +788,22 @@ int tosimp_filter(tosimp_ctx* ctx, const double* in, double* out, int mode) {
   return TOSIMP_OK;
 }
 
+int tosimp_project(tosimp_ctx* ctx, const double* in, const double* g, double* out,
+                   double beta, double eta) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(in && out, TOSIMP_EINVAL, "null pointer");
+  REQUIRE(beta > 0 && std::isfinite(beta) && eta >= 0 && eta <= 1, TOSIMP_EINVAL,
+          "need beta > 0 (finite) and 0 <= eta <= 1");
+  const int64_t nb = 8 * ctx->n_elem;
+  REQUIRE((out == in || !overlaps(out, nb, in, nb)) &&
+              (!g || out == g || !overlaps(out, nb, g, nb)),
+          TOSIMP_EINVAL, "out must be in, g, or not overlap them");
+  if ((rc = set_device(ctx))) return rc;
+  TOSIMP_HIP(ctx, launch_project(ctx, in, g, out, beta, eta));
+  return TOSIMP_OK;
+}
+
 int tosimp_oc_update(tosimp_ctx* ctx, const double* x, const double* dc, double volfrac,
                      double move, double* x_new, double* xphys_new, double* change_host,
                      int* steps_host) {

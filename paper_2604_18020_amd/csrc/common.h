@@ -196,6 +196,8 @@ hipError_t launch_sensitivity(const tosimp_ctx* c, const double* xphys, const do
 hipError_t launch_filter(const tosimp_ctx* c, const double* in, double* out, int mode,
                          const double* Hs);
 hipError_t launch_filter_rowsum(const tosimp_ctx* c, double* Hs);
+hipError_t launch_project(const tosimp_ctx* c, const double* in, const double* g, double* out,
+                          double beta, double eta);
 hipError_t launch_oc_init(const tosimp_ctx* c, OcState* oc, double target);
 hipError_t launch_oc_step(const tosimp_ctx* c, const double* x, const double* dc,
                           const double* dv, double move, OcState* oc, double* partials);

@@ -124,6 +124,31 @@ hipError_t launch_filter_rowsum(const tosimp_ctx* c, double* Hs) {
   return hipGetLastError();
 }
 
+// -------------------------------------------------------------- projection
+// Smoothed Heaviside projection of the filtered density (the projection equation of the
+// three-field scheme): out = (tanh(beta eta) + tanh(beta (in - eta))) / den with
+// den = tanh(beta eta) + tanh(beta (1 - eta)); with g, the chain-rule product
+// out = g beta (1 - tanh^2(beta (in - eta))) / den.  Elementwise, 16 bytes (24 with g)
+// per element; out may be in or g itself.
+__global__ __launch_bounds__(256) void project_kernel(const double* in, const double* g,
+                                                      double* out, int64_t n, double beta,
+                                                      double eta, double tbe, double den) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double t = tanh(beta * (in[e] - eta));
+    out[e] = g ? g[e] * (beta * (1.0 - t * t) / den) : (tbe + t) / den;
+  }
+}
+
+hipError_t launch_project(const tosimp_ctx* c, const double* in, const double* g, double* out,
+                          double beta, double eta) {
+  const double tbe = tanh(beta * eta), den = tbe + tanh(beta * (1.0 - eta));
+  const int64_t n = c->n_elem;
+  const int blocks = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  project_kernel<<<blocks, 256, 0, c->stream>>>(in, g, out, n, beta, eta, tbe, den);
+  return hipGetLastError();
+}
+
 // --------------------------------------------------------------------- OC
 __device__ __forceinline__ double oc_x(double xv, double dcv, double dvv, double lmid,
                                        double move) {

@@ -132,3 +132,41 @@ def test_simp_torsion_symmetry_on_gpu():
         t.simp_step(x, xp, u, volfrac=0.3, tol=1e-10)
     g = x.cpu().numpy().reshape(nz, n, n)
     assert np.max(np.abs(g - np.rot90(g, 1, axes=(1, 2)))) <= 1e-7
+
+
+@pytest.mark.parametrize("dims", [(16, 8, 8), (37, 5, 3)])
+@pytest.mark.parametrize("beta,eta", [(1.0, 0.5), (8.0, 0.5), (32.0, 0.3), (1e-3, 0.5)])
+def test_projection_and_its_chain_rule_match_oracle(dims, beta, eta):
+    """Projection values lie in [0, 1]: both sides evaluate tanh to within an ulp or two,
+    so the bound is absolute (4e-16 x a few); the chain-rule product is bounded
+    relative to its largest value (1 - tanh^2 loses digits only where it is small)."""
+    t, _, _ = gpu_problem(*dims)
+    n = t.n_elem
+    rng = np.random.default_rng(7)
+    xb = rng.uniform(0.0, 1.0, n)
+    xb[:3] = [0.0, 1.0, eta]
+    g = rng.standard_normal(n)
+    p = t.project(dev(xb), beta, eta).cpu().numpy()
+    d = t.project(dev(xb), beta, eta, g=dev(g)).cpu().numpy()
+    po = topopt.heaviside_project(xb, beta, eta)
+    do = g * topopt.heaviside_derivative(xb, beta, eta)
+    assert np.max(np.abs(p - po)) <= 2e-15
+    assert np.max(np.abs(d - do)) <= 1e-14 * np.max(np.abs(do))
+    xin = dev(xb)
+    t.project(xin, beta, eta, out=xin)  # in place
+    gin = dev(g)
+    t.project(dev(xb), beta, eta, g=gin, out=gin)
+    torch.cuda.synchronize()
+    assert torch.equal(xin.cpu(), torch.tensor(p)) and torch.equal(gin.cpu(), torch.tensor(d))
+
+
+def test_projection_argument_errors():
+    from paper_2604_18020_amd import TosimpError
+    t, _, _ = gpu_problem(8, 4, 4)
+    n = t.n_elem
+    buf = torch.full((2 * n,), 0.5, dtype=torch.float64, device="cuda:0")
+    for beta, eta in [(0.0, 0.5), (-1.0, 0.5), (float("inf"), 0.5), (4.0, 1.5), (4.0, -0.1)]:
+        with pytest.raises(TosimpError):
+            t.project(buf[:n], beta, eta)
+    with pytest.raises(TosimpError, match="overlap"):
+        t.project(buf[:n], 4.0, 0.5, out=buf[3:3 + n])
