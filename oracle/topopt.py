@@ -164,6 +164,17 @@ class Problem:
                            self.Emin, self.penal)
 
 
+def three_field_sensitivity(prob: Problem, x, u, beta, eta=0.5):
+    """Three-field chain (Sec. "Three-Dimensional SIMP Topology Optimization": raw x,
+    filtered xbar = H x / Hs, projected xphys = heaviside_project(xbar)): returns xphys
+    and dc/dx = H^T ((dc/dxphys * d xphys / d xbar) / Hs) for the displacement u of
+    K(xphys) u = f."""
+    xbar = filter_forward(prob.H, prob.Hs, x)
+    xphys = heaviside_project(xbar, beta, eta)
+    dc_phys = prob.sensitivity(xphys, u)
+    return xphys, filter_adjoint(prob.H, prob.Hs, dc_phys * heaviside_derivative(xbar, beta, eta))
+
+
 def simp_run(prob: Problem, iters: int, tol=1e-8, move=0.2, direct=False, maxit=20000):
     """Plain SIMP loop: x = volfrac; each iteration solves K(xphys) u = f (warm start),
     takes c and dc, filters dc, runs OC and refilters.  Returns per-iteration history
