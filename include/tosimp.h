@@ -89,6 +89,9 @@ typedef struct tosimp_solve_opts {
   int fcg_window;    /* PRECOND_NN: flexible CG keeps this many directions (1..16; 0 = 1) */
   int eager;         /* 1: launch every kernel directly; 0: Jacobi-PCG replays batches of */
                      /*    check_every iterations as a HIP graph (same kernels, same order) */
+  int nn_stall;      /* PRECOND_NN: once ||r|| has made no new minimum for this many       */
+                     /*   iterations of an inner solve, plain Jacobi-PCG continues it from  */
+                     /*   the current iterate (0 = 50, < 0 = never)                          */
 } tosimp_solve_opts;
 
 typedef struct tosimp_solve_stats {
@@ -99,6 +102,10 @@ typedef struct tosimp_solve_stats {
   double rel_residual;     /* final ||r|| / ||b|| the solver judged convergence on   */
   double true_rel_residual;/* ||b - K u|| / ||b|| recomputed in FP64 at exit         */
   int harvested;           /* (r_k, u_k) pairs written to the harvest arrays         */
+  int restarts;            /* NN inner solves continued by Jacobi-PCG (nn_stall)     */
+  double b_dot_u;          /* b^T u (the compliance when b = f)                      */
+  double b_dot_u_corrected;/* b^T u + u^T (b - K u) = 2 b^T u - u^T K u: differs from */
+                           /* b^T u* by -||u - u*||_K^2 only (second order in u - u*) */
 } tosimp_solve_stats;
 
 typedef struct tosimp_step_opts {
@@ -173,8 +180,13 @@ int tosimp_diag_K(tosimp_ctx* ctx, const void* xphys_dev, int xdtype, void* d_de
  * IR: outer loop in FP64 (true residual r = b - K u, u += s e) around an inner
  * Jacobi-PCG (or NN flexible CG) in FP32 vectors on the unit-norm residual with FP32
  * or MFMA operator; every dot product, norm, alpha and beta is accumulated in FP64.
- * Returns OK, NOT_CONVERGED (cap hit, u valid), FALLBACK_USED, EBREAKDOWN or
- * EPRECISION (enforce_rule and u_inner * kappa >= 1).  stats may be NULL.
+ * PRECOND_NN (IR mode): flexible CG with the learned preconditioner; an iteration whose
+ * preconditioned residual is not a descent direction (<r, z> <= 0) or not finite takes
+ * the Jacobi step instead (stats->fallbacks), and an inner solve that stagnates
+ * (opts->nn_stall) is finished by plain Jacobi-PCG (stats->restarts).
+ * Returns OK, NOT_CONVERGED (cap hit, u valid), FALLBACK_USED (a fallback or restart was
+ * taken, u valid), EBREAKDOWN or EPRECISION (enforce_rule and u_inner * kappa >= 1).
+ * stats may be NULL.
  * The solve runs on a stream of the context, ordered after the work already enqueued on
  * the caller's stream and before any work enqueued there after the call.            */
 int tosimp_pcg_solve(tosimp_ctx* ctx, const double* xphys_dev, const double* b_dev,

@@ -139,11 +139,55 @@ def apply_K_elementwise(nx, ny, nz, E, KE, v, fixed=None, chunk=65536):
     return y
 
 
+def apply_K_grid(nx, ny, nz, E, KE, v, fixed=None):
+    """y = K_c v on the structured grid (Eq. matfree), a third route for full-size
+    checks: the 24 element DOFs of every element are gathered at once as shifted
+    node-grid slices (local node a at offset (ax, ay, az), one slice per component),
+    multiplied by E_e K_E in one matrix product, and each local DOF's results are added
+    back into the slice it came from (within one local node, elements map to distinct
+    nodes).  Components are held as separate grids so that every slice is row-contiguous."""
+    vin = np.array(v, dtype=np.float64, copy=True)
+    if fixed is not None:
+        vin[fixed] = 0.0
+    g = np.ascontiguousarray(vin.reshape(nz + 1, ny + 1, nx + 1, 3).transpose(3, 0, 1, 2))
+    offs = [(a & 1, (a >> 1) & 1, (a >> 2) & 1) for a in range(8)]
+    ve = np.empty((24, nz, ny, nx))
+    for a, (ax, ay, az) in enumerate(offs):
+        for c in range(3):
+            ve[3 * a + c] = g[c, az:az + nz, ay:ay + ny, ax:ax + nx]
+    fe = KE @ ve.reshape(24, -1)
+    fe *= np.asarray(E, dtype=np.float64)[None, :]
+    fe = fe.reshape(24, nz, ny, nx)
+    y = np.zeros((3, nz + 1, ny + 1, nx + 1))
+    for a, (ax, ay, az) in enumerate(offs):
+        for c in range(3):
+            y[c, az:az + nz, ay:ay + ny, ax:ax + nx] += fe[3 * a + c]
+    y = np.ascontiguousarray(y.transpose(1, 2, 3, 0)).reshape(-1)
+    if fixed is not None:
+        y[fixed] = np.asarray(v, dtype=np.float64)[fixed]
+    return y
+
+
 def diag_K(nx, ny, nz, E, KE, fixed=None) -> np.ndarray:
     """Jacobi diagonal of K_c, accumulated element by element (1 on fixed DOFs)."""
     edof = edof_table(nx, ny, nz)
     d = np.zeros(3 * (nx + 1) * (ny + 1) * (nz + 1))
     np.add.at(d, edof.ravel(), (E[:, None] * np.diag(KE)[None, :]).ravel())
+    if fixed is not None:
+        d[fixed] = 1.0
+    return d
+
+
+def diag_K_grid(nx, ny, nz, E, KE, fixed=None) -> np.ndarray:
+    """diag_K on the structured grid: each local node a adds E_e diag(K_E)[3a:3a+3] to
+    the node-grid slice it occupies (the full-size companion of apply_K_grid)."""
+    Eg = np.asarray(E, dtype=np.float64).reshape(nz, ny, nx)
+    dk = np.diag(KE)
+    d = np.zeros((nz + 1, ny + 1, nx + 1, 3))
+    for a in range(8):
+        ax, ay, az = a & 1, (a >> 1) & 1, (a >> 2) & 1
+        d[az:az + nz, ay:ay + ny, ax:ax + nx, :] += Eg[..., None] * dk[3 * a:3 * a + 3]
+    d = d.reshape(-1)
     if fixed is not None:
         d[fixed] = 1.0
     return d

@@ -236,23 +236,45 @@ def adam_step(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 # ------------------------------------------------------------------ flexible CG
-def fcg(apply_A, precond, b, x0=None, tol=1e-8, maxit=10000, window=1):
+def fcg(apply_A, precond, b, x0=None, tol=1e-8, maxit=10000, window=1, d=None, stall=0,
+        info=None):
     """Flexible CG truncated to the `window` latest directions (FCG(m)): z_k = M_k(r_k),
     p_k = z_k - sum_j (<z_k, q_j> / <p_j, q_j>) p_j over the window, q_k = A p_k,
     alpha_k = <r_k, z_k> / <p_k, q_k>.  With a fixed SPD preconditioner this reproduces
     PCG in exact arithmetic for every window.  Stops on ||r|| <= tol ||b||.
-    Returns (x, iters, history)."""
+
+    Guards of the learned preconditioner (plain Jacobi-PCG is its fallback):
+      * with the Jacobi diagonal `d`: a z that is not a descent direction (<r, z> <= 0),
+        is not finite, or gives a non-finite orthogonalisation coefficient is replaced by
+        the Jacobi step z = r / d for that iteration (counted in info["fallbacks"]);
+      * with stall > 0: once ||r|| has made no new minimum for `stall` consecutive
+        iterations, flexible CG stops and plain Jacobi-PCG (solvers.pcg_jacobi, needs d)
+        continues from the current iterate with the same tolerance on ||b|| and the
+        iterations left (info["restarted"] = True, info["fcg_iterations"] = iterations
+        flexible CG took).
+    Returns (x, iters, history); iters and history include the Jacobi-PCG part."""
     x = np.zeros_like(b) if x0 is None else x0.copy()
     bn = np.linalg.norm(b)
     r = b - apply_A(x)
     hist = [np.linalg.norm(r) / bn]
     P, Q = [], []
     it = 0
+    fallbacks = 0
+    best, k_best = hist[0], 0
+    restarted = False
     while hist[-1] > tol and it < maxit:
         z = precond(r)
+        with np.errstate(all="ignore"):
+            rz = float(r @ z)
+            coef = [float(z @ qj) / float(pj @ qj) for pj, qj in zip(P, Q)]
+        ok = np.isfinite(rz) and rz > 0.0 and all(np.isfinite(c) for c in coef)
+        if not ok and d is not None:
+            z = r / d
+            fallbacks += 1
+            coef = [float(z @ qj) / float(pj @ qj) for pj, qj in zip(P, Q)]
         p = z.copy()
-        for pj, qj in zip(P, Q):
-            p -= (z @ qj) / (pj @ qj) * pj
+        for c, pj in zip(coef, P):
+            p -= c * pj
         q = apply_A(p)
         alpha = (r @ z) / (p @ q)
         x = x + alpha * p
@@ -264,6 +286,20 @@ def fcg(apply_A, precond, b, x0=None, tol=1e-8, maxit=10000, window=1):
             Q.pop(0)
         it += 1
         hist.append(np.linalg.norm(r) / bn)
+        if stall > 0 and hist[-1] > tol and it < maxit:
+            if hist[-1] < best:
+                best, k_best = hist[-1], it
+            elif it - k_best >= stall:
+                restarted = True
+                break
+    fcg_its = it
+    if restarted and it < maxit:
+        from oracle.solvers import pcg_jacobi
+        x, it2, h2 = pcg_jacobi(apply_A, d, b, x, tol, maxit - it)
+        it += it2
+        hist.extend(h2[1:])
+    if info is not None:
+        info.update(fallbacks=fallbacks, restarted=restarted, fcg_iterations=fcg_its)
     return x, it, hist
 
 

@@ -6,4 +6,4 @@ package is its thin binding.  Import it with the library built in-tree:
     python paper_2604_18020_amd/build.py
 """
 from .binding import (F32, F64, PREC, Tosimp, TosimpError, tridiag_extremes,  # noqa: F401
-                      version, LIB_PATH)
+                      version, LIB_PATH, OK, NOT_CONVERGED, FALLBACK_USED)

@@ -37,14 +37,15 @@ class SolveOpts(C.Structure):
                 ("precond", C.c_int), ("check_every", C.c_int), ("enforce_rule", C.c_int),
                 ("kappa", C.c_double), ("harvest_r", C.c_void_p), ("harvest_u", C.c_void_p),
                 ("harvest_cap", C.c_int), ("harvest_every", C.c_int), ("fcg_window", C.c_int),
-                ("eager", C.c_int)]
+                ("eager", C.c_int), ("nn_stall", C.c_int)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("outer_iterations", C.c_int),
                 ("fallbacks", C.c_int), ("status", C.c_int),
                 ("rel_residual", C.c_double), ("true_rel_residual", C.c_double),
-                ("harvested", C.c_int)]
+                ("harvested", C.c_int), ("restarts", C.c_int), ("b_dot_u", C.c_double),
+                ("b_dot_u_corrected", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -210,10 +211,10 @@ class Tosimp:
     @staticmethod
     def solve_opts(tol=1e-8, maxit=20000, mode="plain_fp64", inner_prec="fp32",
                    inner_tol=1e-5, max_outer=30, precond="jacobi", check_every=16,
-                   enforce_rule=False, kappa=0.0, fcg_window=1, eager=False):
+                   enforce_rule=False, kappa=0.0, fcg_window=1, eager=False, nn_stall=0):
         return SolveOpts(tol, maxit, SOLVE[mode], PREC[inner_prec], inner_tol, max_outer,
                          PRECOND[precond], check_every, int(enforce_rule), kappa, None, None,
-                         0, 0, int(fcg_window), int(bool(eager)))
+                         0, 0, int(fcg_window), int(bool(eager)), int(nn_stall))
 
     def _opts_with_harvest(self, harvest, harvest_every, **kw):
         o = self.solve_opts(**kw)

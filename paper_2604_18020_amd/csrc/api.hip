@@ -595,10 +595,10 @@ int true_residual(tosimp_ctx* ctx, const double* x, const double* b, const doubl
   return TOSIMP_OK;
 }
 
-int norm2_host(tosimp_ctx* ctx, const double* a, int64_t n, double* out) {
+int dot_host(tosimp_ctx* ctx, const double* a, const double* b, int64_t n, double* out) {
   Workspace& w = ctx->ws;
   SolverState* st = w.st + 2;
-  TOSIMP_HIP(ctx, launch_dot64(ctx, a, a, n, w.partials, st, 0));
+  TOSIMP_HIP(ctx, launch_dot64(ctx, a, b, n, w.partials, st, 0));
   TOSIMP_HIP(ctx, hipMemcpyAsync(w.st_host + 2, st, sizeof(SolverState), hipMemcpyDeviceToHost,
                                  ctx->stream));
   TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -666,9 +666,9 @@ int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
     TOSIMP_HIP(ctx, launch_diag_inv(ctx, x, w.dinv, w.dinv32));
     TOSIMP_HIP(ctx, launch_copy_cast_x(ctx, x, w.x32));
     double bb = 0;
-    if ((rc = norm2_host(ctx, b, ctx->n_dof, &bb))) return rc;
+    if ((rc = dot_host(ctx, b, b, ctx->n_dof, &bb))) return rc;
     const double bn = std::sqrt(bb);
-    int total = 0, outer = 0, fallbacks = 0, slow = 0;
+    int total = 0, outer = 0, fallbacks = 0, restarts = 0, slow = 0;
     double prev = -1, rel = 0;
     int status = TOSIMP_OK;
     for (;;) {
@@ -693,10 +693,23 @@ int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
       int it = 0, done = 0;
       if (o->precond == TOSIMP_PRECOND_NN) {
         int fb = 0;
+        const int stall = o->nn_stall == 0 ? 50 : o->nn_stall;
         rc = nn_fcg_solve(ctx, ip, w.x32, w.e32, w.z32, itol, o->maxit - total,
-                          o->check_every, o->fcg_window, &it, &fb, &done);
+                          o->check_every, o->fcg_window, stall, &it, &fb, &done);
         if (rc < 0) return rc;
         fallbacks += fb;
+        if (done == 4) {
+          // The learned solve stagnated: plain Jacobi-PCG continues from its iterate on
+          // the same right-hand side and tolerance, with the iterations left.
+          PcgResult pr;
+          rc = run_pcg<float>(ctx, ip, w.x32, TOSIMP_F32, w.e32, w.z32, w.dinv32, 1, itol,
+                              o->maxit - total - it, o->check_every, false, &pr, nullptr,
+                              !o->eager);
+          if (rc) return rc;
+          it += pr.iters;
+          done = pr.done;
+          ++restarts;
+        }
       } else {
         PcgResult pr;
         rc = run_pcg<float>(ctx, ip, w.x32, TOSIMP_F32, w.e32, w.z32, w.dinv32, 1,
@@ -714,10 +727,20 @@ int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
     s.iterations = total;
     s.outer_iterations = outer;
     s.fallbacks = fallbacks;
+    s.restarts = restarts;
     s.rel_residual = rel;
     s.true_rel_residual = rel;
     s.status = status;
-    if (status == TOSIMP_OK && fallbacks > 0) s.status = TOSIMP_FALLBACK_USED;
+    if (status == TOSIMP_OK && (fallbacks > 0 || restarts > 0)) s.status = TOSIMP_FALLBACK_USED;
+  }
+  // b^T u and its second-order form b^T u + u^T r (r = b - K u, left in w.r by the final
+  // true-residual evaluation of either mode).
+  if (s.status >= 0) {
+    double bu = 0, ur = 0;
+    if ((rc = dot_host(ctx, b, u, ctx->n_dof, &bu))) return rc;
+    if ((rc = dot_host(ctx, u, w.r, ctx->n_dof, &ur))) return rc;
+    s.b_dot_u = bu;
+    s.b_dot_u_corrected = bu + ur;
   }
   if (stats) *stats = s;
   if (s.status < 0) return tosimp_fail(ctx, s.status, "solve failed (breakdown)");
@@ -761,6 +784,8 @@ int tosimp_sensitivity(tosimp_ctx* ctx, const double* x, const double* u, double
   REQUIRE(x && u && dc, TOSIMP_EINVAL, "null pointer");
   REQUIRE(!overlaps(dc, 8 * ctx->n_elem, u, 8 * ctx->n_dof), TOSIMP_EINVAL,
           "dc must not overlap u");
+  REQUIRE(dc == x || !overlaps(dc, 8 * ctx->n_elem, x, 8 * ctx->n_elem), TOSIMP_EINVAL,
+          "dc must be xphys itself or not overlap it");
   if ((rc = set_device(ctx))) return rc;
   TOSIMP_HIP(ctx, launch_sensitivity(ctx, x, u, dc));
   if (c_host) {

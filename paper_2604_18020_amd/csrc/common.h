@@ -50,6 +50,9 @@ struct SolverState {
   int done;       // 0 running, 1 converged, 2 cap, 3 breakdown
   int nfallback;  // flexible CG: preconditioner fallbacks taken
   int upend;      // Jacobi-PCG: the last iteration's u += alpha p is still to be applied
+  double rmin;    // flexible CG stagnation guard: smallest ||r||^2 so far,
+  int kmin;       //   the iteration that reached it,
+  int stall;      //   and the iterations without a new minimum that stop the solve (0: off)
 };
 
 // Device-side state of the OC bisection.
@@ -186,8 +189,9 @@ hipError_t launch_sqrt_scalar(const tosimp_ctx* c, const SolverState* st, double
 // Learned preconditioner (nn.hip).  nn_fcg_solve: flexible CG on K_c(x32) e = b32 with
 // the network as preconditioner (Jacobi fallback), FP32 vectors, zero initial guess.
 void nn_release(tosimp_ctx* ctx);
+// stall > 0: stop with *done = 4 once ||r|| has made no new minimum for stall iterations.
 int nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const float* b32, float* e32,
-                 double tol, int maxit, int check_every, int window, int* iters,
+                 double tol, int maxit, int check_every, int window, int stall, int* iters,
                  int* fallbacks, int* done);
 
 // SIMP kernels (topopt.hip).

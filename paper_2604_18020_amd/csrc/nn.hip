@@ -746,6 +746,23 @@ __global__ void fcg_store_pq_kernel(const SolverState* st, double* pq, int slot)
   if (threadIdx.x == 0 && blockIdx.x == 0 && !st->done) pq[slot] = st->pq;
 }
 
+// Stagnation guard of the learned solve: after each iteration, ||r||^2 either sets a new
+// minimum or, once st->stall iterations have passed without one, the solve stops with
+// done = 4 (the host then continues with plain Jacobi-PCG from the iterate).  init: the
+// initial residual is the first minimum.
+__global__ void fcg_stall_kernel(SolverState* st, int init) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || st->done || st->stall <= 0) return;
+  if (init) {
+    st->rmin = st->rr;
+    st->kmin = 0;
+  } else if (st->rr < st->rmin) {
+    st->rmin = st->rr;
+    st->kmin = st->iter;
+  } else if (st->iter - st->kmin >= st->stall) {
+    st->done = 4;
+  }
+}
+
 // Two-stage preconditioner: n = network correction, then a Jacobi step on what remains,
 //   s = <r, n> / <n, K n> (energy-optimal scale of n; 0 unless both are positive),
 //   z = s n + D^-1 (r - s K n).
@@ -1133,7 +1150,7 @@ int nn_precond_t(tosimp_ctx* ctx, NNState* S, const float* x32, const float* r, 
 // directions and their images in the network state; the iterate is e32.
 int tosimp::nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const float* b32,
                          float* e32, double tol, int maxit, int check_every, int window,
-                         int* iters, int* fallbacks, int* done) {
+                         int stall, int* iters, int* fallbacks, int* done) {
   NNState* S = nn_of(ctx);
   if (!S) return tosimp_fail(ctx, TOSIMP_ESTATE, "NN preconditioner requested but no network");
   if (window < 1) window = 1;
@@ -1158,6 +1175,7 @@ int tosimp::nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const floa
   *sh = SolverState{};
   sh->aux = tol * tol;
   sh->maxit = maxit < 1 ? 1 : maxit;
+  sh->stall = stall > 0 ? stall : 0;
   TOSIMP_HIP(ctx, hipMemcpyAsync(st, sh, sizeof(SolverState), hipMemcpyHostToDevice, ctx->stream));
   node_density_kernel<float><<<2048, 256, 0, ctx->stream>>>(x32, ctx->nx, ctx->ny, ctx->nz,
                                                            S->rho_node);
@@ -1166,6 +1184,7 @@ int tosimp::nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const floa
   double* kvpart = w.partials + 2 * kMaxPartials;
   // r = b (masked), ||r||, ||b||, tolerance; the direction written here is not used
   TOSIMP_HIP(ctx, launch_pcg_init<float>(ctx, b32, nullptr, r, S->fcgP, w.dinv32, st, part, 0));
+  fcg_stall_kernel<<<1, 64, 0, ctx->stream>>>(st, 1);
   const bool mfma = prec == TOSIMP_PREC_BF16_MFMA || prec == TOSIMP_PREC_FP16_MFMA;
   const int vb = std::min(2048, (n + 255) / 256);
   if (check_every < 1) check_every = 1;
@@ -1205,6 +1224,7 @@ int tosimp::nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const floa
       }
       fcg_store_pq_kernel<<<1, 64, 0, ctx->stream>>>(st, S->fpq, slot);
       TOSIMP_HIP(ctx, launch_pcg_update<float>(ctx, e32, r, P, Q, w.dinv32, st, part));
+      fcg_stall_kernel<<<1, 64, 0, ctx->stream>>>(st, 0);
     }
   }
   *iters = sh->iter;

@@ -11,9 +11,10 @@ namespace tosimp {
 
 // ------------------------------------------------------------ sensitivities
 // ce_e = u_e^T K_E u_e evaluated in the Hadamard basis as hat^T S hat (hat = H u_e);
-// dc_e = -p x^(p-1) (E0 - Emin) ce_e.
+// dc_e = -p x^(p-1) (E0 - Emin) ce_e.  dc may be x itself (each thread reads x_e before
+// writing dc_e), so neither carries __restrict__.
 __global__ __launch_bounds__(256) void sensitivity_kernel(
-    const double* __restrict__ x, const double* __restrict__ u, double* __restrict__ dc,
+    const double* x, const double* __restrict__ u, double* dc,
     int nx, int ny, int nz, HadConsts k, double penal, double E0mEmin) {
   const int64_t n_elem = (int64_t)nx * ny * nz;
   const int64_t NX1 = nx + 1, plane = NX1 * (ny + 1);
@@ -129,14 +130,26 @@ hipError_t launch_filter_rowsum(const tosimp_ctx* c, double* Hs) {
 // three-field scheme): out = (tanh(beta eta) + tanh(beta (in - eta))) / den with
 // den = tanh(beta eta) + tanh(beta (1 - eta)); with g, the chain-rule product
 // out = g beta (1 - tanh^2(beta (in - eta))) / den.  Elementwise, 16 bytes (24 with g)
-// per element; out may be in or g itself.
+// per element; out may be in or g itself.  With y = beta (in - eta), each form takes one
+// exponential: tanh|y| = -m / (2 + m) with m = expm1(-2|y|) (no cancellation near y = 0),
+// and 1 - tanh^2 y = 4 s / (1 + s)^2 with s = exp(-2|y|) (no cancellation where tanh is
+// near 1); the constant divisions are folded into factors on the host.
 __global__ __launch_bounds__(256) void project_kernel(const double* in, const double* g,
                                                       double* out, int64_t n, double beta,
-                                                      double eta, double tbe, double den) {
+                                                      double eta, double tbe_den, double inv_den,
+                                                      double four_beta_den) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const double t = tanh(beta * (in[e] - eta));
-    out[e] = g ? g[e] * (beta * (1.0 - t * t) / den) : (tbe + t) / den;
+    const double y = beta * (in[e] - eta);
+    if (g) {
+      const double s = exp(-2.0 * fabs(y));
+      const double q = 1.0 / (1.0 + s);
+      out[e] = g[e] * (four_beta_den * s * q * q);
+    } else {
+      const double m = expm1(-2.0 * fabs(y));
+      const double t = -m / (2.0 + m);
+      out[e] = tbe_den + copysign(t, y) * inv_den;
+    }
   }
 }
 
@@ -145,7 +158,8 @@ hipError_t launch_project(const tosimp_ctx* c, const double* in, const double* g
   const double tbe = tanh(beta * eta), den = tbe + tanh(beta * (1.0 - eta));
   const int64_t n = c->n_elem;
   const int blocks = (int)std::min<int64_t>(4096, (n + 255) / 256);
-  project_kernel<<<blocks, 256, 0, c->stream>>>(in, g, out, n, beta, eta, tbe, den);
+  project_kernel<<<blocks, 256, 0, c->stream>>>(in, g, out, n, beta, eta, tbe / den, 1.0 / den,
+                                                4.0 * beta / den);
   return hipGetLastError();
 }
 

@@ -350,3 +350,69 @@ def test_forward_on_degenerate_grids_matches_oracle(dims):
     ref, _ = nn.unet_forward(params, _to_oracle(x4, grid, 4), BASE)
     t.close()
     assert rel(_to_oracle(out, grid, 3), ref) <= 1e-4
+
+
+def _oracle_fcg_system(nx, ny, nz, x, fixed, f):
+    E = fem.simp_modulus(np.asarray(x, dtype=np.float64), 1.0, 1e-9, 3.0)
+    Kc = fem.constrain(fem.assemble_K(nx, ny, nz, E, fem.element_stiffness(0.3)),
+                       fem.fixed_mask(f.size, fixed))
+    return Kc, Kc.diagonal()
+
+
+def test_fcg_nan_network_takes_the_jacobi_step_every_iteration():
+    """Host-forced fallback: with NaN weights the network output is not finite, so every
+    flexible-CG iteration takes the Jacobi step (the guard the oracle's flexible CG pins);
+    the solve is then Jacobi-PCG and converges to the direct solution."""
+    from paper_2604_18020_amd import FALLBACK_USED
+    t, fixed, f, x = _fcg_problem()
+    nx, ny, nz = t.dims
+    t.nn_create(16, bf16=True)
+    t.nn_set_weights(np.full(t.nn_params, np.nan, dtype=np.float32))
+    kw = dict(tol=1e-8, mode="ir", inner_prec="fp32", inner_tol=1e-5, check_every=1)
+    u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+    s = t.pcg_solve(dev(x), dev(f), u, precond="nn", nn_stall=-1, **kw)
+    u2 = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+    s_j = t.pcg_solve(dev(x), dev(f), u2, precond="jacobi", **kw)
+    t.close()
+    assert s["rc"] == FALLBACK_USED and s["restarts"] == 0
+    assert s["fallbacks"] == s["iterations"] > 0
+    assert abs(s["iterations"] - s_j["iterations"]) <= 0.15 * s_j["iterations"]
+    assert s["true_rel_residual"] <= 1e-8
+    Kc, d = _oracle_fcg_system(nx, ny, nz, x, fixed, f)
+    u_ref = solvers.solve_direct(Kc, f)
+    assert rel(u.cpu().numpy(), u_ref) <= 1e-6
+    # the oracle's guarded flexible CG with the same forced preconditioner
+    info = {}
+    _, it_o, _ = nn.fcg(lambda v: Kc @ v, lambda r: np.full_like(r, np.nan), f, None, 1e-5,
+                        d=d, info=info)
+    assert info["fallbacks"] == it_o
+
+
+def test_fcg_stagnation_restarts_with_jacobi_pcg():
+    """The solve-level fallback: an inner flexible-CG solve whose residual makes no new
+    minimum for nn_stall iterations is finished by plain Jacobi-PCG from its iterate.
+    Forced from the host with nn_stall = 1 (the first iteration that does not lower
+    ||r||) and NaN weights; the oracle's guarded flexible CG restarts at the same point."""
+    from paper_2604_18020_amd import FALLBACK_USED
+    t, fixed, f, x = _fcg_problem()
+    nx, ny, nz = t.dims
+    Kc, d = _oracle_fcg_system(nx, ny, nz, x, fixed, f)
+    info = {}
+    _, _, h = nn.fcg(lambda v: Kc @ v, lambda r: np.full_like(r, np.nan), f, None, 1e-5,
+                     d=d, stall=1, info=info)
+    k = info["fcg_iterations"]
+    assert info["restarted"] and k >= 1
+    # every step up to k is decided with a margin FP32 rounding cannot flip
+    steps = np.array(h[1:k + 1]) / np.minimum.accumulate(np.array(h[:k]))
+    assert np.all(np.abs(steps - 1.0) > 1e-3)
+    t.nn_create(16, bf16=True)
+    t.nn_set_weights(np.full(t.nn_params, np.nan, dtype=np.float32))
+    u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+    s = t.pcg_solve(dev(x), dev(f), u, precond="nn", nn_stall=1, tol=1e-8, mode="ir",
+                    inner_prec="fp32", inner_tol=1e-5, check_every=1)
+    t.close()
+    assert s["rc"] == FALLBACK_USED and s["restarts"] >= 1
+    # the first inner solve (right-hand side f / ||f||) took k flexible-CG iterations
+    assert s["fallbacks"] >= k
+    assert s["true_rel_residual"] <= 1e-8
+    assert rel(u.cpu().numpy(), solvers.solve_direct(Kc, f)) <= 1e-6

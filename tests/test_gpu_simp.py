@@ -63,7 +63,7 @@ def test_oc_matches_oracle(volfrac, move, seed):
     assert ch == pytest.approx(ch_o, abs=1e-15)
 
 
-def test_overlapping_filter_and_oc_buffers_are_refused():
+def test_overlapping_filter_oc_and_sensitivity_buffers_are_refused():
     from paper_2604_18020_amd import TosimpError
     t, _, _ = gpu_problem(8, 4, 4)
     n = t.n_elem
@@ -75,6 +75,13 @@ def test_overlapping_filter_and_oc_buffers_are_refused():
         t.oc_update(buf[:n], dc, 0.3, 0.2, x_new=buf[n - 1:2 * n - 1], xphys_new=buf[2 * n:])
     with pytest.raises(TosimpError, match="overlap"):
         t.oc_update(buf[:n], dc, 0.3, 0.2, x_new=buf[n:2 * n], xphys_new=buf[2 * n - 3:3 * n - 3])
+    u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(TosimpError, match="overlap"):
+        t.sensitivity(buf[:n], u, dc=buf[3:3 + n])  # dc partly over xphys
+    dcx = buf[2 * n:3 * n].clone()
+    t.sensitivity(dcx, u, dc=dcx)  # dc == xphys exactly is accepted (u = 0: dc = 0)
+    torch.cuda.synchronize()
+    assert torch.all(dcx == 0)
     out = t.filter(buf[:n], out=buf[n:2 * n])  # adjacent ranges are accepted
     torch.cuda.synchronize()
     assert torch.allclose(out, torch.full_like(out, 0.3), rtol=0, atol=1e-15)

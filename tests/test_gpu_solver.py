@@ -214,3 +214,27 @@ def test_lanczos_past_the_free_dimension(jacobi):
     lmin, lmax = tridiag_extremes(a, b)
     assert abs(lmax - hi) <= 1e-8 * hi
     assert abs(lmin - lo) <= 1e-8 * hi
+
+
+@pytest.mark.parametrize("mode", ["plain_fp64", "ir"])
+def test_second_order_compliance_estimate(mode):
+    """stats b_dot_u = b^T u, and b_dot_u_corrected = b^T u + u^T (b - K u), which differs
+    from b^T u* by exactly -||u - u*||_K^2 (the identity is checked with the oracle's K
+    and direct solution at a loose tolerance, where the difference is large)."""
+    nx, ny, nz = 16, 8, 8
+    rho = np.random.default_rng(9).uniform(0.1, 1.0, nx * ny * nz)
+    Kc, f = _oracle_system(nx, ny, nz, rho)
+    u_d = solvers.solve_direct(Kc, f)
+    c_star = float(f @ u_d)
+    t, _, _ = gpu_problem(nx, ny, nz)
+    u = torch.zeros(f.size, dtype=torch.float64, device="cuda:0")
+    st = t.pcg_solve(dev(rho), dev(f), u, tol=1e-3, mode=mode, inner_prec="fp32",
+                     inner_tol=1e-1, max_outer=40)
+    t.close()
+    assert st["rc"] == 0
+    uu = u.cpu().numpy()
+    delta = uu - u_d
+    e2 = float(delta @ (Kc @ delta))
+    assert abs(st["b_dot_u"] - f @ uu) <= 1e-12 * abs(c_star)
+    assert abs((st["b_dot_u_corrected"] - c_star) + e2) <= 1e-9 * abs(c_star)
+    assert abs(st["b_dot_u_corrected"] - c_star) <= abs(st["b_dot_u"] - c_star) + 1e-12 * abs(c_star)

@@ -167,6 +167,35 @@ def test_two_routes_for_Kv_agree():
     assert np.array_equal(y2[fixed], v[fixed])
 
 
+@pytest.mark.parametrize("dims", [(5, 4, 3), (1, 1, 1), (7, 2, 5)])
+def test_grid_route_for_Kv_agrees_with_assembly(dims):
+    """The grid-slice route (used for full-size checks) against the assembled CSR and
+    the element-by-element route, with and without Dirichlet rows; a permuted local-node
+    offset or a transposed K_E would break it (K_E is symmetric, but the offsets are
+    not)."""
+    nx, ny, nz = dims
+    E, KE, K = _small(nx, ny, nz, seed=11)
+    n_dof = K.shape[0]
+    v = np.random.default_rng(12).standard_normal(n_dof)
+    assert np.linalg.norm(fem.apply_K_grid(nx, ny, nz, E, KE, v) - K @ v) <= 1e-14 * np.linalg.norm(K @ v)
+    fixed = fem.fixed_mask(n_dof, si.cantilever_fixed_dofs(nx, ny, nz))
+    y1 = fem.constrain(K, fixed) @ v
+    y3 = fem.apply_K_grid(nx, ny, nz, E, KE, v, fixed)
+    assert np.linalg.norm(y1 - y3) <= 1e-14 * np.linalg.norm(y1)
+    assert np.array_equal(y3[fixed], v[fixed])
+
+
+def test_grid_diagonal_agrees_with_element_route():
+    nx, ny, nz = 6, 3, 4
+    E, KE, K = _small(nx, ny, nz, seed=13)
+    fixed = fem.fixed_mask(K.shape[0], si.cantilever_fixed_dofs(nx, ny, nz))
+    d1 = fem.diag_K(nx, ny, nz, E, KE, fixed)
+    d2 = fem.diag_K_grid(nx, ny, nz, E, KE, fixed)
+    assert np.max(np.abs(d1 - d2)) <= 1e-15 * np.max(d1)
+    assert np.array_equal(d2, fem.constrain(K, fixed).diagonal()) or \
+        np.max(np.abs(d2 - fem.constrain(K, fixed).diagonal())) <= 1e-15 * np.max(d1)
+
+
 def test_constrained_operator_rows():
     nx, ny, nz = 3, 2, 2
     E, KE, K = _small(nx, ny, nz)

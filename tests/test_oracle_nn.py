@@ -215,3 +215,62 @@ def test_fcg_window_equals_pcg_with_fixed_preconditioner_and_helps_variable_one(
     its = [nn.fcg(lambda v: Kc @ v, noisy, f, None, 1e-8, window=m)[1] for m in (1, 8)]
     assert its[1] <= its[0]
 
+
+
+def _fcg_system(seed=5):
+    nx, ny, nz = 6, 3, 3
+    rho = np.random.default_rng(seed).uniform(0.2, 1, nx * ny * nz)
+    K = fem.assemble_K(nx, ny, nz, fem.simp_modulus(rho, 1.0, 1e-9, 3.0), fem.element_stiffness(0.3))
+    fixed = fem.fixed_mask(K.shape[0], si.cantilever_fixed_dofs(nx, ny, nz))
+    Kc = fem.constrain(K, fixed)
+    return Kc, si.cantilever_load(nx, ny, nz), Kc.diagonal()
+
+
+@pytest.mark.parametrize("bad", ["nan", "negative"])
+@pytest.mark.parametrize("window", [1, 4])
+def test_fcg_fallback_reproduces_jacobi_pcg(bad, window):
+    """A preconditioner whose output is not finite, or points uphill (<r, z> < 0), is
+    replaced by the Jacobi step at every iteration, so flexible CG becomes Jacobi-PCG
+    (identical in exact arithmetic) and every iteration counts one fallback."""
+    Kc, f, d = _fcg_system()
+    pre = (lambda r: np.full_like(r, np.nan)) if bad == "nan" else (lambda r: -r)
+    info = {}
+    x, it, h = nn.fcg(lambda v: Kc @ v, pre, f, None, 1e-10, window=window, d=d, info=info)
+    _, it_p, h_p = solvers.pcg_jacobi(lambda v: Kc @ v, d, f, None, 1e-10)
+    assert info["fallbacks"] == it and not info["restarted"]
+    assert abs(it - it_p) <= 2
+    assert np.max(np.abs(np.array(h[:30]) / np.array(h_p[:30]) - 1.0)) < 1e-8
+    u = solvers.solve_direct(Kc, f)
+    assert np.linalg.norm(x - u) <= 1e-8 * np.linalg.norm(u)
+
+
+def test_fcg_without_fallback_diagonal_fails_on_nan():
+    """Without the Jacobi diagonal a non-finite preconditioner output propagates (the
+    fallback is what keeps the solve alive)."""
+    Kc, f, _ = _fcg_system()
+    x, it, h = nn.fcg(lambda v: Kc @ v, lambda r: np.full_like(r, np.nan), f, None, 1e-10, maxit=3)
+    assert not np.all(np.isfinite(x))
+
+
+def test_fcg_stall_restarts_into_jacobi_pcg():
+    """Stagnation guard: when ||r|| makes no new minimum for `stall` iterations, flexible
+    CG stops at the first such iteration and plain Jacobi-PCG continues from its iterate."""
+    Kc, f, d = _fcg_system(seed=8)
+    A = lambda v: Kc @ v
+    pre = lambda r: (r / d) * (1.0 + 0.5 * np.sign(r))  # changes with r: not a fixed SPD M
+    stall = 2
+    info = {}
+    x, it, h = nn.fcg(A, pre, f, None, 1e-10, 5000, d=d, stall=stall, info=info)
+    assert info["restarted"] and info["fallbacks"] == 0
+    k = info["fcg_iterations"]
+    # the same iterations without the guard give the same history up to k ...
+    xk, _, hk = nn.fcg(A, pre, f, None, 1e-10, k, d=d)
+    assert hk == h[:k + 1]
+    # ... and k is the first iteration that is `stall` past the running minimum
+    first = next(j for j in range(1, k + 1) if j - int(np.argmin(hk[:j + 1])) >= stall)
+    assert first == k
+    # then plain Jacobi-PCG from the k-th iterate with the iterations left
+    x2, it2, _ = solvers.pcg_jacobi(A, d, f, xk, 1e-10, 5000 - k)
+    assert np.array_equal(x, x2) and it == k + it2
+    u = solvers.solve_direct(Kc, f)
+    assert np.linalg.norm(x - u) <= 1e-8 * np.linalg.norm(u)

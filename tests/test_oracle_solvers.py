@@ -75,6 +75,24 @@ def test_lanczos_matches_dense_eig():
     assert shi / slo < hi / lo
 
 
+def test_jacobi_scaled_kappa_is_the_generalized_problem():
+    """The spectrum of D^-1/2 K D^-1/2 is that of the pencil K x = lambda D x (D the
+    diagonal of K), solved here by the library's generalized symmetric eigensolver."""
+    import scipy.linalg as sla
+    Kc, fixed, _ = _system(6, 3, 3, uniform=0.4)
+    Kff = solvers.free_block(Kc, fixed)
+    A = Kff.toarray()
+    ev = sla.eigh(A, np.diag(np.diag(A)), eigvals_only=True)
+    slo, shi = solvers.kappa_dense(Kff, jacobi_scaled=True)
+    assert abs(slo - ev[0]) <= 1e-10 * ev[-1] and abs(shi - ev[-1]) <= 1e-12 * ev[-1]
+    # a non-uniform density: the diagonal varies, so a wrong scaling would show
+    Kc2, fixed2, _ = _system(6, 3, 3, uniform=None)
+    A2 = solvers.free_block(Kc2, fixed2).toarray()
+    ev2 = sla.eigh(A2, np.diag(np.diag(A2)), eigvals_only=True)
+    slo2, shi2 = solvers.kappa_dense(solvers.free_block(Kc2, fixed2), jacobi_scaled=True)
+    assert abs(slo2 - ev2[0]) <= 1e-8 * ev2[-1] and abs(shi2 - ev2[-1]) <= 1e-12 * ev2[-1]
+
+
 def test_lanczos_on_constrained_operator_stays_free():
     """A start vector that is zero on fixed DOFs keeps K_c's Krylov space in the free
     subspace, so Lanczos on K_c returns K_ff's extremes (identity rows never enter)."""
