@@ -80,8 +80,10 @@ typedef struct tosimp_solve_opts {
   int max_outer;     /* cap on refinement steps in IR mode                            */
   int precond;       /* TOSIMP_PRECOND_*                                              */
   int check_every;   /* host convergence polls every this many iterations (>= 1)      */
-  int enforce_rule;  /* 1: refuse inner precisions failing u*kappa < 1 (needs kappa)  */
-  double kappa;      /* condition estimate used by enforce_rule (0: unknown)          */
+  int enforce_rule;  /* refuse inner precisions failing u * kappa < 1 (EPRECISION):    */
+                     /*   0 off; 1 with the caller's kappa; 2 with the library's own   */
+                     /*   estimate (see tosimp_pcg_solve)                               */
+  double kappa;      /* condition estimate used by enforce_rule 1                      */
   float* harvest_r;  /* PLAIN_FP64 only, optional (NULL = off): device FP32 array of    */
   float* harvest_u;  /*   harvest_cap x n_dof each, receiving r_k and u_k every          */
   int harvest_cap;   /*   harvest_every iterations (k = 0, he, 2 he, ...) until full;    */
@@ -106,21 +108,54 @@ typedef struct tosimp_solve_stats {
   double b_dot_u;          /* b^T u (the compliance when b = f)                      */
   double b_dot_u_corrected;/* b^T u + u^T (b - K u) = 2 b^T u - u^T K u: differs from */
                            /* b^T u* by -||u - u*||_K^2 only (second order in u - u*) */
+  int escalations;         /* IR: inner precision raised to FP32 after stagnation    */
+  double kappa;            /* the kappa enforce_rule used (0 when off)               */
 } tosimp_solve_stats;
 
 typedef struct tosimp_step_opts {
   double volfrac;    /* target volume fraction                                       */
   double move;       /* OC move limit                                                 */
   tosimp_solve_opts solve;
+  double beta;       /* > 0: three-field scheme with projection sharpness beta;       */
+                     /*   <= 0: density-filter scheme (no projection)                 */
+  double eta;        /* projection threshold (three-field scheme)                     */
 } tosimp_step_opts;
 
 typedef struct tosimp_step_stats {
   double compliance; /* f^T u after the solve                                         */
   double change;     /* max |x_new - x|                                               */
-  double volume;     /* mean of the new filtered density                              */
+  double volume;     /* mean of the new physical density                              */
   int bisection_steps;
   tosimp_solve_stats solve;
+  double grayness;   /* 4/n sum xphys (1 - xphys) of the density the solve used       */
 } tosimp_step_stats;
+
+/* The SIMP-120 protocol (paper Sec. "Experimental Setup"): see tosimp_simp_protocol. */
+typedef struct tosimp_protocol_opts {
+  int iters;              /* outer iterations (the paper: 120)                        */
+  double volfrac;         /* volume fraction of the projected density                 */
+  double eta;             /* projection threshold (the paper: 0.5)                    */
+  double restart_factor;  /* restart when c > restart_factor * c_selected (1.12)      */
+  double eligible_penal;  /* selection needs penal >= this (3.0) ...                  */
+  double eligible_gray;   /* ... and grayness < this (0.25)                           */
+  int nphases;            /* 0: the paper's four phases; else phases[5 * nphases]:     */
+  const double* phases;   /*   last iteration, penal, beta, move, rmin at the phase   */
+                          /*   end (<= 0: unchanged), host memory                      */
+  tosimp_solve_opts solve;
+} tosimp_protocol_opts;
+
+typedef struct tosimp_protocol_record {
+  int it;                 /* 1-based iteration                                        */
+  int cg_iterations;
+  int bisection_steps;    /* 0 on a restart                                           */
+  int restart;            /* 1: the next design is the selected one (no update)       */
+  int eligible;           /* penal and grayness admit the iterate to selection        */
+  int selected;           /* 1: the iterate became the selected one                   */
+  double penal, beta, move, rmin;
+  double compliance;      /* f^T u                                                     */
+  double grayness;        /* of the projected density                                  */
+  double change;          /* max |x_new - x| of the update (0 on a restart)            */
+} tosimp_protocol_record;
 
 /* ---- lifecycle ------------------------------------------------------------------
  * tosimp_create: make a context on HIP device `device` using `stream` (a hipStream_t,
@@ -184,9 +219,17 @@ int tosimp_diag_K(tosimp_ctx* ctx, const void* xphys_dev, int xdtype, void* d_de
  * preconditioned residual is not a descent direction (<r, z> <= 0) or not finite takes
  * the Jacobi step instead (stats->fallbacks), and an inner solve that stagnates
  * (opts->nn_stall) is finished by plain Jacobi-PCG (stats->restarts).
+ * IR stagnation (two outer steps in a row that do not halve the true residual) raises a
+ * matrix-core inner precision to FP32 (stats->escalations); at FP32 it ends the solve
+ * with NOT_CONVERGED.  The precision rule (paper Sec. "Condition Number Estimation",
+ * Eq. bf16barrier) admits inner precision l only when u_l * kappa < 1 with unit
+ * roundoffs 2^-8 (BF16), 2^-11 (FP16), 2^-24 (FP32); with enforce_rule = 2 kappa is the
+ * library's estimate for the Jacobi-scaled operator at uniform density (Lanczos as in
+ * tosimp_kappa with rtol 1e-3, window 50, at most 5,000 steps, seeded start vector),
+ * computed on first use and kept until the mesh or boundary conditions change.
  * Returns OK, NOT_CONVERGED (cap hit, u valid), FALLBACK_USED (a fallback or restart was
- * taken, u valid), EBREAKDOWN or EPRECISION (enforce_rule and u_inner * kappa >= 1).
- * stats may be NULL.
+ * taken, u valid), EBREAKDOWN or EPRECISION (the rule refused the inner precision; stats
+ * holds the kappa used).  stats may be NULL.
  * The solve runs on a stream of the context, ordered after the work already enqueued on
  * the caller's stream and before any work enqueued there after the call.            */
 int tosimp_pcg_solve(tosimp_ctx* ctx, const double* xphys_dev, const double* b_dev,
@@ -200,7 +243,8 @@ int tosimp_pcg_solve(tosimp_ctx* ctx, const double* xphys_dev, const double* b_d
  * overlap u, which is read around every element (EINVAL).                            */
 int tosimp_sensitivity(tosimp_ctx* ctx, const double* xphys_dev, const double* u_dev,
                        double* dc_dev, double* c_host);
-/* Cone density filter, weights max(0, rmin - centroid distance), neighbourhood cut
+/* Cone density filter (paper Sec. "Three-Dimensional SIMP Topology Optimization", the
+ * filter of radius rmin), weights max(0, rmin - centroid distance), neighbourhood cut
  * at the domain boundary.  FORWARD: out = H in / Hs; ADJOINT: out = H (in / Hs).
  * in, out: n_elem FP64, must not overlap (EINVAL).                                    */
 int tosimp_filter(tosimp_ctx* ctx, const double* in_dev, double* out_dev, int mode);
@@ -214,8 +258,17 @@ int tosimp_filter(tosimp_ctx* ctx, const double* in_dev, double* out_dev, int mo
  * must not partly overlap either (EINVAL).  Asynchronous.                             */
 int tosimp_project(tosimp_ctx* ctx, const double* in_dev, const double* g_dev,
                    double* out_dev, double beta, double eta);
-/* Optimality-criteria update with bisection on the volume multiplier (bracket
- * [0, 1e9], stop when (l2-l1)/(l1+l2) <= 1e-3):
+/* tosimp_set_params: change the SIMP penalty and the filter radius of the current mesh
+ * (continuation); the filter weights, row sums and H(1/Hs) are rebuilt when rmin
+ * changes.  Ranges as tosimp_set_mesh.  Synchronises.                               */
+int tosimp_set_params(tosimp_ctx* ctx, double penal, double rmin);
+/* tosimp_grayness (paper Sec. "Experimental Setup"): g = 4/n sum_e rho_e (1 - rho_e)
+ * of n_elem FP64 device values, into *g_host (FP64 reduction).  Synchronises.        */
+int tosimp_grayness(tosimp_ctx* ctx, const double* rho_dev, double* g_host);
+/* Optimality-criteria update of the density-filter scheme (paper Sec.
+ * "Three-Dimensional SIMP Topology Optimization"; the three-field update with the
+ * projected volume is part of tosimp_simp_step) with bisection on the volume
+ * multiplier (bracket [0, 1e9], stop when (l2-l1)/(l1+l2) <= 1e-3):
  * x_new = clip(x sqrt(-dc / (dv lambda)), max(0, x - move), min(1, x + move)) with
  * dv = H(1/Hs); the volume test is sum(filter(x_new)) > volfrac n_elem, evaluated
  * exactly as the weighted sum dv^T x_new.  dc must be the filtered sensitivity.
@@ -226,12 +279,42 @@ int tosimp_project(tosimp_ctx* ctx, const double* in_dev, const double* g_dev,
 int tosimp_oc_update(tosimp_ctx* ctx, const double* x_dev, const double* dc_dev,
                      double volfrac, double move, double* x_new_dev,
                      double* xphys_new_dev, double* change_host, int* steps_host);
-/* One SIMP iteration: solve K(xphys) u = f (warm start from u_inout), sensitivity,
- * adjoint filter, OC update; x_inout and xphys_inout (n_elem FP64) are replaced by the
- * new design, u_inout (n_dof FP64) by the solution.  Synchronises.                  */
+/* One SIMP iteration (paper Sec. "Software Architecture" gives the order): solve
+ * K(xphys) u = f (warm start from u_inout), sensitivity, chain rule to the design, OC
+ * update; x_inout and xphys_inout (n_elem FP64) are replaced by the new design and its
+ * physical density, u_inout (n_dof FP64) by the solution.  xphys_inout must be the
+ * physical density of x_inout on entry.
+ *   opts->beta <= 0, density-filter scheme: xphys = H x / Hs, dc <- H (dc / Hs), OC on
+ *     the filtered volume (tosimp_oc_update).
+ *   opts->beta > 0, three-field scheme (paper Sec. "Three-Dimensional SIMP Topology
+ *     Optimization", projection equation): xbar = H x / Hs, xphys = project(xbar);
+ *     dc <- H ((dc * project'(xbar)) / Hs), dv = H (project'(xbar) / Hs), and the OC
+ *     bisection tests the projected volume sum project(filter(x_new)) against
+ *     volfrac n_elem.
+ * x, xphys and u must not overlap (EINVAL).  Synchronises.                           */
 int tosimp_simp_step(tosimp_ctx* ctx, double* x_inout_dev, double* xphys_inout_dev,
                      double* u_inout_dev, const tosimp_step_opts* opts,
                      tosimp_step_stats* stats);
+/* tosimp_simp_protocol: the three-field SIMP-120 protocol of paper Sec. "Experimental
+ * Setup".  Iteration it = 1..iters: (penal, beta, move, rmin) from the continuation
+ * phases (the paper's: it 1-15 (1.5, 1, 0.20); 16-40 (3.5, 4, 0.15) with rmin moving
+ * linearly to 1.35; 41-65 (4.5, 16, 0.08) to 1.25; 66-120 (4.5, 32, 0.05) to 1.20;
+ * the initial radius is the context's); xphys = project(filter(x)); solve (warm start);
+ * c = f^T u; g = grayness(xphys).  If a selected iterate exists and c > restart_factor
+ * c_selected, the next design is the selected design (restart); otherwise the iterate
+ * is eligible when penal >= eligible_penal and g < eligible_gray, becomes the selected
+ * one when its c is the lowest eligible so far, and the three-field update of
+ * tosimp_simp_step gives the next design.
+ * x_inout: the initial design (the paper: volfrac everywhere), replaced by the final
+ * one; x_sel_dev receives the selected design (unchanged if none); xphys_out the
+ * physical density of the last iteration; u_inout the warm start and final solution
+ * (all FP64 device, no overlaps).  records_host: iters entries.  *it_selected (0 if
+ * none) and *c_selected.  The penalty and radius of the context are restored at exit.
+ * Synchronises.                                                                        */
+int tosimp_simp_protocol(tosimp_ctx* ctx, double* x_inout_dev, double* x_sel_dev,
+                         double* xphys_out_dev, double* u_inout_dev,
+                         const tosimp_protocol_opts* opts, tosimp_protocol_record* records_host,
+                         int* it_selected, double* c_selected);
 
 /* ---- conditioning ----------------------------------------------------------------
  * tosimp_lanczos (paper Sec. "Condition Number Estimation" estimates the extremes of
@@ -247,6 +330,17 @@ int tosimp_lanczos(tosimp_ctx* ctx, const double* xphys_dev, const double* v0_de
                    int* steps_host);
 int tosimp_tridiag_extremes(const double* alpha, const double* beta, int m, double* lmin,
                             double* lmax);
+/* tosimp_kappa (paper Sec. "Condition Number Estimation"): extreme eigenvalues of
+ * K_c(xphys) (jacobi_scaled = 0) or D^-1/2 K_c D^-1/2 (1) by the Lanczos of
+ * tosimp_lanczos with a stopping rule: after every `window` steps the smallest Ritz
+ * value is compared with its value `window` steps earlier, and the run stops once they
+ * agree to rtol (relative), on an invariant subspace, or after kmax steps.  *lmin is an
+ * upper bound of the smallest eigenvalue and *lmax a lower bound of the largest, so
+ * lmax / lmin bounds kappa from below.  *steps = steps taken, *converged = 1 unless kmax
+ * ended the run.  v0 as in tosimp_lanczos.  Synchronises every window.              */
+int tosimp_kappa(tosimp_ctx* ctx, const double* xphys_dev, const double* v0_dev, int kmax,
+                 int jacobi_scaled, double rtol, int window, double* lmin, double* lmax,
+                 int* steps, int* converged);
 
 /* ---- learned preconditioner -------------------------------------------------------
  * A 3-level 3D-convolutional U-Net N on the node grid supplies the correction of a

@@ -92,6 +92,26 @@ def lanczos_tridiagonal(apply_A, v0: np.ndarray, k: int, reorthogonalize: bool =
     return np.array(alphas), np.array(betas)
 
 
+def lanczos_extremes(apply_A, v0: np.ndarray, kmax: int, rtol: float = 1e-3, window: int = 50):
+    """Lanczos with the precision study's stopping rule: after every `window` steps the
+    smallest Ritz value (smallest eigenvalue of the tridiagonal T_j of the steps so far)
+    is compared with its value `window` steps earlier; the run stops at the first j with
+    |theta_j - theta_{j - window}| <= rtol * theta_j, or after kmax steps.  The
+    coefficients of the first j steps do not depend on later ones, so this is evaluated
+    on prefixes of one kmax-step run.  Returns (lmin, lmax, steps, converged): lmin is an
+    upper bound of the smallest eigenvalue, lmax a lower bound of the largest."""
+    a, b = lanczos_tridiagonal(apply_A, v0, kmax)
+    m = a.size
+    prev = None
+    for j in range(window, m + 1, window):
+        lo, hi = tridiagonal_extremes(a[:j], b[:j - 1])
+        if prev is not None and abs(lo - prev) <= rtol * abs(lo):
+            return lo, hi, j, True
+        prev = lo
+    lo, hi = tridiagonal_extremes(a, b[:m - 1])
+    return lo, hi, m, m < kmax
+
+
 def tridiagonal_extremes(alpha: np.ndarray, beta: np.ndarray):
     """Smallest and largest eigenvalue of the symmetric tridiagonal (alpha, beta)."""
     ev = sla.eigh_tridiagonal(alpha, beta, eigvals_only=True)

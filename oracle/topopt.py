@@ -194,3 +194,124 @@ def simp_run(prob: Problem, iters: int, tol=1e-8, move=0.2, direct=False, maxit=
                          vol=float(xphys_new.mean())))
         x, xphys = xnew, xphys_new
     return hist, x, xphys, u
+
+
+# ----------------------------------------------------------- three-field SIMP protocol
+def grayness(rho):
+    """g = 4/n sum_e rho_e (1 - rho_e) (Sec. "Experimental Setup"): 0 for a 0/1 design,
+    1 for a uniform 0.5 field."""
+    rho = np.asarray(rho, dtype=np.float64)
+    return float(4.0 * np.sum(rho * (1.0 - rho)) / rho.size)
+
+
+def projected_volume_gradient(H, Hs, xbar, beta, eta=0.5):
+    """d/dx of sum_e project(filter(x))_e: H^T (project'(xbar) / Hs)."""
+    return filter_adjoint(H, Hs, heaviside_derivative(xbar, beta, eta))
+
+
+def oc_update_projected(x, dc, dv, H, Hs, beta, eta, volfrac, move=0.2, l1=0.0, l2=1e9,
+                        rel_tol=1e-3, max_steps=256):
+    """OC update of the three-field scheme: the same bisection and update rule as
+    oc_update, with the volume of the projected density, sum(project(filter(x_new))),
+    tested against volfrac * n (dc and dv are derivatives with respect to x).  Returns
+    (x_new, xphys_new (projected), change, steps)."""
+    n = x.size
+    target = volfrac * n
+    steps = 0
+    while (l2 - l1) / (l1 + l2) > rel_tol:
+        if steps >= max_steps:
+            raise RuntimeError("OC bisection did not terminate")
+        lmid = 0.5 * (l2 + l1)
+        xnew = np.sqrt(-dc / (dv * lmid)) * x
+        xnew = np.minimum(np.minimum(xnew, x + move), 1.0)
+        xnew = np.maximum(np.maximum(xnew, x - move), 0.0)
+        xphys = heaviside_project(filter_forward(H, Hs, xnew), beta, eta)
+        if xphys.sum() > target:
+            l1 = lmid
+        else:
+            l2 = lmid
+        steps += 1
+    change = float(np.max(np.abs(xnew - x)))
+    return xnew, xphys, change, steps
+
+
+# The four-phase continuation of the SIMP-120 protocol (Sec. "Experimental Setup"):
+# (last iteration of the phase, penalty p, projection sharpness beta, OC move limit,
+#  filter radius reached at the end of the phase; None = unchanged).
+CONTINUATION = ((15, 1.5, 1.0, 0.20, None),
+                (40, 3.5, 4.0, 0.15, 1.35),
+                (65, 4.5, 16.0, 0.08, 1.25),
+                (120, 4.5, 32.0, 0.05, 1.20))
+
+
+def continuation(it, rmin0=1.5, phases=CONTINUATION):
+    """(p, beta, move, rmin) of 1-based iteration `it`.  Within a phase with a radius
+    target, rmin moves linearly from the previous phase's final value to the target,
+    reaching it on the phase's last iteration; iterations past the last phase keep the
+    last phase's values."""
+    start, r_prev = 1, rmin0
+    for last, p, beta, move, r_end in phases:
+        if r_end is None:
+            r_end_v = r_prev
+        else:
+            r_end_v = r_end
+        if it <= last:
+            frac = (it - start + 1) / (last - start + 1)
+            return p, beta, move, r_prev + (r_end_v - r_prev) * frac
+        start, r_prev = last + 1, r_end_v
+    last, p, beta, move, r_end = phases[-1]
+    return p, beta, move, r_prev
+
+
+def simp_protocol(prob: Problem, iters=120, eta=0.5, tol=1e-8, maxit=20000, direct=False,
+                  restart_factor=1.12, eligible_penal=3.0, eligible_gray=0.25,
+                  phases=CONTINUATION):
+    """Three-field SIMP with the continuation schedule, the restart rule and the
+    selected iterate (Sec. "Experimental Setup").  Iteration it = 1..iters:
+      (p, beta, m, rmin) = continuation(it); xbar = filter_rmin(x); xphys = project(xbar);
+      solve K_p(xphys) u = f (warm start); c = f^T u; g = grayness(xphys);
+      restart: if a selected iterate exists and c > restart_factor * c_selected, the next
+        design is the selected design field (no update this iteration);
+      otherwise the iterate is eligible when p >= eligible_penal and g < eligible_gray, and
+        becomes the selected one when its c is the lowest eligible so far; then the OC
+        update with the projected volume gives the next design.
+    The problem's own rmin is the initial filter radius.  Returns (history, selected, x, u)
+    with selected = dict(it, c, g, x, xphys) or None; x is the design after the last
+    iteration and u the last displacement."""
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    x = np.full(prob.n_elem, prob.volfrac)
+    u = np.zeros(prob.n_dof)
+    hist, sel = [], None
+    for it in range(1, iters + 1):
+        p, beta, move, rmin = continuation(it, prob.rmin, phases)
+        H, Hs = filter_matrix(nx, ny, nz, rmin)
+        xbar = filter_forward(H, Hs, x)
+        xphys = heaviside_project(xbar, beta, eta)
+        E = fem.simp_modulus(xphys, prob.E0, prob.Emin, p)
+        Kc = fem.constrain(fem.assemble_K(nx, ny, nz, E, prob.KE), prob.fixed)
+        if direct:
+            u, its = solvers.solve_direct(Kc, prob.f), 0
+        else:
+            d = fem.diag_K(nx, ny, nz, E, prob.KE, prob.fixed)
+            u, its, _ = solvers.pcg_jacobi(lambda v: Kc @ v, d, prob.f, u, tol, maxit)
+        c = compliance(prob.f, u)
+        g = grayness(xphys)
+        rec = dict(it=it, penal=p, beta=beta, move=move, rmin=rmin, c=c, gray=g,
+                   cg_iters=its, restart=False, eligible=False)
+        if sel is not None and c > restart_factor * sel["c"]:
+            rec["restart"] = True
+            hist.append(rec)
+            x = sel["x"].copy()
+            continue
+        if p >= eligible_penal and g < eligible_gray:
+            rec["eligible"] = True
+            if sel is None or c < sel["c"]:
+                sel = dict(it=it, c=c, g=g, x=x.copy(), xphys=xphys.copy())
+        dc_phys = sensitivity(nx, ny, nz, xphys, u, prob.KE, prob.E0, prob.Emin, p)
+        dc = filter_adjoint(H, Hs, dc_phys * heaviside_derivative(xbar, beta, eta))
+        dv = projected_volume_gradient(H, Hs, xbar, beta, eta)
+        x, _, change, steps = oc_update_projected(x, dc, dv, H, Hs, beta, eta, prob.volfrac,
+                                                  move)
+        rec.update(change=change, bisect=steps)
+        hist.append(rec)
+    return hist, sel, x, u

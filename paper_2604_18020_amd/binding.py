@@ -45,24 +45,44 @@ class SolveStats(C.Structure):
                 ("fallbacks", C.c_int), ("status", C.c_int),
                 ("rel_residual", C.c_double), ("true_rel_residual", C.c_double),
                 ("harvested", C.c_int), ("restarts", C.c_int), ("b_dot_u", C.c_double),
-                ("b_dot_u_corrected", C.c_double)]
+                ("b_dot_u_corrected", C.c_double), ("escalations", C.c_int),
+                ("kappa", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class StepOpts(C.Structure):
-    _fields_ = [("volfrac", C.c_double), ("move", C.c_double), ("solve", SolveOpts)]
+    _fields_ = [("volfrac", C.c_double), ("move", C.c_double), ("solve", SolveOpts),
+                ("beta", C.c_double), ("eta", C.c_double)]
 
 
 class StepStats(C.Structure):
     _fields_ = [("compliance", C.c_double), ("change", C.c_double), ("volume", C.c_double),
-                ("bisection_steps", C.c_int), ("solve", SolveStats)]
+                ("bisection_steps", C.c_int), ("solve", SolveStats), ("grayness", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "solve"}
         d["solve"] = self.solve.as_dict()
         return d
+
+
+class ProtocolOpts(C.Structure):
+    _fields_ = [("iters", C.c_int), ("volfrac", C.c_double), ("eta", C.c_double),
+                ("restart_factor", C.c_double), ("eligible_penal", C.c_double),
+                ("eligible_gray", C.c_double), ("nphases", C.c_int),
+                ("phases", C.POINTER(C.c_double)), ("solve", SolveOpts)]
+
+
+class ProtocolRecord(C.Structure):
+    _fields_ = [("it", C.c_int), ("cg_iterations", C.c_int), ("bisection_steps", C.c_int),
+                ("restart", C.c_int), ("eligible", C.c_int), ("selected", C.c_int),
+                ("penal", C.c_double), ("beta", C.c_double), ("move", C.c_double),
+                ("rmin", C.c_double), ("compliance", C.c_double), ("grayness", C.c_double),
+                ("change", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 def _load():
@@ -89,8 +109,14 @@ def _load():
         "tosimp_project": (I, [P, P, P, P, D, D]),
         "tosimp_oc_update": (I, [P, P, P, D, D, P, P, C.POINTER(D), C.POINTER(I)]),
         "tosimp_simp_step": (I, [P, P, P, P, C.POINTER(StepOpts), C.POINTER(StepStats)]),
+        "tosimp_set_params": (I, [P, D, D]),
+        "tosimp_grayness": (I, [P, P, C.POINTER(D)]),
+        "tosimp_simp_protocol": (I, [P, P, P, P, P, C.POINTER(ProtocolOpts),
+                                     C.POINTER(ProtocolRecord), C.POINTER(I), C.POINTER(D)]),
         "tosimp_lanczos": (I, [P, P, P, I, I, P, P, C.POINTER(I)]),
         "tosimp_tridiag_extremes": (I, [P, P, I, C.POINTER(D), C.POINTER(D)]),
+        "tosimp_kappa": (I, [P, P, P, I, I, D, I, C.POINTER(D), C.POINTER(D), C.POINTER(I),
+                             C.POINTER(I)]),
         "tosimp_nn_create": (I, [P, I, I]),
         "tosimp_nn_num_params": (I, [P, C.POINTER(L)]),
         "tosimp_nn_set_weights": (I, [P, P, L]),
@@ -283,9 +309,47 @@ class Tosimp:
             self._dev(xpn, torch.float64, self.n_elem, "xphys_new"), C.byref(ch), C.byref(st)))
         return xn, xpn, ch.value, st.value
 
+    def set_params(self, penal, rmin):
+        self._sync_stream()
+        self._check(LIB.tosimp_set_params(self._h, float(penal), float(rmin)))
+
+    def grayness(self, rho):
+        g = C.c_double()
+        self._sync_stream()
+        self._check(LIB.tosimp_grayness(self._h, self._dev(rho, torch.float64, self.n_elem, "rho"),
+                                        C.byref(g)))
+        return g.value
+
+    def simp_protocol(self, x, u, iters=120, volfrac=0.3, eta=0.5, restart_factor=1.12,
+                      eligible_penal=3.0, eligible_gray=0.25, phases=None, x_sel=None,
+                      xphys=None, **solve_kw):
+        """Three-field SIMP with continuation, restart and selection.  phases: None (the
+        paper's four) or a sequence of (last_it, penal, beta, move, rmin_end or None).
+        Returns (records, it_selected, c_selected, x_sel, xphys)."""
+        x_sel = torch.empty_like(x) if x_sel is None else x_sel
+        xphys = torch.empty_like(x) if xphys is None else xphys
+        if phases is None:
+            nph, arr = 0, None
+        else:
+            flat = [float(v if v is not None else 0.0) for ph in phases for v in ph]
+            nph, arr = len(phases), (C.c_double * len(flat))(*flat)
+        o = ProtocolOpts(int(iters), volfrac, eta, restart_factor, eligible_penal, eligible_gray,
+                         nph, arr, self.solve_opts(**solve_kw))
+        rec = (ProtocolRecord * int(iters))()
+        its, cs = C.c_int(), C.c_double()
+        self._sync_stream()
+        self._check(LIB.tosimp_simp_protocol(
+            self._h, self._dev(x, torch.float64, self.n_elem, "x"),
+            self._dev(x_sel, torch.float64, self.n_elem, "x_sel"),
+            self._dev(xphys, torch.float64, self.n_elem, "xphys"),
+            self._dev(u, torch.float64, self.n_dof, "u"), C.byref(o), rec, C.byref(its),
+            C.byref(cs)))
+        return [r.as_dict() for r in rec], its.value, cs.value, x_sel, xphys
+
     def simp_step(self, x, xphys, u, volfrac=0.3, move=0.2, harvest=None, harvest_every=1,
-                  **solve_kw):
-        o = StepOpts(volfrac, move, self._opts_with_harvest(harvest, harvest_every, **solve_kw))
+                  beta=0.0, eta=0.5, **solve_kw):
+        o = StepOpts(volfrac, move, self._opts_with_harvest(harvest, harvest_every, **solve_kw),
+                     float(beta), float(eta))
         s = StepStats()
         self._sync_stream()
         rc = self._check(LIB.tosimp_simp_step(
@@ -308,6 +372,16 @@ class Tosimp:
             a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), C.byref(m)))
         return a[:m.value].copy(), b[:max(m.value - 1, 0)].copy()
 
+
+    def kappa(self, x, v0, kmax=5000, jacobi_scaled=True, rtol=1e-3, window=50):
+        """Lanczos extremes with the stopping rule: (lmin, lmax, steps, converged)."""
+        lo, hi, st, cv = C.c_double(), C.c_double(), C.c_int(), C.c_int()
+        self._sync_stream()
+        self._check(LIB.tosimp_kappa(
+            self._h, self._dev(x, torch.float64, self.n_elem, "x"),
+            self._dev(v0, torch.float64, self.n_dof, "v0"), int(kmax), int(jacobi_scaled),
+            float(rtol), int(window), C.byref(lo), C.byref(hi), C.byref(st), C.byref(cv)))
+        return lo.value, hi.value, st.value, bool(cv.value)
 
     # ------------------------------------------------------------------ learned preconditioner
     def nn_create(self, base=16, bf16=True):

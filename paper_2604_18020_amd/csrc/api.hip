@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <random>
 #include <vector>
 
 #include "common.h"
@@ -186,6 +187,30 @@ int set_device(tosimp_ctx* ctx) {
   return TOSIMP_OK;
 }
 
+// Cone filter of radius ctx->rmin: weights max(0, rmin - |offset|) on the offset cube,
+// the row sums Hs = H 1 and dv = H (1 / Hs) (the adjoint filter of ones).  Uses etmp.
+int load_filter(tosimp_ctx* ctx) {
+  Workspace& w = ctx->ws;
+  ctx->fR = (int)std::ceil(ctx->rmin) - 1;
+  const int W = 2 * ctx->fR + 1;
+  for (int i = 0; i < kMaxFilterTaps; ++i) ctx->fw_host[i] = 0.0;
+  for (int dk = 0; dk < W; ++dk)
+    for (int dj = 0; dj < W; ++dj)
+      for (int di = 0; di < W; ++di) {
+        const double d = std::sqrt((double)((di - ctx->fR) * (di - ctx->fR) +
+                                            (dj - ctx->fR) * (dj - ctx->fR) +
+                                            (dk - ctx->fR) * (dk - ctx->fR)));
+        ctx->fw_host[di + W * (dj + W * dk)] = std::max(0.0, ctx->rmin - d);
+      }
+  TOSIMP_HIP(ctx, hipMemcpyAsync(w.fw, ctx->fw_host, sizeof(double) * kMaxFilterTaps,
+                                 hipMemcpyHostToDevice, ctx->stream));
+  TOSIMP_HIP(ctx, launch_filter_rowsum(ctx, w.Hs));
+  TOSIMP_HIP(ctx, launch_fill64(ctx, w.etmp, ctx->n_elem, 1.0));
+  TOSIMP_HIP(ctx, launch_filter(ctx, w.etmp, w.dv, TOSIMP_FILTER_ADJOINT, w.Hs));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TOSIMP_OK;
+}
+
 }  // namespace
 
 // ===================================================================== lifecycle
@@ -266,6 +291,7 @@ int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0
   TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   free_ws(ctx);
   ctx->has_mesh = ctx->has_bcs = ctx->has_loads = false;
+  ctx->kappa_uniform = 0;
   ctx->nx = nx; ctx->ny = ny; ctx->nz = nz;
   ctx->n_elem = n_elem; ctx->n_node = n_node; ctx->n_dof = 3 * n_node;
   ctx->h = h; ctx->E0 = E0; ctx->Emin = Emin; ctx->nu = nu; ctx->penal = penal;
@@ -278,18 +304,6 @@ int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0
   for (int i = 1; i < 24; ++i)
     REQUIRE(std::fabs(ctx->KE[i * 25] - ctx->kd) <= 1e-14 * ctx->kd, TOSIMP_EINVAL,
             "unequal diagonal of K_E");
-  // Filter weights on the offset cube.
-  ctx->fR = (int)std::ceil(rmin) - 1;
-  const int W = 2 * ctx->fR + 1;
-  for (int dk = 0; dk < W; ++dk)
-    for (int dj = 0; dj < W; ++dj)
-      for (int di = 0; di < W; ++di) {
-        const double d = std::sqrt((double)((di - ctx->fR) * (di - ctx->fR) +
-                                            (dj - ctx->fR) * (dj - ctx->fR) +
-                                            (dk - ctx->fR) * (dk - ctx->fR)));
-        ctx->fw_host[di + W * (dj + W * dk)] = std::max(0.0, rmin - d);
-      }
-
   Workspace& w = ctx->ws;
   const size_t nd = (size_t)ctx->n_dof, nn = (size_t)n_node, ne = (size_t)n_elem;
   hipError_t e = hipSuccess;
@@ -311,7 +325,7 @@ int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0
   A(dmalloc(&w.e32, nd * 4));
   A(dmalloc(&w.z32, nd * 4));
   A(dmalloc(&w.x32, ne * 4));
-  A(dmalloc(&w.etmp, ne * 8 * 4));
+  A(dmalloc(&w.etmp, ne * 8 * 6));
   // partial sums: 2 kMaxPartials for the vector kernels, then one slot per operator tile
   w.kv_part_cap = std::max<int64_t>(2 * kMaxPartials, kv_num_blocks(ctx));
   A(dmalloc(&w.partials, sizeof(double) * (2 * kMaxPartials + w.kv_part_cap)));
@@ -328,8 +342,6 @@ int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0
   TOSIMP_HIP(ctx, hipMemsetAsync(w.f, 0, nd * 8, ctx->stream));
   TOSIMP_HIP(ctx, hipMemsetAsync(w.st, 0, sizeof(SolverState) * 3, ctx->stream));
   TOSIMP_HIP(ctx, hipMemsetAsync(w.oc, 0, sizeof(OcState), ctx->stream));
-  TOSIMP_HIP(ctx, hipMemcpyAsync(w.fw, ctx->fw_host, sizeof(double) * kMaxFilterTaps,
-                                 hipMemcpyHostToDevice, ctx->stream));
   {
     // K_E (24x24, zero-padded to 32x32) in the A-operand lane layout of
     // v_mfma_f32_16x16x32_{bf16,f16}: lane l holds row 16 t + l % 16, columns
@@ -356,16 +368,22 @@ int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0
                                    ctx->stream));
     TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   }
-  TOSIMP_HIP(ctx, launch_filter_rowsum(ctx, w.Hs));
-  // dv = H (1 / Hs): adjoint filter of a vector of ones.
-  double* ones = w.etmp;
-  {
-    std::vector<double> h1(ne, 1.0);
-    TOSIMP_HIP(ctx, hipMemcpyAsync(ones, h1.data(), ne * 8, hipMemcpyHostToDevice, ctx->stream));
-    TOSIMP_HIP(ctx, launch_filter(ctx, ones, w.dv, TOSIMP_FILTER_ADJOINT, w.Hs));
-    TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  }
+  if ((rc = load_filter(ctx))) return rc;
   ctx->has_mesh = true;
+  return TOSIMP_OK;
+}
+
+int tosimp_set_params(tosimp_ctx* ctx, double penal, double rmin) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(penal >= 1.0 && penal <= 16.0, TOSIMP_EINVAL, "penal must be in [1, 16]");
+  REQUIRE(rmin > 0 && rmin <= kMaxFilterR + 1, TOSIMP_EINVAL, "rmin must be in (0, 4]");
+  if ((rc = set_device(ctx))) return rc;
+  ctx->penal = penal;
+  if (rmin != ctx->rmin) {
+    ctx->rmin = rmin;
+    if ((rc = load_filter(ctx))) return rc;
+  }
   return TOSIMP_OK;
 }
 
@@ -384,6 +402,7 @@ int tosimp_set_bcs(tosimp_ctx* ctx, const int64_t* fixed, int64_t n) {
                                  ctx->stream));
   TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   ctx->has_bcs = true;
+  ctx->kappa_uniform = 0;
   return TOSIMP_OK;
 }
 
@@ -453,6 +472,12 @@ int tosimp_diag_K(tosimp_ctx* ctx, const void* x, int xdtype, void* d, int dtype
 
 // ===================================================================== solvers
 namespace {
+
+int kappa_run(tosimp_ctx* ctx, const double* x, const double* v0, int kmax, int jacobi,
+              double rtol, int window, double* lmin, double* lmax, int* steps, int* converged);
+int oc_run(tosimp_ctx* ctx, const double* x, const double* dc, const double* dv,
+           double volfrac, double move, double beta, double eta, double* x_new,
+           double* xphys_new, double* tmp, double* change, int* steps, double* volume);
 
 struct PcgResult {
   int iters = 0;
@@ -570,6 +595,39 @@ int run_pcg(tosimp_ctx* ctx, int prec, const void* x, int xdtype, const T* b, T*
   return TOSIMP_OK;
 }
 
+// The conditioning estimate of the precision rule (enforce_rule = 2): Lanczos with the
+// stopping rule (rtol 1e-3 over windows of 50 steps, at most 5,000 steps) on the
+// Jacobi-scaled operator at uniform density (kappa does not depend on the uniform
+// value or on the penalty), from a seeded normal start vector zeroed on fixed DOFs.
+// Computed once per mesh and set of boundary conditions.  Uses the last etmp slot, w.r,
+// w.p, w.q, w.w and w.dinv.
+int kappa_uniform(tosimp_ctx* ctx, double* kappa) {
+  if (ctx->kappa_uniform <= 0) {
+    Workspace& w = ctx->ws;
+    int rc = 0;
+    double* xu = w.etmp + 5 * ctx->n_elem;  // the last slot: free during any solve
+    TOSIMP_HIP(ctx, launch_fill64(ctx, xu, ctx->n_elem, 1.0));
+    std::vector<double> h((size_t)ctx->n_dof);
+    std::mt19937_64 gen(42);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (double& v : h) v = nd(gen);
+    TOSIMP_HIP(ctx, hipMemcpyAsync(w.r, h.data(), h.size() * 8, hipMemcpyHostToDevice,
+                                   ctx->stream));
+    TOSIMP_HIP(ctx, launch_mask_vec(ctx, w.r));
+    double lo = 0, hi = 0;
+    int steps = 0, conv = 0;
+    if ((rc = kappa_run(ctx, xu, w.r, 5000, 1, 1e-3, 50, &lo, &hi, &steps, &conv)))
+      return rc;
+    if (!(lo > 0) || !(hi > 0) || !std::isfinite(hi / lo))
+      return tosimp_fail(ctx, TOSIMP_EBREAKDOWN, "conditioning estimate failed");
+    ctx->kappa_uniform = hi / lo;
+    ctx->kappa_converged = conv;
+    ctx->kappa_steps = steps;
+  }
+  *kappa = ctx->kappa_uniform;
+  return TOSIMP_OK;
+}
+
 double unit_roundoff(int prec) {
   switch (prec) {
     case TOSIMP_PREC_FP64: return std::ldexp(1.0, -53);
@@ -652,23 +710,31 @@ int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
     if ((rc = true_residual(ctx, x, b, u, &rr))) return rc;
     s.true_rel_residual = pr.bb > 0 ? std::sqrt(rr / pr.bb) : 0.0;
   } else {
-    const int ip = o->inner_prec;
+    int ip = o->inner_prec;
     REQUIRE(ip == TOSIMP_PREC_FP32 || ip == TOSIMP_PREC_BF16_MFMA || ip == TOSIMP_PREC_FP16_MFMA,
             TOSIMP_EINVAL, "IR inner precision must be FP32 or an MFMA precision");
     REQUIRE(o->inner_tol > 0 && o->inner_tol < 1 && o->max_outer >= 1, TOSIMP_EINVAL,
             "bad inner_tol/max_outer");
+    REQUIRE(o->enforce_rule >= 0 && o->enforce_rule <= 2, TOSIMP_EINVAL, "bad enforce_rule");
     if (o->enforce_rule) {
-      REQUIRE(o->kappa > 0, TOSIMP_EINVAL, "enforce_rule needs kappa > 0");
-      if (unit_roundoff(ip) * o->kappa >= 1.0)
+      double kappa = o->kappa;
+      if (o->enforce_rule == 2) {
+        if ((rc = kappa_uniform(ctx, &kappa))) return rc;
+      }
+      REQUIRE(kappa > 0, TOSIMP_EINVAL, "enforce_rule 1 needs kappa > 0");
+      s.kappa = kappa;
+      if (unit_roundoff(ip) * kappa >= 1.0) {
+        if (stats) *stats = s;
         return tosimp_fail(ctx, TOSIMP_EPRECISION,
                            "inner precision refused: unit roundoff * kappa >= 1");
+      }
     }
     TOSIMP_HIP(ctx, launch_diag_inv(ctx, x, w.dinv, w.dinv32));
     TOSIMP_HIP(ctx, launch_copy_cast_x(ctx, x, w.x32));
     double bb = 0;
     if ((rc = dot_host(ctx, b, b, ctx->n_dof, &bb))) return rc;
     const double bn = std::sqrt(bb);
-    int total = 0, outer = 0, fallbacks = 0, restarts = 0, slow = 0;
+    int total = 0, outer = 0, fallbacks = 0, restarts = 0, escalations = 0, slow = 0;
     double prev = -1, rel = 0;
     int status = TOSIMP_OK;
     for (;;) {
@@ -679,7 +745,14 @@ int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
       if (rel <= o->tol || bn == 0) break;
       if (outer >= o->max_outer || total >= o->maxit) { status = TOSIMP_NOT_CONVERGED; break; }
       if (prev > 0 && rel > 0.5 * prev) {
-        if (++slow >= 2) { status = TOSIMP_NOT_CONVERGED; break; }  // stagnation
+        // two outer steps in a row that did not halve the residual: a matrix-core inner
+        // precision is raised to FP32; at FP32 the solve stops (stagnation)
+        if (++slow >= 2) {
+          if (ip == TOSIMP_PREC_FP32) { status = TOSIMP_NOT_CONVERGED; break; }
+          ip = TOSIMP_PREC_FP32;
+          ++escalations;
+          slow = 0;
+        }
       } else {
         slow = 0;
       }
@@ -728,6 +801,7 @@ int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
     s.outer_iterations = outer;
     s.fallbacks = fallbacks;
     s.restarts = restarts;
+    s.escalations = escalations;
     s.rel_residual = rel;
     s.true_rel_residual = rel;
     s.status = status;
@@ -843,6 +917,21 @@ int tosimp_oc_update(tosimp_ctx* ctx, const double* x, const double* dc, double 
   }
   REQUIRE(volfrac > 0 && volfrac <= 1 && move > 0, TOSIMP_EINVAL, "bad volfrac/move");
   if ((rc = set_device(ctx))) return rc;
+  return oc_run(ctx, x, dc, ctx->ws.dv, volfrac, move, 0.0, 0.0, x_new, xphys_new, nullptr,
+                change_host, steps_host, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+// OC bisection on the host-polled device state: the density-filter volume dv^T x_new
+// (beta <= 0) or the projected volume sum project(filter(x_new)) (beta > 0); writes
+// x_new and its physical density (filtered, then projected when beta > 0), and returns
+// the change, the step count and the volume at the final multiplier.  tmp: n_elem.
+int oc_run(tosimp_ctx* ctx, const double* x, const double* dc, const double* dv,
+           double volfrac, double move, double beta, double eta, double* x_new,
+           double* xphys_new, double* tmp, double* change, int* steps, double* volume) {
   Workspace& w = ctx->ws;
   *w.oc_host = OcState{};
   w.oc_host->l1 = 0.0;
@@ -851,23 +940,108 @@ int tosimp_oc_update(tosimp_ctx* ctx, const double* x, const double* dc, double 
   TOSIMP_HIP(ctx, hipMemcpyAsync(w.oc, w.oc_host, sizeof(OcState), hipMemcpyHostToDevice,
                                  ctx->stream));
   for (int batch = 0; batch < 16; ++batch) {
-    for (int i = 0; i < 16; ++i)
-      TOSIMP_HIP(ctx, launch_oc_step(ctx, x, dc, w.dv, move, w.oc, w.partials));
+    for (int i = 0; i < 16; ++i) {
+      if (beta > 0)
+        TOSIMP_HIP(ctx, launch_oc_step_projected(ctx, x, dc, dv, move, beta, eta, x_new, w.oc,
+                                                 w.partials));
+      else
+        TOSIMP_HIP(ctx, launch_oc_step(ctx, x, dc, dv, move, w.oc, w.partials));
+    }
     TOSIMP_HIP(ctx, hipMemcpyAsync(w.oc_host, w.oc, sizeof(OcState), hipMemcpyDeviceToHost,
                                    ctx->stream));
     TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (w.oc_host->done) break;
   }
   REQUIRE(w.oc_host->done, TOSIMP_EINVAL, "OC bisection did not terminate");
-  TOSIMP_HIP(ctx, launch_oc_final(ctx, x, dc, w.dv, move, w.oc, x_new, w.partials));
-  TOSIMP_HIP(ctx, launch_filter(ctx, x_new, xphys_new, TOSIMP_FILTER_FORWARD, w.Hs));
+  TOSIMP_HIP(ctx, launch_oc_final(ctx, x, dc, dv, move, w.oc, x_new, w.partials));
+  if (beta > 0) {
+    TOSIMP_HIP(ctx, launch_filter(ctx, x_new, tmp, TOSIMP_FILTER_FORWARD, w.Hs));
+    TOSIMP_HIP(ctx, launch_project(ctx, tmp, nullptr, xphys_new, beta, eta));
+  } else {
+    TOSIMP_HIP(ctx, launch_filter(ctx, x_new, xphys_new, TOSIMP_FILTER_FORWARD, w.Hs));
+  }
   TOSIMP_HIP(ctx, hipMemcpyAsync(w.oc_host, w.oc, sizeof(OcState), hipMemcpyDeviceToHost,
                                  ctx->stream));
   TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (change_host) *change_host = w.oc_host->change;
-  if (steps_host) *steps_host = w.oc_host->steps;
+  if (change) *change = w.oc_host->change;
+  if (steps) *steps = w.oc_host->steps;
+  if (volume) *volume = w.oc_host->vol;
   return TOSIMP_OK;
 }
+
+// After the solve of K(xphys) u = f: sensitivities chained to the design x (through the
+// projection when beta > 0, then the adjoint filter), the volume gradient, and the OC
+// update.  x_new / xphys_new receive the new design and its physical density.  Uses
+// etmp slots 0..3 (slot 0 must hold filter(x) when beta > 0).
+int design_update(tosimp_ctx* ctx, const double* x, const double* xphys, const double* u,
+                  double volfrac, double move, double beta, double eta, double* x_new,
+                  double* xphys_new, double* compliance, double* change, int* steps,
+                  double* volume) {
+  Workspace& w = ctx->ws;
+  const size_t ne = (size_t)ctx->n_elem;
+  double* xbar = w.etmp;
+  double* b1 = w.etmp + ne;
+  double* dcx = w.etmp + 2 * ne;
+  double* dvx = w.etmp + 3 * ne;
+  int rc = tosimp_sensitivity(ctx, xphys, u, b1, compliance);
+  if (rc) return rc;
+  const double* dv = w.dv;
+  if (beta > 0) {
+    TOSIMP_HIP(ctx, launch_project(ctx, xbar, b1, b1, beta, eta));  // dc / dxbar
+    TOSIMP_HIP(ctx, launch_filter(ctx, b1, dcx, TOSIMP_FILTER_ADJOINT, w.Hs));
+    TOSIMP_HIP(ctx, launch_fill64(ctx, b1, ctx->n_elem, 1.0));
+    TOSIMP_HIP(ctx, launch_project(ctx, xbar, b1, b1, beta, eta));  // dxphys / dxbar
+    TOSIMP_HIP(ctx, launch_filter(ctx, b1, dvx, TOSIMP_FILTER_ADJOINT, w.Hs));
+    dv = dvx;
+  } else {
+    TOSIMP_HIP(ctx, launch_filter(ctx, b1, dcx, TOSIMP_FILTER_ADJOINT, w.Hs));
+  }
+  return oc_run(ctx, x, dcx, dv, volfrac, move, beta, eta, x_new, xphys_new, b1, change,
+                steps, volume);
+}
+
+int check_beta_eta(tosimp_ctx* ctx, double beta, double eta) {
+  REQUIRE(std::isfinite(beta) && (beta <= 0 || (eta >= 0 && eta <= 1)), TOSIMP_EINVAL,
+          "projection needs a finite beta and 0 <= eta <= 1");
+  return TOSIMP_OK;
+}
+
+// One continuation step of the SIMP-120 protocol: (penal, beta, move, rmin) of
+// iteration `it` (1-based) from phases (5 values each: last iteration, penal, beta,
+// move, rmin at the phase end or <= 0 to keep it).  Within a phase with a radius target
+// the radius moves linearly from the previous phase's end value, reaching the target on
+// the phase's last iteration; past the last phase its values hold.
+void continuation(const double* ph, int nph, double rmin0, int it, double* penal,
+                  double* beta, double* move, double* rmin) {
+  int start = 1;
+  double r_prev = rmin0;
+  for (int k = 0; k < nph; ++k) {
+    const int last = (int)ph[5 * k];
+    const double r_end = ph[5 * k + 4] > 0 ? ph[5 * k + 4] : r_prev;
+    if (it <= last || k == nph - 1) {
+      *penal = ph[5 * k + 1];
+      *beta = ph[5 * k + 2];
+      *move = ph[5 * k + 3];
+      if (it <= last) {
+        const double frac = (double)(it - start + 1) / (double)(last - start + 1);
+        *rmin = r_prev + (r_end - r_prev) * frac;
+      } else {
+        *rmin = r_end;
+      }
+      return;
+    }
+    start = last + 1;
+    r_prev = r_end;
+  }
+}
+
+// The paper's four phases (Sec. "Experimental Setup").
+const double kPaperPhases[20] = {15, 1.5, 1.0, 0.20, 0.0,  40, 3.5, 4.0, 0.15, 1.35,
+                                 65, 4.5, 16.0, 0.08, 1.25, 120, 4.5, 32.0, 0.05, 1.20};
+
+}  // namespace
+
+extern "C" {
 
 int tosimp_simp_step(tosimp_ctx* ctx, double* x, double* xphys, double* u,
                      const tosimp_step_opts* o, tosimp_step_stats* stats) {
@@ -875,22 +1049,32 @@ int tosimp_simp_step(tosimp_ctx* ctx, double* x, double* xphys, double* u,
   if (rc) return rc;
   REQUIRE(x && xphys && u && o, TOSIMP_EINVAL, "null pointer");
   REQUIRE(ctx->has_loads, TOSIMP_ESTATE, "no loads: call tosimp_set_loads first");
+  if ((rc = check_beta_eta(ctx, o->beta, o->eta))) return rc;
+  {
+    const int64_t nb = 8 * ctx->n_elem;
+    REQUIRE(!overlaps(x, nb, xphys, nb) && !overlaps(u, 8 * ctx->n_dof, x, nb) &&
+                !overlaps(u, 8 * ctx->n_dof, xphys, nb),
+            TOSIMP_EINVAL, "x, xphys and u must not overlap");
+  }
+  if ((rc = set_device(ctx))) return rc;
   Workspace& w = ctx->ws;
   const size_t ne = (size_t)ctx->n_elem;
-  double* dc = w.etmp;
-  double* dcf = w.etmp + ne;
-  double* xn = w.etmp + 2 * ne;
-  double* xpn = w.etmp + 3 * ne;
+  double* xn = w.etmp + 4 * ne;
+  double* xpn = w.etmp + 5 * ne;
   tosimp_step_stats s{};
+  if (o->beta > 0) TOSIMP_HIP(ctx, launch_filter(ctx, x, w.etmp, TOSIMP_FILTER_FORWARD, w.Hs));
   rc = tosimp_pcg_solve(ctx, xphys, w.f, u, &o->solve, &s.solve);
   if (rc < 0) return rc;
-  int rc2 = tosimp_sensitivity(ctx, xphys, u, dc, &s.compliance);
+  TOSIMP_HIP(ctx, launch_grayness(ctx, xphys, w.partials, &w.st[2].aux));
+  TOSIMP_HIP(ctx, hipMemcpyAsync(w.st_host + 2, w.st + 2, sizeof(SolverState),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  s.grayness = w.st_host[2].aux;
+  double vol = 0;
+  int rc2 = design_update(ctx, x, xphys, u, o->volfrac, o->move, o->beta, o->eta, xn, xpn,
+                          &s.compliance, &s.change, &s.bisection_steps, &vol);
   if (rc2) return rc2;
-  if ((rc2 = tosimp_filter(ctx, dc, dcf, TOSIMP_FILTER_ADJOINT))) return rc2;
-  if ((rc2 = tosimp_oc_update(ctx, x, dcf, o->volfrac, o->move, xn, xpn, &s.change,
-                              &s.bisection_steps)))
-    return rc2;
-  s.volume = w.oc_host->vol / (double)ne;
+  s.volume = vol / (double)ne;
   TOSIMP_HIP(ctx, hipMemcpyAsync(x, xn, ne * 8, hipMemcpyDeviceToDevice, ctx->stream));
   TOSIMP_HIP(ctx, hipMemcpyAsync(xphys, xpn, ne * 8, hipMemcpyDeviceToDevice, ctx->stream));
   TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -898,65 +1082,256 @@ int tosimp_simp_step(tosimp_ctx* ctx, double* x, double* xphys, double* u,
   return rc;
 }
 
+int tosimp_grayness(tosimp_ctx* ctx, const double* rho, double* g_host) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(rho && g_host, TOSIMP_EINVAL, "null pointer");
+  if ((rc = set_device(ctx))) return rc;
+  Workspace& w = ctx->ws;
+  TOSIMP_HIP(ctx, launch_grayness(ctx, rho, w.partials, &w.st[2].aux));
+  TOSIMP_HIP(ctx, hipMemcpyAsync(w.st_host + 2, w.st + 2, sizeof(SolverState),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *g_host = w.st_host[2].aux;
+  return TOSIMP_OK;
+}
+
+int tosimp_simp_protocol(tosimp_ctx* ctx, double* x, double* x_sel, double* xphys, double* u,
+                         const tosimp_protocol_opts* o, tosimp_protocol_record* rec,
+                         int* it_selected, double* c_selected) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(x && x_sel && xphys && u && o && rec, TOSIMP_EINVAL, "null pointer");
+  REQUIRE(ctx->has_loads, TOSIMP_ESTATE, "no loads: call tosimp_set_loads first");
+  REQUIRE(o->iters >= 1 && o->volfrac > 0 && o->volfrac <= 1 && o->restart_factor > 0,
+          TOSIMP_EINVAL, "bad iters, volfrac or restart_factor");
+  REQUIRE(o->nphases >= 0 && (o->nphases == 0 || o->phases), TOSIMP_EINVAL, "bad phases");
+  if ((rc = check_beta_eta(ctx, 1.0, o->eta))) return rc;
+  {
+    const int64_t nb = 8 * ctx->n_elem, nu = 8 * ctx->n_dof;
+    REQUIRE(!overlaps(x, nb, x_sel, nb) && !overlaps(x, nb, xphys, nb) &&
+                !overlaps(x_sel, nb, xphys, nb) && !overlaps(u, nu, x, nb) &&
+                !overlaps(u, nu, x_sel, nb) && !overlaps(u, nu, xphys, nb),
+            TOSIMP_EINVAL, "x, x_sel, xphys and u must not overlap");
+  }
+  const double* ph = o->nphases ? o->phases : kPaperPhases;
+  const int nph = o->nphases ? o->nphases : 4;
+  for (int k = 0; k < nph; ++k)
+    REQUIRE(ph[5 * k] >= 1 && (k == 0 || ph[5 * k] > ph[5 * (k - 1)]) && ph[5 * k + 1] >= 1 &&
+                ph[5 * k + 2] > 0 && ph[5 * k + 3] > 0 && ph[5 * k + 4] <= kMaxFilterR + 1,
+            TOSIMP_EINVAL, "bad continuation phase");
+  if ((rc = set_device(ctx))) return rc;
+  Workspace& w = ctx->ws;
+  const size_t ne = (size_t)ctx->n_elem;
+  double* xn = w.etmp + 4 * ne;
+  double* xpn = w.etmp + 5 * ne;
+  const double rmin0 = ctx->rmin, penal0 = ctx->penal;
+  bool have_sel = false;
+  double csel = 0;
+  int itsel = 0;
+  for (int it = 1; it <= o->iters; ++it) {
+    tosimp_protocol_record r{};
+    r.it = it;
+    continuation(ph, nph, rmin0, it, &r.penal, &r.beta, &r.move, &r.rmin);
+    if ((rc = tosimp_set_params(ctx, r.penal, r.rmin))) return rc;
+    TOSIMP_HIP(ctx, launch_filter(ctx, x, w.etmp, TOSIMP_FILTER_FORWARD, w.Hs));
+    TOSIMP_HIP(ctx, launch_project(ctx, w.etmp, nullptr, xphys, r.beta, o->eta));
+    tosimp_solve_stats ss{};
+    rc = tosimp_pcg_solve(ctx, xphys, w.f, u, &o->solve, &ss);
+    if (rc < 0) return rc;
+    r.cg_iterations = ss.iterations;
+    r.compliance = ss.b_dot_u;
+    if ((rc = tosimp_grayness(ctx, xphys, &r.grayness))) return rc;
+    if (have_sel && r.compliance > o->restart_factor * csel) {
+      // restart from the selected design field
+      r.restart = 1;
+      TOSIMP_HIP(ctx, hipMemcpyAsync(x, x_sel, ne * 8, hipMemcpyDeviceToDevice, ctx->stream));
+      rec[it - 1] = r;
+      continue;
+    }
+    if (r.penal >= o->eligible_penal && r.grayness < o->eligible_gray) {
+      r.eligible = 1;
+      if (!have_sel || r.compliance < csel) {
+        have_sel = true;
+        csel = r.compliance;
+        itsel = it;
+        r.selected = 1;
+        TOSIMP_HIP(ctx, hipMemcpyAsync(x_sel, x, ne * 8, hipMemcpyDeviceToDevice, ctx->stream));
+      }
+    }
+    double c = 0, vol = 0;
+    if ((rc = design_update(ctx, x, xphys, u, o->volfrac, r.move, r.beta, o->eta, xn, xpn, &c,
+                            &r.change, &r.bisection_steps, &vol)))
+      return rc;
+    TOSIMP_HIP(ctx, hipMemcpyAsync(x, xn, ne * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    rec[it - 1] = r;
+  }
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if ((rc = tosimp_set_params(ctx, penal0, rmin0))) return rc;
+  if (it_selected) *it_selected = have_sel ? itsel : 0;
+  if (c_selected) *c_selected = have_sel ? csel : 0.0;
+  return TOSIMP_OK;
+}
+
 // ===================================================================== Lanczos
+}  // extern "C"
+
+namespace {
+
+// Device state of a Lanczos run: the current and previous basis vectors (swapped every
+// step), the optional Jacobi scaling, and the device arrays of alpha and beta.
+struct LanczosRun {
+  const double* x = nullptr;
+  double* q = nullptr;
+  double* qprev = nullptr;
+  double* s_node = nullptr;
+  double* dal = nullptr;  // alpha[0..k)
+  double* dbe = nullptr;  // beta[-1..k): dbe[0] = ||v0||, dbe[j + 1] = beta_j
+};
+
+// Sets up a run of at most k steps from v0 (workspace vectors w.p, w.q as the basis,
+// w.w for K q, w.r for the scaled input; v0 is read before the first step).
+int lanczos_begin(tosimp_ctx* ctx, const double* x, const double* v0, int k, int jacobi,
+                  LanczosRun* L) {
+  Workspace& w = ctx->ws;
+  if (w.lanczos_cap < k + 1) {
+    if (w.lanczos) TOSIMP_HIP(ctx, hipFree(w.lanczos));
+    w.lanczos = nullptr;
+    w.lanczos_cap = 0;
+    TOSIMP_HIP(ctx, hipMalloc((void**)&w.lanczos, sizeof(double) * 2 * (size_t)(k + 1)));
+    w.lanczos_cap = k + 1;
+  }
+  L->x = x;
+  L->dal = w.lanczos;
+  L->dbe = w.lanczos + w.lanczos_cap;
+  L->s_node = nullptr;
+  SolverState* st = w.st + 2;
+  if (jacobi) {
+    // sqrt(dinv) per node, in place (every solve recomputes w.dinv at its start)
+    TOSIMP_HIP(ctx, launch_diag_inv(ctx, x, w.dinv, nullptr));
+    L->s_node = w.dinv;
+    TOSIMP_HIP(ctx, launch_sqrt_node(ctx, w.dinv, L->s_node));
+  }
+  L->q = w.p;
+  L->qprev = w.q;
+  // q0 = v0 / ||v0||
+  TOSIMP_HIP(ctx, launch_dot64(ctx, v0, v0, ctx->n_dof, w.partials, st, 1));
+  TOSIMP_HIP(ctx, launch_sqrt_scalar(ctx, st, L->dbe));
+  TOSIMP_HIP(ctx, launch_lanczos_normalize(ctx, v0, L->dbe, L->q));
+  return TOSIMP_OK;
+}
+
+// Steps j0 .. j1-1 (asynchronous).
+int lanczos_steps(tosimp_ctx* ctx, LanczosRun* L, int j0, int j1) {
+  Workspace& w = ctx->ws;
+  SolverState* st = w.st + 2;
+  double *wv = w.w, *tmp = w.r;
+  for (int j = j0; j < j1; ++j) {
+    const double* in = L->q;
+    if (L->s_node) {
+      TOSIMP_HIP(ctx, launch_node_scale(ctx, L->s_node, L->q, tmp));
+      in = tmp;
+    }
+    TOSIMP_HIP(ctx, kv_launch(ctx, TOSIMP_PREC_FP64, TOSIMP_F64, L->x, in, wv, w.partials, st,
+                              L->dal + j, 2, false));
+    TOSIMP_HIP(ctx, launch_lanczos_update(ctx, wv, L->q, j > 0 ? L->qprev : nullptr,
+                                          L->dal + j, j > 0 ? L->dbe + j : nullptr, L->s_node,
+                                          w.partials + kMaxPartials, L->dbe + j + 1));
+    TOSIMP_HIP(ctx, launch_lanczos_normalize(ctx, wv, L->dbe + j + 1, L->qprev));
+    std::swap(L->q, L->qprev);
+  }
+  return TOSIMP_OK;
+}
+
+// Copies the coefficients of the first k steps to the host and returns in *m the order
+// of the tridiagonal (m < k only on an invariant subspace: the first beta <= 0).
+int lanczos_fetch(tosimp_ctx* ctx, const LanczosRun& L, int k, std::vector<double>& a,
+                  std::vector<double>& b, int* m) {
+  std::vector<double> hb(k + 1);
+  a.resize(k);
+  TOSIMP_HIP(ctx, hipMemcpyAsync(a.data(), L.dal, sizeof(double) * k, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+  TOSIMP_HIP(ctx, hipMemcpyAsync(hb.data(), L.dbe, sizeof(double) * (k + 1),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  int mm = k;
+  for (int j = 0; j < k - 1; ++j)
+    if (!(hb[j + 1] > 0.0)) {
+      mm = j + 1;
+      break;
+    }
+  b.assign(hb.begin() + 1, hb.begin() + 1 + std::max(mm - 1, 0));
+  a.resize(mm);
+  *m = mm;
+  return TOSIMP_OK;
+}
+
+// Lanczos with the stopping rule (see tosimp_kappa).
+int kappa_run(tosimp_ctx* ctx, const double* x, const double* v0, int kmax, int jacobi,
+              double rtol, int window, double* lmin, double* lmax, int* steps, int* converged) {
+  LanczosRun L;
+  int rc = lanczos_begin(ctx, x, v0, kmax, jacobi, &L);
+  if (rc) return rc;
+  std::vector<double> a, b;
+  double prev = 0.0;
+  bool have_prev = false;
+  int j = 0;
+  for (;;) {
+    const int j1 = std::min(kmax, j + window);
+    if ((rc = lanczos_steps(ctx, &L, j, j1))) return rc;
+    j = j1;
+    int m = 0;
+    if ((rc = lanczos_fetch(ctx, L, j, a, b, &m))) return rc;
+    double lo = 0, hi = 0;
+    tosimp_tridiag_extremes(a.data(), b.empty() ? nullptr : b.data(), m, &lo, &hi);
+    if (m < j) {  // invariant subspace: the extremes of T_m are exact
+      *lmin = lo; *lmax = hi; *steps = m; *converged = 1;
+      return TOSIMP_OK;
+    }
+    if (j % window == 0 && have_prev && std::fabs(lo - prev) <= rtol * std::fabs(lo)) {
+      *lmin = lo; *lmax = hi; *steps = j; *converged = 1;
+      return TOSIMP_OK;
+    }
+    if (j >= kmax) {
+      *lmin = lo; *lmax = hi; *steps = j; *converged = 0;
+      return TOSIMP_OK;
+    }
+    prev = lo;
+    have_prev = true;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
 int tosimp_lanczos(tosimp_ctx* ctx, const double* x, const double* v0, int k, int jacobi,
                    double* alpha_host, double* beta_host, int* steps_host) {
   int rc = check_ready(ctx);
   if (rc) return rc;
   REQUIRE(x && v0 && alpha_host && beta_host && k >= 1, TOSIMP_EINVAL, "bad arguments");
   if ((rc = set_device(ctx))) return rc;
-  Workspace& w = ctx->ws;
-  if (w.lanczos_cap < k + 1) {
-    if (w.lanczos) TOSIMP_HIP(ctx, hipFree(w.lanczos));
-    w.lanczos = nullptr;
-    TOSIMP_HIP(ctx, hipMalloc((void**)&w.lanczos, sizeof(double) * 2 * (size_t)(k + 1)));
-    w.lanczos_cap = k + 1;
-  }
-  double* dal = w.lanczos;               // alpha[0..k)
-  double* dbe = w.lanczos + w.lanczos_cap;  // beta[-1..k): dbe[0] = ||v0||
-  SolverState* st = w.st + 2;
-  double* s_node = nullptr;
-  if (jacobi) {
-    // sqrt(dinv) per node, in place (every solve recomputes w.dinv at its start)
-    TOSIMP_HIP(ctx, launch_diag_inv(ctx, x, w.dinv, nullptr));
-    s_node = w.dinv;
-    TOSIMP_HIP(ctx, launch_sqrt_node(ctx, w.dinv, s_node));
-  }
-  double *q = w.p, *qprev = w.q, *wv = w.w, *tmp = w.r;
-  // q0 = v0 / ||v0||
-  TOSIMP_HIP(ctx, launch_dot64(ctx, v0, v0, ctx->n_dof, w.partials, st, 1));
-  TOSIMP_HIP(ctx, launch_sqrt_scalar(ctx, st, dbe));
-  TOSIMP_HIP(ctx, launch_lanczos_normalize(ctx, v0, dbe, q));
-  for (int j = 0; j < k; ++j) {
-    const double* in = q;
-    if (jacobi) {
-      TOSIMP_HIP(ctx, launch_node_scale(ctx, s_node, q, tmp));
-      in = tmp;
-    }
-    TOSIMP_HIP(ctx, kv_launch(ctx, TOSIMP_PREC_FP64, TOSIMP_F64, x, in, wv, w.partials, st,
-                              dal + j, 2, false));
-    TOSIMP_HIP(ctx, launch_lanczos_update(ctx, wv, q, j > 0 ? qprev : nullptr, dal + j,
-                                          j > 0 ? dbe + j : nullptr, s_node,
-                                          w.partials + kMaxPartials, dbe + j + 1));
-    TOSIMP_HIP(ctx, launch_lanczos_normalize(ctx, wv, dbe + j + 1, qprev));
-    std::swap(q, qprev);
-  }
-  std::vector<double> ha(k), hb(k + 1);
-  TOSIMP_HIP(ctx, hipMemcpyAsync(ha.data(), dal, sizeof(double) * k, hipMemcpyDeviceToHost,
-                                 ctx->stream));
-  TOSIMP_HIP(ctx, hipMemcpyAsync(hb.data(), dbe, sizeof(double) * (k + 1),
-                                 hipMemcpyDeviceToHost, ctx->stream));
-  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  int m = k;
-  for (int j = 0; j < k - 1; ++j)
-    if (!(hb[j + 1] > 0.0)) {
-      m = j + 1;
-      break;
-    }
-  for (int j = 0; j < m; ++j) alpha_host[j] = ha[j];
-  for (int j = 0; j + 1 < m; ++j) beta_host[j] = hb[j + 1];
+  LanczosRun L;
+  if ((rc = lanczos_begin(ctx, x, v0, k, jacobi, &L))) return rc;
+  if ((rc = lanczos_steps(ctx, &L, 0, k))) return rc;
+  std::vector<double> a, b;
+  int m = 0;
+  if ((rc = lanczos_fetch(ctx, L, k, a, b, &m))) return rc;
+  for (int j = 0; j < m; ++j) alpha_host[j] = a[j];
+  for (int j = 0; j + 1 < m; ++j) beta_host[j] = b[j];
   if (steps_host) *steps_host = m;
   return TOSIMP_OK;
+}
+
+int tosimp_kappa(tosimp_ctx* ctx, const double* x, const double* v0, int kmax, int jacobi,
+                 double rtol, int window, double* lmin, double* lmax, int* steps,
+                 int* converged) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(x && v0 && lmin && lmax && steps && converged, TOSIMP_EINVAL, "null pointer");
+  REQUIRE(kmax >= 1 && window >= 1 && rtol > 0, TOSIMP_EINVAL, "need kmax, window >= 1, rtol > 0");
+  if ((rc = set_device(ctx))) return rc;
+  return kappa_run(ctx, x, v0, kmax, jacobi, rtol, window, lmin, lmax, steps, converged);
 }
 
 // Number of eigenvalues of the tridiagonal (a, b) smaller than s (Sturm count).

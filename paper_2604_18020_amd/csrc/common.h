@@ -84,7 +84,7 @@ struct Workspace {
   float* e32 = nullptr;
   float* z32 = nullptr;
   float* x32 = nullptr;        // n_elem FP32 density copy
-  double* etmp = nullptr;      // n_elem scratch (x 4)
+  double* etmp = nullptr;      // n_elem scratch (x 6)
   double* partials = nullptr;  // 2 kMaxPartials + kv_part_cap
   int64_t kv_part_cap = 0;     // operator tiles a fused dot may use
   uint16_t* ke_mfma = nullptr; // K_E in the MFMA A-operand layout: [bf16|f16][2][64][8]
@@ -115,6 +115,10 @@ struct tosimp_ctx {
   double fw_host[tosimp::kMaxFilterTaps];
   tosimp::Workspace ws;
   void* nn = nullptr;          // learned preconditioner state (nn.hip)
+  // conditioning estimate of the Jacobi-scaled operator at uniform density (0: not yet
+  // computed for the current mesh and boundary conditions)
+  double kappa_uniform = 0;
+  int kappa_converged = 0, kappa_steps = 0;
 };
 
 // ------------------------------------------------------------------ error plumbing
@@ -171,6 +175,7 @@ hipError_t launch_axpy_from32(const tosimp_ctx* c, double* u, double s, const fl
 hipError_t launch_copy_cast_x(const tosimp_ctx* c, const double* x, float* x32);
 hipError_t launch_cast32(const tosimp_ctx* c, const double* x, float* y, int64_t n);
 hipError_t launch_fill_zero(const tosimp_ctx* c, void* p, int64_t bytes);
+hipError_t launch_fill64(const tosimp_ctx* c, double* p, int64_t n, double v);
 hipError_t launch_dot64(const tosimp_ctx* c, const double* a, const double* b, int64_t n,
                         double* partials, SolverState* st, int what);
 hipError_t launch_lanczos_update(const tosimp_ctx* c, double* w, const double* q,
@@ -208,5 +213,10 @@ hipError_t launch_oc_step(const tosimp_ctx* c, const double* x, const double* dc
 hipError_t launch_oc_final(const tosimp_ctx* c, const double* x, const double* dc,
                            const double* dv, double move, OcState* oc, double* xnew,
                            double* partials);
+hipError_t launch_oc_step_projected(const tosimp_ctx* c, const double* x, const double* dc,
+                                    const double* dv, double move, double beta, double eta,
+                                    double* xn, OcState* oc, double* partials);
+hipError_t launch_grayness(const tosimp_ctx* c, const double* rho, double* partials,
+                           double* out);
 
 }  // namespace tosimp

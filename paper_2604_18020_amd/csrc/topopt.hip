@@ -243,4 +243,107 @@ hipError_t launch_oc_final(const tosimp_ctx* c, const double* x, const double* d
 
 hipError_t launch_oc_init(const tosimp_ctx*, OcState*, double) { return hipSuccess; }
 
+// ------------------------------------------------- OC with the projected volume
+// Three-field scheme: the bisection's volume is that of the projected density,
+// sum_e project(filter(x_new))_e, which is not linear in x_new: each step writes x_new at
+// the midpoint multiplier, then filters, projects and sums it (same block order every
+// step).  The projection is evaluated as in project_kernel.
+__device__ __forceinline__ double project_value(double xbar, double beta, double eta,
+                                                double tbe_den, double inv_den) {
+  const double y = beta * (xbar - eta);
+  const double m = expm1(-2.0 * fabs(y));
+  return tbe_den + copysign(-m / (2.0 + m), y) * inv_den;
+}
+
+__global__ __launch_bounds__(kRedThreads) void oc_xnew_kernel(
+    const double* __restrict__ x, const double* __restrict__ dc, const double* __restrict__ dv,
+    double move, int64_t n, const OcState* oc, double* __restrict__ xn) {
+  if (oc->done) return;
+  const double lmid = 0.5 * (oc->l2 + oc->l1);
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads)
+    xn[i] = oc_x(x[i], dc[i], dv[i], lmid, move);
+}
+
+__global__ __launch_bounds__(kRedThreads) void filter_project_sum_kernel(
+    const double* __restrict__ in, const double* __restrict__ Hs, const double* __restrict__ w,
+    int R, int nx, int ny, int nz, double beta, double eta, double tbe_den, double inv_den,
+    const OcState* oc, double* partials) {
+  __shared__ double sred[kRedThreads / 64];
+  if (oc && oc->done) return;
+  const int64_t n_elem = (int64_t)nx * ny * nz;
+  const int W = 2 * R + 1;
+  double acc = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; e < n_elem;
+       e += (int64_t)gridDim.x * kRedThreads) {
+    const int ex = (int)(e % nx);
+    const int64_t r = e / nx;
+    const int ey = (int)(r % ny);
+    const int ez = (int)(r / ny);
+    double s = 0.0;
+    for (int dk = -R; dk <= R; ++dk) {
+      const int jz = ez + dk;
+      if (jz < 0 || jz >= nz) continue;
+      for (int dj = -R; dj <= R; ++dj) {
+        const int jy = ey + dj;
+        if (jy < 0 || jy >= ny) continue;
+        for (int di = -R; di <= R; ++di) {
+          const int jx = ex + di;
+          if (jx < 0 || jx >= nx) continue;
+          const double wt = w[(di + R) + W * ((dj + R) + W * (dk + R))];
+          if (wt <= 0.0) continue;
+          s += wt * in[jx + (int64_t)nx * (jy + (int64_t)ny * jz)];
+        }
+      }
+    }
+    acc += project_value(s / Hs[e], beta, eta, tbe_den, inv_den);
+  }
+  const double v[1] = {acc};
+  store_block_sums<1>(v, partials, sred);
+}
+
+static void projection_factors(double beta, double eta, double* tbe_den, double* inv_den) {
+  const double tbe = tanh(beta * eta), den = tbe + tanh(beta * (1.0 - eta));
+  *tbe_den = tbe / den;
+  *inv_den = 1.0 / den;
+}
+
+hipError_t launch_oc_step_projected(const tosimp_ctx* c, const double* x, const double* dc,
+                                    const double* dv, double move, double beta, double eta,
+                                    double* xn, OcState* oc, double* partials) {
+  double tbe_den, inv_den;
+  projection_factors(beta, eta, &tbe_den, &inv_den);
+  oc_xnew_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(x, dc, dv, move, c->n_elem, oc, xn);
+  filter_project_sum_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(
+      xn, c->ws.Hs, c->ws.fw, c->fR, c->nx, c->ny, c->nz, beta, eta, tbe_den, inv_den, oc,
+      partials);
+  return launch_finalize_sum<1>(c->stream, partials, kRedBlocks, OcStepFin{oc});
+}
+
+// ------------------------------------------------------------------ grayness
+// g = 4/n sum_e rho_e (1 - rho_e): block sums of rho (1 - rho), finished into *out.
+__global__ __launch_bounds__(kRedThreads) void gray_kernel(const double* __restrict__ rho,
+                                                           int64_t n, double* partials) {
+  __shared__ double sred[kRedThreads / 64];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads)
+    s += rho[i] * (1.0 - rho[i]);
+  const double v[1] = {s};
+  store_block_sums<1>(v, partials, sred);
+}
+
+struct GrayFin {
+  double* out;
+  double scale;
+  __device__ void operator()(const double* t) const { *out = scale * t[0]; }
+};
+
+hipError_t launch_grayness(const tosimp_ctx* c, const double* rho, double* partials,
+                           double* out) {
+  gray_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(rho, c->n_elem, partials);
+  return launch_finalize_sum<1>(c->stream, partials, kRedBlocks,
+                                GrayFin{out, 4.0 / (double)c->n_elem});
+}
+
 }  // namespace tosimp

@@ -363,6 +363,18 @@ hipError_t launch_fill_zero(const tosimp_ctx* c, void* p, int64_t bytes) {
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kRedThreads) void fill64_kernel(double* __restrict__ p, int64_t n,
+                                                             double v) {
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads)
+    p[i] = v;
+}
+
+hipError_t launch_fill64(const tosimp_ctx* c, double* p, int64_t n, double v) {
+  fill64_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(p, n, v);
+  return hipGetLastError();
+}
+
 // <a, b> over n values into st->aux (what = 0) or st->rr (what = 1).
 __global__ __launch_bounds__(kRedThreads) void dot64_kernel(const double* __restrict__ a,
                                                             const double* __restrict__ b,

@@ -24,7 +24,9 @@ def test_header_declares_entry_points():
     names = _declared()
     for must in ["tosimp_create", "tosimp_set_mesh", "tosimp_set_bcs", "tosimp_set_loads",
                  "tosimp_apply_K", "tosimp_pcg_solve", "tosimp_sensitivity", "tosimp_filter",
-                 "tosimp_oc_update", "tosimp_simp_step", "tosimp_lanczos"]:
+                 "tosimp_oc_update", "tosimp_simp_step", "tosimp_lanczos", "tosimp_kappa",
+                 "tosimp_set_params", "tosimp_grayness", "tosimp_simp_protocol",
+                 "tosimp_project"]:
         assert must in names
 
 
@@ -52,3 +54,34 @@ def test_null_context_is_rejected():
     assert LIB.tosimp_set_mesh(None, 1, 1, 1, 1.0, 1.0, 1e-9, 0.3, 3.0, 1.5) < 0
     assert LIB.tosimp_apply_K(None, None, 0, None, None, 0) < 0
     assert LIB.tosimp_destroy(None) == 0
+
+
+def test_binding_structures_match_the_header(tmp_path):
+    """The ctypes mirrors of the option and statistics structures have the C layout:
+    sizes and field offsets from a C program compiled against include/tosimp.h."""
+    import shutil
+    import subprocess
+    from paper_2604_18020_amd import binding as b
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"tosimp_solve_opts": b.SolveOpts, "tosimp_solve_stats": b.SolveStats,
+               "tosimp_step_opts": b.StepOpts, "tosimp_step_stats": b.StepStats,
+               "tosimp_protocol_opts": b.ProtocolOpts,
+               "tosimp_protocol_record": b.ProtocolRecord}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tosimp.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -238,3 +238,92 @@ def test_second_order_compliance_estimate(mode):
     assert abs(st["b_dot_u"] - f @ uu) <= 1e-12 * abs(c_star)
     assert abs((st["b_dot_u_corrected"] - c_star) + e2) <= 1e-9 * abs(c_star)
     assert abs(st["b_dot_u_corrected"] - c_star) <= abs(st["b_dot_u"] - c_star) + 1e-12 * abs(c_star)
+
+
+def test_kappa_stopping_rule_matches_oracle():
+    """tosimp_kappa against the oracle's Lanczos with the same stopping rule, from the
+    same start vector: same stopping step (the decisions have clear margins here) and the
+    same extremes; both lie inside the dense spectrum."""
+    nx, ny, nz = 8, 4, 4
+    rho = np.full(nx * ny * nz, 0.5)
+    Kc, f = _oracle_system(nx, ny, nz, rho)
+    fixed = fem.fixed_mask(f.size, si.cantilever_fixed_dofs(nx, ny, nz))
+    Kff = solvers.free_block(Kc, fixed)
+    lo, hi = solvers.kappa_dense(Kff, jacobi_scaled=True)
+    s = 1.0 / np.sqrt(Kff.diagonal())
+    v0 = np.random.default_rng(42).standard_normal(f.size)
+    v0[fixed] = 0.0
+    lo_o, hi_o, st_o, cv_o = solvers.lanczos_extremes(lambda v: s * (Kff @ (s * v)), v0[~fixed],
+                                                      3000, rtol=1e-3, window=50)
+    a, b = solvers.lanczos_tridiagonal(lambda v: s * (Kff @ (s * v)), v0[~fixed], st_o)
+    th = [solvers.tridiagonal_extremes(a[:j], b[:j - 1])[0] for j in range(50, st_o + 1, 50)]
+    margins = [abs(abs(th[i] - th[i - 1]) / th[i] - 1e-3) for i in range(1, len(th))]
+    assert min(margins) > 1e-5  # no decision sits at the threshold
+    t, _, _ = gpu_problem(nx, ny, nz)
+    lmin, lmax, steps, conv = t.kappa(dev(rho), dev(v0), 3000, True, 1e-3, 50)
+    t.close()
+    assert cv_o and conv and steps == st_o
+    assert abs(lmax - hi_o) <= 1e-10 * hi and abs(lmin - lo_o) <= 1e-8 * lo
+    assert lo * (1 - 1e-10) <= lmin <= lo * (1 + 2e-3) and hi * (1 - 1e-6) <= lmax <= hi * (1 + 1e-10)
+    # a cap below the stopping point: not converged, extremes still inside the spectrum
+    t, _, _ = gpu_problem(nx, ny, nz)
+    lmin2, lmax2, steps2, conv2 = t.kappa(dev(rho), dev(v0), 60, True, 1e-3, 50)
+    t.close()
+    assert not conv2 and steps2 == 60 and lmin2 >= lo * (1 - 1e-10) and lmax2 <= hi * (1 + 1e-10)
+
+
+def test_precision_rule_with_the_library_kappa():
+    """enforce_rule = 2: the library estimates kappa of the Jacobi-scaled operator at
+    uniform density itself (a lower bound within the stopping rule's tolerance of the
+    dense value) and refuses exactly the precisions the rule u * kappa < 1 refuses."""
+    from paper_2604_18020_amd import TosimpError
+    nx, ny, nz = 16, 8, 8
+    rho = np.random.default_rng(3).uniform(0.2, 1.0, nx * ny * nz)
+    Kc_u, _ = _oracle_system(nx, ny, nz, np.full(nx * ny * nz, 1.0))
+    fixed = fem.fixed_mask(Kc_u.shape[0], si.cantilever_fixed_dofs(nx, ny, nz))
+    lo, hi = solvers.kappa_dense(solvers.free_block(Kc_u, fixed), jacobi_scaled=True)
+    kd = hi / lo
+    t, _, f = gpu_problem(nx, ny, nz)
+    u = torch.zeros(f.size, dtype=torch.float64, device="cuda:0")
+    st = t.pcg_solve(dev(rho), dev(f), u, tol=1e-8, mode="ir", inner_prec="fp32",
+                     enforce_rule=2)
+    assert st["rc"] == 0
+    assert kd / (1 + 5e-3) <= st["kappa"] <= kd * (1 + 1e-9)
+    for prec, u_l in [("bf16_mfma", 2.0 ** -8), ("fp16_mfma", 2.0 ** -11)]:
+        assert abs(u_l * kd - 1.0) > 0.1  # the decision is not at the threshold
+        u2 = torch.zeros(f.size, dtype=torch.float64, device="cuda:0")
+        if u_l * kd >= 1.0:
+            with pytest.raises(TosimpError) as e:
+                t.pcg_solve(dev(rho), dev(f), u2, tol=1e-8, mode="ir", inner_prec=prec,
+                            enforce_rule=2)
+            assert e.value.code == -5
+        else:
+            assert t.pcg_solve(dev(rho), dev(f), u2, tol=1e-8, mode="ir", inner_prec=prec,
+                               enforce_rule=2)["rc"] in (0, 1)
+    t.close()
+
+
+def test_stagnating_bf16_refinement_escalates_to_fp32():
+    """A matrix-core inner precision the rule refuses by a wide margin (u_bf16 * kappa
+    >= 10 even for the Lanczos lower bound of kappa): the BF16 inner solves stop halving
+    the true residual, the library raises the inner precision to FP32 and the refinement
+    then reaches the FP64 tolerance and the direct solution."""
+    nx, ny, nz = 24, 12, 12
+    rho = np.random.default_rng(17).uniform(0.05, 1.0, nx * ny * nz)
+    Kc, f = _oracle_system(nx, ny, nz, rho)
+    fixed = fem.fixed_mask(f.size, si.cantilever_fixed_dofs(nx, ny, nz))
+    Kff = solvers.free_block(Kc, fixed)
+    s = 1.0 / np.sqrt(Kff.diagonal())
+    v0 = np.random.default_rng(42).standard_normal(Kff.shape[0])
+    lo, hi, _, _ = solvers.lanczos_extremes(lambda v: s * (Kff @ (s * v)), v0, 400)
+    assert 2.0 ** -8 * hi / lo >= 10.0
+    t, _, _ = gpu_problem(nx, ny, nz)
+    u = torch.zeros(f.size, dtype=torch.float64, device="cuda:0")
+    st = t.pcg_solve(dev(rho), dev(f), u, tol=1e-10, mode="ir", inner_prec="bf16_mfma",
+                     inner_tol=1e-3, max_outer=80, maxit=200000)
+    t.close()
+    print(f"[escalation] outer {st['outer_iterations']} inner {st['iterations']} "
+          f"escalations {st['escalations']}", flush=True)
+    assert st["escalations"] == 1 and st["rc"] == 0
+    assert st["true_rel_residual"] <= 1e-10
+    assert rel(u.cpu().numpy(), solvers.solve_direct(Kc, f)) <= 1e-8

@@ -124,3 +124,28 @@ def test_precision_rule():
     assert not solvers.precision_allowed(256.0, "bf16")
     assert solvers.precision_allowed(1e7, "fp32")
     assert not solvers.precision_allowed(1e4, "fp16")
+
+
+def test_lanczos_stopping_rule():
+    """The stopping rule ends the run at the first multiple of the window where the
+    smallest Ritz value moved by less than rtol over the last window; the extremes then
+    bound the dense spectrum from inside and are close to it."""
+    Kc, fixed, _ = _system(8, 4, 4, uniform=0.5)
+    Kff = solvers.free_block(Kc, fixed)
+    lo, hi = solvers.kappa_dense(Kff, jacobi_scaled=True)
+    d = Kff.diagonal()
+    s = 1.0 / np.sqrt(d)
+    A = lambda v: s * (Kff @ (s * v))
+    v0 = np.random.default_rng(42).standard_normal(Kff.shape[0])
+    lmin, lmax, steps, conv = solvers.lanczos_extremes(A, v0, 2000, rtol=1e-3, window=50)
+    assert conv and steps % 50 == 0 and steps < 2000
+    assert lmin >= lo * (1 - 1e-10) and lmax <= hi * (1 + 1e-10)
+    assert lmax >= hi * (1 - 1e-6) and lmin <= lo * (1 + 2e-3)
+    # the rule, restated on the same coefficients: it did not fire one window earlier
+    a, b = solvers.lanczos_tridiagonal(A, v0, steps)
+    th = [solvers.tridiagonal_extremes(a[:j], b[:j - 1])[0] for j in range(50, steps + 1, 50)]
+    assert abs(th[-1] - th[-2]) <= 1e-3 * th[-1]
+    assert all(abs(th[i] - th[i - 1]) > 1e-3 * th[i] for i in range(1, len(th) - 1))
+    # a cap below the convergence point reports "not converged"
+    lmin2, _, steps2, conv2 = solvers.lanczos_extremes(A, v0, 60, rtol=1e-3, window=50)
+    assert not conv2 and steps2 == 60 and lmin2 >= lmin * (1 - 1e-12)
