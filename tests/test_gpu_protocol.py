@@ -34,13 +34,17 @@ def test_three_field_steps_match_oracle(beta):
     xp = t.project(t.filter(xd), beta, eta)
     u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
     for k in range(3):
+        xp_in = xp.cpu().numpy()
         st = t.simp_step(xd, xp, u, volfrac=0.3, move=0.2, beta=beta, eta=eta, tol=1e-11)
         xbar = topopt.filter_forward(prob.H, prob.Hs, xo)
         xpo = topopt.heaviside_project(xbar, beta, eta)
         uo = solvers.solve_direct(prob.stiffness(xpo), prob.f)
         co = float(prob.f @ uo)
         assert abs(st["compliance"] - co) <= 1e-8 * co, k
-        assert abs(st["grayness"] - topopt.grayness(xpo)) <= 1e-12
+        # grayness 4/n sum rho(1 - rho) has |d/drho| <= 4: after the first step the two
+        # designs differ by the bisection's rounding, which bounds the grayness gap.
+        gbound = 4.0 * np.max(np.abs(xp_in - xpo)) + 1e-13
+        assert abs(st["grayness"] - topopt.grayness(xpo)) <= gbound, k
         dc_phys = prob.sensitivity(xpo, uo)
         dc = topopt.filter_adjoint(prob.H, prob.Hs, dc_phys * topopt.heaviside_derivative(xbar, beta, eta))
         dv = topopt.projected_volume_gradient(prob.H, prob.Hs, xbar, beta, eta)
@@ -54,13 +58,17 @@ def test_three_field_steps_match_oracle(beta):
 
 
 def test_protocol_twenty_iterations_match_oracle():
-    """A 20-iteration continuation (penalty 1.5 -> 3 -> 3.5, beta 1 -> 2 -> 4, radius
-    1.5 -> 1.45 -> 1.4) with the restart and selection rules active (restart factor
-    1.001 so that the rule fires): iteration by iteration the compliance, grayness and
-    the eligible / restart / selected decisions of the GPU run equal the oracle's."""
+    """A 20-iteration continuation (penalty 1.5 -> 3 -> 3.5 -> 4, beta 1 -> 1 -> 4 -> 8,
+    radius 1.5 -> 1.45 -> 1.4) with the restart and selection rules active: the jump of
+    penalty and beta after iteration 10 raises the compliance above 1.001 x the selected
+    one, so the rule restarts from the selected design (every later iteration, the
+    parameters staying above those of the selection): iteration by iteration the
+    compliance, grayness and the eligible / restart / selected decisions of the GPU run
+    equal the oracle's."""
     nx, ny, nz = 16, 8, 8
     prob = _prob(nx, ny, nz)
-    phases = ((5, 1.5, 1.0, 0.2, None), (12, 3.0, 2.0, 0.15, 1.45), (20, 3.5, 4.0, 0.1, 1.4))
+    phases = ((3, 1.5, 1.0, 0.2, None), (10, 3.0, 1.0, 0.2, 1.45), (14, 3.5, 4.0, 0.15, 1.4),
+              (20, 4.0, 8.0, 0.1, 1.4))
     kw = dict(restart_factor=1.001, eligible_gray=0.9)
     hist, sel, xo, _ = topopt.simp_protocol(prob, 20, direct=True, phases=phases, **kw)
     t, _, _ = gpu_problem(nx, ny, nz)
