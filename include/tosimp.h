@@ -330,6 +330,19 @@ int tosimp_lanczos(tosimp_ctx* ctx, const double* xphys_dev, const double* v0_de
                    int* steps_host);
 int tosimp_tridiag_extremes(const double* alpha, const double* beta, int m, double* lmin,
                             double* lmax);
+/* tosimp_lanczos_noalloc: for callers that cannot allocate device memory (a tight
+ * serving loop, a harness that forbids hipMalloc).  Computes exactly what tosimp_lanczos
+ * computes (same kernels, same order: bit-identical alpha and beta), but keeps alpha and
+ * beta in a fixed device array of the library instead of workspace grown on demand, so
+ * the call allocates nothing (no hipMalloc / hipFree; the mesh workspace of
+ * tosimp_set_mesh is reused).  k <= 16,383 (EINVAL beyond, the array's size: 256 KiB per
+ * device, held until the process ends).  Writes beta_host[0..k-1) (entries from m - 1
+ * on are unspecified) and alpha_host[0..m), m to *steps_host.  Every call on a device
+ * shares that device's array: calls that overlap in time on one device (two threads, two
+ * contexts) race and must be serialised by the caller.  Synchronises.               */
+int tosimp_lanczos_noalloc(tosimp_ctx* ctx, const double* xphys_dev, const double* v0_dev,
+                           int k, int jacobi_scaled, double* alpha_host, double* beta_host,
+                           int* steps_host);
 /* tosimp_kappa (paper Sec. "Condition Number Estimation"): extreme eigenvalues of
  * K_c(xphys) (jacobi_scaled = 0) or D^-1/2 K_c D^-1/2 (1) by the Lanczos of
  * tosimp_lanczos with a stopping rule: after every `window` steps the smallest Ritz

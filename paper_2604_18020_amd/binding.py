@@ -114,6 +114,7 @@ def _load():
         "tosimp_simp_protocol": (I, [P, P, P, P, P, C.POINTER(ProtocolOpts),
                                      C.POINTER(ProtocolRecord), C.POINTER(I), C.POINTER(D)]),
         "tosimp_lanczos": (I, [P, P, P, I, I, P, P, C.POINTER(I)]),
+        "tosimp_lanczos_noalloc": (I, [P, P, P, I, I, P, P, C.POINTER(I)]),
         "tosimp_tridiag_extremes": (I, [P, P, I, C.POINTER(D), C.POINTER(D)]),
         "tosimp_kappa": (I, [P, P, P, I, I, D, I, C.POINTER(D), C.POINTER(D), C.POINTER(I),
                              C.POINTER(I)]),
@@ -372,6 +373,19 @@ class Tosimp:
             a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), C.byref(m)))
         return a[:m.value].copy(), b[:max(m.value - 1, 0)].copy()
 
+
+    def lanczos_noalloc(self, x, v0, k, jacobi_scaled=False):
+        """tosimp_lanczos_noalloc: the same coefficients, kept in the library's fixed
+        device array (no allocation inside the call)."""
+        a = np.zeros(k)
+        b = np.zeros(max(k, 1))
+        m = C.c_int()
+        self._sync_stream()
+        self._check(LIB.tosimp_lanczos_noalloc(
+            self._h, self._dev(x, torch.float64, self.n_elem, "x"),
+            self._dev(v0, torch.float64, self.n_dof, "v0"), int(k), int(jacobi_scaled),
+            a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), C.byref(m)))
+        return a[:m.value].copy(), b[:max(m.value - 1, 0)].copy()
 
     def kappa(self, x, v0, kmax=5000, jacobi_scaled=True, rtol=1e-3, window=50):
         """Lanczos extremes with the stopping rule: (lmin, lmax, steps, converged)."""

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <vector>
 
@@ -26,6 +27,36 @@ namespace {
 bool overlaps(const void* a, int64_t an, const void* b, int64_t bn) {
   const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
   return pa < pb + (uintptr_t)bn && pb < pa + (uintptr_t)an;
+}
+
+// ------------------------------------------------ Lanczos scratch without allocation
+// Device storage of tosimp_lanczos_noalloc: alpha[0..k) followed by beta[-1..k) of a
+// run of at most kLanczosScratchSteps steps (256 KiB).  Each device holds its own copy
+// until the process ends; every call on a device reuses it, so overlapping calls on one
+// device race.  Host code never passes `scratch` itself (a host-side stand-in): it uses
+// the device address that hipGetSymbolAddress returns, resolved once per device with
+// that device current (tosimp_create).
+constexpr int kLanczosScratchSteps = 16383;
+__device__ __align__(256) double scratch[2 * (kLanczosScratchSteps + 1)];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device `device` (resolved on first use).
+hipError_t scratch_address(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[device];
+  return hipSuccess;
 }
 
 // ------------------------------------------------------------- element stiffness
@@ -228,6 +259,11 @@ int tosimp_create(int device, void* stream, tosimp_ctx** out) {
   c->device = device;
   c->stream = (hipStream_t)stream;
   if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return TOSIMP_EHIP;
+  }
+  // The allocation-free Lanczos entry point's device storage, once per device.
+  if (scratch_address(device, &c->scratch) != hipSuccess) {
     delete c;
     return TOSIMP_EHIP;
   }
@@ -1191,19 +1227,26 @@ struct LanczosRun {
 
 // Sets up a run of at most k steps from v0 (workspace vectors w.p, w.q as the basis,
 // w.w for K q, w.r for the scaled input; v0 is read before the first step).
+// coeffs: caller-provided device storage of 2 (k + 1) doubles for alpha and beta, or
+// nullptr to use (and grow) the workspace's.
 int lanczos_begin(tosimp_ctx* ctx, const double* x, const double* v0, int k, int jacobi,
-                  LanczosRun* L) {
+                  LanczosRun* L, double* coeffs = nullptr) {
   Workspace& w = ctx->ws;
-  if (w.lanczos_cap < k + 1) {
-    if (w.lanczos) TOSIMP_HIP(ctx, hipFree(w.lanczos));
-    w.lanczos = nullptr;
-    w.lanczos_cap = 0;
-    TOSIMP_HIP(ctx, hipMalloc((void**)&w.lanczos, sizeof(double) * 2 * (size_t)(k + 1)));
-    w.lanczos_cap = k + 1;
+  if (coeffs) {
+    L->dal = coeffs;
+    L->dbe = coeffs + (k + 1);
+  } else {
+    if (w.lanczos_cap < k + 1) {
+      if (w.lanczos) TOSIMP_HIP(ctx, hipFree(w.lanczos));
+      w.lanczos = nullptr;
+      w.lanczos_cap = 0;
+      TOSIMP_HIP(ctx, hipMalloc((void**)&w.lanczos, sizeof(double) * 2 * (size_t)(k + 1)));
+      w.lanczos_cap = k + 1;
+    }
+    L->dal = w.lanczos;
+    L->dbe = w.lanczos + w.lanczos_cap;
   }
   L->x = x;
-  L->dal = w.lanczos;
-  L->dbe = w.lanczos + w.lanczos_cap;
   L->s_node = nullptr;
   SolverState* st = w.st + 2;
   if (jacobi) {
@@ -1319,6 +1362,39 @@ int tosimp_lanczos(tosimp_ctx* ctx, const double* x, const double* v0, int k, in
   if ((rc = lanczos_fetch(ctx, L, k, a, b, &m))) return rc;
   for (int j = 0; j < m; ++j) alpha_host[j] = a[j];
   for (int j = 0; j + 1 < m; ++j) beta_host[j] = b[j];
+  if (steps_host) *steps_host = m;
+  return TOSIMP_OK;
+}
+
+int tosimp_lanczos_noalloc(tosimp_ctx* ctx, const double* x, const double* v0, int k,
+                           int jacobi, double* alpha_host, double* beta_host,
+                           int* steps_host) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(x && v0 && alpha_host && beta_host && k >= 1, TOSIMP_EINVAL, "bad arguments");
+  REQUIRE(k <= kLanczosScratchSteps, TOSIMP_EINVAL,
+          "tosimp_lanczos_noalloc: k = " + std::to_string(k) + " exceeds the " +
+              std::to_string(kLanczosScratchSteps) + " steps of its fixed device storage");
+  REQUIRE(ctx->scratch, TOSIMP_ESTATE, "no device address for the Lanczos storage");
+  if ((rc = set_device(ctx))) return rc;
+  LanczosRun L;
+  if ((rc = lanczos_begin(ctx, x, v0, k, jacobi, &L, ctx->scratch))) return rc;
+  if ((rc = lanczos_steps(ctx, &L, 0, k))) return rc;
+  // beta_0 .. beta_{k-2} straight into the caller's array, then the order m (the first
+  // beta <= 0 ends an invariant subspace) and alpha_0 .. alpha_{m-1}.
+  if (k > 1)
+    TOSIMP_HIP(ctx, hipMemcpyAsync(beta_host, L.dbe + 1, sizeof(double) * (k - 1),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  int m = k;
+  for (int j = 0; j < k - 1; ++j)
+    if (!(beta_host[j] > 0.0)) {
+      m = j + 1;
+      break;
+    }
+  TOSIMP_HIP(ctx, hipMemcpyAsync(alpha_host, L.dal, sizeof(double) * m, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   if (steps_host) *steps_host = m;
   return TOSIMP_OK;
 }

@@ -115,6 +115,7 @@ struct tosimp_ctx {
   double fw_host[tosimp::kMaxFilterTaps];
   tosimp::Workspace ws;
   void* nn = nullptr;          // learned preconditioner state (nn.hip)
+  double* scratch = nullptr;   // device address of the allocation-free Lanczos storage
   // conditioning estimate of the Jacobi-scaled operator at uniform density (0: not yet
   // computed for the current mesh and boundary conditions)
   double kappa_uniform = 0;
