@@ -10,8 +10,10 @@
 //    on the low side of each axis is recomputed by the neighbouring block); a row of 32
 //    element columns lies in one wavefront.
 //  * The block streams up the z axis.  Each step stages one node plane of v (33 x 9
-//    nodes x 3 components) in LDS with coalesced row loads issued ahead (two planes
-//    in FP32, one in FP64).
+//    nodes x 3 components) in LDS, one node per lane (a 12-byte FP32 / 24-byte FP64
+//    buffer load; consecutive lanes take consecutive nodes of a row), issued ahead (two
+//    planes in FP32, one in FP64), as 16- / 32-byte node records so that a corner is
+//    one LDS read.
 //    Each thread applies the element stiffness of its element column at the current
 //    layer and keeps every partial result in registers in the 2D (x, y) Hadamard basis:
 //    the forward transform of a plane is reused as the bottom face of the next layer,
@@ -20,10 +22,11 @@
 //  * K_E is applied in factored form K_E = H^T S H / 64 (45 non-zeros in S, eight
 //    distinct values, see common.h): about 150 VALU ops per element instead of 1,152.
 //  * Each owned node sums the four element-column contributions around it in a fixed
-//    order (the x pair by a DPP shift of the wave by one lane, the y pair through LDS);
-//    finished planes are staged in LDS and written as coalesced row segments, the
-//    plane's base in the scalar buffer resource.  Fixed DOFs output y = v (a branch
-//    that only waves holding a clamped node take).
+//    order (the x pair by a DPP shift of the wave by one lane, the y pair through LDS)
+//    and the owner stores its node straight from registers (one 12- / 24-byte store;
+//    a wave's lanes write contiguous row segments), the plane's base in the scalar
+//    buffer resource.  Fixed DOFs output y = v (a branch that only waves holding a
+//    clamped node take).
 //  * Operands known to be zero on fixed DOFs (all CG vectors) skip the BC bytes of the
 //    loaded planes; only the owned node's BC byte is read.
 //  * Block ids are remapped so that each XCD gets a contiguous range of tiles.
@@ -146,6 +149,47 @@ __device__ __forceinline__ double lane_next(double v) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// Node-wide buffer accesses: one lane moves the three components of a node (12 bytes in
+// FP32, 24 in FP64).  Per-lane 4-byte accesses cap the memory pipeline far below HBM speed
+// on this GPU; whole-node accesses keep the operator's loads and stores near streaming
+// rates.
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Node3 {
+  T c[3];
+};
+
+__device__ __forceinline__ Node3<float> buf_ld_node(const float*, __amdgpu_buffer_rsrc_t r,
+                                                    int off, int soff) {
+  const u32x3 w = __builtin_amdgcn_raw_buffer_load_b96(r, off, soff, 0);
+  return {{__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z)}};
+}
+__device__ __forceinline__ Node3<double> buf_ld_node(const double*, __amdgpu_buffer_rsrc_t r,
+                                                     int off, int soff) {
+  // an offset past num_records (kOOB) stays past it after the + 16 (no wrap below 2^32)
+  const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, 0);
+  const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(r, (int)((unsigned)off + 16u), soff, 0);
+  Node3<double> n;
+  n.c[0] = __builtin_bit_cast(double, (unsigned long long)a.x | ((unsigned long long)a.y << 32));
+  n.c[1] = __builtin_bit_cast(double, (unsigned long long)a.z | ((unsigned long long)a.w << 32));
+  n.c[2] = __builtin_bit_cast(double, b);
+  return n;
+}
+// Stores keep the whole offset in the VGPR and a zero soffset (see buf_st).
+__device__ __forceinline__ void buf_st_node(const float* v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  const u32x3 w = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2])};
+  __builtin_amdgcn_raw_buffer_store_b96(w, r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_st_node(const double* v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  const unsigned long long a = __builtin_bit_cast(unsigned long long, v[0]);
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v[1]);
+  const u32x4 w = {(unsigned)a, (unsigned)(a >> 32), (unsigned)b, (unsigned)(b >> 32)};
+  __builtin_amdgcn_raw_buffer_store_b128(w, r, (int)off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v[2]), r, (int)(off + 16u), 0, 0);
+}
+
 // PM: v is known to be zero on fixed DOFs (every vector the CG iterations apply K_c to
 // is), so the plane's BC bytes are not loaded and v needs no masking; only the owned
 // node's BC byte is read (fixed rows output y = v = 0).
@@ -155,13 +199,14 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   // every z step rounds identically whatever was folded away around it (a chunk's first
   // layer starts from zero accumulators): results do not depend on the chunk depth.
 #pragma clang fp contract(on)
-  constexpr int NXL = KBX + 1, NYL = KBY + 1, ROW = 3 * NXL, NPV = ROW * NYL;
-  constexpr int NLD = (NPV + 255) / 256;
+  constexpr int NXL = KBX + 1, NYL = KBY + 1, NPN = NXL * NYL;  // nodes of a plane window
+  constexpr int NS = (NPN + 255) / 256;                          // node slots per thread
   constexpr int NE = KBX * KBY;
-  __shared__ T sv[NLD * 256];    // node plane ((KBX+1) x (KBY+1) nodes x 3), masked; padded
-  __shared__ T sr[NLD * 256];    // the same plane unmasked (fixed rows output y = v)
-  __shared__ T sb[3 * NE];       // lower-row corner pairs, [c][element column]
-  __shared__ T so[2][NLD * 256]; // finished output planes (owned nodes), same layout as sv
+  static_assert(NS == 2, "two node slots per thread");
+  // Node records of four values (the fourth unused) so that a corner is one LDS read.
+  __shared__ __attribute__((aligned(16))) T sv[NPN][4];  // node plane window, masked
+  __shared__ __attribute__((aligned(16))) T sr[PM ? 1 : NPN][4];  // unmasked (fixed rows: y = v)
+  __shared__ T sb[3 * NE];        // lower-row corner pairs, [c][element column]
   __shared__ double sred[4];
 
   const int bid = blockIdx.x;
@@ -187,23 +232,18 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   const auto rx = make_rsrc(A.x, (long long)elayer * A.nz * (long long)sizeof(XT));
   const int vplane_bytes = 3 * plane * (int)sizeof(T);
 
-  // Plane-load slots: flat LDS index f = jl*ROW + il*3 + c matches a contiguous row
-  // segment of the interleaved vector, so consecutive threads read consecutive words.
-  int voff[NLD], moff[NLD], gcomp[NLD];
-  unsigned ooff[NLD];
+  // Plane-load slots: window node q = tid + 256 s, local (q % NXL, q / NXL).  Lanes of a
+  // wave take consecutive nodes of a row, so a wave's loads cover contiguous segments.
+  int voff[NS], moff[NS];
 #pragma unroll
-  for (int s = 0; s < NLD; ++s) {
-    const int f = tid + 256 * s;
-    const int jl = f / ROW, w = f - jl * ROW, il = w / 3, c = w - il * 3;
+  for (int s = 0; s < NS; ++s) {
+    const int q = tid + 256 * s;
+    const int jl = q / NXL, il = q - jl * NXL;
     const int i = ex0 + il, j = ey0 + jl;
-    const bool ok = f < NPV && i >= 0 && i <= A.nx && j >= 0 && j <= A.ny;
+    const bool ok = q < NPN && i >= 0 && i <= A.nx && j >= 0 && j <= A.ny;
     const int node = i + NX1 * j;
-    voff[s] = ok ? (3 * node + c) * (int)sizeof(T) : kOOB;
+    voff[s] = ok ? 3 * node * (int)sizeof(T) : kOOB;
     moff[s] = ok ? node : kOOB;
-    gcomp[s] = c;
-    // owned output slot: local node (il, jl) with 1 <= il <= KBX-1, 1 <= jl <= KBY-1
-    const bool own = ok && il >= 1 && il <= KBX - 1 && jl >= 1 && jl <= KBY - 1;
-    ooff[s] = own ? (unsigned)voff[s] : (unsigned)kOOB;
   }
   // Element column of this thread.
   const int ex = ex0 + lx, ey = ey0 + ly;
@@ -212,24 +252,27 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   // Node owned by this thread in the output phase: local (lx+1, ly+1).
   const int ni = ex0 + lx + 1, nj = ey0 + ly + 1;
   const bool owner = lx < KBX - 1 && ly < KBY - 1 && ni <= A.nx && nj <= A.ny;
-  const int sown = (ly + 1) * ROW + (lx + 1) * 3;  // this thread's owned node in so
+  const int qown = (ly + 1) * NXL + (lx + 1);  // this thread's owned node in sv / sr
   const int moffown = owner ? ni + NX1 * nj : kOOB;
+  // Out-of-range lanes keep an offset past num_records (the sum stays below 2^32 and the
+  // range check is unsigned).
+  const unsigned yoffown = owner ? (unsigned)(3 * (ni + NX1 * nj) * (int)sizeof(T)) : (unsigned)kOOB;
 
-  // Register ring of D planes in flight: the plane's values and BC bytes, the owned
+  // Register ring of D planes in flight: the plane's node values and BC bytes, the owned
   // node's BC byte, and the density of the element layer below the plane.  The main
   // loop is branch-free so that every wait is for a load issued D steps earlier
   // (vmcnt waits are in order: any late load would drain the whole ring).  Planes
   // outside the mesh load a clamped plane with every DOF flagged fixed (zero).
-  T pv[D][NLD];
-  uint8_t pm[D][NLD];
+  Node3<T> pv[D][NS];
+  uint8_t pm[D][NS];
   uint8_t po[D];
   XT px[D];
-  auto issue = [&](T* v, uint8_t* m, uint8_t& mo, XT& xv, int k) {
+  auto issue = [&](Node3<T>* v, uint8_t* m, uint8_t& mo, XT& xv, int k) {
     const int kc = min(max(k, 0), A.nz);
 #pragma unroll
-    for (int s = 0; s < NLD; ++s) {
+    for (int s = 0; s < NS; ++s) {
       if constexpr (!PM) m[s] = buf_ld_u8(rm, moff[s], plane * kc);
-      v[s] = buf_ld<T>(rv, voff[s], vplane_bytes * kc);
+      v[s] = buf_ld_node(A.v, rv, voff[s], vplane_bytes * kc);
     }
     mo = buf_ld_u8(rm, moffown, plane * kc);
     const int ez = min(max(k - 1, 0), A.nz - 1);
@@ -250,63 +293,60 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   for (int c = 0; c < 3; ++c) VA[c] = VB[c] = T(0);
   double dotacc = 0.0;
 
+  T ya[3];  // upper-row corner pair of the owned node, kept across the barrier
   // One z step at node plane p: stage the plane, transform the top face, and (when
   // ELEM) apply element layer p-1 and (when OUT) emit node plane p-1.
-  // Coalesced write of a finished output plane q from so[q & 1]: every thread stores its
-  // flat slots that hold an owned node (row segments of the interleaved vector).
-  // The plane's base moves into the (scalar) resource, so the per-lane offsets stay
-  // loop-invariant and soffset stays zero.
-  auto store_plane = [&](int q) {
-    const T* src = so[q & 1];
-    const int qb = vplane_bytes * q;
-    const auto ryq = make_rsrc32(reinterpret_cast<const char*>(A.y) + qb, ybytes - qb);
-#pragma unroll
-    for (int s = 0; s < NLD; ++s) buf_st(src[tid + 256 * s], ryq, ooff[s]);
-  };
-
-  T ya[3];  // upper-row corner pair of the owned node, kept across the barrier
-  auto step = [&](int p, T* v, uint8_t* m, uint8_t& mo, XT& xv, const T* tb, T* tt,
+  auto step = [&](int p, Node3<T>* v, uint8_t* m, uint8_t& mo, XT& xv, const T* tb, T* tt,
                   const T* vown, T* vnew, uint8_t mown, uint8_t& mnew, bool elem, bool out,
-                  bool flush, int refill) {
+                  int refill) {
     // Keep each step's instructions inside its own region: the scheduler must not hoist
     // a later step's use of a ring slot above this step (that would wait on a fresh load).
     __builtin_amdgcn_sched_barrier(0);
     // A plane outside the mesh (p = -1 or nz + 1) was loaded clamped: zero it here.
     const int force = (p >= 0 && p <= A.nz) ? 0 : 7;
 #pragma unroll
-    for (int s = 0; s < NLD; ++s) {
-      const int f = tid + 256 * s;
-      if constexpr (PM) {
-        sv[f] = force ? T(0) : v[s];
-      } else {
-        sv[f] = (((m[s] | force) >> gcomp[s]) & 1) ? T(0) : v[s];
-        sr[f] = v[s];
+    for (int s = 0; s < NS; ++s) {
+      const int q = tid + 256 * s;
+      if (s > 0 && q >= NPN) continue;  // the second slot covers the window's last nodes
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if constexpr (PM) {
+          sv[q][c] = force ? T(0) : v[s].c[c];
+        } else {
+          sv[q][c] = (((m[s] | force) >> c) & 1) ? T(0) : v[s].c[c];
+          sr[q][c] = v[s].c[c];
+        }
       }
     }
     const XT xcur = xv;
     mnew = mo;
     __syncthreads();
     issue(v, m, mo, xv, refill);
-    // The output plane finished in the previous step (p - 2) leaves in coalesced rows.
-    if (flush) store_plane(p - 2);
     __builtin_amdgcn_sched_barrier(0);
 
     // Forward 2D transform of the top face (plane p) of this element column.
+    {
+      const int q00 = ly * NXL + lx;
+      T v00[3], v10[3], v01[3], v11[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const T v00 = sv[ly * ROW + lx * 3 + c];
-      const T v10 = sv[ly * ROW + (lx + 1) * 3 + c];
-      const T v01 = sv[(ly + 1) * ROW + lx * 3 + c];
-      const T v11 = sv[(ly + 1) * ROW + (lx + 1) * 3 + c];
-      const T a0 = v00 + v10, a1 = v10 - v00, b0 = v01 + v11, b1 = v11 - v01;
-      tt[0 * 3 + c] = a0 + b0;
-      tt[1 * 3 + c] = a1 + b1;
-      tt[2 * 3 + c] = b0 - a0;
-      tt[3 * 3 + c] = b1 - a1;
+      for (int c = 0; c < 3; ++c) {
+        v00[c] = sv[q00][c];
+        v10[c] = sv[q00 + 1][c];
+        v01[c] = sv[q00 + NXL][c];
+        v11[c] = sv[q00 + NXL + 1][c];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T a0 = v00[c] + v10[c], a1 = v10[c] - v00[c];
+        const T b0 = v01[c] + v11[c], b1 = v11[c] - v01[c];
+        tt[0 * 3 + c] = a0 + b0;
+        tt[1 * 3 + c] = a1 + b1;
+        tt[2 * 3 + c] = b0 - a0;
+        tt[3 * 3 + c] = b1 - a1;
+      }
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) vnew[c] = PM ? sv[(ly + 1) * ROW + (lx + 1) * 3 + c]
-                                              : sr[(ly + 1) * ROW + (lx + 1) * 3 + c];
+    for (int c = 0; c < 3; ++c) vnew[c] = PM ? sv[qown][c] : sr[qown][c];
 
     if (elem) {
       // ---- element layer ez = p - 1: bottom face tb, top face tt -------------
@@ -369,9 +409,8 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     // before the next step overwrites them.
     __syncthreads();
     if (elem && out) {
-      // Node plane p-1: sum the four element columns around the owned node into so; the
-      // next step stores it (after its first barrier).
-      T* dst = so[(p - 1) & 1];
+      // Node plane p-1: sum the four element columns around the owned node and store it
+      // (consecutive lanes hold consecutive nodes of a row: contiguous segments).
       T yv[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) yv[c] = ya[c] + sb[c * NE + tid + KBX];
@@ -381,10 +420,12 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) yv[c] = bit_select(yv[c], vown[c], (mown >> c) & 1);
       }
+      const int qb = vplane_bytes * (p - 1);
+      const auto ryq = make_rsrc32(reinterpret_cast<const char*>(A.y) + qb, ybytes - qb);
+      buf_st_node(yv, ryq, yoffown);
+      if constexpr (DOT) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (owner) dst[sown + c] = yv[c];
-        if constexpr (DOT) dotacc += owner ? (double)vown[c] * (double)yv[c] : 0.0;
+        for (int c = 0; c < 3; ++c) dotacc += owner ? (double)vown[c] * (double)yv[c] : 0.0;
       }
     }
   };
@@ -402,14 +443,11 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     const int refill = min(p + D, k1);
     if (i % 2 == 0)
       step(p, pv[i % D], pm[i % D], po[i % D], px[i % D], TA, TB, VA, VB, MA, MB, i >= 1,
-           i >= 2, i >= 3, refill);
+           i >= 2, refill);
     else
       step(p, pv[i % D], pm[i % D], po[i % D], px[i % D], TB, TA, VB, VA, MB, MA, i >= 1,
-           i >= 2, i >= 3, refill);
+           i >= 2, refill);
   }
-  // The last output plane (k1 - 1, finished in the final step).
-  __syncthreads();
-  store_plane(k1 - 1);
 
   if constexpr (DOT) {
     const double bsum = block_sum<256>(dotacc, sred);
