@@ -232,6 +232,208 @@ void conv_igemm_kernel(ConvArgs a) {
   }
 }
 
+// Stride-1 3x3x3 convolutions (forward, and the data gradient as the convolution with
+// mirrored taps), tiled through LDS.  A block owns an output brick of 16 x 8 x 4 voxels
+// (x fastest) and a group of up to 32 result channels.  For each slice of CS channels
+// along K (32 bytes per voxel: 16 BF16 / 8 FP32) it stages in LDS the halo'd brick of
+// 18 x 10 x 6 operand voxels (zero outside the grid; for the data gradient
+// dZ = dY leaky'(a) is formed while staging) and the group's weights of the slice (27
+// taps x CS).  Wave w computes the 8 rows (y) of z layer w: for each tap pair (tz, tx)
+// it holds the weight tiles of the three y taps in registers and walks the ten brick
+// rows rho once; the operand tile of row rho (16 consecutive voxels x CS channels, one
+// 8-byte LDS read per lane, conflict-free) feeds output rows rho - oy(ty) for all three
+// y taps, so each operand tile read serves up to three matrix-core products.  Products
+// are 16 x 16 x 16 (BF16) or two 16 x 16 x 4 (FP32).  Summation order: channel slice, tz,
+// tx, row, ty (fixed: deterministic).
+constexpr int kBrX = 16, kBrY = 4, kBrZ = 4;                      // output brick
+constexpr int kHaX = kBrX + 2, kHaY = kBrY + 2, kHaZ = kBrZ + 2;  // staged brick
+constexpr int kHaVox = kHaX * kHaY * kHaZ;                        // 1080
+constexpr int kC3Group = 32;                                      // result channels per block
+constexpr int kC3SliceBytes = 32;                                 // K channel bytes per voxel and slice
+constexpr int kC3WPad = 8;                                        // weight row pad (elements)
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+// Four BF16 / two FP32 consecutive channels (8 bytes) of a lane's share of a K step.
+template <typename ST>
+struct Pk4;
+template <>
+struct Pk4<bf16_t> {
+  s16x4 v;
+  __device__ __forceinline__ void load(const bf16_t* p) { v = *reinterpret_cast<const s16x4*>(p); }
+};
+template <>
+struct Pk4<float> {
+  float2 v;
+  __device__ __forceinline__ void load(const float* p) { v = *reinterpret_cast<const float2*>(p); }
+};
+// acc += A (16 x K) B (K x 16) for one K step of CS channels: lane (m or n, q) supplies
+// the channels 4q..4q+3 (BF16) or 2q, 2q+1 (FP32, one per 16 x 16 x 4 product).
+__device__ __forceinline__ void mma16(f32x4& acc, const Pk4<bf16_t>& a, const Pk4<bf16_t>& b) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.v, b.v, acc, 0, 0, 0);
+}
+__device__ __forceinline__ void mma16(f32x4& acc, const Pk4<float>& a, const Pk4<float>& b) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v.x, b.v.x, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v.y, b.v.y, acc, 0, 0, 0);
+}
+
+template <typename ST>
+constexpr int conv3_cs() { return kC3SliceBytes / (int)sizeof(ST); }  // 16 BF16, 8 FP32
+template <typename ST>
+constexpr int conv3_wrow() { return 27 * conv3_cs<ST>() + kC3WPad; }
+template <typename ST>
+constexpr int conv3_lds_bytes() {
+  return (kHaVox * conv3_cs<ST>() + kC3Group * conv3_wrow<ST>()) * (int)sizeof(ST);
+}
+
+template <typename ST, bool BWD>
+__global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a) {
+  constexpr int CS = conv3_cs<ST>(), WROW = conv3_wrow<ST>();
+  constexpr int PV = CS / 8;       // 8-element staging pieces per voxel slice
+  constexpr int LQ = CS / 4;       // elements per lane and K step
+  __shared__ __attribute__((aligned(16))) unsigned char smem[conv3_lds_bytes<ST>()];
+  ST* brick = reinterpret_cast<ST*>(smem);   // [1080 voxels][CS]
+  ST* ws = brick + kHaVox * CS;               // [32 channels][27 taps x CS (+ pad)]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const Grid3 g = a.gout;  // stride 1: input and output grids agree
+  const int nbx = (g.X + kBrX - 1) / kBrX, nby = (g.Y + kBrY - 1) / kBrY;
+  const int bx = blockIdx.x % nbx, rest = blockIdx.x / nbx;
+  const int by = rest % nby, bz = rest / nby;
+  const int x0 = bx * kBrX, y0 = by * kBrY, z0 = bz * kBrZ;
+  const int kch = BWD ? a.cout : a.cin;   // channels along K
+  const int nres = BWD ? a.cin : a.cout;  // result channels
+  const int Kw = 27 * kch;                // weight row length in global memory
+  const int cg = blockIdx.y * kC3Group;
+  const int ng = min(kC3Group, nres - cg), nblk = ng / 16;
+  const int m = lane & 15, q = lane >> 4;
+  const ST* in = (const ST*)a.in;
+  const ST* act = (const ST*)a.act;
+  const ST* w = (const ST*)a.w;
+
+  f32x4 acc[kBrY][2];
+#pragma unroll
+  for (int r = 0; r < kBrY; ++r)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[r][b] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+
+  for (int cs0 = 0; cs0 < kch; cs0 += CS) {
+    // ---- stage the brick's slice of channels [cs0, cs0 + CS) and the group's weights:
+    // each batch of loads is issued before its LDS stores (one latency per batch).
+    constexpr int NBP = (kHaVox * PV + 255) / 256;        // brick pieces per thread
+    constexpr int NWP = (kC3Group * 27 * PV + 255) / 256;  // weight pieces per thread
+    {
+      Pack8<ST> pb[NBP], pa[BWD ? NBP : 1];
+#pragma unroll
+      for (int i = 0; i < NBP; ++i) {
+        const int idx = tid + 256 * i;
+        const int vb = idx / PV, pc = idx - vb * PV;
+        const int hx = vb % kHaX, hr = vb / kHaX, hy = hr % kHaY, hz = hr / kHaY;
+        const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+        pb[i].zero();
+        if (BWD) pa[i].zero();
+        if (idx < kHaVox * PV && gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 &&
+            gz < g.Z) {
+          const long long o =
+              ((long long)gx + (long long)g.X * (gy + (long long)g.Y * gz)) * kch + cs0 + 8 * pc;
+          pb[i].load(in + o);
+          if (BWD && act) pa[i].load(act + o);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NBP; ++i) {
+        const int idx = tid + 256 * i;
+        if (idx < kHaVox * PV) {
+          if (BWD && act) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              pb[i].set(j, pb[i].get(j) * (pa[i].get(j) > 0.0f ? 1.0f : kLeak));
+          }
+          const int vb = idx / PV, pc = idx - vb * PV;
+          pb[i].store(brick + vb * CS + 8 * pc);
+        }
+      }
+    }
+    {
+      Pack8<ST> pw[NWP];
+#pragma unroll
+      for (int i = 0; i < NWP; ++i) {
+        const int idx = tid + 256 * i;
+        const int n = idx / (27 * PV), rr = idx - n * (27 * PV), t = rr / PV, pc = rr - t * PV;
+        pw[i].zero();
+        if (n < ng) pw[i].load(w + (long long)(cg + n) * Kw + t * kch + cs0 + 8 * pc);
+      }
+#pragma unroll
+      for (int i = 0; i < NWP; ++i) {
+        const int idx = tid + 256 * i;
+        const int n = idx / (27 * PV), rr = idx - n * (27 * PV), t = rr / PV, pc = rr - t * PV;
+        if (n < ng) pw[i].store(ws + n * WROW + t * CS + 8 * pc);
+      }
+    }
+    __syncthreads();
+    // ---- taps: for each (tz, tx) the three y taps share every operand row tile
+    for (int tz = 0; tz < 3; ++tz) {
+      const int oz = BWD ? 2 - tz : tz;
+      for (int tx = 0; tx < 3; ++tx) {
+        const int ox = BWD ? 2 - tx : tx;
+        Pk4<ST> B[3][2];
+#pragma unroll
+        for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            if (b < nblk) B[ty][b].load(ws + (b * 16 + m) * WROW + (tx + 3 * ty + 9 * tz) * CS + LQ * q);
+        const ST* arow = brick + ((m + ox) + kHaX * kHaY * (wv + oz)) * CS + LQ * q;
+#pragma unroll
+        for (int rho = 0; rho < kHaY; ++rho) {
+          Pk4<ST> A;
+          A.load(arow + kHaX * rho * CS);
+#pragma unroll
+          for (int ty = 0; ty < 3; ++ty) {
+            // forward: output row rho - ty reads tap ty; data gradient: rho - (2 - ty)
+            const int r = rho - (BWD ? 2 - ty : ty);
+            if (r >= 0 && r < kBrY) {
+#pragma unroll
+              for (int b = 0; b < 2; ++b)
+                if (b < nblk) mma16(acc[r][b], A, B[ty][b]);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();  // the next slice overwrites the brick and the weights
+  }
+  ST* out = (ST*)a.out;
+  const int gz = z0 + wv;
+#pragma unroll
+  for (int r = 0; r < kBrY; ++r) {
+    const int gy = y0 + r;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      if (b < nblk && gy < g.Y && gz < g.Z) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int gx = x0 + 4 * q + j;
+          if (gx < g.X) {
+            float val = acc[r][b][j];
+            if (!BWD && a.apply_act) val = val > 0.0f ? val : kLeak * val;
+            const long long o = (long long)gx + (long long)g.X * (gy + (long long)g.Y * gz);
+            out[o * nres + cg + b * 16 + m] = from_f<ST>(val);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <typename ST, bool BWD>
+hipError_t launch_conv3_lds(hipStream_t s, const ConvArgs& a) {
+  const int kch = BWD ? a.cout : a.cin, nres = BWD ? a.cin : a.cout;
+  if (kch % conv3_cs<ST>() || nres % 16) return hipErrorInvalidValue;
+  const Grid3 g = a.gout;
+  const int nb = ((g.X + kBrX - 1) / kBrX) * ((g.Y + kBrY - 1) / kBrY) * ((g.Z + kBrZ - 1) / kBrZ);
+  conv3_lds_kernel<ST, BWD><<<dim3(nb, (nres + kC3Group - 1) / kC3Group), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 // Weight gradient, one block per (chunk of cvox output voxels, tap, group of up to 32
 // (cout/16 x cin/16) tiles).  Per step of kc voxels (a multiple of 32 dividing cvox,
 // as many as fit 32 KB of LDS) the block stages dZ = dY leaky'(a)
@@ -874,6 +1076,8 @@ hipError_t conv_fwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* in, v
   a.ksize = l.k;
   a.stride = l.s;
   a.apply_act = act;
+  if (l.k == 3 && l.s == 1 && a.cin % conv3_cs<ST>() == 0)
+    return launch_conv3_lds<ST, false>(c->stream, a);
   const int waves = (a.gout.n() + 16 * kConvRT - 1) / (16 * kConvRT);
   conv_igemm_kernel<ST, false><<<dim3((waves + 3) / 4, (a.cout + 63) / 64), 256, 0, c->stream>>>(a);
   return hipGetLastError();
@@ -917,6 +1121,8 @@ hipError_t conv_bwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* dY, c
     a.act = a_out;
     a.w = (const char*)S->WT + l.woff * S->es;
     a.out = dX;
+    if (l.k == 3 && l.s == 1 && a.cout % conv3_cs<ST>() == 0 && a.cin % 16 == 0)
+      return launch_conv3_lds<ST, true>(c->stream, a);
     const int waves = (a.gin.n() + 16 * kConvRT - 1) / (16 * kConvRT);
     conv_igemm_kernel<ST, true><<<dim3((waves + 3) / 4, (a.cin + 63) / 64), 256, 0, c->stream>>>(a);
   }
