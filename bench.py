@@ -12,9 +12,10 @@ them, bracketed by torch.cuda.synchronize().  `value` = DOFs processed per secon
   * kv_other_precision: the same measurement for the other operator precision,
   * kv_mfma: the BF16 / FP16 matrix-core contraction variant (FP32 storage),
   * kv_torsion_55x55x165: FP32 / FP64 on the torsion mesh,
-  * pcg: wall time to ||r|| <= 1e-6 ||f|| for plain FP64 Jacobi-PCG and for FP64
-    refinement around an FP32 inner Jacobi-PCG, with the compliance error of each
-    against an FP64 solve to 1e-10,
+  * pcg: wall time to ||r|| <= 1e-6 ||f|| for plain FP64 Jacobi-PCG, for FP64
+    refinement around an FP32 inner Jacobi-PCG, and for CG preconditioned by the
+    geometric-multigrid V-cycle (FP64, and FP32 inside FP64 refinement), with the
+    compliance error of each against an FP64 solve to 1e-10,
   * learned_pcg: the learned preconditioner on the 200x100x50 cantilever (pairs
     harvested from the first 10 SIMP iterations, U-Net trained on the GPU, flexible CG
     against Jacobi-PCG on the next iteration's system),
@@ -153,14 +154,26 @@ def pcg_compare(t, f, tol, volfrac=0.3):
     x = torch.full((t.n_elem,), volfrac, dtype=torch.float64, device="cuda:0")
     _, ref = _solve_timed(t, x, f, 1e-10, mode="plain_fp64", check_every=64)
     out = {"reference_compliance_tol1e-10": ref["compliance"]}
-    for name, kw in [("plain_fp64", dict(mode="plain_fp64", check_every=64)),
-                     ("ir_fp32", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,
-                                      max_outer=30, check_every=64))]:
+    # the multigrid hierarchy is allocated on first use: one untimed solve first
+    _solve_timed(t, x, f, 1e-2, mode="plain_fp64", precond="mg", check_every=4)
+    for name, kw in SOLVERS:
         _, r = _solve_timed(t, x, f, tol, **kw)
         r["compliance_rel_err"] = abs(r["compliance"] - ref["compliance"]) / abs(ref["compliance"])
         out[name] = r
     out["speedup_ir_over_plain"] = out["plain_fp64"]["seconds"] / out["ir_fp32"]["seconds"]
+    out["speedup_ir_mg_over_plain"] = out["plain_fp64"]["seconds"] / out["ir_fp32_mg"]["seconds"]
     return out
+
+
+# Solvers compared on one system: Jacobi-PCG in FP64, FP64 refinement around FP32
+# Jacobi-PCG, and CG preconditioned by the geometric-multigrid V-cycle (FP64, and FP32
+# inside FP64 refinement).
+SOLVERS = [("plain_fp64", dict(mode="plain_fp64", check_every=64)),
+           ("ir_fp32", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4, max_outer=30,
+                            check_every=64)),
+           ("plain_fp64_mg", dict(mode="plain_fp64", precond="mg", check_every=4)),
+           ("ir_fp32_mg", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4, max_outer=30,
+                               precond="mg", check_every=4))]
 
 
 def time_nn(workload="cantilever_200x100x50", simp_iters=10, per_solve=200, every=5,
@@ -206,9 +219,12 @@ def time_nn(workload="cantilever_200x100x50", simp_iters=10, per_solve=200, ever
            "train_s": t_train, "loss": "relative MSE to the unit-RMS error",
            "loss_first50": float(np.mean(losses[:50])),
            "loss_last50": float(np.mean(losses[-50:]))}
+    _solve_timed(t, xp, f, 1e-2, mode="plain_fp64", precond="mg", check_every=4)  # allocation
     for name, kw in [("plain_fp64_jacobi", dict(mode="plain_fp64", check_every=64)),
                      ("ir_fp32_jacobi", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,
                                              check_every=64)),
+                     ("ir_fp32_mg", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,
+                                         precond="mg", check_every=4)),
                      ("ir_fp32_nn_fcg", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,
                                              precond="nn", check_every=8, maxit=20000))]:
         _, r = _solve_timed(t, xp, f, tol, **kw)

@@ -67,6 +67,7 @@ extern "C" {
 
 #define TOSIMP_PRECOND_JACOBI 0
 #define TOSIMP_PRECOND_NN 1       /* learned U-Net correction in flexible CG          */
+#define TOSIMP_PRECOND_MG 2       /* geometric-multigrid V-cycle (see tosimp_mg_apply) */
 
 typedef struct tosimp_ctx tosimp_ctx;
 
@@ -94,6 +95,8 @@ typedef struct tosimp_solve_opts {
   int nn_stall;      /* PRECOND_NN: once ||r|| has made no new minimum for this many       */
                      /*   iterations of an inner solve, plain Jacobi-PCG continues it from  */
                      /*   the current iterate (0 = 50, < 0 = never)                          */
+  int mg_degree;     /* PRECOND_MG: Chebyshev smoothing degree (1..16; 0 = 2)               */
+  double mg_alpha;   /* PRECOND_MG: smoothing interval [lam / alpha, lam] (> 1; 0 = 20)     */
 } tosimp_solve_opts;
 
 typedef struct tosimp_solve_stats {
@@ -354,6 +357,29 @@ int tosimp_lanczos_noalloc(tosimp_ctx* ctx, const double* xphys_dev, const doubl
 int tosimp_kappa(tosimp_ctx* ctx, const double* xphys_dev, const double* v0_dev, int kmax,
                  int jacobi_scaled, double rtol, int window, double* lmin, double* lmax,
                  int* steps, int* converged);
+
+/* ---- geometric multigrid ------------------------------------------------------------
+ * tosimp_mg_apply (paper Sec. "Path to Geometric Multigrid Integration": the fused
+ * operator as smoother, restriction R, prolongation P = R^T, direct coarsest solve):
+ * z = V(r), one V-cycle for K_c(xphys) z = r.  Levels: n -> ceil(n/2) elements per axis of
+ * twice the edge until an axis has one element (at most 12 levels); coarse operators
+ * re-discretised (K_E scaled by the edge, a coarse modulus = sum of the existing children's
+ * moduli / 8); a coarse DOF is fixed when a fine DOF in its interpolation support is;
+ * trilinear P; Chebyshev smoothing of the given degree (0 = 2) on D^-1 K over
+ * [lam / alpha, lam] (alpha 0 = 20), lam = lambda_max(K_E) / K_E[0][0] (an upper bound of
+ * lambda_max(D^-1 K) for any density), before and after the coarse correction (symmetric
+ * V-cycle); the coarsest level is solved with the dense inverse of its operator (at most
+ * 1,536 DOFs: EINVAL for meshes whose coarsest grid is larger).  xphys: n_elem FP64; r, z:
+ * n_dof values of prec (TOSIMP_PREC_FP64 or TOSIMP_PREC_FP32), r zero on fixed DOFs; z
+ * must not overlap r or xphys (EINVAL).  The hierarchy is rebuilt for xphys on every call
+ * (synchronises once for the coarsest inverse).  tosimp_pcg_solve with precond =
+ * TOSIMP_PRECOND_MG runs CG preconditioned by one V-cycle per iteration (plain mode: FP64
+ * vectors and V-cycle; IR mode: FP32 inner vectors and V-cycle).
+ * tosimp_mg_levels: writes the element counts of up to `cap` levels to dims_host[3 l ..
+ * 3 l + 2] and returns the number of levels (negative: an error status).              */
+int tosimp_mg_apply(tosimp_ctx* ctx, const double* xphys_dev, const void* r_dev, void* z_dev,
+                    int prec, int degree, double alpha);
+int tosimp_mg_levels(tosimp_ctx* ctx, int* dims_host, int cap);
 
 /* ---- learned preconditioner -------------------------------------------------------
  * A 3-level 3D-convolutional U-Net N on the node grid supplies the correction of a

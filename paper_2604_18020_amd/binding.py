@@ -21,7 +21,7 @@ V_ZERO_ON_FIXED = 0x100
 PREC = {"fp64": 0, "fp32": 1, "bf16_mfma": 2, "fp16_mfma": 3}
 FILTER = {"forward": 0, "adjoint": 1}
 SOLVE = {"plain_fp64": 0, "ir": 1}
-PRECOND = {"jacobi": 0, "nn": 1}
+PRECOND = {"jacobi": 0, "nn": 1, "mg": 2}
 _DT = {torch.float64: F64, torch.float32: F32}
 
 
@@ -37,7 +37,8 @@ class SolveOpts(C.Structure):
                 ("precond", C.c_int), ("check_every", C.c_int), ("enforce_rule", C.c_int),
                 ("kappa", C.c_double), ("harvest_r", C.c_void_p), ("harvest_u", C.c_void_p),
                 ("harvest_cap", C.c_int), ("harvest_every", C.c_int), ("fcg_window", C.c_int),
-                ("eager", C.c_int), ("nn_stall", C.c_int)]
+                ("eager", C.c_int), ("nn_stall", C.c_int), ("mg_degree", C.c_int),
+                ("mg_alpha", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -118,6 +119,8 @@ def _load():
         "tosimp_tridiag_extremes": (I, [P, P, I, C.POINTER(D), C.POINTER(D)]),
         "tosimp_kappa": (I, [P, P, P, I, I, D, I, C.POINTER(D), C.POINTER(D), C.POINTER(I),
                              C.POINTER(I)]),
+        "tosimp_mg_apply": (I, [P, P, P, P, I, I, D]),
+        "tosimp_mg_levels": (I, [P, P, I]),
         "tosimp_nn_create": (I, [P, I, I]),
         "tosimp_nn_num_params": (I, [P, C.POINTER(L)]),
         "tosimp_nn_set_weights": (I, [P, P, L]),
@@ -238,10 +241,12 @@ class Tosimp:
     @staticmethod
     def solve_opts(tol=1e-8, maxit=20000, mode="plain_fp64", inner_prec="fp32",
                    inner_tol=1e-5, max_outer=30, precond="jacobi", check_every=16,
-                   enforce_rule=False, kappa=0.0, fcg_window=1, eager=False, nn_stall=0):
+                   enforce_rule=False, kappa=0.0, fcg_window=1, eager=False, nn_stall=0,
+                   mg_degree=0, mg_alpha=0.0):
         return SolveOpts(tol, maxit, SOLVE[mode], PREC[inner_prec], inner_tol, max_outer,
                          PRECOND[precond], check_every, int(enforce_rule), kappa, None, None,
-                         0, 0, int(fcg_window), int(bool(eager)), int(nn_stall))
+                         0, 0, int(fcg_window), int(bool(eager)), int(nn_stall),
+                         int(mg_degree), float(mg_alpha))
 
     def _opts_with_harvest(self, harvest, harvest_every, **kw):
         o = self.solve_opts(**kw)
@@ -396,6 +401,27 @@ class Tosimp:
             self._dev(v0, torch.float64, self.n_dof, "v0"), int(kmax), int(jacobi_scaled),
             float(rtol), int(window), C.byref(lo), C.byref(hi), C.byref(st), C.byref(cv)))
         return lo.value, hi.value, st.value, bool(cv.value)
+
+    # ------------------------------------------------------------------ multigrid
+    def mg_apply(self, x, r, z=None, degree=0, alpha=0.0):
+        """One V-cycle z = V(r) for K_c(x) (FP64 or FP32 by r's dtype)."""
+        if z is None:
+            z = torch.empty_like(r)
+        prec = PREC["fp64"] if r.dtype == torch.float64 else PREC["fp32"]
+        self._sync_stream()
+        self._check(LIB.tosimp_mg_apply(
+            self._h, self._dev(x, torch.float64, self.n_elem, "x"),
+            self._dev(r, r.dtype, self.n_dof, "r"), self._dev(z, r.dtype, self.n_dof, "z"),
+            prec, int(degree), float(alpha)))
+        return z
+
+    def mg_levels(self, cap=16):
+        dims = (C.c_int * (3 * cap))()
+        self._sync_stream()
+        n = LIB.tosimp_mg_levels(self._h, dims, cap)
+        if n < 0:
+            self._check(n)
+        return [tuple(dims[3 * l:3 * l + 3]) for l in range(n)]
 
     # ------------------------------------------------------------------ learned preconditioner
     def nn_create(self, base=16, bf16=True):

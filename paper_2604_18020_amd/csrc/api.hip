@@ -190,6 +190,7 @@ bool hadamard_consts(const double* KE, HadConsts* hc, double* max_dev) {
 
 void free_ws(tosimp_ctx* c) {
   nn_release(c);  // the network's tensors are sized for the mesh
+  mg_release(c);  // so is the multigrid hierarchy
   Workspace& w = c->ws;
   void* dev[] = {w.mask, w.f,   w.Hs,  w.dv,  w.fw,  w.dinv, w.dinv32,  w.r,
                  w.p,    w.q,   w.w,   w.r32, w.p32, w.q32,  w.e32,     w.z32,
@@ -283,6 +284,7 @@ int tosimp_destroy(tosimp_ctx* ctx) {
   }
   free_ws(ctx);
   nn_release(ctx);
+  mg_release(ctx);
   delete ctx;
   return TOSIMP_OK;
 }
@@ -719,9 +721,30 @@ int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
   tosimp_solve_stats s{};
   Workspace& w = ctx->ws;
   TOSIMP_HIP(ctx, launch_mask_vec(ctx, u));
-  if (o->mode == TOSIMP_SOLVE_PLAIN_FP64) {
+  REQUIRE(o->precond == TOSIMP_PRECOND_JACOBI || o->precond == TOSIMP_PRECOND_NN ||
+              o->precond == TOSIMP_PRECOND_MG,
+          TOSIMP_EINVAL, "bad preconditioner");
+  int mg_deg = o->mg_degree;
+  double mg_alpha = o->mg_alpha;
+  if (o->precond == TOSIMP_PRECOND_MG) {
+    if ((rc = mg_prepare(ctx, x, &mg_deg, &mg_alpha))) return rc;
+  }
+  if (o->mode == TOSIMP_SOLVE_PLAIN_FP64 && o->precond == TOSIMP_PRECOND_MG) {
+    // CG in FP64 preconditioned by an FP64 V-cycle (warm start from u)
+    MgPcgResult pr;
+    rc = mg_pcg<double>(ctx, x, b, u, w.r, w.w, w.p, w.q, 0, o->tol, o->maxit, o->check_every,
+                        false, mg_deg, mg_alpha, &pr);
+    if (rc) return rc;
+    s.iterations = pr.iters;
+    s.rel_residual = pr.bb > 0 ? std::sqrt(pr.rr / pr.bb) : 0.0;
+    s.status = pr.done == 3 ? TOSIMP_EBREAKDOWN
+                            : (pr.done == 2 ? TOSIMP_NOT_CONVERGED : TOSIMP_OK);
+    double rr = 0;
+    if ((rc = true_residual(ctx, x, b, u, &rr))) return rc;
+    s.true_rel_residual = pr.bb > 0 ? std::sqrt(rr / pr.bb) : 0.0;
+  } else if (o->mode == TOSIMP_SOLVE_PLAIN_FP64) {
     REQUIRE(o->precond == TOSIMP_PRECOND_JACOBI, TOSIMP_EINVAL,
-            "plain FP64 mode uses the Jacobi preconditioner");
+            "plain FP64 mode uses the Jacobi or multigrid preconditioner");
     TOSIMP_HIP(ctx, launch_diag_inv(ctx, x, w.dinv, nullptr));
     PcgResult pr;
     Harvest hv;
@@ -800,7 +823,16 @@ int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
       const double need = 0.3 * o->tol * bn / sc;
       const double itol = std::min(0.5, std::max(o->inner_tol, need));
       int it = 0, done = 0;
-      if (o->precond == TOSIMP_PRECOND_NN) {
+      if (o->precond == TOSIMP_PRECOND_MG) {
+        REQUIRE(ip == TOSIMP_PREC_FP32, TOSIMP_EINVAL,
+                "the multigrid inner solve runs in FP32");
+        MgPcgResult pr;
+        rc = mg_pcg<float>(ctx, w.x32, w.e32, w.z32, w.r32, (float*)w.w, w.p32, w.q32, 1, itol,
+                           o->maxit - total, o->check_every, true, mg_deg, mg_alpha, &pr);
+        if (rc) return rc;
+        it = pr.iters;
+        done = pr.done;
+      } else if (o->precond == TOSIMP_PRECOND_NN) {
         int fb = 0;
         const int stall = o->nn_stall == 0 ? 50 : o->nn_stall;
         rc = nn_fcg_solve(ctx, ip, w.x32, w.e32, w.z32, itol, o->maxit - total,
@@ -1408,6 +1440,31 @@ int tosimp_kappa(tosimp_ctx* ctx, const double* x, const double* v0, int kmax, i
   REQUIRE(kmax >= 1 && window >= 1 && rtol > 0, TOSIMP_EINVAL, "need kmax, window >= 1, rtol > 0");
   if ((rc = set_device(ctx))) return rc;
   return kappa_run(ctx, x, v0, kmax, jacobi, rtol, window, lmin, lmax, steps, converged);
+}
+
+int tosimp_mg_apply(tosimp_ctx* ctx, const double* x, const void* r, void* z, int prec,
+                    int degree, double alpha) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(x && r && z, TOSIMP_EINVAL, "null pointer");
+  REQUIRE(prec == TOSIMP_PREC_FP64 || prec == TOSIMP_PREC_FP32, TOSIMP_EINVAL,
+          "multigrid precision must be FP64 or FP32");
+  const int64_t vb = ctx->n_dof * (prec == TOSIMP_PREC_FP64 ? 8 : 4);
+  REQUIRE(!overlaps(z, vb, r, vb) && !overlaps(z, vb, x, 8 * ctx->n_elem), TOSIMP_EINVAL,
+          "z must not overlap r or xphys");
+  if ((rc = set_device(ctx))) return rc;
+  if ((rc = mg_prepare(ctx, x, &degree, &alpha))) return rc;
+  if (prec == TOSIMP_PREC_FP64)
+    return mg_apply<double>(ctx, (const double*)r, (double*)z, degree, alpha, nullptr);
+  return mg_apply<float>(ctx, (const float*)r, (float*)z, degree, alpha, nullptr);
+}
+
+int tosimp_mg_levels(tosimp_ctx* ctx, int* dims_host, int cap) {
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  REQUIRE(dims_host && cap >= 1, TOSIMP_EINVAL, "bad arguments");
+  if ((rc = set_device(ctx))) return rc;
+  return mg_levels(ctx, dims_host, cap);
 }
 
 // Number of eigenvalues of the tridiagonal (a, b) smaller than s (Sturm count).

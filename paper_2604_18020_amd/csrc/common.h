@@ -116,6 +116,7 @@ struct tosimp_ctx {
   tosimp::Workspace ws;
   void* nn = nullptr;          // learned preconditioner state (nn.hip)
   double* scratch = nullptr;   // device address of the allocation-free Lanczos storage
+  void* mg = nullptr;          // multigrid hierarchy (mg.hip), sized for the mesh
   // conditioning estimate of the Jacobi-scaled operator at uniform density (0: not yet
   // computed for the current mesh and boundary conditions)
   double kappa_uniform = 0;
@@ -152,6 +153,32 @@ hipError_t launch_diag_inv(const tosimp_ctx* c, const double* xphys, double* din
 hipError_t launch_diag_inv32(const tosimp_ctx* c, const float* x32, float* dinv32);
 hipError_t launch_diag_full(const tosimp_ctx* c, int xdtype, const void* x, int dtype,
                             void* d);
+// Multigrid levels: operator with element moduli given and K_E scaled by kscale (v zero
+// on fixed DOFs), and the per-node inverse Jacobi diagonal of such a level.
+hipError_t kv_level_launch(const tosimp_ctx* c, int prec, const void* E, const void* v,
+                           void* y, int nx, int ny, int nz, const uint8_t* mask,
+                           double kscale, const SolverState* st = nullptr);
+
+// Geometric multigrid (mg.hip).  mg_prepare: hierarchy for density x (FP64) with the
+// Chebyshev degree and alpha (0 = defaults 2 and 20, validated); mg_apply: z = V(r) on the
+// fine level; mg_pcg: CG preconditioned by V(.) (slot: solver-state slot); mg_levels:
+// level dims into dims[3 l + {0,1,2}], returns the level count (or a negative status);
+// mg_release: frees the hierarchy (mesh change, destroy).
+struct MgPcgResult {
+  int iters = 0, done = 0;
+  double rr = 0, bb = 0;
+};
+int mg_prepare(tosimp_ctx* ctx, const double* x, int* degree, double* alpha);
+template <typename T>
+int mg_apply(tosimp_ctx* ctx, const T* r, T* z, int degree, double alpha, const SolverState* st);
+template <typename T>
+int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T* q,
+           int slot, double tol, int maxit, int check_every, bool zero_guess, int degree,
+           double alpha, MgPcgResult* res);
+int mg_levels(tosimp_ctx* ctx, int* dims, int cap);
+void mg_release(tosimp_ctx* ctx);
+hipError_t launch_diag_level(const tosimp_ctx* c, const double* E, int nx, int ny, int nz,
+                             double kscale, double* dinv64, float* dinv32);
 
 // Solver kernels (vec.hip).
 hipError_t launch_finalize_dot(const tosimp_ctx* c, const double* partials, int n,

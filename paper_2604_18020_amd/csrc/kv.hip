@@ -66,11 +66,17 @@ struct KvArgs {
   KvC<T> k;
 };
 
-template <typename T, typename XT, bool P3>
+// Element modulus from the element value xv.  PEN selects the law: kPenPow
+// Emin + x^penal (E0 - Emin), kPenCube the same with penal = 3, kPenModulus: xv is the
+// modulus itself (multigrid levels carry averaged moduli, not densities).
+enum KvPen { kPenPow = 0, kPenCube = 1, kPenModulus = 2 };
+
+template <typename T, typename XT, int PEN>
 __device__ __forceinline__ T simp_E(XT xv, T Emin, T E0mEmin, T penal) {
   T x = static_cast<T>(xv);
+  if constexpr (PEN == kPenModulus) return x;
   T xp;
-  if constexpr (P3) {
+  if constexpr (PEN == kPenCube) {
     xp = x * x * x;
   } else {
     xp = x > T(0) ? pow(x, penal) : T(0);
@@ -193,7 +199,7 @@ __device__ __forceinline__ void buf_st_node(const double* v, __amdgpu_buffer_rsr
 // PM: v is known to be zero on fixed DOFs (every vector the CG iterations apply K_c to
 // is), so the plane's BC bytes are not loaded and v needs no masking; only the owned
 // node's BC byte is read (fixed rows output y = v = 0).
-template <typename T, typename XT, bool P3, bool DOT, bool PM, int D, int KZMAX>
+template <typename T, typename XT, int PEN, bool DOT, bool PM, int D, int KZMAX>
 __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   // Multiply-adds are fused only within one expression, never across statements, so
   // every z step rounds identically whatever was folded away around it (a chunk's first
@@ -351,7 +357,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     if (elem) {
       // ---- element layer ez = p - 1: bottom face tb, top face tt -------------
       const bool eok = exy_ok && p - 1 >= 0 && p - 1 < A.nz;
-      const T E = eok ? simp_E<T, XT, P3>(xcur, A.Emin, A.E0mEmin, A.penal) : T(0);
+      const T E = eok ? simp_E<T, XT, PEN>(xcur, A.Emin, A.E0mEmin, A.penal) : T(0);
 #define HB(m2, c) (tb[(m2) * 3 + (c)] + tt[(m2) * 3 + (c)])
 #define HT(m2, c) (tt[(m2) * 3 + (c)] - tb[(m2) * 3 + (c)])
       const T h1x = HB(1, 0), h1y = HB(1, 1), h1z = HB(1, 2);
@@ -486,17 +492,17 @@ constexpr int kv_depth() { return sizeof(T) == 8 ? 1 : 2; }
 template <typename T>
 constexpr int kv_kzmax() { return sizeof(T) == 8 ? 24 : 16; }
 
-template <typename T, typename XT, bool P3, bool DOT, bool PM>
+template <typename T, typename XT, int PEN, bool DOT, bool PM>
 __global__ __launch_bounds__(256) void kv_stream(KvArgs<T, XT> A) {
-  kv_body<T, XT, P3, DOT, PM, kv_depth<T>(), kv_kzmax<T>()>(A);
+  kv_body<T, XT, PEN, DOT, PM, kv_depth<T>(), kv_kzmax<T>()>(A);
 }
 
 // Solver variant: skips the whole operator once the solve has finished, so batches of
 // iterations can be enqueued without a host round trip per iteration.
-template <typename T, typename XT, bool P3, bool DOT, bool PM>
+template <typename T, typename XT, int PEN, bool DOT, bool PM>
 __global__ __launch_bounds__(256) void kv_stream_guarded(KvArgs<T, XT> A) {
   if (A.st->done) return;
-  kv_body<T, XT, P3, DOT, PM, kv_depth<T>(), kv_kzmax<T>()>(A);
+  kv_body<T, XT, PEN, DOT, PM, kv_depth<T>(), kv_kzmax<T>()>(A);
 }
 
 // ------------------------------------------------------------------ host side
@@ -509,12 +515,12 @@ struct KvGeom {
 // waste less; but the whole grid runs in ceil(ntiles / resident) rounds of equal blocks,
 // so the chunk count is chosen to minimise rounds * (kz + 2) for the number of blocks
 // the GPU keeps resident (occupancy x CUs).
-static KvGeom kv_geom_for(const tosimp_ctx* c, int resident, int kzmax) {
+static KvGeom kv_geom_for(int nx, int ny, int nz, int resident, int kzmax) {
   KvGeom g;
-  g.tiles_x = (c->nx + 1 + KBX - 2) / (KBX - 1);
-  g.tiles_y = (c->ny + 1 + KBY - 2) / (KBY - 1);
+  g.tiles_x = (nx + 1 + KBX - 2) / (KBX - 1);
+  g.tiles_y = (ny + 1 + KBY - 2) / (KBY - 1);
   const int cols = g.tiles_x * g.tiles_y;
-  const int planes = c->nz + 1;
+  const int planes = nz + 1;
   if (resident < 1) resident = 1;
   double best = 1e300;
   int best_kz = kzmax < planes ? kzmax : planes;
@@ -572,9 +578,9 @@ static int resident_blocks(const tosimp_ctx* c, K kernel) {
   return per_cu * num_cus(c);
 }
 
-template <typename T, typename XT, bool P3, bool DOT, bool PM>
+template <typename T, typename XT, int PEN, bool DOT, bool PM>
 static hipError_t kv_launch_v(const tosimp_ctx* c, KvArgs<T, XT> A, bool guarded) {
-  auto kern = guarded ? kv_stream_guarded<T, XT, P3, DOT, PM> : kv_stream<T, XT, P3, DOT, PM>;
+  auto kern = guarded ? kv_stream_guarded<T, XT, PEN, DOT, PM> : kv_stream<T, XT, PEN, DOT, PM>;
   // Resident blocks per device and kernel instance, computed once (concurrent first calls
   // compute the same value; devices beyond the table are queried every time).
   constexpr int kDevs = 64;
@@ -586,7 +592,7 @@ static hipError_t kv_launch_v(const tosimp_ctx* c, KvArgs<T, XT> A, bool guarded
     res = resident_blocks(c, kern);
     if (cached) resident[c->device][guarded ? 1 : 0].store(res, std::memory_order_relaxed);
   }
-  const KvGeom g = kv_geom_for(c, res, kv_kzmax<T>());
+  const KvGeom g = kv_geom_for(A.nx, A.ny, A.nz, res, kv_kzmax<T>());
   A.tiles_x = g.tiles_x; A.tiles_y = g.tiles_y; A.chunks_z = g.chunks_z; A.kz = g.kz;
   A.ntiles = g.ntiles; A.per_xcd = g.per_xcd;
   if (DOT && g.ntiles > c->ws.kv_part_cap) return hipErrorInvalidValue;  // partial slots
@@ -610,10 +616,10 @@ static hipError_t kv_launch_t(const tosimp_ctx* c, const XT* x, const T* v, T* y
   A.k = kv_consts<T>(c);
   const bool p3 = c->penal == 3.0;
   const bool dot = fin != FIN_NONE;
-  if (p3 && dot) return kv_launch_v<T, XT, true, true, PM>(c, A, guarded);
-  if (p3) return kv_launch_v<T, XT, true, false, PM>(c, A, guarded);
-  if (dot) return kv_launch_v<T, XT, false, true, PM>(c, A, guarded);
-  return kv_launch_v<T, XT, false, false, PM>(c, A, guarded);
+  if (p3 && dot) return kv_launch_v<T, XT, kPenCube, true, PM>(c, A, guarded);
+  if (p3) return kv_launch_v<T, XT, kPenCube, false, PM>(c, A, guarded);
+  if (dot) return kv_launch_v<T, XT, kPenPow, true, PM>(c, A, guarded);
+  return kv_launch_v<T, XT, kPenPow, false, PM>(c, A, guarded);
 }
 
 hipError_t kv_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
@@ -640,10 +646,43 @@ hipError_t kv_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
                                           partials, st, out, fin, guarded);
 }
 
+// Operator on a grid of the multigrid hierarchy: element moduli E given (no SIMP law),
+// element stiffness scaled by kscale (K_E of an element of edge kscale h), fixed DOFs
+// from `mask`, v zero on fixed DOFs.  Same kernel as the fine-grid operator; with st the
+// launch returns at once when the solve has finished (guarded).
+template <typename T>
+static hipError_t kv_level_t(const tosimp_ctx* c, const T* E, const T* v, T* y, int nx,
+                             int ny, int nz, const uint8_t* mask, double kscale,
+                             const SolverState* st) {
+  KvArgs<T, T> A{};
+  A.v = v; A.y = y; A.x = E; A.mask = mask;
+  A.st = const_cast<SolverState*>(st);
+  A.fin = FIN_NONE;
+  A.nx = nx; A.ny = ny; A.nz = nz;
+  A.E0mEmin = T(1); A.Emin = T(0); A.penal = T(1);
+  KvC<T> k;
+  k.ad = (T)(kscale * c->hc.ad); k.ao = (T)(kscale * c->hc.ao);
+  k.cs = (T)(kscale * c->hc.cs); k.bd = (T)(kscale * c->hc.bd);
+  k.bo = (T)(kscale * c->hc.bo); k.cd = (T)(kscale * c->hc.cd);
+  k.co = (T)(kscale * c->hc.co); k.hg = (T)(kscale * c->hc.hg);
+  A.k = k;
+  return kv_launch_v<T, T, kPenModulus, false, true>(c, A, st != nullptr);
+}
+
+hipError_t kv_level_launch(const tosimp_ctx* c, int prec, const void* E, const void* v,
+                           void* y, int nx, int ny, int nz, const uint8_t* mask,
+                           double kscale, const SolverState* st) {
+  if (prec == TOSIMP_PREC_FP64)
+    return kv_level_t<double>(c, (const double*)E, (const double*)v, (double*)y, nx, ny, nz,
+                              mask, kscale, st);
+  return kv_level_t<float>(c, (const float*)E, (const float*)v, (float*)y, nx, ny, nz, mask,
+                           kscale, st);
+}
+
 // ------------------------------------------------------------ Jacobi diagonal
 // Every diagonal entry of K_E is the same value kd, so diag(K)_(n,c) = kd * sum of E
 // over the (at most eight) elements around node n, identical for the three components.
-template <typename XT, bool P3>
+template <typename XT, int PEN>
 __global__ __launch_bounds__(256) void diag_node_kernel(const XT* __restrict__ x, int nx,
                                                         int ny, int nz, double kd,
                                                         double Emin, double E0mEmin,
@@ -666,8 +705,12 @@ __global__ __launch_bounds__(256) void diag_node_kernel(const XT* __restrict__ x
           const int ex = i + dx, ey = j + dy, ez = k + dz;
           if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
           const double xv = (double)x[ex + (int64_t)nx * (ey + (int64_t)ny * ez)];
-          const double xp = P3 ? xv * xv * xv : (xv > 0.0 ? pow(xv, penal) : 0.0);
-          s += Emin + xp * E0mEmin;
+          if (PEN == kPenModulus) {
+            s += xv;
+          } else {
+            const double xp = PEN == kPenCube ? xv * xv * xv : (xv > 0.0 ? pow(xv, penal) : 0.0);
+            s += Emin + xp * E0mEmin;
+          }
         }
     const double d = kd * s;
     if (dinv64) dinv64[n] = 1.0 / d;
@@ -689,11 +732,11 @@ static hipError_t diag_launch(const tosimp_ctx* c, const XT* x, double* dinv64,
   const bool p3 = c->penal == 3.0;
   dim3 grid(2048), block(256);
   if (p3)
-    diag_node_kernel<XT, true><<<grid, block, 0, c->stream>>>(
+    diag_node_kernel<XT, kPenCube><<<grid, block, 0, c->stream>>>(
         x, c->nx, c->ny, c->nz, c->kd, c->Emin, c->E0 - c->Emin, c->penal, dinv64, dinv32,
         dfull, dfull32, c->ws.mask);
   else
-    diag_node_kernel<XT, false><<<grid, block, 0, c->stream>>>(
+    diag_node_kernel<XT, kPenPow><<<grid, block, 0, c->stream>>>(
         x, c->nx, c->ny, c->nz, c->kd, c->Emin, c->E0 - c->Emin, c->penal, dinv64, dinv32,
         dfull, dfull32, c->ws.mask);
   return hipGetLastError();
@@ -706,6 +749,15 @@ hipError_t launch_diag_inv(const tosimp_ctx* c, const double* xphys, double* din
 
 hipError_t launch_diag_inv32(const tosimp_ctx* c, const float* x32, float* dinv32) {
   return diag_launch<float>(c, x32, nullptr, dinv32, nullptr, nullptr);
+}
+
+// Inverse Jacobi diagonal per node of a multigrid level: 1 / (kd kscale sum of E around
+// the node), FP64 and / or FP32 (either may be null).
+hipError_t launch_diag_level(const tosimp_ctx* c, const double* E, int nx, int ny, int nz,
+                             double kscale, double* dinv64, float* dinv32) {
+  diag_node_kernel<double, kPenModulus><<<dim3(2048), dim3(256), 0, c->stream>>>(
+      E, nx, ny, nz, c->kd * kscale, 0.0, 1.0, 1.0, dinv64, dinv32, nullptr, nullptr, nullptr);
+  return hipGetLastError();
 }
 
 hipError_t launch_diag_full(const tosimp_ctx* c, int xdtype, const void* x, int dtype,

@@ -1,0 +1,748 @@
+// Geometric multigrid: a V-cycle preconditioner built on the fused operator, and CG
+// preconditioned by it.
+//
+// Paper: Sec. "Path to Geometric Multigrid Integration" (the fused kernel as the
+// fine-grid smoother, a restriction R and prolongation P = R^T between grids, a direct
+// solve on the coarsest grid).  Design on gfx950:
+//  * Hierarchy: level l + 1 has ceil(n / 2) elements per axis of twice the edge;
+//    coarsening stops once an axis has one element.  Coarse operators are
+//    re-discretised: the element stiffness scales with the edge (kscale = 2^l) and a
+//    coarse element's modulus is the sum of its existing children's moduli over eight.
+//    Every level's operator is the same fused kernel (kv_level_launch, moduli given).
+//  * Boundary conditions: a coarse DOF is fixed when a fine DOF in its interpolation
+//    support is; fixed rows are identity and every V-cycle vector is zero on them.
+//  * Smoother: Chebyshev iteration of degree k on D^-1 K over [lam / alpha, lam] with
+//    lam = lambda_max(K_E) / K_E[0][0], an upper bound of lambda_max(D^-1 K) for any
+//    density field; the same polynomial before and after the coarse correction, so the
+//    V-cycle is symmetric.  The first pre-smoothing step starts from zero and needs no
+//    operator application.
+//  * Transfer: trilinear interpolation P and R = P^T as gathers (each coarse node sums
+//    its <= 27 fine nodes, each fine node its <= 8 coarse nodes): no atomics, fixed
+//    order, deterministic.
+//  * Coarsest level: dense inverse of the assembled constrained operator, computed in
+//    FP64 on the host (Cholesky) once per set-up, applied as a matrix-vector product.
+//  * CG: FP64 reductions and scalars on the device (SolverState), host polls every
+//    check_every iterations; vectors in FP64 (plain mode) or FP32 (refinement inner solve).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "dev.h"
+
+namespace tosimp {
+
+namespace {
+
+constexpr int kMgMaxLevels = 12;
+constexpr int kMgCoarseMax = 1536;  // DOFs of the dense coarsest level
+
+struct MgLevel {
+  int nx = 0, ny = 0, nz = 0;
+  int64_t n_node = 0, n_elem = 0, n_dof = 0;
+  double kscale = 1;
+  double* E64 = nullptr;
+  float* E32 = nullptr;
+  uint8_t* mask = nullptr;  // level 0: the context's mask (not owned)
+  double* dinv64 = nullptr;
+  float* dinv32 = nullptr;
+  void* b = nullptr;   // right-hand side (coarse levels; level 0: the caller's vector)
+  void* x = nullptr;   // iterate (coarse levels; level 0: the caller's vector)
+  void* t = nullptr;   // operator output
+  void* dd = nullptr;  // Chebyshev direction
+};
+
+struct MgState {
+  int nlev = 0;
+  MgLevel L[kMgMaxLevels];
+  int nc = 0;  // coarsest DOFs
+  double* Ainv64 = nullptr;
+  float* Ainv32 = nullptr;
+  double lam = 0;  // lambda_max(K_E) / K_E[0][0]
+};
+
+MgState* mg_of(tosimp_ctx* c) { return (MgState*)c->mg; }
+
+// ------------------------------------------------------------------------ kernels
+template <typename T>
+__global__ __launch_bounds__(256) void simp_modulus_kernel(const double* __restrict__ x,
+                                                           int64_t n, double Emin,
+                                                           double E0mEmin, double penal,
+                                                           double* __restrict__ E64,
+                                                           float* __restrict__ E32) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double xv = x[e];
+    const double xp = penal == 3.0 ? xv * xv * xv : (xv > 0.0 ? pow(xv, penal) : 0.0);
+    const double E = Emin + xp * E0mEmin;
+    E64[e] = E;
+    E32[e] = (float)E;
+  }
+}
+
+// Coarse modulus: (sum of the existing children) / 8.
+__global__ __launch_bounds__(256) void restrict_modulus_kernel(
+    const double* __restrict__ Ef, int fx, int fy, int fz, double* __restrict__ Ec,
+    float* __restrict__ Ec32, int cx, int cy, int cz) {
+  const int64_t n = (int64_t)cx * cy * cz;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int I = (int)(e % cx);
+    const int64_t r = e / cx;
+    const int J = (int)(r % cy), K = (int)(r / cy);
+    double s = 0.0;
+    for (int c = 0; c < 2; ++c)
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) {
+          const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
+          if (i < fx && j < fy && k < fz) s += Ef[i + (int64_t)fx * (j + (int64_t)fy * k)];
+        }
+    const double v = s / 8.0;
+    Ec[e] = v;
+    Ec32[e] = (float)v;
+  }
+}
+
+// Coarse BC byte: OR of the fine BC bytes over the node's interpolation support.
+__global__ __launch_bounds__(256) void coarse_mask_kernel(const uint8_t* __restrict__ mf, int fx,
+                                                          int fy, int fz,
+                                                          uint8_t* __restrict__ mc, int cx,
+                                                          int cy, int cz) {
+  const int CX = cx + 1, CY = cy + 1;
+  const int64_t n = (int64_t)CX * CY * (cz + 1);
+  for (int64_t N = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; N < n;
+       N += (int64_t)gridDim.x * blockDim.x) {
+    const int I = (int)(N % CX);
+    const int64_t r = N / CX;
+    const int J = (int)(r % CY), K = (int)(r / CY);
+    unsigned m = 0;
+    for (int k = max(2 * K - 1, 0); k <= min(2 * K + 1, fz); ++k)
+      for (int j = max(2 * J - 1, 0); j <= min(2 * J + 1, fy); ++j)
+        for (int i = max(2 * I - 1, 0); i <= min(2 * I + 1, fx); ++i)
+          m |= mf[i + (int64_t)(fx + 1) * (j + (int64_t)(fy + 1) * k)];
+    mc[N] = (uint8_t)m;
+  }
+}
+
+// Chebyshev step.  FIRST_ZERO: first step from a zero iterate (r = b): x = dd = c2 b dinv.
+// FIRST: first step from x (r = b - t): dd = c2 r dinv; x += dd.  Otherwise
+// dd = c1 dd + c2 r dinv; x += dd.  Fixed DOFs stay zero (b and t vanish there).
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void cheb_kernel(const T* __restrict__ b,
+                                                   const T* __restrict__ t, T* __restrict__ x,
+                                                   T* __restrict__ dd,
+                                                   const T* __restrict__ dinv, T c1, T c2,
+                                                   int64_t n_dof, const SolverState* st) {
+  if (st && st->done) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_dof;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T di = dinv[i / 3];
+    if (MODE == 0) {
+      const T d = c2 * (b[i] * di);
+      dd[i] = d;
+      x[i] = d;
+    } else {
+      const T r = b[i] - t[i];
+      const T d = MODE == 1 ? c2 * (r * di) : c1 * dd[i] + c2 * (r * di);
+      dd[i] = d;
+      x[i] += d;
+    }
+  }
+}
+
+// bc = P^T (b - t) on the coarse grid, zero on fixed coarse DOFs.  Fine nodes of the
+// support in index order (k, j, i), weights 1 (even offset) / 1/2 (odd) per axis.
+template <typename T>
+__global__ __launch_bounds__(256) void restrict_residual_kernel(
+    const T* __restrict__ bf, const T* __restrict__ tf, int fx, int fy, int fz,
+    T* __restrict__ bc, const uint8_t* __restrict__ mc, int cx, int cy, int cz,
+    const SolverState* st) {
+  if (st && st->done) return;
+  const int CX = cx + 1, CY = cy + 1;
+  const int64_t n = (int64_t)CX * CY * (cz + 1);
+  for (int64_t N = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; N < n;
+       N += (int64_t)gridDim.x * blockDim.x) {
+    const int I = (int)(N % CX);
+    const int64_t r = N / CX;
+    const int J = (int)(r % CY), K = (int)(r / CY);
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+    for (int k = max(2 * K - 1, 0); k <= min(2 * K + 1, fz); ++k) {
+      const T wk = k == 2 * K ? T(1) : T(0.5);
+      for (int j = max(2 * J - 1, 0); j <= min(2 * J + 1, fy); ++j) {
+        const T wj = j == 2 * J ? T(1) : T(0.5);
+        for (int i = max(2 * I - 1, 0); i <= min(2 * I + 1, fx); ++i) {
+          const T w = (i == 2 * I ? T(1) : T(0.5)) * wj * wk;
+          const int64_t f = 3 * (i + (int64_t)(fx + 1) * (j + (int64_t)(fy + 1) * k));
+          s0 += w * (bf[f] - tf[f]);
+          s1 += w * (bf[f + 1] - tf[f + 1]);
+          s2 += w * (bf[f + 2] - tf[f + 2]);
+        }
+      }
+    }
+    const unsigned m = mc[N];
+    bc[3 * N] = (m & 1) ? T(0) : s0;
+    bc[3 * N + 1] = (m & 2) ? T(0) : s1;
+    bc[3 * N + 2] = (m & 4) ? T(0) : s2;
+  }
+}
+
+// xf += P xc on free fine DOFs.
+template <typename T>
+__global__ __launch_bounds__(256) void prolong_add_kernel(
+    T* __restrict__ xf, const uint8_t* __restrict__ mf, int fx, int fy, int fz,
+    const T* __restrict__ xc, int cx, int cy, int cz, const SolverState* st) {
+  if (st && st->done) return;
+  const int FX = fx + 1, FY = fy + 1, CX = cx + 1, CY = cy + 1;
+  const int64_t n = (int64_t)FX * FY * (fz + 1);
+  for (int64_t nf = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; nf < n;
+       nf += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(nf % FX);
+    const int64_t r = nf / FX;
+    const int j = (int)(r % FY), k = (int)(r / FY);
+    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1;
+    const int k0 = k >> 1, k1 = (k + 1) >> 1;
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+    for (int K = k0; K <= k1; ++K) {
+      const T wk = k0 == k1 ? T(1) : T(0.5);
+      for (int J = j0; J <= j1; ++J) {
+        const T wj = j0 == j1 ? T(1) : T(0.5);
+        for (int I = i0; I <= i1; ++I) {
+          const T w = (i0 == i1 ? T(1) : T(0.5)) * wj * wk;
+          const int64_t c = 3 * (I + (int64_t)CX * (J + (int64_t)CY * K));
+          s0 += w * xc[c];
+          s1 += w * xc[c + 1];
+          s2 += w * xc[c + 2];
+        }
+      }
+    }
+    const unsigned m = mf[nf];
+    if (!(m & 1)) xf[3 * nf] += s0;
+    if (!(m & 2)) xf[3 * nf + 1] += s1;
+    if (!(m & 4)) xf[3 * nf + 2] += s2;
+  }
+}
+
+// x = Ainv b on the coarsest level: one wave per row, FP64 accumulation, fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void dense_solve_kernel(const T* __restrict__ Ainv,
+                                                          const T* __restrict__ b,
+                                                          T* __restrict__ x, int n,
+                                                          const SolverState* st) {
+  if (st && st->done) return;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += (double)Ainv[(int64_t)row * n + j] * (double)b[j];
+  s = wave_sum(s);
+  if (lane == 0) x[row] = (T)s;
+}
+
+// ------------------------------------------------------------- CG kernels (device state)
+// r = b - Ku (Ku may be null: zero initial iterate), zero on fixed DOFs; sums of
+// ||r||^2 and ||b||^2.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void mgcg_init_kernel(
+    const T* __restrict__ b, const T* __restrict__ Ku, T* __restrict__ r,
+    const uint8_t* __restrict__ mask, int64_t n_dof, double* partials) {
+  __shared__ double sred[kRedThreads / 64];
+  double rr = 0.0, bb = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n_dof;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const bool fixed = (mask[i / 3] >> (int)(i % 3)) & 1;
+    const T bv = fixed ? T(0) : b[i];
+    const T rv = fixed ? T(0) : (Ku ? bv - Ku[i] : bv);
+    r[i] = rv;
+    rr += (double)rv * (double)rv;
+    bb += (double)bv * (double)bv;
+  }
+  const double v[2] = {rr, bb};
+  store_block_sums<2>(v, partials, sred);
+}
+
+struct MgInitFin {
+  SolverState* st;
+  __device__ void operator()(const double* t) const {
+    const double RR = t[0], BB = t[1];
+    st->rr = RR;
+    st->bb = BB;
+    st->tol2 = st->aux * BB;  // aux holds tol^2 on entry
+    st->iter = 0;
+    st->rz = 0.0;
+    st->done = (BB == 0.0 || RR <= st->tol2) ? 1 : 0;
+    if (!finite_val(RR)) st->done = 3;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void dot_rz_kernel(const T* __restrict__ r,
+                                                             const T* __restrict__ z,
+                                                             int64_t n, const SolverState* st,
+                                                             double* partials) {
+  __shared__ double sred[kRedThreads / 64];
+  if (st->done) return;
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads)
+    s += (double)r[i] * (double)z[i];
+  const double v[1] = {s};
+  store_block_sums<1>(v, partials, sred);
+}
+
+struct MgRzFin {
+  SolverState* st;
+  __device__ void operator()(const double* t) const {
+    if (st->done) return;
+    const double RZ = t[0];
+    st->beta = st->iter == 0 ? 0.0 : RZ / st->rz;
+    st->rz = RZ;
+    if (!finite_val(RZ) || !(RZ > 0.0)) st->done = 3;  // the V-cycle is SPD: <r, z> > 0
+  }
+};
+
+// p = z (first iteration) or z + beta p.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void mg_direction_kernel(const T* __restrict__ z,
+                                                                   T* __restrict__ p, int64_t n,
+                                                                   const SolverState* st) {
+  if (st->done) return;
+  const bool first = st->iter == 0;
+  const T beta = (T)st->beta;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads)
+    p[i] = first ? z[i] : z[i] + beta * p[i];
+}
+
+// u += alpha p, r -= alpha q; sums of ||r||^2.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void mg_update_kernel(
+    T* __restrict__ u, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
+    int64_t n, const SolverState* st, double* partials) {
+  __shared__ double sred[kRedThreads / 64];
+  if (st->done) return;
+  const T alpha = (T)st->alpha;
+  double rr = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    u[i] += alpha * p[i];
+    const T rn = r[i] - alpha * q[i];
+    r[i] = rn;
+    rr += (double)rn * (double)rn;
+  }
+  const double v[1] = {rr};
+  store_block_sums<1>(v, partials, sred);
+}
+
+struct MgUpdateFin {
+  SolverState* st;
+  __device__ void operator()(const double* t) const {
+    if (st->done) return;
+    const double RR = t[0];
+    st->iter += 1;
+    st->rr = RR;
+    if (!finite_val(RR)) st->done = 3;
+    else if (RR <= st->tol2) st->done = 1;
+    else if (st->iter >= st->maxit) st->done = 2;
+  }
+};
+
+int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(2048, (n + 255) / 256)); }
+
+// ------------------------------------------------------------------------ host side
+// Largest eigenvalue of a symmetric n x n matrix (cyclic Jacobi rotations).
+double sym_lambda_max(std::vector<double> a, int n) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += a[p * n + q] * a[p * n + q];
+    if (off < 1e-30) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double th = 0.5 * (a[q * n + q] - a[p * n + p]) / apq;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = a[k * n + p], akq = a[k * n + q];
+          a[k * n + p] = c * akp - s * akq;
+          a[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = a[p * n + k], aqk = a[q * n + k];
+          a[p * n + k] = c * apk - s * aqk;
+          a[q * n + k] = s * apk + c * aqk;
+        }
+      }
+  }
+  double m = a[0];
+  for (int i = 1; i < n; ++i) m = std::max(m, a[i * n + i]);
+  return m;
+}
+
+// Dense constrained stiffness of a small level (host, FP64), element stiffness K_E
+// scaled by kscale, fixed rows and columns replaced by identity.
+void assemble_dense(const tosimp_ctx* c, int nx, int ny, int nz, double kscale,
+                    const std::vector<double>& E, const std::vector<uint8_t>& mask,
+                    std::vector<double>& A) {
+  const int NX = nx + 1, NY = ny + 1;
+  const int nd = 3 * NX * NY * (nz + 1);
+  A.assign((size_t)nd * nd, 0.0);
+  for (int ez = 0; ez < nz; ++ez)
+    for (int ey = 0; ey < ny; ++ey)
+      for (int ex = 0; ex < nx; ++ex) {
+        const double Ee = E[ex + nx * (ey + ny * ez)] * kscale;
+        int dof[24];
+        for (int a = 0; a < 8; ++a) {
+          const int node = (ex + (a & 1)) + NX * ((ey + ((a >> 1) & 1)) + NY * (ez + ((a >> 2) & 1)));
+          for (int cc = 0; cc < 3; ++cc) dof[3 * a + cc] = 3 * node + cc;
+        }
+        for (int i = 0; i < 24; ++i)
+          for (int j = 0; j < 24; ++j) A[(size_t)dof[i] * nd + dof[j]] += Ee * c->KE[i * 24 + j];
+      }
+  for (int d = 0; d < nd; ++d)
+    if ((mask[d / 3] >> (d % 3)) & 1) {
+      for (int j = 0; j < nd; ++j) {
+        A[(size_t)d * nd + j] = 0.0;
+        A[(size_t)j * nd + d] = 0.0;
+      }
+      A[(size_t)d * nd + d] = 1.0;
+    }
+}
+
+// Inverse of an SPD matrix by Cholesky (host, FP64); false if not positive definite.
+bool spd_inverse(std::vector<double>& A, int n) {
+  std::vector<double> L((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double s = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(s > 0.0)) return false;
+    const double d = std::sqrt(s);
+    L[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = t / d;
+    }
+  }
+  // columns of A^-1: solve L L^T x = e_j
+  std::vector<double> y(n);
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) {
+      double t = i == j ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) t -= L[(size_t)i * n + k] * y[k];
+      y[i] = t / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double t = y[i];
+      for (int k = i + 1; k < n; ++k) t -= L[(size_t)k * n + i] * y[k];
+      y[i] = t / L[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) A[(size_t)i * n + j] = y[i];
+  }
+  return true;
+}
+
+hipError_t mg_alloc(void** p, size_t bytes) { return hipMalloc(p, bytes < 256 ? 256 : bytes); }
+
+// Builds the level geometry and allocates every buffer (once per mesh).
+int mg_create_impl(tosimp_ctx* ctx);
+int mg_create(tosimp_ctx* ctx) {
+  if (ctx->mg) return TOSIMP_OK;
+  const int rc = mg_create_impl(ctx);
+  if (rc) mg_release(ctx);  // no half-built hierarchy survives a failure
+  return rc;
+}
+int mg_create_impl(tosimp_ctx* ctx) {
+  MgState* M = new (std::nothrow) MgState();
+  if (!M) return tosimp_fail(ctx, TOSIMP_ENOMEM, "multigrid state");
+  ctx->mg = M;
+  int nx = ctx->nx, ny = ctx->ny, nz = ctx->nz;
+  double ks = ctx->h;
+  for (;;) {
+    MgLevel& L = M->L[M->nlev];
+    L.nx = nx; L.ny = ny; L.nz = nz;
+    L.n_node = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    L.n_elem = (int64_t)nx * ny * nz;
+    L.n_dof = 3 * L.n_node;
+    L.kscale = ks / ctx->h;  // relative to the fine element (the constants hold h)
+    ++M->nlev;
+    if (std::min(nx, std::min(ny, nz)) < 2 || M->nlev == kMgMaxLevels) break;
+    nx = (nx + 1) / 2; ny = (ny + 1) / 2; nz = (nz + 1) / 2;
+    ks *= 2.0;
+  }
+  MgLevel& C = M->L[M->nlev - 1];
+  if (M->nlev < 2 || C.n_dof > kMgCoarseMax)
+    return tosimp_fail(ctx, TOSIMP_EINVAL,
+                       "multigrid: the coarsest grid of this mesh has " +
+                           std::to_string(C.n_dof) + " DOFs (at most " +
+                           std::to_string(kMgCoarseMax) + " and two levels are needed)");
+  M->nc = (int)C.n_dof;
+  for (int l = 0; l < M->nlev; ++l) {
+    MgLevel& L = M->L[l];
+    const size_t nd = (size_t)L.n_dof, ne = (size_t)L.n_elem, nn = (size_t)L.n_node;
+    TOSIMP_HIP(ctx, mg_alloc((void**)&L.E64, ne * 8));
+    TOSIMP_HIP(ctx, mg_alloc((void**)&L.E32, ne * 4));
+    TOSIMP_HIP(ctx, mg_alloc((void**)&L.dinv64, nn * 8));
+    TOSIMP_HIP(ctx, mg_alloc((void**)&L.dinv32, nn * 4));
+    if (l > 0) {
+      TOSIMP_HIP(ctx, mg_alloc((void**)&L.mask, nn));
+      TOSIMP_HIP(ctx, mg_alloc(&L.b, nd * 8));
+      TOSIMP_HIP(ctx, mg_alloc(&L.x, nd * 8));
+    } else {
+      L.mask = ctx->ws.mask;
+    }
+    TOSIMP_HIP(ctx, mg_alloc(&L.t, nd * 8));
+    TOSIMP_HIP(ctx, mg_alloc(&L.dd, nd * 8));
+  }
+  TOSIMP_HIP(ctx, mg_alloc((void**)&M->Ainv64, (size_t)M->nc * M->nc * 8));
+  TOSIMP_HIP(ctx, mg_alloc((void**)&M->Ainv32, (size_t)M->nc * M->nc * 4));
+  std::vector<double> ke(ctx->KE, ctx->KE + 576);
+  M->lam = sym_lambda_max(ke, 24) / ctx->KE[0];
+  return TOSIMP_OK;
+}
+
+// Moduli, masks and diagonals of every level and the coarsest inverse for density x.
+int mg_setup(tosimp_ctx* ctx, const double* x) {
+  int rc = mg_create(ctx);
+  if (rc) return rc;
+  MgState* M = mg_of(ctx);
+  MgLevel& F = M->L[0];
+  simp_modulus_kernel<double><<<grid_for(F.n_elem), 256, 0, ctx->stream>>>(
+      x, F.n_elem, ctx->Emin, ctx->E0 - ctx->Emin, ctx->penal, F.E64, F.E32);
+  TOSIMP_HIP(ctx, hipGetLastError());
+  for (int l = 1; l < M->nlev; ++l) {
+    MgLevel &P = M->L[l - 1], &L = M->L[l];
+    restrict_modulus_kernel<<<grid_for(L.n_elem), 256, 0, ctx->stream>>>(
+        P.E64, P.nx, P.ny, P.nz, L.E64, L.E32, L.nx, L.ny, L.nz);
+    coarse_mask_kernel<<<grid_for(L.n_node), 256, 0, ctx->stream>>>(P.mask, P.nx, P.ny, P.nz,
+                                                                    L.mask, L.nx, L.ny, L.nz);
+    TOSIMP_HIP(ctx, hipGetLastError());
+  }
+  for (int l = 0; l < M->nlev; ++l) {
+    MgLevel& L = M->L[l];
+    TOSIMP_HIP(ctx, launch_diag_level(ctx, L.E64, L.nx, L.ny, L.nz, L.kscale, L.dinv64, L.dinv32));
+  }
+  // coarsest: dense constrained operator, inverted on the host
+  MgLevel& C = M->L[M->nlev - 1];
+  std::vector<double> E((size_t)C.n_elem);
+  std::vector<uint8_t> mask((size_t)C.n_node);
+  TOSIMP_HIP(ctx, hipMemcpyAsync(E.data(), C.E64, E.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+  TOSIMP_HIP(ctx, hipMemcpyAsync(mask.data(), C.mask, mask.size(), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  std::vector<double> A;
+  assemble_dense(ctx, C.nx, C.ny, C.nz, C.kscale, E, mask, A);
+  if (!spd_inverse(A, M->nc))
+    return tosimp_fail(ctx, TOSIMP_EBREAKDOWN, "multigrid: coarsest operator not positive definite");
+  std::vector<float> A32(A.size());
+  for (size_t i = 0; i < A.size(); ++i) A32[i] = (float)A[i];
+  TOSIMP_HIP(ctx, hipMemcpyAsync(M->Ainv64, A.data(), A.size() * 8, hipMemcpyHostToDevice,
+                                 ctx->stream));
+  TOSIMP_HIP(ctx, hipMemcpyAsync(M->Ainv32, A32.data(), A32.size() * 4, hipMemcpyHostToDevice,
+                                 ctx->stream));
+  TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // host vectors leave scope
+  return TOSIMP_OK;
+}
+
+// Chebyshev coefficients: step 1 uses c2 = 1 / theta; step k >= 2 c1 = rho' rho,
+// c2 = 2 rho' / delta with rho' = 1 / (2 sigma - rho).
+struct ChebCoef {
+  double c1[16], c2[16];
+};
+ChebCoef cheb_coef(double lam, double alpha, int degree) {
+  ChebCoef k{};
+  const double lo = lam / alpha, hi = lam;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  k.c1[0] = 0.0;
+  k.c2[0] = 1.0 / theta;
+  for (int s = 1; s < degree; ++s) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    k.c1[s] = rn * rho;
+    k.c2[s] = 2.0 * rn / delta;
+    rho = rn;
+  }
+  return k;
+}
+
+template <typename T>
+const T* lev_E(const MgLevel& L) {
+  if constexpr (sizeof(T) == 8) return (const T*)L.E64; else return (const T*)L.E32;
+}
+template <typename T>
+const T* lev_dinv(const MgLevel& L) {
+  if constexpr (sizeof(T) == 8) return (const T*)L.dinv64; else return (const T*)L.dinv32;
+}
+
+// One V-cycle from level l: x_l ~ K_l^-1 b_l (x_l overwritten).
+template <typename T>
+int vcycle(tosimp_ctx* ctx, MgState* M, int l, const ChebCoef& K, int degree,
+           const SolverState* st) {
+  constexpr int prec = sizeof(T) == 8 ? TOSIMP_PREC_FP64 : TOSIMP_PREC_FP32;
+  MgLevel& L = M->L[l];
+  T *b = (T*)L.b, *x = (T*)L.x, *t = (T*)L.t, *dd = (T*)L.dd;
+  const int nd = (int)L.n_dof;
+  const int g = grid_for(L.n_dof);
+  if (l == M->nlev - 1) {
+    const T* Ainv;
+    if constexpr (sizeof(T) == 8) Ainv = (const T*)M->Ainv64; else Ainv = (const T*)M->Ainv32;
+    dense_solve_kernel<T><<<(M->nc + 3) / 4, 256, 0, ctx->stream>>>(Ainv, b, x, M->nc, st);
+    TOSIMP_HIP(ctx, hipGetLastError());
+    return TOSIMP_OK;
+  }
+  const T* E = lev_E<T>(L);
+  const T* dinv = lev_dinv<T>(L);
+  auto Kx = [&]() -> hipError_t {
+    return kv_level_launch(ctx, prec, E, x, t, L.nx, L.ny, L.nz, L.mask, L.kscale, st);
+  };
+  // pre-smoothing from zero
+  cheb_kernel<T, 0><<<g, 256, 0, ctx->stream>>>(b, nullptr, x, dd, dinv, T(0), (T)K.c2[0], nd, st);
+  for (int s = 1; s < degree; ++s) {
+    TOSIMP_HIP(ctx, Kx());
+    cheb_kernel<T, 2><<<g, 256, 0, ctx->stream>>>(b, t, x, dd, dinv, (T)K.c1[s], (T)K.c2[s], nd, st);
+  }
+  // coarse-grid correction
+  TOSIMP_HIP(ctx, Kx());
+  MgLevel& Cn = M->L[l + 1];
+  restrict_residual_kernel<T><<<grid_for(Cn.n_node), 256, 0, ctx->stream>>>(
+      b, t, L.nx, L.ny, L.nz, (T*)Cn.b, Cn.mask, Cn.nx, Cn.ny, Cn.nz, st);
+  TOSIMP_HIP(ctx, hipGetLastError());
+  int rc = vcycle<T>(ctx, M, l + 1, K, degree, st);
+  if (rc) return rc;
+  prolong_add_kernel<T><<<grid_for(L.n_node), 256, 0, ctx->stream>>>(
+      x, L.mask, L.nx, L.ny, L.nz, (const T*)Cn.x, Cn.nx, Cn.ny, Cn.nz, st);
+  TOSIMP_HIP(ctx, hipGetLastError());
+  // post-smoothing from x (same polynomial)
+  TOSIMP_HIP(ctx, Kx());
+  cheb_kernel<T, 1><<<g, 256, 0, ctx->stream>>>(b, t, x, dd, dinv, T(0), (T)K.c2[0], nd, st);
+  for (int s = 1; s < degree; ++s) {
+    TOSIMP_HIP(ctx, Kx());
+    cheb_kernel<T, 2><<<g, 256, 0, ctx->stream>>>(b, t, x, dd, dinv, (T)K.c1[s], (T)K.c2[s], nd, st);
+  }
+  TOSIMP_HIP(ctx, hipGetLastError());
+  return TOSIMP_OK;
+}
+
+int check_degree_alpha(tosimp_ctx* ctx, int* degree, double* alpha) {
+  if (*degree == 0) *degree = 2;
+  if (*alpha == 0) *alpha = 20.0;
+  if (*degree < 1 || *degree > 16 || !(*alpha > 1.0) || !std::isfinite(*alpha))
+    return tosimp_fail(ctx, TOSIMP_EINVAL, "multigrid: degree 1..16 and alpha > 1 needed");
+  return TOSIMP_OK;
+}
+
+}  // namespace
+
+// z = V(r) on the fine level (set-up must be current).
+template <typename T>
+int mg_apply(tosimp_ctx* ctx, const T* r, T* z, int degree, double alpha, const SolverState* st) {
+  MgState* M = mg_of(ctx);
+  M->L[0].b = const_cast<T*>(r);
+  M->L[0].x = z;
+  const ChebCoef K = cheb_coef(M->lam, alpha, degree);
+  const int rc = vcycle<T>(ctx, M, 0, K, degree, st);
+  M->L[0].b = M->L[0].x = nullptr;
+  return rc;
+}
+
+// CG on K_c(x) u = b preconditioned by one V-cycle per iteration (set-up done by the
+// caller).  r, z, p, q: n_dof work vectors of T.  x: element values of the operator's
+// type (FP64 densities for T = double, the FP32 copy for T = float).
+template <typename T>
+int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T* q,
+           int slot, double tol, int maxit, int check_every, bool zero_guess, int degree,
+           double alpha, MgPcgResult* res) {
+  constexpr int prec = sizeof(T) == 8 ? TOSIMP_PREC_FP64 : TOSIMP_PREC_FP32;
+  constexpr int xdt = sizeof(T) == 8 ? TOSIMP_F64 : TOSIMP_F32;
+  Workspace& w = ctx->ws;
+  SolverState* st = w.st + slot;
+  SolverState* sh = w.st_host + slot;
+  *sh = SolverState{};
+  sh->aux = tol * tol;
+  sh->maxit = maxit < 1 ? 1 : maxit;
+  TOSIMP_HIP(ctx, hipMemcpyAsync(st, sh, sizeof(SolverState), hipMemcpyHostToDevice, ctx->stream));
+  double* part = w.partials;
+  double* kvpart = w.partials + 2 * kMaxPartials;
+  const int64_t n = ctx->n_dof;
+  if (zero_guess) {
+    TOSIMP_HIP(ctx, launch_fill_zero(ctx, u, n * (int64_t)sizeof(T)));
+    mgcg_init_kernel<T><<<kRedBlocks, kRedThreads, 0, ctx->stream>>>(b, nullptr, r, w.mask, n, part);
+  } else {
+    TOSIMP_HIP(ctx, kv_launch(ctx, prec, xdt, x, u, q, nullptr, st, nullptr, 0, false, true));
+    mgcg_init_kernel<T><<<kRedBlocks, kRedThreads, 0, ctx->stream>>>(b, q, r, w.mask, n, part);
+  }
+  TOSIMP_HIP(ctx, launch_finalize_sum<2>(ctx->stream, part, kRedBlocks, MgInitFin{st}));
+  if (check_every < 1) check_every = 1;
+  const int g = grid_for(n);
+  for (;;) {
+    TOSIMP_HIP(ctx, hipMemcpyAsync(sh, st, sizeof(SolverState), hipMemcpyDeviceToHost, ctx->stream));
+    TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (sh->done) break;
+    for (int i = 0; i < check_every; ++i) {
+      int rc = mg_apply<T>(ctx, r, z, degree, alpha, st);
+      if (rc) return rc;
+      dot_rz_kernel<T><<<g, kRedThreads, 0, ctx->stream>>>(r, z, n, st, part);
+      TOSIMP_HIP(ctx, launch_finalize_sum<1>(ctx->stream, part, g, MgRzFin{st}));
+      mg_direction_kernel<T><<<g, kRedThreads, 0, ctx->stream>>>(z, p, n, st);
+      TOSIMP_HIP(ctx, kv_launch(ctx, prec, xdt, x, p, q, kvpart, st, nullptr, 1, true, true));
+      mg_update_kernel<T><<<g, kRedThreads, 0, ctx->stream>>>(u, r, p, q, n, st, part);
+      TOSIMP_HIP(ctx, launch_finalize_sum<1>(ctx->stream, part, g, MgUpdateFin{st}));
+    }
+  }
+  res->iters = sh->iter;
+  res->done = sh->done;
+  res->rr = sh->rr;
+  res->bb = sh->bb;
+  return TOSIMP_OK;
+}
+
+template int mg_apply<double>(tosimp_ctx*, const double*, double*, int, double, const SolverState*);
+template int mg_apply<float>(tosimp_ctx*, const float*, float*, int, double, const SolverState*);
+template int mg_pcg<double>(tosimp_ctx*, const void*, const double*, double*, double*, double*,
+                            double*, double*, int, double, int, int, bool, int, double,
+                            MgPcgResult*);
+template int mg_pcg<float>(tosimp_ctx*, const void*, const float*, float*, float*, float*,
+                           float*, float*, int, double, int, int, bool, int, double,
+                           MgPcgResult*);
+
+int mg_prepare(tosimp_ctx* ctx, const double* x, int* degree, double* alpha) {
+  int rc = check_degree_alpha(ctx, degree, alpha);
+  if (rc) return rc;
+  return mg_setup(ctx, x);
+}
+
+int mg_levels(tosimp_ctx* ctx, int* dims, int cap) {
+  int rc = mg_create(ctx);
+  if (rc) return rc;
+  MgState* M = mg_of(ctx);
+  for (int l = 0; l < M->nlev && l < cap; ++l) {
+    dims[3 * l] = M->L[l].nx;
+    dims[3 * l + 1] = M->L[l].ny;
+    dims[3 * l + 2] = M->L[l].nz;
+  }
+  return M->nlev;
+}
+
+void mg_release(tosimp_ctx* ctx) {
+  MgState* M = ctx ? mg_of(ctx) : nullptr;
+  if (!M) return;
+  for (int l = 0; l < M->nlev; ++l) {
+    MgLevel& L = M->L[l];
+    void* ps[] = {L.E64, L.E32, L.dinv64, L.dinv32, L.t, L.dd};
+    for (void* p : ps)
+      if (p) (void)hipFree(p);
+    if (l > 0) {
+      if (L.mask) (void)hipFree(L.mask);
+      if (L.b) (void)hipFree(L.b);
+      if (L.x) (void)hipFree(L.x);
+    }
+  }
+  if (M->Ainv64) (void)hipFree(M->Ainv64);
+  if (M->Ainv32) (void)hipFree(M->Ainv32);
+  delete M;
+  ctx->mg = nullptr;
+}
+
+}  // namespace tosimp
