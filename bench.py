@@ -40,13 +40,13 @@ HBM_PEAK_GBS = 8000.0
 # valid only for the kernel sources they were taken with (sha256 of kv.hip, dev.h,
 # common.h); reported as null once those change.
 KV_TRAFFIC = {
-    "fp32": (2.0 * 49121.5 + 59237.0) * 1024,
-    "fp64": (2.0 * 94562.9 + 118117.0) * 1024,
+    "fp32": (2.0 * 49076.1 + 59118.0) * 1024,
+    "fp64": (2.0 * 94457.4 + 118070.1) * 1024,
 }
 KV_TRAFFIC_SOURCES = {
-    "kv.hip": "b997b4519ff1929ca674a395eed60a690f3b07fdc361d552c77a7f7902184c22",
+    "kv.hip": "7f5bee66ad024f9c6ec5db9f16379d19d0208163de17f5a69eb4146aeb0a8a6f",
     "dev.h": "914e569c6016d8856a85207550abda3abeb3299f20de5017738d7e883af47280",
-    "common.h": "8e6881f18d94e4f7dfdc2b633ca224dff98cba74af3245bd4494e9b4733b8bc9",
+    "common.h": "e885e249916ffef45216d1150dea48af681037008edba1c03b4bad268ed6845b",
 }
 
 
@@ -91,25 +91,28 @@ def time_kv(t, nx, ny, nz, prec, steps, warmup, fixed, seed=42, resident=False):
     for i in range(warmup):
         t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec, v_zero_on_fixed=True)
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
-    t0 = time.perf_counter()
-    for i in range(steps):
-        ev[2 * i].record(stream)
-        t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec, v_zero_on_fixed=True)
-        ev[2 * i + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launch_ms = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)]
-    avg_ms = float(np.mean(launch_ms))
-    # the same launches back to back without per-launch events (includes launch gaps)
+    stream = torch.cuda.current_stream()  # the library launches on the caller's stream
+    # Timed region: `steps` launches back to back, bracketed by synchronisations (wall
+    # clock) and by HIP events on the launch stream (average launch duration, gaps
+    # included).
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
     e0.record(stream)
     for i in range(steps):
         t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec, v_zero_on_fixed=True)
     e1.record(stream)
     torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     batch_ms = e0.elapsed_time(e1) / steps
+    # Per-launch events (diagnostic: each launch's own duration incl. its event overhead).
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+    for i in range(steps):
+        ev[2 * i].record(stream)
+        t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec, v_zero_on_fixed=True)
+        ev[2 * i + 1].record(stream)
+    torch.cuda.synchronize()
+    launch_ms = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)]
+    avg_ms = float(np.mean(launch_ms))
     ok = bool(torch.isfinite(ys[(steps - 1) % nset]).all())
     del xs, vs, ys
     torch.cuda.empty_cache()
@@ -130,8 +133,8 @@ def _solve_timed(t, x, f, tol, **kw):
     c = float(torch.dot(f, u))
     return u, dict(seconds=sec, iterations=st["iterations"],
                    outer_iterations=st["outer_iterations"], fallbacks=st["fallbacks"],
-                   status=st["status"], true_rel_residual=st["true_rel_residual"],
-                   compliance=c)
+                   restarts=st["restarts"], status=st["status"],
+                   true_rel_residual=st["true_rel_residual"], compliance=c)
 
 
 def time_pcg(t, nx, ny, nz, tol, volfrac=0.3):
@@ -358,7 +361,7 @@ def kv_study(workloads=("cantilever_120x60x30", "cantilever_340x170x85")):
             res[p] = {}
             for label, resident in (("hbm", False), ("mall_resident", True)):
                 r = time_kv(t, nx, ny, nz, p, reps, 10, fixed, resident=resident)
-                us = r["avg_launch_ms"] * 1e3
+                us = r["batch_ms"] * 1e3
                 res[p][label] = {"avg_launch_us": us, "median_launch_us": r["median_launch_ms"] * 1e3,
                                  "gdof_s": t.n_dof / (us * 1e-6) / 1e9,
                                  "algorithmic_gbs": r["bytes"] / (us * 1e-6) / 1e9,
@@ -413,20 +416,36 @@ def pcg_cold_study(workloads=("cantilever_120x60x30", "torsion_55x55x165",
     return out
 
 
-def cpu_baseline(budget_s=20.0):
-    """The oracle's element-by-element K v (gather, dense 24x24 product, scatter-add)
-    on the 120x60x30 mesh, repeated until ~budget_s of CPU time."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workload="cantilever_340x170x85", kv_budget_s=10.0, pcg_iters=3,
+                 pcg_iterations_to_tol=None):
+    """The oracle on the host: its element-by-element K v (gather, dense 24x24 product,
+    scatter-add) on the workload's mesh, repeated for ~kv_budget_s, and a few iterations
+    of its Jacobi-PCG (same operator) on the workload's cold-start system (uniform
+    density 0.3), whose time per iteration times the iterations the FP64 solve takes to
+    1e-6 (pcg_iterations_to_tol, when given) estimates its time to 1e-6."""
     import numpy as np
 
     import synth_inputs as si
-    from oracle import fem
+    from oracle import fem, solvers
 
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = 1
-    nx, ny, nz = 120, 60, 30
+    cfg = si.CONFIGS[workload]
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
     rho, v = si.random_density_and_vector(nx, ny, nz, 42)
     KE = fem.element_stiffness(0.3)
     E = fem.simp_modulus(rho, 1.0, 1e-9, 3.0)
@@ -436,12 +455,27 @@ def cpu_baseline(budget_s=20.0):
         fem.apply_K_elementwise(nx, ny, nz, E, KE, v, fixed)
         calls += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or calls >= 50:
+        if el >= kv_budget_s:
             break
-    return {"value": calls * v.size / el / 1e9, "unit": "GDOF/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"oracle element-by-element K v on the 120x60x30 cantilever "
-                      f"({v.size} DOFs), {calls} calls in {el:.1f} s"}
+    # Jacobi-PCG: a bounded number of iterations on the cold-start system
+    E3 = fem.simp_modulus(np.full(nx * ny * nz, 0.3), 1.0, 1e-9, 3.0)
+    f = si.cantilever_load(nx, ny, nz)
+    d = fem.diag_K(nx, ny, nz, E3, KE, fixed)
+    t1 = time.perf_counter()
+    _, its, _ = solvers.pcg_jacobi(lambda x: fem.apply_K_elementwise(nx, ny, nz, E3, KE, x, fixed),
+                                   d, f, tol=1e-6, maxit=pcg_iters)
+    per_it = (time.perf_counter() - t1) / max(its, 1)
+    out = {"value": calls * v.size / el / 1e9, "unit": "GDOF/s", "cores": int(threads),
+           "kind": "oracle",
+           "sample": f"oracle element-by-element K v on {workload} ({v.size} DOFs), {calls} "
+                     f"calls in {el:.1f} s; {its} oracle Jacobi-PCG iterations on its "
+                     f"cold-start system (uniform density 0.3)",
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "blas_threads": int(threads),
+           "pcg_seconds_per_iteration": per_it}
+    if pcg_iterations_to_tol:
+        out["pcg_seconds_to_1e-6_extrapolated"] = per_it * pcg_iterations_to_tol
+        out["pcg_iterations_to_1e-6"] = int(pcg_iterations_to_tol)
+    return out
 
 
 def main():
@@ -498,13 +532,15 @@ def main():
 
     ms = main_kv["wall_s"] * 1e3 / a.steps
     value = t.n_dof / (ms * 1e-3) / 1e9
-    achieved = main_kv["bytes"] / (main_kv["avg_launch_ms"] * 1e-3) / 1e9
+    # achieved: algorithmic bytes per launch over the average launch duration that the
+    # HIP events around the timed region give
+    achieved = main_kv["bytes"] / (main_kv["batch_ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": kv_traffic(a.prec),
                 "bytes_per_launch": main_kv["bytes"],
-                "avg_launch_us": main_kv["avg_launch_ms"] * 1e3,
-                "median_launch_us": main_kv["median_launch_ms"] * 1e3,
-                "back_to_back_us": main_kv["batch_ms"] * 1e3}
+                "avg_launch_us": main_kv["batch_ms"] * 1e3,
+                "per_launch_event_avg_us": main_kv["avg_launch_ms"] * 1e3,
+                "per_launch_event_median_us": main_kv["median_launch_ms"] * 1e3}
     line = {
         "metric": "K·v GDOF/s + PCG time-to-1e-6 residual: plain FP64 vs mixed/learned form",
         "value": value, "unit": "GDOF/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -517,16 +553,15 @@ def main():
         "roofline": roofline,
         "kv_other_precision": {
             "precision": other,
-            "gdof_s": t.n_dof / (other_kv["avg_launch_ms"] * 1e-3) / 1e9,
-            "achieved_gbs": other_kv["bytes"] / (other_kv["avg_launch_ms"] * 1e-3) / 1e9,
-            "frac": other_kv["bytes"] / (other_kv["avg_launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "avg_launch_us": other_kv["avg_launch_ms"] * 1e3,
-            "median_launch_us": other_kv["median_launch_ms"] * 1e3,
-            "back_to_back_us": other_kv["batch_ms"] * 1e3,
+            "gdof_s": t.n_dof / (other_kv["batch_ms"] * 1e-3) / 1e9,
+            "achieved_gbs": other_kv["bytes"] / (other_kv["batch_ms"] * 1e-3) / 1e9,
+            "frac": other_kv["bytes"] / (other_kv["batch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "avg_launch_us": other_kv["batch_ms"] * 1e3,
+            "per_launch_event_avg_us": other_kv["avg_launch_ms"] * 1e3,
             "traffic": kv_traffic(other)},
     }
     def summary(r, prec):
-        us = r["avg_launch_ms"] * 1e3
+        us = r["batch_ms"] * 1e3
         return {"gdof_s": t.n_dof / (us * 1e-6) / 1e9, "achieved_gbs": r["bytes"] / (us * 1e-6) / 1e9,
                 "frac": r["bytes"] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "avg_launch_us": us}
     # low-precision contraction on the matrix cores (FP32 storage, FP32 accumulate)
@@ -544,7 +579,7 @@ def main():
     line["kv_torsion_55x55x165"] = {}
     for p in ("fp32", "fp64"):
         r = time_kv(tor, 55, 55, 165, p, 100, 10, tfix)
-        us = r["avg_launch_ms"] * 1e3
+        us = r["batch_ms"] * 1e3
         line["kv_torsion_55x55x165"][p] = {
             "gdof_s": tor.n_dof / (us * 1e-6) / 1e9, "avg_launch_us": us,
             "frac": r["bytes"] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
@@ -552,7 +587,8 @@ def main():
     if not a.no_nn:
         line["learned_pcg"] = time_nn()
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
+        its = line.get("pcg", {}).get("plain_fp64", {}).get("iterations")
+        line["cpu_baseline"] = cpu_baseline(a.workload, pcg_iterations_to_tol=its)
     print(json.dumps(line), flush=True)
 
 
