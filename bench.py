@@ -245,10 +245,7 @@ def _problem(workload):
     cfg = si.CONFIGS[workload]
     nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
     t = Tosimp(0).set_mesh(nx, ny, nz)
-    if cfg["kind"] == "cantilever":
-        fixed, f = si.cantilever_fixed_dofs(nx, ny, nz), si.cantilever_load(nx, ny, nz)
-    else:
-        fixed, f = si.torsion_fixed_dofs(nx, ny, nz), si.torsion_load(nx, ny, nz)
+    fixed, f = si.bcs_and_load(cfg["kind"], nx, ny, nz)
     t.set_bcs(fixed)
     fd = torch.tensor(f, device="cuda:0")
     t.set_loads(fd)
@@ -416,6 +413,167 @@ def pcg_cold_study(workloads=("cantilever_120x60x30", "torsion_55x55x165",
     return out
 
 
+class PowerMeter:
+    """Board power from the amdgpu hwmon sensor (power1_input, microwatts), polled by a
+    thread every `period` s and integrated by the trapezoid rule over the measured
+    window.  The sensor's own update cadence limits the resolution: windows are kept
+    >= 1 s by repeating the measured work."""
+
+    def __init__(self, period=0.02):
+        import glob
+        self.path = None
+        for d in sorted(glob.glob("/sys/class/drm/card*/device/hwmon/hwmon*")):
+            try:
+                with open(os.path.join(d, "name")) as fh:
+                    if fh.read().strip() == "amdgpu" and os.access(os.path.join(d, "power1_input"), os.R_OK):
+                        self.path = os.path.join(d, "power1_input")
+                        break
+            except OSError:
+                continue
+        self.period = period
+        self.samples = []
+
+    def _read(self):
+        with open(self.path) as fh:
+            return float(fh.read()) * 1e-6
+
+    def __enter__(self):
+        import threading
+        self.samples = []
+        self._stop = threading.Event()
+
+        def run():
+            while not self._stop.is_set():
+                try:
+                    self.samples.append((time.perf_counter(), self._read()))
+                except (OSError, ValueError):
+                    pass
+                self._stop.wait(self.period)
+
+        if self.path:
+            self._t = threading.Thread(target=run, daemon=True)
+            self._t.start()
+        return self
+
+    def __exit__(self, *exc):
+        if self.path:
+            self._stop.set()
+            self._t.join()
+
+    def energy(self):
+        """(joules, mean watts) over the samples, or (None, None) without a sensor."""
+        if len(self.samples) < 2:
+            return None, None
+        e = sum(0.5 * (w0 + w1) * (t1 - t0)
+                for (t0, w0), (t1, w1) in zip(self.samples, self.samples[1:]))
+        span = self.samples[-1][0] - self.samples[0][0]
+        return e, e / span
+
+
+def _solve_energy(t, x, f, tol, min_window=1.5, **kw):
+    """One timed solve (as _solve_timed), then the same solve repeated for >= min_window
+    seconds under the power meter: energy per solve and mean board power."""
+    import torch
+    u, r = _solve_timed(t, x, f, tol, **kw)
+    meter = PowerMeter()
+    n, t0 = 0, time.perf_counter()
+    with meter:
+        while time.perf_counter() - t0 < min_window:
+            u.zero_()
+            t.pcg_solve(x, f, u, tol=tol, **kw)
+            torch.cuda.synchronize()
+            n += 1
+    e, w = meter.energy()
+    r["energy_J_per_solve"] = None if e is None else e / n
+    r["mean_board_W"] = w
+    return u, r
+
+
+def presets_study(tol=1e-6):
+    """Paper presets and reports: the cold-start FEA ladder of 4:2:1 cantilevers at uniform
+    density 0.5 from 216 k to 8 M elements (time, iterations, energy per solve, VRAM), and
+    the MBB and bridge stress tests at 150x50x25 (FEA-only cold start at uniform density
+    volfrac, and 60 SIMP iterations with cold-start solves)."""
+    import torch
+
+    import synth_inputs as si
+    from paper_2604_18020_amd import Tosimp
+
+    gb = 1024.0 ** 3
+    out = {"fea_ladder": [], "vram_note": "device memory in use (hipMemGetInfo) at the end of "
+                                           "each ladder size, and the part the library's "
+                                           "context holds (mesh workspace + multigrid hierarchy)"}
+    solvers = [s for s in SOLVERS]
+    for nx, ny, nz in si.FEA_LADDER:
+        torch.cuda.empty_cache()
+        free0, total = torch.cuda.mem_get_info()
+        t = Tosimp(0).set_mesh(nx, ny, nz)
+        fixed, f = si.bcs_and_load("cantilever", nx, ny, nz)
+        t.set_bcs(fixed)
+        fd = torch.tensor(f, device="cuda:0")
+        t.set_loads(fd)
+        x = torch.full((t.n_elem,), 0.5, dtype=torch.float64, device="cuda:0")
+        row = {"mesh": f"{nx}x{ny}x{nz}", "n_elem": t.n_elem, "n_dof": t.n_dof}
+        _solve_timed(t, x, fd, 1e-2, mode="plain_fp64", precond="mg", check_every=4)
+        for name, kw in solvers:
+            _, r = _solve_energy(t, x, fd, tol, **kw)
+            row[name] = r
+        torch.cuda.synchronize()
+        free1, _ = torch.cuda.mem_get_info()
+        row["vram_in_use_GB"] = (total - free1) / gb
+        row["vram_context_and_vectors_GB"] = (free0 - free1) / gb
+        out["fea_ladder"].append(row)
+        del x, fd
+        t.close()
+        print(json.dumps({"ladder": row["mesh"], **{k: (v["seconds"], v["iterations"])
+                                                  for k, v in row.items() if isinstance(v, dict)}}),
+              file=sys.stderr, flush=True)
+    for name in ("mbb_150x50x25", "bridge_150x50x25"):
+        cfg = si.CONFIGS[name]
+        nx, ny, nz, vf = cfg["nx"], cfg["ny"], cfg["nz"], cfg["volfrac"]
+        t = Tosimp(0).set_mesh(nx, ny, nz)
+        fixed, f = si.bcs_and_load(cfg["kind"], nx, ny, nz)
+        t.set_bcs(fixed)
+        fd = torch.tensor(f, device="cuda:0")
+        t.set_loads(fd)
+        x = torch.full((t.n_elem,), vf, dtype=torch.float64, device="cuda:0")
+        res = {"fea_cold_start": {}, "simp60_cold_start": {}}
+        _solve_timed(t, x, fd, 1e-2, mode="plain_fp64", precond="mg", check_every=4)
+        for sname, kw in solvers:
+            res["fea_cold_start"][sname] = _solve_energy(t, x, fd, tol, **kw)[1]
+        for sname, kw in (("plain_fp64_jacobi", dict(mode="plain_fp64", check_every=64)),
+                          ("ir_fp32_mg", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,
+                                              precond="mg", check_every=4))):
+            xs = torch.full((t.n_elem,), vf, dtype=torch.float64, device="cuda:0")
+            xp = xs.clone()
+            u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+            cs, its = [], 0
+            meter = PowerMeter()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with meter:
+                for _ in range(cfg["simp_iters"]):
+                    u.zero_()  # cold start
+                    st = t.simp_step(xs, xp, u, volfrac=vf, move=0.2, tol=tol, maxit=60000, **kw)
+                    cs.append(st["compliance"])
+                    its += st["solve"]["iterations"]
+                torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            e, w = meter.energy()
+            res["simp60_cold_start"][sname] = {"seconds": sec, "cg_iterations": its,
+                                               "final_compliance": cs[-1], "energy_J": e,
+                                               "mean_board_W": w}
+        a_, b_ = (res["simp60_cold_start"][k]["final_compliance"]
+                  for k in ("plain_fp64_jacobi", "ir_fp32_mg"))
+        res["simp60_cold_start"]["final_compliance_rel_diff"] = abs(a_ - b_) / abs(a_)
+        res["simp60_cold_start"]["speedup"] = (res["simp60_cold_start"]["plain_fp64_jacobi"]["seconds"]
+                                               / res["simp60_cold_start"]["ir_fp32_mg"]["seconds"])
+        out[name] = res
+        t.close()
+        print(json.dumps({name: res["simp60_cold_start"]["speedup"]}), file=sys.stderr, flush=True)
+    return out
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -492,6 +650,9 @@ def main():
                     help="instead of the benchmark line: precision study (340x170x85) and "
                          "SIMP runs (120x60x30, torsion 55x55x165), one JSON line each")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--presets", action="store_true",
+                    help="paper presets and reports: FEA ladder to 8M elements with energy and "
+                         "VRAM, MBB and bridge stress tests (prints that JSON only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for scaling profiler byte counters)")
     a = ap.parse_args()
@@ -505,6 +666,9 @@ def main():
     import synth_inputs as si
     from paper_2604_18020_amd import Tosimp
 
+    if a.presets:
+        print(json.dumps({"presets_study": presets_study()}), flush=True)
+        return
     if a.suite:
         print(json.dumps({"kv_study": kv_study()}), flush=True)
         print(json.dumps({"projection_study": projection_study()}), flush=True)

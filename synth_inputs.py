@@ -2,7 +2,7 @@
 
 This module holds problem *inputs* only: mesh sizes and material constants of the
 benchmark problems, the node/DOF numbering convention, the Dirichlet sets and load
-vectors of the cantilever and torsion cases, and seeded random fields.  It holds none
+vectors of the cantilever, torsion, MBB and bridge cases, and seeded random fields.  It holds none
 of the method's arithmetic (no stiffness, no solver, no filter, no update rule), so the
 oracle and the GPU library can both consume it without sharing any computation.
 
@@ -36,7 +36,17 @@ CONFIGS = {
     # 1,000,000 elements, 3,106,053 DOFs
     "cantilever_200x100x50": dict(kind="cantilever", nx=200, ny=100, nz=50, volfrac=0.3,
                                   simp_iters=20, pcg_tol=1e-6),
+    # hard-problem stress tests: 187,500 elements each (domain 3 x 1 x 0.5)
+    "mbb_150x50x25": dict(kind="mbb", nx=150, ny=50, nz=25, volfrac=0.5, simp_iters=60,
+                          pcg_tol=1e-6),
+    "bridge_150x50x25": dict(kind="bridge", nx=150, ny=50, nz=25, volfrac=0.3, simp_iters=60,
+                             pcg_tol=1e-6),
 }
+
+# Cold-start FEA scaling ladder (4:2:1 cantilevers, uniform density 0.5):
+# 216 k, 512 k, 1 M, 2.0 M, 4.9 M and 8 M elements.
+FEA_LADDER = [(120, 60, 30), (160, 80, 40), (200, 100, 50), (252, 126, 63), (340, 170, 85),
+              (400, 200, 100)]
 
 
 def counts(nx: int, ny: int, nz: int) -> dict:
@@ -103,16 +113,72 @@ def torsion_load(nx: int, ny: int, nz: int) -> np.ndarray:
     return f
 
 
+def _mid_nodes(n: int):
+    """The node(s) at the middle of an axis of n elements: one for even n, the two
+    nearest for odd n."""
+    return [n // 2] if n % 2 == 0 else [n // 2, n // 2 + 1]
+
+
+def mbb_fixed_dofs(nx: int, ny: int, nz: int) -> np.ndarray:
+    """MBB stress test on the domain 3 x 1 x 0.5 (x, y, z; y up): u_x = 0 on every node of
+    the x = 0 face (the symmetry plane of the half beam); u_y = 0 along the bottom edge of
+    the far end, (x, y) = (nx, 0), over the whole depth (the support point, extended so
+    that no rotation about the x axis survives); u_z = 0 at its mid-depth node(s) (the z
+    translation)."""
+    j, k = np.meshgrid(np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
+    face = 3 * node_id(0, j.ravel(), k.ravel(), nx, ny)
+    edge = node_id(nx, 0, np.arange(nz + 1), nx, ny)
+    mid = node_id(nx, 0, np.array(_mid_nodes(nz)), nx, ny)
+    ids = np.concatenate([face, 3 * edge + 1, 3 * mid + 2])
+    return np.unique(ids).astype(np.int64)
+
+
+def mbb_load(nx: int, ny: int, nz: int) -> np.ndarray:
+    """Unit downward (-y) load at the top of the symmetry plane, (x, y) = (0, ny) at
+    mid-depth, split evenly over the mid-depth node(s)."""
+    f = np.zeros(3 * (nx + 1) * (ny + 1) * (nz + 1))
+    ks = _mid_nodes(nz)
+    n = node_id(0, ny, np.array(ks), nx, ny)
+    f[3 * n + 1] = -1.0 / len(ks)
+    return f
+
+
+def bridge_fixed_dofs(nx: int, ny: int, nz: int) -> np.ndarray:
+    """Bridge stress test: the left lower edge (x = 0, y = 0, every z) fixed in all three
+    components; the right lower edge (x = nx, y = 0) a roller in x (u_y = u_z = 0)."""
+    k = np.arange(nz + 1)
+    left = node_id(0, 0, k, nx, ny)
+    right = node_id(nx, 0, k, nx, ny)
+    ids = np.concatenate([3 * left, 3 * left + 1, 3 * left + 2, 3 * right + 1, 3 * right + 2])
+    return np.unique(ids).astype(np.int64)
+
+
+def bridge_load(nx: int, ny: int, nz: int) -> np.ndarray:
+    """Distributed downward load on the top (y = ny face), total magnitude 1, equal on
+    every node of the face."""
+    f = np.zeros(3 * (nx + 1) * (ny + 1) * (nz + 1))
+    i, k = np.meshgrid(np.arange(nx + 1), np.arange(nz + 1), indexing="ij")
+    n = node_id(i.ravel(), ny, k.ravel(), nx, ny)
+    f[3 * n + 1] = -1.0 / n.size
+    return f
+
+
+def bcs_and_load(kind: str, nx: int, ny: int, nz: int):
+    """(fixed DOF ids, load vector) of a problem kind on an nx x ny x nz mesh."""
+    table = {"cantilever": (cantilever_fixed_dofs, cantilever_load),
+             "torsion": (torsion_fixed_dofs, torsion_load),
+             "mbb": (mbb_fixed_dofs, mbb_load),
+             "bridge": (bridge_fixed_dofs, bridge_load)}
+    fixed, load = table[kind]
+    return fixed(nx, ny, nz), load(nx, ny, nz)
+
+
 def problem(name: str):
     """(config dict, fixed DOF ids, load vector) of a named benchmark problem."""
     cfg = dict(CONFIGS[name])
     cfg.update(MATERIAL)
     nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
-    if cfg["kind"] == "cantilever":
-        return cfg, cantilever_fixed_dofs(nx, ny, nz), cantilever_load(nx, ny, nz)
-    if cfg["kind"] == "torsion":
-        return cfg, torsion_fixed_dofs(nx, ny, nz), torsion_load(nx, ny, nz)
-    raise KeyError(name)
+    return (cfg, *bcs_and_load(cfg["kind"], nx, ny, nz))
 
 
 def random_density_and_vector(nx: int, ny: int, nz: int, seed: int = 42):

@@ -8,10 +8,8 @@ def gpu_problem(nx, ny, nz, kind="cantilever", penal=3.0, nu=0.3, rmin=1.5, h=1.
     import torch
     from paper_2604_18020_amd import Tosimp
 
-    if kind == "cantilever":
-        fixed, f = si.cantilever_fixed_dofs(nx, ny, nz), si.cantilever_load(nx, ny, nz)
-    elif kind == "torsion":
-        fixed, f = si.torsion_fixed_dofs(nx, ny, nz), si.torsion_load(nx, ny, nz)
+    if kind in ("cantilever", "torsion", "mbb", "bridge"):
+        fixed, f = si.bcs_and_load(kind, nx, ny, nz)
     elif kind == "midpoint":
         fixed, f = si.cantilever_fixed_dofs(nx, ny, nz), si.cantilever_midpoint_load(nx, ny, nz)
     elif kind == "free":

@@ -204,3 +204,29 @@ def test_three_field_chain_from_gpu_primitives_matches_oracle(dims, beta):
     _, dc_o = topopt.three_field_sensitivity(prob, x, u_o, beta, eta)
     assert np.max(np.abs(xphys.cpu().numpy() - xphys_o)) <= 1e-14  # filter rounding x slope <= beta / 2
     assert np.max(np.abs(dc - dc_o)) <= 1e-7 * np.max(np.abs(dc_o))
+
+
+@pytest.mark.parametrize("kind,volfrac", [("mbb", 0.5), ("bridge", 0.3)])
+@pytest.mark.parametrize("precond", ["jacobi", "mg"])
+def test_stress_test_presets_match_oracle(kind, volfrac, precond):
+    """MBB and bridge stress tests (Sec. "Experimental Setup") on a 24x8x4 mesh of the
+    same 3 x 1 x 0.5 proportions: three SIMP iterations with the GPU solve (Jacobi- or
+    multigrid-preconditioned, to 1e-10) against the oracle's direct solves."""
+    import synth_inputs as si
+    nx, ny, nz = 24, 8, 4
+    fixed, f = si.bcs_and_load(kind, nx, ny, nz)
+    prob = topopt.Problem(nx, ny, nz, fixed, f, volfrac=volfrac)
+    hist, x_o, xp_o, _ = topopt.simp_run(prob, 3, direct=True)
+    t, _, _ = gpu_problem(nx, ny, nz, kind=kind)
+    x = torch.full((prob.n_elem,), volfrac, dtype=torch.float64, device="cuda:0")
+    xp = x.clone()
+    u = torch.zeros(prob.n_dof, dtype=torch.float64, device="cuda:0")
+    for k in range(3):
+        st = t.simp_step(x, xp, u, volfrac=volfrac, move=0.2, tol=1e-10, precond=precond,
+                         check_every=4)
+        assert st["solve"]["status"] == 0
+        assert abs(st["compliance"] - hist[k]["c"]) <= 1e-7 * hist[k]["c"], k
+        assert st["bisection_steps"] == hist[k]["bisect"], k
+    t.close()
+    assert np.max(np.abs(x.cpu().numpy() - x_o)) <= 1e-6
+    assert np.max(np.abs(xp.cpu().numpy() - xp_o)) <= 1e-6

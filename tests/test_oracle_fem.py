@@ -242,3 +242,29 @@ def test_problem_inputs():
     c = si.counts(16, 8, 8)
     assert (c["n_node"], c["n_dof"]) == (1377, 4131)
     assert si.cantilever_fixed_dofs(16, 8, 8).size == 243
+
+
+@pytest.mark.parametrize("kind,dims", [("mbb", (12, 4, 3)), ("mbb", (12, 4, 2)),
+                                       ("bridge", (12, 4, 3)), ("bridge", (9, 3, 2))])
+def test_stress_test_presets_are_well_posed(kind, dims):
+    """MBB and bridge (Sec. "Experimental Setup", hard-problem stress tests): the
+    constrained operator is positive definite (no rigid mode survives the supports), the
+    load is a unit downward total applied only on free DOFs."""
+    nx, ny, nz = dims
+    fixed_ids, f = si.bcs_and_load(kind, nx, ny, nz)
+    fixed = fem.fixed_mask(f.size, fixed_ids)
+    K = fem.constrain(fem.assemble_K(nx, ny, nz, np.full(nx * ny * nz, 0.5),
+                                     fem.element_stiffness(0.3)), fixed).toarray()
+    assert np.linalg.eigvalsh(K)[0] > 1e-6
+    F = f.reshape(-1, 3)
+    assert abs(F[:, 1].sum() + 1.0) <= 1e-12 and np.all(F[:, [0, 2]] == 0.0)
+    assert np.all(f[fixed] == 0.0)
+    # the reading of the MBB supports: x = 0 face holds u_x only; the far bottom edge
+    # holds u_y over the depth and u_z at mid-depth
+    if kind == "mbb":
+        c = si.node_coords(nx, ny, nz)
+        fx = fixed.reshape(-1, 3)
+        assert np.array_equal(fx[:, 0], c[:, 0] == 0)
+        edge = (c[:, 0] == nx) & (c[:, 1] == 0)
+        mid = np.isin(c[:, 2], [nz // 2] if nz % 2 == 0 else [nz // 2, nz // 2 + 1])
+        assert np.array_equal(fx[:, 1], edge) and np.array_equal(fx[:, 2], edge & mid)
