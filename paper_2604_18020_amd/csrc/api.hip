@@ -733,7 +733,7 @@ int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
     // CG in FP64 preconditioned by an FP64 V-cycle (warm start from u)
     MgPcgResult pr;
     rc = mg_pcg<double>(ctx, x, b, u, w.r, w.w, w.p, w.q, 0, o->tol, o->maxit, o->check_every,
-                        false, mg_deg, mg_alpha, &pr);
+                        false, mg_deg, mg_alpha, !o->eager, &pr);
     if (rc) return rc;
     s.iterations = pr.iters;
     s.rel_residual = pr.bb > 0 ? std::sqrt(pr.rr / pr.bb) : 0.0;
@@ -828,7 +828,8 @@ int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
                 "the multigrid inner solve runs in FP32");
         MgPcgResult pr;
         rc = mg_pcg<float>(ctx, w.x32, w.e32, w.z32, w.r32, (float*)w.w, w.p32, w.q32, 1, itol,
-                           o->maxit - total, o->check_every, true, mg_deg, mg_alpha, &pr);
+                           o->maxit - total, o->check_every, true, mg_deg, mg_alpha, !o->eager,
+                           &pr);
         if (rc) return rc;
         it = pr.iters;
         done = pr.done;

@@ -174,7 +174,7 @@ int mg_apply(tosimp_ctx* ctx, const T* r, T* z, int degree, double alpha, const 
 template <typename T>
 int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T* q,
            int slot, double tol, int maxit, int check_every, bool zero_guess, int degree,
-           double alpha, MgPcgResult* res);
+           double alpha, bool graphs, MgPcgResult* res);
 int mg_levels(tosimp_ctx* ctx, int* dims, int cap);
 void mg_release(tosimp_ctx* ctx);
 hipError_t launch_diag_level(const tosimp_ctx* c, const double* E, int nx, int ny, int nz,

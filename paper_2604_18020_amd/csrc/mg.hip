@@ -23,6 +23,7 @@
 //    FP64 on the host (Cholesky) once per set-up, applied as a matrix-vector product.
 //  * CG: FP64 reductions and scalars on the device (SolverState), host polls every
 //    check_every iterations; vectors in FP64 (plain mode) or FP32 (refinement inner solve).
+//    Batches of check_every iterations are captured once as a HIP graph and replayed.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -653,7 +654,7 @@ int mg_apply(tosimp_ctx* ctx, const T* r, T* z, int degree, double alpha, const 
 template <typename T>
 int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T* q,
            int slot, double tol, int maxit, int check_every, bool zero_guess, int degree,
-           double alpha, MgPcgResult* res) {
+           double alpha, bool graphs, MgPcgResult* res) {
   constexpr int prec = sizeof(T) == 8 ? TOSIMP_PREC_FP64 : TOSIMP_PREC_FP32;
   constexpr int xdt = sizeof(T) == 8 ? TOSIMP_F64 : TOSIMP_F32;
   Workspace& w = ctx->ws;
@@ -676,10 +677,8 @@ int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T
   TOSIMP_HIP(ctx, launch_finalize_sum<2>(ctx->stream, part, kRedBlocks, MgInitFin{st}));
   if (check_every < 1) check_every = 1;
   const int g = grid_for(n);
-  for (;;) {
-    TOSIMP_HIP(ctx, hipMemcpyAsync(sh, st, sizeof(SolverState), hipMemcpyDeviceToHost, ctx->stream));
-    TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (sh->done) break;
+  // One batch of check_every iterations (every kernel returns at once after convergence).
+  auto batch = [&]() -> int {
     for (int i = 0; i < check_every; ++i) {
       int rc = mg_apply<T>(ctx, r, z, degree, alpha, st);
       if (rc) return rc;
@@ -690,6 +689,44 @@ int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T
       mg_update_kernel<T><<<g, kRedThreads, 0, ctx->stream>>>(u, r, p, q, n, st, part);
       TOSIMP_HIP(ctx, launch_finalize_sum<1>(ctx->stream, part, g, MgUpdateFin{st}));
     }
+    return TOSIMP_OK;
+  };
+  // After one eager batch the batch is captured once into a HIP graph and replayed: a
+  // V-cycle is a few hundred small launches, which bound the iteration on small meshes.
+  // The graph holds only this library's kernels (no memset or copy nodes).
+  hipGraphExec_t exec = nullptr;
+  struct ExecGuard {
+    hipGraphExec_t* e;
+    ~ExecGuard() {
+      if (*e) (void)hipGraphExecDestroy(*e);
+    }
+  } guard{&exec};
+  int batches = 0;
+  for (;;) {
+    TOSIMP_HIP(ctx, hipMemcpyAsync(sh, st, sizeof(SolverState), hipMemcpyDeviceToHost, ctx->stream));
+    TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (sh->done) break;
+    if (graphs && batches == 1 && !exec) {
+      hipGraph_t gr = nullptr;
+      TOSIMP_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+      const int rc = batch();
+      const hipError_t ee = hipStreamEndCapture(ctx->stream, &gr);
+      if (rc) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return rc;
+      }
+      TOSIMP_HIP(ctx, ee);
+      const hipError_t ie = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      TOSIMP_HIP(ctx, ie);
+    }
+    if (exec) {
+      TOSIMP_HIP(ctx, hipGraphLaunch(exec, ctx->stream));
+    } else {
+      const int rc = batch();
+      if (rc) return rc;
+    }
+    ++batches;
   }
   res->iters = sh->iter;
   res->done = sh->done;
@@ -701,10 +738,10 @@ int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T
 template int mg_apply<double>(tosimp_ctx*, const double*, double*, int, double, const SolverState*);
 template int mg_apply<float>(tosimp_ctx*, const float*, float*, int, double, const SolverState*);
 template int mg_pcg<double>(tosimp_ctx*, const void*, const double*, double*, double*, double*,
-                            double*, double*, int, double, int, int, bool, int, double,
+                            double*, double*, int, double, int, int, bool, int, double, bool,
                             MgPcgResult*);
 template int mg_pcg<float>(tosimp_ctx*, const void*, const float*, float*, float*, float*,
-                           float*, float*, int, double, int, int, bool, int, double,
+                           float*, float*, int, double, int, int, bool, int, double, bool,
                            MgPcgResult*);
 
 int mg_prepare(tosimp_ctx* ctx, const double* x, int* degree, double* alpha) {

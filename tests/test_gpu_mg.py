@@ -133,3 +133,25 @@ def test_mg_arguments_refused():
     with pytest.raises(TosimpError):
         t.pcg_solve(x, dev(f), u, mode="ir", precond="mg", inner_prec="bf16_mfma")
     t.close()
+
+
+@pytest.mark.parametrize("mode", ["plain_fp64", "ir"])
+def test_mg_graph_replay_matches_eager_bitwise(mode):
+    """Batches of MG-CG iterations replayed as a HIP graph (many replays, with the host's
+    polls between them) give bit-identical iterates to direct launches."""
+    nx, ny, nz = 20, 10, 10
+    rng = np.random.default_rng(12)
+    x = dev(rng.uniform(0.01, 1.0, nx * ny * nz))
+    t, _, f = gpu_problem(nx, ny, nz)
+    out = []
+    for eager in (True, False):
+        u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+        kw = dict(tol=1e-10, precond="mg", check_every=2, eager=eager)
+        if mode == "ir":
+            kw.update(mode="ir", inner_tol=1e-4)
+        st = t.pcg_solve(x, dev(f), u, **kw)
+        assert st["rc"] == 0
+        out.append((st["iterations"], u.cpu().numpy()))
+    t.close()
+    assert out[0][0] == out[1][0] and out[0][0] > 4
+    assert np.array_equal(out[0][1], out[1][1])
