@@ -401,6 +401,44 @@ def projection_study(workload="cantilever_340x170x85", reps=200, sets=4):
     return res
 
 
+def simp_kernels_study(workload="cantilever_340x170x85", reps=20, sets=4):
+    """The SIMP pieces beside the solve, one density field per element of the mesh, buffer
+    sets rotated (>= 4 x the Infinity Cache is not guaranteed for the element fields, so
+    the per-kernel HBM bytes come from the profiler's counters): sensitivity (with the
+    compliance, one host synchronisation per call), density filter forward and adjoint,
+    OC update (bisection, synchronises), Heaviside projection.  Wall time per call."""
+    import numpy as np
+    import torch
+
+    t, cfg, _, _ = _problem(workload)
+    n = t.n_elem
+    rng = np.random.default_rng(5)
+    xs = [torch.tensor(rng.uniform(0.01, 1.0, n), device="cuda:0") for _ in range(sets)]
+    us = [torch.tensor(rng.standard_normal(t.n_dof), device="cuda:0") for _ in range(sets)]
+    dcs = [torch.tensor(-rng.uniform(0.1, 1.0, n), device="cuda:0") for _ in range(sets)]
+    outs = [torch.empty(n, dtype=torch.float64, device="cuda:0") for _ in range(sets)]
+    outs2 = [torch.empty(n, dtype=torch.float64, device="cuda:0") for _ in range(sets)]
+    calls = {
+        "sensitivity": lambda k: t.sensitivity(xs[k], us[k], outs[k]),
+        "filter_forward": lambda k: t.filter(xs[k], "forward", outs[k]),
+        "filter_adjoint": lambda k: t.filter(dcs[k], "adjoint", outs[k]),
+        "oc_update": lambda k: t.oc_update(xs[k], dcs[k], 0.3, 0.2, outs[k], outs2[k]),
+        "projection": lambda k: t.project(xs[k], 8.0, 0.5, out=outs[k]),
+    }
+    res = {"workload": workload, "n_elem": n, "calls": reps}
+    for name, fn in calls.items():
+        for k in range(4):
+            fn(k % sets)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(reps):
+            fn(k % sets)
+        torch.cuda.synchronize()
+        res[name] = {"wall_us_per_call": (time.perf_counter() - t0) * 1e6 / reps}
+    t.close()
+    return res
+
+
 def pcg_cold_study(workloads=("cantilever_120x60x30", "torsion_55x55x165",
                               "cantilever_200x100x50"), tol=1e-6):
     """Cold-start PCG at uniform density on the other benchmark meshes (the main line
@@ -653,6 +691,9 @@ def main():
     ap.add_argument("--presets", action="store_true",
                     help="paper presets and reports: FEA ladder to 8M elements with energy and "
                          "VRAM, MBB and bridge stress tests (prints that JSON only)")
+    ap.add_argument("--simp-kernels", action="store_true",
+                    help="time the SIMP kernels beside the solve on the workload (prints that "
+                         "JSON only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for scaling profiler byte counters)")
     a = ap.parse_args()
@@ -668,6 +709,14 @@ def main():
 
     if a.presets:
         print(json.dumps({"presets_study": presets_study()}), flush=True)
+        return
+    if a.simp_kernels:
+        if a.copy_calibration:
+            src = torch.empty(2 ** 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+            del src
+        print(json.dumps({"simp_kernels_study": simp_kernels_study(a.workload)}), flush=True)
         return
     if a.suite:
         print(json.dumps({"kv_study": kv_study()}), flush=True)
