@@ -203,7 +203,7 @@ def time_nn(workload="cantilever_200x100x50", simp_iters=10, per_solve=200, ever
     u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
     t0 = time.perf_counter()
     ps, stats = learned.harvest(t, x, xp, u, iters=simp_iters, every=every, per_solve=per_solve,
-                                volfrac=volfrac)
+                                f=f, volfrac=volfrac)
     torch.cuda.synchronize()
     t_harvest = time.perf_counter() - t0
     t.nn_create(16, bf16=True)
@@ -223,15 +223,22 @@ def time_nn(workload="cantilever_200x100x50", simp_iters=10, per_solve=200, ever
            "loss_first50": float(np.mean(losses[:50])),
            "loss_last50": float(np.mean(losses[-50:]))}
     _solve_timed(t, xp, f, 1e-2, mode="plain_fp64", precond="mg", check_every=4)  # allocation
+    nn = dict(mode="ir", inner_prec="fp32", inner_tol=1e-4, precond="nn", check_every=8)
     for name, kw in [("plain_fp64_jacobi", dict(mode="plain_fp64", check_every=64)),
                      ("ir_fp32_jacobi", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,
                                              check_every=64)),
                      ("ir_fp32_mg", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,
                                          precond="mg", check_every=4)),
-                     ("ir_fp32_nn_fcg", dict(mode="ir", inner_prec="fp32", inner_tol=1e-4,
-                                             precond="nn", check_every=8, maxit=20000))]:
+                     # guarded: an inner solve without a new residual minimum for 50
+                     # iterations is finished by Jacobi-PCG; unguarded: the network alone
+                     ("ir_fp32_nn_fcg_guarded", dict(nn, maxit=20000)),
+                     ("ir_fp32_nn_fcg_unguarded", dict(nn, maxit=12000, nn_stall=-1))]:
         _, r = _solve_timed(t, xp, f, tol, **kw)
         out[name] = r
+    # ablation: the untrained (He-normal) network, guarded
+    t.nn_set_weights(learned.he_normal_weights(t, 0))
+    _, r = _solve_timed(t, xp, f, tol, **dict(nn, maxit=20000))
+    out["ir_fp32_nn_fcg_untrained_guarded"] = r
     t.close()
     return out
 

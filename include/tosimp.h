@@ -97,6 +97,9 @@ typedef struct tosimp_solve_opts {
                      /*   the current iterate (0 = 50, < 0 = never)                          */
   int mg_degree;     /* PRECOND_MG: Chebyshev smoothing degree (1..16; 0 = 2)               */
   double mg_alpha;   /* PRECOND_MG: smoothing interval [lam / alpha, lam] (> 1; 0 = 20)     */
+  const double* harvest_ustar; /* optional with harvesting (NULL = off): device FP64 n_dof  */
+                     /*   reference solution; harvest_u then receives ustar - u_k formed in  */
+                     /*   FP64 before the cast (the error, not the iterate)                  */
 } tosimp_solve_opts;
 
 typedef struct tosimp_solve_stats {

@@ -38,7 +38,7 @@ class SolveOpts(C.Structure):
                 ("kappa", C.c_double), ("harvest_r", C.c_void_p), ("harvest_u", C.c_void_p),
                 ("harvest_cap", C.c_int), ("harvest_every", C.c_int), ("fcg_window", C.c_int),
                 ("eager", C.c_int), ("nn_stall", C.c_int), ("mg_degree", C.c_int),
-                ("mg_alpha", C.c_double)]
+                ("mg_alpha", C.c_double), ("harvest_ustar", C.c_void_p)]
 
 
 class SolveStats(C.Structure):
@@ -248,8 +248,10 @@ class Tosimp:
                          0, 0, int(fcg_window), int(bool(eager)), int(nn_stall),
                          int(mg_degree), float(mg_alpha))
 
-    def _opts_with_harvest(self, harvest, harvest_every, **kw):
+    def _opts_with_harvest(self, harvest, harvest_every, harvest_ustar=None, **kw):
         o = self.solve_opts(**kw)
+        if harvest_ustar is not None:
+            o.harvest_ustar = self._dev(harvest_ustar, torch.float64, self.n_dof, "harvest_ustar").value
         if harvest is not None:
             hr, hu = harvest
             cap = hr.shape[0]
@@ -258,9 +260,10 @@ class Tosimp:
             o.harvest_cap, o.harvest_every = cap, int(harvest_every)
         return o
 
-    def pcg_solve(self, x, b, u, harvest=None, harvest_every=1, **kw):
-        """harvest: optional (r, u) pair of FP32 device tensors [cap, n_dof] (plain FP64)."""
-        o = self._opts_with_harvest(harvest, harvest_every, **kw)
+    def pcg_solve(self, x, b, u, harvest=None, harvest_every=1, harvest_ustar=None, **kw):
+        """harvest: optional (r, u) pair of FP32 device tensors [cap, n_dof] (plain FP64);
+        with harvest_ustar (FP64 reference solution) u receives ustar - u_k."""
+        o = self._opts_with_harvest(harvest, harvest_every, harvest_ustar, **kw)
         s = SolveStats()
         self._sync_stream()
         rc = self._check(LIB.tosimp_pcg_solve(

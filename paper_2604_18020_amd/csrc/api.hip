@@ -528,6 +528,7 @@ struct PcgResult {
 struct Harvest {
   float* r = nullptr;
   float* u = nullptr;
+  const double* ustar = nullptr;  // if set, u receives ustar - u_k (formed in FP64)
   int cap = 0;
 };
 
@@ -602,7 +603,11 @@ int run_pcg(tosimp_ctx* ctx, int prec, const void* x, int xdtype, const T* b, T*
       if (hv && res->harvested < hv->cap) {
         const size_t off = (size_t)res->harvested * ctx->n_dof;
         TOSIMP_HIP(ctx, launch_cast32(ctx, (const double*)r, hv->r + off, ctx->n_dof));
-        TOSIMP_HIP(ctx, launch_cast32(ctx, (const double*)u, hv->u + off, ctx->n_dof));
+        if (hv->ustar)
+          TOSIMP_HIP(ctx, launch_diff_cast32(ctx, hv->ustar, (const double*)u, hv->u + off,
+                                             ctx->n_dof));
+        else
+          TOSIMP_HIP(ctx, launch_cast32(ctx, (const double*)u, hv->u + off, ctx->n_dof));
         res->harvested += 1;
       }
     }
@@ -754,6 +759,7 @@ int pcg_solve_impl(tosimp_ctx* ctx, const double* x, const double* b, double* u,
               TOSIMP_EINVAL, "harvest needs both arrays, harvest_cap >= 1, harvest_every >= 1");
       hv.r = o->harvest_r;
       hv.u = o->harvest_u;
+      hv.ustar = o->harvest_ustar;
       hv.cap = o->harvest_cap;
       every = o->harvest_every;
     }

@@ -202,6 +202,8 @@ hipError_t launch_scale_to32(const tosimp_ctx* c, const double* r, double inv_s,
 hipError_t launch_axpy_from32(const tosimp_ctx* c, double* u, double s, const float* e);
 hipError_t launch_copy_cast_x(const tosimp_ctx* c, const double* x, float* x32);
 hipError_t launch_cast32(const tosimp_ctx* c, const double* x, float* y, int64_t n);
+hipError_t launch_diff_cast32(const tosimp_ctx* c, const double* a, const double* b, float* y,
+                              int64_t n);
 hipError_t launch_fill_zero(const tosimp_ctx* c, void* p, int64_t bytes);
 hipError_t launch_fill64(const tosimp_ctx* c, double* p, int64_t n, double v);
 hipError_t launch_dot64(const tosimp_ctx* c, const double* a, const double* b, int64_t n,

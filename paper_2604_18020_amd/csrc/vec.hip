@@ -342,6 +342,20 @@ __global__ void cast_kernel(const double* x, float* y, int64_t n) {
     y[i] = (float)x[i];
 }
 
+// y = (float)(a - b): the error of an iterate against a reference, formed in FP64 before
+// the cast (harvested training targets).
+__global__ void diff_cast_kernel(const double* a, const double* b, float* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)(a[i] - b[i]);
+}
+
+hipError_t launch_diff_cast32(const tosimp_ctx* c, const double* a, const double* b, float* y,
+                              int64_t n) {
+  diff_cast_kernel<<<2048, 256, 0, c->stream>>>(a, b, y, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_cast32(const tosimp_ctx* c, const double* x, float* y, int64_t n) {
   cast_kernel<<<kRedBlocks, kRedThreads, 0, c->stream>>>(x, y, n);
   return hipGetLastError();

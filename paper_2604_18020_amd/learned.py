@@ -1,8 +1,15 @@
 """Training pipeline of the learned preconditioner (orchestration of library calls).
 
-1. harvest: run SIMP iterations with plain FP64 Jacobi-PCG; each solve copies (r_k, u_k)
-   every `every` iterations into FP32 device arrays, and after the solve the library turns
-   u_k into the error e_k = u* - u_k.  All pairs stay resident in HBM.
+1. harvest: run SIMP iterations with plain FP64 Jacobi-PCG.  With the load vector given,
+   each step's solution is refined to a tighter tolerance on the same system (ref_tol,
+   default 1e-10) and the step's Jacobi-PCG run is replayed from its warm start (the
+   library's CG is deterministic: the same iterates), copying r_k and e_k = u* - u_k
+   (formed in FP64, then stored in FP32) every `every` iterations.  Snapshots are taken
+   while the solve has not converged, so every harvested ||r_k|| exceeds tol ||b||, and
+   K e_k - r_k = -r* with ||r*|| <= ref_tol ||b|| up to the FP32 storage of r_k and e_k
+   (an FP32 u_k differenced afterwards would carry 2^-24 ||u*||, large against the late
+   errors).  Without the load vector the pairs come from the step's own solve and the
+   library forms e_k from the stored FP32 u_k.  All pairs stay resident in HBM.
 2. train: Adam steps on batches of consecutive pairs of one SIMP iteration (the network's
    density input is that iteration's filtered density).
 3. solve: flexible CG with the trained network inside FP64 iterative refinement.
@@ -42,10 +49,12 @@ class PairSet:
         return sum(n for _, n in self.groups)
 
 
-def harvest(t, x, xphys, u, iters: int, every: int, per_solve: int, volfrac=0.3,
-            move=0.2, tol=1e-8, maxit=50000, check_every=64) -> tuple[PairSet, list]:
-    """Run `iters` SIMP steps (FP64 Jacobi-PCG, warm start) harvesting pairs.
-    Returns the pairs and the per-step statistics."""
+def harvest(t, x, xphys, u, iters: int, every: int, per_solve: int, f=None, volfrac=0.3,
+            move=0.2, tol=1e-8, ref_tol=1e-10, maxit=50000, check_every=64
+            ) -> tuple[PairSet, list]:
+    """Run `iters` SIMP steps (FP64 Jacobi-PCG, warm start) harvesting pairs; with the
+    load vector f given, each step's solution is refined to ref_tol before the targets
+    are formed.  Returns the pairs and the per-step statistics."""
     dev = x.device
     cap = iters * per_solve
     ps = PairSet()
@@ -56,11 +65,23 @@ def harvest(t, x, xphys, u, iters: int, every: int, per_solve: int, volfrac=0.3,
     for _ in range(iters):
         rho = xphys.clone()  # density of the system this step solves
         hr, hu = ps.R[start:start + per_solve], ps.E[start:start + per_solve]
-        st = t.simp_step(x, xphys, u, volfrac=volfrac, move=move, harvest=(hr, hu),
-                         harvest_every=every, tol=tol, maxit=maxit, check_every=check_every,
-                         mode="plain_fp64")
-        n = st["solve"]["harvested"]
-        t.nn_make_targets(u, hu, n)  # u now holds this step's solution u*
+        if f is None:
+            st = t.simp_step(x, xphys, u, volfrac=volfrac, move=move, harvest=(hr, hu),
+                             harvest_every=every, tol=tol, maxit=maxit,
+                             check_every=check_every, mode="plain_fp64")
+            n = st["solve"]["harvested"]
+            t.nn_make_targets(u, hu, n)  # u holds this step's solution u*
+        else:
+            u0 = u.clone()  # the warm start of this step's solve
+            st = t.simp_step(x, xphys, u, volfrac=volfrac, move=move, tol=tol, maxit=maxit,
+                             check_every=check_every, mode="plain_fp64")
+            # u* of this step's system (density rho) to the tighter tolerance
+            t.pcg_solve(rho, f, u, tol=min(ref_tol, tol), maxit=maxit,
+                        check_every=check_every, mode="plain_fp64")
+            hst = t.pcg_solve(rho, f, u0, tol=tol, maxit=maxit, mode="plain_fp64",
+                              harvest=(hr, hu), harvest_every=every, harvest_ustar=u)
+            n = hst["harvested"]
+            st["solve"]["harvested"] = n
         ps.density.append(rho)
         ps.groups.append((start, n))
         start += n

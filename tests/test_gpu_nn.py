@@ -416,3 +416,37 @@ def test_fcg_stagnation_restarts_with_jacobi_pcg():
     assert s["fallbacks"] >= k
     assert s["true_rel_residual"] <= 1e-8
     assert rel(u.cpu().numpy(), solvers.solve_direct(Kc, f)) <= 1e-6
+
+
+def test_harvested_targets_are_consistent():
+    """learned.harvest with the reference solve refined to 1e-10: the refined solution
+    has ||b - K u*|| <= 1e-10 ||b|| (FP64); every harvested residual is above the
+    harvesting tolerance (taken before convergence); each stored pair satisfies
+    K e_k - r_k = -r* up to its FP32 storage: ||K e_k - r_k|| <= 1e-8 ||b|| +
+    2^-23 (||r_k|| + ||K|| ||e_k||) with ||K|| <= 8 lambda_max(K_E) max E (each node lies
+    in at most eight elements)."""
+    from paper_2604_18020_amd import learned
+    nx, ny, nz = 12, 6, 6
+    t, fixed, f = gpu_problem(nx, ny, nz)
+    x = torch.full((t.n_elem,), 0.3, dtype=torch.float64, device="cuda:0")
+    xp = x.clone()
+    u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+    b = dev(f)
+    ps, stats = learned.harvest(t, x, xp, u, iters=2, every=7, per_solve=8, f=b, tol=1e-8,
+                                ref_tol=1e-10)
+    bn = float(torch.linalg.norm(b))
+    # the last group's refined solution: u holds u* of its density
+    rstar = b - t.apply_K(ps.density[-1], u)
+    assert float(torch.linalg.norm(rstar)) <= 1.5e-10 * bn
+    knorm = 8.0 * float(np.linalg.eigvalsh(fem.element_stiffness(0.3))[-1])  # E <= 1
+    assert ps.count >= 8
+    for g, (s0, n) in enumerate(ps.groups):
+        rho = ps.density[g]
+        for k in range(s0, s0 + n):
+            r = ps.R[k].double()
+            e = ps.E[k].double()
+            rn, en = float(torch.linalg.norm(r)), float(torch.linalg.norm(e))
+            assert rn > 1e-8 * bn
+            err = float(torch.linalg.norm(t.apply_K(rho, e) - r))
+            assert err <= 1e-8 * bn + 2.0 ** -23 * (rn + knorm * en), (g, k, err)
+    t.close()
