@@ -68,10 +68,13 @@ def kv_bytes(prec: str, n_node: int, n_elem: int) -> int:
     return 2 * 3 * w * n_node + w * n_elem + n_node
 
 
-def time_kv(t, nx, ny, nz, prec, steps, warmup, fixed, seed=42, resident=False):
+def time_kv(t, nx, ny, nz, prec, steps, warmup, fixed, seed=42, resident=False,
+            scatter="owner"):
     """Per-launch HIP-event timing of the operator as the CG iterations apply it.  Buffer
     sets are rotated so that >= 512 MB are touched (the 256 MB Infinity Cache cannot hold
-    them); resident=True uses one set ("MALL-resident" figures)."""
+    them); resident=True uses one set ("MALL-resident" figures).  scatter selects the
+    deterministic default or an atomic-scatter form (whose launch is a clearing pass plus
+    the scatter kernel)."""
     import numpy as np
     import torch
 
@@ -89,7 +92,8 @@ def time_kv(t, nx, ny, nz, prec, steps, warmup, fixed, seed=42, resident=False):
     ys = [torch.empty_like(vs[0]) for _ in range(nset)]
     del rho, v
     for i in range(warmup):
-        t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec, v_zero_on_fixed=True)
+        t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec, v_zero_on_fixed=True,
+                  scatter=scatter)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()  # the library launches on the caller's stream
     # Timed region: `steps` launches back to back, bracketed by synchronisations (wall
@@ -99,7 +103,8 @@ def time_kv(t, nx, ny, nz, prec, steps, warmup, fixed, seed=42, resident=False):
     t0 = time.perf_counter()
     e0.record(stream)
     for i in range(steps):
-        t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec, v_zero_on_fixed=True)
+        t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec, v_zero_on_fixed=True,
+                  scatter=scatter)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -108,7 +113,8 @@ def time_kv(t, nx, ny, nz, prec, steps, warmup, fixed, seed=42, resident=False):
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
     for i in range(steps):
         ev[2 * i].record(stream)
-        t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec, v_zero_on_fixed=True)
+        t.apply_K(xs[i % nset], vs[i % nset], ys[i % nset], prec=prec, v_zero_on_fixed=True,
+                  scatter=scatter)
         ev[2 * i + 1].record(stream)
     torch.cuda.synchronize()
     launch_ms = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)]
@@ -446,6 +452,28 @@ def simp_kernels_study(workload="cantilever_340x170x85", reps=20, sets=4):
     return res
 
 
+def scatter_study(workload="cantilever_340x170x85", steps=100, warmup=10):
+    """The operator's scatter designs side by side on one mesh: owner-computes (the
+    default: every node written once from registers, no atomics) against the atomic
+    scatter of the paper's fused algorithm, as stated (one thread per element, 24 global
+    atomic additions) and reduced per 8x8x4 brick in LDS (global atomics on brick faces
+    only).  Same buffers, same byte count per launch: algorithmic GB/s over the average
+    launch (the atomic forms include their clearing pass)."""
+    t, cfg, _, fixed = _problem(workload)
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+    out = {"workload": workload, "n_elem": t.n_elem, "n_dof": t.n_dof}
+    for prec in ("fp32", "fp64"):
+        for scatter in ("owner", "atomic_brick", "atomic_element"):
+            r = time_kv(t, nx, ny, nz, prec, steps, warmup, fixed, scatter=scatter)
+            gbs = r["bytes"] / (r["batch_ms"] * 1e-3) / 1e9
+            out[f"{prec}_{scatter}"] = {"us_per_launch": r["batch_ms"] * 1e3,
+                                        "median_launch_us": r["median_launch_ms"] * 1e3,
+                                        "algorithmic_gbs": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS,
+                                        "finite": r["finite"]}
+    t.close()
+    return out
+
+
 def pcg_cold_study(workloads=("cantilever_120x60x30", "torsion_55x55x165",
                               "cantilever_200x100x50"), tol=1e-6):
     """Cold-start PCG at uniform density on the other benchmark meshes (the main line
@@ -701,6 +729,9 @@ def main():
     ap.add_argument("--simp-kernels", action="store_true",
                     help="time the SIMP kernels beside the solve on the workload (prints that "
                          "JSON only)")
+    ap.add_argument("--scatter-study", action="store_true",
+                    help="time the owner-computes operator against its atomic-scatter forms "
+                         "on the workload (prints that JSON only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for scaling profiler byte counters)")
     a = ap.parse_args()
@@ -717,13 +748,17 @@ def main():
     if a.presets:
         print(json.dumps({"presets_study": presets_study()}), flush=True)
         return
-    if a.simp_kernels:
+    if a.simp_kernels or a.scatter_study:
         if a.copy_calibration:
             src = torch.empty(2 ** 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
             torch.empty_like(src).copy_(src)
             torch.cuda.synchronize()
             del src
-        print(json.dumps({"simp_kernels_study": simp_kernels_study(a.workload)}), flush=True)
+        if a.scatter_study:
+            print(json.dumps({"scatter_study": scatter_study(a.workload, a.steps, a.warmup)}),
+                  flush=True)
+        else:
+            print(json.dumps({"simp_kernels_study": simp_kernels_study(a.workload)}), flush=True)
         return
     if a.suite:
         print(json.dumps({"kv_study": kv_study()}), flush=True)

@@ -56,6 +56,16 @@ extern "C" {
  * fixed DOF (as for every CG vector); the per-node BC bytes of v's planes are then not
  * read.  The result is bit-identical to the call without the flag for such v.        */
 #define TOSIMP_V_ZERO_ON_FIXED 0x100
+/* Scatter forms of tosimp_apply_K, OR-ed into the precision (FP64 / FP32 only), kept as
+ * measured alternatives to the default owner-computes pass (paper Alg. "Fused
+ * Gather-GEMM-Scatter" scatters with atomic additions).  Both clear y first, then add
+ * element results with atomics; the order of the additions is not fixed, so results
+ * agree with the default to rounding, not bit for bit, and vary from call to call.
+ *   ATOMIC_ELEMENT: one thread per element, 24 global atomic additions per element.
+ *   ATOMIC_BRICK:   8x8x4-element bricks reduced in LDS; only nodes on brick faces use
+ *                   global atomic additions.                                         */
+#define TOSIMP_SCATTER_ATOMIC_ELEMENT 0x200
+#define TOSIMP_SCATTER_ATOMIC_BRICK 0x400
 
 /* ---- filter modes -------------------------------------------------------------- */
 #define TOSIMP_FILTER_FORWARD 0  /* out = H in / Hs                                   */
@@ -201,8 +211,9 @@ int tosimp_counts(const tosimp_ctx* ctx, int64_t* n_elem, int64_t* n_node, int64
  * xphys: n_elem element densities of type xdtype; v, y: n_dof values.  prec selects
  * the arithmetic: PREC_FP64 needs v, y FP64; PREC_FP32 and the MFMA precisions need
  * v, y FP32; it may carry TOSIMP_V_ZERO_ON_FIXED (FP64/FP32 with xdtype of the same
- * width; ignored otherwise).  y is overwritten (not accumulated); y must not overlap v
- * or xphys (EINVAL).                                                                  */
+ * width; ignored otherwise) or one TOSIMP_SCATTER_* flag (FP64 / FP32; EINVAL
+ * otherwise).  y is overwritten (not accumulated); y must not overlap v or xphys
+ * (EINVAL).                                                                           */
 int tosimp_apply_K(tosimp_ctx* ctx, const void* xphys_dev, int xdtype, const void* v_dev,
                    void* y_dev, int prec);
 /* Jacobi diagonal (paper Sec. "Preconditioned Conjugate Gradient"): d = diag(K_c),

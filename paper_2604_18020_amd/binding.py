@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtosimp.so")
 OK, NOT_CONVERGED, FALLBACK_USED = 0, 1, 2
 F64, F32 = 0, 1
 V_ZERO_ON_FIXED = 0x100
+SCATTER = {"owner": 0, "atomic_element": 0x200, "atomic_brick": 0x400}
 PREC = {"fp64": 0, "fp32": 1, "bf16_mfma": 2, "fp16_mfma": 3}
 FILTER = {"forward": 0, "adjoint": 1}
 SOLVE = {"plain_fp64": 0, "ir": 1}
@@ -217,10 +218,11 @@ class Tosimp:
         self._check(LIB.tosimp_set_loads(self._h, self._dev(f, torch.float64, self.n_dof, "f")))
 
     # ------------------------------------------------------------------ operator
-    def apply_K(self, x, v, y=None, prec="fp64", v_zero_on_fixed=False):
-        """v_zero_on_fixed: the caller guarantees v = 0 on fixed DOFs (skips the BC bytes)."""
-        p = PREC[prec]
-        vt = torch.float64 if p == 0 else torch.float32
+    def apply_K(self, x, v, y=None, prec="fp64", v_zero_on_fixed=False, scatter="owner"):
+        """v_zero_on_fixed: the caller guarantees v = 0 on fixed DOFs (skips the BC bytes).
+        scatter: "owner" (deterministic default), "atomic_element" or "atomic_brick"."""
+        p = PREC[prec] | SCATTER[scatter]
+        vt = torch.float64 if PREC[prec] == 0 else torch.float32
         if y is None:
             y = torch.empty_like(v)
         self._sync_stream()

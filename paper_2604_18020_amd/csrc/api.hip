@@ -474,9 +474,13 @@ int tosimp_apply_K(tosimp_ctx* ctx, const void* x, int xdtype, const void* v, vo
   REQUIRE(x && v && y, TOSIMP_EINVAL, "null pointer");
   REQUIRE(xdtype == TOSIMP_F64 || xdtype == TOSIMP_F32, TOSIMP_EINVAL, "bad xdtype");
   const bool vzero = (prec & TOSIMP_V_ZERO_ON_FIXED) != 0;
-  prec &= ~TOSIMP_V_ZERO_ON_FIXED;
+  const int scatter = prec & (TOSIMP_SCATTER_ATOMIC_ELEMENT | TOSIMP_SCATTER_ATOMIC_BRICK);
+  prec &= ~(TOSIMP_V_ZERO_ON_FIXED | TOSIMP_SCATTER_ATOMIC_ELEMENT | TOSIMP_SCATTER_ATOMIC_BRICK);
   REQUIRE(prec >= TOSIMP_PREC_FP64 && prec <= TOSIMP_PREC_FP16_MFMA, TOSIMP_EINVAL,
           "bad precision");
+  REQUIRE(scatter != (TOSIMP_SCATTER_ATOMIC_ELEMENT | TOSIMP_SCATTER_ATOMIC_BRICK) &&
+              (!scatter || prec == TOSIMP_PREC_FP64 || prec == TOSIMP_PREC_FP32),
+          TOSIMP_EINVAL, "one scatter form, FP64 or FP32 only");
   {
     const int64_t vb = ctx->n_dof * (prec == TOSIMP_PREC_FP64 ? 8 : 4);
     const int64_t xb = ctx->n_elem * (xdtype == TOSIMP_F64 ? 8 : 4);
@@ -484,7 +488,9 @@ int tosimp_apply_K(tosimp_ctx* ctx, const void* x, int xdtype, const void* v, vo
             "y must not overlap v or xphys");
   }
   if ((rc = set_device(ctx))) return rc;
-  if (prec == TOSIMP_PREC_BF16_MFMA || prec == TOSIMP_PREC_FP16_MFMA) {
+  if (scatter) {
+    TOSIMP_HIP(ctx, kv_atomic_launch(ctx, prec, xdtype, x, v, y, scatter));
+  } else if (prec == TOSIMP_PREC_BF16_MFMA || prec == TOSIMP_PREC_FP16_MFMA) {
     TOSIMP_HIP(ctx, kv_mfma_launch(ctx, prec, xdtype, x, (const float*)v, (float*)y,
                                    ctx->ws.st, false));
   } else {

@@ -143,6 +143,9 @@ namespace tosimp {
 hipError_t kv_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
                      const void* v, void* y, double* partials, SolverState* st,
                      double* out, int fin, bool guarded, bool premasked = false);
+// Atomic-scatter alternatives (kv_atomic.hip); variant is a TOSIMP_SCATTER_* flag.
+hipError_t kv_atomic_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
+                            const void* v, void* y, int variant);
 hipError_t kv_mfma_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
                           const float* v, float* y, SolverState* st, bool guarded);
 hipError_t launch_apply_K(const tosimp_ctx* c, int prec, int xdtype, const void* x,

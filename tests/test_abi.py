@@ -85,3 +85,17 @@ def test_binding_structures_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_binding_flags_match_the_header():
+    """The flag values the binding OR-s into the operator's precision are the header's."""
+    from paper_2604_18020_amd import binding as b
+    txt = open(os.path.join(ROOT, "include", "tosimp.h")).read()
+    defs = {k: int(v, 0) for k, v in re.findall(r"#define (TOSIMP_\w+) (0x[0-9a-fA-F]+|\d+)", txt)}
+    assert b.V_ZERO_ON_FIXED == defs["TOSIMP_V_ZERO_ON_FIXED"]
+    assert b.SCATTER["atomic_element"] == defs["TOSIMP_SCATTER_ATOMIC_ELEMENT"]
+    assert b.SCATTER["atomic_brick"] == defs["TOSIMP_SCATTER_ATOMIC_BRICK"]
+    assert b.SCATTER["owner"] == 0
+    flags = [defs["TOSIMP_V_ZERO_ON_FIXED"], defs["TOSIMP_SCATTER_ATOMIC_ELEMENT"],
+             defs["TOSIMP_SCATTER_ATOMIC_BRICK"]]
+    assert all(f & 0xff == 0 for f in flags) and len({f for f in flags}) == 3
