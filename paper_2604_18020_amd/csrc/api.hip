@@ -192,7 +192,7 @@ void free_ws(tosimp_ctx* c) {
   nn_release(c);  // the network's tensors are sized for the mesh
   mg_release(c);  // so is the multigrid hierarchy
   Workspace& w = c->ws;
-  void* dev[] = {w.mask, w.f,   w.Hs,  w.dv,  w.fw,  w.dinv, w.dinv32,  w.r,
+  void* dev[] = {w.mask, w.f,   w.Hs,  w.Hsinv, w.dv,  w.fw,  w.dinv, w.dinv32,  w.r,
                  w.p,    w.q,   w.w,   w.r32, w.p32, w.q32,  w.e32,     w.z32,
                  w.x32,  w.etmp, w.partials, w.lanczos, w.st, w.oc, w.ke_mfma};
   for (void* p : dev)
@@ -220,7 +220,8 @@ int set_device(tosimp_ctx* ctx) {
 }
 
 // Cone filter of radius ctx->rmin: weights max(0, rmin - |offset|) on the offset cube,
-// the row sums Hs = H 1 and dv = H (1 / Hs) (the adjoint filter of ones).  Uses etmp.
+// the row sums Hs = H 1, their reciprocals, and dv = H (1 / Hs) (the adjoint filter of
+// ones).  Uses etmp.
 int load_filter(tosimp_ctx* ctx) {
   Workspace& w = ctx->ws;
   ctx->fR = (int)std::ceil(ctx->rmin) - 1;
@@ -237,8 +238,9 @@ int load_filter(tosimp_ctx* ctx) {
   TOSIMP_HIP(ctx, hipMemcpyAsync(w.fw, ctx->fw_host, sizeof(double) * kMaxFilterTaps,
                                  hipMemcpyHostToDevice, ctx->stream));
   TOSIMP_HIP(ctx, launch_filter_rowsum(ctx, w.Hs));
+  TOSIMP_HIP(ctx, launch_reciprocal(ctx, w.Hs, w.Hsinv, ctx->n_elem));
   TOSIMP_HIP(ctx, launch_fill64(ctx, w.etmp, ctx->n_elem, 1.0));
-  TOSIMP_HIP(ctx, launch_filter(ctx, w.etmp, w.dv, TOSIMP_FILTER_ADJOINT, w.Hs));
+  TOSIMP_HIP(ctx, launch_filter(ctx, w.etmp, w.dv, TOSIMP_FILTER_ADJOINT));
   TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return TOSIMP_OK;
 }
@@ -349,6 +351,7 @@ int tosimp_set_mesh(tosimp_ctx* ctx, int nx, int ny, int nz, double h, double E0
   A(dmalloc(&w.mask, nn));
   A(dmalloc(&w.f, nd * 8));
   A(dmalloc(&w.Hs, ne * 8));
+  A(dmalloc(&w.Hsinv, ne * 8));
   A(dmalloc(&w.dv, ne * 8));
   A(dmalloc(&w.fw, sizeof(double) * kMaxFilterTaps));
   A(dmalloc(&w.dinv, nn * 8));
@@ -964,7 +967,7 @@ int tosimp_filter(tosimp_ctx* ctx, const double* in, double* out, int mode) {
   REQUIRE(mode == TOSIMP_FILTER_FORWARD || mode == TOSIMP_FILTER_ADJOINT, TOSIMP_EINVAL,
           "bad filter mode");
   if ((rc = set_device(ctx))) return rc;
-  TOSIMP_HIP(ctx, launch_filter(ctx, in, out, mode, ctx->ws.Hs));
+  TOSIMP_HIP(ctx, launch_filter(ctx, in, out, mode));
   return TOSIMP_OK;
 }
 
@@ -1036,10 +1039,10 @@ int oc_run(tosimp_ctx* ctx, const double* x, const double* dc, const double* dv,
   REQUIRE(w.oc_host->done, TOSIMP_EINVAL, "OC bisection did not terminate");
   TOSIMP_HIP(ctx, launch_oc_final(ctx, x, dc, dv, move, w.oc, x_new, w.partials));
   if (beta > 0) {
-    TOSIMP_HIP(ctx, launch_filter(ctx, x_new, tmp, TOSIMP_FILTER_FORWARD, w.Hs));
+    TOSIMP_HIP(ctx, launch_filter(ctx, x_new, tmp, TOSIMP_FILTER_FORWARD));
     TOSIMP_HIP(ctx, launch_project(ctx, tmp, nullptr, xphys_new, beta, eta));
   } else {
-    TOSIMP_HIP(ctx, launch_filter(ctx, x_new, xphys_new, TOSIMP_FILTER_FORWARD, w.Hs));
+    TOSIMP_HIP(ctx, launch_filter(ctx, x_new, xphys_new, TOSIMP_FILTER_FORWARD));
   }
   TOSIMP_HIP(ctx, hipMemcpyAsync(w.oc_host, w.oc, sizeof(OcState), hipMemcpyDeviceToHost,
                                  ctx->stream));
@@ -1069,13 +1072,13 @@ int design_update(tosimp_ctx* ctx, const double* x, const double* xphys, const d
   const double* dv = w.dv;
   if (beta > 0) {
     TOSIMP_HIP(ctx, launch_project(ctx, xbar, b1, b1, beta, eta));  // dc / dxbar
-    TOSIMP_HIP(ctx, launch_filter(ctx, b1, dcx, TOSIMP_FILTER_ADJOINT, w.Hs));
+    TOSIMP_HIP(ctx, launch_filter(ctx, b1, dcx, TOSIMP_FILTER_ADJOINT));
     TOSIMP_HIP(ctx, launch_fill64(ctx, b1, ctx->n_elem, 1.0));
     TOSIMP_HIP(ctx, launch_project(ctx, xbar, b1, b1, beta, eta));  // dxphys / dxbar
-    TOSIMP_HIP(ctx, launch_filter(ctx, b1, dvx, TOSIMP_FILTER_ADJOINT, w.Hs));
+    TOSIMP_HIP(ctx, launch_filter(ctx, b1, dvx, TOSIMP_FILTER_ADJOINT));
     dv = dvx;
   } else {
-    TOSIMP_HIP(ctx, launch_filter(ctx, b1, dcx, TOSIMP_FILTER_ADJOINT, w.Hs));
+    TOSIMP_HIP(ctx, launch_filter(ctx, b1, dcx, TOSIMP_FILTER_ADJOINT));
   }
   return oc_run(ctx, x, dcx, dv, volfrac, move, beta, eta, x_new, xphys_new, b1, change,
                 steps, volume);
@@ -1143,7 +1146,7 @@ int tosimp_simp_step(tosimp_ctx* ctx, double* x, double* xphys, double* u,
   double* xn = w.etmp + 4 * ne;
   double* xpn = w.etmp + 5 * ne;
   tosimp_step_stats s{};
-  if (o->beta > 0) TOSIMP_HIP(ctx, launch_filter(ctx, x, w.etmp, TOSIMP_FILTER_FORWARD, w.Hs));
+  if (o->beta > 0) TOSIMP_HIP(ctx, launch_filter(ctx, x, w.etmp, TOSIMP_FILTER_FORWARD));
   rc = tosimp_pcg_solve(ctx, xphys, w.f, u, &o->solve, &s.solve);
   if (rc < 0) return rc;
   TOSIMP_HIP(ctx, launch_grayness(ctx, xphys, w.partials, &w.st[2].aux));
@@ -1215,7 +1218,7 @@ int tosimp_simp_protocol(tosimp_ctx* ctx, double* x, double* x_sel, double* xphy
     r.it = it;
     continuation(ph, nph, rmin0, it, &r.penal, &r.beta, &r.move, &r.rmin);
     if ((rc = tosimp_set_params(ctx, r.penal, r.rmin))) return rc;
-    TOSIMP_HIP(ctx, launch_filter(ctx, x, w.etmp, TOSIMP_FILTER_FORWARD, w.Hs));
+    TOSIMP_HIP(ctx, launch_filter(ctx, x, w.etmp, TOSIMP_FILTER_FORWARD));
     TOSIMP_HIP(ctx, launch_project(ctx, w.etmp, nullptr, xphys, r.beta, o->eta));
     tosimp_solve_stats ss{};
     rc = tosimp_pcg_solve(ctx, xphys, w.f, u, &o->solve, &ss);

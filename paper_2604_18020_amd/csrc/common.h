@@ -70,6 +70,7 @@ struct Workspace {
   uint8_t* mask = nullptr;     // n_node: bit c set = DOF 3n+c fixed
   double* f = nullptr;         // n_dof load vector
   double* Hs = nullptr;        // n_elem filter row sums
+  double* Hsinv = nullptr;     // n_elem 1 / Hs
   double* dv = nullptr;        // n_elem H(1/Hs)
   double* fw = nullptr;        // filter weights, (2R+1)^3
   double* dinv = nullptr;      // n_node inverse Jacobi diagonal (FP64)
@@ -157,10 +158,21 @@ hipError_t launch_diag_inv32(const tosimp_ctx* c, const float* x32, float* dinv3
 hipError_t launch_diag_full(const tosimp_ctx* c, int xdtype, const void* x, int dtype,
                             void* d);
 // Multigrid levels: operator with element moduli given and K_E scaled by kscale (v zero
-// on fixed DOFs), and the per-node inverse Jacobi diagonal of such a level.
+// on fixed DOFs), and the per-node inverse Jacobi diagonal of such a level.  With ch
+// (mode 1 / 2) the launch is a whole Chebyshev smoothing step: t = K v stays in
+// registers, dd <- c2 (b - t) dinv (mode 1) or c1 dd + c2 (b - t) dinv (mode 2), and y
+// receives the new iterate v + dd (y, v and dd distinct).
+struct KvCheb {
+  int mode = 0;
+  const void* b = nullptr;
+  void* dd = nullptr;
+  const void* dinv = nullptr;  // per node, of the operator's type
+  double c1 = 0, c2 = 0;
+};
 hipError_t kv_level_launch(const tosimp_ctx* c, int prec, const void* E, const void* v,
                            void* y, int nx, int ny, int nz, const uint8_t* mask,
-                           double kscale, const SolverState* st = nullptr);
+                           double kscale, const SolverState* st = nullptr,
+                           const KvCheb* ch = nullptr);
 
 // Geometric multigrid (mg.hip).  mg_prepare: hierarchy for density x (FP64) with the
 // Chebyshev degree and alpha (0 = defaults 2 and 20, validated); mg_apply: z = V(r) on the
@@ -235,8 +247,9 @@ int nn_fcg_solve(tosimp_ctx* ctx, int prec, const float* x32, const float* b32, 
 // SIMP kernels (topopt.hip).
 hipError_t launch_sensitivity(const tosimp_ctx* c, const double* xphys, const double* u,
                               double* dc);
-hipError_t launch_filter(const tosimp_ctx* c, const double* in, double* out, int mode,
-                         const double* Hs);
+// mode: TOSIMP_FILTER_FORWARD / _ADJOINT with the context's row sums.
+hipError_t launch_filter(const tosimp_ctx* c, const double* in, double* out, int mode);
+hipError_t launch_reciprocal(const tosimp_ctx* c, const double* in, double* out, int64_t n);
 hipError_t launch_filter_rowsum(const tosimp_ctx* c, double* Hs);
 hipError_t launch_project(const tosimp_ctx* c, const double* in, const double* g, double* out,
                           double beta, double eta);

@@ -135,6 +135,21 @@ inline hipError_t launch_finalize_max(hipStream_t s, const double* partials, int
   return hipGetLastError();
 }
 
+// XCD-major item layout for kernels whose items read neighbours one plane of the mesh
+// away: the hardware deals blocks to the 8 XCDs round-robin (block b runs on XCD b % 8),
+// so block b takes slot (b % 8) per_xcd + b / 8 and each XCD sweeps one contiguous range
+// of items; a neighbouring plane is then read by the XCD that already holds it in its L2.
+// Launch 8 per_xcd blocks with per_xcd = ceil(ceil(n / blockDim) / 8); items >= n return.
+__device__ __forceinline__ int64_t xcd_item(int per_xcd) {
+  const int b = blockIdx.x;
+  const int64_t slot = (int64_t)(b & 7) * per_xcd + (b >> 3);
+  return slot * blockDim.x + threadIdx.x;
+}
+
+inline int xcd_per(int64_t n, int threads) {
+  return (int)(((n + threads - 1) / threads + 7) / 8);
+}
+
 template <typename T>
 __device__ __forceinline__ bool finite_val(T v) {
   return v == v && v - v == T(0);

@@ -64,6 +64,13 @@ struct KvArgs {
   T E0mEmin, Emin;
   T penal;
   KvC<T> k;
+  // Chebyshev epilogue of a multigrid smoothing step (EPI > 0): with t = K v at the owned
+  // node, r = eb - t, d = ec2 r edinv (EPI 1) or ec1 edd + ec2 r edinv (EPI 2); edd <- d
+  // and y <- v + d (y is the new iterate, never v itself).
+  const T* eb;
+  T* edd;
+  const T* edinv;  // per node
+  T ec1, ec2;
 };
 
 // Element modulus from the element value xv.  PEN selects the law: kPenPow
@@ -199,12 +206,13 @@ __device__ __forceinline__ void buf_st_node(const double* v, __amdgpu_buffer_rsr
 // PM: v is known to be zero on fixed DOFs (every vector the CG iterations apply K_c to
 // is), so the plane's BC bytes are not loaded and v needs no masking; only the owned
 // node's BC byte is read (fixed rows output y = v = 0).
-template <typename T, typename XT, int PEN, bool DOT, bool PM, int D, int KZMAX>
+template <typename T, typename XT, int PEN, bool DOT, bool PM, int D, int KZMAX, int EPI>
 __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   // Multiply-adds are fused only within one expression, never across statements, so
   // every z step rounds identically whatever was folded away around it (a chunk's first
   // layer starts from zero accumulators): results do not depend on the chunk depth.
 #pragma clang fp contract(on)
+  static_assert(EPI == 0 || (PM && !DOT), "the smoothing epilogue needs v = 0 on fixed DOFs");
   constexpr int NXL = KBX + 1, NYL = KBY + 1, NPN = NXL * NYL;  // nodes of a plane window
   constexpr int NS = (NPN + 255) / 256;                          // node slots per thread
   constexpr int NE = KBX * KBY;
@@ -237,6 +245,9 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   const auto rm = make_rsrc(A.mask, n_node);
   const auto rx = make_rsrc(A.x, (long long)elayer * A.nz * (long long)sizeof(XT));
   const int vplane_bytes = 3 * plane * (int)sizeof(T);
+  const auto reb = make_rsrc(A.eb, EPI ? 3LL * n_node * (long long)sizeof(T) : 0);
+  const auto redd = make_rsrc(A.edd, EPI == 2 ? 3LL * n_node * (long long)sizeof(T) : 0);
+  const auto redi = make_rsrc(A.edinv, EPI ? (long long)n_node * (long long)sizeof(T) : 0);
 
   // Plane-load slots: window node q = tid + 256 s, local (q % NXL, q / NXL).  Lanes of a
   // wave take consecutive nodes of a row, so a wave's loads cover contiguous segments.
@@ -263,6 +274,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   // Out-of-range lanes keep an offset past num_records (the sum stays below 2^32 and the
   // range check is unsigned).
   const unsigned yoffown = owner ? (unsigned)(3 * (ni + NX1 * nj) * (int)sizeof(T)) : (unsigned)kOOB;
+  const int dioffown = owner ? (ni + NX1 * nj) * (int)sizeof(T) : kOOB;
 
   // Register ring of D planes in flight: the plane's node values and BC bytes, the owned
   // node's BC byte, and the density of the element layer below the plane.  The main
@@ -328,6 +340,16 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     mnew = mo;
     __syncthreads();
     issue(v, m, mo, xv, refill);
+    // Epilogue operands of the owned node of plane p-1 (stored at the end of this step).
+    Node3<T> eb_n{}, edd_n{};
+    T edi = T(0);
+    if constexpr (EPI > 0) {
+      if (elem && out) {
+        eb_n = buf_ld_node(A.eb, reb, (int)yoffown, vplane_bytes * (p - 1));
+        if constexpr (EPI == 2) edd_n = buf_ld_node(A.edd, redd, (int)yoffown, vplane_bytes * (p - 1));
+        edi = buf_ld<T>(redi, dioffown, plane * (p - 1) * (int)sizeof(T));
+      }
+    }
     __builtin_amdgcn_sched_barrier(0);
 
     // Forward 2D transform of the top face (plane p) of this element column.
@@ -428,7 +450,21 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
       }
       const int qb = vplane_bytes * (p - 1);
       const auto ryq = make_rsrc32(reinterpret_cast<const char*>(A.y) + qb, ybytes - qb);
-      buf_st_node(yv, ryq, yoffown);
+      if constexpr (EPI == 0) {
+        buf_st_node(yv, ryq, yoffown);
+      } else {
+        T dv[3], xo[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T r = eb_n.c[c] - yv[c];
+          const T d = EPI == 1 ? A.ec2 * (r * edi) : A.ec1 * edd_n.c[c] + A.ec2 * (r * edi);
+          dv[c] = d;
+          xo[c] = vown[c] + d;
+        }
+        buf_st_node(xo, ryq, yoffown);
+        const auto rddq = make_rsrc32(reinterpret_cast<const char*>(A.edd) + qb, ybytes - qb);
+        buf_st_node(dv, rddq, yoffown);
+      }
       if constexpr (DOT) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) dotacc += owner ? (double)vown[c] * (double)yv[c] : 0.0;
@@ -492,17 +528,17 @@ constexpr int kv_depth() { return sizeof(T) == 8 ? 1 : 2; }
 template <typename T>
 constexpr int kv_kzmax() { return sizeof(T) == 8 ? 24 : 16; }
 
-template <typename T, typename XT, int PEN, bool DOT, bool PM>
+template <typename T, typename XT, int PEN, bool DOT, bool PM, int EPI = 0>
 __global__ __launch_bounds__(256) void kv_stream(KvArgs<T, XT> A) {
-  kv_body<T, XT, PEN, DOT, PM, kv_depth<T>(), kv_kzmax<T>()>(A);
+  kv_body<T, XT, PEN, DOT, PM, kv_depth<T>(), kv_kzmax<T>(), EPI>(A);
 }
 
 // Solver variant: skips the whole operator once the solve has finished, so batches of
 // iterations can be enqueued without a host round trip per iteration.
-template <typename T, typename XT, int PEN, bool DOT, bool PM>
+template <typename T, typename XT, int PEN, bool DOT, bool PM, int EPI = 0>
 __global__ __launch_bounds__(256) void kv_stream_guarded(KvArgs<T, XT> A) {
   if (A.st->done) return;
-  kv_body<T, XT, PEN, DOT, PM, kv_depth<T>(), kv_kzmax<T>()>(A);
+  kv_body<T, XT, PEN, DOT, PM, kv_depth<T>(), kv_kzmax<T>(), EPI>(A);
 }
 
 // ------------------------------------------------------------------ host side
@@ -578,9 +614,10 @@ static int resident_blocks(const tosimp_ctx* c, K kernel) {
   return per_cu * num_cus(c);
 }
 
-template <typename T, typename XT, int PEN, bool DOT, bool PM>
+template <typename T, typename XT, int PEN, bool DOT, bool PM, int EPI = 0>
 static hipError_t kv_launch_v(const tosimp_ctx* c, KvArgs<T, XT> A, bool guarded) {
-  auto kern = guarded ? kv_stream_guarded<T, XT, PEN, DOT, PM> : kv_stream<T, XT, PEN, DOT, PM>;
+  auto kern = guarded ? kv_stream_guarded<T, XT, PEN, DOT, PM, EPI>
+                      : kv_stream<T, XT, PEN, DOT, PM, EPI>;
   // Resident blocks per device and kernel instance, computed once (concurrent first calls
   // compute the same value; devices beyond the table are queried every time).
   constexpr int kDevs = 64;
@@ -653,7 +690,7 @@ hipError_t kv_launch(const tosimp_ctx* c, int prec, int xdtype, const void* x,
 template <typename T>
 static hipError_t kv_level_t(const tosimp_ctx* c, const T* E, const T* v, T* y, int nx,
                              int ny, int nz, const uint8_t* mask, double kscale,
-                             const SolverState* st) {
+                             const SolverState* st, const KvCheb* ch) {
   KvArgs<T, T> A{};
   A.v = v; A.y = y; A.x = E; A.mask = mask;
   A.st = const_cast<SolverState*>(st);
@@ -666,17 +703,25 @@ static hipError_t kv_level_t(const tosimp_ctx* c, const T* E, const T* v, T* y, 
   k.bo = (T)(kscale * c->hc.bo); k.cd = (T)(kscale * c->hc.cd);
   k.co = (T)(kscale * c->hc.co); k.hg = (T)(kscale * c->hc.hg);
   A.k = k;
-  return kv_launch_v<T, T, kPenModulus, false, true>(c, A, st != nullptr);
+  if (!ch || ch->mode == 0) return kv_launch_v<T, T, kPenModulus, false, true>(c, A, st != nullptr);
+  A.eb = (const T*)ch->b;
+  A.edd = (T*)ch->dd;
+  A.edinv = (const T*)ch->dinv;
+  A.ec1 = (T)ch->c1;
+  A.ec2 = (T)ch->c2;
+  if (ch->mode == 1) return kv_launch_v<T, T, kPenModulus, false, true, 1>(c, A, st != nullptr);
+  return kv_launch_v<T, T, kPenModulus, false, true, 2>(c, A, st != nullptr);
 }
 
 hipError_t kv_level_launch(const tosimp_ctx* c, int prec, const void* E, const void* v,
                            void* y, int nx, int ny, int nz, const uint8_t* mask,
-                           double kscale, const SolverState* st) {
+                           double kscale, const SolverState* st, const KvCheb* ch) {
+  if (ch && ch->mode != 0 && (y == v || ch->dd == v || ch->dd == y)) return hipErrorInvalidValue;
   if (prec == TOSIMP_PREC_FP64)
     return kv_level_t<double>(c, (const double*)E, (const double*)v, (double*)y, nx, ny, nz,
-                              mask, kscale, st);
+                              mask, kscale, st, ch);
   return kv_level_t<float>(c, (const float*)E, (const float*)v, (float*)y, nx, ny, nz, mask,
-                           kscale, st);
+                           kscale, st, ch);
 }
 
 // ------------------------------------------------------------ Jacobi diagonal

@@ -52,6 +52,7 @@ struct MgLevel {
   void* x = nullptr;   // iterate (coarse levels; level 0: the caller's vector)
   void* t = nullptr;   // operator output
   void* dd = nullptr;  // Chebyshev direction
+  void* xa = nullptr;  // second iterate buffer (fused smoothing steps alternate x / xa)
 };
 
 struct MgState {
@@ -496,6 +497,7 @@ int mg_create_impl(tosimp_ctx* ctx) {
     }
     TOSIMP_HIP(ctx, mg_alloc(&L.t, nd * 8));
     TOSIMP_HIP(ctx, mg_alloc(&L.dd, nd * 8));
+    TOSIMP_HIP(ctx, mg_alloc(&L.xa, nd * 8));
   }
   TOSIMP_HIP(ctx, mg_alloc((void**)&M->Ainv64, (size_t)M->nc * M->nc * 8));
   TOSIMP_HIP(ctx, mg_alloc((void**)&M->Ainv32, (size_t)M->nc * M->nc * 4));
@@ -595,17 +597,32 @@ int vcycle(tosimp_ctx* ctx, MgState* M, int l, const ChebCoef& K, int degree,
   }
   const T* E = lev_E<T>(L);
   const T* dinv = lev_dinv<T>(L);
-  auto Kx = [&]() -> hipError_t {
-    return kv_level_launch(ctx, prec, E, x, t, L.nx, L.ny, L.nz, L.mask, L.kscale, st);
+  // Every smoothing step after a visit's first applies the operator and the Chebyshev
+  // update in one pass (t = K x stays in registers) and writes the new iterate to the
+  // other buffer; 2 degree - 1 such steps per visit, so starting in xa ends in x.
+  T* xs[2] = {x, (T*)L.xa};
+  int cur = 1;
+  auto fused = [&](int mode, double c1, double c2) -> hipError_t {
+    KvCheb ch;
+    ch.mode = mode;
+    ch.b = b;
+    ch.dd = dd;
+    ch.dinv = dinv;
+    ch.c1 = c1;
+    ch.c2 = c2;
+    const hipError_t e = kv_level_launch(ctx, prec, E, xs[cur], xs[cur ^ 1], L.nx, L.ny, L.nz,
+                                         L.mask, L.kscale, st, &ch);
+    cur ^= 1;
+    return e;
   };
   // pre-smoothing from zero
-  cheb_kernel<T, 0><<<g, 256, 0, ctx->stream>>>(b, nullptr, x, dd, dinv, T(0), (T)K.c2[0], nd, st);
-  for (int s = 1; s < degree; ++s) {
-    TOSIMP_HIP(ctx, Kx());
-    cheb_kernel<T, 2><<<g, 256, 0, ctx->stream>>>(b, t, x, dd, dinv, (T)K.c1[s], (T)K.c2[s], nd, st);
-  }
+  cheb_kernel<T, 0><<<g, 256, 0, ctx->stream>>>(b, nullptr, xs[cur], dd, dinv, T(0),
+                                                (T)K.c2[0], nd, st);
+  TOSIMP_HIP(ctx, hipGetLastError());
+  for (int s = 1; s < degree; ++s) TOSIMP_HIP(ctx, fused(2, K.c1[s], K.c2[s]));
   // coarse-grid correction
-  TOSIMP_HIP(ctx, Kx());
+  TOSIMP_HIP(ctx, kv_level_launch(ctx, prec, E, xs[cur], t, L.nx, L.ny, L.nz, L.mask,
+                                  L.kscale, st));
   MgLevel& Cn = M->L[l + 1];
   restrict_residual_kernel<T><<<grid_for(Cn.n_node), 256, 0, ctx->stream>>>(
       b, t, L.nx, L.ny, L.nz, (T*)Cn.b, Cn.mask, Cn.nx, Cn.ny, Cn.nz, st);
@@ -613,16 +630,12 @@ int vcycle(tosimp_ctx* ctx, MgState* M, int l, const ChebCoef& K, int degree,
   int rc = vcycle<T>(ctx, M, l + 1, K, degree, st);
   if (rc) return rc;
   prolong_add_kernel<T><<<grid_for(L.n_node), 256, 0, ctx->stream>>>(
-      x, L.mask, L.nx, L.ny, L.nz, (const T*)Cn.x, Cn.nx, Cn.ny, Cn.nz, st);
+      xs[cur], L.mask, L.nx, L.ny, L.nz, (const T*)Cn.x, Cn.nx, Cn.ny, Cn.nz, st);
   TOSIMP_HIP(ctx, hipGetLastError());
   // post-smoothing from x (same polynomial)
-  TOSIMP_HIP(ctx, Kx());
-  cheb_kernel<T, 1><<<g, 256, 0, ctx->stream>>>(b, t, x, dd, dinv, T(0), (T)K.c2[0], nd, st);
-  for (int s = 1; s < degree; ++s) {
-    TOSIMP_HIP(ctx, Kx());
-    cheb_kernel<T, 2><<<g, 256, 0, ctx->stream>>>(b, t, x, dd, dinv, (T)K.c1[s], (T)K.c2[s], nd, st);
-  }
-  TOSIMP_HIP(ctx, hipGetLastError());
+  TOSIMP_HIP(ctx, fused(1, 0.0, K.c2[0]));
+  for (int s = 1; s < degree; ++s) TOSIMP_HIP(ctx, fused(2, K.c1[s], K.c2[s]));
+  if (cur != 0) return tosimp_fail(ctx, TOSIMP_ESTATE, "multigrid: smoothing parity");
   return TOSIMP_OK;
 }
 
@@ -767,7 +780,7 @@ void mg_release(tosimp_ctx* ctx) {
   if (!M) return;
   for (int l = 0; l < M->nlev; ++l) {
     MgLevel& L = M->L[l];
-    void* ps[] = {L.E64, L.E32, L.dinv64, L.dinv32, L.t, L.dd};
+    void* ps[] = {L.E64, L.E32, L.dinv64, L.dinv32, L.t, L.dd, L.xa};
     for (void* p : ps)
       if (p) (void)hipFree(p);
     if (l > 0) {

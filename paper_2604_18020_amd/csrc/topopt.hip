@@ -15,11 +15,12 @@ namespace tosimp {
 // writing dc_e), so neither carries __restrict__.
 __global__ __launch_bounds__(256) void sensitivity_kernel(
     const double* x, const double* __restrict__ u, double* dc,
-    int nx, int ny, int nz, HadConsts k, double penal, double E0mEmin) {
+    int nx, int ny, int nz, HadConsts k, double penal, double E0mEmin, int per_xcd) {
   const int64_t n_elem = (int64_t)nx * ny * nz;
   const int64_t NX1 = nx + 1, plane = NX1 * (ny + 1);
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_elem;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  {
+    const int64_t e = xcd_item(per_xcd);
+    if (e >= n_elem) return;
     const int ex = (int)(e % nx);
     const int64_t r = e / nx;
     const int ey = (int)(r % ny);
@@ -68,8 +69,9 @@ __global__ __launch_bounds__(256) void sensitivity_kernel(
 
 hipError_t launch_sensitivity(const tosimp_ctx* c, const double* xphys, const double* u,
                               double* dc) {
-  sensitivity_kernel<<<2048, 256, 0, c->stream>>>(xphys, u, dc, c->nx, c->ny, c->nz, c->hc,
-                                                  c->penal, c->E0 - c->Emin);
+  const int per = xcd_per(c->n_elem, 256);
+  sensitivity_kernel<<<8 * per, 256, 0, c->stream>>>(xphys, u, dc, c->nx, c->ny, c->nz, c->hc,
+                                                     c->penal, c->E0 - c->Emin, per);
   return hipGetLastError();
 }
 
@@ -80,11 +82,13 @@ __global__ __launch_bounds__(256) void filter_kernel(const double* __restrict__ 
                                                      double* __restrict__ out,
                                                      const double* __restrict__ Hs,
                                                      const double* __restrict__ w, int R,
-                                                     int nx, int ny, int nz, int mode) {
+                                                     int nx, int ny, int nz, int mode,
+                                                     int per_xcd) {
   const int64_t n_elem = (int64_t)nx * ny * nz;
   const int W = 2 * R + 1;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_elem;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  {
+    const int64_t e = xcd_item(per_xcd);
+    if (e >= n_elem) return;
     const int ex = (int)(e % nx);
     const int64_t r = e / nx;
     const int ey = (int)(r % ny);
@@ -112,16 +116,90 @@ __global__ __launch_bounds__(256) void filter_kernel(const double* __restrict__ 
   }
 }
 
-hipError_t launch_filter(const tosimp_ctx* c, const double* in, double* out, int mode,
-                         const double* Hs) {
-  filter_kernel<<<2048, 256, 0, c->stream>>>(in, out, Hs, c->ws.fw, c->fR, c->nx, c->ny,
-                                             c->nz, mode);
+// Radius-one filter (rmin in (1, 2]: the 27-point offset cube), the common case.  Branch
+// free: every tap loads a neighbour clamped into the mesh and takes weight 0 outside it,
+// so all loads of an element are in flight together; the weights sit in scalar
+// registers; the adjoint and the normalisation multiply by 1 / Hs instead of dividing.
+// mode as filter_kernel (forward, adjoint).
+struct Taps27 {
+  double w[27];
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void filter27_kernel(const double* __restrict__ in,
+                                                       double* __restrict__ out,
+                                                       const double* __restrict__ hinv,
+                                                       Taps27 tw, int nx, int ny, int nz,
+                                                       int per_xcd) {
+  const int n_elem = nx * ny * nz;  // < 2^31 (the mesh limit)
+  const int64_t e64 = xcd_item(per_xcd);
+  if (e64 >= n_elem) return;
+  const int e = (int)e64;
+  const int ex = e % nx, r = e / nx;
+  const int ey = r % ny, ez = r / ny;
+  int cx[3], cy[3], cz[3];
+  bool ox[3], oy[3], oz[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int jx = ex + d - 1, jy = ey + d - 1, jz = ez + d - 1;
+    ox[d] = jx >= 0 && jx < nx;
+    oy[d] = jy >= 0 && jy < ny;
+    oz[d] = jz >= 0 && jz < nz;
+    cx[d] = ox[d] ? jx : ex;
+    cy[d] = oy[d] ? jy : ey;
+    cz[d] = oz[d] ? jz : ez;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int dk = 0; dk < 3; ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 3; ++dj) {
+      const int row = nx * (cy[dj] + ny * cz[dk]);
+#pragma unroll
+      for (int di = 0; di < 3; ++di) {
+        const int j = row + cx[di];
+        const double wt = (ox[di] && oy[dj] && oz[dk]) ? tw.w[di + 3 * (dj + 3 * dk)] : 0.0;
+        const double v = MODE == TOSIMP_FILTER_ADJOINT ? in[j] * hinv[j] : in[j];
+        s = fma(wt, v, s);
+      }
+    }
+  out[e] = MODE == TOSIMP_FILTER_FORWARD ? s * hinv[e] : s;
+}
+
+hipError_t launch_filter(const tosimp_ctx* c, const double* in, double* out, int mode) {
+  const int per = xcd_per(c->n_elem, 256);
+  if (c->fR == 1) {
+    Taps27 tw;
+    for (int i = 0; i < 27; ++i) tw.w[i] = c->fw_host[i];
+    if (mode == TOSIMP_FILTER_ADJOINT)
+      filter27_kernel<TOSIMP_FILTER_ADJOINT><<<8 * per, 256, 0, c->stream>>>(
+          in, out, c->ws.Hsinv, tw, c->nx, c->ny, c->nz, per);
+    else
+      filter27_kernel<TOSIMP_FILTER_FORWARD><<<8 * per, 256, 0, c->stream>>>(
+          in, out, c->ws.Hsinv, tw, c->nx, c->ny, c->nz, per);
+    return hipGetLastError();
+  }
+  filter_kernel<<<8 * per, 256, 0, c->stream>>>(in, out, c->ws.Hs, c->ws.fw, c->fR, c->nx,
+                                                c->ny, c->nz, mode, per);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void reciprocal_kernel(const double* __restrict__ in,
+                                                         double* __restrict__ out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = 1.0 / in[i];
+}
+
+hipError_t launch_reciprocal(const tosimp_ctx* c, const double* in, double* out, int64_t n) {
+  reciprocal_kernel<<<2048, 256, 0, c->stream>>>(in, out, n);
   return hipGetLastError();
 }
 
 hipError_t launch_filter_rowsum(const tosimp_ctx* c, double* Hs) {
-  filter_kernel<<<2048, 256, 0, c->stream>>>(nullptr, Hs, nullptr, c->ws.fw, c->fR, c->nx,
-                                             c->ny, c->nz, 2);
+  const int per = xcd_per(c->n_elem, 256);
+  filter_kernel<<<8 * per, 256, 0, c->stream>>>(nullptr, Hs, nullptr, c->ws.fw, c->fR, c->nx,
+                                                c->ny, c->nz, 2, per);
   return hipGetLastError();
 }
 

@@ -34,8 +34,12 @@ def test_sensitivity_matches_oracle(dims):
     assert abs(c - prob.f @ u) <= 1e-12 * abs(prob.f @ u)
 
 
-@pytest.mark.parametrize("dims,rmin", [((16, 8, 8), 1.5), ((13, 7, 9), 2.5), ((5, 4, 3), 1.0)])
+@pytest.mark.parametrize("dims,rmin", [((16, 8, 8), 1.5), ((13, 7, 9), 2.5), ((5, 4, 3), 1.0),
+                                       ((11, 6, 7), 2.0), ((1, 1, 1), 1.5), ((1, 5, 2), 1.5),
+                                       ((40, 3, 1), 1.8)])
 def test_filter_matches_oracle(dims, rmin):
+    """Radius one (rmin in (1, 2]: 27-point cube, corner taps weighted for rmin > sqrt 3)
+    and the general kernel (rmin 1, 2.5), on meshes one element thick along some axes."""
     nx, ny, nz = dims
     H, Hs = topopt.filter_matrix(nx, ny, nz, rmin)
     t, _, _ = gpu_problem(nx, ny, nz, rmin=rmin)
