@@ -116,69 +116,102 @@ __global__ __launch_bounds__(256) void filter_kernel(const double* __restrict__ 
   }
 }
 
-// Radius-one filter (rmin in (1, 2]: the 27-point offset cube), the common case.  Branch
-// free: every tap loads a neighbour clamped into the mesh and takes weight 0 outside it,
-// so all loads of an element are in flight together; the weights sit in scalar
-// registers; the adjoint and the normalisation multiply by 1 / Hs instead of dividing.
-// mode as filter_kernel (forward, adjoint).
-struct Taps27 {
-  double w[27];
-};
+// Radius-one filter (rmin in (1, 2]: the 27-point offset cube), the common case.  The cone
+// weight depends only on the distance, so with w0..w3 the weights at distance 0, 1, sqrt 2
+// and sqrt 3, and per plane z the centre value c, the sum F of its four in-plane face
+// neighbours and the sum G of its four in-plane diagonal neighbours,
+//   A(z) = w0 c + w1 F + w2 G   (the plane's own contribution),
+//   B(z) = w1 c + w2 F + w3 G   (its contribution to the planes above and below),
+// and the filtered value is B(z-1) + A(z) + B(z+1).  A block sweeps a 64 x 4 element tile
+// up a chunk of z planes, staging each plane with a one-element halo in LDS (values
+// outside the mesh staged as 0); the adjoint stages in / Hs, the forward multiplies the
+// sum by 1 / Hs.
+constexpr int kFtX = 64, kFtY = 4, kFtKz = 8;
+constexpr int kFwX = kFtX + 2, kFwY = kFtY + 2, kFwin = kFwX * kFwY;  // 396 staged values
 
 template <int MODE>
-__global__ __launch_bounds__(256) void filter27_kernel(const double* __restrict__ in,
-                                                       double* __restrict__ out,
-                                                       const double* __restrict__ hinv,
-                                                       Taps27 tw, int nx, int ny, int nz,
-                                                       int per_xcd) {
-  const int n_elem = nx * ny * nz;  // < 2^31 (the mesh limit)
-  const int64_t e64 = xcd_item(per_xcd);
-  if (e64 >= n_elem) return;
-  const int e = (int)e64;
-  const int ex = e % nx, r = e / nx;
-  const int ey = r % ny, ez = r / ny;
-  int cx[3], cy[3], cz[3];
-  bool ox[3], oy[3], oz[3];
+__global__ __launch_bounds__(256) void filter_sweep_kernel(const double* __restrict__ in,
+                                                           double* __restrict__ out,
+                                                           const double* __restrict__ hinv,
+                                                           double w0, double w1, double w2,
+                                                           double w3, int nx, int ny, int nz,
+                                                           int tiles_x, int tiles_y,
+                                                           int ntiles, int per_xcd) {
+  __shared__ double sp[2][kFwin];
+  const int bid = blockIdx.x;
+  const int t = (bid & 7) * per_xcd + (bid >> 3);  // contiguous tile range per XCD
+  if (t >= ntiles) return;
+  const int tx = t % tiles_x, rest = t / tiles_x;
+  const int ty = rest % tiles_y, cz = rest / tiles_y;
+  const int x0 = tx * kFtX - 1, y0 = ty * kFtY - 1;
+  const int k0 = cz * kFtKz, k1 = min(k0 + kFtKz, nz);  // output planes [k0, k1)
+  const int tid = threadIdx.x;
+  const int lx = tid % kFtX, ly = tid / kFtX;
+  const int ex = x0 + 1 + lx, ey = y0 + 1 + ly;
+  const bool own = ex < nx && ey < ny;
+  const int layer = nx * ny;
+  // staged slots of this thread (two per plane at most: 396 values over 256 threads)
+  int soff[2];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int jx = ex + d - 1, jy = ey + d - 1, jz = ez + d - 1;
-    ox[d] = jx >= 0 && jx < nx;
-    oy[d] = jy >= 0 && jy < ny;
-    oz[d] = jz >= 0 && jz < nz;
-    cx[d] = ox[d] ? jx : ex;
-    cy[d] = oy[d] ? jy : ey;
-    cz[d] = oz[d] ? jz : ez;
+  for (int s = 0; s < 2; ++s) {
+    const int q = tid + 256 * s;
+    const int i = x0 + q % kFwX, j = y0 + q / kFwX;
+    soff[s] = (q < kFwin && i >= 0 && i < nx && j >= 0 && j < ny) ? i + nx * j : -1;
   }
-  double s = 0.0;
+  double Bm2 = 0.0, Am1 = 0.0, Bm1 = 0.0;  // B(z-2), A(z-1), B(z-1)
+  for (int z = k0 - 1; z <= k1; ++z) {
+    double* P = sp[(z - k0 + 1) & 1];
+    const bool zin = z >= 0 && z < nz;
 #pragma unroll
-  for (int dk = 0; dk < 3; ++dk)
-#pragma unroll
-    for (int dj = 0; dj < 3; ++dj) {
-      const int row = nx * (cy[dj] + ny * cz[dk]);
-#pragma unroll
-      for (int di = 0; di < 3; ++di) {
-        const int j = row + cx[di];
-        const double wt = (ox[di] && oy[dj] && oz[dk]) ? tw.w[di + 3 * (dj + 3 * dk)] : 0.0;
-        const double v = MODE == TOSIMP_FILTER_ADJOINT ? in[j] * hinv[j] : in[j];
-        s = fma(wt, v, s);
+    for (int s = 0; s < 2; ++s) {
+      const int q = tid + 256 * s;
+      if (q < kFwin) {
+        double v = 0.0;
+        if (zin && soff[s] >= 0) {
+          const int j = soff[s] + layer * z;
+          v = MODE == TOSIMP_FILTER_ADJOINT ? in[j] * hinv[j] : in[j];
+        }
+        P[q] = v;
       }
     }
-  out[e] = MODE == TOSIMP_FILTER_FORWARD ? s * hinv[e] : s;
+    __syncthreads();
+    const int q = (ly + 1) * kFwX + lx + 1;
+    const double c = P[q];
+    const double F = (P[q - 1] + P[q + 1]) + (P[q - kFwX] + P[q + kFwX]);
+    const double G = (P[q - kFwX - 1] + P[q - kFwX + 1]) + (P[q + kFwX - 1] + P[q + kFwX + 1]);
+    const double A = w0 * c + w1 * F + w2 * G;
+    const double B = w1 * c + w2 * F + w3 * G;
+    // plane z - 1 is complete: B(z-2) + A(z-1) + B(z)
+    if (z - 1 >= k0 && own) {
+      const int e = ex + nx * ey + layer * (z - 1);
+      const double sum = Bm2 + Am1 + B;
+      out[e] = MODE == TOSIMP_FILTER_FORWARD ? sum * hinv[e] : sum;
+    }
+    Bm2 = Bm1;
+    Am1 = A;
+    Bm1 = B;
+    // the other buffer is rewritten next step; this one two steps on, after the next
+    // barrier, so one barrier per plane suffices
+  }
 }
 
 hipError_t launch_filter(const tosimp_ctx* c, const double* in, double* out, int mode) {
-  const int per = xcd_per(c->n_elem, 256);
   if (c->fR == 1) {
-    Taps27 tw;
-    for (int i = 0; i < 27; ++i) tw.w[i] = c->fw_host[i];
+    // weights at distance 0, 1, sqrt 2, sqrt 3 (offset-cube layout di + 3 (dj + 3 dk))
+    const double w0 = c->fw_host[13], w1 = c->fw_host[14], w2 = c->fw_host[17],
+                 w3 = c->fw_host[26];
+    const int tiles_x = (c->nx + kFtX - 1) / kFtX, tiles_y = (c->ny + kFtY - 1) / kFtY;
+    const int ntiles = tiles_x * tiles_y * ((c->nz + kFtKz - 1) / kFtKz);
+    const int per = (ntiles + 7) / 8;
     if (mode == TOSIMP_FILTER_ADJOINT)
-      filter27_kernel<TOSIMP_FILTER_ADJOINT><<<8 * per, 256, 0, c->stream>>>(
-          in, out, c->ws.Hsinv, tw, c->nx, c->ny, c->nz, per);
+      filter_sweep_kernel<TOSIMP_FILTER_ADJOINT><<<8 * per, 256, 0, c->stream>>>(
+          in, out, c->ws.Hsinv, w0, w1, w2, w3, c->nx, c->ny, c->nz, tiles_x, tiles_y, ntiles, per);
     else
-      filter27_kernel<TOSIMP_FILTER_FORWARD><<<8 * per, 256, 0, c->stream>>>(
-          in, out, c->ws.Hsinv, tw, c->nx, c->ny, c->nz, per);
+      filter_sweep_kernel<TOSIMP_FILTER_FORWARD><<<8 * per, 256, 0, c->stream>>>(
+          in, out, c->ws.Hsinv, w0, w1, w2, w3, c->nx, c->ny, c->nz, tiles_x, tiles_y, ntiles, per);
     return hipGetLastError();
   }
+  const int per = xcd_per(c->n_elem, 256);
   filter_kernel<<<8 * per, 256, 0, c->stream>>>(in, out, c->ws.Hs, c->ws.fw, c->fR, c->nx,
                                                 c->ny, c->nz, mode, per);
   return hipGetLastError();
