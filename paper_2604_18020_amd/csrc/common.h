@@ -161,13 +161,15 @@ hipError_t launch_diag_full(const tosimp_ctx* c, int xdtype, const void* x, int 
 // on fixed DOFs), and the per-node inverse Jacobi diagonal of such a level.  With ch
 // (mode 1 / 2) the launch is a whole Chebyshev smoothing step: t = K v stays in
 // registers, dd <- c2 (b - t) dinv (mode 1) or c1 dd + c2 (b - t) dinv (mode 2), and y
-// receives the new iterate v + dd (y, v and dd distinct).
+// receives the new iterate v + dd (y, v and dd distinct).  Mode 3 is the first two steps
+// from a zero iterate in one pass: v must be b, the operator acts on x1 = c0 b dinv
+// (formed while staging), and the update is mode 2's with dd = x1.
 struct KvCheb {
   int mode = 0;
   const void* b = nullptr;
   void* dd = nullptr;
   const void* dinv = nullptr;  // per node, of the operator's type
-  double c1 = 0, c2 = 0;
+  double c0 = 0, c1 = 0, c2 = 0;
 };
 hipError_t kv_level_launch(const tosimp_ctx* c, int prec, const void* E, const void* v,
                            void* y, int nx, int ny, int nz, const uint8_t* mask,

@@ -66,11 +66,13 @@ struct KvArgs {
   KvC<T> k;
   // Chebyshev epilogue of a multigrid smoothing step (EPI > 0): with t = K v at the owned
   // node, r = eb - t, d = ec2 r edinv (EPI 1) or ec1 edd + ec2 r edinv (EPI 2); edd <- d
-  // and y <- v + d (y is the new iterate, never v itself).
+  // and y <- v + d (y is the new iterate, never v itself).  EPI 3 is a visit's first two
+  // steps from a zero iterate: the operand is formed while staging, v = ec0 (v_in
+  // edinv) with v_in = eb, and the epilogue is EPI 2's with edd = v.
   const T* eb;
   T* edd;
   const T* edinv;  // per node
-  T ec1, ec2;
+  T ec0, ec1, ec2;
 };
 
 // Element modulus from the element value xv.  PEN selects the law: kPenPow
@@ -251,7 +253,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
 
   // Plane-load slots: window node q = tid + 256 s, local (q % NXL, q / NXL).  Lanes of a
   // wave take consecutive nodes of a row, so a wave's loads cover contiguous segments.
-  int voff[NS], moff[NS];
+  int voff[NS], moff[NS], doff[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int q = tid + 256 * s;
@@ -261,6 +263,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     const int node = i + NX1 * j;
     voff[s] = ok ? 3 * node * (int)sizeof(T) : kOOB;
     moff[s] = ok ? node : kOOB;
+    doff[s] = ok ? node * (int)sizeof(T) : kOOB;
   }
   // Element column of this thread.
   const int ex = ex0 + lx, ey = ey0 + ly;
@@ -285,12 +288,14 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   uint8_t pm[D][NS];
   uint8_t po[D];
   XT px[D];
-  auto issue = [&](Node3<T>* v, uint8_t* m, uint8_t& mo, XT& xv, int k) {
+  T pd[D][NS];  // EPI 3: per-node scale of the staged operand
+  auto issue = [&](Node3<T>* v, uint8_t* m, uint8_t& mo, XT& xv, T* d, int k) {
     const int kc = min(max(k, 0), A.nz);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if constexpr (!PM) m[s] = buf_ld_u8(rm, moff[s], plane * kc);
       v[s] = buf_ld_node(A.v, rv, voff[s], vplane_bytes * kc);
+      if constexpr (EPI == 3) d[s] = buf_ld<T>(redi, doff[s], plane * kc * (int)sizeof(T));
     }
     mo = buf_ld_u8(rm, moffown, plane * kc);
     const int ez = min(max(k - 1, 0), A.nz - 1);
@@ -314,9 +319,9 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   T ya[3];  // upper-row corner pair of the owned node, kept across the barrier
   // One z step at node plane p: stage the plane, transform the top face, and (when
   // ELEM) apply element layer p-1 and (when OUT) emit node plane p-1.
-  auto step = [&](int p, Node3<T>* v, uint8_t* m, uint8_t& mo, XT& xv, const T* tb, T* tt,
-                  const T* vown, T* vnew, uint8_t mown, uint8_t& mnew, bool elem, bool out,
-                  int refill) {
+  auto step = [&](int p, Node3<T>* v, uint8_t* m, uint8_t& mo, XT& xv, T* d, const T* tb,
+                  T* tt, const T* vown, T* vnew, uint8_t mown, uint8_t& mnew, bool elem,
+                  bool out, int refill) {
     // Keep each step's instructions inside its own region: the scheduler must not hoist
     // a later step's use of a ring slot above this step (that would wait on a fresh load).
     __builtin_amdgcn_sched_barrier(0);
@@ -328,7 +333,9 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
       if (s > 0 && q >= NPN) continue;  // the second slot covers the window's last nodes
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        if constexpr (PM) {
+        if constexpr (EPI == 3) {
+          sv[q][c] = force ? T(0) : A.ec0 * (v[s].c[c] * d[s]);
+        } else if constexpr (PM) {
           sv[q][c] = force ? T(0) : v[s].c[c];
         } else {
           sv[q][c] = (((m[s] | force) >> c) & 1) ? T(0) : v[s].c[c];
@@ -339,7 +346,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     const XT xcur = xv;
     mnew = mo;
     __syncthreads();
-    issue(v, m, mo, xv, refill);
+    issue(v, m, mo, xv, d, refill);
     // Epilogue operands of the owned node of plane p-1 (stored at the end of this step).
     Node3<T> eb_n{}, edd_n{};
     T edi = T(0);
@@ -457,7 +464,8 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const T r = eb_n.c[c] - yv[c];
-          const T d = EPI == 1 ? A.ec2 * (r * edi) : A.ec1 * edd_n.c[c] + A.ec2 * (r * edi);
+          const T dprev = EPI == 3 ? vown[c] : edd_n.c[c];
+          const T d = EPI == 1 ? A.ec2 * (r * edi) : A.ec1 * dprev + A.ec2 * (r * edi);
           dv[c] = d;
           xo[c] = vown[c] + d;
         }
@@ -474,7 +482,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
 
   // Prologue: fill the ring with planes k0-1 .. k0+D-2.
 #pragma unroll
-  for (int s = 0; s < D; ++s) issue(pv[s], pm[s], po[s], px[s], k0 - 1 + s);
+  for (int s = 0; s < D; ++s) issue(pv[s], pm[s], po[s], px[s], pd[s], k0 - 1 + s);
   // Fully unrolled z sweep (no loop back-edge, so no register copies of in-flight
   // loads): step i handles plane k0-1+i; plane k0-1 only seeds the bottom face, plane
   // k0 applies layer k0-1 (plane k0-1 is not owned), later steps emit the plane below.
@@ -484,11 +492,11 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
     if (p > k1) break;
     const int refill = min(p + D, k1);
     if (i % 2 == 0)
-      step(p, pv[i % D], pm[i % D], po[i % D], px[i % D], TA, TB, VA, VB, MA, MB, i >= 1,
-           i >= 2, refill);
+      step(p, pv[i % D], pm[i % D], po[i % D], px[i % D], pd[i % D], TA, TB, VA, VB, MA, MB,
+           i >= 1, i >= 2, refill);
     else
-      step(p, pv[i % D], pm[i % D], po[i % D], px[i % D], TB, TA, VB, VA, MB, MA, i >= 1,
-           i >= 2, refill);
+      step(p, pv[i % D], pm[i % D], po[i % D], px[i % D], pd[i % D], TB, TA, VB, VA, MB, MA,
+           i >= 1, i >= 2, refill);
   }
 
   if constexpr (DOT) {
@@ -707,9 +715,11 @@ static hipError_t kv_level_t(const tosimp_ctx* c, const T* E, const T* v, T* y, 
   A.eb = (const T*)ch->b;
   A.edd = (T*)ch->dd;
   A.edinv = (const T*)ch->dinv;
+  A.ec0 = (T)ch->c0;
   A.ec1 = (T)ch->c1;
   A.ec2 = (T)ch->c2;
   if (ch->mode == 1) return kv_launch_v<T, T, kPenModulus, false, true, 1>(c, A, st != nullptr);
+  if (ch->mode == 3) return kv_launch_v<T, T, kPenModulus, false, true, 3>(c, A, st != nullptr);
   return kv_launch_v<T, T, kPenModulus, false, true, 2>(c, A, st != nullptr);
 }
 

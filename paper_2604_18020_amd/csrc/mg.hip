@@ -599,7 +599,8 @@ int vcycle(tosimp_ctx* ctx, MgState* M, int l, const ChebCoef& K, int degree,
   const T* dinv = lev_dinv<T>(L);
   // Every smoothing step after a visit's first applies the operator and the Chebyshev
   // update in one pass (t = K x stays in registers) and writes the new iterate to the
-  // other buffer; 2 degree - 1 such steps per visit, so starting in xa ends in x.
+  // other buffer; 2 degree - 1 such passes per visit (the first one also forms the first
+  // step's iterate), so starting in xa ends in x.
   T* xs[2] = {x, (T*)L.xa};
   int cur = 1;
   auto fused = [&](int mode, double c1, double c2) -> hipError_t {
@@ -615,11 +616,26 @@ int vcycle(tosimp_ctx* ctx, MgState* M, int l, const ChebCoef& K, int degree,
     cur ^= 1;
     return e;
   };
-  // pre-smoothing from zero
-  cheb_kernel<T, 0><<<g, 256, 0, ctx->stream>>>(b, nullptr, xs[cur], dd, dinv, T(0),
-                                                (T)K.c2[0], nd, st);
-  TOSIMP_HIP(ctx, hipGetLastError());
-  for (int s = 1; s < degree; ++s) TOSIMP_HIP(ctx, fused(2, K.c1[s], K.c2[s]));
+  // pre-smoothing from zero: the first two steps in one pass (the first step's iterate
+  // c2 D^-1 b is formed while the operator stages its planes)
+  if (degree >= 2) {
+    KvCheb ch;
+    ch.mode = 3;
+    ch.b = b;
+    ch.dd = dd;
+    ch.dinv = dinv;
+    ch.c0 = K.c2[0];
+    ch.c1 = K.c1[1];
+    ch.c2 = K.c2[1];
+    TOSIMP_HIP(ctx, kv_level_launch(ctx, prec, E, b, xs[cur ^ 1], L.nx, L.ny, L.nz, L.mask,
+                                    L.kscale, st, &ch));
+    cur ^= 1;
+  } else {
+    cheb_kernel<T, 0><<<g, 256, 0, ctx->stream>>>(b, nullptr, xs[cur], dd, dinv, T(0),
+                                                  (T)K.c2[0], nd, st);
+    TOSIMP_HIP(ctx, hipGetLastError());
+  }
+  for (int s = 2; s < degree; ++s) TOSIMP_HIP(ctx, fused(2, K.c1[s], K.c2[s]));
   // coarse-grid correction
   TOSIMP_HIP(ctx, kv_level_launch(ctx, prec, E, xs[cur], t, L.nx, L.ny, L.nz, L.mask,
                                   L.kscale, st));
