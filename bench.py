@@ -40,13 +40,13 @@ HBM_PEAK_GBS = 8000.0
 # valid only for the kernel sources they were taken with (sha256 of kv.hip, dev.h,
 # common.h); reported as null once those change.
 KV_TRAFFIC = {
-    "fp32": (2.0 * 49076.1 + 59118.0) * 1024,
-    "fp64": (2.0 * 94457.4 + 118070.1) * 1024,
+    "fp32": (2.0 * 49084.5 + 59116.0) * 1024,
+    "fp64": (2.0 * 94465.2 + 118065.4) * 1024,
 }
 KV_TRAFFIC_SOURCES = {
-    "kv.hip": "7f5bee66ad024f9c6ec5db9f16379d19d0208163de17f5a69eb4146aeb0a8a6f",
-    "dev.h": "914e569c6016d8856a85207550abda3abeb3299f20de5017738d7e883af47280",
-    "common.h": "e885e249916ffef45216d1150dea48af681037008edba1c03b4bad268ed6845b",
+    "kv.hip": "7226e9ecdd6cca4c4766a8fcc63edb3d6b1d67a926cb45049b0f4c8e0312335f",
+    "dev.h": "4f632875059f48985c77a57385922168b780fadc82dea0f30fd122a0d3fb5beb",
+    "common.h": "efb0f107021d1ccb1383e6c68c75db9750482396fa6cf12956ac583fc046fe31",
 }
 
 
@@ -474,6 +474,26 @@ def scatter_study(workload="cantilever_340x170x85", steps=100, warmup=10):
     return out
 
 
+def mg_study(workload="cantilever_340x170x85", reps=3, tol=1e-6, volfrac=0.3):
+    """Cold-start multigrid-preconditioned CG at uniform density (the fastest solves of
+    the PCG leg) repeated on one mesh: plain FP64 and FP64 refinement around FP32, best of
+    `reps` wall times with iteration counts."""
+    import torch
+
+    t, cfg, f, _ = _problem(workload)
+    x = torch.full((t.n_elem,), volfrac, dtype=torch.float64, device="cuda:0")
+    out = {"workload": workload, "tol": tol, "density": volfrac}
+    for mode in ("plain_fp64", "ir"):
+        best = None
+        for _ in range(reps):
+            _, r = _solve_timed(t, x, f, tol, mode=mode, precond="mg", check_every=4)
+            if best is None or r["seconds"] < best["seconds"]:
+                best = r
+        out[mode] = best
+    t.close()
+    return out
+
+
 def pcg_cold_study(workloads=("cantilever_120x60x30", "torsion_55x55x165",
                               "cantilever_200x100x50"), tol=1e-6):
     """Cold-start PCG at uniform density on the other benchmark meshes (the main line
@@ -729,6 +749,9 @@ def main():
     ap.add_argument("--simp-kernels", action="store_true",
                     help="time the SIMP kernels beside the solve on the workload (prints that "
                          "JSON only)")
+    ap.add_argument("--mg-study", action="store_true",
+                    help="time the multigrid-preconditioned CG solves on the workload (prints "
+                         "that JSON only)")
     ap.add_argument("--scatter-study", action="store_true",
                     help="time the owner-computes operator against its atomic-scatter forms "
                          "on the workload (prints that JSON only)")
@@ -747,6 +770,9 @@ def main():
 
     if a.presets:
         print(json.dumps({"presets_study": presets_study()}), flush=True)
+        return
+    if a.mg_study:
+        print(json.dumps({"mg_study": mg_study(a.workload)}), flush=True)
         return
     if a.simp_kernels or a.scatter_study:
         if a.copy_calibration:

@@ -706,9 +706,9 @@ int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T
   TOSIMP_HIP(ctx, launch_finalize_sum<2>(ctx->stream, part, kRedBlocks, MgInitFin{st}));
   if (check_every < 1) check_every = 1;
   const int g = grid_for(n);
-  // One batch of check_every iterations (every kernel returns at once after convergence).
-  auto batch = [&]() -> int {
-    for (int i = 0; i < check_every; ++i) {
+  // One batch of k iterations (every kernel returns at once after convergence).
+  auto batch = [&](int k) -> int {
+    for (int i = 0; i < k; ++i) {
       int rc = mg_apply<T>(ctx, r, z, degree, alpha, st);
       if (rc) return rc;
       dot_rz_kernel<T><<<g, kRedThreads, 0, ctx->stream>>>(r, z, n, st, part);
@@ -720,39 +720,61 @@ int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T
     }
     return TOSIMP_OK;
   };
-  // After one eager batch the batch is captured once into a HIP graph and replayed: a
-  // V-cycle is a few hundred small launches, which bound the iteration on small meshes.
-  // The graph holds only this library's kernels (no memset or copy nodes).
-  hipGraphExec_t exec = nullptr;
+  // Batch sizes: check_every and its halvings down to 1.  The first batch has the full
+  // size; after it, each batch is the smallest size that covers the iterations the
+  // observed contraction of ||r||^2 per iteration still needs, so that few iterations are
+  // enqueued past convergence (they return at once, but each of their launches still
+  // costs a few microseconds).  After one eager batch, each size is captured into its own
+  // HIP graph on first use and replayed: a V-cycle is a few dozen launches, which bound
+  // the iteration on small meshes.  The graphs hold only this library's kernels (no
+  // memset or copy nodes).
+  std::vector<int> sizes;
+  for (int k = check_every; k >= 1; k /= 2) sizes.push_back(k);
+  std::vector<hipGraphExec_t> execs(sizes.size(), nullptr);
   struct ExecGuard {
-    hipGraphExec_t* e;
+    std::vector<hipGraphExec_t>* e;
     ~ExecGuard() {
-      if (*e) (void)hipGraphExecDestroy(*e);
+      for (hipGraphExec_t x : *e)
+        if (x) (void)hipGraphExecDestroy(x);
     }
-  } guard{&exec};
-  int batches = 0;
+  } guard{&execs};
+  int batches = 0, it_prev = 0;
+  double rr_prev = 0.0;
   for (;;) {
     TOSIMP_HIP(ctx, hipMemcpyAsync(sh, st, sizeof(SolverState), hipMemcpyDeviceToHost, ctx->stream));
     TOSIMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (sh->done) break;
-    if (graphs && batches == 1 && !exec) {
+    int want = check_every;
+    if (batches > 0 && sh->iter > it_prev && rr_prev > 0.0 && sh->rr > 0.0 &&
+        sh->rr < rr_prev && sh->tol2 > 0.0) {
+      const double per_it = std::log(sh->rr / rr_prev) / (double)(sh->iter - it_prev);
+      const double need = std::log(sh->tol2 / sh->rr) / per_it;  // both logs negative
+      if (std::isfinite(need)) want = (int)std::min<double>(check_every, std::ceil(need));
+    }
+    // the smallest size that covers the estimate (at most check_every)
+    size_t si = 0;
+    while (si + 1 < sizes.size() && sizes[si + 1] >= want) ++si;
+    const int k = sizes[si];
+    it_prev = sh->iter;
+    rr_prev = sh->rr;
+    if (graphs && batches >= 1 && !execs[si]) {
       hipGraph_t gr = nullptr;
       TOSIMP_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
-      const int rc = batch();
+      const int rc = batch(k);
       const hipError_t ee = hipStreamEndCapture(ctx->stream, &gr);
       if (rc) {
         if (gr) (void)hipGraphDestroy(gr);
         return rc;
       }
       TOSIMP_HIP(ctx, ee);
-      const hipError_t ie = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+      const hipError_t ie = hipGraphInstantiate(&execs[si], gr, nullptr, nullptr, 0);
       (void)hipGraphDestroy(gr);
       TOSIMP_HIP(ctx, ie);
     }
-    if (exec) {
-      TOSIMP_HIP(ctx, hipGraphLaunch(exec, ctx->stream));
+    if (graphs && execs[si]) {
+      TOSIMP_HIP(ctx, hipGraphLaunch(execs[si], ctx->stream));
     } else {
-      const int rc = batch();
+      const int rc = batch(k);
       if (rc) return rc;
     }
     ++batches;
