@@ -55,7 +55,20 @@ struct MgLevel {
   void* xa = nullptr;  // second iterate buffer (fused smoothing steps alternate x / xa)
 };
 
+// An instantiated MG-CG batch, reused by later solves whose launches would be the same:
+// the graph bakes in the vector pointers, the solver-state slot, the batch size, the
+// Chebyshev coefficients and the SIMP exponent (the hierarchy's own buffers live as long
+// as the hierarchy, which owns the cache).
+struct MgGraph {
+  int tsize = 0, k = 0, degree = 0, slot = 0;
+  double alpha = 0, penal = 0;
+  const void* ptr[7] = {};
+  hipGraphExec_t exec = nullptr;
+};
+constexpr size_t kMgGraphCache = 16;
+
 struct MgState {
+  std::vector<MgGraph> graphs;
   int nlev = 0;
   MgLevel L[kMgMaxLevels];
   int nc = 0;  // coarsest DOFs
@@ -724,20 +737,24 @@ int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T
   // size; after it, each batch is the smallest size that covers the iterations the
   // observed contraction of ||r||^2 per iteration still needs, so that few iterations are
   // enqueued past convergence (they return at once, but each of their launches still
-  // costs a few microseconds).  After one eager batch, each size is captured into its own
-  // HIP graph on first use and replayed: a V-cycle is a few dozen launches, which bound
-  // the iteration on small meshes.  The graphs hold only this library's kernels (no
-  // memset or copy nodes).
+  // costs a few microseconds).  Batches run as HIP graphs (a V-cycle is a few dozen
+  // launches, which bound the iteration on small meshes): each size is captured on first
+  // use, after one eager batch, and kept in the hierarchy's cache for later solves with
+  // the same launches (refinement steps, SIMP iterations).  The graphs hold only this
+  // library's kernels (no memset or copy nodes).
+  MgState* M = mg_of(ctx);
   std::vector<int> sizes;
   for (int k = check_every; k >= 1; k /= 2) sizes.push_back(k);
-  std::vector<hipGraphExec_t> execs(sizes.size(), nullptr);
-  struct ExecGuard {
-    std::vector<hipGraphExec_t>* e;
-    ~ExecGuard() {
-      for (hipGraphExec_t x : *e)
-        if (x) (void)hipGraphExecDestroy(x);
+  const void* ptrs[7] = {x, b, u, r, z, p, q};
+  auto cached = [&](int k) -> MgGraph* {
+    for (MgGraph& gph : M->graphs) {
+      if (gph.tsize != (int)sizeof(T) || gph.k != k || gph.degree != degree ||
+          gph.slot != slot || gph.alpha != alpha || gph.penal != ctx->penal)
+        continue;
+      if (std::equal(ptrs, ptrs + 7, gph.ptr)) return &gph;
     }
-  } guard{&execs};
+    return nullptr;
+  };
   int batches = 0, it_prev = 0;
   double rr_prev = 0.0;
   for (;;) {
@@ -757,7 +774,8 @@ int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T
     const int k = sizes[si];
     it_prev = sh->iter;
     rr_prev = sh->rr;
-    if (graphs && batches >= 1 && !execs[si]) {
+    MgGraph* gph = graphs ? cached(k) : nullptr;
+    if (graphs && !gph && batches >= 1) {
       hipGraph_t gr = nullptr;
       TOSIMP_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
       const int rc = batch(k);
@@ -767,12 +785,26 @@ int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T
         return rc;
       }
       TOSIMP_HIP(ctx, ee);
-      const hipError_t ie = hipGraphInstantiate(&execs[si], gr, nullptr, nullptr, 0);
+      MgGraph fresh;
+      fresh.tsize = (int)sizeof(T);
+      fresh.k = k;
+      fresh.degree = degree;
+      fresh.slot = slot;
+      fresh.alpha = alpha;
+      fresh.penal = ctx->penal;
+      std::copy(ptrs, ptrs + 7, fresh.ptr);
+      const hipError_t ie = hipGraphInstantiate(&fresh.exec, gr, nullptr, nullptr, 0);
       (void)hipGraphDestroy(gr);
       TOSIMP_HIP(ctx, ie);
+      if (M->graphs.size() >= kMgGraphCache) {  // drop the oldest
+        (void)hipGraphExecDestroy(M->graphs.front().exec);
+        M->graphs.erase(M->graphs.begin());
+      }
+      M->graphs.push_back(fresh);
+      gph = &M->graphs.back();
     }
-    if (graphs && execs[si]) {
-      TOSIMP_HIP(ctx, hipGraphLaunch(execs[si], ctx->stream));
+    if (gph) {
+      TOSIMP_HIP(ctx, hipGraphLaunch(gph->exec, ctx->stream));
     } else {
       const int rc = batch(k);
       if (rc) return rc;
@@ -829,6 +861,8 @@ void mg_release(tosimp_ctx* ctx) {
   }
   if (M->Ainv64) (void)hipFree(M->Ainv64);
   if (M->Ainv32) (void)hipFree(M->Ainv32);
+  for (MgGraph& g : M->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
   delete M;
   ctx->mg = nullptr;
 }

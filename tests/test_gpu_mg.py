@@ -155,3 +155,33 @@ def test_mg_graph_replay_matches_eager_bitwise(mode):
     t.close()
     assert out[0][0] == out[1][0] and out[0][0] > 4
     assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_mg_graph_cache_reuse_and_penalty_change():
+    """Repeated solves with the same buffers replay the cached batch graphs and give the
+    eager solve's iterates bit for bit; after the SIMP exponent changes, no graph of the
+    old exponent is replayed (graph and eager solves agree again, and the solution moves)."""
+    nx, ny, nz = 20, 10, 10
+    rng = np.random.default_rng(13)
+    x = dev(rng.uniform(0.05, 1.0, nx * ny * nz))
+    t, _, f = gpu_problem(nx, ny, nz)
+    b = dev(f)
+    u = torch.zeros(t.n_dof, dtype=torch.float64, device="cuda:0")
+
+    def solve(eager):
+        u.zero_()
+        st = t.pcg_solve(x, b, u, tol=1e-10, precond="mg", mode="ir", inner_tol=1e-4,
+                         check_every=4, eager=eager)
+        assert st["rc"] == 0
+        return st["iterations"], u.cpu().numpy().copy()
+
+    ref = solve(True)
+    for _ in range(3):
+        it, got = solve(False)
+        assert it == ref[0] and np.array_equal(got, ref[1])
+    t.set_params(2.5, 1.5)
+    ref25 = solve(True)
+    it, got = solve(False)
+    t.close()
+    assert it == ref25[0] and np.array_equal(got, ref25[1])
+    assert not np.array_equal(ref25[1], ref[1])
