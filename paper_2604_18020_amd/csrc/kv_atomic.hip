@@ -16,15 +16,11 @@
 // DOFs then receive no additions.  The order of the atomic additions is not fixed, so
 // results agree with the main kernel to rounding, not bit for bit.
 #include "common.h"
+#include "hex.h"
 
 namespace tosimp {
 
 namespace {
-
-template <typename T>
-struct AtomicK {
-  T ad, ao, cs, bd, bo, cd, co, hg;
-};
 
 template <typename T, typename XT>
 struct AtomicArgs {
@@ -36,7 +32,7 @@ struct AtomicArgs {
   int bricks_x, bricks_y, nbricks, per_xcd;
   T E0mEmin, Emin, penal;
   bool cube;
-  AtomicK<T> k;
+  HexK<T> k;
 };
 
 template <typename T, typename XT>
@@ -44,76 +40,6 @@ __device__ __forceinline__ T atomic_modulus(const AtomicArgs<T, XT>& A, XT xv) {
   const T x = (T)xv;
   const T xp = A.cube ? x * x * x : (x > T(0) ? pow(x, A.penal) : T(0));
   return A.Emin + xp * A.E0mEmin;
-}
-
-// 24 element results from the 8 corner values of one element (corner q = cx + 2 cy +
-// 4 cz).  Per axis the basis is {v0 + v1, v1 - v0}; mode m = mx + 2 my + 4 mz.  The
-// forward transform takes (a, b) to (a + b, b - a) along each axis, the transposed one
-// takes (g0, g1) back to (g0 - g1, g0 + g1); between them the 45 non-zeros of
-// S = H K_E H^T / 64 (see the constants in common.h).
-template <typename T>
-__device__ __forceinline__ void element_apply(T E, const AtomicK<T>& K, const T (&v)[8][3],
-                                              T (&y)[8][3]) {
-  T h[8][3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) h[q][c] = v[q][c];
-#pragma unroll
-    for (int bit = 1; bit < 8; bit <<= 1)
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (!(q & bit)) {
-          const T a = h[q][c], b = h[q | bit][c];
-          h[q][c] = a + b;
-          h[q | bit][c] = b - a;
-        }
-  }
-  const T kad = E * K.ad, kao = E * K.ao, kcs = E * K.cs, kbd = E * K.bd;
-  const T kbo = E * K.bo, kcd = E * K.cd, kco = E * K.co, khg = E * K.hg;
-  T g[8][3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) g[0][c] = T(0);
-  // normal block (1,x), (2,y), (4,z)
-  const T sA = kao * (h[1][0] + h[2][1] + h[4][2]);
-  g[1][0] = kad * h[1][0] + sA;
-  g[2][1] = kad * h[2][1] + sA;
-  g[4][2] = kad * h[4][2] + sA;
-  // shear pairs
-  const T s1 = kcs * (h[1][1] + h[2][0]), s2 = kcs * (h[1][2] + h[4][0]);
-  const T s3 = kcs * (h[2][2] + h[4][1]);
-  g[1][1] = s1; g[2][0] = s1;
-  g[1][2] = s2; g[4][0] = s2;
-  g[2][2] = s3; g[4][1] = s3;
-  // bending pairs
-  g[3][0] = kbd * h[3][0] + kbo * h[6][2];
-  g[6][2] = kbo * h[3][0] + kbd * h[6][2];
-  g[3][1] = kbd * h[3][1] + kbo * h[5][2];
-  g[5][2] = kbo * h[3][1] + kbd * h[5][2];
-  g[5][0] = kbd * h[5][0] + kbo * h[6][1];
-  g[6][1] = kbo * h[5][0] + kbd * h[6][1];
-  // twist block (3,z), (5,y), (6,x)
-  const T sC = kco * (h[3][2] + h[5][1] + h[6][0]);
-  g[3][2] = kcd * h[3][2] + sC;
-  g[5][1] = kcd * h[5][1] + sC;
-  g[6][0] = kcd * h[6][0] + sC;
-  // hourglass
-#pragma unroll
-  for (int c = 0; c < 3; ++c) g[7][c] = khg * h[7][c];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int bit = 4; bit >= 1; bit >>= 1)
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (!(q & bit)) {
-          const T g0 = g[q][c], g1 = g[q | bit][c];
-          g[q][c] = g0 - g1;
-          g[q | bit][c] = g0 + g1;
-        }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) y[q][c] = g[q][c];
-  }
 }
 
 // y = v on fixed DOFs, 0 elsewhere (the cleared output the additions go into).
@@ -151,7 +77,7 @@ __global__ __launch_bounds__(256) void kv_atomic_element(AtomicArgs<T, XT> A) {
     for (int c = 0; c < 3; ++c) v[q][c] = ((m[q] >> c) & 1) ? T(0) : A.v[3 * node[q] + c];
   }
   T y[8][3];
-  element_apply(atomic_modulus(A, A.x[e]), A.k, v, y);
+  hex_apply(atomic_modulus(A, A.x[e]), A.k, v, y);
 #pragma unroll
   for (int q = 0; q < 8; ++q)
 #pragma unroll
@@ -215,7 +141,7 @@ __global__ __launch_bounds__(256) void kv_atomic_brick(AtomicArgs<T, XT> A) {
       }
       const XT xv = A.x[ex + (int64_t)A.nx * (ey + (int64_t)A.ny * ez)];
       T y[8][3];
-      element_apply(atomic_modulus(A, xv), A.k, v, y);
+      hex_apply(atomic_modulus(A, xv), A.k, v, y);
 #pragma unroll
       for (int q = 0; q < 8; ++q)
 #pragma unroll
@@ -252,8 +178,8 @@ hipError_t atomic_launch_t(const tosimp_ctx* c, const XT* x, const T* v, T* y, i
   A.nx = c->nx; A.ny = c->ny; A.nz = c->nz;
   A.E0mEmin = (T)(c->E0 - c->Emin); A.Emin = (T)c->Emin; A.penal = (T)c->penal;
   A.cube = c->penal == 3.0;
-  A.k = AtomicK<T>{(T)c->hc.ad, (T)c->hc.ao, (T)c->hc.cs, (T)c->hc.bd,
-                   (T)c->hc.bo, (T)c->hc.cd, (T)c->hc.co, (T)c->hc.hg};
+  A.k = HexK<T>{(T)c->hc.ad, (T)c->hc.ao, (T)c->hc.cs, (T)c->hc.bd,
+                (T)c->hc.bo, (T)c->hc.cd, (T)c->hc.co, (T)c->hc.hg};
   atomic_clear_kernel<T><<<dim3(2048), dim3(256), 0, c->stream>>>(v, c->ws.mask, y, c->n_node);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -31,6 +31,7 @@
 
 #include "common.h"
 #include "dev.h"
+#include "hex.h"
 
 namespace tosimp {
 
@@ -69,6 +70,8 @@ constexpr size_t kMgGraphCache = 16;
 
 struct MgState {
   std::vector<MgGraph> graphs;
+  int tail = -1;          // first level of the single-workgroup tail (-1: none)
+  void* tail_er = nullptr;  // element results of a tail level (n_elem x 24 values)
   int nlev = 0;
   MgLevel L[kMgMaxLevels];
   int nc = 0;  // coarsest DOFs
@@ -252,6 +255,210 @@ __global__ __launch_bounds__(256) void dense_solve_kernel(const T* __restrict__ 
   for (int j = lane; j < n; j += 64) s += (double)Ainv[(int64_t)row * n + j] * (double)b[j];
   s = wave_sum(s);
   if (lane == 0) x[row] = (T)s;
+}
+
+// -------------------------------------------------------- single-workgroup tail
+// The smallest levels (at most kTailNodes nodes each, down to the dense coarsest) run
+// as one workgroup that walks its part of the V-cycle with barriers between the steps:
+// there a launch costs more than the work.  Same steps as the per-level kernels: the
+// operator element by element (each thread one element's 24 results, then each node
+// sums its up to eight elements' results in a fixed order), Chebyshev updates,
+// restriction, prolongation and the dense coarsest solve.
+constexpr int kTailNodes = 512;
+constexpr int kTailMaxLevels = 6;
+constexpr int kTailThreads = 512;
+constexpr int kChebMax = 16;
+
+template <typename T>
+struct TailLevel {
+  int nx, ny, nz;
+  const T* E;
+  const T* dinv;
+  const uint8_t* mask;
+  T* b;
+  T* x;
+  T* t;
+  T* dd;
+  HexK<T> k;  // element constants of the level's edge
+};
+
+template <typename T>
+struct TailArgs {
+  TailLevel<T> L[kTailMaxLevels];
+  int nlev;  // levels from the tail's first; the last one is solved densely
+  const T* Ainv;
+  int nc;
+  T* er;  // element results, n_elem x 24 of the level being applied
+  T c1[kChebMax], c2[kChebMax];
+  int degree;
+  const SolverState* st;
+};
+
+// t = K_c x on level L (x zero on fixed DOFs; fixed rows give t = x).
+template <typename T>
+__device__ void tail_apply(const TailLevel<T>& L, T* er) {
+  const int NX1 = L.nx + 1, NY1 = L.ny + 1;
+  const int ne = L.nx * L.ny * L.nz, nn = NX1 * NY1 * (L.nz + 1);
+  for (int e = threadIdx.x; e < ne; e += kTailThreads) {
+    const int ex = e % L.nx, r = e / L.nx;
+    const int ey = r % L.ny, ez = r / L.ny;
+    T v[8][3];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int n = (ex + (q & 1)) + NX1 * ((ey + ((q >> 1) & 1)) + NY1 * (ez + (q >> 2)));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[q][c] = L.x[3 * n + c];
+    }
+    T y[8][3];
+    hex_apply(L.E[e], L.k, v, y);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) er[24 * e + 3 * q + c] = y[q][c];
+  }
+  __syncthreads();
+  for (int n = threadIdx.x; n < nn; n += kTailThreads) {
+    const int i = n % NX1, r = n / NX1;
+    const int j = r % NY1, k = r / NY1;
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+    for (int ez = k - 1; ez <= k; ++ez) {
+      if (ez < 0 || ez >= L.nz) continue;
+      for (int ey = j - 1; ey <= j; ++ey) {
+        if (ey < 0 || ey >= L.ny) continue;
+        for (int ex = i - 1; ex <= i; ++ex) {
+          if (ex < 0 || ex >= L.nx) continue;
+          const int q = (i - ex) + 2 * (j - ey) + 4 * (k - ez);
+          const T* yr = er + 24 * (ex + L.nx * (ey + L.ny * ez)) + 3 * q;
+          s0 += yr[0];
+          s1 += yr[1];
+          s2 += yr[2];
+        }
+      }
+    }
+    const unsigned m = L.mask[n];
+    L.t[3 * n] = (m & 1) ? L.x[3 * n] : s0;
+    L.t[3 * n + 1] = (m & 2) ? L.x[3 * n + 1] : s1;
+    L.t[3 * n + 2] = (m & 4) ? L.x[3 * n + 2] : s2;
+  }
+  __syncthreads();
+}
+
+// Chebyshev step on level L (the modes of cheb_kernel).
+template <typename T, int MODE>
+__device__ void tail_cheb(const TailLevel<T>& L, T c1, T c2) {
+  const int nd = 3 * (L.nx + 1) * (L.ny + 1) * (L.nz + 1);
+  for (int i = threadIdx.x; i < nd; i += kTailThreads) {
+    const T di = L.dinv[i / 3];
+    if (MODE == 0) {
+      const T d = c2 * (L.b[i] * di);
+      L.dd[i] = d;
+      L.x[i] = d;
+    } else {
+      const T r = L.b[i] - L.t[i];
+      const T d = MODE == 1 ? c2 * (r * di) : c1 * L.dd[i] + c2 * (r * di);
+      L.dd[i] = d;
+      L.x[i] += d;
+    }
+  }
+  __syncthreads();
+}
+
+// C.b = P^T (F.b - F.t), zero on fixed coarse DOFs (as restrict_residual_kernel).
+template <typename T>
+__device__ void tail_restrict(const TailLevel<T>& F, const TailLevel<T>& C) {
+  const int CX = C.nx + 1, CY = C.ny + 1;
+  const int n = CX * CY * (C.nz + 1);
+  for (int N = threadIdx.x; N < n; N += kTailThreads) {
+    const int I = N % CX, r = N / CX;
+    const int J = r % CY, K = r / CY;
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+    for (int k = max(2 * K - 1, 0); k <= min(2 * K + 1, F.nz); ++k) {
+      const T wk = k == 2 * K ? T(1) : T(0.5);
+      for (int j = max(2 * J - 1, 0); j <= min(2 * J + 1, F.ny); ++j) {
+        const T wj = j == 2 * J ? T(1) : T(0.5);
+        for (int i = max(2 * I - 1, 0); i <= min(2 * I + 1, F.nx); ++i) {
+          const T w = (i == 2 * I ? T(1) : T(0.5)) * wj * wk;
+          const int f = 3 * (i + (F.nx + 1) * (j + (F.ny + 1) * k));
+          s0 += w * (F.b[f] - F.t[f]);
+          s1 += w * (F.b[f + 1] - F.t[f + 1]);
+          s2 += w * (F.b[f + 2] - F.t[f + 2]);
+        }
+      }
+    }
+    const unsigned m = C.mask[N];
+    C.b[3 * N] = (m & 1) ? T(0) : s0;
+    C.b[3 * N + 1] = (m & 2) ? T(0) : s1;
+    C.b[3 * N + 2] = (m & 4) ? T(0) : s2;
+  }
+  __syncthreads();
+}
+
+// F.x += P C.x on free fine DOFs (as prolong_add_kernel).
+template <typename T>
+__device__ void tail_prolong(const TailLevel<T>& F, const TailLevel<T>& C) {
+  const int FX = F.nx + 1, FY = F.ny + 1, CX = C.nx + 1, CY = C.ny + 1;
+  const int n = FX * FY * (F.nz + 1);
+  for (int nf = threadIdx.x; nf < n; nf += kTailThreads) {
+    const int i = nf % FX, r = nf / FX;
+    const int j = r % FY, k = r / FY;
+    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1;
+    const int k0 = k >> 1, k1 = (k + 1) >> 1;
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+    for (int K = k0; K <= k1; ++K) {
+      const T wk = k0 == k1 ? T(1) : T(0.5);
+      for (int J = j0; J <= j1; ++J) {
+        const T wj = j0 == j1 ? T(1) : T(0.5);
+        for (int I = i0; I <= i1; ++I) {
+          const T w = (i0 == i1 ? T(1) : T(0.5)) * wj * wk;
+          const int c = 3 * (I + CX * (J + CY * K));
+          s0 += w * C.x[c];
+          s1 += w * C.x[c + 1];
+          s2 += w * C.x[c + 2];
+        }
+      }
+    }
+    const unsigned m = F.mask[nf];
+    if (!(m & 1)) F.x[3 * nf] += s0;
+    if (!(m & 2)) F.x[3 * nf + 1] += s1;
+    if (!(m & 4)) F.x[3 * nf + 2] += s2;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void mg_tail_kernel(TailArgs<T> A) {
+  if (A.st && A.st->done) return;
+  const int last = A.nlev - 1;
+  for (int l = 0; l < last; ++l) {
+    const TailLevel<T>& L = A.L[l];
+    tail_cheb<T, 0>(L, T(0), A.c2[0]);
+    for (int s = 1; s < A.degree; ++s) {
+      tail_apply(L, A.er);
+      tail_cheb<T, 2>(L, A.c1[s], A.c2[s]);
+    }
+    tail_apply(L, A.er);
+    tail_restrict(L, A.L[l + 1]);
+  }
+  {
+    // x = Ainv b, one row per thread, FP64 sums in column order
+    const TailLevel<T>& C = A.L[last];
+    for (int row = threadIdx.x; row < A.nc; row += kTailThreads) {
+      double s = 0.0;
+      for (int j = 0; j < A.nc; ++j) s += (double)A.Ainv[row * A.nc + j] * (double)C.b[j];
+      C.x[row] = (T)s;
+    }
+    __syncthreads();
+  }
+  for (int l = last - 1; l >= 0; --l) {
+    const TailLevel<T>& L = A.L[l];
+    tail_prolong(L, A.L[l + 1]);
+    tail_apply(L, A.er);
+    tail_cheb<T, 1>(L, T(0), A.c2[0]);
+    for (int s = 1; s < A.degree; ++s) {
+      tail_apply(L, A.er);
+      tail_cheb<T, 2>(L, A.c1[s], A.c2[s]);
+    }
+  }
 }
 
 // ------------------------------------------------------------- CG kernels (device state)
@@ -514,6 +721,16 @@ int mg_create_impl(tosimp_ctx* ctx) {
   }
   TOSIMP_HIP(ctx, mg_alloc((void**)&M->Ainv64, (size_t)M->nc * M->nc * 8));
   TOSIMP_HIP(ctx, mg_alloc((void**)&M->Ainv32, (size_t)M->nc * M->nc * 4));
+  // The tail: from the first level with at most kTailNodes nodes (every later one is
+  // smaller), if it leaves at least one level to smooth and fits the launch's table.
+  M->tail = -1;
+  for (int l = 0; l + 1 < M->nlev; ++l) {
+    if (M->L[l].n_node > kTailNodes) continue;
+    if (M->nlev - l <= kTailMaxLevels) M->tail = l;
+    break;
+  }
+  if (M->tail >= 0)
+    TOSIMP_HIP(ctx, mg_alloc(&M->tail_er, (size_t)M->L[M->tail].n_elem * 24 * 8));
   std::vector<double> ke(ctx->KE, ctx->KE + 576);
   M->lam = sym_lambda_max(ke, 24) / ctx->KE[0];
   return TOSIMP_OK;
@@ -592,11 +809,50 @@ const T* lev_dinv(const MgLevel& L) {
   if constexpr (sizeof(T) == 8) return (const T*)L.dinv64; else return (const T*)L.dinv32;
 }
 
+// The V-cycle from the tail's first level down, in one single-workgroup launch.
+template <typename T>
+int tail_vcycle(tosimp_ctx* ctx, MgState* M, const ChebCoef& K, int degree,
+                const SolverState* st) {
+  TailArgs<T> A{};
+  A.nlev = M->nlev - M->tail;
+  for (int i = 0; i < A.nlev; ++i) {
+    const MgLevel& L = M->L[M->tail + i];
+    TailLevel<T>& D = A.L[i];
+    D.nx = L.nx;
+    D.ny = L.ny;
+    D.nz = L.nz;
+    D.E = lev_E<T>(L);
+    D.dinv = lev_dinv<T>(L);
+    D.mask = L.mask;
+    D.b = (T*)L.b;
+    D.x = (T*)L.x;
+    D.t = (T*)L.t;
+    D.dd = (T*)L.dd;
+    const double ks = L.kscale;
+    D.k = HexK<T>{(T)(ks * ctx->hc.ad), (T)(ks * ctx->hc.ao), (T)(ks * ctx->hc.cs),
+                  (T)(ks * ctx->hc.bd), (T)(ks * ctx->hc.bo), (T)(ks * ctx->hc.cd),
+                  (T)(ks * ctx->hc.co), (T)(ks * ctx->hc.hg)};
+  }
+  if constexpr (sizeof(T) == 8) A.Ainv = (const T*)M->Ainv64; else A.Ainv = (const T*)M->Ainv32;
+  A.nc = M->nc;
+  A.er = (T*)M->tail_er;
+  for (int s = 0; s < degree && s < kChebMax; ++s) {
+    A.c1[s] = (T)K.c1[s];
+    A.c2[s] = (T)K.c2[s];
+  }
+  A.degree = degree;
+  A.st = st;
+  mg_tail_kernel<T><<<1, kTailThreads, 0, ctx->stream>>>(A);
+  TOSIMP_HIP(ctx, hipGetLastError());
+  return TOSIMP_OK;
+}
+
 // One V-cycle from level l: x_l ~ K_l^-1 b_l (x_l overwritten).
 template <typename T>
 int vcycle(tosimp_ctx* ctx, MgState* M, int l, const ChebCoef& K, int degree,
            const SolverState* st) {
   constexpr int prec = sizeof(T) == 8 ? TOSIMP_PREC_FP64 : TOSIMP_PREC_FP32;
+  if (l == M->tail) return tail_vcycle<T>(ctx, M, K, degree, st);
   MgLevel& L = M->L[l];
   T *b = (T*)L.b, *x = (T*)L.x, *t = (T*)L.t, *dd = (T*)L.dd;
   const int nd = (int)L.n_dof;
@@ -863,6 +1119,7 @@ void mg_release(tosimp_ctx* ctx) {
   if (M->Ainv32) (void)hipFree(M->Ainv32);
   for (MgGraph& g : M->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (M->tail_er) (void)hipFree(M->tail_er);
   delete M;
   ctx->mg = nullptr;
 }
