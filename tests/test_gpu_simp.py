@@ -36,10 +36,11 @@ def test_sensitivity_matches_oracle(dims):
 
 @pytest.mark.parametrize("dims,rmin", [((16, 8, 8), 1.5), ((13, 7, 9), 2.5), ((5, 4, 3), 1.0),
                                        ((11, 6, 7), 2.0), ((1, 1, 1), 1.5), ((1, 5, 2), 1.5),
-                                       ((40, 3, 1), 1.8)])
+                                       ((40, 3, 1), 1.8), ((70, 9, 17), 1.5)])
 def test_filter_matches_oracle(dims, rmin):
     """Radius one (rmin in (1, 2]: 27-point cube, corner taps weighted for rmin > sqrt 3)
-    and the general kernel (rmin 1, 2.5), on meshes one element thick along some axes."""
+    and the general kernel (rmin 1, 2.5), on meshes one element thick along some axes and
+    one that cuts the radius-one sweep's 64 x 4 tiles and 8-plane chunks raggedly."""
     nx, ny, nz = dims
     H, Hs = topopt.filter_matrix(nx, ny, nz, rmin)
     t, _, _ = gpu_problem(nx, ny, nz, rmin=rmin)
