@@ -70,8 +70,10 @@ constexpr size_t kMgGraphCache = 16;
 
 struct MgState {
   std::vector<MgGraph> graphs;
-  int tail = -1;          // first level of the single-workgroup tail (-1: none)
-  void* tail_er = nullptr;  // element results of a tail level (n_elem x 24 values)
+  int tail = -1;  // first level of the single-workgroup tail (-1: none)
+  int tail_off[kMgMaxLevels][5] = {};  // LDS offsets of b, x, dd, dinv, E per tail level
+  int tail_oer = 0;     // LDS offset of the element results
+  int tail_values = 0;  // LDS values in all (bytes: times the vector type's size)
   int nlev = 0;
   MgLevel L[kMgMaxLevels];
   int nc = 0;  // coarsest DOFs
@@ -260,10 +262,13 @@ __global__ __launch_bounds__(256) void dense_solve_kernel(const T* __restrict__ 
 // -------------------------------------------------------- single-workgroup tail
 // The smallest levels (at most kTailNodes nodes each, down to the dense coarsest) run
 // as one workgroup that walks its part of the V-cycle with barriers between the steps:
-// there a launch costs more than the work.  Same steps as the per-level kernels: the
-// operator element by element (each thread one element's 24 results, then each node
-// sums its up to eight elements' results in a fixed order), Chebyshev updates,
-// restriction, prolongation and the dense coarsest solve.
+// there a launch costs more than the work.  Every vector of these levels, their moduli
+// and inverse diagonals, and one level's element results live in LDS (the top level's
+// right-hand side is read from and its iterate written to device memory).  The
+// operator goes element by element (each thread one element's 24 results), then each
+// node sums its up to eight elements' results in a fixed order and applies the
+// Chebyshev update at once; a visit's first two steps form the first iterate c0 D^-1 b
+// while gathering.  The steps are those of the per-level kernels.
 constexpr int kTailNodes = 512;
 constexpr int kTailMaxLevels = 6;
 constexpr int kTailThreads = 512;
@@ -272,14 +277,13 @@ constexpr int kChebMax = 16;
 template <typename T>
 struct TailLevel {
   int nx, ny, nz;
-  const T* E;
-  const T* dinv;
-  const uint8_t* mask;
-  T* b;
-  T* x;
-  T* t;
-  T* dd;
-  HexK<T> k;  // element constants of the level's edge
+  const T* E;           // device memory (copied in)
+  const T* dinv;        // device memory (copied in)
+  const uint8_t* mask;  // device memory
+  const T* b_in;        // top level: the right-hand side
+  T* x_out;             // top level: the iterate
+  HexK<T> k;            // element constants of the level's edge
+  int ob, ox, odd, odi, oE;  // LDS offsets (in values of T) of b, x, dd, dinv, E
 };
 
 template <typename T>
@@ -288,17 +292,24 @@ struct TailArgs {
   int nlev;  // levels from the tail's first; the last one is solved densely
   const T* Ainv;
   int nc;
-  T* er;  // element results, n_elem x 24 of the level being applied
+  int oer;   // LDS offset of the element results
   T c1[kChebMax], c2[kChebMax];
   int degree;
   const SolverState* st;
 };
 
-// t = K_c x on level L (x zero on fixed DOFs; fixed rows give t = x).
-template <typename T>
-__device__ void tail_apply(const TailLevel<T>& L, T* er) {
+enum TailStep { kTailFirst2 = 3, kTailCheb1 = 1, kTailCheb2 = 2, kTailResidual = 4 };
+
+// Element phase: er[24 e + 3 q + c] = E_e (K_E v_e) with v the level's x, or (FIRST2)
+// the first iterate c0 b D^-1 formed on the fly.
+template <typename T, bool FIRST2>
+__device__ void tail_elem(const TailLevel<T>& L, T* S, T* er, T c0) {
   const int NX1 = L.nx + 1, NY1 = L.ny + 1;
-  const int ne = L.nx * L.ny * L.nz, nn = NX1 * NY1 * (L.nz + 1);
+  const int ne = L.nx * L.ny * L.nz;
+  const T* x = S + L.ox;
+  const T* b = S + L.ob;
+  const T* di = S + L.odi;
+  const T* E = S + L.oE;
   for (int e = threadIdx.x; e < ne; e += kTailThreads) {
     const int ex = e % L.nx, r = e / L.nx;
     const int ey = r % L.ny, ez = r / L.ny;
@@ -307,20 +318,31 @@ __device__ void tail_apply(const TailLevel<T>& L, T* er) {
     for (int q = 0; q < 8; ++q) {
       const int n = (ex + (q & 1)) + NX1 * ((ey + ((q >> 1) & 1)) + NY1 * (ez + (q >> 2)));
 #pragma unroll
-      for (int c = 0; c < 3; ++c) v[q][c] = L.x[3 * n + c];
+      for (int c = 0; c < 3; ++c) v[q][c] = FIRST2 ? c0 * (b[3 * n + c] * di[n]) : x[3 * n + c];
     }
     T y[8][3];
-    hex_apply(L.E[e], L.k, v, y);
+    hex_apply(E[e], L.k, v, y);
 #pragma unroll
     for (int q = 0; q < 8; ++q)
 #pragma unroll
       for (int c = 0; c < 3; ++c) er[24 * e + 3 * q + c] = y[q][c];
   }
   __syncthreads();
+}
+
+// Node phase: t = K_c v at each node (fixed rows t = v), then the step's update.
+template <typename T, int STEP>
+__device__ void tail_node(const TailLevel<T>& L, T* S, const T* er, T c0, T c1, T c2) {
+  const int NX1 = L.nx + 1, NY1 = L.ny + 1;
+  const int nn = NX1 * NY1 * (L.nz + 1);
+  T* x = S + L.ox;
+  T* dd = S + L.odd;
+  const T* b = S + L.ob;
+  const T* di = S + L.odi;
   for (int n = threadIdx.x; n < nn; n += kTailThreads) {
     const int i = n % NX1, r = n / NX1;
     const int j = r % NY1, k = r / NY1;
-    T s0 = T(0), s1 = T(0), s2 = T(0);
+    T s[3] = {T(0), T(0), T(0)};
     for (int ez = k - 1; ez <= k; ++ez) {
       if (ez < 0 || ez >= L.nz) continue;
       for (int ey = j - 1; ey <= j; ++ey) {
@@ -329,43 +351,54 @@ __device__ void tail_apply(const TailLevel<T>& L, T* er) {
           if (ex < 0 || ex >= L.nx) continue;
           const int q = (i - ex) + 2 * (j - ey) + 4 * (k - ez);
           const T* yr = er + 24 * (ex + L.nx * (ey + L.ny * ez)) + 3 * q;
-          s0 += yr[0];
-          s1 += yr[1];
-          s2 += yr[2];
+          s[0] += yr[0];
+          s[1] += yr[1];
+          s[2] += yr[2];
         }
       }
     }
     const unsigned m = L.mask[n];
-    L.t[3 * n] = (m & 1) ? L.x[3 * n] : s0;
-    L.t[3 * n + 1] = (m & 2) ? L.x[3 * n + 1] : s1;
-    L.t[3 * n + 2] = (m & 4) ? L.x[3 * n + 2] : s2;
-  }
-  __syncthreads();
-}
-
-// Chebyshev step on level L (the modes of cheb_kernel).
-template <typename T, int MODE>
-__device__ void tail_cheb(const TailLevel<T>& L, T c1, T c2) {
-  const int nd = 3 * (L.nx + 1) * (L.ny + 1) * (L.nz + 1);
-  for (int i = threadIdx.x; i < nd; i += kTailThreads) {
-    const T di = L.dinv[i / 3];
-    if (MODE == 0) {
-      const T d = c2 * (L.b[i] * di);
-      L.dd[i] = d;
-      L.x[i] = d;
-    } else {
-      const T r = L.b[i] - L.t[i];
-      const T d = MODE == 1 ? c2 * (r * di) : c1 * L.dd[i] + c2 * (r * di);
-      L.dd[i] = d;
-      L.x[i] += d;
+    const T dn = di[n];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int I = 3 * n + c;
+      const T v = STEP == kTailFirst2 ? c0 * (b[I] * dn) : x[I];
+      const T t = ((m >> c) & 1) ? v : s[c];
+      const T rr = b[I] - t;
+      if (STEP == kTailResidual) {
+        dd[I] = rr;  // dd is dead until the next visit's first step overwrites it
+      } else {
+        const T dprev = STEP == kTailFirst2 ? v : dd[I];
+        const T d = STEP == kTailCheb1 ? c2 * (rr * dn) : c1 * dprev + c2 * (rr * dn);
+        dd[I] = d;
+        x[I] = v + d;
+      }
     }
   }
   __syncthreads();
 }
 
-// C.b = P^T (F.b - F.t), zero on fixed coarse DOFs (as restrict_residual_kernel).
+// x = dd = c2 b D^-1 (the first step from zero when the degree is 1).
 template <typename T>
-__device__ void tail_restrict(const TailLevel<T>& F, const TailLevel<T>& C) {
+__device__ void tail_first(const TailLevel<T>& L, T* S, T c2) {
+  const int nd = 3 * (L.nx + 1) * (L.ny + 1) * (L.nz + 1);
+  T* x = S + L.ox;
+  T* dd = S + L.odd;
+  const T* b = S + L.ob;
+  const T* di = S + L.odi;
+  for (int i = threadIdx.x; i < nd; i += kTailThreads) {
+    const T d = c2 * (b[i] * di[i / 3]);
+    dd[i] = d;
+    x[i] = d;
+  }
+  __syncthreads();
+}
+
+// C.b = P^T r_F (r_F in F's dd), zero on fixed coarse DOFs.
+template <typename T>
+__device__ void tail_restrict(const TailLevel<T>& F, const TailLevel<T>& C, T* S) {
+  const T* rf = S + F.odd;
+  T* bc = S + C.ob;
   const int CX = C.nx + 1, CY = C.ny + 1;
   const int n = CX * CY * (C.nz + 1);
   for (int N = threadIdx.x; N < n; N += kTailThreads) {
@@ -379,23 +412,25 @@ __device__ void tail_restrict(const TailLevel<T>& F, const TailLevel<T>& C) {
         for (int i = max(2 * I - 1, 0); i <= min(2 * I + 1, F.nx); ++i) {
           const T w = (i == 2 * I ? T(1) : T(0.5)) * wj * wk;
           const int f = 3 * (i + (F.nx + 1) * (j + (F.ny + 1) * k));
-          s0 += w * (F.b[f] - F.t[f]);
-          s1 += w * (F.b[f + 1] - F.t[f + 1]);
-          s2 += w * (F.b[f + 2] - F.t[f + 2]);
+          s0 += w * rf[f];
+          s1 += w * rf[f + 1];
+          s2 += w * rf[f + 2];
         }
       }
     }
     const unsigned m = C.mask[N];
-    C.b[3 * N] = (m & 1) ? T(0) : s0;
-    C.b[3 * N + 1] = (m & 2) ? T(0) : s1;
-    C.b[3 * N + 2] = (m & 4) ? T(0) : s2;
+    bc[3 * N] = (m & 1) ? T(0) : s0;
+    bc[3 * N + 1] = (m & 2) ? T(0) : s1;
+    bc[3 * N + 2] = (m & 4) ? T(0) : s2;
   }
   __syncthreads();
 }
 
-// F.x += P C.x on free fine DOFs (as prolong_add_kernel).
+// F.x += P C.x on free fine DOFs.
 template <typename T>
-__device__ void tail_prolong(const TailLevel<T>& F, const TailLevel<T>& C) {
+__device__ void tail_prolong(const TailLevel<T>& F, const TailLevel<T>& C, T* S) {
+  T* xf = S + F.ox;
+  const T* xc = S + C.ox;
   const int FX = F.nx + 1, FY = F.ny + 1, CX = C.nx + 1, CY = C.ny + 1;
   const int n = FX * FY * (F.nz + 1);
   for (int nf = threadIdx.x; nf < n; nf += kTailThreads) {
@@ -411,53 +446,82 @@ __device__ void tail_prolong(const TailLevel<T>& F, const TailLevel<T>& C) {
         for (int I = i0; I <= i1; ++I) {
           const T w = (i0 == i1 ? T(1) : T(0.5)) * wj * wk;
           const int c = 3 * (I + CX * (J + CY * K));
-          s0 += w * C.x[c];
-          s1 += w * C.x[c + 1];
-          s2 += w * C.x[c + 2];
+          s0 += w * xc[c];
+          s1 += w * xc[c + 1];
+          s2 += w * xc[c + 2];
         }
       }
     }
     const unsigned m = F.mask[nf];
-    if (!(m & 1)) F.x[3 * nf] += s0;
-    if (!(m & 2)) F.x[3 * nf + 1] += s1;
-    if (!(m & 4)) F.x[3 * nf + 2] += s2;
+    if (!(m & 1)) xf[3 * nf] += s0;
+    if (!(m & 2)) xf[3 * nf + 1] += s1;
+    if (!(m & 4)) xf[3 * nf + 2] += s2;
   }
   __syncthreads();
 }
 
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void mg_tail_kernel(TailArgs<T> A) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char tail_lds[];
   if (A.st && A.st->done) return;
+  T* S = reinterpret_cast<T*>(tail_lds);
+  T* er = S + A.oer;
   const int last = A.nlev - 1;
+  // copy in: moduli and inverse diagonals of the smoothed levels, the top right-hand side
   for (int l = 0; l < last; ++l) {
     const TailLevel<T>& L = A.L[l];
-    tail_cheb<T, 0>(L, T(0), A.c2[0]);
-    for (int s = 1; s < A.degree; ++s) {
-      tail_apply(L, A.er);
-      tail_cheb<T, 2>(L, A.c1[s], A.c2[s]);
+    const int ne = L.nx * L.ny * L.nz, nn = (L.nx + 1) * (L.ny + 1) * (L.nz + 1);
+    for (int i = threadIdx.x; i < ne; i += kTailThreads) S[L.oE + i] = L.E[i];
+    for (int i = threadIdx.x; i < nn; i += kTailThreads) S[L.odi + i] = L.dinv[i];
+  }
+  {
+    const TailLevel<T>& L = A.L[0];
+    const int nd = 3 * (L.nx + 1) * (L.ny + 1) * (L.nz + 1);
+    for (int i = threadIdx.x; i < nd; i += kTailThreads) S[L.ob + i] = L.b_in[i];
+  }
+  __syncthreads();
+  for (int l = 0; l < last; ++l) {
+    const TailLevel<T>& L = A.L[l];
+    if (A.degree >= 2) {
+      tail_elem<T, true>(L, S, er, A.c2[0]);
+      tail_node<T, kTailFirst2>(L, S, er, A.c2[0], A.c1[1], A.c2[1]);
+    } else {
+      tail_first(L, S, A.c2[0]);
     }
-    tail_apply(L, A.er);
-    tail_restrict(L, A.L[l + 1]);
+    for (int s = 2; s < A.degree; ++s) {
+      tail_elem<T, false>(L, S, er, T(0));
+      tail_node<T, kTailCheb2>(L, S, er, T(0), A.c1[s], A.c2[s]);
+    }
+    tail_elem<T, false>(L, S, er, T(0));
+    tail_node<T, kTailResidual>(L, S, er, T(0), T(0), T(0));
+    tail_restrict(L, A.L[l + 1], S);
   }
   {
     // x = Ainv b, one row per thread, FP64 sums in column order
     const TailLevel<T>& C = A.L[last];
+    const T* bc = S + C.ob;
+    T* xc = S + C.ox;
     for (int row = threadIdx.x; row < A.nc; row += kTailThreads) {
       double s = 0.0;
-      for (int j = 0; j < A.nc; ++j) s += (double)A.Ainv[row * A.nc + j] * (double)C.b[j];
-      C.x[row] = (T)s;
+      for (int j = 0; j < A.nc; ++j) s += (double)A.Ainv[row * A.nc + j] * (double)bc[j];
+      xc[row] = (T)s;
     }
     __syncthreads();
   }
   for (int l = last - 1; l >= 0; --l) {
     const TailLevel<T>& L = A.L[l];
-    tail_prolong(L, A.L[l + 1]);
-    tail_apply(L, A.er);
-    tail_cheb<T, 1>(L, T(0), A.c2[0]);
+    tail_prolong(L, A.L[l + 1], S);
+    tail_elem<T, false>(L, S, er, T(0));
+    tail_node<T, kTailCheb1>(L, S, er, T(0), T(0), A.c2[0]);
     for (int s = 1; s < A.degree; ++s) {
-      tail_apply(L, A.er);
-      tail_cheb<T, 2>(L, A.c1[s], A.c2[s]);
+      tail_elem<T, false>(L, S, er, T(0));
+      tail_node<T, kTailCheb2>(L, S, er, T(0), A.c1[s], A.c2[s]);
     }
+  }
+  {
+    const TailLevel<T>& L = A.L[0];
+    const int nd = 3 * (L.nx + 1) * (L.ny + 1) * (L.nz + 1);
+    for (int i = threadIdx.x; i < nd; i += kTailThreads) L.x_out[i] = S[L.ox + i];
   }
 }
 
@@ -722,15 +786,46 @@ int mg_create_impl(tosimp_ctx* ctx) {
   TOSIMP_HIP(ctx, mg_alloc((void**)&M->Ainv64, (size_t)M->nc * M->nc * 8));
   TOSIMP_HIP(ctx, mg_alloc((void**)&M->Ainv32, (size_t)M->nc * M->nc * 4));
   // The tail: from the first level with at most kTailNodes nodes (every later one is
-  // smaller), if it leaves at least one level to smooth and fits the launch's table.
+  // smaller), if it leaves at least one level to smooth, fits the launch's table and its
+  // LDS arena (FP64 sizes) fits a workgroup.
   M->tail = -1;
   for (int l = 0; l + 1 < M->nlev; ++l) {
     if (M->L[l].n_node > kTailNodes) continue;
     if (M->nlev - l <= kTailMaxLevels) M->tail = l;
     break;
   }
-  if (M->tail >= 0)
-    TOSIMP_HIP(ctx, mg_alloc(&M->tail_er, (size_t)M->L[M->tail].n_elem * 24 * 8));
+  if (M->tail >= 0) {
+    int off = 0;
+    for (int i = 0; M->tail + i < M->nlev; ++i) {
+      const MgLevel& L = M->L[M->tail + i];
+      const bool dense = M->tail + i == M->nlev - 1;
+      M->tail_off[i][0] = off;  // b
+      off += (int)L.n_dof;
+      M->tail_off[i][1] = off;  // x
+      off += (int)L.n_dof;
+      M->tail_off[i][2] = off;  // dd
+      off += dense ? 0 : (int)L.n_dof;
+      M->tail_off[i][3] = off;  // dinv
+      off += dense ? 0 : (int)L.n_node;
+      M->tail_off[i][4] = off;  // E
+      off += dense ? 0 : (int)L.n_elem;
+      off = (off + 1) & ~1;  // 16-byte alignment for FP64 pairs
+    }
+    M->tail_oer = off;
+    off += 24 * (int)M->L[M->tail].n_elem;
+    M->tail_values = off;
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) !=
+            hipSuccess ||
+        (size_t)off * 8 > (size_t)lds_max ||
+        hipFuncSetAttribute((const void*)mg_tail_kernel<double>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) != hipSuccess ||
+        hipFuncSetAttribute((const void*)mg_tail_kernel<float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) != hipSuccess) {
+      (void)hipGetLastError();
+      M->tail = -1;  // the per-level kernels take the whole V-cycle
+    }
+  }
   std::vector<double> ke(ctx->KE, ctx->KE + 576);
   M->lam = sym_lambda_max(ke, 24) / ctx->KE[0];
   return TOSIMP_OK;
@@ -824,25 +919,28 @@ int tail_vcycle(tosimp_ctx* ctx, MgState* M, const ChebCoef& K, int degree,
     D.E = lev_E<T>(L);
     D.dinv = lev_dinv<T>(L);
     D.mask = L.mask;
-    D.b = (T*)L.b;
-    D.x = (T*)L.x;
-    D.t = (T*)L.t;
-    D.dd = (T*)L.dd;
+    D.b_in = (const T*)L.b;
+    D.x_out = (T*)L.x;
     const double ks = L.kscale;
     D.k = HexK<T>{(T)(ks * ctx->hc.ad), (T)(ks * ctx->hc.ao), (T)(ks * ctx->hc.cs),
                   (T)(ks * ctx->hc.bd), (T)(ks * ctx->hc.bo), (T)(ks * ctx->hc.cd),
                   (T)(ks * ctx->hc.co), (T)(ks * ctx->hc.hg)};
+    D.ob = M->tail_off[i][0];
+    D.ox = M->tail_off[i][1];
+    D.odd = M->tail_off[i][2];
+    D.odi = M->tail_off[i][3];
+    D.oE = M->tail_off[i][4];
   }
   if constexpr (sizeof(T) == 8) A.Ainv = (const T*)M->Ainv64; else A.Ainv = (const T*)M->Ainv32;
   A.nc = M->nc;
-  A.er = (T*)M->tail_er;
+  A.oer = M->tail_oer;
   for (int s = 0; s < degree && s < kChebMax; ++s) {
     A.c1[s] = (T)K.c1[s];
     A.c2[s] = (T)K.c2[s];
   }
   A.degree = degree;
   A.st = st;
-  mg_tail_kernel<T><<<1, kTailThreads, 0, ctx->stream>>>(A);
+  mg_tail_kernel<T><<<1, kTailThreads, (size_t)M->tail_values * sizeof(T), ctx->stream>>>(A);
   TOSIMP_HIP(ctx, hipGetLastError());
   return TOSIMP_OK;
 }
@@ -1119,7 +1217,6 @@ void mg_release(tosimp_ctx* ctx) {
   if (M->Ainv32) (void)hipFree(M->Ainv32);
   for (MgGraph& g : M->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
-  if (M->tail_er) (void)hipFree(M->tail_er);
   delete M;
   ctx->mg = nullptr;
 }
