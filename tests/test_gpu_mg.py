@@ -185,3 +185,25 @@ def test_mg_graph_cache_reuse_and_penalty_change():
     t.close()
     assert it == ref25[0] and np.array_equal(got, ref25[1])
     assert not np.array_equal(ref25[1], ref[1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_vcycle_degrees_through_the_per_level_kernels(prec):
+    """Degrees 1, 3 and 4 on a mesh whose two finest levels run the per-level kernels
+    (degree 1: no fused first-two-steps pass; degree >= 3: extra fused passes) and whose
+    coarser levels run the single-workgroup tail, against the oracle's V-cycle."""
+    nx, ny, nz = 40, 20, 10
+    rng = np.random.default_rng(21)
+    x = rng.uniform(0.01, 1.0, nx * ny * nz)
+    levels, fixed = _oracle_levels(nx, ny, nz, x)
+    r = rng.standard_normal(fixed.size)
+    r[fixed] = 0.0
+    t, _, _ = gpu_problem(nx, ny, nz)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    for degree, alpha in ((1, 20.0), (3, 10.0), (4, 30.0)):
+        z_o = mg.vcycle(levels, r, LAM, degree=degree, alpha=alpha)
+        z = t.mg_apply(dev(x), dev(r, dt), degree=degree, alpha=alpha).double().cpu().numpy()
+        err = np.max(np.abs(z - z_o)) / np.max(np.abs(z_o))
+        assert err <= (1e-11 if prec == "fp64" else 2e-4), (degree, alpha, err)
+        assert np.all(z[fixed] == 0.0)
+    t.close()
