@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void dense_solve_kernel(const T* __restrict__ 
 // node sums its up to eight elements' results in a fixed order and applies the
 // Chebyshev update at once; a visit's first two steps form the first iterate c0 D^-1 b
 // while gathering.  The steps are those of the per-level kernels.
-constexpr int kTailNodes = 512;
+constexpr int kTailNodes = 512;  // largest level a single workgroup takes
 constexpr int kTailMaxLevels = 6;
 constexpr int kTailThreads = 512;
 constexpr int kChebMax = 16;
@@ -785,47 +785,46 @@ int mg_create_impl(tosimp_ctx* ctx) {
   }
   TOSIMP_HIP(ctx, mg_alloc((void**)&M->Ainv64, (size_t)M->nc * M->nc * 8));
   TOSIMP_HIP(ctx, mg_alloc((void**)&M->Ainv32, (size_t)M->nc * M->nc * 4));
-  // The tail: from the first level with at most kTailNodes nodes (every later one is
-  // smaller), if it leaves at least one level to smooth, fits the launch's table and its
-  // LDS arena (FP64 sizes) fits a workgroup.
+  // The tail: the longest run of coarsest levels (at least one smoothed level above the
+  // dense one, at most kTailMaxLevels, none with more than kTailNodes nodes) whose LDS
+  // arena, sized for FP64, fits a workgroup; none if even the last two do not fit.
   M->tail = -1;
-  for (int l = 0; l + 1 < M->nlev; ++l) {
-    if (M->L[l].n_node > kTailNodes) continue;
-    if (M->nlev - l <= kTailMaxLevels) M->tail = l;
-    break;
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) !=
+          hipSuccess ||
+      hipFuncSetAttribute((const void*)mg_tail_kernel<double>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) != hipSuccess ||
+      hipFuncSetAttribute((const void*)mg_tail_kernel<float>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) != hipSuccess) {
+    (void)hipGetLastError();
+    lds_max = 0;  // no tail
   }
-  if (M->tail >= 0) {
+  // Arena layout from level `first` down: b, x, dd, dinv, E per smoothed level (b, x on the
+  // dense one), then one level's element results; returns its size in values.
+  auto layout = [&](int first, bool store) -> int {
     int off = 0;
-    for (int i = 0; M->tail + i < M->nlev; ++i) {
-      const MgLevel& L = M->L[M->tail + i];
-      const bool dense = M->tail + i == M->nlev - 1;
-      M->tail_off[i][0] = off;  // b
-      off += (int)L.n_dof;
-      M->tail_off[i][1] = off;  // x
-      off += (int)L.n_dof;
-      M->tail_off[i][2] = off;  // dd
-      off += dense ? 0 : (int)L.n_dof;
-      M->tail_off[i][3] = off;  // dinv
-      off += dense ? 0 : (int)L.n_node;
-      M->tail_off[i][4] = off;  // E
-      off += dense ? 0 : (int)L.n_elem;
+    for (int i = 0; first + i < M->nlev; ++i) {
+      const MgLevel& L = M->L[first + i];
+      const bool dense = first + i == M->nlev - 1;
+      const int o[5] = {off, off + (int)L.n_dof, off + 2 * (int)L.n_dof,
+                        off + (dense ? 2 : 3) * (int)L.n_dof,
+                        off + (dense ? 2 * (int)L.n_dof : 3 * (int)L.n_dof + (int)L.n_node)};
+      off = dense ? o[3] : o[4] + (int)L.n_elem;
       off = (off + 1) & ~1;  // 16-byte alignment for FP64 pairs
+      if (store)
+        for (int k = 0; k < 5; ++k) M->tail_off[i][k] = o[k];
     }
-    M->tail_oer = off;
-    off += 24 * (int)M->L[M->tail].n_elem;
-    M->tail_values = off;
-    int lds_max = 0;
-    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) !=
-            hipSuccess ||
-        (size_t)off * 8 > (size_t)lds_max ||
-        hipFuncSetAttribute((const void*)mg_tail_kernel<double>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) != hipSuccess ||
-        hipFuncSetAttribute((const void*)mg_tail_kernel<float>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) != hipSuccess) {
-      (void)hipGetLastError();
-      M->tail = -1;  // the per-level kernels take the whole V-cycle
-    }
+    if (store) M->tail_oer = off;
+    off += 24 * (int)M->L[first].n_elem;
+    if (store) M->tail_values = off;
+    return off;
+  };
+  for (int l = M->nlev - 2; l >= 0 && lds_max > 0; --l) {
+    if (M->nlev - l > kTailMaxLevels || M->L[l].n_node > kTailNodes) break;
+    if ((size_t)layout(l, false) * 8 > (size_t)lds_max) break;
+    M->tail = l;
   }
+  if (M->tail >= 0) layout(M->tail, true);
   std::vector<double> ke(ctx->KE, ctx->KE + 576);
   M->lam = sym_lambda_max(ke, 24) / ctx->KE[0];
   return TOSIMP_OK;
