@@ -40,7 +40,10 @@ def test_hierarchy_matches_oracle(dims):
 @pytest.mark.parametrize("dims,kind,seed", [((12, 6, 6), "cantilever", 1),
                                             ((13, 7, 5), "cantilever", 2),
                                             ((9, 9, 14), "torsion", 3),
-                                            ((40, 20, 10), "cantilever", 4)])
+                                            ((40, 20, 10), "cantilever", 4),
+                                            # whole V-cycle in the single-workgroup tail,
+                                            # its LDS arena ~112 KB in FP64
+                                            ((11, 6, 5), "cantilever", 5)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_vcycle_matches_oracle(dims, kind, seed, prec):
     nx, ny, nz = dims
