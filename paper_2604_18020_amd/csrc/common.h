@@ -170,6 +170,11 @@ struct KvCheb {
   void* dd = nullptr;
   const void* dinv = nullptr;  // per node, of the operator's type
   double c0 = 0, c1 = 0, c2 = 0;
+  // Modes 1 and 2: with dot set the pass also stores, per operator tile, the FP64 sum of
+  // b . y over the tile's owned nodes into dot[0..tiles) and the tile count into
+  // *dot_tiles (no finalize is launched).
+  double* dot = nullptr;
+  int* dot_tiles = nullptr;
 };
 hipError_t kv_level_launch(const tosimp_ctx* c, int prec, const void* E, const void* v,
                            void* y, int nx, int ny, int nz, const uint8_t* mask,
@@ -178,7 +183,8 @@ hipError_t kv_level_launch(const tosimp_ctx* c, int prec, const void* E, const v
 
 // Geometric multigrid (mg.hip).  mg_prepare: hierarchy for density x (FP64) with the
 // Chebyshev degree and alpha (0 = defaults 2 and 20, validated); mg_apply: z = V(r) on the
-// fine level; mg_pcg: CG preconditioned by V(.) (slot: solver-state slot); mg_levels:
+// fine level (with dot_part, <r, z> as per-tile partials of the last finest-level pass,
+// *dot_tiles of them, 0 if the V-cycle had no such pass); mg_pcg: CG preconditioned by V(.) (slot: solver-state slot); mg_levels:
 // level dims into dims[3 l + {0,1,2}], returns the level count (or a negative status);
 // mg_release: frees the hierarchy (mesh change, destroy).
 struct MgPcgResult {
@@ -187,7 +193,8 @@ struct MgPcgResult {
 };
 int mg_prepare(tosimp_ctx* ctx, const double* x, int* degree, double* alpha);
 template <typename T>
-int mg_apply(tosimp_ctx* ctx, const T* r, T* z, int degree, double alpha, const SolverState* st);
+int mg_apply(tosimp_ctx* ctx, const T* r, T* z, int degree, double alpha, const SolverState* st,
+             double* dot_part = nullptr, int* dot_tiles = nullptr);
 template <typename T>
 int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T* q,
            int slot, double tol, int maxit, int check_every, bool zero_guess, int degree,

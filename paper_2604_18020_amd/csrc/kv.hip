@@ -214,7 +214,7 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
   // every z step rounds identically whatever was folded away around it (a chunk's first
   // layer starts from zero accumulators): results do not depend on the chunk depth.
 #pragma clang fp contract(on)
-  static_assert(EPI == 0 || (PM && !DOT), "the smoothing epilogue needs v = 0 on fixed DOFs");
+  static_assert(EPI == 0 || PM, "the smoothing epilogue needs v = 0 on fixed DOFs");
   constexpr int NXL = KBX + 1, NYL = KBY + 1, NPN = NXL * NYL;  // nodes of a plane window
   constexpr int NS = (NPN + 255) / 256;                          // node slots per thread
   constexpr int NE = KBX * KBY;
@@ -469,11 +469,15 @@ __device__ __forceinline__ void kv_body(const KvArgs<T, XT>& A) {
           dv[c] = d;
           xo[c] = vown[c] + d;
         }
+        if constexpr (DOT) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) dotacc += owner ? (double)eb_n.c[c] * (double)xo[c] : 0.0;
+        }
         buf_st_node(xo, ryq, yoffown);
         const auto rddq = make_rsrc32(reinterpret_cast<const char*>(A.edd) + qb, ybytes - qb);
         buf_st_node(dv, rddq, yoffown);
       }
-      if constexpr (DOT) {
+      if constexpr (DOT && EPI == 0) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) dotacc += owner ? (double)vown[c] * (double)yv[c] : 0.0;
       }
@@ -623,7 +627,8 @@ static int resident_blocks(const tosimp_ctx* c, K kernel) {
 }
 
 template <typename T, typename XT, int PEN, bool DOT, bool PM, int EPI = 0>
-static hipError_t kv_launch_v(const tosimp_ctx* c, KvArgs<T, XT> A, bool guarded) {
+static hipError_t kv_launch_v(const tosimp_ctx* c, KvArgs<T, XT> A, bool guarded,
+                              int* tiles_out = nullptr) {
   auto kern = guarded ? kv_stream_guarded<T, XT, PEN, DOT, PM, EPI>
                       : kv_stream<T, XT, PEN, DOT, PM, EPI>;
   // Resident blocks per device and kernel instance, computed once (concurrent first calls
@@ -642,7 +647,8 @@ static hipError_t kv_launch_v(const tosimp_ctx* c, KvArgs<T, XT> A, bool guarded
   A.ntiles = g.ntiles; A.per_xcd = g.per_xcd;
   if (DOT && g.ntiles > c->ws.kv_part_cap) return hipErrorInvalidValue;  // partial slots
   kern<<<dim3(g.grid), dim3(256), 0, c->stream>>>(A);
-  if (!DOT) return hipGetLastError();
+  if (tiles_out) *tiles_out = g.ntiles;
+  if (!DOT || A.fin == FIN_NONE) return hipGetLastError();  // partials left to the caller
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_finalize_sum<1>(c->stream, A.partials, g.ntiles,
@@ -718,6 +724,12 @@ static hipError_t kv_level_t(const tosimp_ctx* c, const T* E, const T* v, T* y, 
   A.ec0 = (T)ch->c0;
   A.ec1 = (T)ch->c1;
   A.ec2 = (T)ch->c2;
+  if (ch->dot && (ch->mode == 1 || ch->mode == 2)) {
+    A.partials = ch->dot;
+    if (ch->mode == 1)
+      return kv_launch_v<T, T, kPenModulus, true, true, 1>(c, A, st != nullptr, ch->dot_tiles);
+    return kv_launch_v<T, T, kPenModulus, true, true, 2>(c, A, st != nullptr, ch->dot_tiles);
+  }
   if (ch->mode == 1) return kv_launch_v<T, T, kPenModulus, false, true, 1>(c, A, st != nullptr);
   if (ch->mode == 3) return kv_launch_v<T, T, kPenModulus, false, true, 3>(c, A, st != nullptr);
   return kv_launch_v<T, T, kPenModulus, false, true, 2>(c, A, st != nullptr);

@@ -70,6 +70,10 @@ constexpr size_t kMgGraphCache = 16;
 
 struct MgState {
   std::vector<MgGraph> graphs;
+  // <r, z> of the current V-cycle, fused into its last finest-level smoothing pass when
+  // requested (partials per operator tile; dot_tiles stays 0 when not fused)
+  double* dot_part = nullptr;
+  int dot_tiles = 0;
   int tail = -1;  // first level of the single-workgroup tail (-1: none)
   int tail_off[kMgMaxLevels][5] = {};  // LDS offsets of b, x, dd, dinv, E per tail level
   int tail_oer = 0;     // LDS offset of the element results
@@ -969,7 +973,7 @@ int vcycle(tosimp_ctx* ctx, MgState* M, int l, const ChebCoef& K, int degree,
   // step's iterate), so starting in xa ends in x.
   T* xs[2] = {x, (T*)L.xa};
   int cur = 1;
-  auto fused = [&](int mode, double c1, double c2) -> hipError_t {
+  auto fused = [&](int mode, double c1, double c2, bool with_dot = false) -> hipError_t {
     KvCheb ch;
     ch.mode = mode;
     ch.b = b;
@@ -977,6 +981,10 @@ int vcycle(tosimp_ctx* ctx, MgState* M, int l, const ChebCoef& K, int degree,
     ch.dinv = dinv;
     ch.c1 = c1;
     ch.c2 = c2;
+    if (with_dot) {
+      ch.dot = M->dot_part;
+      ch.dot_tiles = &M->dot_tiles;
+    }
     const hipError_t e = kv_level_launch(ctx, prec, E, xs[cur], xs[cur ^ 1], L.nx, L.ny, L.nz,
                                          L.mask, L.kscale, st, &ch);
     cur ^= 1;
@@ -1014,9 +1022,12 @@ int vcycle(tosimp_ctx* ctx, MgState* M, int l, const ChebCoef& K, int degree,
   prolong_add_kernel<T><<<grid_for(L.n_node), 256, 0, ctx->stream>>>(
       xs[cur], L.mask, L.nx, L.ny, L.nz, (const T*)Cn.x, Cn.nx, Cn.ny, Cn.nz, st);
   TOSIMP_HIP(ctx, hipGetLastError());
-  // post-smoothing from x (same polynomial)
-  TOSIMP_HIP(ctx, fused(1, 0.0, K.c2[0]));
-  for (int s = 1; s < degree; ++s) TOSIMP_HIP(ctx, fused(2, K.c1[s], K.c2[s]));
+  // post-smoothing from x (same polynomial); on the finest level the last pass also
+  // forms <b, x> when the caller asked for it
+  const bool dot_here = l == 0 && M->dot_part != nullptr;
+  TOSIMP_HIP(ctx, fused(1, 0.0, K.c2[0], dot_here && degree == 1));
+  for (int s = 1; s < degree; ++s)
+    TOSIMP_HIP(ctx, fused(2, K.c1[s], K.c2[s], dot_here && s == degree - 1));
   if (cur != 0) return tosimp_fail(ctx, TOSIMP_ESTATE, "multigrid: smoothing parity");
   return TOSIMP_OK;
 }
@@ -1033,13 +1044,18 @@ int check_degree_alpha(tosimp_ctx* ctx, int* degree, double* alpha) {
 
 // z = V(r) on the fine level (set-up must be current).
 template <typename T>
-int mg_apply(tosimp_ctx* ctx, const T* r, T* z, int degree, double alpha, const SolverState* st) {
+int mg_apply(tosimp_ctx* ctx, const T* r, T* z, int degree, double alpha, const SolverState* st,
+             double* dot_part, int* dot_tiles) {
   MgState* M = mg_of(ctx);
   M->L[0].b = const_cast<T*>(r);
   M->L[0].x = z;
+  M->dot_part = dot_part;
+  M->dot_tiles = 0;
   const ChebCoef K = cheb_coef(M->lam, alpha, degree);
   const int rc = vcycle<T>(ctx, M, 0, K, degree, st);
+  if (dot_tiles) *dot_tiles = M->dot_tiles;
   M->L[0].b = M->L[0].x = nullptr;
+  M->dot_part = nullptr;
   return rc;
 }
 
@@ -1075,10 +1091,17 @@ int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T
   // One batch of k iterations (every kernel returns at once after convergence).
   auto batch = [&](int k) -> int {
     for (int i = 0; i < k; ++i) {
-      int rc = mg_apply<T>(ctx, r, z, degree, alpha, st);
+      // <r, z> comes out of the V-cycle's last finest-level pass (per-tile partials),
+      // else (the whole V-cycle in the single-workgroup tail) from its own kernel
+      int tiles = 0;
+      int rc = mg_apply<T>(ctx, r, z, degree, alpha, st, kvpart, &tiles);
       if (rc) return rc;
-      dot_rz_kernel<T><<<g, kRedThreads, 0, ctx->stream>>>(r, z, n, st, part);
-      TOSIMP_HIP(ctx, launch_finalize_sum<1>(ctx->stream, part, g, MgRzFin{st}));
+      if (tiles > 0) {
+        TOSIMP_HIP(ctx, launch_finalize_sum<1>(ctx->stream, kvpart, tiles, MgRzFin{st}));
+      } else {
+        dot_rz_kernel<T><<<g, kRedThreads, 0, ctx->stream>>>(r, z, n, st, part);
+        TOSIMP_HIP(ctx, launch_finalize_sum<1>(ctx->stream, part, g, MgRzFin{st}));
+      }
       mg_direction_kernel<T><<<g, kRedThreads, 0, ctx->stream>>>(z, p, n, st);
       TOSIMP_HIP(ctx, kv_launch(ctx, prec, xdt, x, p, q, kvpart, st, nullptr, 1, true, true));
       mg_update_kernel<T><<<g, kRedThreads, 0, ctx->stream>>>(u, r, p, q, n, st, part);
@@ -1171,8 +1194,10 @@ int mg_pcg(tosimp_ctx* ctx, const void* x, const T* b, T* u, T* r, T* z, T* p, T
   return TOSIMP_OK;
 }
 
-template int mg_apply<double>(tosimp_ctx*, const double*, double*, int, double, const SolverState*);
-template int mg_apply<float>(tosimp_ctx*, const float*, float*, int, double, const SolverState*);
+template int mg_apply<double>(tosimp_ctx*, const double*, double*, int, double, const SolverState*,
+                              double*, int*);
+template int mg_apply<float>(tosimp_ctx*, const float*, float*, int, double, const SolverState*,
+                             double*, int*);
 template int mg_pcg<double>(tosimp_ctx*, const void*, const double*, double*, double*, double*,
                             double*, double*, int, double, int, int, bool, int, double, bool,
                             MgPcgResult*);
