@@ -40,13 +40,13 @@ HBM_PEAK_GBS = 8000.0
 # valid only for the kernel sources they were taken with (sha256 of kv.hip, dev.h,
 # common.h); reported as null once those change.
 KV_TRAFFIC = {
-    "fp32": (2.0 * 49084.5 + 59116.0) * 1024,
-    "fp64": (2.0 * 94465.2 + 118065.4) * 1024,
+    "fp32": (2.0 * 49071.3 + 59171.4) * 1024,
+    "fp64": (2.0 * 94440.2 + 118010.8) * 1024,
 }
 KV_TRAFFIC_SOURCES = {
-    "kv.hip": "7226e9ecdd6cca4c4766a8fcc63edb3d6b1d67a926cb45049b0f4c8e0312335f",
+    "kv.hip": "d2f1041226fdb8f15f2a23303016a4577d1384ff5e3a4ae62cc63f8888814d29",
     "dev.h": "4f632875059f48985c77a57385922168b780fadc82dea0f30fd122a0d3fb5beb",
-    "common.h": "efb0f107021d1ccb1383e6c68c75db9750482396fa6cf12956ac583fc046fe31",
+    "common.h": "df30c16e1b3674dd02ea4ea4ba8d26a6be57acd103967395e33bfc1f6290c412",
 }
 
 
