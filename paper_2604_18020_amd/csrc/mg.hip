@@ -176,17 +176,20 @@ __global__ __launch_bounds__(256) void cheb_kernel(const T* __restrict__ b,
 }
 
 // bc = P^T (b - t) on the coarse grid, zero on fixed coarse DOFs.  Fine nodes of the
-// support in index order (k, j, i), weights 1 (even offset) / 1/2 (odd) per axis.
+// support in index order (k, j, i), weights 1 (even offset) / 1/2 (odd) per axis.  One
+// coarse node per thread, blocks laid out XCD-major (the fine planes a node gathers stay
+// in its XCD's L2).
 template <typename T>
 __global__ __launch_bounds__(256) void restrict_residual_kernel(
     const T* __restrict__ bf, const T* __restrict__ tf, int fx, int fy, int fz,
     T* __restrict__ bc, const uint8_t* __restrict__ mc, int cx, int cy, int cz,
-    const SolverState* st) {
+    const SolverState* st, int per_xcd) {
   if (st && st->done) return;
   const int CX = cx + 1, CY = cy + 1;
   const int64_t n = (int64_t)CX * CY * (cz + 1);
-  for (int64_t N = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; N < n;
-       N += (int64_t)gridDim.x * blockDim.x) {
+  {
+    const int64_t N = xcd_item(per_xcd);
+    if (N >= n) return;
     const int I = (int)(N % CX);
     const int64_t r = N / CX;
     const int J = (int)(r % CY), K = (int)(r / CY);
@@ -211,16 +214,17 @@ __global__ __launch_bounds__(256) void restrict_residual_kernel(
   }
 }
 
-// xf += P xc on free fine DOFs.
+// xf += P xc on free fine DOFs.  One fine node per thread, blocks laid out XCD-major.
 template <typename T>
 __global__ __launch_bounds__(256) void prolong_add_kernel(
     T* __restrict__ xf, const uint8_t* __restrict__ mf, int fx, int fy, int fz,
-    const T* __restrict__ xc, int cx, int cy, int cz, const SolverState* st) {
+    const T* __restrict__ xc, int cx, int cy, int cz, const SolverState* st, int per_xcd) {
   if (st && st->done) return;
   const int FX = fx + 1, FY = fy + 1, CX = cx + 1, CY = cy + 1;
   const int64_t n = (int64_t)FX * FY * (fz + 1);
-  for (int64_t nf = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; nf < n;
-       nf += (int64_t)gridDim.x * blockDim.x) {
+  {
+    const int64_t nf = xcd_item(per_xcd);
+    if (nf >= n) return;
     const int i = (int)(nf % FX);
     const int64_t r = nf / FX;
     const int j = (int)(r % FY), k = (int)(r / FY);
@@ -1014,13 +1018,19 @@ int vcycle(tosimp_ctx* ctx, MgState* M, int l, const ChebCoef& K, int degree,
   TOSIMP_HIP(ctx, kv_level_launch(ctx, prec, E, xs[cur], t, L.nx, L.ny, L.nz, L.mask,
                                   L.kscale, st));
   MgLevel& Cn = M->L[l + 1];
-  restrict_residual_kernel<T><<<grid_for(Cn.n_node), 256, 0, ctx->stream>>>(
-      b, t, L.nx, L.ny, L.nz, (T*)Cn.b, Cn.mask, Cn.nx, Cn.ny, Cn.nz, st);
+  {
+    const int per = xcd_per(Cn.n_node, 256);
+    restrict_residual_kernel<T><<<8 * per, 256, 0, ctx->stream>>>(
+        b, t, L.nx, L.ny, L.nz, (T*)Cn.b, Cn.mask, Cn.nx, Cn.ny, Cn.nz, st, per);
+  }
   TOSIMP_HIP(ctx, hipGetLastError());
   int rc = vcycle<T>(ctx, M, l + 1, K, degree, st);
   if (rc) return rc;
-  prolong_add_kernel<T><<<grid_for(L.n_node), 256, 0, ctx->stream>>>(
-      xs[cur], L.mask, L.nx, L.ny, L.nz, (const T*)Cn.x, Cn.nx, Cn.ny, Cn.nz, st);
+  {
+    const int per = xcd_per(L.n_node, 256);
+    prolong_add_kernel<T><<<8 * per, 256, 0, ctx->stream>>>(
+        xs[cur], L.mask, L.nx, L.ny, L.nz, (const T*)Cn.x, Cn.nx, Cn.ny, Cn.nz, st, per);
+  }
   TOSIMP_HIP(ctx, hipGetLastError());
   // post-smoothing from x (same polynomial); on the finest level the last pass also
   // forms <b, x> when the caller asked for it
