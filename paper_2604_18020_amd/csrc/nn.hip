@@ -17,6 +17,7 @@
 // (leaky ReLU preserves the sign, so a determines the slope).  Weight gradients are
 // reduced per voxel chunk and the chunks summed in a fixed order (deterministic).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -434,6 +435,322 @@ hipError_t launch_conv3_lds(hipStream_t s, const ConvArgs& a) {
   return hipGetLastError();
 }
 
+// Stride-1 3x3x3 convolutions in BF16 as a sweep up the z axis (forward, and the data
+// gradient as the convolution with mirrored taps).  A block owns a 16 x 8 column of
+// result voxels (x fastest), a chunk of result planes and 16 result channels
+// (blockIdx.y); wave w holds result rows 2w and 2w + 1.  Operand planes pass through a
+// ring of four LDS slots, each an 18 x 10 voxel window with all KCH channels: while the
+// block forms result plane z from the slots of planes z - 1, z, z + 1, the loads of
+// plane z + 2 are in flight; they are stored into the fourth slot after the products, and
+// one barrier per plane separates the steps.  For each y offset oy of the taps, K = the
+// nine (oz, ox) offsets x KCH channels is cut into matrix-core steps of 32 (one
+// v_mfma_f32_16x16x32_bf16; a lane's eight K values lie in one tap; the last step is
+// padded with zero weights), so the operand row tile that a lane reads from LDS for a
+// window row feeds the products of every result row that uses that row (up to three oy).
+// The weight tiles of the whole K (3 x S tiles of 16 channels x 32) stay in registers
+// for the sweep.  Summation order per result: step, then oy (fixed, deterministic).
+constexpr int kZX = 16, kZRW = 2, kZY = 4 * kZRW;                  // result tile, rows per wave
+constexpr int kZPX = kZX + 2, kZPY = kZY + 2, kZPlane = kZPX * kZPY;  // 18 x 10 window
+constexpr int kZSlots = 4;
+
+template <int KCH>
+constexpr int conv3z_steps() { return (9 * KCH + 31) / 32; }
+// LDS voxel pitch in elements: an odd number of 16-byte units, so the 16-byte operand
+// reads of consecutive voxels (one per lane) fall in distinct banks.
+template <int KCH>
+constexpr int conv3z_vs() { return (KCH / 8) % 2 ? KCH : KCH + 8; }
+template <int KCH>
+constexpr int conv3z_lds_bytes() { return kZSlots * kZPlane * conv3z_vs<KCH>() * 2; }
+
+struct Conv3zGeom {
+  int tiles_x, tiles_y, kz, nblk, per_xcd;
+};
+
+// Weight piece of step s, y offset oy, result channel n and lane quarter q (8 K values):
+// K index 32 s + 8 q within oy's group; zero past the nine (oz, ox) offsets.
+template <int KCH, bool BWD>
+__device__ __forceinline__ void conv3z_wload(Pack8<bf16_t>& B, const bf16_t* w, int row, int oy,
+                                             int s, int q) {
+  const int kk = 32 * s + 8 * q;
+  const int c = kk / KCH, ch = kk - c * KCH;
+  B.zero();
+  if (c < 9) {
+    const int oz = c / 3, ox = c - 3 * oz;
+    const int t = ox + 3 * oy + 9 * oz;
+    B.load(w + (long long)row * (27 * KCH) + (BWD ? 26 - t : t) * KCH + ch);
+  }
+}
+
+typedef unsigned int u32x4z __attribute__((ext_vector_type(4)));
+constexpr int kZOOB = 0x7FFFFFF0;  // buffer offset past any range: loads return 0, stores drop
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t conv3z_rsrc(const void* base, long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+
+// Planes issued a whole step before they are stored into LDS (two register sets, steps in
+// pairs), or at the start of the step that stores them.
+template <int KCH>
+constexpr bool conv3z_prefetch() { return KCH == 32; }
+
+// Waves per SIMD the register budget is set for (forward KCH 16: 128 VGPRs, four waves;
+// the data gradient also holds the stored activation of the planes in flight).
+template <int KCH, bool BWD>
+constexpr int conv3z_waves() {
+  return KCH <= 8 ? 5 : KCH <= 16 ? (BWD ? 3 : 4) : KCH <= 32 ? 2 : 1;
+}
+
+template <int KCH, bool BWD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv3z_waves<KCH, BWD>())))
+void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
+  constexpr int S = conv3z_steps<KCH>();
+  constexpr int PV = KCH / 8;                     // 16-byte pieces per voxel
+  constexpr int NP = (kZPlane * PV + 255) / 256;  // plane pieces per thread
+  constexpr int VS = conv3z_vs<KCH>();
+  extern __shared__ __attribute__((aligned(16))) unsigned char zsm[];
+  bf16_t* planes = reinterpret_cast<bf16_t*>(zsm);   // [4 slots][180 voxels][VS]
+  const int blin = (blockIdx.x & 7) * gm.per_xcd + (blockIdx.x >> 3);
+  if (blin >= gm.nblk) return;  // whole block
+  const Grid3 g = a.gout;       // stride 1: operand and result grids agree
+  const int bx = blin % gm.tiles_x, rest = blin / gm.tiles_x;
+  const int by = rest % gm.tiles_y, bz = rest / gm.tiles_y;
+  const int x0 = bx * kZX, y0 = by * kZY;
+  const int za = bz * gm.kz, zb = min(za + gm.kz, g.Z);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m = lane & 15, q = lane >> 4;
+  const int nres = BWD ? a.cin : a.cout;
+  const int cg = blockIdx.y * 16;
+  const long long nvox = (long long)g.X * g.Y * g.Z;
+  // Operand (and stored activation) and result tensors as buffer resources: lanes outside
+  // the grid use an offset past the range, so loads return zeros and stores are dropped
+  // without branches (the wait for a plane's loads then has a fixed count).
+  const __amdgpu_buffer_rsrc_t rin = conv3z_rsrc(a.in, nvox * KCH * 2);
+  const __amdgpu_buffer_rsrc_t ract = conv3z_rsrc(BWD ? a.act : a.in, nvox * KCH * 2);
+  const __amdgpu_buffer_rsrc_t rout = conv3z_rsrc(a.out, nvox * nres * 2);
+  const bf16_t* w = (const bf16_t*)a.w;
+
+  // Plane pieces of this thread: window voxel and byte offset in the plane.
+  int pvox[NP], pgo[NP];
+  bool pok[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int idx = tid + 256 * i;
+    const int vb = idx / PV, pc = idx - vb * PV;
+    const int hx = vb % kZPX, hy = vb / kZPX;
+    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
+    pok[i] = idx < kZPlane * PV && gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y;
+    pvox[i] = idx < kZPlane * PV ? vb * VS + 8 * pc : -1;
+    pgo[i] = ((gx + g.X * gy) * KCH + 8 * pc) * 2;
+  }
+  const int pstride = g.X * g.Y * KCH * 2;  // bytes per plane
+  auto plane_load = [&](Pack8<bf16_t>* pb, Pack8<bf16_t>* pa, int gz) {
+    const bool zok = gz >= 0 && gz < g.Z;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int off = zok && pok[i] ? pgo[i] + gz * pstride : kZOOB;
+      pb[i].v = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rin, off, 0, 0));
+      if (BWD)
+        pa[i].v = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(ract, off, 0, 0));
+    }
+  };
+  auto plane_store = [&](Pack8<bf16_t>* pb, Pack8<bf16_t>* pa, int gz) {
+    bf16_t* dst = planes + ((gz + 4) & 3) * (kZPlane * VS);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      if (pvox[i] >= 0) {
+        if (BWD) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            pb[i].set(j, pb[i].get(j) * (pa[i].get(j) > 0.0f ? 1.0f : kLeak));
+        }
+        pb[i].store(dst + pvox[i]);
+      }
+    }
+  };
+
+  // Weights: in registers for the sweep.
+  Pack8<bf16_t> Bw[3][S];
+#pragma unroll
+  for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+    for (int s = 0; s < S; ++s) conv3z_wload<KCH, BWD>(Bw[oy][s], w, cg + m, oy, s, q);
+  {  // planes za - 1, za, za + 1
+    Pack8<bf16_t> p0[NP], a0[BWD ? NP : 1], p1[NP], a1[BWD ? NP : 1], p2[NP], a2[BWD ? NP : 1];
+    plane_load(p0, a0, za - 1);
+    plane_load(p1, a1, za);
+    plane_load(p2, a2, za + 1);
+    plane_store(p0, a0, za - 1);
+    plane_store(p1, a1, za);
+    plane_store(p2, a2, za + 1);
+  }
+  // With PF, two register sets for planes in flight: the loads of plane z + 3 are issued
+  // at step z and stored into LDS at step z + 1, so each plane has a whole step to arrive.
+  constexpr bool PF = conv3z_prefetch<KCH>();
+  Pack8<bf16_t> r0[NP], ra0[BWD ? NP : 1], r1[PF ? NP : 1], ra1[PF && BWD ? NP : 1];
+  if (PF) plane_load(r0, ra0, za + 2);
+  __syncthreads();
+
+  // Per step s: this lane's (oz, ox, channel) and its operand offset within a slot.
+  int aoff[S], aoz[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int kk = 32 * s + 8 * q;
+    int c = kk / KCH;
+    const int ch = kk - c * KCH;
+    if (c >= 9) c = 0;  // zero weights: any finite operand
+    const int oz = c / 3, ox = c - 3 * oz;
+    aoz[s] = oz;
+    aoff[s] = ((kZRW * wv) * kZPX + m + ox) * VS + ch;
+  }
+  // Result offsets (bytes) of this lane's voxels in a plane; past the range outside the grid.
+  int ooff[kZRW][4];
+#pragma unroll
+  for (int r = 0; r < kZRW; ++r)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gx = x0 + 4 * q + j, gy = y0 + kZRW * wv + r;
+      ooff[r][j] = gx < g.X && gy < g.Y ? ((gx + g.X * gy) * nres + cg + m) * 2 : -1;
+    }
+  const int ostride = g.X * g.Y * nres * 2;  // bytes per result plane
+  // Step z: issue plane z + 3 into `ld`, form result plane z, store plane z + 2 (issued
+  // the step before, in `st`) into its slot, barrier.  Steps run in pairs; the second of
+  // a pair past the chunk stores nothing.  Every load and store is issued unconditionally.
+  auto step = [&](int z, Pack8<bf16_t>* ld, Pack8<bf16_t>* lda, Pack8<bf16_t>* st,
+                  Pack8<bf16_t>* sta) {
+    if (PF)
+      plane_load(ld, lda, z + 3);
+    else
+      plane_load(st, sta, z + 2);
+    f32x4 acc[kZRW];
+#pragma unroll
+    for (int r = 0; r < kZRW; ++r) acc[r] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    const int sb0 = ((z + 3) & 3) * (kZPlane * VS), sb1 = ((z + 4) & 3) * (kZPlane * VS),
+              sb2 = ((z + 5) & 3) * (kZPlane * VS);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const bf16_t* ab = planes + (aoz[s] == 0 ? sb0 : aoz[s] == 1 ? sb1 : sb2) + aoff[s];
+#pragma unroll
+      for (int rho = 0; rho < kZRW + 2; ++rho) {
+        Pack8<bf16_t> A;
+        A.load(ab + rho * (kZPX * VS));
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) {
+          const int r = rho - oy;
+          if (r >= 0 && r < kZRW) mma32(acc[r], A, Bw[oy][s]);
+        }
+      }
+    }
+    const bool zin = z < zb;
+#pragma unroll
+    for (int r = 0; r < kZRW; ++r)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float val = acc[r][j];
+        if (!BWD && a.apply_act) val = val > 0.0f ? val : kLeak * val;
+        const int off = zin && ooff[r][j] >= 0 ? ooff[r][j] + z * ostride : kZOOB;
+        __builtin_amdgcn_raw_buffer_store_b16(from_f<bf16_t>(val).bits, rout, off, 0, 0);
+      }
+    plane_store(st, sta, z + 2);
+    __syncthreads();
+  };
+  if constexpr (PF) {
+    for (int z = za; z < zb; z += 2) {  // in pairs: the register sets alternate
+      step(z, r1, ra1, r0, ra0);
+      step(z + 1, r0, ra0, r1, ra1);
+    }
+  } else {
+    for (int z = za; z < zb; ++z) step(z, r0, ra0, r0, ra0);
+  }
+}
+
+// Chunks of result planes: a chunk of kz planes loads kz + 2 operand planes, and the grid
+// runs in ceil(blocks / resident) rounds, so kz minimises rounds x (kz + 2) (idle slots of
+// a partial first round counted as lost).
+static Conv3zGeom conv3z_geom(const Grid3& g, int groups, int resident) {
+  Conv3zGeom gm;
+  gm.tiles_x = (g.X + kZX - 1) / kZX;
+  gm.tiles_y = (g.Y + kZY - 1) / kZY;
+  const long long cols = (long long)gm.tiles_x * gm.tiles_y * groups;
+  if (resident < 1) resident = 1;
+  double best = 1e300;
+  int best_kz = g.Z;
+  for (int chunks = 1; chunks <= g.Z; ++chunks) {
+    const int kz = (g.Z + chunks - 1) / chunks;
+    const int nch = (g.Z + kz - 1) / kz;
+    const long long n = cols * nch;
+    const long long rounds = (n + resident - 1) / resident;
+    const double fill = n >= resident ? 1.0 : (double)n / resident;
+    const double cost = (double)rounds * (kz + 2) / fill;
+    if (cost < best - 1e-9) {
+      best = cost;
+      best_kz = kz;
+    }
+  }
+  gm.kz = best_kz;
+  gm.nblk = gm.tiles_x * gm.tiles_y * ((g.Z + gm.kz - 1) / gm.kz);
+  gm.per_xcd = (gm.nblk + 7) / 8;
+  return gm;
+}
+
+template <int KCH, bool BWD>
+hipError_t launch_conv3z_t(hipStream_t s, const ConvArgs& a) {
+  constexpr int smem = conv3z_lds_bytes<KCH>();
+  auto kern = conv3z_kernel<KCH, BWD>;
+  // Blocks per CU x CUs, per kernel instance, computed once (concurrent first calls
+  // compute the same value).
+  static std::atomic<int> resident_once{0};
+  int resident = resident_once.load(std::memory_order_relaxed);
+  if (resident == 0) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, smem);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, smem) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    resident = per_cu * cus;
+    resident_once.store(resident, std::memory_order_relaxed);
+  }
+  const int nres = BWD ? a.cin : a.cout;
+  const Conv3zGeom gm = conv3z_geom(a.gout, nres / 16, resident);
+  kern<<<dim3(8 * gm.per_xcd, nres / 16), 256, smem, s>>>(a, gm);
+  return hipGetLastError();
+}
+
+// BF16 stride-1 3x3x3 layers whose K channel count has a z-sweep instance (forward 8, 16,
+// 32, 48, 64; data gradient 16, 32); returns hipErrorNotSupported for the others (the caller
+// uses the brick kernel).
+template <bool BWD>
+hipError_t launch_conv3z(hipStream_t s, const ConvArgs& a) {
+  const int kch = BWD ? a.cout : a.cin, nres = BWD ? a.cin : a.cout;
+  // 32-bit byte offsets into the operand and result tensors; the data gradient forms
+  // dY leaky'(a) from the stored activation.
+  if (nres % 16 || 2LL * a.gout.n() * (kch > nres ? kch : nres) >= (1LL << 31) ||
+      (BWD && !a.act))
+    return hipErrorNotSupported;
+  if constexpr (BWD) {
+    switch (kch) {
+      case 16: return launch_conv3z_t<16, true>(s, a);
+      case 32: return launch_conv3z_t<32, true>(s, a);
+      default: return hipErrorNotSupported;
+    }
+  } else {
+    switch (kch) {
+      case 8: return launch_conv3z_t<8, false>(s, a);
+      case 16: return launch_conv3z_t<16, false>(s, a);
+      case 32: return launch_conv3z_t<32, false>(s, a);
+      case 48: return launch_conv3z_t<48, false>(s, a);
+      case 64: return launch_conv3z_t<64, false>(s, a);
+      default: return hipErrorNotSupported;
+    }
+  }
+}
+
 // Weight gradient, one block per (chunk of cvox output voxels, tap, group of up to 32
 // (cout/16 x cin/16) tiles).  Per step of kc voxels (a multiple of 32 dividing cvox,
 // as many as fit 32 KB of LDS) the block stages dZ = dY leaky'(a)
@@ -721,14 +1038,32 @@ __global__ void loss_grad_kernel(const ST* out, const float* e, const uint8_t* m
 }
 
 // Network output to a DOF vector: z[3v + c] = scale * out[v][c], zero on fixed DOFs.
+// The preconditioner's output with the 1x1 head fused in: z = ||r|| / sqrt(n_dof) *
+// (W_head a) on free DOFs, 0 on fixed ones, from the last hidden layer's 16 channels a.
+// The head's result is rounded to the storage type, as the head layer stores it.
 template <typename ST>
-__global__ void output_kernel(const ST* out, const uint8_t* mask, const double* rnorm2, float* z,
-                              int n_node) {
+__global__ __launch_bounds__(256) void head_output_kernel(const ST* a, const ST* wh, int cip,
+                                                          const uint8_t* mask,
+                                                          const double* rnorm2, float* z,
+                                                          int n_node) {
+  __shared__ float w[3][16];
+  if (threadIdx.x < 48) w[threadIdx.x >> 4][threadIdx.x & 15] = to_f(wh[(threadIdx.x >> 4) * cip + (threadIdx.x & 15)]);
+  __syncthreads();
   const float s = (float)(sqrt(*rnorm2) / sqrt(3.0 * n_node));  // ||r|| / sqrt(n_dof)
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n_node; v += gridDim.x * blockDim.x) {
+    Pack8<ST> lo, hi;
+    lo.load(a + 16 * (long long)v);
+    hi.load(a + 16 * (long long)v + 8);
     const uint8_t mk = mask[v];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) z[3 * v + c] = ((mk >> c) & 1) ? 0.0f : s * to_f(out[16 * v + c]);
+    for (int c = 0; c < 3; ++c) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc += w[c][j] * lo.get(j);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc += w[c][8 + j] * hi.get(j);
+      z[3 * (long long)v + c] = ((mk >> c) & 1) ? 0.0f : s * to_f(from_f<ST>(acc));
+    }
   }
 }
 
@@ -1076,6 +1411,12 @@ hipError_t conv_fwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* in, v
   a.ksize = l.k;
   a.stride = l.s;
   a.apply_act = act;
+  if constexpr (sizeof(ST) == 2) {
+    if (l.k == 3 && l.s == 1) {
+      const hipError_t e = launch_conv3z<false>(c->stream, a);
+      if (e != hipErrorNotSupported) return e;
+    }
+  }
   if (l.k == 3 && l.s == 1 && a.cin % conv3_cs<ST>() == 0)
     return launch_conv3_lds<ST, false>(c->stream, a);
   const int waves = (a.gout.n() + 16 * kConvRT - 1) / (16 * kConvRT);
@@ -1121,6 +1462,12 @@ hipError_t conv_bwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* dY, c
     a.act = a_out;
     a.w = (const char*)S->WT + l.woff * S->es;
     a.out = dX;
+    if constexpr (sizeof(ST) == 2) {
+      if (l.k == 3 && l.s == 1) {
+        const hipError_t e = launch_conv3z<true>(c->stream, a);
+        if (e != hipErrorNotSupported) return e;
+      }
+    }
     if (l.k == 3 && l.s == 1 && a.cout % conv3_cs<ST>() == 0 && a.cin % 16 == 0)
       return launch_conv3_lds<ST, true>(c->stream, a);
     const int waves = (a.gin.n() + 16 * kConvRT - 1) / (16 * kConvRT);
@@ -1154,7 +1501,7 @@ hipError_t nn_alloc(void** p, size_t bytes) { return hipMalloc(p, bytes < 256 ? 
 
 // Forward pass from the padded input tensor in act[12]; layer outputs in act[0..11].
 template <typename ST>
-hipError_t nn_forward(tosimp_ctx* c, NNState* S) {
+hipError_t nn_forward(tosimp_ctx* c, NNState* S, bool head = true) {
   hipError_t e = hipSuccess;
   auto F = [&](int li, const void* in, int act) {
     if (e == hipSuccess) e = conv_fwd<ST>(c, S, S->L[li], in, S->act[li], act);
@@ -1177,7 +1524,7 @@ hipError_t nn_forward(tosimp_ctx* c, NNState* S) {
                                                (const ST*)S->act[1], b, (ST*)S->cat0, S->g[0]);
   F(9, S->cat0, 1);                    // u0a
   F(10, S->act[9], 1);                 // u0b
-  F(11, S->act[10], 0);                // head (no activation)
+  if (head) F(11, S->act[10], 0);      // head (no activation)
   return e == hipSuccess ? hipGetLastError() : e;
 }
 
@@ -1280,8 +1627,11 @@ int nn_apply_t(tosimp_ctx* ctx, NNState* S, const float* r, float* z) {
   const int nn = (int)ctx->n_node;
   TOSIMP_HIP(ctx, launch_norm2f(ctx->stream, r, (int)ctx->n_dof, S->part, S->scal));
   build_input_kernel<ST><<<2048, 256, 0, ctx->stream>>>(r, S->scal, S->rho_node, (ST*)S->act[12], nn);
-  TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S));
-  output_kernel<ST><<<2048, 256, 0, ctx->stream>>>((const ST*)S->act[11], ctx->ws.mask, S->scal, z, nn);
+  TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S, /*head=*/false));
+  const Layer& hl = S->L[11];
+  head_output_kernel<ST><<<2048, 256, 0, ctx->stream>>>(
+      (const ST*)S->act[10], (const ST*)((const char*)S->W + hl.woff * S->es), hl.cip,
+      ctx->ws.mask, S->scal, z, nn);
   TOSIMP_HIP(ctx, hipGetLastError());
   return TOSIMP_OK;
 }
