@@ -110,6 +110,12 @@ struct ConvArgs {
   int cin, cout;       // channels (multiples of 8 / 16) of the forward convolution
   int ksize, stride;
   int apply_act;       // FWD: leaky ReLU on the output
+  // z-sweep forward with the up-sampling concatenation read in place (c1 > 0): operand
+  // channels [0, c1) are the nearest up-sampling of `in` [Vcoarse][c1] on grid gcoarse,
+  // channels [c1, cin) are `skip` [Vout][cin - c1].
+  const void* skip;
+  Grid3 gcoarse;
+  int c1;
 };
 
 // One wave: RT x 16 "row" voxels of the result x a group of up to 64 result channels
@@ -501,9 +507,10 @@ constexpr int conv3z_waves() {
   return KCH <= 8 ? 5 : KCH <= 16 ? (BWD ? 3 : 4) : KCH <= 32 ? 2 : 1;
 }
 
-template <int KCH, bool BWD>
+template <int KCH, bool BWD, int C1 = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv3z_waves<KCH, BWD>())))
 void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
+  static_assert(C1 == 0 || (!BWD && C1 % 8 == 0 && C1 < KCH), "concatenated operand: forward");
   constexpr int S = conv3z_steps<KCH>();
   constexpr int PV = KCH / 8;                     // 16-byte pieces per voxel
   constexpr int NP = (kZPlane * PV + 255) / 256;  // plane pieces per thread
@@ -525,33 +532,65 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
   // Operand (and stored activation) and result tensors as buffer resources: lanes outside
   // the grid use an offset past the range, so loads return zeros and stores are dropped
   // without branches (the wait for a plane's loads then has a fixed count).
-  const __amdgpu_buffer_rsrc_t rin = conv3z_rsrc(a.in, nvox * KCH * 2);
-  const __amdgpu_buffer_rsrc_t ract = conv3z_rsrc(BWD ? a.act : a.in, nvox * KCH * 2);
+  constexpr int C2 = KCH - C1;  // channels read at the voxel itself
+  const Grid3 gc = a.gcoarse;
+  const __amdgpu_buffer_rsrc_t rin =
+      C1 ? conv3z_rsrc(a.in, (long long)gc.X * gc.Y * gc.Z * C1 * 2) : conv3z_rsrc(a.in, nvox * KCH * 2);
+  const __amdgpu_buffer_rsrc_t ract = C1 ? conv3z_rsrc(a.skip, nvox * C2 * 2)
+                                         : conv3z_rsrc(BWD ? a.act : a.in, nvox * KCH * 2);
   const __amdgpu_buffer_rsrc_t rout = conv3z_rsrc(a.out, nvox * nres * 2);
   const bf16_t* w = (const bf16_t*)a.w;
 
-  // Plane pieces of this thread: window voxel and byte offset in the plane.
+  // Plane pieces of this thread: window voxel and byte offset in the plane.  With C1 the
+  // pieces of the up-sampled channels of every window voxel come first (NC of them, byte
+  // offsets in the coarse plane), then those of the skipped channels, so only the one
+  // register slot straddling the boundary needs both loads.
+  constexpr int NC = kZPlane * C1 / 8;
   int pvox[NP], pgo[NP];
-  bool pok[NP];
+  bool pok[NP], pco[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
     const int idx = tid + 256 * i;
-    const int vb = idx / PV, pc = idx - vb * PV;
+    pco[i] = idx < NC;
+    const int k = pco[i] ? idx : idx - NC;
+    const int pw = pco[i] ? C1 / 8 : C2 / 8;  // pieces per voxel in this part
+    const int vb = k / pw, pc = k - vb * pw;
+    const int ch = pco[i] ? 8 * pc : C1 + 8 * pc;
     const int hx = vb % kZPX, hy = vb / kZPX;
     const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
     pok[i] = idx < kZPlane * PV && gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y;
-    pvox[i] = idx < kZPlane * PV ? vb * VS + 8 * pc : -1;
-    pgo[i] = ((gx + g.X * gy) * KCH + 8 * pc) * 2;
+    pvox[i] = idx < kZPlane * PV ? vb * VS + ch : -1;
+    if (C1 == 0)
+      pgo[i] = ((gx + g.X * gy) * KCH + ch) * 2;
+    else if (pco[i])
+      pgo[i] = (((gx >> 1) + gc.X * (gy >> 1)) * C1 + ch) * 2;
+    else
+      pgo[i] = ((gx + g.X * gy) * C2 + ch - C1) * 2;
   }
-  const int pstride = g.X * g.Y * KCH * 2;  // bytes per plane
+  const int pstride = g.X * g.Y * C2 * 2;          // bytes per plane
+  const int cstride = gc.X * gc.Y * C1 * 2;        // bytes per coarse plane (C1 > 0)
   auto plane_load = [&](Pack8<bf16_t>* pb, Pack8<bf16_t>* pa, int gz) {
     const bool zok = gz >= 0 && gz < g.Z;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-      const int off = zok && pok[i] ? pgo[i] + gz * pstride : kZOOB;
-      pb[i].v = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rin, off, 0, 0));
-      if (BWD)
-        pa[i].v = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(ract, off, 0, 0));
+      if constexpr (C1 == 0) {
+        const int off = zok && pok[i] ? pgo[i] + gz * pstride : kZOOB;
+        pb[i].v = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rin, off, 0, 0));
+        if (BWD)
+          pa[i].v =
+              __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(ract, off, 0, 0));
+      } else if (256 * i + 255 < NC) {  // up-sampled channels only
+        const int offc = zok && pok[i] ? pgo[i] + (gz >> 1) * cstride : kZOOB;
+        pb[i].v = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rin, offc, 0, 0));
+      } else if (256 * i >= NC) {  // skipped channels only
+        const int offs = zok && pok[i] ? pgo[i] + gz * pstride : kZOOB;
+        pb[i].v = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(ract, offs, 0, 0));
+      } else {  // both issued, the one not holding the piece out of range (it returns 0)
+        const int offc = zok && pok[i] && pco[i] ? pgo[i] + (gz >> 1) * cstride : kZOOB;
+        const int offs = zok && pok[i] && !pco[i] ? pgo[i] + gz * pstride : kZOOB;
+        pb[i].v = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rin, offc, 0, 0) |
+                                                __builtin_amdgcn_raw_buffer_load_b128(ract, offs, 0, 0));
+      }
     }
   };
   auto plane_store = [&](Pack8<bf16_t>* pb, Pack8<bf16_t>* pa, int gz) {
@@ -693,10 +732,10 @@ static Conv3zGeom conv3z_geom(const Grid3& g, int groups, int resident) {
   return gm;
 }
 
-template <int KCH, bool BWD>
+template <int KCH, bool BWD, int C1 = 0>
 hipError_t launch_conv3z_t(hipStream_t s, const ConvArgs& a) {
   constexpr int smem = conv3z_lds_bytes<KCH>();
-  auto kern = conv3z_kernel<KCH, BWD>;
+  auto kern = conv3z_kernel<KCH, BWD, C1>;
   // Blocks per CU x CUs, per kernel instance, computed once (concurrent first calls
   // compute the same value).
   static std::atomic<int> resident_once{0};
@@ -720,6 +759,17 @@ hipError_t launch_conv3z_t(hipStream_t s, const ConvArgs& a) {
   const Conv3zGeom gm = conv3z_geom(a.gout, nres / 16, resident);
   kern<<<dim3(8 * gm.per_xcd, nres / 16), 256, smem, s>>>(a, gm);
   return hipGetLastError();
+}
+
+// The level-0 up-sampling layer reading its concatenated operand in place (48 channels:
+// 32 up-sampled, 16 skipped); hipErrorNotSupported for other shapes.
+hipError_t launch_conv3z_cat(hipStream_t s, const ConvArgs& a) {
+  if (a.cin != 48 || a.c1 != 32 || a.cout % 16 || !a.skip ||
+      2LL * a.gout.n() * 48 >= (1LL << 31) ||
+      (a.gcoarse.X - 1) * 2 + 1 < a.gout.X || (a.gcoarse.Y - 1) * 2 + 1 < a.gout.Y ||
+      (a.gcoarse.Z - 1) * 2 + 1 < a.gout.Z)
+    return hipErrorNotSupported;
+  return launch_conv3z_t<48, false, 32>(s, a);
 }
 
 // BF16 stride-1 3x3x3 layers whose K channel count has a z-sweep instance (forward 8, 16,
@@ -1398,8 +1448,11 @@ int wgrad_chunk(int nvox) {
   return std::max(256, (per + 255) / 256 * 256);
 }
 
+// With skip set (BF16 only), `in` is the coarse tensor of an up-sampling concatenation
+// [up(in) | skip] that the z-sweep reads in place; hipErrorNotSupported if it cannot.
 template <typename ST>
-hipError_t conv_fwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* in, void* out, int act) {
+hipError_t conv_fwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* in, void* out, int act,
+                    const void* skip = nullptr, int c1 = 0, Grid3 gcoarse = {}) {
   ConvArgs a{};
   a.in = in;
   a.w = (const char*)S->W + l.woff * S->es;
@@ -1411,6 +1464,13 @@ hipError_t conv_fwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* in, v
   a.ksize = l.k;
   a.stride = l.s;
   a.apply_act = act;
+  if (skip) {
+    if (sizeof(ST) != 2 || l.k != 3 || l.s != 1) return hipErrorNotSupported;
+    a.skip = skip;
+    a.c1 = c1;
+    a.gcoarse = gcoarse;
+    return launch_conv3z_cat(c->stream, a);
+  }
   if constexpr (sizeof(ST) == 2) {
     if (l.k == 3 && l.s == 1) {
       const hipError_t e = launch_conv3z<false>(c->stream, a);
@@ -1500,8 +1560,10 @@ namespace {
 hipError_t nn_alloc(void** p, size_t bytes) { return hipMalloc(p, bytes < 256 ? 256 : bytes); }
 
 // Forward pass from the padded input tensor in act[12]; layer outputs in act[0..11].
+// infer: the preconditioner's forward (no head: it is fused into the output kernel; in
+// BF16 the level-0 concatenation is read in place by u0a instead of being stored).
 template <typename ST>
-hipError_t nn_forward(tosimp_ctx* c, NNState* S, bool head = true) {
+hipError_t nn_forward(tosimp_ctx* c, NNState* S, bool infer = false) {
   hipError_t e = hipSuccess;
   auto F = [&](int li, const void* in, int act) {
     if (e == hipSuccess) e = conv_fwd<ST>(c, S, S->L[li], in, S->act[li], act);
@@ -1520,11 +1582,20 @@ hipError_t nn_forward(tosimp_ctx* c, NNState* S, bool head = true) {
   F(7, S->cat1, 1);                    // u1a
   F(8, S->act[7], 1);                  // u1b
   if (e != hipSuccess) return e;
-  upcat_kernel<ST><<<2048, 256, 0, c->stream>>>((const ST*)S->act[8], S->g[1], 2 * b,
-                                               (const ST*)S->act[1], b, (ST*)S->cat0, S->g[0]);
-  F(9, S->cat0, 1);                    // u0a
+  bool cat0_done = false;
+  if (infer && sizeof(ST) == 2) {      // u0a on [up(u1b) | s0] read in place
+    e = conv_fwd<ST>(c, S, S->L[9], S->act[8], S->act[9], 1, S->act[1], 2 * b, S->g[1]);
+    cat0_done = e == hipSuccess;
+    if (e == hipErrorNotSupported) e = hipSuccess;
+    if (e != hipSuccess) return e;
+  }
+  if (!cat0_done) {
+    upcat_kernel<ST><<<2048, 256, 0, c->stream>>>((const ST*)S->act[8], S->g[1], 2 * b,
+                                                 (const ST*)S->act[1], b, (ST*)S->cat0, S->g[0]);
+    F(9, S->cat0, 1);                  // u0a
+  }
   F(10, S->act[9], 1);                 // u0b
-  if (head) F(11, S->act[10], 0);      // head (no activation)
+  if (!infer) F(11, S->act[10], 0);    // head (no activation)
   return e == hipSuccess ? hipGetLastError() : e;
 }
 
@@ -1627,7 +1698,7 @@ int nn_apply_t(tosimp_ctx* ctx, NNState* S, const float* r, float* z) {
   const int nn = (int)ctx->n_node;
   TOSIMP_HIP(ctx, launch_norm2f(ctx->stream, r, (int)ctx->n_dof, S->part, S->scal));
   build_input_kernel<ST><<<2048, 256, 0, ctx->stream>>>(r, S->scal, S->rho_node, (ST*)S->act[12], nn);
-  TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S, /*head=*/false));
+  TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S, /*infer=*/true));
   const Layer& hl = S->L[11];
   head_output_kernel<ST><<<2048, 256, 0, ctx->stream>>>(
       (const ST*)S->act[10], (const ST*)((const char*)S->W + hl.woff * S->es), hl.cip,
