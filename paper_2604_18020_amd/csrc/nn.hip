@@ -504,7 +504,7 @@ constexpr bool conv3z_prefetch() { return KCH == 32; }
 // the data gradient also holds the stored activation of the planes in flight).
 template <int KCH, bool BWD>
 constexpr int conv3z_waves() {
-  return KCH <= 8 ? 5 : KCH <= 16 ? (BWD ? 3 : 4) : KCH <= 32 ? 2 : 1;
+  return KCH <= 8 ? 5 : KCH <= 16 ? (BWD ? 3 : 4) : KCH <= 48 ? 2 : 1;
 }
 
 template <int KCH, bool BWD, int C1 = 0>
@@ -630,27 +630,12 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
   if (PF) plane_load(r0, ra0, za + 2);
   __syncthreads();
 
-  // Per step s: this lane's (oz, ox, channel) and its operand offset within a slot.
-  int aoff[S], aoz[S];
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int kk = 32 * s + 8 * q;
-    int c = kk / KCH;
-    const int ch = kk - c * KCH;
-    if (c >= 9) c = 0;  // zero weights: any finite operand
-    const int oz = c / 3, ox = c - 3 * oz;
-    aoz[s] = oz;
-    aoff[s] = ((kZRW * wv) * kZPX + m + ox) * VS + ch;
-  }
-  // Result offsets (bytes) of this lane's voxels in a plane; past the range outside the grid.
-  int ooff[kZRW][4];
-#pragma unroll
-  for (int r = 0; r < kZRW; ++r)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gx = x0 + 4 * q + j, gy = y0 + kZRW * wv + r;
-      ooff[r][j] = gx < g.X && gy < g.Y ? ((gx + g.X * gy) * nres + cg + m) * 2 : -1;
-    }
+  // Operand offset of this lane's window row 2 wv, voxel m, within a slot; per step s the
+  // lane's (oz, ox, channel) follow from 32 s + 8 q (formed where used: few registers).
+  const int lbase = ((kZRW * wv) * kZPX + m) * VS;
+  // Result offset (bytes) of this lane's first voxel in a plane.
+  const int gx0 = x0 + 4 * q, gy0 = y0 + kZRW * wv;
+  const int obase = ((gx0 + g.X * gy0) * nres + cg + m) * 2;
   const int ostride = g.X * g.Y * nres * 2;  // bytes per result plane
   // Step z: issue plane z + 3 into `ld`, form result plane z, store plane z + 2 (issued
   // the step before, in `st`) into its slot, barrier.  Steps run in pairs; the second of
@@ -668,7 +653,12 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
               sb2 = ((z + 5) & 3) * (kZPlane * VS);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const bf16_t* ab = planes + (aoz[s] == 0 ? sb0 : aoz[s] == 1 ? sb1 : sb2) + aoff[s];
+      const int kk = 32 * s + 8 * q;
+      int c = kk / KCH;
+      const int ch = kk - c * KCH;
+      if (c >= 9) c = 0;  // zero weights: any finite operand
+      const int oz = c / 3, ox = c - 3 * oz;
+      const bf16_t* ab = planes + (oz == 0 ? sb0 : oz == 1 ? sb1 : sb2) + lbase + ox * VS + ch;
 #pragma unroll
       for (int rho = 0; rho < kZRW + 2; ++rho) {
         Pack8<bf16_t> A;
@@ -687,7 +677,8 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
       for (int j = 0; j < 4; ++j) {
         float val = acc[r][j];
         if (!BWD && a.apply_act) val = val > 0.0f ? val : kLeak * val;
-        const int off = zin && ooff[r][j] >= 0 ? ooff[r][j] + z * ostride : kZOOB;
+        const bool ok = zin && gx0 + j < g.X && gy0 + r < g.Y;
+        const int off = ok ? obase + (j + g.X * r) * (nres * 2) + z * ostride : kZOOB;
         __builtin_amdgcn_raw_buffer_store_b16(from_f<bf16_t>(val).bits, rout, off, 0, 0);
       }
     plane_store(st, sta, z + 2);
