@@ -494,6 +494,56 @@ def mg_study(workload="cantilever_340x170x85", reps=3, tol=1e-6, volfrac=0.3):
     return out
 
 
+def unet_study(workload="cantilever_200x100x50", applies=20, train_steps=5, base=16):
+    """The learned preconditioner's kernels on their own: the U-Net (BF16 storage, random
+    He-scaled weights, uniform density 0.3) applied `applies` times to a random residual,
+    then `train_steps` Adam steps on batches of four random pairs.  Per-call wall times
+    (HIP synchronised) and the forward's matrix-core rate."""
+    import numpy as np
+    import torch
+
+    t, cfg, f, _ = _problem(workload)
+    t.nn_create(base, bf16=True)
+    rng = np.random.default_rng(0)
+    t.nn_set_weights(rng.standard_normal(t.nn_params).astype(np.float32) * 0.05)
+    t.nn_set_density(torch.full((t.n_elem,), 0.3, dtype=torch.float64, device="cuda:0"))
+    gen = torch.Generator(device="cuda:0").manual_seed(1)
+    r = torch.randn(t.n_dof, dtype=torch.float32, device="cuda:0", generator=gen)
+    z = torch.empty_like(r)
+    for _ in range(3):
+        t.nn_apply(r, z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(applies):
+        t.nn_apply(r, z)
+    torch.cuda.synchronize()
+    apply_s = (time.perf_counter() - t0) / applies
+    rb = torch.randn(4, t.n_dof, dtype=torch.float32, device="cuda:0", generator=gen)
+    eb = torch.randn(4, t.n_dof, dtype=torch.float32, device="cuda:0", generator=gen)
+    t.nn_train_step(rb, eb, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(train_steps):
+        t.nn_train_step(rb, eb, 1e-4)
+    torch.cuda.synchronize()
+    train_s = (time.perf_counter() - t0) / train_steps
+    # matrix-core work of one forward: 2 x taps x cin x cout per output voxel and layer
+    g = [(cfg["nx"] + 1, cfg["ny"] + 1, cfg["nz"] + 1)]
+    for _ in range(2):
+        g.append(tuple((d - 1) // 2 + 1 for d in g[-1]))
+    nvox = [a * b * c for a, b, c in g]
+    b = base
+    layers = [(4, b, 27, 0), (b, b, 27, 0), (b, 2 * b, 27, 1), (2 * b, 2 * b, 27, 1),
+              (2 * b, 4 * b, 27, 2), (4 * b, 4 * b, 27, 2), (4 * b, 4 * b, 27, 2),
+              (6 * b, 2 * b, 27, 1), (2 * b, 2 * b, 27, 1), (3 * b, b, 27, 0), (b, b, 27, 0),
+              (b, 3, 1, 0)]
+    flop = sum(2.0 * taps * ci * co * nvox[lv] for ci, co, taps, lv in layers)
+    t.close()
+    return {"workload": workload, "base": base, "storage": "bf16", "apply_ms": apply_s * 1e3,
+            "forward_gflop": flop / 1e9, "forward_tflops": flop / apply_s / 1e12,
+            "frac_of_bf16_peak": flop / apply_s / 2.5e15, "train_step_ms_batch4": train_s * 1e3}
+
+
 def pcg_cold_study(workloads=("cantilever_120x60x30", "torsion_55x55x165",
                               "cantilever_200x100x50"), tol=1e-6):
     """Cold-start PCG at uniform density on the other benchmark meshes (the main line
@@ -752,6 +802,9 @@ def main():
     ap.add_argument("--mg-study", action="store_true",
                     help="time the multigrid-preconditioned CG solves on the workload (prints "
                          "that JSON only)")
+    ap.add_argument("--unet-study", action="store_true",
+                    help="time the U-Net preconditioner's forward application and training "
+                         "step at 200x100x50 (prints that JSON only)")
     ap.add_argument("--scatter-study", action="store_true",
                     help="time the owner-computes operator against its atomic-scatter forms "
                          "on the workload (prints that JSON only)")
@@ -773,6 +826,9 @@ def main():
         return
     if a.mg_study:
         print(json.dumps({"mg_study": mg_study(a.workload)}), flush=True)
+        return
+    if a.unet_study:
+        print(json.dumps({"unet_study": unet_study()}), flush=True)
         return
     if a.simp_kernels or a.scatter_study:
         if a.copy_calibration:

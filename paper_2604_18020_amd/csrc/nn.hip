@@ -755,10 +755,10 @@ hipError_t launch_conv3z_t(hipStream_t s, const ConvArgs& a) {
 // The level-0 up-sampling layer reading its concatenated operand in place (48 channels:
 // 32 up-sampled, 16 skipped); hipErrorNotSupported for other shapes.
 hipError_t launch_conv3z_cat(hipStream_t s, const ConvArgs& a) {
+  // every result voxel's coarse parent (x / 2, y / 2, z / 2) lies on the coarse grid
   if (a.cin != 48 || a.c1 != 32 || a.cout % 16 || !a.skip ||
-      2LL * a.gout.n() * 48 >= (1LL << 31) ||
-      (a.gcoarse.X - 1) * 2 + 1 < a.gout.X || (a.gcoarse.Y - 1) * 2 + 1 < a.gout.Y ||
-      (a.gcoarse.Z - 1) * 2 + 1 < a.gout.Z)
+      2LL * a.gout.n() * 48 >= (1LL << 31) || a.gout.X > 2 * a.gcoarse.X ||
+      a.gout.Y > 2 * a.gcoarse.Y || a.gout.Z > 2 * a.gcoarse.Z)
     return hipErrorNotSupported;
   return launch_conv3z_t<48, false, 32>(s, a);
 }
