@@ -694,13 +694,14 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
   }
 }
 
-// Chunks of result planes: a chunk of kz planes loads kz + 2 operand planes, and the grid
-// runs in ceil(blocks / resident) rounds, so kz minimises rounds x (kz + 2) (idle slots of
-// a partial first round counted as lost).
-static Conv3zGeom conv3z_geom(const Grid3& g, int groups, int resident) {
+// Chunks of result planes: a chunk of kz planes loads stride (kz - 1) + 3 operand planes,
+// and the grid runs in ceil(blocks / resident) rounds, so kz minimises rounds x planes
+// loaded (idle slots of a partial first round counted as lost).  Result tiles tx x ty.
+static Conv3zGeom conv3z_geom(const Grid3& g, int groups, int resident, int tx = kZX,
+                              int ty = kZY, int stride = 1) {
   Conv3zGeom gm;
-  gm.tiles_x = (g.X + kZX - 1) / kZX;
-  gm.tiles_y = (g.Y + kZY - 1) / kZY;
+  gm.tiles_x = (g.X + tx - 1) / tx;
+  gm.tiles_y = (g.Y + ty - 1) / ty;
   const long long cols = (long long)gm.tiles_x * gm.tiles_y * groups;
   if (resident < 1) resident = 1;
   double best = 1e300;
@@ -711,7 +712,7 @@ static Conv3zGeom conv3z_geom(const Grid3& g, int groups, int resident) {
     const long long n = cols * nch;
     const long long rounds = (n + resident - 1) / resident;
     const double fill = n >= resident ? 1.0 : (double)n / resident;
-    const double cost = (double)rounds * (kz + 2) / fill;
+    const double cost = (double)rounds * (stride * (kz - 1) + 3) / fill;
     if (cost < best - 1e-9) {
       best = cost;
       best_kz = kz;
@@ -723,15 +724,12 @@ static Conv3zGeom conv3z_geom(const Grid3& g, int groups, int resident) {
   return gm;
 }
 
-template <int KCH, bool BWD, int C1 = 0>
-hipError_t launch_conv3z_t(hipStream_t s, const ConvArgs& a) {
-  constexpr int smem = conv3z_lds_bytes<KCH>();
-  auto kern = conv3z_kernel<KCH, BWD, C1>;
-  // Blocks per CU x CUs, per kernel instance, computed once (concurrent first calls
-  // compute the same value).
-  static std::atomic<int> resident_once{0};
-  int resident = resident_once.load(std::memory_order_relaxed);
-  if (resident == 0) {
+// Blocks per CU x CUs for a kernel instance with `smem` bytes of dynamic LDS (which it is
+// allowed), computed once per instance (concurrent first calls compute the same value).
+template <typename K>
+static hipError_t conv_resident(K kern, int smem, std::atomic<int>& once, int* resident) {
+  int r = once.load(std::memory_order_relaxed);
+  if (r == 0) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, smem);
     if (e != hipSuccess) return e;
@@ -743,13 +741,178 @@ hipError_t launch_conv3z_t(hipStream_t s, const ConvArgs& a) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, smem) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
-    resident = per_cu * cus;
-    resident_once.store(resident, std::memory_order_relaxed);
+    r = per_cu * cus;
+    once.store(r, std::memory_order_relaxed);
   }
+  *resident = r;
+  return hipSuccess;
+}
+
+template <int KCH, bool BWD, int C1 = 0>
+hipError_t launch_conv3z_t(hipStream_t s, const ConvArgs& a) {
+  constexpr int smem = conv3z_lds_bytes<KCH>();
+  auto kern = conv3z_kernel<KCH, BWD, C1>;
+  static std::atomic<int> once{0};
+  int resident = 0;
+  const hipError_t e = conv_resident(kern, smem, once, &resident);
+  if (e != hipSuccess) return e;
   const int nres = BWD ? a.cin : a.cout;
   const Conv3zGeom gm = conv3z_geom(a.gout, nres / 16, resident);
   kern<<<dim3(8 * gm.per_xcd, nres / 16), 256, smem, s>>>(a, gm);
   return hipGetLastError();
+}
+
+// Stride-2 3x3x3 convolutions in BF16 (the encoder's down-sampling layers, forward) as a
+// z-sweep: result plane z reads operand planes 2z - 1, 2z, 2z + 1.  A block owns a 16 x 4
+// column of result voxels, a chunk of result planes and 16 result channels; wave w holds
+// result row w.  Operand planes pass through a ring of five LDS slots (33 x 9 voxel
+// windows with all KCH channels): step z issues the loads of planes 2z + 2 and 2z + 3,
+// forms result plane z from the slots of planes 2z - 1 .. 2z + 1 (lane m reads window
+// voxel 2m + ox), stores the two new planes into their slots and ends with one barrier.
+// K steps and register-held weights as in the stride-1 sweep; one accumulator per y
+// offset, added in the order oy = 0, 1, 2.
+constexpr int kSX = 16, kSY = 4;                                                // result tile
+constexpr int kSPX = 2 * kSX + 1, kSPY = 2 * kSY + 1, kSPlane = kSPX * kSPY;  // 33 x 9 window
+constexpr int kSSlots = 5;
+
+template <int KCH>
+constexpr int conv3s2_lds_bytes() { return kSSlots * kSPlane * KCH * 2; }
+
+template <int KCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KCH <= 16 ? 3 : 1)))
+void conv3s2_kernel(ConvArgs a, Conv3zGeom gm) {
+  constexpr int S = conv3z_steps<KCH>();
+  constexpr int PV = KCH / 8;                      // 16-byte pieces per voxel
+  constexpr int NP = (kSPlane * PV + 255) / 256;   // pieces per thread and plane
+  constexpr int SLOT = kSPlane * KCH;              // elements per slot
+  extern __shared__ __attribute__((aligned(16))) unsigned char zsm[];
+  bf16_t* planes = reinterpret_cast<bf16_t*>(zsm);  // [5 slots][297 voxels][KCH]
+  const int blin = (blockIdx.x & 7) * gm.per_xcd + (blockIdx.x >> 3);
+  if (blin >= gm.nblk) return;  // whole block
+  const Grid3 gi = a.gin, g = a.gout;
+  const int bx = blin % gm.tiles_x, rest = blin / gm.tiles_x;
+  const int by = rest % gm.tiles_y, bz = rest / gm.tiles_y;
+  const int x0 = bx * kSX, y0 = by * kSY;
+  const int za = bz * gm.kz, zb = min(za + gm.kz, g.Z);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m = lane & 15, q = lane >> 4;
+  const int nres = a.cout;
+  const int cg = blockIdx.y * 16;
+  const __amdgpu_buffer_rsrc_t rin = conv3z_rsrc(a.in, (long long)gi.n() * KCH * 2);
+  const __amdgpu_buffer_rsrc_t rout = conv3z_rsrc(a.out, (long long)g.n() * nres * 2);
+
+  int pvox[NP], pgo[NP];
+  bool pok[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int idx = tid + 256 * i;
+    const int vb = idx / PV, pc = idx - vb * PV;
+    const int hx = vb % kSPX, hy = vb / kSPX;
+    const int gx = 2 * x0 - 1 + hx, gy = 2 * y0 - 1 + hy;
+    pok[i] = idx < kSPlane * PV && gx >= 0 && gx < gi.X && gy >= 0 && gy < gi.Y;
+    pvox[i] = idx < kSPlane * PV ? vb * KCH + 8 * pc : -1;
+    pgo[i] = ((gx + gi.X * gy) * KCH + 8 * pc) * 2;
+  }
+  const int pstride = gi.X * gi.Y * KCH * 2;  // bytes per operand plane
+  auto plane_load = [&](Pack8<bf16_t>* pb, int gz) {
+    const bool zok = gz >= 0 && gz < gi.Z;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int off = zok && pok[i] ? pgo[i] + gz * pstride : kZOOB;
+      pb[i].v = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rin, off, 0, 0));
+    }
+  };
+  auto plane_store = [&](const Pack8<bf16_t>* pb, int gz) {  // gz >= -1
+    bf16_t* dst = planes + ((gz + kSSlots) % kSSlots) * SLOT;
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+      if (pvox[i] >= 0) pb[i].store(dst + pvox[i]);
+  };
+
+  Pack8<bf16_t> Bw[3][S];
+#pragma unroll
+  for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+    for (int s = 0; s < S; ++s) conv3z_wload<KCH, false>(Bw[oy][s], (const bf16_t*)a.w, cg + m, oy, s, q);
+  {  // planes 2 za - 1, 2 za, 2 za + 1
+    Pack8<bf16_t> p0[NP], p1[NP], p2[NP];
+    plane_load(p0, 2 * za - 1);
+    plane_load(p1, 2 * za);
+    plane_load(p2, 2 * za + 1);
+    plane_store(p0, 2 * za - 1);
+    plane_store(p1, 2 * za);
+    plane_store(p2, 2 * za + 1);
+  }
+  __syncthreads();
+
+  const int lbase = ((2 * wv) * kSPX + 2 * m) * KCH;  // window row 2 wv, voxel 2 m
+  const int gx0 = x0 + 4 * q, gy = y0 + wv;
+  const int obase = ((gx0 + g.X * gy) * nres + cg + m) * 2;
+  const int ostride = g.X * g.Y * nres * 2;
+  for (int z = za; z < zb; ++z) {
+    Pack8<bf16_t> pa[NP], pb[NP];
+    plane_load(pa, 2 * z + 2);
+    plane_load(pb, 2 * z + 3);
+    f32x4 acc[3];
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy) acc[oy] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    const int sb0 = ((2 * z - 1 + kSSlots) % kSSlots) * SLOT;
+    const int sb1 = ((2 * z + kSSlots) % kSSlots) * SLOT;
+    const int sb2 = ((2 * z + 1 + kSSlots) % kSSlots) * SLOT;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int kk = 32 * s + 8 * q;
+      int c = kk / KCH;
+      const int ch = kk - c * KCH;
+      if (c >= 9) c = 0;  // zero weights: any finite operand
+      const int oz = c / 3, ox = c - 3 * oz;
+      const bf16_t* ab = planes + (oz == 0 ? sb0 : oz == 1 ? sb1 : sb2) + lbase + ox * KCH + ch;
+#pragma unroll
+      for (int oy = 0; oy < 3; ++oy) {
+        Pack8<bf16_t> A;
+        A.load(ab + oy * (kSPX * KCH));
+        mma32(acc[oy], A, Bw[oy][s]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float val = (acc[0][j] + acc[1][j]) + acc[2][j];
+      if (a.apply_act) val = val > 0.0f ? val : kLeak * val;
+      const bool ok = gx0 + j < g.X && gy < g.Y;
+      const int off = ok ? obase + j * (nres * 2) + z * ostride : kZOOB;
+      __builtin_amdgcn_raw_buffer_store_b16(from_f<bf16_t>(val).bits, rout, off, 0, 0);
+    }
+    plane_store(pa, 2 * z + 2);
+    plane_store(pb, 2 * z + 3);
+    __syncthreads();
+  }
+}
+
+template <int KCH>
+hipError_t launch_conv3s2_t(hipStream_t s, const ConvArgs& a) {
+  constexpr int smem = conv3s2_lds_bytes<KCH>();
+  auto kern = conv3s2_kernel<KCH>;
+  static std::atomic<int> once{0};
+  int resident = 0;
+  const hipError_t e = conv_resident(kern, smem, once, &resident);
+  if (e != hipSuccess) return e;
+  const Conv3zGeom gm = conv3z_geom(a.gout, a.cout / 16, resident, kSX, kSY, 2);
+  kern<<<dim3(8 * gm.per_xcd, a.cout / 16), 256, smem, s>>>(a, gm);
+  return hipGetLastError();
+}
+
+// BF16 stride-2 3x3x3 forward with 16 or 32 operand channels on grids whose result is the
+// operand's (n - 1) / 2 + 1 per axis; hipErrorNotSupported for the others.
+hipError_t launch_conv3s2(hipStream_t s, const ConvArgs& a) {
+  if (a.cout % 16 || a.gout.X != (a.gin.X - 1) / 2 + 1 || a.gout.Y != (a.gin.Y - 1) / 2 + 1 ||
+      a.gout.Z != (a.gin.Z - 1) / 2 + 1 || 2LL * a.gin.n() * a.cin >= (1LL << 31) ||
+      2LL * a.gout.n() * a.cout >= (1LL << 31))
+    return hipErrorNotSupported;
+  switch (a.cin) {
+    case 16: return launch_conv3s2_t<16>(s, a);
+    case 32: return launch_conv3s2_t<32>(s, a);
+    default: return hipErrorNotSupported;
+  }
 }
 
 // The level-0 up-sampling layer reading its concatenated operand in place (48 channels:
@@ -1463,8 +1626,9 @@ hipError_t conv_fwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* in, v
     return launch_conv3z_cat(c->stream, a);
   }
   if constexpr (sizeof(ST) == 2) {
-    if (l.k == 3 && l.s == 1) {
-      const hipError_t e = launch_conv3z<false>(c->stream, a);
+    if (l.k == 3 && (l.s == 1 || l.s == 2)) {
+      const hipError_t e = l.s == 1 ? launch_conv3z<false>(c->stream, a)
+                                    : launch_conv3s2(c->stream, a);
       if (e != hipErrorNotSupported) return e;
     }
   }
