@@ -476,6 +476,41 @@ struct Conv3zGeom {
 // K index 32 s + 8 q within oy's group; zero past the nine (oz, ox) offsets.
 template <int KCH, bool BWD>
 __device__ __forceinline__ void conv3z_wload(Pack8<bf16_t>& B, const bf16_t* w, int row, int oy,
+                                             int s, int q);
+
+// The block's weight tiles (16 result channels from row0, 3 oy x S steps) fetched once
+// per block into the LDS area `stage` (before any operand plane is staged there), then
+// into every wave's registers; the block's threads share the global loads.
+template <int KCH, bool BWD, int NT>
+__device__ __forceinline__ void conv3z_weights(Pack8<bf16_t> (&Bw)[3][conv3z_steps<KCH>()],
+                                               const bf16_t* w, int row0, bf16_t* stage) {
+  constexpr int S = conv3z_steps<KCH>();
+  constexpr int NW = 3 * S * 16 * 4;  // 16-byte pieces
+  constexpr int NI = (NW + NT - 1) / NT;
+  const int tid = threadIdx.x, m = tid & 15, q = (tid & 63) >> 4;
+  Pack8<bf16_t> t[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int idx = tid + NT * i;
+    const int qq = idx & 3, n = (idx >> 2) & 15, rs = idx >> 6;
+    t[i].zero();
+    if (idx < NW) conv3z_wload<KCH, BWD>(t[i], w, row0 + n, rs / S, rs % S, qq);
+  }
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int idx = tid + NT * i;
+    if (idx < NW) t[i].store(stage + 8 * idx);  // piece idx = ((oy S + s) 16 + n) 4 + qq
+  }
+  __syncthreads();
+#pragma unroll
+  for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+    for (int s = 0; s < S; ++s) Bw[oy][s].load(stage + 8 * ((((oy * S + s) * 16 + m) << 2) + q));
+  __syncthreads();  // the operand planes overwrite the staging area next
+}
+
+template <int KCH, bool BWD>
+__device__ __forceinline__ void conv3z_wload(Pack8<bf16_t>& B, const bf16_t* w, int row, int oy,
                                              int s, int q) {
   const int kk = 32 * s + 8 * q;
   const int c = kk / KCH, ch = kk - c * KCH;
@@ -609,11 +644,9 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
   };
 
   // Weights: in registers for the sweep.
+  static_assert(3 * S * 16 * 32 <= kZSlots * kZPlane * VS, "weight staging fits the slots");
   Pack8<bf16_t> Bw[3][S];
-#pragma unroll
-  for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-    for (int s = 0; s < S; ++s) conv3z_wload<KCH, BWD>(Bw[oy][s], w, cg + m, oy, s, q);
+  conv3z_weights<KCH, BWD, 256>(Bw, w, cg, planes);
   {  // planes za - 1, za, za + 1
     Pack8<bf16_t> p0[NP], a0[BWD ? NP : 1], p1[NP], a1[BWD ? NP : 1], p2[NP], a2[BWD ? NP : 1];
     plane_load(p0, a0, za - 1);
@@ -829,11 +862,9 @@ void conv3s2_kernel(ConvArgs a, Conv3zGeom gm) {
       if (pvox[i] >= 0) pb[i].store(dst + pvox[i]);
   };
 
+  static_assert(3 * S * 16 * 32 <= kSSlots * SLOT, "weight staging fits the slots");
   Pack8<bf16_t> Bw[3][S];
-#pragma unroll
-  for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-    for (int s = 0; s < S; ++s) conv3z_wload<KCH, false>(Bw[oy][s], (const bf16_t*)a.w, cg + m, oy, s, q);
+  conv3z_weights<KCH, false, 256>(Bw, (const bf16_t*)a.w, cg, planes);
   {  // planes 2 za - 1, 2 za, 2 za + 1
     Pack8<bf16_t> p0[NP], p1[NP], p2[NP];
     plane_load(p0, 2 * za - 1);
