@@ -116,6 +116,10 @@ struct ConvArgs {
   const void* skip;
   Grid3 gcoarse;
   int c1;
+  // z-sweep weight rows: channel stride per tap wk (0: the sweep's K channels) and first
+  // channel wc0 (a pass over part of K); FP32 partial result of a two-pass layer.
+  int wk, wc0;
+  float* part;
 };
 
 // One wave: RT x 16 "row" voxels of the result x a group of up to 64 result channels
@@ -476,14 +480,15 @@ struct Conv3zGeom {
 // K index 32 s + 8 q within oy's group; zero past the nine (oz, ox) offsets.
 template <int KCH, bool BWD>
 __device__ __forceinline__ void conv3z_wload(Pack8<bf16_t>& B, const bf16_t* w, int row, int oy,
-                                             int s, int q);
+                                             int s, int q, int wk, int wc0);
 
 // The block's weight tiles (16 result channels from row0, 3 oy x S steps) fetched once
 // per block into the LDS area `stage` (before any operand plane is staged there), then
 // into every wave's registers; the block's threads share the global loads.
 template <int KCH, bool BWD, int NT>
 __device__ __forceinline__ void conv3z_weights(Pack8<bf16_t> (&Bw)[3][conv3z_steps<KCH>()],
-                                               const bf16_t* w, int row0, bf16_t* stage) {
+                                               const bf16_t* w, int row0, bf16_t* stage,
+                                               int wk = KCH, int wc0 = 0) {
   constexpr int S = conv3z_steps<KCH>();
   constexpr int NW = 3 * S * 16 * 4;  // 16-byte pieces
   constexpr int NI = (NW + NT - 1) / NT;
@@ -494,7 +499,7 @@ __device__ __forceinline__ void conv3z_weights(Pack8<bf16_t> (&Bw)[3][conv3z_ste
     const int idx = tid + NT * i;
     const int qq = idx & 3, n = (idx >> 2) & 15, rs = idx >> 6;
     t[i].zero();
-    if (idx < NW) conv3z_wload<KCH, BWD>(t[i], w, row0 + n, rs / S, rs % S, qq);
+    if (idx < NW) conv3z_wload<KCH, BWD>(t[i], w, row0 + n, rs / S, rs % S, qq, wk, wc0);
   }
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
@@ -509,16 +514,17 @@ __device__ __forceinline__ void conv3z_weights(Pack8<bf16_t> (&Bw)[3][conv3z_ste
   __syncthreads();  // the operand planes overwrite the staging area next
 }
 
+// Weight rows hold 27 taps of wk channels; the sweep's K channels start at wc0.
 template <int KCH, bool BWD>
 __device__ __forceinline__ void conv3z_wload(Pack8<bf16_t>& B, const bf16_t* w, int row, int oy,
-                                             int s, int q) {
+                                             int s, int q, int wk, int wc0) {
   const int kk = 32 * s + 8 * q;
   const int c = kk / KCH, ch = kk - c * KCH;
   B.zero();
   if (c < 9) {
     const int oz = c / 3, ox = c - 3 * oz;
     const int t = ox + 3 * oy + 9 * oz;
-    B.load(w + (long long)row * (27 * KCH) + (BWD ? 26 - t : t) * KCH + ch);
+    B.load(w + (long long)row * (27 * wk) + (BWD ? 26 - t : t) * wk + wc0 + ch);
   }
 }
 
@@ -542,10 +548,14 @@ constexpr int conv3z_waves() {
   return KCH <= 8 ? 5 : KCH <= 16 ? (BWD ? 3 : 4) : KCH <= 48 ? 2 : 1;
 }
 
-template <int KCH, bool BWD, int C1 = 0>
+// OUTM 0: BF16 result (with the activation); 1: FP32 partial sums into a.part (no
+// activation); 2: the FP32 partial in a.part added first, then the activation and the
+// BF16 result (the two passes of a layer whose K is split).
+template <int KCH, bool BWD, int C1 = 0, int OUTM = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv3z_waves<KCH, BWD>())))
 void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
-  static_assert(C1 == 0 || (!BWD && C1 % 8 == 0 && C1 < KCH), "concatenated operand: forward");
+  static_assert(C1 == 0 || (!BWD && C1 % 8 == 0 && C1 <= KCH), "concatenated operand: forward");
+  static_assert(OUTM == 0 || !BWD, "split K: forward");
   constexpr int S = conv3z_steps<KCH>();
   constexpr int PV = KCH / 8;                     // 16-byte pieces per voxel
   constexpr int NP = (kZPlane * PV + 255) / 256;  // plane pieces per thread
@@ -574,6 +584,7 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
   const __amdgpu_buffer_rsrc_t ract = C1 ? conv3z_rsrc(a.skip, nvox * C2 * 2)
                                          : conv3z_rsrc(BWD ? a.act : a.in, nvox * KCH * 2);
   const __amdgpu_buffer_rsrc_t rout = conv3z_rsrc(a.out, nvox * nres * 2);
+  const __amdgpu_buffer_rsrc_t rpart = conv3z_rsrc(a.part, OUTM ? nvox * nres * 4 : 0);
   const bf16_t* w = (const bf16_t*)a.w;
 
   // Plane pieces of this thread: window voxel and byte offset in the plane.  With C1 the
@@ -588,7 +599,7 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
     const int idx = tid + 256 * i;
     pco[i] = idx < NC;
     const int k = pco[i] ? idx : idx - NC;
-    const int pw = pco[i] ? C1 / 8 : C2 / 8;  // pieces per voxel in this part
+    const int pw = pco[i] ? C1 / 8 : (C2 ? C2 / 8 : 1);  // pieces per voxel in this part
     const int vb = k / pw, pc = k - vb * pw;
     const int ch = pco[i] ? 8 * pc : C1 + 8 * pc;
     const int hx = vb % kZPX, hy = vb / kZPX;
@@ -646,7 +657,7 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
   // Weights: in registers for the sweep.
   static_assert(3 * S * 16 * 32 <= kZSlots * kZPlane * VS, "weight staging fits the slots");
   Pack8<bf16_t> Bw[3][S];
-  conv3z_weights<KCH, BWD, 256>(Bw, w, cg, planes);
+  conv3z_weights<KCH, BWD, 256>(Bw, w, cg, planes, a.wk ? a.wk : KCH, a.wc0);
   {  // planes za - 1, za, za + 1
     Pack8<bf16_t> p0[NP], a0[BWD ? NP : 1], p1[NP], a1[BWD ? NP : 1], p2[NP], a2[BWD ? NP : 1];
     plane_load(p0, a0, za - 1);
@@ -679,6 +690,18 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
       plane_load(ld, lda, z + 3);
     else
       plane_load(st, sta, z + 2);
+    const bool zin = z < zb;
+    float pin[kZRW][4];  // the first pass's FP32 sums (OUTM 2), issued with the planes
+    if constexpr (OUTM == 2) {
+#pragma unroll
+      for (int r = 0; r < kZRW; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool ok = zin && gx0 + j < g.X && gy0 + r < g.Y;
+          const int off = ok ? 2 * (obase + (j + g.X * r) * (nres * 2) + z * ostride) : kZOOB;
+          pin[r][j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rpart, off, 0, 0));
+        }
+    }
     f32x4 acc[kZRW];
 #pragma unroll
     for (int r = 0; r < kZRW; ++r) acc[r] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
@@ -703,16 +726,20 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
         }
       }
     }
-    const bool zin = z < zb;
 #pragma unroll
     for (int r = 0; r < kZRW; ++r)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        float val = acc[r][j];
-        if (!BWD && a.apply_act) val = val > 0.0f ? val : kLeak * val;
         const bool ok = zin && gx0 + j < g.X && gy0 + r < g.Y;
         const int off = ok ? obase + (j + g.X * r) * (nres * 2) + z * ostride : kZOOB;
-        __builtin_amdgcn_raw_buffer_store_b16(from_f<bf16_t>(val).bits, rout, off, 0, 0);
+        if constexpr (OUTM == 1) {
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[r][j]), rpart,
+                                                ok ? 2 * off : kZOOB, 0, 0);
+        } else {
+          float val = OUTM == 2 ? pin[r][j] + acc[r][j] : acc[r][j];
+          if (!BWD && a.apply_act) val = val > 0.0f ? val : kLeak * val;
+          __builtin_amdgcn_raw_buffer_store_b16(from_f<bf16_t>(val).bits, rout, off, 0, 0);
+        }
       }
     plane_store(st, sta, z + 2);
     __syncthreads();
@@ -781,10 +808,10 @@ static hipError_t conv_resident(K kern, int smem, std::atomic<int>& once, int* r
   return hipSuccess;
 }
 
-template <int KCH, bool BWD, int C1 = 0>
+template <int KCH, bool BWD, int C1 = 0, int OUTM = 0>
 hipError_t launch_conv3z_t(hipStream_t s, const ConvArgs& a) {
   constexpr int smem = conv3z_lds_bytes<KCH>();
-  auto kern = conv3z_kernel<KCH, BWD, C1>;
+  auto kern = conv3z_kernel<KCH, BWD, C1, OUTM>;
   static std::atomic<int> once{0};
   int resident = 0;
   const hipError_t e = conv_resident(kern, smem, once, &resident);
@@ -864,7 +891,7 @@ void conv3s2_kernel(ConvArgs a, Conv3zGeom gm) {
 
   static_assert(3 * S * 16 * 32 <= kSSlots * SLOT, "weight staging fits the slots");
   Pack8<bf16_t> Bw[3][S];
-  conv3z_weights<KCH, false, 256>(Bw, (const bf16_t*)a.w, cg, planes);
+  conv3z_weights<KCH, false, 256>(Bw, (const bf16_t*)a.w, cg, planes, KCH, 0);
   {  // planes 2 za - 1, 2 za, 2 za + 1
     Pack8<bf16_t> p0[NP], p1[NP], p2[NP];
     plane_load(p0, 2 * za - 1);
@@ -946,15 +973,32 @@ hipError_t launch_conv3s2(hipStream_t s, const ConvArgs& a) {
   }
 }
 
-// The level-0 up-sampling layer reading its concatenated operand in place (48 channels:
-// 32 up-sampled, 16 skipped); hipErrorNotSupported for other shapes.
+// The up-sampling layers reading their concatenated operand in place (48 channels: 32
+// up-sampled, 16 skipped; 96: 64 up-sampled, 32 skipped, in two passes through a.part);
+// hipErrorNotSupported for other shapes.
 hipError_t launch_conv3z_cat(hipStream_t s, const ConvArgs& a) {
   // every result voxel's coarse parent (x / 2, y / 2, z / 2) lies on the coarse grid
-  if (a.cin != 48 || a.c1 != 32 || a.cout % 16 || !a.skip ||
-      2LL * a.gout.n() * 48 >= (1LL << 31) || a.gout.X > 2 * a.gcoarse.X ||
-      a.gout.Y > 2 * a.gcoarse.Y || a.gout.Z > 2 * a.gcoarse.Z)
+  if (a.cout % 16 || !a.skip || 4LL * a.gout.n() * (a.cin > a.cout ? a.cin : a.cout) >= (1LL << 31) ||
+      a.gout.X > 2 * a.gcoarse.X || a.gout.Y > 2 * a.gcoarse.Y || a.gout.Z > 2 * a.gcoarse.Z)
     return hipErrorNotSupported;
-  return launch_conv3z_t<48, false, 32>(s, a);
+  if (a.cin == 48 && a.c1 == 32) return launch_conv3z_t<48, false, 32>(s, a);
+  if (a.cin == 96 && a.c1 == 64 && a.part) {
+    // two passes over K: the 64 up-sampled channels into the FP32 partial, then the 32
+    // skipped channels added with the activation (weight rows of 27 x 96 channels)
+    ConvArgs p = a;
+    p.wk = 96;
+    p.wc0 = 0;
+    hipError_t e = launch_conv3z_t<64, false, 64, 1>(s, p);
+    if (e != hipSuccess) return e;
+    ConvArgs q = a;
+    q.in = a.skip;
+    q.skip = nullptr;
+    q.c1 = 0;
+    q.wk = 96;
+    q.wc0 = 64;
+    return launch_conv3z_t<32, false, 0, 2>(s, q);
+  }
+  return hipErrorNotSupported;
 }
 
 // BF16 stride-1 3x3x3 layers whose K channel count has a z-sweep instance (forward 8, 16,
@@ -1605,6 +1649,7 @@ struct NNState {
   void* act[13] = {};          // per layer output (a), plus input at index 12
   void* cat1 = nullptr;        // [up(m2b) | s1] at level 1
   void* cat0 = nullptr;        // [up(u1b) | s0] at level 0
+  float* u1part = nullptr;     // u1a's FP32 partial sums (BF16 forward in two passes)
   void* gbuf[6] = {};          // gradient scratch (largest level-0 sizes)
   float* gsum = nullptr;       // summed gradient of a training batch (master layout)
   float* x32 = nullptr;        // element density of the training pairs (FP32, for K n)
@@ -1637,7 +1682,8 @@ int wgrad_chunk(int nvox) {
 // [up(in) | skip] that the z-sweep reads in place; hipErrorNotSupported if it cannot.
 template <typename ST>
 hipError_t conv_fwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* in, void* out, int act,
-                    const void* skip = nullptr, int c1 = 0, Grid3 gcoarse = {}) {
+                    const void* skip = nullptr, int c1 = 0, Grid3 gcoarse = {},
+                    float* part = nullptr) {
   ConvArgs a{};
   a.in = in;
   a.w = (const char*)S->W + l.woff * S->es;
@@ -1654,6 +1700,7 @@ hipError_t conv_fwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* in, v
     a.skip = skip;
     a.c1 = c1;
     a.gcoarse = gcoarse;
+    a.part = part;
     return launch_conv3z_cat(c->stream, a);
   }
   if constexpr (sizeof(ST) == 2) {
@@ -1728,7 +1775,7 @@ void tosimp::nn_release(tosimp_ctx* ctx) {
   NNState* S = ctx ? nn_of(ctx) : nullptr;
   if (!S) return;
   void* ptrs[] = {S->master, S->m,        S->v,    S->grad, S->gpack, S->W,   S->WT, S->cat1,
-                  S->cat0,   S->wpart,    S->rho_node, S->scal, S->part, S->gsum, S->x32,
+                  S->cat0,   S->wpart,    S->rho_node, S->scal, S->part, S->gsum, S->x32, S->u1part,
                   S->fcgP, S->fcgQ, S->fpq, S->fco};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -1747,7 +1794,8 @@ hipError_t nn_alloc(void** p, size_t bytes) { return hipMalloc(p, bytes < 256 ? 
 
 // Forward pass from the padded input tensor in act[12]; layer outputs in act[0..11].
 // infer: the preconditioner's forward (no head: it is fused into the output kernel; in
-// BF16 the level-0 concatenation is read in place by u0a instead of being stored).
+// BF16 the up-sampling concatenations are read in place by u1a and u0a instead of being
+// stored).
 template <typename ST>
 hipError_t nn_forward(tosimp_ctx* c, NNState* S, bool infer = false) {
   hipError_t e = hipSuccess;
@@ -1763,9 +1811,19 @@ hipError_t nn_forward(tosimp_ctx* c, NNState* S, bool infer = false) {
   F(5, S->act[4], 1);                  // m2a
   F(6, S->act[5], 1);                  // m2b
   if (e != hipSuccess) return e;
-  upcat_kernel<ST><<<2048, 256, 0, c->stream>>>((const ST*)S->act[6], S->g[2], 4 * b,
-                                               (const ST*)S->act[3], 2 * b, (ST*)S->cat1, S->g[1]);
-  F(7, S->cat1, 1);                    // u1a
+  bool cat1_done = false;
+  if (infer && sizeof(ST) == 2) {      // u1a on [up(m2b) | s1] read in place, two passes
+    e = conv_fwd<ST>(c, S, S->L[7], S->act[6], S->act[7], 1, S->act[3], 4 * b, S->g[2],
+                     S->u1part);
+    cat1_done = e == hipSuccess;
+    if (e == hipErrorNotSupported) e = hipSuccess;
+    if (e != hipSuccess) return e;
+  }
+  if (!cat1_done) {
+    upcat_kernel<ST><<<2048, 256, 0, c->stream>>>((const ST*)S->act[6], S->g[2], 4 * b,
+                                                 (const ST*)S->act[3], 2 * b, (ST*)S->cat1, S->g[1]);
+    F(7, S->cat1, 1);                  // u1a
+  }
   F(8, S->act[7], 1);                  // u1b
   if (e != hipSuccess) return e;
   bool cat0_done = false;
@@ -2122,6 +2180,7 @@ int tosimp_nn_create(tosimp_ctx* ctx, int base, int bf16) {
   A(&S->act[12], n0 * 8 * S->es);
   A(&S->cat1, n1 * 6 * b * S->es);
   A(&S->cat0, n0 * 3 * b * S->es);
+  if (S->es == 2) A((void**)&S->u1part, n1 * 2 * b * 4);
   const size_t gsz = std::max(n0 * 3 * b, n1 * 6 * b) * S->es;
   for (int i = 0; i < 6; ++i) A(&S->gbuf[i], gsz);
   A((void**)&S->wpart, wpart * 4);
