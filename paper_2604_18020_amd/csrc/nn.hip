@@ -120,6 +120,8 @@ struct ConvArgs {
   // channel wc0 (a pass over part of K); FP32 partial result of a two-pass layer.
   int wk, wc0;
   float* part;
+  // channels per coarse voxel (0: c1) and the first one read (a pass over part of them)
+  int cstr, cc0;
 };
 
 // One wave: RT x 16 "row" voxels of the result x a group of up to 64 result channels
@@ -550,7 +552,8 @@ constexpr int conv3z_waves() {
 
 // OUTM 0: BF16 result (with the activation); 1: FP32 partial sums into a.part (no
 // activation); 2: the FP32 partial in a.part added first, then the activation and the
-// BF16 result (the two passes of a layer whose K is split).
+// BF16 result; 3: the partial added first and stored back (passes of a layer whose K is
+// split, in a fixed order).
 template <int KCH, bool BWD, int C1 = 0, int OUTM = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv3z_waves<KCH, BWD>())))
 void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
@@ -579,8 +582,9 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
   // without branches (the wait for a plane's loads then has a fixed count).
   constexpr int C2 = KCH - C1;  // channels read at the voxel itself
   const Grid3 gc = a.gcoarse;
+  const int cstr = a.cstr ? a.cstr : C1;  // channels per coarse voxel
   const __amdgpu_buffer_rsrc_t rin =
-      C1 ? conv3z_rsrc(a.in, (long long)gc.X * gc.Y * gc.Z * C1 * 2) : conv3z_rsrc(a.in, nvox * KCH * 2);
+      C1 ? conv3z_rsrc(a.in, (long long)gc.X * gc.Y * gc.Z * cstr * 2) : conv3z_rsrc(a.in, nvox * KCH * 2);
   const __amdgpu_buffer_rsrc_t ract = C1 ? conv3z_rsrc(a.skip, nvox * C2 * 2)
                                          : conv3z_rsrc(BWD ? a.act : a.in, nvox * KCH * 2);
   const __amdgpu_buffer_rsrc_t rout = conv3z_rsrc(a.out, nvox * nres * 2);
@@ -609,12 +613,12 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
     if (C1 == 0)
       pgo[i] = ((gx + g.X * gy) * KCH + ch) * 2;
     else if (pco[i])
-      pgo[i] = (((gx >> 1) + gc.X * (gy >> 1)) * C1 + ch) * 2;
+      pgo[i] = (((gx >> 1) + gc.X * (gy >> 1)) * cstr + a.cc0 + ch) * 2;
     else
       pgo[i] = ((gx + g.X * gy) * C2 + ch - C1) * 2;
   }
   const int pstride = g.X * g.Y * C2 * 2;          // bytes per plane
-  const int cstride = gc.X * gc.Y * C1 * 2;        // bytes per coarse plane (C1 > 0)
+  const int cstride = gc.X * gc.Y * cstr * 2;      // bytes per coarse plane (C1 > 0)
   auto plane_load = [&](Pack8<bf16_t>* pb, Pack8<bf16_t>* pa, int gz) {
     const bool zok = gz >= 0 && gz < g.Z;
 #pragma unroll
@@ -692,7 +696,7 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
       plane_load(st, sta, z + 2);
     const bool zin = z < zb;
     float pin[kZRW][4];  // the first pass's FP32 sums (OUTM 2), issued with the planes
-    if constexpr (OUTM == 2) {
+    if constexpr (OUTM >= 2) {
 #pragma unroll
       for (int r = 0; r < kZRW; ++r)
 #pragma unroll
@@ -732,9 +736,10 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
       for (int j = 0; j < 4; ++j) {
         const bool ok = zin && gx0 + j < g.X && gy0 + r < g.Y;
         const int off = ok ? obase + (j + g.X * r) * (nres * 2) + z * ostride : kZOOB;
-        if constexpr (OUTM == 1) {
-          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[r][j]), rpart,
-                                                ok ? 2 * off : kZOOB, 0, 0);
+        if constexpr (OUTM == 1 || OUTM == 3) {
+          const float v = OUTM == 3 ? pin[r][j] + acc[r][j] : acc[r][j];
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rpart, ok ? 2 * off : kZOOB,
+                                                0, 0);
         } else {
           float val = OUTM == 2 ? pin[r][j] + acc[r][j] : acc[r][j];
           if (!BWD && a.apply_act) val = val > 0.0f ? val : kLeak * val;
@@ -974,7 +979,7 @@ hipError_t launch_conv3s2(hipStream_t s, const ConvArgs& a) {
 }
 
 // The up-sampling layers reading their concatenated operand in place (48 channels: 32
-// up-sampled, 16 skipped; 96: 64 up-sampled, 32 skipped, in two passes through a.part);
+// up-sampled, 16 skipped; 96: 64 up-sampled, 32 skipped, in three passes through a.part);
 // hipErrorNotSupported for other shapes.
 hipError_t launch_conv3z_cat(hipStream_t s, const ConvArgs& a) {
   // every result voxel's coarse parent (x / 2, y / 2, z / 2) lies on the coarse grid
@@ -983,12 +988,20 @@ hipError_t launch_conv3z_cat(hipStream_t s, const ConvArgs& a) {
     return hipErrorNotSupported;
   if (a.cin == 48 && a.c1 == 32) return launch_conv3z_t<48, false, 32>(s, a);
   if (a.cin == 96 && a.c1 == 64 && a.part) {
-    // two passes over K: the 64 up-sampled channels into the FP32 partial, then the 32
-    // skipped channels added with the activation (weight rows of 27 x 96 channels)
+    // three passes over K, each with 32 channels: up-sampled channels 0-31 into the FP32
+    // partial, 32-63 added to it, then the 32 skipped channels added with the activation
+    // (weight rows of 27 x 96 channels)
     ConvArgs p = a;
     p.wk = 96;
     p.wc0 = 0;
-    hipError_t e = launch_conv3z_t<64, false, 64, 1>(s, p);
+    p.c1 = 32;
+    p.cstr = 64;
+    p.cc0 = 0;
+    hipError_t e = launch_conv3z_t<32, false, 32, 1>(s, p);
+    if (e != hipSuccess) return e;
+    p.wc0 = 32;
+    p.cc0 = 32;
+    e = launch_conv3z_t<32, false, 32, 3>(s, p);
     if (e != hipSuccess) return e;
     ConvArgs q = a;
     q.in = a.skip;
