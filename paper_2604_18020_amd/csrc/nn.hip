@@ -245,6 +245,90 @@ void conv_igemm_kernel(ConvArgs a) {
   }
 }
 
+// Data gradient of a stride-2 3x3x3 convolution (its transpose): an operand voxel i
+// receives, per axis, the taps whose i + 1 - t is even, t = 1 for even i and t = 0, 2 for
+// odd i, so a voxel has 1 to 8 taps instead of 27.  A wave holds 16 operand voxels of one
+// parity class along a row (x = 2 (16 b + m) + px) and up to 64 result channels; its K
+// runs over the class's taps only, in ascending tap order and the cout channels in chunks
+// of 32 within a tap: the order in which the implicit GEMM meets the same non-zero terms
+// (it adds zeros for the others), so the sums agree with it.
+template <typename ST>
+__global__ __launch_bounds__(256) void conv_tgrad_s2_kernel(ConvArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const Grid3 gi = a.gin, go = a.gout;
+  const int nxb = ((gi.X + 1) / 2 + 15) / 16;  // 16-voxel blocks of one x parity per row
+  const int xb = wave % nxb;
+  int rr = wave / nxb;
+  const int px = rr & 1;
+  rr >>= 1;
+  const int y = rr % gi.Y, z = rr / gi.Y;
+  if (z >= gi.Z) return;  // whole wave
+  const int m = lane & 15, q = lane >> 4;
+  const int kch = a.cout, nres = a.cin;  // K channels (dY), result channels (dX)
+  const int cg = blockIdx.y * 64;
+  const int nblk = min(4, (nres - cg) / 16);
+  const int x = 2 * (16 * xb + m) + px;  // this lane's operand-row voxel
+  const ST* dY = (const ST*)a.in;
+  const ST* act = (const ST*)a.act;
+  const ST* wt = (const ST*)a.w;          // WT [cin][27][cout]
+  f32x4 acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+  const int py = y & 1, pz = z & 1;
+  for (int iz = 0; iz < 1 + pz; ++iz) {
+    const int tz = pz ? 2 * iz : 1;
+    const int oz = (z + 1 - tz) / 2;
+    if (oz >= go.Z) continue;
+    for (int iy = 0; iy < 1 + py; ++iy) {
+      const int ty = py ? 2 * iy : 1;
+      const int oy = (y + 1 - ty) / 2;
+      if (oy >= go.Y) continue;
+      for (int ix = 0; ix < 1 + px; ++ix) {
+        const int tx = px ? 2 * ix : 1;
+        const int ox = (x + 1 - tx) / 2;
+        const bool ok = x < gi.X && ox < go.X;
+        const int t = tx + 3 * ty + 9 * tz;
+        const long long o = (long long)ox + (long long)go.X * (oy + (long long)go.Y * oz);
+        for (int cc = 0; cc < kch; cc += 32) {
+          Pack8<ST> A;
+          A.zero();
+          if (ok) {
+            A.load(dY + o * kch + cc + 8 * q);
+            if (act) {
+              Pack8<ST> av;
+              av.load(act + o * kch + cc + 8 * q);
+#pragma unroll
+              for (int j = 0; j < 8; ++j) A.set(j, A.get(j) * (av.get(j) > 0.0f ? 1.0f : kLeak));
+            }
+          }
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            if (b < nblk) {
+              Pack8<ST> B;
+              B.load(wt + (long long)(cg + 16 * b + m) * (27 * kch) + t * kch + cc + 8 * q);
+              mma32(acc[b], A, B);
+            }
+          }
+        }
+      }
+    }
+  }
+  ST* out = (ST*)a.out;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    if (b < nblk) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int xr = 2 * (16 * xb + 4 * q + j) + px;
+        if (xr < gi.X)
+          out[((long long)xr + (long long)gi.X * (y + (long long)gi.Y * z)) * nres + cg + 16 * b + m] =
+              from_f<ST>(acc[b][j]);
+      }
+    }
+  }
+}
+
 // Stride-1 3x3x3 convolutions (forward, and the data gradient as the convolution with
 // mirrored taps), tiled through LDS.  A block owns an output brick of 16 x 8 x 4 voxels
 // (x fastest) and a group of up to 32 result channels.  For each slice of CS channels
@@ -1776,6 +1860,15 @@ hipError_t conv_bwd(tosimp_ctx* c, NNState* S, const Layer& l, const void* dY, c
     }
     if (l.k == 3 && l.s == 1 && a.cout % conv3_cs<ST>() == 0 && a.cin % 16 == 0)
       return launch_conv3_lds<ST, true>(c->stream, a);
+    if (l.k == 3 && l.s == 2 && a.cout % 32 == 0 && a.cin % 16 == 0 &&
+        a.gout.X == (a.gin.X - 1) / 2 + 1 && a.gout.Y == (a.gin.Y - 1) / 2 + 1 &&
+        a.gout.Z == (a.gin.Z - 1) / 2 + 1) {
+      const long long waves =
+          (long long)(((a.gin.X + 1) / 2 + 15) / 16) * 2 * a.gin.Y * a.gin.Z;
+      conv_tgrad_s2_kernel<ST><<<dim3((unsigned)((waves + 3) / 4), (a.cin + 63) / 64), 256, 0,
+                                 c->stream>>>(a);
+      return hipGetLastError();
+    }
     const int waves = (a.gin.n() + 16 * kConvRT - 1) / (16 * kConvRT);
     conv_igemm_kernel<ST, true><<<dim3((waves + 3) / 4, (a.cin + 63) / 64), 256, 0, c->stream>>>(a);
   }
