@@ -1275,6 +1275,32 @@ __global__ void build_input_kernel(const float* r, const double* rnorm2, const f
   }
 }
 
+// The same from the 512 per-block partial sums of ||r||^2: every block adds them in one
+// fixed order (each thread two, then a tree in LDS), so all blocks use the same value;
+// block 0 also stores it into *rnorm2 (for the output scaling).
+template <typename ST>
+__global__ __launch_bounds__(256) void build_input_sum_kernel(const float* r, const double* partials,
+                                                              double* rnorm2, const float* rho_node,
+                                                              ST* inp, int n_node) {
+  __shared__ double red[256];
+  red[threadIdx.x] = partials[2 * threadIdx.x] + partials[2 * threadIdx.x + 1];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double tot = red[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *rnorm2 = tot;
+  const float inv = (float)(sqrt(3.0 * n_node) / sqrt(fmax(tot, 1e-300)));
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n_node; v += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) inp[8 * v + c] = from_f<ST>(r[3 * v + c] * inv);
+    inp[8 * v + 3] = from_f<ST>(rho_node[v]);
+#pragma unroll
+    for (int c = 4; c < 8; ++c) inp[8 * v + c] = from_f<ST>(0.0f);
+  }
+}
+
 // Same from an FP32 channels-last [v][4] tensor (test hook / training input).
 template <typename ST>
 __global__ void pad_input_kernel(const float* x4, ST* inp, int n) {
@@ -2046,8 +2072,11 @@ __global__ void sub_targets_kernel(const double* ustar, float* hu, int n_dof, in
 template <typename ST>
 int nn_apply_t(tosimp_ctx* ctx, NNState* S, const float* r, float* z) {
   const int nn = (int)ctx->n_node;
-  TOSIMP_HIP(ctx, launch_norm2f(ctx->stream, r, (int)ctx->n_dof, S->part, S->scal));
-  build_input_kernel<ST><<<2048, 256, 0, ctx->stream>>>(r, S->scal, S->rho_node, (ST*)S->act[12], nn);
+  // ||r||^2 as 512 block partials, added by every block of the input kernel (no separate
+  // finalising launch)
+  norm2f_kernel<<<512, 256, 0, ctx->stream>>>(r, (int)ctx->n_dof, S->part);
+  build_input_sum_kernel<ST><<<2048, 256, 0, ctx->stream>>>(r, S->part, S->scal, S->rho_node,
+                                                           (ST*)S->act[12], nn);
   TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S, /*infer=*/true));
   const Layer& hl = S->L[11];
   head_output_kernel<ST><<<2048, 256, 0, ctx->stream>>>(
