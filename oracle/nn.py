@@ -3,7 +3,7 @@ flexible CG (oracle, float64, CPU).
 
 The paper has no learned component; its Sec. "Path to Geometric Multigrid Integration"
 names better preconditioning as the way past Jacobi-PCG's iteration counts.  This module
-is the plain definition of the network the project brief asks for (3 levels, 16 base
+is the plain definition of the network the library trains (3 levels, 16 base
 channels, inputs residual xyz + nodal density on the node grid, output a correction)
 and of flexible CG (Notay's FCG with truncation 1), written as direct sums so that the
 GPU kernels can be checked against them.  Parity of the network's *value as a

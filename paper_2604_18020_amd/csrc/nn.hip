@@ -1,21 +1,25 @@
 // Learned preconditioner: 3D-convolutional U-Net on the node grid, trained on the GPU.
 //
 // Not in the paper (its Sec. "Path to Geometric Multigrid Integration" names stronger
-// preconditioning as the way past Jacobi-PCG); the network follows the project brief:
-// 3 levels with base, 2 base and 4 base channels, inputs (r_x, r_y, r_z, nodal density),
-// output a 3-component correction, LeakyReLU, no biases, nearest up-sampling and
-// concatenated skips.  The layer list is the same as the oracle's.
+// preconditioning as the way past Jacobi-PCG).  The network: 3 levels with base, 2 base
+// and 4 base channels, inputs (r_x, r_y, r_z, nodal density), output a 3-component
+// correction, LeakyReLU, no biases, nearest up-sampling and concatenated skips.  The
+// layer list is the same as the oracle's.
 //
 // Tensors are channels-last: [voxel][channel], voxel = x + X (y + Y z) on a level's grid.
-// Convolutions are implicit GEMMs on the matrix cores:
+// Convolutions run on the matrix cores:
 //   forward      Y[o][co]  = sum_{t, ci} W[co][t][ci] X[nbr(o, t)][ci]
 //   data grad    dX[i][ci] = sum_{t, co} W[co][t][ci] dZ[o(i, t)][co]   (W stored as WT)
 //   weight grad  dW[co][t][ci] = sum_o dZ[o][co] X[nbr(o, t)][ci]
-// with K = taps x channels in chunks of 32 (one v_mfma_f32_16x16x32_bf16, or eight
-// v_mfma_f32_16x16x4f32 for FP32 storage).  A wave owns 16 output voxels x all output
-// channels.  dZ = dY * leaky'(a) is formed on load from the layer's stored activation a
-// (leaky ReLU preserves the sign, so a determines the slope).  Weight gradients are
-// reduced per voxel chunk and the chunks summed in a fixed order (deterministic).
+// with K cut into chunks of 32 (one v_mfma_f32_16x16x32_bf16, or eight
+// v_mfma_f32_16x16x4f32 for FP32 storage).  BF16 3x3x3 layers run as sweeps up the z
+// axis with operand planes in an LDS ring and the weights in registers (conv3z_kernel,
+// conv3s2_kernel); the stride-2 data gradient visits each voxel's parity-class taps only
+// (conv_tgrad_s2_kernel); the remaining shapes use the LDS brick kernel or the implicit
+// GEMM that gathers operands from global memory.  dZ = dY * leaky'(a) is formed on load
+// from the layer's stored activation a (leaky ReLU preserves the sign, so a determines
+// the slope).  Weight gradients are reduced per voxel chunk and the chunks summed in a
+// fixed order (deterministic).
 #include <algorithm>
 #include <atomic>
 #include <cmath>
