@@ -359,16 +359,31 @@ def test_energy_loss_gradient_matches_oracle(bf16, tol):
 
 
 
+@pytest.mark.parametrize("bf16,tol", [(False, 1e-4), (True, 5e-2)])
 @pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 3)])
-def test_forward_on_degenerate_grids_matches_oracle(dims):
-    """Level grids of one or two nodes per axis (stride-2 convolutions down to 1 x 1 x 1)."""
+def test_forward_on_degenerate_grids_matches_oracle(dims, bf16, tol):
+    """Level grids of one or two nodes per axis (stride-2 convolutions down to 1 x 1 x 1;
+    in BF16 the z-sweeps with single-plane chunks and one partial tile); the BF16 case
+    also applies the preconditioner (its in-place concatenations and fused head)."""
     nx, ny, nz = dims
-    t, _, _, params = _net(nx, ny, nz, bf16=False)
+    t, fixed, _, params = _net(nx, ny, nz, bf16=bf16)
     grid, x4 = _inputs(nx, ny, nz, seed=8)
     out = t.nn_forward(dev(x4.reshape(-1))).cpu().numpy()
     ref, _ = nn.unet_forward(params, _to_oracle(x4, grid, 4), BASE)
+    assert rel(_to_oracle(out, grid, 3), ref) <= tol
+    if bf16:
+        rng = np.random.default_rng(5)
+        x = rng.uniform(0.05, 1.0, t.n_elem).astype(np.float32)
+        r = rng.standard_normal(t.n_dof).astype(np.float32)
+        r[fixed] = 0.0
+        t.nn_set_density(dev(x))
+        z = t.nn_apply(dev(r)).cpu().numpy()
+        zo = nn.nn_precondition(params, r.astype(np.float64),
+                                nn.node_density(x.astype(np.float64), nx, ny, nz),
+                                fem.fixed_mask(t.n_dof, fixed), base=BASE)
+        assert np.all(z[fixed] == 0.0)
+        assert rel(z, zo) <= tol
     t.close()
-    assert rel(_to_oracle(out, grid, 3), ref) <= 1e-4
 
 
 def _oracle_fcg_system(nx, ny, nz, x, fixed, f):
