@@ -126,6 +126,10 @@ struct ConvArgs {
   float* part;
   // channels per coarse voxel (0: c1) and the first one read (a pass over part of them)
   int cstr, cc0;
+  // first layer reading the residual in place: `in` = r (FP32, 3 per node), `skip` = the
+  // nodal density (FP32); ||r||^2 from the 512 block partials npart, stored into *nout
+  const double* npart;
+  double* nout;
 };
 
 // One wave: RT x 16 "row" voxels of the result x a group of up to 64 result channels
@@ -642,11 +646,14 @@ constexpr int conv3z_waves() {
 // activation); 2: the FP32 partial in a.part added first, then the activation and the
 // BF16 result; 3: the partial added first and stored back (passes of a layer whose K is
 // split, in a fixed order).
-template <int KCH, bool BWD, int C1 = 0, int OUTM = 0>
+// INP: the first layer of the preconditioner, its operand (r at unit RMS per DOF, the
+// nodal density, four zero channels) formed while staging from r and the density.
+template <int KCH, bool BWD, int C1 = 0, int OUTM = 0, bool INP = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv3z_waves<KCH, BWD>())))
 void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
   static_assert(C1 == 0 || (!BWD && C1 % 8 == 0 && C1 <= KCH), "concatenated operand: forward");
   static_assert(OUTM == 0 || !BWD, "split K: forward");
+  static_assert(!INP || (KCH == 8 && !BWD && C1 == 0 && OUTM == 0), "input layer: 8 channels");
   constexpr int S = conv3z_steps<KCH>();
   constexpr int PV = KCH / 8;                     // 16-byte pieces per voxel
   constexpr int NP = (kZPlane * PV + 255) / 256;  // plane pieces per thread
@@ -672,9 +679,12 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
   const Grid3 gc = a.gcoarse;
   const int cstr = a.cstr ? a.cstr : C1;  // channels per coarse voxel
   const __amdgpu_buffer_rsrc_t rin =
-      C1 ? conv3z_rsrc(a.in, (long long)gc.X * gc.Y * gc.Z * cstr * 2) : conv3z_rsrc(a.in, nvox * KCH * 2);
-  const __amdgpu_buffer_rsrc_t ract = C1 ? conv3z_rsrc(a.skip, nvox * C2 * 2)
-                                         : conv3z_rsrc(BWD ? a.act : a.in, nvox * KCH * 2);
+      INP ? conv3z_rsrc(a.in, nvox * 12)
+          : C1 ? conv3z_rsrc(a.in, (long long)gc.X * gc.Y * gc.Z * cstr * 2)
+               : conv3z_rsrc(a.in, nvox * KCH * 2);
+  const __amdgpu_buffer_rsrc_t ract = INP  ? conv3z_rsrc(a.skip, nvox * 4)
+                                      : C1 ? conv3z_rsrc(a.skip, nvox * C2 * 2)
+                                           : conv3z_rsrc(BWD ? a.act : a.in, nvox * KCH * 2);
   const __amdgpu_buffer_rsrc_t rout = conv3z_rsrc(a.out, nvox * nres * 2);
   const __amdgpu_buffer_rsrc_t rpart = conv3z_rsrc(a.part, OUTM ? nvox * nres * 4 : 0);
   const bf16_t* w = (const bf16_t*)a.w;
@@ -698,20 +708,33 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
     const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
     pok[i] = idx < kZPlane * PV && gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y;
     pvox[i] = idx < kZPlane * PV ? vb * VS + ch : -1;
-    if (C1 == 0)
+    if (INP)
+      pgo[i] = gx + g.X * gy;  // node index in the plane
+    else if (C1 == 0)
       pgo[i] = ((gx + g.X * gy) * KCH + ch) * 2;
     else if (pco[i])
       pgo[i] = (((gx >> 1) + gc.X * (gy >> 1)) * cstr + a.cc0 + ch) * 2;
     else
       pgo[i] = ((gx + g.X * gy) * C2 + ch - C1) * 2;
   }
-  const int pstride = g.X * g.Y * C2 * 2;          // bytes per plane
+  const int pstride = INP ? g.X * g.Y : g.X * g.Y * C2 * 2;  // bytes (INP: nodes) per plane
   const int cstride = gc.X * gc.Y * cstr * 2;      // bytes per coarse plane (C1 > 0)
+  float inv = 0.0f;  // INP: sqrt(n_dof) / ||r||
   auto plane_load = [&](Pack8<bf16_t>* pb, Pack8<bf16_t>* pa, int gz) {
     const bool zok = gz >= 0 && gz < g.Z;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-      if constexpr (C1 == 0) {
+      if constexpr (INP) {
+        const bool ok = zok && pok[i];
+        const int nd = pgo[i] + gz * pstride;
+        const auto rv = __builtin_amdgcn_raw_buffer_load_b96(rin, ok ? 12 * nd : kZOOB, 0, 0);
+        const unsigned dv = __builtin_amdgcn_raw_buffer_load_b32(ract, ok ? 4 * nd : kZOOB, 0, 0);
+        pb[i].zero();
+        pb[i].set(0, __uint_as_float(rv[0]) * inv);
+        pb[i].set(1, __uint_as_float(rv[1]) * inv);
+        pb[i].set(2, __uint_as_float(rv[2]) * inv);
+        pb[i].set(3, __uint_as_float(dv));
+      } else if constexpr (C1 == 0) {
         const int off = zok && pok[i] ? pgo[i] + gz * pstride : kZOOB;
         pb[i].v = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rin, off, 0, 0));
         if (BWD)
@@ -750,6 +773,21 @@ void conv3z_kernel(ConvArgs a, Conv3zGeom gm) {
   static_assert(3 * S * 16 * 32 <= kZSlots * kZPlane * VS, "weight staging fits the slots");
   Pack8<bf16_t> Bw[3][S];
   conv3z_weights<KCH, BWD, 256>(Bw, w, cg, planes, a.wk ? a.wk : KCH, a.wc0);
+  if constexpr (INP) {
+    // ||r||^2 from its 512 block partials, added in one fixed order by every block (each
+    // thread two, then a tree in LDS, in the plane slots before any plane is staged)
+    double* red = reinterpret_cast<double*>(zsm);
+    red[tid] = a.npart[2 * tid] + a.npart[2 * tid + 1];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    const double tot = red[0];
+    if (blin == 0 && blockIdx.y == 0 && tid == 0) *a.nout = tot;
+    inv = (float)(sqrt(3.0 * (double)nvox) / sqrt(fmax(tot, 1e-300)));
+    __syncthreads();  // the planes overwrite the reduction area next
+  }
   {  // planes za - 1, za, za + 1
     Pack8<bf16_t> p0[NP], a0[BWD ? NP : 1], p1[NP], a1[BWD ? NP : 1], p2[NP], a2[BWD ? NP : 1];
     plane_load(p0, a0, za - 1);
@@ -901,10 +939,11 @@ static hipError_t conv_resident(K kern, int smem, std::atomic<int>& once, int* r
   return hipSuccess;
 }
 
-template <int KCH, bool BWD, int C1 = 0, int OUTM = 0>
+template <int KCH, bool BWD, int C1 = 0, int OUTM = 0, bool INP = false>
 hipError_t launch_conv3z_t(hipStream_t s, const ConvArgs& a) {
   constexpr int smem = conv3z_lds_bytes<KCH>();
-  auto kern = conv3z_kernel<KCH, BWD, C1, OUTM>;
+  static_assert(!INP || smem >= 256 * 8, "the norm's reduction fits the plane slots");
+  auto kern = conv3z_kernel<KCH, BWD, C1, OUTM, INP>;
   static std::atomic<int> once{0};
   int resident = 0;
   const hipError_t e = conv_resident(kern, smem, once, &resident);
@@ -1100,6 +1139,15 @@ hipError_t launch_conv3z_cat(hipStream_t s, const ConvArgs& a) {
     return launch_conv3z_t<32, false, 0, 2>(s, q);
   }
   return hipErrorNotSupported;
+}
+
+// The preconditioner's first layer reading r and the density in place (8 operand channels,
+// 16 results); hipErrorNotSupported for other shapes.
+hipError_t launch_conv3z_input(hipStream_t s, const ConvArgs& a) {
+  if (a.cin != 8 || a.cout % 16 || !a.in || !a.skip || !a.npart || !a.nout ||
+      12LL * a.gout.n() >= (1LL << 31) || 2LL * a.gout.n() * a.cout >= (1LL << 31))
+    return hipErrorNotSupported;
+  return launch_conv3z_t<8, false, 0, 0, true>(s, a);
 }
 
 // BF16 stride-1 3x3x3 layers whose K channel count has a z-sweep instance (forward 8, 16,
@@ -1932,14 +1980,43 @@ hipError_t nn_alloc(void** p, size_t bytes) { return hipMalloc(p, bytes < 256 ? 
 // infer: the preconditioner's forward (no head: it is fused into the output kernel; in
 // BF16 the up-sampling concatenations are read in place by u1a and u0a instead of being
 // stored).
+// r_in (BF16 inference): the first layer forms its operand from r (and the density) in
+// place, the norm from the 512 partials in S->part; without it act[12] holds the input.
 template <typename ST>
-hipError_t nn_forward(tosimp_ctx* c, NNState* S, bool infer = false) {
+hipError_t nn_forward(tosimp_ctx* c, NNState* S, bool infer = false, const float* r_in = nullptr) {
   hipError_t e = hipSuccess;
   auto F = [&](int li, const void* in, int act) {
     if (e == hipSuccess) e = conv_fwd<ST>(c, S, S->L[li], in, S->act[li], act);
   };
   const int b = S->base;
-  F(0, S->act[12], 1);                 // e0a
+  bool in_done = false;
+  if (infer && sizeof(ST) == 2 && r_in) {
+    const Layer& l0 = S->L[0];
+    ConvArgs a0{};
+    a0.in = r_in;
+    a0.skip = S->rho_node;
+    a0.npart = S->part;
+    a0.nout = S->scal;
+    a0.w = (const char*)S->W + l0.woff * S->es;
+    a0.out = S->act[0];
+    a0.gin = S->g[0];
+    a0.gout = S->g[0];
+    a0.cin = l0.cip;
+    a0.cout = l0.cop;
+    a0.ksize = 3;
+    a0.stride = 1;
+    a0.apply_act = 1;
+    e = launch_conv3z_input(c->stream, a0);
+    in_done = e == hipSuccess;
+    if (e == hipErrorNotSupported) e = hipSuccess;
+    if (e != hipSuccess) return e;
+  }
+  if (!in_done) {
+    if (r_in)
+      build_input_sum_kernel<ST><<<2048, 256, 0, c->stream>>>(r_in, S->part, S->scal, S->rho_node,
+                                                            (ST*)S->act[12], (int)S->g[0].n());
+    F(0, S->act[12], 1);               // e0a
+  }
   F(1, S->act[0], 1);                  // e0b -> s0
   F(2, S->act[1], 1);                  // d1
   F(3, S->act[2], 1);                  // e1 -> s1
@@ -2076,12 +2153,10 @@ __global__ void sub_targets_kernel(const double* ustar, float* hu, int n_dof, in
 template <typename ST>
 int nn_apply_t(tosimp_ctx* ctx, NNState* S, const float* r, float* z) {
   const int nn = (int)ctx->n_node;
-  // ||r||^2 as 512 block partials, added by every block of the input kernel (no separate
-  // finalising launch)
+  // ||r||^2 as 512 block partials, added by every block of the kernel that forms the
+  // network's input (in BF16 the first convolution itself; no separate finalising launch)
   norm2f_kernel<<<512, 256, 0, ctx->stream>>>(r, (int)ctx->n_dof, S->part);
-  build_input_sum_kernel<ST><<<2048, 256, 0, ctx->stream>>>(r, S->part, S->scal, S->rho_node,
-                                                           (ST*)S->act[12], nn);
-  TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S, /*infer=*/true));
+  TOSIMP_HIP(ctx, nn_forward<ST>(ctx, S, /*infer=*/true, r));
   const Layer& hl = S->L[11];
   head_output_kernel<ST><<<2048, 256, 0, ctx->stream>>>(
       (const ST*)S->act[10], (const ST*)((const char*)S->W + hl.woff * S->es), hl.cip,
